@@ -1,0 +1,181 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) fast multipole library for the 3-D
+ * Laplace N-body problem of Ltaief & Yokota, "Data-Driven Execution of Fast
+ * Multipole Methods" (arXiv:1203.0889).
+ *
+ * Problem (Sec. 2.1): N bodies with positions x_i and charges q_i; the
+ * "solution on the particle" is the potential and field
+ *     phi_i = sum_{j : |x_i - x_j| > 0} q_j / |x_i - x_j|
+ *     E_i   = -grad phi (x_i) = sum_j q_j (x_i - x_j) / |x_i - x_j|^3
+ * (unit Coulomb constant, pairs at zero distance contribute nothing), and the
+ * force F_i = q_i E_i.  The FMM approximates these with an adaptive cubic
+ * octree (Sec. 2.1, 2.2), a dual tree traversal producing M2L / P2P pair
+ * lists (Sec. 4), and the six stages P2M, M2M, M2L, P2P, L2L, L2P (Sec. 2.1,
+ * Fig. 1).  The paper's multicore task runtime (Sec. 3) is replaced by a
+ * device-side work queue.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns fmm_status; FMM_OK == 0.  No call aborts or exits.
+ *   - Pointers documented "device" must point to device memory of the plan's
+ *     device; "host" to host memory.  The caller owns every buffer it passes;
+ *     the library owns everything inside the plan.
+ *   - All device work is enqueued on the plan's stream and is asynchronous
+ *     with respect to the host, except where stated.  Host-side argument
+ *     checks fail synchronously with FMM_ERR_INVALID_ARG / FMM_ERR_STATE and
+ *     leave the plan unchanged.
+ *   - Device arrays of vectors are row-major (N, 3) FP64: x0 y0 z0 x1 ...
+ *   - Results are in the caller's (input) particle order.
+ *   - A plan is not thread safe; one plan per stream.
+ */
+#ifndef FMM_MI355X_H
+#define FMM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_ERR_INVALID_ARG = -1, /* bad pointer, size or parameter */
+    FMM_ERR_STATE = -2,       /* call out of order (see state machine) */
+    FMM_ERR_OOM = -3,         /* device allocation failed */
+    FMM_ERR_DEVICE = -4,      /* a HIP runtime call failed */
+    FMM_ERR_CAPACITY = -5,    /* an internal capacity limit was exceeded */
+    FMM_ERR_UNSUPPORTED = -6  /* valid request this build does not provide */
+} fmm_status;
+
+typedef enum {
+    FMM_PREC_FP64 = 0,  /* every stage in FP64 (the plain GPU path) */
+    FMM_PREC_MIXED = 1  /* P2P on FP32 VALU, M2L on FP32 MFMA with FP32
+                           accumulation; tree, P2M, M2M, L2L, L2P and the
+                           per-particle / per-cell accumulation in FP64 */
+} fmm_precision;
+
+enum {
+    FMM_FLAG_USER_BOX = 1u << 0 /* use params.box_min / box_side for every
+                                   instance instead of the tight bounding cube */
+};
+
+typedef struct {
+    int32_t p;           /* expansion order: every degree 0..p kept; 0 <= p <= 16 */
+    int32_t ncrit;       /* leaf size limit: a cell with more particles is split (Sec. 2.1) */
+    int32_t theta_num;   /* multipole acceptance ratio theta = num / den, exact rational, */
+    int32_t theta_den;   /*   1 <= num, den <= 100, 0 < theta < 1 (Sec. 2.1, Sec. 4) */
+    int32_t max_level;   /* deepest octree level, 1 <= max_level <= 21 (63-bit keys) */
+    int32_t precision;   /* fmm_precision */
+    uint32_t flags;      /* FMM_FLAG_* */
+    double box_min[3];   /* used with FMM_FLAG_USER_BOX */
+    double box_side;     /*   (must enclose every particle) */
+} fmm_params;
+
+/* Fill *params with defaults: p = 8, ncrit = 64, theta = 1/2,
+ * max_level = 21, mixed precision, no flags. */
+fmm_status fmm_default_params(fmm_params *params);
+
+typedef struct fmm_plan fmm_plan; /* opaque; owns all device workspaces */
+
+/* Create a plan on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  params is copied. */
+fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fmm_plan **out);
+
+/* Release every device allocation of the plan (synchronises its stream).
+ * NULL is accepted. */
+fmm_status fmm_destroy(fmm_plan *plan);
+
+/*
+ * Build keys, sort, octree and interaction lists (Sec. 2.1, 2.2, 4).
+ *   n_inst   number of independent instances (>= 1), batched in one forest
+ *   offsets  host int64[n_inst + 1], offsets[0] = 0, non-decreasing;
+ *            instance k owns particles [offsets[k], offsets[k+1])
+ *   pos      device FP64 (N, 3), N = offsets[n_inst]; finite values
+ *   q        device FP64 (N)
+ * Copies what it needs; pos and q may be reused once the stream reaches the
+ * end of this call.  Synchronises the stream internally (sizes of the tree
+ * and lists are read back).  Non-finite coordinates -> FMM_ERR_INVALID_ARG.
+ * Empty instances (N_k = 0) are allowed.
+ */
+fmm_status fmm_build_tree(fmm_plan *plan, int32_t n_inst, const int64_t *offsets,
+                          const double *pos, const double *q);
+
+/* Upward pass: P2M at leaves, M2M to the roots (Sec. 2.1).  Requires a
+ * built tree. */
+fmm_status fmm_upward(fmm_plan *plan);
+
+/*
+ * Downward pass and near field: M2L and P2P through the device work queue,
+ * then L2L and L2P (Sec. 2.1, Sec. 4).  Requires fmm_upward.  Each output
+ * is optional (NULL skips it):
+ *   phi     device FP64 (N)      potential
+ *   field   device FP64 (N, 3)   E = -grad phi
+ *   force   device FP64 (N, 3)   F = q E
+ *   energy  device FP64 (n_inst) E_k = 1/2 sum_{i in k} q_i phi_i
+ */
+fmm_status fmm_evaluate(fmm_plan *plan, double *phi, double *field, double *force, double *energy);
+
+/*
+ * Adjoint: gradient of the FMM total energy, sum_k g_k E_k, with respect to
+ * positions and charges.  Requires fmm_evaluate on the same plan.
+ *   grad_energy  device FP64 (n_inst) upstream weights g_k
+ *   grad_pos     device FP64 (N, 3)  (NULL skips)
+ *   grad_q       device FP64 (N)     (NULL skips)
+ */
+fmm_status fmm_backward(fmm_plan *plan, const double *grad_energy, double *grad_pos, double *grad_q);
+
+/* Wait for the plan's stream; returns the first device-detected error
+ * recorded since the last call (e.g. FMM_ERR_CAPACITY), else FMM_OK. */
+fmm_status fmm_sync(fmm_plan *plan);
+
+/* Sizes of the built tree and lists (host outputs; any may be NULL). */
+fmm_status fmm_get_counts(const fmm_plan *plan, int64_t *ncell, int64_t *nleaf, int64_t *nm2l,
+                          int64_t *np2p);
+
+/*
+ * Copy the tree to host memory (synchronous).  Cells are in canonical order:
+ * by level, then instance, then Morton prefix.
+ *   keys   host uint64[N]: Morton key of every particle, input order
+ *   perm   host int64[N]:  perm[r] = input index of the r-th sorted particle
+ *   cells  host int64[ncell * 10]: per cell
+ *          [level, ix, iy, iz, first, count, child_first, nchild, parent, instance]
+ *          (first is a sorted rank; child_first = -1 for leaves)
+ * Any pointer may be NULL.
+ */
+fmm_status fmm_copy_tree(const fmm_plan *plan, uint64_t *keys, int64_t *perm, int64_t *cells);
+
+/*
+ * Copy the interaction lists, sorted by (target cell, source cell), as CSR
+ * over target cells (synchronous).  host int64 m2l_ptr[ncell + 1],
+ * int32 m2l_src[nm2l], p2p_ptr[ncell + 1], p2p_src[np2p].  Any may be NULL.
+ */
+fmm_status fmm_copy_lists(const fmm_plan *plan, int64_t *m2l_ptr, int32_t *m2l_src, int64_t *p2p_ptr,
+                          int32_t *p2p_src);
+
+/*
+ * Tuning knobs of the work queue and kernels (an autotuner fills them).
+ * Results do not depend on them, only speed.
+ */
+typedef struct {
+    int32_t queue_chunk;   /* P2P tasks claimed per atomic grab (>= 1) */
+    int32_t p2p_split;     /* max source leaves per P2P task (>= 1) */
+    int32_t m2l_block;     /* targets per M2L MFMA tile column block (16 or 32) */
+    int32_t grid_per_cu;   /* persistent workgroups per compute unit (1..8) */
+} fmm_tuning;
+
+fmm_status fmm_get_tuning(const fmm_plan *plan, fmm_tuning *tuning);
+fmm_status fmm_set_tuning(fmm_plan *plan, const fmm_tuning *tuning);
+
+/* Per-stage device times of the last build / upward / evaluate in ms,
+ * measured with HIP events on the plan's stream.  times: host double[16],
+ * names: optional host array of 16 const char* filled with stage names. */
+fmm_status fmm_get_stage_times(const fmm_plan *plan, double *times, const char **names);
+
+const char *fmm_status_string(fmm_status status);
+/* Last error message of this plan (host-side detail), never NULL. */
+const char *fmm_last_error(const fmm_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_MI355X_H */

@@ -1,0 +1,226 @@
+// The plain FP64 GPU path of the two dominant stages (Sec. 2.1: M2L and P2P
+// take most of the time).  Target-owned: each workgroup owns one target cell
+// and walks its CSR list, so no two workgroups write the same data (the
+// non-mutual interaction of Sec. 4).  This path is the accuracy anchor and
+// the baseline the mixed-precision work queue is measured against.
+#include "tree.h"
+
+namespace fmm {
+
+namespace {
+
+// ---------------------------------------------------------------- P2P
+// One wave per target leaf; a lane per target particle; source particles of
+// every listed source leaf staged through LDS 64 at a time.
+constexpr int kP2P64Threads = 64;
+
+__global__ void __launch_bounds__(kP2P64Threads)
+    k_p2p_fp64(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+               const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+               const double *__restrict__ qs, double *__restrict__ phi, double *__restrict__ fld) {
+    __shared__ double sx[kP2P64Threads], sy[kP2P64Threads], sz[kP2P64Threads], sq[kP2P64Threads];
+    int32_t A = blockIdx.x;
+    if (A >= ncell || c.child[A] >= 0) return;
+    const int lane = threadIdx.x;
+    int32_t tf = c.first[A], tc = c.count[A];
+    int32_t e0 = ptr[A], e1 = ptr[A + 1];
+    for (int32_t t0 = 0; t0 < tc; t0 += kP2P64Threads) {
+        int32_t r = tf + t0 + lane;
+        bool active = t0 + lane < tc;
+        double xt = active ? xs[r] : 0.0, yt = active ? ys[r] : 0.0, zt = active ? zs[r] : 0.0;
+        double p = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int32_t e = e0; e < e1; e++) {
+            int32_t B = src[e];
+            int32_t sf = c.first[B], sc = c.count[B];
+            for (int32_t s0 = 0; s0 < sc; s0 += kP2P64Threads) {
+                int ns = sc - s0 < kP2P64Threads ? sc - s0 : kP2P64Threads;
+                __syncthreads();
+                if (lane < ns) {
+                    sx[lane] = xs[sf + s0 + lane];
+                    sy[lane] = ys[sf + s0 + lane];
+                    sz[lane] = zs[sf + s0 + lane];
+                    sq[lane] = qs[sf + s0 + lane];
+                }
+                __syncthreads();
+                for (int j = 0; j < ns; j++) {
+                    double dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
+                    double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 > 0.0) {
+                        double inv = 1.0 / sqrt(r2);
+                        double qi = sq[j] * inv;
+                        double qi3 = qi * inv * inv;
+                        p += qi;
+                        ex += dx * qi3;
+                        ey += dy * qi3;
+                        ez += dz * qi3;
+                    }
+                }
+            }
+        }
+        if (active) {
+            phi[r] = p;
+            fld[3 * (int64_t)r] = ex;
+            fld[3 * (int64_t)r + 1] = ey;
+            fld[3 * (int64_t)r + 2] = ez;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- M2L
+// One wave per target cell.  Per source cell B (class offset rho = (c_A -
+// c_B) / S_A, level difference delta = l_A - l_B):
+//   L~_n^m += (-1)^n sum_(k <= p) 2^(delta k) sum_l M~_k^l I_(n+k)^(m+l)(rho)
+// with the irregular solid harmonics (m >= 0, r^2 = |rho|^2, zeta = x + iy)
+//   I_0^0 = 1/r,  I_m^m = (2m-1) zeta I_(m-1)^(m-1) / r^2,
+//   I_(m+1)^m = (2m+1) z I_m^m / r^2,
+//   I_n^m = ((2n-1) z I_(n-1)^m - ((n-1)^2 - m^2) I_(n-2)^m) / r^2,
+// I_n^(-m) = (-1)^m conj(I_n^m).  Lane m evaluates column m of I into LDS,
+// then every lane accumulates its outputs (n, m) over all (k, l).
+constexpr int kM2L64Threads = 64;
+constexpr int kMaxI = (2 * kMaxP + 1) * (2 * kMaxP + 2) / 2;
+
+__device__ inline int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+
+__global__ void __launch_bounds__(kM2L64Threads)
+    k_m2l_fp64(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+               const double *__restrict__ M, double *__restrict__ L) {
+    __shared__ double Ire[kMaxI], Iim[kMaxI];
+    __shared__ double Ms[ncoef(kMaxP)];
+    int32_t A = blockIdx.x;
+    if (A >= ncell) return;
+    const int lane = threadIdx.x;
+    const int P = ncoef(p);
+    const int NC = (p + 1) * (p + 2) / 2;
+    // this lane's outputs: complex index j = lane, lane + 64, lane + 128
+    int on[3], om[3];
+    double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
+    for (int s = 0; s < 3; s++) {
+        int j = lane + 64 * s;
+        on[s] = -1;
+        om[s] = 0;
+        if (j < NC) {
+            int n = 0;
+            while ((n + 1) * (n + 2) / 2 <= j) n++;
+            on[s] = n;
+            om[s] = j - n * (n + 1) / 2;
+        }
+    }
+    int la = c.level[A];
+    int64_t SA = (int64_t)1 << (kLevels - la);
+    int64_t cax = (2 * (int64_t)c.ix[A] + 1) * SA, cay = (2 * (int64_t)c.iy[A] + 1) * SA,
+            caz = (2 * (int64_t)c.iz[A] + 1) * SA;
+    for (int32_t e = ptr[A]; e < ptr[A + 1]; e++) {
+        int32_t B = src[e];
+        int lb = c.level[B];
+        int64_t SB = (int64_t)1 << (kLevels - lb);
+        // rho in units of the target side: (C_A - C_B) / (2 S_A), exact
+        double rx = ldexp((double)(cax - (2 * (int64_t)c.ix[B] + 1) * SB), -(kLevels - la + 1));
+        double ry = ldexp((double)(cay - (2 * (int64_t)c.iy[B] + 1) * SB), -(kLevels - la + 1));
+        double rz = ldexp((double)(caz - (2 * (int64_t)c.iz[B] + 1) * SB), -(kLevels - la + 1));
+        int delta = la - lb;
+        __syncthreads();
+        for (int i = lane; i < P; i += 64) Ms[i] = M[(int64_t)B * P + i];
+        if (lane <= 2 * p) {
+            int m = lane, nmax = 2 * p;
+            double r2 = rx * rx + ry * ry + rz * rz;
+            double ir2 = 1.0 / r2;
+            double mr = 1.0 / sqrt(r2), mi = 0.0;  // I_m^m
+            for (int j = 1; j <= m; j++) {
+                double f = (2 * j - 1) * ir2;
+                double nr = (mr * rx - mi * ry) * f, ni = (mr * ry + mi * rx) * f;
+                mr = nr;
+                mi = ni;
+            }
+            Ire[tri(m, m)] = mr;
+            Iim[tri(m, m)] = mi;
+            double pr = 0, pi = 0, cr = mr, ci = mi;
+            for (int n = m + 1; n <= nmax; n++) {
+                double nr, ni;
+                if (n == m + 1) {
+                    double f = (2 * m + 1) * rz * ir2;
+                    nr = f * cr;
+                    ni = f * ci;
+                } else {
+                    double a = (2 * n - 1) * rz, b = (double)((n - 1) * (n - 1) - m * m);
+                    nr = (a * cr - b * pr) * ir2;
+                    ni = (a * ci - b * pi) * ir2;
+                }
+                Ire[tri(n, m)] = nr;
+                Iim[tri(n, m)] = ni;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+            }
+        }
+        __syncthreads();
+        for (int s = 0; s < 3; s++) {
+            int n = on[s];
+            if (n < 0) continue;
+            int m = om[s];
+            double sr = 0, si = 0;
+            for (int k = 0; k <= p; k++) {
+                double fk = ldexp(1.0, delta * k);
+                double tr = 0, ti = 0;
+                for (int l = -k; l <= k; l++) {
+                    int al = l < 0 ? -l : l;
+                    double mre = Ms[cidx_re(k, al)], mim = al > 0 ? Ms[cidx_im(k, al)] : 0.0;
+                    if (l < 0) {
+                        mim = -mim;
+                        if (al & 1) {
+                            mre = -mre;
+                            mim = -mim;
+                        }
+                    }
+                    int nn = n + k, mm = m + l;
+                    int amm = mm < 0 ? -mm : mm;
+                    double ire = Ire[tri(nn, amm)], iim = Iim[tri(nn, amm)];
+                    if (mm < 0) {
+                        iim = -iim;
+                        if (amm & 1) {
+                            ire = -ire;
+                            iim = -iim;
+                        }
+                    }
+                    tr += mre * ire - mim * iim;
+                    ti += mre * iim + mim * ire;
+                }
+                sr += fk * tr;
+                si += fk * ti;
+            }
+            if (n & 1) {
+                sr = -sr;
+                si = -si;
+            }
+            accr[s] += sr;
+            acci[s] += si;
+        }
+    }
+    double *out = L + (int64_t)A * P;
+    for (int s = 0; s < 3; s++) {
+        int n = on[s];
+        if (n < 0) continue;
+        int m = om[s];
+        out[cidx_re(n, m)] = accr[s];
+        if (m > 0) out[cidx_im(n, m)] = acci[s];
+    }
+}
+
+}  // namespace
+
+void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
+                     const double *ys, const double *zs, const double *qs, double *phi, double *fld, hipStream_t s) {
+    if (ncell == 0) return;
+    hipLaunchKernelGGL(k_p2p_fp64, dim3(ncell), dim3(kP2P64Threads), 0, s, g.c, ncell, ptr, src, xs, ys, zs, qs, phi,
+                       fld);
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
+                     double *L, hipStream_t s) {
+    if (ncell == 0) return;
+    hipLaunchKernelGGL(k_m2l_fp64, dim3(ncell), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, M, L);
+    FMM_LAUNCH_CHECK();
+}
+
+}  // namespace fmm

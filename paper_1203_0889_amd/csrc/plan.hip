@@ -1,0 +1,691 @@
+// Host side of the C ABI declared in include/fmm.h: the plan object, argument
+// checks, the call-order state machine and the stream-ordered pipelines
+//   build_tree : bounding cube -> keys -> radix sort -> octree -> traversal -> CSR
+//   upward     : P2M -> M2M
+//   evaluate   : M2L + P2P -> L2L -> L2P -> outputs in input order
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "../../include/fmm.h"
+#include "near_far.h"
+#include "tree.h"
+
+namespace fmm {
+
+hipError_t DevBuf::grow(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    size_t nb = want + want / 4 + 256;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) return e;
+    if (ptr) {
+        hipDeviceSynchronize();
+        hipFree(ptr);
+    }
+    ptr = p;
+    bytes = nb;
+    return hipSuccess;
+}
+
+hipError_t DevBuf::grow_keep(size_t want, hipStream_t s) {
+    if (want <= bytes) return hipSuccess;
+    size_t nb = want + want / 2 + 256;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) return e;
+    if (ptr) {
+        e = hipMemcpyAsync(p, ptr, bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        hipStreamSynchronize(s);
+        hipFree(ptr);
+    }
+    ptr = p;
+    bytes = nb;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+}  // namespace fmm
+
+using fmm::DevBuf;
+
+enum { kStateCreated = 0, kStateBuilt = 1, kStateUp = 2, kStateEval = 3 };
+
+enum Stage {
+    ST_BOX = 0, ST_SORT, ST_TREE, ST_LISTS, ST_CSR, ST_P2M, ST_M2M, ST_M2L, ST_P2P, ST_L2L, ST_L2P, ST_OUT,
+    ST_COUNT
+};
+static const char *kStageNames[16] = {"bbox_keys", "sort", "tree", "traverse", "csr", "p2m", "m2m", "m2l", "p2p",
+                                      "l2l", "l2p", "output", "", "", "", ""};
+
+struct fmm_plan {
+    fmm_params prm;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int state = kStateCreated;
+    int64_t n = 0;
+    int32_t n_inst = 0;
+    std::vector<int64_t> h_off;
+    // particles
+    DevBuf off, ord, flag, box, scale;
+    DevBuf keys, kalt, idx, valt, ikey, ialt, rank, ralt, tmp;
+    DevBuf xs, ys, zs, qs, leaf_of;
+    // tree
+    DevBuf cb[10];
+    int64_t cell_cap = 0;
+    DevBuf bounds, nch, counters;
+    int64_t ncell = 0, nleaf = 0, nm2l = 0, np2p = 0;
+    std::vector<int32_t> level_begin;  // level l cells: [level_begin[l], level_begin[l+1])
+    // lists
+    DevBuf front[2], m2l_pairs, p2p_pairs, pair_alt, m2l_ptr, m2l_src, p2p_ptr, p2p_src;
+    int64_t cap_front = 0, cap_m2l = 0, cap_p2p = 0;
+    // expansions and fields
+    DevBuf M, L, ops_m2m, ops_l2l;
+    int ops_p = -1;
+    DevBuf phi_near, fld_near, phi_far, fld_far;
+    fmm::NearFarState nf;
+    fmm_tuning tuning;
+    hipEvent_t ev_beg[ST_COUNT] = {}, ev_end[ST_COUNT] = {};
+    hipEvent_t beg_of[ST_COUNT] = {};
+    hipEvent_t last_ev = nullptr;
+    bool ev_ok = false;
+    bool ev_used[ST_COUNT] = {};
+};
+
+namespace {
+
+fmm_status fail(fmm_plan *p, fmm_status st, const std::string &msg) {
+    if (p) p->err = msg;
+    return st;
+}
+
+fmm::CellArrays cells_of(fmm_plan *p) {
+    fmm::CellArrays c;
+    int32_t **f[10] = {&c.level, &c.ix, &c.iy, &c.iz, &c.first, &c.count, &c.child, &c.nchild, &c.parent, &c.inst};
+    for (int i = 0; i < 10; i++) *f[i] = p->cb[i].as<int32_t>();
+    return c;
+}
+
+void ensure_cells(fmm_plan *p, int64_t want) {
+    if (want <= p->cell_cap) return;
+    for (int i = 0; i < 10; i++) FMM_HIP_CHECK(p->cb[i].grow_keep((size_t)want * sizeof(int32_t), p->stream));
+    int64_t cap = (int64_t)(p->cb[0].bytes / sizeof(int32_t));
+    for (int i = 1; i < 10; i++) cap = std::min<int64_t>(cap, (int64_t)(p->cb[i].bytes / sizeof(int32_t)));
+    p->cell_cap = cap;
+}
+
+// Stage timing: record() opens a stage; mark() closes one, timed from the
+// most recent event (the opening one, or the end of the previous stage).
+void record(fmm_plan *p, int stage) {
+    if (!p->ev_ok) return;
+    hipEventRecord(p->ev_beg[stage], p->stream);
+    p->last_ev = p->ev_beg[stage];
+}
+
+void mark(fmm_plan *p, int stage) {
+    if (!p->ev_ok || !p->last_ev) return;
+    hipEventRecord(p->ev_end[stage], p->stream);
+    p->beg_of[stage] = p->last_ev;
+    p->last_ev = p->ev_end[stage];
+    p->ev_used[stage] = true;
+}
+
+void sync_read(fmm_plan *p, void *host, const void *dev, size_t bytes) {
+    FMM_HIP_CHECK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, p->stream));
+    FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+}
+
+int bits_for(int64_t n) {
+    int b = 1;
+    while (((int64_t)1 << b) < n) b++;
+    return b;
+}
+
+fmm::Geometry geom(fmm_plan *p) {
+    fmm::Geometry g;
+    g.box = p->box.as<double>();
+    g.c = cells_of(p);
+    return g;
+}
+
+void do_build(fmm_plan *p, const double *pos, const double *q) {
+    hipStream_t s = p->stream;
+    const int64_t n = p->n;
+    const int ni = p->n_inst;
+    FMM_HIP_CHECK(p->off.grow((ni + 1) * sizeof(int64_t)));
+    FMM_HIP_CHECK(hipMemcpyAsync(p->off.ptr, p->h_off.data(), (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    FMM_HIP_CHECK(p->ord.grow(6 * ni * sizeof(unsigned long long)));
+    FMM_HIP_CHECK(p->flag.grow(16 * sizeof(int)));
+    FMM_HIP_CHECK(p->box.grow(4 * ni * sizeof(double)));
+    FMM_HIP_CHECK(p->scale.grow(ni * sizeof(double)));
+    FMM_HIP_CHECK(hipMemsetAsync(p->flag.ptr, 0, 16 * sizeof(int), s));
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    FMM_HIP_CHECK(p->keys.grow(nn * 8));
+    FMM_HIP_CHECK(p->kalt.grow(nn * 8));
+    FMM_HIP_CHECK(p->idx.grow(nn * 4));
+    FMM_HIP_CHECK(p->valt.grow(nn * 4));
+    FMM_HIP_CHECK(p->xs.grow(nn * 8));
+    FMM_HIP_CHECK(p->ys.grow(nn * 8));
+    FMM_HIP_CHECK(p->zs.grow(nn * 8));
+    FMM_HIP_CHECK(p->qs.grow(nn * 8));
+    FMM_HIP_CHECK(p->leaf_of.grow(nn * 4));
+    FMM_HIP_CHECK(p->tmp.grow(std::max(fmm::radix_tmp_elems(n), fmm::scan_tmp_elems(n)) * sizeof(int32_t)));
+    if (ni > 1) {
+        FMM_HIP_CHECK(p->ikey.grow(nn * 4));
+        FMM_HIP_CHECK(p->ialt.grow(nn * 4));
+        FMM_HIP_CHECK(p->rank.grow(nn * 4));
+        FMM_HIP_CHECK(p->ralt.grow(nn * 4));
+    }
+    const double *pbox = p->prm.box_min;
+    double ubox[4] = {pbox[0], pbox[1], pbox[2], p->prm.box_side};
+    bool user = (p->prm.flags & FMM_FLAG_USER_BOX) != 0;
+
+    record(p, ST_BOX);
+    fmm::launch_bbox(pos, n, p->off.as<int64_t>(), ni, p->ord.as<unsigned long long>(), p->flag.as<int>(), s);
+    fmm::launch_box_finish(p->ord.as<unsigned long long>(), ni, p->off.as<int64_t>(), user, ubox, p->box.as<double>(),
+                           p->scale.as<double>(), s);
+    fmm::launch_keys(pos, n, p->off.as<int64_t>(), ni, p->box.as<double>(), p->scale.as<double>(),
+                     p->keys.as<uint64_t>(), p->idx.as<uint32_t>(), s);
+    mark(p, ST_BOX);
+    fmm::radix_sort_u64(p->keys.as<uint64_t>(), p->idx.as<uint32_t>(), p->kalt.as<uint64_t>(), p->valt.as<uint32_t>(), n,
+                        0, 63, p->tmp.as<int32_t>(), s);
+    fmm::sort_by_instance(p->keys.as<uint64_t>(), p->idx.as<uint32_t>(), p->kalt.as<uint64_t>(), p->valt.as<uint32_t>(),
+                          p->ikey.as<uint32_t>(), p->ialt.as<uint32_t>(), p->rank.as<uint32_t>(),
+                          p->ralt.as<uint32_t>(), n, p->off.as<int64_t>(), ni, p->tmp.as<int32_t>(), s);
+    fmm::launch_gather(pos, q, p->idx.as<uint32_t>(), n, p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
+                       p->qs.as<double>(), s);
+    mark(p, ST_SORT);
+
+    // ---- octree, level by level
+    ensure_cells(p, std::max<int64_t>(2 * ni, n / std::max(1, p->prm.ncrit) * 3 + 64));
+    fmm::launch_roots(p->off.as<int64_t>(), ni, cells_of(p), s);
+    p->level_begin.assign(1, 0);
+    int32_t lb = 0, le = ni;
+    p->level_begin.push_back(le);
+    for (int level = 0; level < p->prm.max_level && le > lb; level++) {
+        int64_t ncur = le - lb;
+        FMM_HIP_CHECK(p->bounds.grow((size_t)ncur * 9 * sizeof(int32_t)));
+        FMM_HIP_CHECK(p->nch.grow((size_t)(ncur + 1) * sizeof(int32_t) * 2));
+        FMM_HIP_CHECK(p->tmp.grow(std::max(p->tmp.bytes, fmm::scan_tmp_elems(ncur) * sizeof(int32_t))));
+        int32_t *nch = p->nch.as<int32_t>();
+        int32_t *off = nch + (ncur + 1);
+        fmm::launch_tree_count(cells_of(p), lb, le, p->prm.ncrit, p->prm.max_level, p->keys.as<uint64_t>(),
+                               p->bounds.as<int32_t>(), nch, s);
+        FMM_HIP_CHECK(hipMemcpyAsync(off, nch, ncur * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        fmm::exclusive_scan_i32(off, ncur, off + ncur, p->tmp.as<int32_t>(), s);
+        int32_t total = 0;
+        sync_read(p, &total, off + ncur, sizeof(int32_t));
+        if (total == 0) break;
+        ensure_cells(p, (int64_t)le + total);
+        fmm::launch_tree_write(cells_of(p), lb, le, p->bounds.as<int32_t>(), nch, off, s);
+        lb = le;
+        le = le + total;
+        p->level_begin.push_back(le);
+    }
+    p->ncell = le;
+    fmm::launch_leaf_of(cells_of(p), (int32_t)p->ncell, p->leaf_of.as<int32_t>(), s);
+    mark(p, ST_TREE);
+
+    int bad = 0;
+    sync_read(p, &bad, p->flag.ptr, sizeof(int));
+    if (bad) throw std::invalid_argument("non-finite particle coordinate");
+
+    // ---- dual tree traversal, breadth first
+    const int64_t ncell = p->ncell;
+    if (p->cap_front < 1024) p->cap_front = std::max<int64_t>(4096, 8 * ncell);
+    p->cap_front = std::max<int64_t>(p->cap_front, 2 * (int64_t)ni);
+    if (p->cap_m2l < 1024) p->cap_m2l = std::max<int64_t>(4096, 64 * ncell);
+    if (p->cap_p2p < 1024) p->cap_p2p = std::max<int64_t>(4096, 32 * ncell);
+    FMM_HIP_CHECK(p->front[0].grow(p->cap_front * sizeof(int2)));
+    FMM_HIP_CHECK(p->front[1].grow(p->cap_front * sizeof(int2)));
+    FMM_HIP_CHECK(p->m2l_pairs.grow(p->cap_m2l * 8));
+    FMM_HIP_CHECK(p->p2p_pairs.grow(p->cap_p2p * 8));
+    FMM_HIP_CHECK(p->counters.grow(8 * sizeof(int32_t)));
+    int32_t *ctr = p->counters.as<int32_t>();
+    fmm::launch_init_frontier(p->off.as<int64_t>(), ni, p->front[0].as<int2>(), ctr, s);
+    int32_t hc[3];
+    sync_read(p, hc, ctr, 3 * sizeof(int32_t));
+    int32_t nf = hc[0], have_m2l = 0, have_p2p = 0;
+    int cur = 0;
+    uint32_t ta = (uint32_t)p->prm.theta_num, tb = (uint32_t)p->prm.theta_den;
+    while (nf > 0) {
+        for (;;) {
+            int32_t reset[3] = {0, have_m2l, have_p2p};
+            FMM_HIP_CHECK(hipMemcpyAsync(ctr, reset, sizeof(reset), hipMemcpyHostToDevice, s));
+            fmm::PairBuf pb{p->m2l_pairs.as<uint64_t>(), p->p2p_pairs.as<uint64_t>(), (int32_t)p->cap_m2l,
+                            (int32_t)p->cap_p2p};
+            fmm::launch_traverse(cells_of(p), p->front[cur].as<int2>(), nf, p->front[cur ^ 1].as<int2>(),
+                                 (int32_t)p->cap_front, pb, ctr, ta, tb, s);
+            sync_read(p, hc, ctr, 3 * sizeof(int32_t));
+            bool redo = false;
+            if (hc[0] > p->cap_front) {
+                p->cap_front = (int64_t)hc[0] * 2;
+                // the current frontier must survive: keep front[cur]
+                FMM_HIP_CHECK(p->front[cur].grow_keep(p->cap_front * sizeof(int2), s));
+                FMM_HIP_CHECK(p->front[cur ^ 1].grow(p->cap_front * sizeof(int2)));
+                redo = true;
+            }
+            if (hc[1] > p->cap_m2l) {
+                p->cap_m2l = (int64_t)hc[1] * 2;
+                FMM_HIP_CHECK(p->m2l_pairs.grow_keep(p->cap_m2l * 8, s));
+                redo = true;
+            }
+            if (hc[2] > p->cap_p2p) {
+                p->cap_p2p = (int64_t)hc[2] * 2;
+                FMM_HIP_CHECK(p->p2p_pairs.grow_keep(p->cap_p2p * 8, s));
+                redo = true;
+            }
+            if (!redo) break;
+        }
+        have_m2l = hc[1];
+        have_p2p = hc[2];
+        nf = hc[0];
+        cur ^= 1;
+    }
+    p->nm2l = have_m2l;
+    p->np2p = have_p2p;
+    mark(p, ST_LISTS);
+
+    // ---- canonical CSR lists sorted by (target, source)
+    int bits = bits_for(ncell);
+    int64_t mx = std::max<int64_t>(std::max(p->nm2l, p->np2p), 1);
+    FMM_HIP_CHECK(p->pair_alt.grow(mx * 8));
+    FMM_HIP_CHECK(p->tmp.grow(std::max(p->tmp.bytes, fmm::radix_tmp_elems(mx) * sizeof(int32_t))));
+    FMM_HIP_CHECK(p->m2l_ptr.grow((ncell + 1) * 4));
+    FMM_HIP_CHECK(p->p2p_ptr.grow((ncell + 1) * 4));
+    FMM_HIP_CHECK(p->m2l_src.grow(std::max<int64_t>(p->nm2l, 1) * 4));
+    FMM_HIP_CHECK(p->p2p_src.grow(std::max<int64_t>(p->np2p, 1) * 4));
+    uint64_t *lists[2] = {p->m2l_pairs.as<uint64_t>(), p->p2p_pairs.as<uint64_t>()};
+    int64_t cnts[2] = {p->nm2l, p->np2p};
+    int32_t *ptrs[2] = {p->m2l_ptr.as<int32_t>(), p->p2p_ptr.as<int32_t>()};
+    int32_t *srcs[2] = {p->m2l_src.as<int32_t>(), p->p2p_src.as<int32_t>()};
+    for (int t = 0; t < 2; t++) {
+        fmm::launch_repack(lists[t], cnts[t], bits, s);
+        fmm::radix_sort_u64(lists[t], nullptr, p->pair_alt.as<uint64_t>(), nullptr, cnts[t], 0, 2 * bits,
+                            p->tmp.as<int32_t>(), s);
+        fmm::launch_csr(lists[t], cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], s);
+    }
+    mark(p, ST_CSR);
+    // leaves
+    {
+        std::vector<int32_t> ch(ncell);
+        sync_read(p, ch.data(), p->cb[6].ptr, ncell * sizeof(int32_t));
+        p->nleaf = std::count(ch.begin(), ch.end(), -1);
+    }
+}
+
+void ensure_ops(fmm_plan *p) {
+    int pp = p->prm.p;
+    if (p->ops_p == pp) return;
+    const int P = fmm::ncoef(pp);
+    std::vector<double> a = fmm::build_translation_ops(pp, 0), b = fmm::build_translation_ops(pp, 1);
+    FMM_HIP_CHECK(p->ops_m2m.grow(a.size() * 8));
+    FMM_HIP_CHECK(p->ops_l2l.grow(b.size() * 8));
+    FMM_HIP_CHECK(hipMemcpy(p->ops_m2m.ptr, a.data(), a.size() * 8, hipMemcpyHostToDevice));
+    FMM_HIP_CHECK(hipMemcpy(p->ops_l2l.ptr, b.data(), b.size() * 8, hipMemcpyHostToDevice));
+    (void)P;
+    p->ops_p = pp;
+}
+
+void do_upward(fmm_plan *p) {
+    hipStream_t s = p->stream;
+    const int P = fmm::ncoef(p->prm.p);
+    ensure_ops(p);
+    FMM_HIP_CHECK(p->M.grow((size_t)std::max<int64_t>(p->ncell, 1) * P * 8));
+    fmm::Geometry g = geom(p);
+    record(p, ST_P2M);
+    fmm::launch_p2m(g, (int32_t)p->ncell, p->prm.p, p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
+                    p->qs.as<double>(), p->M.as<double>(), s);
+    mark(p, ST_P2M);
+    int depth = (int)p->level_begin.size() - 1;  // number of levels present
+    for (int l = depth - 2; l >= 0; l--)
+        fmm::launch_m2m_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_m2m.as<double>(),
+                              p->M.as<double>(), s);
+    mark(p, ST_M2M);
+}
+
+void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double *energy) {
+    hipStream_t s = p->stream;
+    const int P = fmm::ncoef(p->prm.p);
+    const size_t nn = (size_t)std::max<int64_t>(p->n, 1);
+    FMM_HIP_CHECK(p->L.grow((size_t)std::max<int64_t>(p->ncell, 1) * P * 8));
+    FMM_HIP_CHECK(p->phi_near.grow(nn * 8));
+    FMM_HIP_CHECK(p->fld_near.grow(nn * 24));
+    FMM_HIP_CHECK(p->phi_far.grow(nn * 8));
+    FMM_HIP_CHECK(p->fld_far.grow(nn * 24));
+    fmm::Geometry g = geom(p);
+    const int32_t ncell = (int32_t)p->ncell;
+    record(p, ST_M2L);
+    if (p->prm.precision == FMM_PREC_FP64) {
+        fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->M.as<double>(),
+                             p->L.as<double>(), s);
+        mark(p, ST_M2L);
+        fmm::launch_p2p_fp64(g, ncell, p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(), p->xs.as<double>(),
+                             p->ys.as<double>(), p->zs.as<double>(), p->qs.as<double>(), p->phi_near.as<double>(),
+                             p->fld_near.as<double>(), s);
+        mark(p, ST_P2P);
+    } else {
+        fmm::NearFarArgs a;
+        a.g = g;
+        a.ncell = ncell;
+        a.nleaf = p->nleaf;
+        a.n = p->n;
+        a.p = p->prm.p;
+        a.m2l_ptr = p->m2l_ptr.as<int32_t>();
+        a.m2l_src = p->m2l_src.as<int32_t>();
+        a.p2p_ptr = p->p2p_ptr.as<int32_t>();
+        a.p2p_src = p->p2p_src.as<int32_t>();
+        a.xs = p->xs.as<double>();
+        a.ys = p->ys.as<double>();
+        a.zs = p->zs.as<double>();
+        a.qs = p->qs.as<double>();
+        a.M = p->M.as<double>();
+        a.L = p->L.as<double>();
+        a.phi = p->phi_near.as<double>();
+        a.fld = p->fld_near.as<double>();
+        a.tuning = p->tuning;
+        fmm::run_near_far_mixed(p->nf, a, s);
+        mark(p, ST_M2L);
+        mark(p, ST_P2P);
+    }
+    int depth = (int)p->level_begin.size() - 1;
+    for (int l = 1; l < depth; l++)
+        fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_l2l.as<double>(),
+                              p->L.as<double>(), s);
+    mark(p, ST_L2L);
+    fmm::launch_l2p(g, p->n, p->prm.p, p->leaf_of.as<int32_t>(), p->xs.as<double>(), p->ys.as<double>(),
+                    p->zs.as<double>(), p->L.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), s);
+    mark(p, ST_L2P);
+    fmm::launch_finalize(p->n, p->idx.as<uint32_t>(), p->qs.as<double>(), p->phi_near.as<double>(),
+                         p->fld_near.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), phi, field, force,
+                         s);
+    if (energy)
+        fmm::launch_energy(p->off.as<int64_t>(), p->n_inst, p->qs.as<double>(), p->phi_near.as<double>(),
+                           p->phi_far.as<double>(), energy, s);
+    mark(p, ST_OUT);
+}
+
+template <class F>
+fmm_status guarded(fmm_plan *p, F &&f) {
+    try {
+        if (p) {
+            hipError_t e = hipSetDevice(p->device);
+            if (e != hipSuccess) return fail(p, FMM_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+        }
+        return f();
+    } catch (const fmm::HipError &e) {
+        if (e.err == hipErrorOutOfMemory) return fail(p, FMM_ERR_OOM, std::string("out of device memory: ") + e.what);
+        return fail(p, FMM_ERR_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
+    } catch (const std::invalid_argument &e) {
+        return fail(p, FMM_ERR_INVALID_ARG, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(p, FMM_ERR_OOM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(p, FMM_ERR_DEVICE, e.what());
+    }
+}
+
+fmm_status check_params(const fmm_params *q, std::string *why) {
+    if (q->p < 0 || q->p > fmm::kMaxP) return *why = "p must be in [0, 16]", FMM_ERR_INVALID_ARG;
+    if (q->ncrit < 1) return *why = "ncrit must be >= 1", FMM_ERR_INVALID_ARG;
+    if (q->theta_num < 1 || q->theta_den < 1 || q->theta_num > 100 || q->theta_den > 100 ||
+        q->theta_num >= q->theta_den)
+        return *why = "theta must be num/den with 1 <= num < den <= 100", FMM_ERR_INVALID_ARG;
+    if (q->max_level < 1 || q->max_level > fmm::kLevels) return *why = "max_level must be in [1, 21]", FMM_ERR_INVALID_ARG;
+    if (q->precision != FMM_PREC_FP64 && q->precision != FMM_PREC_MIXED)
+        return *why = "unknown precision", FMM_ERR_INVALID_ARG;
+    if (q->flags & ~(uint32_t)FMM_FLAG_USER_BOX) return *why = "unknown flag", FMM_ERR_INVALID_ARG;
+    if ((q->flags & FMM_FLAG_USER_BOX) &&
+        !(q->box_side > 0 && std::isfinite(q->box_side) && std::isfinite(q->box_min[0]) &&
+          std::isfinite(q->box_min[1]) && std::isfinite(q->box_min[2])))
+        return *why = "user box must be finite with side > 0", FMM_ERR_INVALID_ARG;
+    return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fmm_status fmm_default_params(fmm_params *params) {
+    if (!params) return FMM_ERR_INVALID_ARG;
+    std::memset(params, 0, sizeof(*params));
+    params->p = 8;
+    params->ncrit = 64;
+    params->theta_num = 1;
+    params->theta_den = 2;
+    params->max_level = fmm::kLevels;
+    params->precision = FMM_PREC_MIXED;
+    params->flags = 0;
+    params->box_side = 1.0;
+    return FMM_OK;
+}
+
+fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fmm_plan **out) {
+    if (!params || !out) return FMM_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::string why;
+    fmm_status st = check_params(params, &why);
+    if (st != FMM_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FMM_ERR_INVALID_ARG;
+    fmm_plan *p = new (std::nothrow) fmm_plan();
+    if (!p) return FMM_ERR_OOM;
+    p->prm = *params;
+    p->device = device;
+    p->stream = (hipStream_t)hip_stream;
+    p->tuning = fmm::default_tuning();
+    if (hipSetDevice(device) != hipSuccess) {
+        delete p;
+        return FMM_ERR_DEVICE;
+    }
+    p->ev_ok = true;
+    for (int i = 0; i < ST_COUNT; i++)
+        if (hipEventCreate(&p->ev_beg[i]) != hipSuccess || hipEventCreate(&p->ev_end[i]) != hipSuccess)
+            p->ev_ok = false;
+    *out = p;
+    return FMM_OK;
+}
+
+fmm_status fmm_destroy(fmm_plan *p) {
+    if (!p) return FMM_OK;
+    hipSetDevice(p->device);
+    hipStreamSynchronize(p->stream);
+    DevBuf *all[] = {&p->off, &p->ord, &p->flag, &p->box, &p->scale, &p->keys, &p->kalt, &p->idx, &p->valt,
+                     &p->ikey, &p->ialt, &p->rank, &p->ralt, &p->tmp, &p->xs, &p->ys, &p->zs, &p->qs,
+                     &p->leaf_of, &p->bounds, &p->nch, &p->counters, &p->front[0], &p->front[1], &p->m2l_pairs,
+                     &p->p2p_pairs, &p->pair_alt, &p->m2l_ptr, &p->m2l_src, &p->p2p_ptr, &p->p2p_src, &p->M,
+                     &p->L, &p->ops_m2m, &p->ops_l2l, &p->phi_near, &p->fld_near, &p->phi_far, &p->fld_far};
+    for (DevBuf *b : all) b->release();
+    for (auto &b : p->cb) b.release();
+    fmm::release_near_far(p->nf);
+    for (int i = 0; i < ST_COUNT; i++) {
+        if (p->ev_beg[i]) hipEventDestroy(p->ev_beg[i]);
+        if (p->ev_end[i]) hipEventDestroy(p->ev_end[i]);
+    }
+    delete p;
+    return FMM_OK;
+}
+
+fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, const double *pos, const double *q) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (n_inst < 1 || !offsets) return fail(p, FMM_ERR_INVALID_ARG, "n_inst >= 1 and offsets required");
+    if (offsets[0] != 0) return fail(p, FMM_ERR_INVALID_ARG, "offsets[0] must be 0");
+    for (int k = 0; k < n_inst; k++)
+        if (offsets[k + 1] < offsets[k]) return fail(p, FMM_ERR_INVALID_ARG, "offsets must be non-decreasing");
+    int64_t n = offsets[n_inst];
+    if (n >= ((int64_t)1 << 31) - 1) return fail(p, FMM_ERR_INVALID_ARG, "too many particles (limit 2^31 - 2)");
+    if (n > 0 && (!pos || !q)) return fail(p, FMM_ERR_INVALID_ARG, "pos and q required");
+    return guarded(p, [&]() -> fmm_status {
+        p->state = kStateCreated;
+        p->n = n;
+        p->n_inst = n_inst;
+        p->h_off.assign(offsets, offsets + n_inst + 1);
+        for (bool &u : p->ev_used) u = false;
+        p->last_ev = nullptr;
+        do_build(p, pos, q);
+        p->state = kStateBuilt;
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_upward(fmm_plan *p) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateBuilt) return fail(p, FMM_ERR_STATE, "fmm_upward before fmm_build_tree");
+    return guarded(p, [&]() -> fmm_status {
+        do_upward(p);
+        p->state = kStateUp;
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_evaluate(fmm_plan *p, double *phi, double *field, double *force, double *energy) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateUp) return fail(p, FMM_ERR_STATE, "fmm_evaluate before fmm_upward");
+    return guarded(p, [&]() -> fmm_status {
+        do_evaluate(p, phi, field, force, energy);
+        p->state = kStateEval;
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_backward(fmm_plan *p, const double *grad_energy, double *grad_pos, double *grad_q) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateEval) return fail(p, FMM_ERR_STATE, "fmm_backward before fmm_evaluate");
+    if (!grad_energy) return fail(p, FMM_ERR_INVALID_ARG, "grad_energy required");
+    (void)grad_pos;
+    (void)grad_q;
+    return fail(p, FMM_ERR_UNSUPPORTED, "adjoint not available in this build");
+}
+
+fmm_status fmm_sync(fmm_plan *p) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    return guarded(p, [&]() -> fmm_status {
+        FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_get_counts(const fmm_plan *p, int64_t *ncell, int64_t *nleaf, int64_t *nm2l, int64_t *np2p) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateBuilt) return FMM_ERR_STATE;
+    if (ncell) *ncell = p->ncell;
+    if (nleaf) *nleaf = p->nleaf;
+    if (nm2l) *nm2l = p->nm2l;
+    if (np2p) *np2p = p->np2p;
+    return FMM_OK;
+}
+
+fmm_status fmm_copy_tree(const fmm_plan *cp, uint64_t *keys, int64_t *perm, int64_t *cells) {
+    fmm_plan *p = const_cast<fmm_plan *>(cp);
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateBuilt) return fail(p, FMM_ERR_STATE, "no tree");
+    return guarded(p, [&]() -> fmm_status {
+        const int64_t n = p->n;
+        if (n > 0 && (keys || perm)) {
+            std::vector<uint64_t> sk(n);
+            std::vector<uint32_t> ix(n);
+            FMM_HIP_CHECK(hipMemcpyAsync(sk.data(), p->keys.ptr, n * 8, hipMemcpyDeviceToHost, p->stream));
+            FMM_HIP_CHECK(hipMemcpyAsync(ix.data(), p->idx.ptr, n * 4, hipMemcpyDeviceToHost, p->stream));
+            FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+            for (int64_t r = 0; r < n; r++) {
+                if (keys) keys[ix[r]] = sk[r];
+                if (perm) perm[r] = ix[r];
+            }
+        }
+        if (cells && p->ncell > 0) {
+            std::vector<int32_t> col(p->ncell);
+            for (int f = 0; f < 10; f++) {
+                FMM_HIP_CHECK(hipMemcpyAsync(col.data(), p->cb[f].ptr, p->ncell * 4, hipMemcpyDeviceToHost, p->stream));
+                FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+                for (int64_t c = 0; c < p->ncell; c++) cells[c * 10 + f] = col[c];
+            }
+        }
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_copy_lists(const fmm_plan *cp, int64_t *m2l_ptr, int32_t *m2l_src, int64_t *p2p_ptr, int32_t *p2p_src) {
+    fmm_plan *p = const_cast<fmm_plan *>(cp);
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateBuilt) return fail(p, FMM_ERR_STATE, "no lists");
+    return guarded(p, [&]() -> fmm_status {
+        const int64_t nc1 = p->ncell + 1;
+        std::vector<int32_t> tmp(nc1);
+        int64_t *outs[2] = {m2l_ptr, p2p_ptr};
+        DevBuf *ptrs[2] = {&p->m2l_ptr, &p->p2p_ptr};
+        for (int t = 0; t < 2; t++) {
+            if (!outs[t]) continue;
+            FMM_HIP_CHECK(hipMemcpyAsync(tmp.data(), ptrs[t]->ptr, nc1 * 4, hipMemcpyDeviceToHost, p->stream));
+            FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+            for (int64_t i = 0; i < nc1; i++) outs[t][i] = tmp[i];
+        }
+        if (m2l_src && p->nm2l > 0)
+            FMM_HIP_CHECK(hipMemcpyAsync(m2l_src, p->m2l_src.ptr, p->nm2l * 4, hipMemcpyDeviceToHost, p->stream));
+        if (p2p_src && p->np2p > 0)
+            FMM_HIP_CHECK(hipMemcpyAsync(p2p_src, p->p2p_src.ptr, p->np2p * 4, hipMemcpyDeviceToHost, p->stream));
+        FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_get_tuning(const fmm_plan *p, fmm_tuning *t) {
+    if (!p || !t) return FMM_ERR_INVALID_ARG;
+    *t = p->tuning;
+    return FMM_OK;
+}
+
+fmm_status fmm_set_tuning(fmm_plan *p, const fmm_tuning *t) {
+    if (!p || !t) return FMM_ERR_INVALID_ARG;
+    if (t->queue_chunk < 1 || t->p2p_split < 1 || (t->m2l_block != 16 && t->m2l_block != 32) || t->grid_per_cu < 1 ||
+        t->grid_per_cu > 8)
+        return fail(p, FMM_ERR_INVALID_ARG, "tuning out of range");
+    p->tuning = *t;
+    return FMM_OK;
+}
+
+fmm_status fmm_get_stage_times(const fmm_plan *cp, double *times, const char **names) {
+    fmm_plan *p = const_cast<fmm_plan *>(cp);
+    if (!p || !times) return FMM_ERR_INVALID_ARG;
+    return guarded(p, [&]() -> fmm_status {
+        FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+        for (int i = 0; i < 16; i++) {
+            times[i] = 0.0;
+            if (names) names[i] = kStageNames[i];
+        }
+        if (!p->ev_ok) return FMM_OK;
+        for (int i = 0; i < ST_COUNT; i++) {
+            if (!p->ev_used[i]) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p->beg_of[i], p->ev_end[i]) == hipSuccess) times[i] = ms;
+        }
+        return FMM_OK;
+    });
+}
+
+const char *fmm_status_string(fmm_status s) {
+    switch (s) {
+        case FMM_OK: return "ok";
+        case FMM_ERR_INVALID_ARG: return "invalid argument";
+        case FMM_ERR_STATE: return "call out of order";
+        case FMM_ERR_OOM: return "out of memory";
+        case FMM_ERR_DEVICE: return "device error";
+        case FMM_ERR_CAPACITY: return "capacity exceeded";
+        case FMM_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *fmm_last_error(const fmm_plan *p) {
+    if (!p) return "null plan";
+    return p->err.c_str();
+}
+
+}  // extern "C"

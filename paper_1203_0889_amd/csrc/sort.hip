@@ -1,0 +1,254 @@
+// Device-wide exclusive scan and stable LSD radix sort (keys of the Morton
+// octree, Sec. 2.2, and of the interaction-pair lists).
+//
+// Radix sort: 8-bit digits; per pass three launches -- per-tile digit
+// histograms, one exclusive scan over the (digit-major, tile-minor) count
+// table, and a stable scatter.  Inside a tile each wave64 ranks its keys with
+// ballot-based peer masks (lanes holding the same digit), so ranks follow the
+// input order and the sort is stable.
+#include "common.h"
+
+namespace fmm {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across a block of kScanThreads;
+// returns the exclusive prefix and writes the block total to *total.
+__device__ inline int block_exclusive_scan(int v, int *total) {
+    __shared__ int wsum[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = wave_inclusive_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kScanThreads / 64; i++) {
+        if (i < w) base += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+__global__ void k_scan_reduce(const int32_t *__restrict__ data, int64_t n, int32_t *__restrict__ sums) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++)
+        if (base + i < n) s += data[base + i];
+    int tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Single block, 256 threads: exclusive scan of nb block sums in chunks.
+__global__ void k_scan_top(int32_t *__restrict__ sums, int64_t nb, int32_t *__restrict__ total) {
+    int carry = 0;
+    for (int64_t c = 0; c < nb; c += kScanTile) {
+        int64_t base = c + (int64_t)threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int s = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) {
+            v[i] = base + i < nb ? sums[base + i] : 0;
+            s += v[i];
+        }
+        int tot;
+        int pre = block_exclusive_scan(s, &tot) + carry;
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) {
+            if (base + i < nb) sums[base + i] = pre;
+            pre += v[i];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ void k_scan_down(int32_t *__restrict__ data, int64_t n, const int32_t *__restrict__ sums) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        v[i] = base + i < n ? data[base + i] : 0;
+        s += v[i];
+    }
+    int tot;
+    int pre = block_exclusive_scan(s, &tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        if (base + i < n) data[base + i] = pre;
+        pre += v[i];
+    }
+}
+
+// ---------------------------------------------------------------- radix sort
+
+constexpr int kRsThreads = 256;
+constexpr int kRsWaves = kRsThreads / 64;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr int kRsWaveTile = 64 * kRsItems;
+
+template <class K>
+__global__ void __launch_bounds__(kRsThreads) k_rs_hist(const K *__restrict__ kin, int64_t n, int shift,
+                                                        int nbits, int32_t *__restrict__ counts, int nblocks) {
+    __shared__ int hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int mask = (1 << nbits) - 1;
+    int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kRsWaveTile + lane;
+#pragma unroll 4
+    for (int it = 0; it < kRsItems; it++) {
+        int64_t i = base + it * 64;
+        if (i < n) atomicAdd(&hist[(int)((kin[i] >> shift) & (K)mask)], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+template <class K>
+__global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                           K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
+                                                           int shift, int nbits, const int32_t *__restrict__ offs,
+                                                           int nblocks) {
+    __shared__ int wcount[kRsWaves][256];
+    __shared__ int wbase[kRsWaves][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int mask = (1 << nbits) - 1;
+    for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&wcount[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kRsWaveTile + lane;
+    K key[kRsItems];
+    uint32_t val[kRsItems];
+    int rank[kRsItems];
+#pragma unroll
+    for (int it = 0; it < kRsItems; it++) {
+        int64_t i = base + it * 64;
+        bool valid = i < n;
+        K k = valid ? kin[i] : (K)0;
+        key[it] = k;
+        val[it] = (valid && vin) ? vin[i] : 0u;
+        int d = (int)((k >> shift) & (K)mask);
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < nbits; b++) {
+            uint64_t m = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        int r = __popcll(peers & lt_mask);
+        int cnt = __popcll(peers);
+        int prior = valid ? wcount[w][d] : 0;
+        if (valid && r == 0) wcount[w][d] = prior + cnt;
+        rank[it] = prior + r;
+    }
+    __syncthreads();
+    {
+        int d = threadIdx.x;  // 256 threads == 256 digits
+        int run = offs[(int64_t)d * nblocks + blockIdx.x];
+#pragma unroll
+        for (int ww = 0; ww < kRsWaves; ww++) {
+            wbase[ww][d] = run;
+            run += wcount[ww][d];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRsItems; it++) {
+        int64_t i = base + it * 64;
+        if (i < n) {
+            int d = (int)((key[it] >> shift) & (K)mask);
+            int pos = wbase[w][d] + rank[it];
+            kout[pos] = key[it];
+            if (vout) vout[pos] = val[it];
+        }
+    }
+}
+
+template <class K>
+void radix_sort_impl(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, int bit_lo, int bit_hi,
+                     int32_t *d_tmp, hipStream_t s) {
+    if (n <= 1 || bit_hi <= bit_lo) return;
+    const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
+    int32_t *counts = d_tmp;
+    int32_t *scan_tmp = d_tmp + (int64_t)256 * nblocks;
+    K *ka = kin, *kb = kalt;
+    uint32_t *va = vin, *vb = vin ? valt : nullptr;
+    int passes = 0;
+    for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+        int nbits = bit_hi - shift < 8 ? bit_hi - shift : 8;
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(kRsThreads), 0, s, ka, n, shift, nbits, counts, nblocks);
+        FMM_LAUNCH_CHECK();
+        exclusive_scan_i32(counts, (int64_t)256 * nblocks, nullptr, scan_tmp, s);
+        hipLaunchKernelGGL(k_rs_scatter<K>, dim3(nblocks), dim3(kRsThreads), 0, s, ka, va, kb, vb, n, shift, nbits,
+                           counts, nblocks);
+        FMM_LAUNCH_CHECK();
+        K *tk = ka;
+        ka = kb;
+        kb = tk;
+        uint32_t *tv = va;
+        va = vb;
+        vb = tv;
+        passes++;
+    }
+    if (passes & 1) {
+        FMM_HIP_CHECK(hipMemcpyAsync(kin, ka, n * sizeof(K), hipMemcpyDeviceToDevice, s));
+        if (vin) FMM_HIP_CHECK(hipMemcpyAsync(vin, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
+}
+
+}  // namespace
+
+size_t scan_tmp_elems(int64_t n) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return (size_t)(nb + 1);
+}
+
+void exclusive_scan_i32(int32_t *d_data, int64_t n, int32_t *d_total, int32_t *d_tmp, hipStream_t s) {
+    if (n <= 0) {
+        if (d_total) FMM_HIP_CHECK(hipMemsetAsync(d_total, 0, sizeof(int32_t), s));
+        return;
+    }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_data, n, d_tmp);
+    FMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, d_tmp, nb, d_total);
+    FMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_data, n, d_tmp);
+    FMM_LAUNCH_CHECK();
+}
+
+size_t radix_tmp_elems(int64_t n) {
+    int64_t nblocks = (n + kRsTile - 1) / kRsTile;
+    return (size_t)(256 * nblocks) + scan_tmp_elems(256 * nblocks) + 64;
+}
+
+void radix_sort_u64(uint64_t *kin, uint32_t *vin, uint64_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
+                    int bit_hi, int32_t *d_tmp, hipStream_t s) {
+    radix_sort_impl<uint64_t>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s);
+}
+
+void radix_sort_u32(uint32_t *kin, uint32_t *vin, uint32_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
+                    int bit_hi, int32_t *d_tmp, hipStream_t s) {
+    radix_sort_impl<uint32_t>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s);
+}
+
+}  // namespace fmm

@@ -1,0 +1,83 @@
+// Internal launchers of the tree, list and expansion kernels.
+#pragma once
+
+#include "common.h"
+
+namespace fmm {
+
+// Structure-of-arrays cell table.  Cells are numbered by level, then
+// instance, then Morton prefix.
+struct CellArrays {
+    int32_t *level, *ix, *iy, *iz;  // octree level and integer cell coordinates
+    int32_t *first, *count;         // particle range in sorted order
+    int32_t *child, *nchild;        // first child (-1 for leaves), number of children
+    int32_t *parent, *inst;         // parent cell (-1 for roots), instance
+};
+
+// ---- tree.hip
+void launch_bbox(const double *pos, int64_t n, const int64_t *d_offsets, int n_inst, unsigned long long *d_ord,
+                 int *d_bad, hipStream_t s);
+void launch_box_finish(const unsigned long long *d_ord, int n_inst, const int64_t *d_offsets, bool user,
+                       const double *ubox, double *d_box, double *d_scale, hipStream_t s);
+void launch_keys(const double *pos, int64_t n, const int64_t *d_offsets, int n_inst, const double *d_box,
+                 const double *d_scale, uint64_t *keys, uint32_t *idx, hipStream_t s);
+void sort_by_instance(uint64_t *keys, uint32_t *idx, uint64_t *kalt, uint32_t *valt, uint32_t *ikey, uint32_t *ialt,
+                      uint32_t *rank, uint32_t *ralt, int64_t n, const int64_t *d_offsets, int n_inst, int32_t *tmp,
+                      hipStream_t s);
+void launch_gather(const double *pos, const double *q, const uint32_t *idx, int64_t n, double *xs, double *ys,
+                   double *zs, double *qs, hipStream_t s);
+void launch_roots(const int64_t *d_offsets, int n_inst, CellArrays c, hipStream_t s);
+void launch_tree_count(CellArrays c, int32_t lb, int32_t le, int ncrit, int max_level, const uint64_t *skeys,
+                       int32_t *bounds, int32_t *nch, hipStream_t s);
+void launch_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t *bounds, const int32_t *nch,
+                       const int32_t *off, hipStream_t s);
+void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, hipStream_t s);
+
+// ---- lists.hip
+struct PairBuf {
+    uint64_t *m2l;  // packed (target << 32) | source, unsorted
+    uint64_t *p2p;
+    int32_t cap_m2l, cap_p2p;
+};
+// One breadth-first step of the dual tree traversal: consumes nf frontier
+// pairs, appends accepted M2L / P2P pairs and the split pairs of the next
+// frontier.  counters[0] = next frontier size, [1] = #M2L, [2] = #P2P (all
+// counted even past capacity, so the host can detect overflow).
+void launch_traverse(CellArrays c, const int2 *fin, int32_t nf, int2 *fout, int32_t capf, PairBuf pb,
+                     int32_t *counters, uint32_t theta_num, uint32_t theta_den, hipStream_t s);
+void launch_init_frontier(const int64_t *d_offsets, int n_inst, int2 *front, int32_t *counters, hipStream_t s);
+// Repack (target << 32 | source) into (target << bits | source) for sorting.
+void launch_repack(uint64_t *pairs, int64_t n, int bits, hipStream_t s);
+// CSR from pairs sorted by (target, source) packed with `bits`.
+void launch_csr(const uint64_t *sorted, int64_t n, int bits, int32_t ncell, int32_t *ptr, int32_t *src,
+                hipStream_t s);
+
+// ---- expansions.hip  (FP64, scaled solid harmonics)
+struct Geometry {
+    const double *box;    // per instance: min xyz, side
+    CellArrays c;
+};
+void launch_p2m(Geometry g, int32_t ncell, int p, const double *xs, const double *ys, const double *zs,
+                const double *qs, double *M, hipStream_t s);
+void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, hipStream_t s);
+void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *L, hipStream_t s);
+void launch_l2p(Geometry g, int64_t n, int p, const int32_t *leaf_of, const double *xs, const double *ys,
+                const double *zs, const double *L, double *phi, double *fld, hipStream_t s);
+// Host: M2M (dir 0) or L2L (dir 1) operator matrices for the 8 octants,
+// row-major P x P each (P = (p+1)^2), acting on the real coefficient layout.
+std::vector<double> build_translation_ops(int p, int dir);
+
+// ---- near / far field, FP64 plain path
+void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
+                     const double *ys, const double *zs, const double *qs, double *phi, double *fld, hipStream_t s);
+void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
+                     double *L, hipStream_t s);
+
+// ---- output
+void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,
+                     const double *fld_near, const double *phi_far, const double *fld_far, double *phi, double *field,
+                     double *force, hipStream_t s);
+void launch_energy(const int64_t *d_offsets, int n_inst, const double *qs, const double *phi_near,
+                   const double *phi_far, double *energy, hipStream_t s);
+
+}  // namespace fmm

@@ -1,0 +1,248 @@
+"""Python binding of the C ABI in include/fmm.h (ctypes; argument marshalling only).
+
+Every step of the method runs in the HIP library libfmm_mi355x.so; torch is
+used for device memory and the current HIP stream.  There is no fallback: if
+the library is missing, loading fails with an error.
+
+    plan = Plan(p=8, ncrit=64, theta=(1, 2), precision="mixed")
+    plan.build_tree(pos, q)          # pos (N, 3) float64 cuda, q (N,) float64 cuda
+    plan.upward()
+    out = plan.evaluate()            # dict: phi, field, force, energy
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm_mi355x.so")
+
+FMM_OK = 0
+STATUS = {0: "FMM_OK", -1: "FMM_ERR_INVALID_ARG", -2: "FMM_ERR_STATE", -3: "FMM_ERR_OOM",
+          -4: "FMM_ERR_DEVICE", -5: "FMM_ERR_CAPACITY", -6: "FMM_ERR_UNSUPPORTED"}
+PREC = {"fp64": 0, "mixed": 1}
+FLAG_USER_BOX = 1
+
+# every symbol include/fmm.h declares
+EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
+           "fmm_backward", "fmm_sync", "fmm_get_counts", "fmm_copy_tree", "fmm_copy_lists", "fmm_get_tuning",
+           "fmm_set_tuning", "fmm_get_stage_times", "fmm_status_string", "fmm_last_error")
+
+
+class fmm_params(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("ncrit", ctypes.c_int32), ("theta_num", ctypes.c_int32),
+                ("theta_den", ctypes.c_int32), ("max_level", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("box_min", ctypes.c_double * 3), ("box_side", ctypes.c_double)]
+
+
+class fmm_tuning(ctypes.Structure):
+    _fields_ = [("queue_chunk", ctypes.c_int32), ("p2p_split", ctypes.c_int32), ("m2l_block", ctypes.c_int32),
+                ("grid_per_cu", ctypes.c_int32)]
+
+
+class FMMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load_library():
+    """Load libfmm_mi355x.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("HIP library %s is missing: run __graft_entry__.build() (or "
+                          "python paper_1203_0889_amd/build.py) first" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER
+    lib.fmm_default_params.argtypes = [P(fmm_params)]
+    lib.fmm_create.argtypes = [P(fmm_params), ctypes.c_int, vp, P(vp)]
+    lib.fmm_destroy.argtypes = [vp]
+    lib.fmm_build_tree.argtypes = [vp, i32, P(i64), vp, vp]
+    lib.fmm_upward.argtypes = [vp]
+    lib.fmm_evaluate.argtypes = [vp, vp, vp, vp, vp]
+    lib.fmm_backward.argtypes = [vp, vp, vp, vp]
+    lib.fmm_sync.argtypes = [vp]
+    lib.fmm_get_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64)]
+    lib.fmm_copy_tree.argtypes = [vp, vp, vp, vp]
+    lib.fmm_copy_lists.argtypes = [vp, vp, vp, vp, vp]
+    lib.fmm_get_tuning.argtypes = [vp, P(fmm_tuning)]
+    lib.fmm_set_tuning.argtypes = [vp, P(fmm_tuning)]
+    lib.fmm_get_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_char_p)]
+    lib.fmm_status_string.argtypes = [ctypes.c_int]
+    lib.fmm_status_string.restype = ctypes.c_char_p
+    lib.fmm_last_error.argtypes = [vp]
+    lib.fmm_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("fmm_status_string", "fmm_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_dev(t, name, dtype=torch.float64, shape_tail=()):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor on the GPU" % (name, dtype))
+    if shape_tail and tuple(t.shape[1:]) != shape_tail:
+        raise ValueError("%s must have shape (N, %s)" % (name, ", ".join(map(str, shape_tail))))
+
+
+class Plan:
+    """One FMM plan: owns the tree, lists and expansions on one device/stream."""
+
+    def __init__(self, p=8, ncrit=64, theta=(1, 2), max_level=21, precision="mixed", device=None, stream=None,
+                 box=None):
+        self._lib = load_library()
+        prm = fmm_params()
+        self._lib.fmm_default_params(ctypes.byref(prm))
+        prm.p, prm.ncrit = int(p), int(ncrit)
+        prm.theta_num, prm.theta_den = int(theta[0]), int(theta[1])
+        prm.max_level = int(max_level)
+        prm.precision = PREC[precision]
+        if box is not None:
+            prm.flags |= FLAG_USER_BOX
+            prm.box_min[0], prm.box_min[1], prm.box_min[2] = map(float, box[:3])
+            prm.box_side = float(box[3])
+        self.params = prm
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self._lib.fmm_create(ctypes.byref(prm), self.device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != FMM_OK:
+            raise FMMError(st, "fmm_create failed")
+        self._h = h
+        self.n = 0
+        self.n_inst = 0
+        self._keep = None
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.fmm_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, *args):
+        st = fn(self._h, *args)
+        if st != FMM_OK:
+            raise FMMError(st, self._lib.fmm_last_error(self._h).decode())
+
+    # ---- the four calls of the method
+    def build_tree(self, pos, q, offsets=None):
+        """Keys, sort, octree and interaction lists.  offsets (host ints,
+        n_inst + 1) batches independent instances."""
+        _check_dev(pos, "pos", shape_tail=(3,))
+        _check_dev(q, "q")
+        n = pos.shape[0]
+        if q.shape != (n,):
+            raise ValueError("q must have shape (N,)")
+        if offsets is None:
+            offsets = [0, n]
+        offs = (ctypes.c_int64 * len(offsets))(*[int(o) for o in offsets])
+        self._call(self._lib.fmm_build_tree, ctypes.c_int32(len(offsets) - 1), offs, _ptr(pos), _ptr(q))
+        self.n = n
+        self.n_inst = len(offsets) - 1
+        self._keep = (pos, q)
+
+    def upward(self):
+        self._call(self._lib.fmm_upward)
+
+    def evaluate(self, phi=True, field=True, force=True, energy=True):
+        dev = torch.device("cuda", self.device)
+        out = {}
+        n = self.n
+        out["phi"] = torch.empty(n, dtype=torch.float64, device=dev) if phi else None
+        out["field"] = torch.empty((n, 3), dtype=torch.float64, device=dev) if field else None
+        out["force"] = torch.empty((n, 3), dtype=torch.float64, device=dev) if force else None
+        out["energy"] = torch.empty(self.n_inst, dtype=torch.float64, device=dev) if energy else None
+        self._call(self._lib.fmm_evaluate, _ptr(out["phi"]), _ptr(out["field"]), _ptr(out["force"]),
+                   _ptr(out["energy"]))
+        return out
+
+    def evaluate_into(self, phi=None, field=None, force=None, energy=None):
+        self._call(self._lib.fmm_evaluate, _ptr(phi), _ptr(field), _ptr(force), _ptr(energy))
+
+    def backward(self, grad_energy, want_pos=True, want_q=True):
+        dev = torch.device("cuda", self.device)
+        _check_dev(grad_energy, "grad_energy")
+        gp = torch.empty((self.n, 3), dtype=torch.float64, device=dev) if want_pos else None
+        gq = torch.empty(self.n, dtype=torch.float64, device=dev) if want_q else None
+        self._call(self._lib.fmm_backward, _ptr(grad_energy), _ptr(gp), _ptr(gq))
+        return gp, gq
+
+    # ---- introspection
+    def sync(self):
+        self._call(self._lib.fmm_sync)
+
+    def counts(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        self._call(self._lib.fmm_get_counts, *[ctypes.byref(x) for x in v])
+        return dict(zip(("ncell", "nleaf", "nm2l", "np2p"), (x.value for x in v)))
+
+    def copy_tree(self):
+        import numpy as np
+        c = self.counts()
+        keys = np.zeros(self.n, dtype=np.uint64)
+        perm = np.zeros(self.n, dtype=np.int64)
+        cells = np.zeros((c["ncell"], 10), dtype=np.int64)
+        self._call(self._lib.fmm_copy_tree, ctypes.c_void_p(keys.ctypes.data), ctypes.c_void_p(perm.ctypes.data),
+                   ctypes.c_void_p(cells.ctypes.data))
+        return keys, perm, cells
+
+    def copy_lists(self):
+        import numpy as np
+        c = self.counts()
+        mp = np.zeros(c["ncell"] + 1, dtype=np.int64)
+        pp = np.zeros(c["ncell"] + 1, dtype=np.int64)
+        ms = np.zeros(max(c["nm2l"], 1), dtype=np.int32)
+        ps = np.zeros(max(c["np2p"], 1), dtype=np.int32)
+        self._call(self._lib.fmm_copy_lists, ctypes.c_void_p(mp.ctypes.data), ctypes.c_void_p(ms.ctypes.data),
+                   ctypes.c_void_p(pp.ctypes.data), ctypes.c_void_p(ps.ctypes.data))
+        return mp, ms[:c["nm2l"]], pp, ps[:c["np2p"]]
+
+    def stage_times(self):
+        t = (ctypes.c_double * 16)()
+        names = (ctypes.c_char_p * 16)()
+        self._call(self._lib.fmm_get_stage_times, t, names)
+        return {names[i].decode(): t[i] for i in range(16) if names[i] and names[i].decode()}
+
+    def get_tuning(self):
+        t = fmm_tuning()
+        self._call(self._lib.fmm_get_tuning, ctypes.byref(t))
+        return {f: getattr(t, f) for f, _ in fmm_tuning._fields_}
+
+    def set_tuning(self, **kw):
+        t = fmm_tuning()
+        self._call(self._lib.fmm_get_tuning, ctypes.byref(t))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        self._call(self._lib.fmm_set_tuning, ctypes.byref(t))
+
+
+def evaluate(pos, q, p=8, ncrit=64, theta=(1, 2), precision="mixed", **kw):
+    """One-shot FMM: returns (phi, field) in input order."""
+    plan = Plan(p=p, ncrit=ncrit, theta=theta, precision=precision, **kw)
+    plan.build_tree(pos, q)
+    plan.upward()
+    out = plan.evaluate(force=False, energy=False)
+    return out["phi"], out["field"]

@@ -1,0 +1,191 @@
+"""GPU parity of the plain FP64 path against the FP64 CPU oracle, through the
+C ABI: keys, permutation, octree and interaction lists bit-exact; potentials
+and fields to 1e-11 relative L2 (the two FMMs compute the same function in
+exact arithmetic: same tree, lists, centres and degrees; only the expansion
+basis and the summation order differ)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1203_0889_amd import fmm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def make(dist, n, seed):
+    if dist == "uniform":
+        return W.uniform_cube(n, seed)
+    if dist == "plummer":
+        return W.plummer(n, seed)
+    raise ValueError(dist)
+
+
+def gpu_run(pos, q, p, ncrit, theta, precision="fp64", offsets=None):
+    plan = fmm.Plan(p=p, ncrit=ncrit, theta=theta, precision=precision, device=0)
+    dpos = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+    dq = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    plan.build_tree(dpos, dq, offsets)
+    plan.upward()
+    out = plan.evaluate()
+    torch.cuda.synchronize()
+    return plan, {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+# (name, dist, n, seed, p, ncrit, theta) -- several tiles, ragged leaves,
+# adaptive depth, both MAC values
+CASES = [
+    ("uniform4k_p4", "uniform", 4096, 1, 4, 64, (1, 2)),
+    ("uniform5k_p8_ragged", "uniform", 5003, 7, 8, 40, (1, 2)),
+    ("plummer20k_p6", "plummer", 20000, 3, 6, 16, (1, 2)),
+    ("plummer9k_p10_theta04", "plummer", 9001, 5, 10, 32, (2, 5)),
+    ("uniform70k_p8", "uniform", 70000, 2, 8, 64, (1, 2)),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    name, dist, n, seed, p, ncrit, theta = request.param
+    say("case", name)
+    pos, q = make(dist, n, seed)
+    T = oracle.Tree(pos, ncrit)
+    T.lists(*theta)
+    plan, out = gpu_run(pos, q, p, ncrit, theta)
+    return dict(name=name, pos=pos, q=q, p=p, ncrit=ncrit, theta=theta, T=T, plan=plan, out=out)
+
+
+def test_keys_and_permutation_bit_exact(case):
+    keys, perm, cells = case["plan"].copy_tree()
+    T = case["T"]
+    assert np.array_equal(keys, T.keys)
+    assert np.array_equal(perm, T.perm)
+
+
+def test_tree_bit_exact(case):
+    _, _, cells = case["plan"].copy_tree()
+    T = case["T"]
+    assert cells.shape[0] == T.ncell
+    assert np.array_equal(cells[:, :9], T.cells)
+    assert np.all(cells[:, 9] == 0)
+
+
+def test_lists_bit_exact(case):
+    mp, ms, pp, ps = case["plan"].copy_lists()
+    T = case["T"]
+    c = case["plan"].counts()
+    assert c["nm2l"] == len(T.m2l) and c["np2p"] == len(T.p2p)
+    assert c["nleaf"] == int(np.sum(T.cell("child_first") < 0))
+    for ptr, src, ref in ((mp, ms, T.m2l), (pp, ps, T.p2p)):
+        tgt = np.repeat(np.arange(T.ncell), np.diff(ptr))
+        assert np.array_equal(tgt, ref[:, 0])
+        assert np.array_equal(src, ref[:, 1])
+
+
+def test_fp64_matches_oracle_fmm(case):
+    T = case["T"]
+    phi_ref, fld_ref = T.fmm(case["q"], case["p"])
+    out = case["out"]
+    e_phi, e_fld = rel(out["phi"], phi_ref), rel(out["field"], fld_ref)
+    say(case["name"], "fp64 vs oracle fmm", e_phi, e_fld)
+    assert e_phi < 1e-11 and e_fld < 1e-11
+    # force and energy follow from phi and field
+    assert np.allclose(out["force"], case["q"][:, None] * out["field"], rtol=1e-15, atol=0)
+    assert out["energy"][0] == pytest.approx(0.5 * np.dot(case["q"], out["phi"]), rel=1e-12)
+
+
+def test_fp64_vs_direct_sum(case):
+    pos, q = case["pos"], case["q"]
+    tg = W.error_sample(len(q), 11, 2048)
+    pd, fd = oracle.direct(pos, q, tg)
+    out = case["out"]
+    e_phi, e_fld = rel(out["phi"][tg], pd), rel(out["field"][tg], fd)
+    say(case["name"], "fp64 vs direct", e_phi, e_fld)
+    tol = {4: (1e-3, 1e-2), 6: (1e-4, 1e-3), 8: (1e-5, 1e-4), 10: (1e-6, 1e-5)}[case["p"]]
+    assert e_phi < tol[0] and e_fld < tol[1]
+
+
+def test_root_leaf_is_exact_direct_sum():
+    pos, q = W.uniform_cube(60, 4)
+    plan, out = gpu_run(pos, q, 6, 64, (1, 2))
+    pd, fd = oracle.direct(pos, q)
+    assert plan.counts()["ncell"] == 1
+    assert rel(out["phi"], pd) < 1e-14 and rel(out["field"], fd) < 1e-14
+
+
+def test_single_particle_and_coincident_pairs():
+    plan, out = gpu_run(np.array([[0.3, 0.2, 0.1]]), np.array([2.0]), 4, 8, (1, 2))
+    assert out["phi"][0] == 0.0 and np.all(out["field"][0] == 0.0)
+    # coincident distinct particles contribute nothing to each other
+    pos = np.array([[0.1, 0.1, 0.1], [0.1, 0.1, 0.1], [0.9, 0.2, 0.4]])
+    q = np.array([1.0, -2.0, 0.5])
+    plan, out = gpu_run(pos, q, 4, 1, (1, 2))
+    pd, fd = oracle.direct(pos, q)
+    assert np.all(np.isfinite(out["phi"])) and rel(out["phi"], pd) < 1e-14 and rel(out["field"], fd) < 1e-13
+
+
+def test_all_particles_coincident_reach_max_level():
+    pos = np.tile(np.array([[0.25, 0.5, 0.75]]), (40, 1))
+    q = np.linspace(-1, 1, 40)
+    plan, out = gpu_run(pos, q, 4, 4, (1, 2))
+    T = oracle.Tree(pos, 4)
+    _, _, cells = plan.copy_tree()
+    assert np.array_equal(cells[:, :9], T.cells)
+    assert np.all(out["phi"] == 0.0) and np.all(out["field"] == 0.0)
+
+
+def test_non_finite_input_is_rejected():
+    pos, q = W.uniform_cube(100, 1)
+    pos[17, 1] = np.nan
+    plan = fmm.Plan(p=4, ncrit=8, precision="fp64", device=0)
+    with pytest.raises(fmm.FMMError) as ei:
+        plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    assert ei.value.status == -1
+    with pytest.raises(fmm.FMMError) as ei:
+        plan.upward()
+    assert ei.value.status == -2
+
+
+def test_call_order_is_enforced():
+    plan = fmm.Plan(p=4, ncrit=8, precision="fp64", device=0)
+    with pytest.raises(fmm.FMMError) as ei:
+        plan.upward()
+    assert ei.value.status == -2
+    with pytest.raises(fmm.FMMError) as ei:
+        plan.evaluate()
+    assert ei.value.status == -2
+
+
+def test_user_box_matches_oracle():
+    pos, q = W.uniform_cube(3000, 9)
+    box = np.array([-0.5, -0.25, -1.0, 2.5])
+    plan = fmm.Plan(p=6, ncrit=16, precision="fp64", device=0, box=box)
+    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    plan.upward()
+    out = plan.evaluate()
+    T = oracle.Tree(pos, 16, box=box)
+    T.lists(1, 2)
+    keys, perm, cells = plan.copy_tree()
+    assert np.array_equal(keys, T.keys) and np.array_equal(cells[:, :9], T.cells)
+    phi_ref, fld_ref = T.fmm(q, 6)
+    assert rel(out["phi"].cpu().numpy(), phi_ref) < 1e-11
+
+
+def test_repeated_builds_reuse_plan():
+    plan = fmm.Plan(p=6, ncrit=32, precision="fp64", device=0)
+    for n, seed in ((8000, 1), (3000, 2), (12000, 3)):
+        say("rebuild", n)
+        pos, q = W.uniform_cube(n, seed)
+        plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+        plan.upward()
+        out = plan.evaluate()
+        phi_ref, fld_ref, _ = oracle.fmm(pos, q, 6, 32, 1, 2)
+        assert rel(out["phi"].cpu().numpy(), phi_ref) < 1e-11
+        assert rel(out["field"].cpu().numpy(), fld_ref) < 1e-11
