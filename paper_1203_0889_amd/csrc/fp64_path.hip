@@ -83,11 +83,12 @@ __device__ inline int tri(int n, int m) { return n * (n + 1) / 2 + m; }
 
 __global__ void __launch_bounds__(kM2L64Threads)
     k_m2l_fp64(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
-               const double *__restrict__ M, double *__restrict__ L) {
+               const double *__restrict__ M, double *__restrict__ L, int accumulate) {
     __shared__ double Ire[kMaxI], Iim[kMaxI];
     __shared__ double Ms[ncoef(kMaxP)];
     int32_t A = blockIdx.x;
     if (A >= ncell) return;
+    if (accumulate && ptr[A] == ptr[A + 1]) return;
     const int lane = threadIdx.x;
     const int P = ncoef(p);
     const int NC = (p + 1) * (p + 2) / 2;
@@ -201,8 +202,13 @@ __global__ void __launch_bounds__(kM2L64Threads)
         int n = on[s];
         if (n < 0) continue;
         int m = om[s];
-        out[cidx_re(n, m)] = accr[s];
-        if (m > 0) out[cidx_im(n, m)] = acci[s];
+        if (accumulate) {
+            out[cidx_re(n, m)] += accr[s];
+            if (m > 0) out[cidx_im(n, m)] += acci[s];
+        } else {
+            out[cidx_re(n, m)] = accr[s];
+            if (m > 0) out[cidx_im(n, m)] = acci[s];
+        }
     }
 }
 
@@ -219,7 +225,14 @@ void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_
 void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
                      double *L, hipStream_t s) {
     if (ncell == 0) return;
-    hipLaunchKernelGGL(k_m2l_fp64, dim3(ncell), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, M, L);
+    hipLaunchKernelGGL(k_m2l_fp64, dim3(ncell), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, M, L, 0);
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
+                         double *L, hipStream_t s) {
+    if (ncell == 0) return;
+    hipLaunchKernelGGL(k_m2l_fp64, dim3(ncell), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, M, L, 1);
     FMM_LAUNCH_CHECK();
 }
 

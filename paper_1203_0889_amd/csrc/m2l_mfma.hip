@@ -1,0 +1,485 @@
+// M2L as a dense contraction on the FP32 matrix cores (the multipole-to-local
+// stage of Sec. 2.1, applied hundreds of times per cell).
+//
+// With level-scaled coefficients the M2L operator of a pair (A <- B) depends
+// only on its class c = (delta, rho): delta = level(A) - level(B) and rho =
+// (C_A - C_B) / min(S_A, S_B), the integer displacement of the centres in
+// units of the smaller cell (half grid units C, cell sides S).  The real
+// operator T_c ((p+1)^2 x (p+1)^2, FP32) is built once per class from the
+// irregular solid harmonics I_n^m(rho / (2 S_A / S_min)):
+//   L~_n^m += (-1)^n sum_k 2^(delta k) sum_l M~_k^l I_(n+k)^(m+l)
+// Classes with |delta| <= 1 (all pairs of a uniform tree, >95% of an
+// adaptive one) index a dense table; their operators are cached in the plan
+// across builds.  Pairs with |delta| >= 2 are nearly one class each and go
+// to the per-pair FP64 kernel instead.
+//
+// Batching: targets are grouped 32 at a time (same level and octant, Morton
+// order, so neighbouring targets share their class sets).  A group's entries
+// are its distinct classes in class order, each with the source cell of
+// every target slot (-1 if absent).  One wave applies T_c to the 32 gathered
+// multipoles with v_mfma_f32_32x32x2_f32: A operand = T_c fragments
+// (pre-swizzled so each wave load is one contiguous 256-byte line), B operand
+// = M~ of the slot's source, C = the 32 targets' local expansions in FP32
+// accumulators.  Results are added into the FP64 locals.
+#include "m2l_mfma.h"
+
+#include <stdexcept>
+
+namespace fmm {
+
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ inline int dense_key(int delta, int rx, int ry, int rz) {
+    if (delta < -1 || delta > 1) return -1;
+    if (rx < -kRhoMax || rx > kRhoMax || ry < -kRhoMax || ry > kRhoMax || rz < -kRhoMax || rz > kRhoMax) return -1;
+    return (((delta + 1) * kRhoSpan + (rx + kRhoMax)) * kRhoSpan + (ry + kRhoMax)) * kRhoSpan + (rz + kRhoMax);
+}
+
+// Class key of every M2L pair in CSR order; marks used dense keys.
+__global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr,
+                               const int32_t *__restrict__ src, int32_t *__restrict__ pkey,
+                               int32_t *__restrict__ used) {
+    for (int32_t A = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; A < ncell; A += gridDim.x * blockDim.x / 64) {
+        int la = c.level[A];
+        int64_t SA = (int64_t)1 << (kLevels - la);
+        int64_t ca[3] = {(2 * (int64_t)c.ix[A] + 1) * SA, (2 * (int64_t)c.iy[A] + 1) * SA,
+                         (2 * (int64_t)c.iz[A] + 1) * SA};
+        for (int32_t e = ptr[A] + (threadIdx.x & 63); e < ptr[A + 1]; e += 64) {
+            int32_t B = src[e];
+            int lb = c.level[B];
+            int64_t SB = (int64_t)1 << (kLevels - lb);
+            int64_t smin = SA < SB ? SA : SB;
+            int rx = (int)((ca[0] - (2 * (int64_t)c.ix[B] + 1) * SB) / smin);
+            int ry = (int)((ca[1] - (2 * (int64_t)c.iy[B] + 1) * SB) / smin);
+            int rz = (int)((ca[2] - (2 * (int64_t)c.iz[B] + 1) * SB) / smin);
+            int k = dense_key(la - lb, rx, ry, rz);
+            pkey[e] = k;
+            if (k >= 0) used[k] = 1;
+        }
+    }
+}
+
+// New dense keys get a slot in the operator store.
+__global__ void k_alloc_slots(const int32_t *__restrict__ used, int32_t nkeys, int32_t *__restrict__ slot_of,
+                              int32_t *__restrict__ nslots, int32_t *__restrict__ new_keys) {
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nkeys; k += gridDim.x * blockDim.x) {
+        if (used[k] && slot_of[k] < 0) {
+            int32_t s = atomicAdd(&nslots[0], 1);
+            slot_of[k] = s;
+            int32_t j = atomicAdd(&nslots[1], 1);
+            new_keys[j] = k;
+        }
+    }
+}
+
+// Build the FP32 operator fragments of each new class: one workgroup per
+// class.  Lane m computes column m of I_n^m (n <= 2p) in FP64.
+__global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ new_keys, int32_t nnew,
+                                                   const int32_t *__restrict__ slot_of, int p, int RT, int KS,
+                                                   float *__restrict__ frags) {
+    __shared__ double Ire[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2], Iim[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2];
+    int32_t j = blockIdx.x;
+    if (j >= nnew) return;
+    int k = new_keys[j];
+    int rz = k % kRhoSpan - kRhoMax;
+    int t = k / kRhoSpan;
+    int ry = t % kRhoSpan - kRhoMax;
+    t /= kRhoSpan;
+    int rx = t % kRhoSpan - kRhoMax;
+    int delta = t / kRhoSpan - 1;
+    // rho in units of the target side: (C_A - C_B) / (2 S_A) = r_int * S_min / (2 S_A)
+    double sc = delta >= 0 ? 0.5 : ldexp(0.5, delta);  // S_min / S_A = 2^min(0, delta)
+    double x = rx * sc, y = ry * sc, z = rz * sc;
+    const int nmax = 2 * p;
+    auto tri = [](int n, int m) { return n * (n + 1) / 2 + m; };
+    if ((int)threadIdx.x <= nmax) {
+        int m = threadIdx.x;
+        double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
+        double mr = 1.0 / sqrt(r2), mi = 0.0;
+        for (int q = 1; q <= m; q++) {
+            double f = (2 * q - 1) * ir2;
+            double nr = (mr * x - mi * y) * f, ni = (mr * y + mi * x) * f;
+            mr = nr;
+            mi = ni;
+        }
+        Ire[tri(m, m)] = mr;
+        Iim[tri(m, m)] = mi;
+        double pr = 0, pi = 0, cr = mr, ci = mi;
+        for (int n = m + 1; n <= nmax; n++) {
+            double nr, ni;
+            if (n == m + 1) {
+                double f = (2 * m + 1) * z * ir2;
+                nr = f * cr;
+                ni = f * ci;
+            } else {
+                double a = (2 * n - 1) * z, b = (double)((n - 1) * (n - 1) - m * m);
+                nr = (a * cr - b * pr) * ir2;
+                ni = (a * ci - b * pi) * ir2;
+            }
+            Ire[tri(n, m)] = nr;
+            Iim[tri(n, m)] = ni;
+            pr = cr;
+            pi = ci;
+            cr = nr;
+            ci = ni;
+        }
+    }
+    __syncthreads();
+    const int P = ncoef(p);
+    float *out = frags + (int64_t)slot_of[k] * RT * KS * 64;
+    const int total = RT * KS * 64;
+    for (int f = threadIdx.x; f < total; f += blockDim.x) {
+        int lane = f & 63, ks = (f >> 6) % KS, rt = (f >> 6) / KS;
+        int row = rt * 32 + (lane & 31), col = 2 * ks + (lane >> 5);
+        double v = 0.0;
+        if (row < P && col < P) {
+            // output (n, m, part) and input (kk, l, part) of the real layouts
+            int n = 0;
+            while ((n + 1) * (n + 1) <= row) n++;
+            int ro = row - n * n, m = (ro + 1) / 2;
+            bool out_im = ro > 0 && !(ro & 1);
+            int kk = 0;
+            while ((kk + 1) * (kk + 1) <= col) kk++;
+            int co = col - kk * kk, l = (co + 1) / 2;
+            bool in_im = co > 0 && !(co & 1);
+            // I_(n+kk)^(mm) with conjugate symmetry for mm < 0
+            auto Ig = [&](int mm, double &re, double &im) {
+                int nn = n + kk, am = mm < 0 ? -mm : mm;
+                re = Ire[tri(nn, am)];
+                im = Iim[tri(nn, am)];
+                if (mm < 0) {
+                    im = -im;
+                    if (am & 1) {
+                        re = -re;
+                        im = -im;
+                    }
+                }
+            };
+            double zr, zi;
+            if (l == 0) {
+                Ig(m, zr, zi);
+            } else {
+                double ar, ai, br, bi;
+                Ig(m + l, ar, ai);
+                Ig(m - l, br, bi);
+                double sg = (l & 1) ? -1.0 : 1.0;
+                if (!in_im) {
+                    zr = ar + sg * br;
+                    zi = ai + sg * bi;
+                } else {  // i * (a - sg b)
+                    double dr = ar - sg * br, di = ai - sg * bi;
+                    zr = -di;
+                    zi = dr;
+                }
+            }
+            v = out_im ? zi : zr;
+            v *= ldexp(1.0, delta * kk);
+            if (n & 1) v = -v;
+        }
+        out[f] = (float)v;
+    }
+}
+
+// Compact id of a pair's class (rank of its dense key among used keys).
+__global__ void k_pair_cid(const int32_t *__restrict__ pkey, int64_t npair, const int32_t *__restrict__ cid_of,
+                           int32_t *__restrict__ pcid, int32_t *__restrict__ xflag) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npair; e += (int64_t)gridDim.x * blockDim.x) {
+        int k = pkey[e];
+        pcid[e] = k >= 0 ? cid_of[k] : -1;
+        xflag[e] = k < 0 ? 1 : 0;
+    }
+}
+
+__global__ void k_cid_tables(const int32_t *__restrict__ used_scan, const int32_t *__restrict__ used, int32_t nkeys,
+                             const int32_t *__restrict__ slot_of, int32_t *__restrict__ cid_of,
+                             int32_t *__restrict__ slot_of_cid) {
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nkeys; k += gridDim.x * blockDim.x) {
+        if (used[k]) {
+            int32_t c = used_scan[k];
+            cid_of[k] = c;
+            slot_of_cid[c] = slot_of[k];
+        }
+    }
+}
+
+// Sort key of every cell that has batched M2L pairs: (level, octant, cell).
+__global__ void k_target_keys(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr,
+                              const int32_t *__restrict__ xscan, uint64_t *__restrict__ tkey,
+                              int32_t *__restrict__ has) {
+    for (int32_t A = blockIdx.x * blockDim.x + threadIdx.x; A < ncell; A += gridDim.x * blockDim.x) {
+        int32_t nb = (ptr[A + 1] - ptr[A]) - (xscan[ptr[A + 1]] - xscan[ptr[A]]);
+        has[A] = nb > 0;
+        int oct = (c.ix[A] & 1) | ((c.iy[A] & 1) << 1) | ((c.iz[A] & 1) << 2);
+        tkey[A] = nb > 0 ? (((uint64_t)c.level[A] << 35) | ((uint64_t)oct << 32) | (uint32_t)A) : ~0ull;
+    }
+}
+
+// Per group (workgroup): mark the classes of its targets in an LDS bitmap;
+// mode 0 counts them, mode 1 writes the entries.
+__global__ void __launch_bounds__(256) k_group_entries(int mode, const uint64_t *__restrict__ tsorted, int32_t ntarget,
+                                                       const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                                                       const int32_t *__restrict__ pcid, int32_t ncid,
+                                                       int32_t *__restrict__ gcount, const int32_t *__restrict__ goff,
+                                                       int32_t *__restrict__ ecls, int32_t *__restrict__ esrc,
+                                                       int32_t *__restrict__ gtarget) {
+    extern __shared__ uint32_t bits[];
+    __shared__ int32_t wbase[1024 + 1];
+    const int g = blockIdx.x;
+    const int nwords = (ncid + 31) / 32;
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) bits[w] = 0u;
+    __syncthreads();
+    int t0 = g * kGroup;
+    int nt = ntarget - t0 < kGroup ? ntarget - t0 : kGroup;
+    for (int s = 0; s < nt; s++) {
+        int32_t A = (int32_t)(tsorted[t0 + s] & 0xffffffffull);
+        for (int32_t e = ptr[A] + threadIdx.x; e < ptr[A + 1]; e += blockDim.x) {
+            int32_t cid = pcid[e];
+            if (cid >= 0) atomicOr(&bits[cid >> 5], 1u << (cid & 31));
+        }
+    }
+    __syncthreads();
+    if (mode == 0) {
+        int cnt = 0;
+        for (int w = threadIdx.x; w < nwords; w += blockDim.x) cnt += __popc(bits[w]);
+        for (int d = 32; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d, 64);  // wave sum
+        __shared__ int wsum[4];
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) gcount[g] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        return;
+    }
+    // mode 1: exclusive popcount prefix over words, chunked by 1024 words
+    const int32_t base = goff[g];
+    if (threadIdx.x < kGroup) gtarget[g * kGroup + threadIdx.x] =
+        threadIdx.x < nt ? (int32_t)(tsorted[t0 + threadIdx.x] & 0xffffffffull) : -1;
+    // serial-per-thread chunks: thread t owns words [t*per, (t+1)*per)
+    int per = (nwords + blockDim.x - 1) / blockDim.x;
+    int mine = 0;
+    for (int w = threadIdx.x * per; w < (int)(threadIdx.x + 1) * per && w < nwords; w++) mine += __popc(bits[w]);
+    // block exclusive scan of `mine`
+    wbase[threadIdx.x] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int i = 0; i < (int)blockDim.x; i++) {
+            int v = wbase[i];
+            wbase[i] = run;
+            run += v;
+        }
+        wbase[blockDim.x] = run;
+    }
+    __syncthreads();
+    // word prefix stored back into a second region of `bits` (after nwords)
+    uint32_t *wpre = bits + nwords;
+    {
+        int run = wbase[threadIdx.x];
+        for (int w = threadIdx.x * per; w < (int)(threadIdx.x + 1) * per && w < nwords; w++) {
+            wpre[w] = run;
+            run += __popc(bits[w]);
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < nt; s++) {
+        int32_t A = (int32_t)(tsorted[t0 + s] & 0xffffffffull);
+        for (int32_t e = ptr[A] + threadIdx.x; e < ptr[A + 1]; e += blockDim.x) {
+            int32_t cid = pcid[e];
+            if (cid < 0) continue;
+            uint32_t wv = bits[cid >> 5] & ((1u << (cid & 31)) - 1u);
+            int32_t ent = base + (int32_t)wpre[cid >> 5] + __popc(wv);
+            ecls[ent] = cid;
+            esrc[(int64_t)ent * kGroup + s] = src[e];
+        }
+    }
+}
+
+// Tasks: each group's entries split into chunks of `chunk`.
+__global__ void k_make_tasks(const int32_t *__restrict__ gcount, const int32_t *__restrict__ goff, int32_t ngroup,
+                             int chunk, const int32_t *__restrict__ toff, int4 *__restrict__ tasks) {
+    for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroup; g += gridDim.x * blockDim.x) {
+        int32_t n = gcount[g], t = toff[g];
+        for (int32_t e = 0; e < n; e += chunk) tasks[t++] = make_int4(g, goff[g] + e, goff[g] + (e + chunk < n ? e + chunk : n), 0);
+    }
+}
+
+__global__ void k_task_counts(const int32_t *__restrict__ gcount, int32_t ngroup, int chunk, int32_t *__restrict__ tcount) {
+    for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroup; g += gridDim.x * blockDim.x)
+        tcount[g] = (gcount[g] + chunk - 1) / chunk;
+}
+
+__global__ void k_compact_extra(const int32_t *__restrict__ xflag, const int32_t *__restrict__ xscan, int64_t npair,
+                                const int32_t *__restrict__ src, int32_t *__restrict__ xsrc) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npair; e += (int64_t)gridDim.x * blockDim.x)
+        if (xflag[e]) xsrc[xscan[e]] = src[e];
+}
+
+__global__ void k_extra_ptr(const int32_t *__restrict__ ptr, int32_t ncell, const int32_t *__restrict__ xscan,
+                            int32_t *__restrict__ xptr) {
+    for (int32_t A = blockIdx.x * blockDim.x + threadIdx.x; A <= ncell; A += gridDim.x * blockDim.x) xptr[A] = xscan[ptr[A]];
+}
+
+__global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+// One wave per task (group, entry range).  RT row tiles of 32.
+template <int RT>
+__global__ void __launch_bounds__(256) k_m2l_mfma(const int4 *__restrict__ tasks, int32_t ntask,
+                                                  const int32_t *__restrict__ gtarget, const int32_t *__restrict__ ecls,
+                                                  const int32_t *__restrict__ esrc, const int32_t *__restrict__ slot_of_cid,
+                                                  const float *__restrict__ frags, const float *__restrict__ M32, int P,
+                                                  int KS, double *__restrict__ L) {
+    const int lane = threadIdx.x & 63;
+    const int32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= ntask) return;
+    int4 task = tasks[t];
+    f16v acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; r++)
+        for (int i = 0; i < 16; i++) acc[r][i] = 0.f;
+    const int col = lane & 31, khalf = lane >> 5;
+    for (int32_t e = task.y; e < task.z; e++) {
+        int32_t cid = ecls[e];
+        int32_t s = esrc[(int64_t)e * kGroup + col];
+        const float *Tf = frags + (int64_t)slot_of_cid[cid] * RT * KS * 64 + lane;
+        const float *Ms = M32 + (int64_t)(s < 0 ? 0 : s) * P;
+        for (int ks = 0; ks < KS; ks++) {
+            int kk = 2 * ks + khalf;
+            float b = (s >= 0 && kk < P) ? Ms[kk] : 0.f;
+#pragma unroll
+            for (int r = 0; r < RT; r++) {
+                float a = Tf[(r * KS + ks) * 64];
+                acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[r], 0, 0, 0);
+            }
+        }
+    }
+    int32_t A = gtarget[task.x * kGroup + col];
+    if (A < 0) return;
+    double *Lc = L + (int64_t)A * P;
+#pragma unroll
+    for (int r = 0; r < RT; r++)
+        for (int i = 0; i < 16; i++) {
+            int row = r * 32 + 8 * (i >> 2) + 4 * khalf + (i & 3);
+            if (row < P) atomicAdd(&Lc[row], (double)acc[r][i]);
+        }
+}
+
+}  // namespace
+
+void m2l_dense_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *src, int32_t *pkey,
+                    int32_t *used, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_classes, dim3(grid_for((int64_t)ncell * 64, 256, 16384)), dim3(256), 0, s, c, ncell, ptr,
+                       src, pkey, used);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_alloc_slots(const int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, hipStream_t s) {
+    hipLaunchKernelGGL(k_alloc_slots, dim3(grid_for(kDenseKeys, 256, 4096)), dim3(256), 0, s, used, kDenseKeys, slot_of,
+                       nslots, new_keys);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int KS, float *frags,
+                   hipStream_t s) {
+    if (nnew <= 0) return;
+    hipLaunchKernelGGL(k_build_ops, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, KS, frags);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_cid_tables(const int32_t *used_scan, const int32_t *used, const int32_t *slot_of, int32_t *cid_of,
+                    int32_t *slot_of_cid, hipStream_t s) {
+    hipLaunchKernelGGL(k_cid_tables, dim3(grid_for(kDenseKeys, 256, 4096)), dim3(256), 0, s, used_scan, used, kDenseKeys,
+                       slot_of, cid_of, slot_of_cid);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int32_t *pcid, int32_t *xflag,
+                  hipStream_t s) {
+    if (npair <= 0) return;
+    hipLaunchKernelGGL(k_pair_cid, dim3(grid_for(npair, 256, 16384)), dim3(256), 0, s, pkey, npair, cid_of, pcid, xflag);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_target_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *xscan, uint64_t *tkey,
+                     int32_t *has, hipStream_t s) {
+    hipLaunchKernelGGL(k_target_keys, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, ptr, xscan, tkey, has);
+    FMM_LAUNCH_CHECK();
+}
+
+size_t m2l_group_lds(int32_t ncid) {
+    int nwords = (ncid + 31) / 32;
+    return (size_t)(2 * nwords + 1) * sizeof(uint32_t);
+}
+
+void m2l_group_entries(int mode, const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
+                       const int32_t *pcid, int32_t ncid, int32_t *gcount, const int32_t *goff, int32_t *ecls,
+                       int32_t *esrc, int32_t *gtarget, hipStream_t s) {
+    int32_t ngroup = (ntarget + kGroup - 1) / kGroup;
+    if (ngroup <= 0) return;
+    if (m2l_group_lds(ncid) > 60 * 1024) throw std::runtime_error("too many M2L classes for the group builder");
+    hipLaunchKernelGGL(k_group_entries, dim3(ngroup), dim3(256), m2l_group_lds(ncid), s, mode, tsorted, ntarget, ptr, src,
+                       pcid, ncid, gcount, goff, ecls, esrc, gtarget);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *tcount, hipStream_t s) {
+    if (ngroup <= 0) return;
+    hipLaunchKernelGGL(k_task_counts, dim3(grid_for(ngroup, 256, 4096)), dim3(256), 0, s, gcount, ngroup, chunk, tcount);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, int chunk, const int32_t *toff,
+                    int4 *tasks, hipStream_t s) {
+    if (ngroup <= 0) return;
+    hipLaunchKernelGGL(k_make_tasks, dim3(grid_for(ngroup, 256, 4096)), dim3(256), 0, s, gcount, goff, ngroup, chunk,
+                       toff, tasks);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_extra(const int32_t *xflag, const int32_t *xscan, int64_t npair, const int32_t *src, const int32_t *ptr,
+               int32_t ncell, int32_t *xsrc, int32_t *xptr, hipStream_t s) {
+    if (npair > 0) {
+        hipLaunchKernelGGL(k_compact_extra, dim3(grid_for(npair, 256, 16384)), dim3(256), 0, s, xflag, xscan, npair, src,
+                           xsrc);
+        FMM_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_extra_ptr, dim3(grid_for(ncell + 1, 256, 4096)), dim3(256), 0, s, ptr, ncell, xscan, xptr);
+    FMM_LAUNCH_CHECK();
+}
+
+void to_f32(const double *in, float *out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, in, out, n);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_mfma(const int4 *tasks, int32_t ntask, const int32_t *gtarget, const int32_t *ecls, const int32_t *esrc,
+              const int32_t *slot_of_cid, const float *frags, const float *M32, int p, double *L, hipStream_t s) {
+    if (ntask <= 0) return;
+    const int P = ncoef(p), RT = (P + 31) / 32, KS = (P + 1) / 2;
+    dim3 grid((ntask + 3) / 4), block(256);
+#define FMM_M2L_CASE(R)                                                                                         \
+    case R:                                                                                                     \
+        hipLaunchKernelGGL(k_m2l_mfma<R>, grid, block, 0, s, tasks, ntask, gtarget, ecls, esrc, slot_of_cid, frags, \
+                           M32, P, KS, L);                                                                      \
+        break;
+    switch (RT) {
+        FMM_M2L_CASE(1)
+        FMM_M2L_CASE(2)
+        FMM_M2L_CASE(3)
+        FMM_M2L_CASE(4)
+        FMM_M2L_CASE(5)
+        FMM_M2L_CASE(6)
+        FMM_M2L_CASE(7)
+        FMM_M2L_CASE(8)
+        FMM_M2L_CASE(9)
+        FMM_M2L_CASE(10)
+        default: throw HipError{hipErrorInvalidValue, "m2l_mfma: unsupported order"};
+    }
+#undef FMM_M2L_CASE
+    FMM_LAUNCH_CHECK();
+}
+
+}  // namespace fmm

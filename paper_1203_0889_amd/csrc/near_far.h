@@ -1,5 +1,5 @@
-// Internal interface of the mixed-precision near/far field stage: the device
-// work queue that runs P2P (FP32 VALU) and M2L (FP32 MFMA) tasks.
+// Internal interface of the mixed-precision near/far field stage: P2P tasks
+// (FP32 VALU) and class-batched M2L tasks (FP32 MFMA).
 #pragma once
 
 #include "../../include/fmm.h"
@@ -10,9 +10,10 @@ namespace fmm {
 struct NearFarArgs {
     Geometry g;
     int32_t ncell;
-    int64_t nleaf, n;
+    int64_t nleaf, n, nm2l;
     int p;
     const int32_t *m2l_ptr, *m2l_src, *p2p_ptr, *p2p_src;
+    const int32_t *leaf_of;
     const double *xs, *ys, *zs, *qs;
     const double *M;   // FP64 multipoles (input)
     double *L;         // FP64 locals (output, overwritten)
@@ -20,12 +21,21 @@ struct NearFarArgs {
     fmm_tuning tuning;
 };
 
-// Device workspaces owned by the plan for this stage.
+// Device workspaces of this stage, owned by the plan.  The class operator
+// store (slot_of, frags) persists across builds of the same plan.
 struct NearFarState {
-    DevBuf buf[16];
+    DevBuf used, slot_of, nslots, new_keys, frags, used_scan, cid_of, slot_of_cid;
+    DevBuf pkey, pcid, xflag, xscan, tkey, tkey_alt, has, gcount, goff, tcount, toff;
+    DevBuf ecls, esrc, gtarget, tasks, xsrc, xptr, leafbuf, leaves, pf, M32, tmp, cnt;
+    int p = -1;
+    int32_t nslot_total = 0, ncid = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0, nleaves = 0;
+    bool built = false;
 };
 
 fmm_tuning default_tuning();
+// Build-time part (after the lists): classes, operators, groups, tasks.
+void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+// Evaluate-time part: M2L (MFMA + per-pair remainder) and P2P.
 void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 void release_near_far(NearFarState &st);
 

@@ -1,25 +1,162 @@
-// Mixed-precision near/far field stage (placeholder until the work queue lands).
+// Orchestration of the mixed-precision near/far field stage.
+#include <algorithm>
 #include <stdexcept>
 
+#include "m2l_mfma.h"
 #include "near_far.h"
 
 namespace fmm {
 
 fmm_tuning default_tuning() {
     fmm_tuning t;
-    t.queue_chunk = 1;
+    t.queue_chunk = 64;     // M2L entries per task
     t.p2p_split = 1 << 20;
     t.m2l_block = 32;
     t.grid_per_cu = 2;
     return t;
 }
 
-void run_near_far_mixed(NearFarState &, const NearFarArgs &, hipStream_t) {
-    throw std::runtime_error("mixed precision path not built yet");
+namespace {
+void read_sync(void *h, const void *d, size_t b, hipStream_t s) {
+    FMM_HIP_CHECK(hipMemcpyAsync(h, d, b, hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+}
+}  // namespace
+
+void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    const int p = a.p, P = ncoef(p), RT = (P + 31) / 32, KS = (P + 1) / 2;
+    const int64_t fragsz = (int64_t)RT * KS * 64;
+    const int32_t ncell = a.ncell;
+    const int64_t npair = a.nm2l;
+    if (P > 320) throw std::runtime_error("order too high for the MFMA M2L");
+    // ---- persistent class tables
+    if (st.p != p) {
+        FMM_HIP_CHECK(st.slot_of.grow(kDenseKeys * 4));
+        FMM_HIP_CHECK(hipMemsetAsync(st.slot_of.ptr, 0xff, kDenseKeys * 4, s));
+        FMM_HIP_CHECK(st.nslots.grow(2 * 4));
+        FMM_HIP_CHECK(hipMemsetAsync(st.nslots.ptr, 0, 2 * 4, s));
+        st.nslot_total = 0;
+        st.p = p;
+    }
+    FMM_HIP_CHECK(st.used.grow(kDenseKeys * 4));
+    FMM_HIP_CHECK(st.new_keys.grow(kDenseKeys * 4));
+    FMM_HIP_CHECK(st.used_scan.grow((kDenseKeys + 1) * 4));
+    FMM_HIP_CHECK(st.cid_of.grow(kDenseKeys * 4));
+    FMM_HIP_CHECK(st.slot_of_cid.grow(kDenseKeys * 4));
+    const size_t np1 = (size_t)std::max<int64_t>(npair, 1) + 1;
+    FMM_HIP_CHECK(st.pkey.grow(np1 * 4));
+    FMM_HIP_CHECK(st.pcid.grow(np1 * 4));
+    FMM_HIP_CHECK(st.xflag.grow(np1 * 4));
+    FMM_HIP_CHECK(st.xscan.grow(np1 * 4));
+    FMM_HIP_CHECK(st.cnt.grow(16 * 4));
+    int64_t tmp_elems = std::max<int64_t>({(int64_t)scan_tmp_elems(kDenseKeys + 1), (int64_t)scan_tmp_elems(np1),
+                                           (int64_t)radix_tmp_elems(ncell + 1), (int64_t)scan_tmp_elems(ncell + 1)});
+    FMM_HIP_CHECK(st.tmp.grow(tmp_elems * 4));
+    int32_t *cnt = st.cnt.as<int32_t>();
+
+    FMM_HIP_CHECK(hipMemsetAsync(st.used.ptr, 0, kDenseKeys * 4, s));
+    m2l_dense_keys(a.g.c, ncell, a.m2l_ptr, a.m2l_src, st.pkey.as<int32_t>(), st.used.as<int32_t>(), s);
+    FMM_HIP_CHECK(hipMemsetAsync(st.nslots.as<int32_t>() + 1, 0, 4, s));
+    m2l_alloc_slots(st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.nslots.as<int32_t>(), st.new_keys.as<int32_t>(), s);
+    int32_t ns[2];
+    read_sync(ns, st.nslots.ptr, 8, s);
+    if (ns[0] > st.nslot_total) {
+        FMM_HIP_CHECK(st.frags.grow_keep((size_t)ns[0] * fragsz * 4, s));
+        m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, KS, st.frags.as<float>(), s);
+        st.nslot_total = ns[0];
+    }
+    // compact class ids in dense-key order
+    FMM_HIP_CHECK(hipMemcpyAsync(st.used_scan.ptr, st.used.ptr, kDenseKeys * 4, hipMemcpyDeviceToDevice, s));
+    exclusive_scan_i32(st.used_scan.as<int32_t>(), kDenseKeys, cnt + 0, st.tmp.as<int32_t>(), s);
+    m2l_cid_tables(st.used_scan.as<int32_t>(), st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.cid_of.as<int32_t>(),
+                   st.slot_of_cid.as<int32_t>(), s);
+    m2l_pair_cid(st.pkey.as<int32_t>(), npair, st.cid_of.as<int32_t>(), st.pcid.as<int32_t>(), st.xflag.as<int32_t>(), s);
+    // exclusive scan over npair + 1 elements (the last one zero): xscan[npair]
+    // = number of pairs left to the per-pair kernel
+    FMM_HIP_CHECK(hipMemcpyAsync(st.xscan.ptr, st.xflag.ptr, npair * 4, hipMemcpyDeviceToDevice, s));
+    FMM_HIP_CHECK(hipMemsetAsync(st.xscan.as<int32_t>() + npair, 0, 4, s));
+    exclusive_scan_i32(st.xscan.as<int32_t>(), npair + 1, cnt + 1, st.tmp.as<int32_t>(), s);
+    // ---- targets sorted by (level, octant, cell)
+    FMM_HIP_CHECK(st.tkey.grow((size_t)(ncell + 1) * 8));
+    FMM_HIP_CHECK(st.tkey_alt.grow((size_t)(ncell + 1) * 8));
+    FMM_HIP_CHECK(st.has.grow((size_t)(ncell + 1) * 4));
+    m2l_target_keys(a.g.c, ncell, a.m2l_ptr, st.xscan.as<int32_t>(), st.tkey.as<uint64_t>(), st.has.as<int32_t>(), s);
+    radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 0, 40,
+                   st.tmp.as<int32_t>(), s);
+    exclusive_scan_i32(st.has.as<int32_t>(), ncell, cnt + 2, st.tmp.as<int32_t>(), s);
+    int32_t h3[3];
+    read_sync(h3, cnt, 12, s);
+    st.ncid = h3[0];
+    st.nextra = h3[1];
+    st.ntarget = h3[2];
+    st.ngroup = (st.ntarget + kGroup - 1) / kGroup;
+    const int32_t ng = std::max(st.ngroup, 1);
+    FMM_HIP_CHECK(st.gcount.grow((size_t)(ng + 1) * 4));
+    FMM_HIP_CHECK(st.goff.grow((size_t)(ng + 1) * 4));
+    FMM_HIP_CHECK(st.tcount.grow((size_t)(ng + 1) * 4));
+    FMM_HIP_CHECK(st.toff.grow((size_t)(ng + 1) * 4));
+    FMM_HIP_CHECK(st.gtarget.grow((size_t)ng * kGroup * 4));
+    FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, scan_tmp_elems(ng + 1) * 4)));
+    m2l_group_entries(0, st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
+                      st.gcount.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, s);
+    FMM_HIP_CHECK(hipMemcpyAsync(st.goff.ptr, st.gcount.ptr, (size_t)st.ngroup * 4, hipMemcpyDeviceToDevice, s));
+    exclusive_scan_i32(st.goff.as<int32_t>(), st.ngroup, cnt + 3, st.tmp.as<int32_t>(), s);
+    const int chunk = std::max(1, a.tuning.queue_chunk);
+    m2l_task_counts(st.gcount.as<int32_t>(), st.ngroup, chunk, st.tcount.as<int32_t>(), s);
+    FMM_HIP_CHECK(hipMemcpyAsync(st.toff.ptr, st.tcount.ptr, (size_t)st.ngroup * 4, hipMemcpyDeviceToDevice, s));
+    exclusive_scan_i32(st.toff.as<int32_t>(), st.ngroup, cnt + 4, st.tmp.as<int32_t>(), s);
+    int32_t h2[2];
+    read_sync(h2, cnt + 3, 8, s);
+    st.nentries = st.ngroup > 0 ? h2[0] : 0;
+    st.ntask = st.ngroup > 0 ? h2[1] : 0;
+    FMM_HIP_CHECK(st.ecls.grow((size_t)std::max(st.nentries, 1) * 4));
+    FMM_HIP_CHECK(st.esrc.grow((size_t)std::max(st.nentries, 1) * kGroup * 4));
+    FMM_HIP_CHECK(st.tasks.grow((size_t)std::max(st.ntask, 1) * sizeof(int4)));
+    if (st.nentries > 0)
+        FMM_HIP_CHECK(hipMemsetAsync(st.esrc.ptr, 0xff, (size_t)st.nentries * kGroup * 4, s));
+    m2l_group_entries(1, st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
+                      st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(), st.esrc.as<int32_t>(),
+                      st.gtarget.as<int32_t>(), s);
+    m2l_make_tasks(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, chunk, st.toff.as<int32_t>(),
+                   st.tasks.as<int4>(), s);
+    // ---- pairs left to the per-pair kernel (|delta| >= 2 or far displacement)
+    FMM_HIP_CHECK(st.xsrc.grow((size_t)std::max(st.nextra, 1) * 4));
+    FMM_HIP_CHECK(st.xptr.grow((size_t)(ncell + 1) * 4));
+    m2l_extra(st.xflag.as<int32_t>(), st.xscan.as<int32_t>(), npair, a.m2l_src, a.m2l_ptr, ncell, st.xsrc.as<int32_t>(),
+              st.xptr.as<int32_t>(), s);
+    // ---- P2P leaf list
+    FMM_HIP_CHECK(st.leafbuf.grow((size_t)(2 * ncell + 2) * 4));
+    FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
+    p2p_leaf_list(a.g.c, ncell, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(), st.tmp.as<int32_t>(), cnt + 5, s);
+    int32_t nl;
+    read_sync(&nl, cnt + 5, 4, s);
+    st.nleaves = nl;
+    st.built = true;
+}
+
+void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
+    const int P = ncoef(a.p);
+    const int32_t ncell = a.ncell;
+    FMM_HIP_CHECK(st.M32.grow((size_t)std::max(ncell, 1) * P * 4));
+    FMM_HIP_CHECK(st.pf.grow((size_t)std::max<int64_t>(a.n, 1) * sizeof(float4)));
+    to_f32(a.M, st.M32.as<float>(), (int64_t)ncell * P, s);
+    FMM_HIP_CHECK(hipMemsetAsync(a.L, 0, (size_t)ncell * P * 8, s));
+    m2l_mfma(st.tasks.as<int4>(), st.ntask, st.gtarget.as<int32_t>(), st.ecls.as<int32_t>(), st.esrc.as<int32_t>(),
+             st.slot_of_cid.as<int32_t>(), st.frags.as<float>(), st.M32.as<float>(), a.p, a.L, s);
+    if (st.nextra > 0) launch_m2l_fp64_add(a.g, ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, s);
+    p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
+    p2p_fp32(a.g, st.leaves.as<int32_t>(), st.nleaves, a.p2p_ptr, a.p2p_src, st.pf.as<float4>(), a.phi, a.fld, s);
 }
 
 void release_near_far(NearFarState &st) {
-    for (auto &b : st.buf) b.release();
+    DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.used_scan, &st.cid_of,
+                     &st.slot_of_cid, &st.pkey, &st.pcid, &st.xflag, &st.xscan, &st.tkey, &st.tkey_alt, &st.has,
+                     &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
+                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt};
+    for (DevBuf *b : all) b->release();
+    st.p = -1;
+    st.built = false;
 }
 
 }  // namespace fmm

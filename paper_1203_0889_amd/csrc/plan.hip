@@ -156,6 +156,8 @@ fmm::Geometry geom(fmm_plan *p) {
     return g;
 }
 
+fmm::NearFarArgs nf_args(fmm_plan *p);
+
 void do_build(fmm_plan *p, const double *pos, const double *q) {
     hipStream_t s = p->stream;
     const int64_t n = p->n;
@@ -320,6 +322,35 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         sync_read(p, ch.data(), p->cb[6].ptr, ncell * sizeof(int32_t));
         p->nleaf = std::count(ch.begin(), ch.end(), -1);
     }
+    if (p->prm.precision == FMM_PREC_MIXED) {
+        fmm::build_near_far_mixed(p->nf, nf_args(p), s);
+        mark(p, ST_CSR);
+    }
+}
+
+fmm::NearFarArgs nf_args(fmm_plan *p) {
+    fmm::NearFarArgs a;
+    a.g = geom(p);
+    a.ncell = (int32_t)p->ncell;
+    a.nleaf = p->nleaf;
+    a.n = p->n;
+    a.nm2l = p->nm2l;
+    a.p = p->prm.p;
+    a.m2l_ptr = p->m2l_ptr.as<int32_t>();
+    a.m2l_src = p->m2l_src.as<int32_t>();
+    a.p2p_ptr = p->p2p_ptr.as<int32_t>();
+    a.p2p_src = p->p2p_src.as<int32_t>();
+    a.leaf_of = p->leaf_of.as<int32_t>();
+    a.xs = p->xs.as<double>();
+    a.ys = p->ys.as<double>();
+    a.zs = p->zs.as<double>();
+    a.qs = p->qs.as<double>();
+    a.M = p->M.as<double>();
+    a.L = p->L.as<double>();
+    a.phi = p->phi_near.as<double>();
+    a.fld = p->fld_near.as<double>();
+    a.tuning = p->tuning;
+    return a;
 }
 
 void ensure_ops(fmm_plan *p) {
@@ -373,25 +404,7 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
                              p->fld_near.as<double>(), s);
         mark(p, ST_P2P);
     } else {
-        fmm::NearFarArgs a;
-        a.g = g;
-        a.ncell = ncell;
-        a.nleaf = p->nleaf;
-        a.n = p->n;
-        a.p = p->prm.p;
-        a.m2l_ptr = p->m2l_ptr.as<int32_t>();
-        a.m2l_src = p->m2l_src.as<int32_t>();
-        a.p2p_ptr = p->p2p_ptr.as<int32_t>();
-        a.p2p_src = p->p2p_src.as<int32_t>();
-        a.xs = p->xs.as<double>();
-        a.ys = p->ys.as<double>();
-        a.zs = p->zs.as<double>();
-        a.qs = p->qs.as<double>();
-        a.M = p->M.as<double>();
-        a.L = p->L.as<double>();
-        a.phi = p->phi_near.as<double>();
-        a.fld = p->fld_near.as<double>();
-        a.tuning = p->tuning;
+        fmm::NearFarArgs a = nf_args(p);
         fmm::run_near_far_mixed(p->nf, a, s);
         mark(p, ST_M2L);
         mark(p, ST_P2P);

@@ -72,6 +72,9 @@ void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_
                      const double *ys, const double *zs, const double *qs, double *phi, double *fld, hipStream_t s);
 void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
                      double *L, hipStream_t s);
+// Same kernel, adding into L (used for the pairs the MFMA path leaves out).
+void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
+                         double *L, hipStream_t s);
 
 // ---- output
 void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,

@@ -1,0 +1,109 @@
+"""GPU parity of the mixed-precision path (FP32 P2P on VALU, FP32 M2L on
+MFMA, FP64 elsewhere and in the final per-particle / per-cell accumulation)
+against the FP64 CPU oracle, and of batched instances against single solves."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1203_0889_amd import fmm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def gpu_run(pos, q, p, ncrit, theta, precision, offsets=None):
+    plan = fmm.Plan(p=p, ncrit=ncrit, theta=theta, precision=precision, device=0)
+    plan.build_tree(torch.from_numpy(np.ascontiguousarray(pos)).cuda(),
+                    torch.from_numpy(np.ascontiguousarray(q)).cuda(), offsets)
+    plan.upward()
+    out = plan.evaluate()
+    torch.cuda.synchronize()
+    return plan, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+# FP32 rounding of the near field and of M2L bounds the agreement with the
+# FP64 oracle FMM (same tree, lists and truncation): 1e-5 relative L2.
+MIXED_CASES = [
+    ("uniform4k_p4", "uniform", 4096, 1, 4, 64, (1, 2)),
+    ("uniform70k_p8", "uniform", 70000, 2, 8, 64, (1, 2)),
+    ("uniform33k_p6_ragged", "uniform", 33333, 8, 6, 50, (1, 2)),
+    ("plummer30k_p8", "plummer", 30000, 4, 8, 64, (1, 2)),
+    ("plummer20k_p10_theta04", "plummer", 20000, 3, 10, 32, (2, 5)),
+]
+
+
+@pytest.mark.parametrize("case", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_matches_oracle_fmm(case):
+    name, dist, n, seed, p, ncrit, theta = case
+    say("case", name)
+    pos, q = W.uniform_cube(n, seed) if dist == "uniform" else W.plummer(n, seed)
+    plan, out = gpu_run(pos, q, p, ncrit, theta, "mixed")
+    phi_ref, fld_ref, T = oracle.fmm(pos, q, p, ncrit, *theta)
+    e_phi, e_fld = rel(out["phi"], phi_ref), rel(out["field"], fld_ref)
+    say(name, "mixed vs oracle fmm", e_phi, e_fld)
+    assert e_phi < 1e-5 and e_fld < 1e-5
+    # tree and lists are those of the FP64 path: bit-exact vs the oracle
+    keys, perm, cells = plan.copy_tree()
+    assert np.array_equal(cells[:, :9], T.cells)
+    tg = W.error_sample(n, 13, 2048)
+    pd, fd = oracle.direct(pos, q, tg)
+    e_phi_d, e_fld_d = rel(out["phi"][tg], pd), rel(out["field"][tg], fd)
+    say(name, "mixed vs direct", e_phi_d, e_fld_d)
+    tol = {4: (1e-3, 1e-2), 6: (1e-4, 1e-3), 8: (1e-4, 1e-4), 10: (1e-4, 1e-4)}[p]
+    assert e_phi_d < tol[0] and e_fld_d < tol[1]
+    assert out["energy"][0] == pytest.approx(0.5 * np.dot(q, out["phi"]), rel=1e-12)
+
+
+def test_mixed_root_leaf_and_single_particle():
+    pos, q = W.uniform_cube(40, 5)
+    plan, out = gpu_run(pos, q, 8, 64, (1, 2), "mixed")
+    pd, fd = oracle.direct(pos, q)
+    assert rel(out["phi"], pd) < 1e-5 and rel(out["field"], fd) < 1e-5
+    plan, out = gpu_run(np.array([[0.5, 0.5, 0.5]]), np.array([1.0]), 8, 64, (1, 2), "mixed")
+    assert out["phi"][0] == 0.0 and np.all(out["field"] == 0.0)
+
+
+def test_mixed_repeated_builds_reuse_operator_cache():
+    plan = fmm.Plan(p=6, ncrit=32, precision="mixed", device=0)
+    for n, seed, dist in ((8000, 1, "uniform"), (12000, 2, "plummer"), (5000, 3, "uniform")):
+        say("rebuild", n, dist)
+        pos, q = W.uniform_cube(n, seed) if dist == "uniform" else W.plummer(n, seed)
+        plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+        plan.upward()
+        out = plan.evaluate()
+        phi_ref, fld_ref, _ = oracle.fmm(pos, q, 6, 32, 1, 2)
+        assert rel(out["phi"].cpu().numpy(), phi_ref) < 1e-5
+        assert rel(out["field"].cpu().numpy(), fld_ref) < 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_batched_instances_equal_single_solves(precision, tol):
+    # uneven sizes, an empty instance, uniform and Plummer mixed
+    parts = [W.uniform_cube(3000, 1), W.plummer(5000, 2), (np.zeros((0, 3)), np.zeros(0)),
+             W.uniform_cube(1500, 3), W.plummer(800, 4)]
+    pos = np.concatenate([p for p, _ in parts])
+    q = np.concatenate([c for _, c in parts])
+    offsets = np.cumsum([0] + [len(c) for _, c in parts])
+    plan, out = gpu_run(pos, q, 6, 32, (1, 2), precision, list(offsets))
+    _, _, cells = plan.copy_tree()
+    for k, (pk, qk) in enumerate(parts):
+        a, b = offsets[k], offsets[k + 1]
+        if b == a:
+            assert out["energy"][k] == 0.0
+            continue
+        say("instance", k, b - a)
+        _, single = gpu_run(pk, qk, 6, 32, (1, 2), precision)
+        assert rel(out["phi"][a:b], single["phi"]) < tol and rel(out["field"][a:b], single["field"]) < tol
+        phi_ref, fld_ref, T = oracle.fmm(pk, qk, 6, 32, 1, 2)
+        assert rel(out["phi"][a:b], phi_ref) < max(tol, 1e-11)
+        mine = cells[cells[:, 9] == k]
+        assert np.array_equal(mine[:, :4], T.cells[:, :4])   # same cells (level, coords) per instance
+        assert out["energy"][k] == pytest.approx(0.5 * np.dot(qk, out["phi"][a:b]), rel=1e-12)
