@@ -47,54 +47,59 @@ __device__ inline void cell_frame(const Geometry &g, int32_t cell, double *c, do
     *level = l;
 }
 
-// P2M: one thread per (leaf, order m); accumulates degrees n = m..p.
-__global__ void k_p2m(Geometry g, int32_t ncell, int p, const double *__restrict__ xs, const double *__restrict__ ys,
+// P2M: one thread per (cell, order m); non-leaves exit.  Degrees n = m..PP
+// are accumulated in registers (PP = p at compile time), with the recurrence
+// constants 1/((n+m)(n-m)) computed once per thread.
+template <int PP>
+__global__ void k_p2m(Geometry g, int32_t ncell, const double *__restrict__ xs, const double *__restrict__ ys,
                       const double *__restrict__ zs, const double *__restrict__ qs, double *__restrict__ M) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int32_t cell = (int32_t)(t / (p + 1));
-    int m = (int)(t % (p + 1));
+    int32_t cell = (int32_t)(t / (PP + 1));
+    const int m = (int)(t % (PP + 1));
     if (cell >= ncell || g.c.child[cell] >= 0) return;
-    const int P = ncoef(p);
+    constexpr int P = ncoef(PP);
     double c[3], side;
     int l;
     cell_frame(g, cell, c, &side, &l);
-    Cplx acc[kMaxP + 1];
-    for (int n = 0; n <= p; n++) acc[n] = {0.0, 0.0};
+    const double inv_side = ldexp(1.0 / side, l);
+    double dmm = 1.0;  // 1 / (2^m m!)
+    for (int i = 1; i <= m; i++) dmm /= 2 * i;
+    double inv[PP + 1];
+#pragma unroll
+    for (int n = 0; n <= PP; n++) inv[n] = n >= m + 2 ? 1.0 / (double)((n + m) * (n - m)) : 0.0;
+    double ar[PP + 1], ai[PP + 1];
+#pragma unroll
+    for (int n = 0; n <= PP; n++) ar[n] = ai[n] = 0.0;
     int32_t f = g.c.first[cell], e = f + g.c.count[cell];
     for (int32_t r = f; r < e; r++) {
-        double ux = ldexp((xs[r] - c[0]) / side, l);
-        double uy = ldexp((ys[r] - c[1]) / side, l);
-        double uz = ldexp((zs[r] - c[2]) / side, l);
+        double ux = (xs[r] - c[0]) * inv_side, uy = (ys[r] - c[1]) * inv_side, uz = (zs[r] - c[2]) * inv_side;
         double r2 = ux * ux + uy * uy + uz * uz;
-        Cplx zeta = {ux, uy};
-        Cplx rmm = {1.0, 0.0};
-        for (int j = 1; j <= m; j++) {
-            rmm = cmul(rmm, zeta);
-            rmm.re /= 2 * j;
-            rmm.im /= 2 * j;
-        }
         double q = qs[r];
-        Cplx r2m = {0.0, 0.0}, r1m = rmm;  // R_(n-2)^m, R_(n-1)^m
-        acc[m].re += q * rmm.re;
-        acc[m].im -= q * rmm.im;
-        for (int n = m + 1; n <= p; n++) {
-            Cplx rn;
+        Cplx cur = {dmm, 0.0};
+        for (int i = 1; i <= m; i++) cur = cmul(cur, Cplx{ux, uy});
+        Cplx prev = {0.0, 0.0};
+#pragma unroll
+        for (int n = 0; n <= PP; n++) {
+            if (n < m) continue;
             if (n == m + 1) {
-                rn = {uz * r1m.re, uz * r1m.im};
-            } else {
-                double a = (2 * n - 1) * uz, den = (double)((n + m) * (n - m));
-                rn = {(a * r1m.re - r2 * r2m.re) / den, (a * r1m.im - r2 * r2m.im) / den};
+                prev = cur;
+                cur = {uz * cur.re, uz * cur.im};
+            } else if (n > m + 1) {
+                double a = (2 * n - 1) * uz;
+                Cplx nx = {(a * cur.re - r2 * prev.re) * inv[n], (a * cur.im - r2 * prev.im) * inv[n]};
+                prev = cur;
+                cur = nx;
             }
-            acc[n].re += q * rn.re;
-            acc[n].im -= q * rn.im;
-            r2m = r1m;
-            r1m = rn;
+            ar[n] += q * cur.re;
+            ai[n] -= q * cur.im;
         }
     }
     double *out = M + (int64_t)cell * P;
-    for (int n = m; n <= p; n++) {
-        out[cidx_re(n, m)] = acc[n].re;
-        if (m > 0) out[cidx_im(n, m)] = acc[n].im;
+#pragma unroll
+    for (int n = 0; n <= PP; n++) {
+        if (n < m) continue;
+        out[cidx_re(n, m)] = ar[n];
+        if (m > 0) out[cidx_im(n, m)] = ai[n];
     }
 }
 
@@ -102,40 +107,124 @@ __device__ inline int octant_of(const CellArrays &c, int32_t cell) {
     return (c.ix[cell] & 1) | ((c.iy[cell] & 1) << 1) | ((c.iz[cell] & 1) << 2);
 }
 
-// M2M for the non-leaf cells of one level: thread per (cell, output row).
-__global__ void k_m2m(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ ops, double *__restrict__ M) {
-    const int P = ncoef(p);
-    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int32_t cell = lb + (int32_t)(t / P);
-    int row = (int)(t % P);
-    if (cell >= le) return;
-    int32_t ch = g.c.child[cell];
-    if (ch < 0) return;
-    int nch = g.c.nchild[cell];
-    double s = 0.0;
-    for (int k = 0; k < nch; k++) {
-        int32_t cc = ch + k;
-        const double *A = ops + (int64_t)octant_of(g.c, cc) * P * P + (int64_t)row * P;
-        const double *x = M + (int64_t)cc * P;
-        for (int i = 0; i < P; i++) s += A[i] * x[i];
-    }
-    M[(int64_t)cell * P + row] = s;
+// M2M and L2L, octant-major.  A block owns kPB parents of one level and a
+// thread owns one coefficient row; for each octant o the block applies the
+// matrix of o (column-major, so a wave reads consecutive rows) to the kPB
+// vectors staged in LDS.  Each matrix column is read once per kPB parents.
+constexpr int kPB = 16;
+
+__device__ inline int32_t child_in_octant(const CellArrays &c, int32_t parent, int o) {
+    int32_t ch = c.child[parent];
+    if (ch < 0) return -1;
+    int nch = c.nchild[parent];
+    for (int k = 0; k < nch; k++)
+        if (octant_of(c, ch + k) == o) return ch + k;
+    return -1;
 }
 
-// L2L for the cells of one level (all have parents): L_child += B L_parent.
-__global__ void k_l2l(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ ops, double *__restrict__ L) {
+constexpr int kCW = 32;  // operator columns staged in LDS at a time
+
+// Bulk copy global -> LDS with several loads in flight per thread.
+__device__ inline void stage(double *__restrict__ dst, const double *__restrict__ src, int n) {
+    int i = threadIdx.x;
+    const int step = blockDim.x;
+    for (; i + 3 * step < n; i += 4 * step) {
+        double a0 = src[i], a1 = src[i + step], a2 = src[i + 2 * step], a3 = src[i + 3 * step];
+        dst[i] = a0;
+        dst[i + step] = a1;
+        dst[i + 2 * step] = a2;
+        dst[i + 3 * step] = a3;
+    }
+    for (; i < n; i += step) dst[i] = src[i];
+}
+
+// acc[k] += sum_(i in [c0, c0+cw)) Op[i][row] * x[k][i] with the operator's
+// column chunk staged in LDS.
+__device__ inline void apply_chunk(const double *__restrict__ op, int P, int c0, int cw, double *__restrict__ sh,
+                                   const double *__restrict__ x, int row, double *acc) {
+    __syncthreads();
+    stage(sh, op + (int64_t)c0 * P, cw * P);
+    __syncthreads();
+    if (row < P)
+        for (int i = 0; i < cw; i++) {
+            double a = sh[i * P + row];
+#pragma unroll
+            for (int k = 0; k < kPB; k++) acc[k] += a * x[k * P + c0 + i];
+        }
+}
+
+// M2M: block (parent chunk of kPB, octant o) writes the octant's
+// contribution to part[o][parent][row]; k_m2m_sum adds the 8 parts in a
+// fixed order (deterministic).
+__global__ void k_m2m(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ ops,
+                      const double *__restrict__ M, double *__restrict__ part) {
+    extern __shared__ double dyn[];
+    __shared__ int32_t kid[kPB];
     const int P = ncoef(p);
-    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int32_t cell = lb + (int32_t)(t / P);
-    int row = (int)(t % P);
-    if (cell >= le) return;
-    int32_t par = g.c.parent[cell];
-    if (par < 0) return;
-    const double *B = ops + (int64_t)octant_of(g.c, cell) * P * P + (int64_t)row * P;
-    const double *x = L + (int64_t)par * P;
-    double s = 0.0;
-    for (int i = 0; i < P; i++) s += B[i] * x[i];
-    L[(int64_t)cell * P + row] += s;
+    double *xs_ = dyn, *sh = dyn + kPB * P;
+    const int o = blockIdx.y;
+    const int32_t p0 = lb + blockIdx.x * kPB;
+    const int row = threadIdx.x;
+    if (threadIdx.x < kPB) {
+        int32_t par = p0 + threadIdx.x;
+        kid[threadIdx.x] = par < le ? child_in_octant(g.c, par, o) : -1;
+    }
+    __syncthreads();
+    for (int k = 0; k < kPB; k++) {
+        int32_t ch = kid[k];
+        for (int i = threadIdx.x; i < P; i += blockDim.x) xs_[k * P + i] = ch >= 0 ? M[(int64_t)ch * P + i] : 0.0;
+    }
+    double acc[kPB];
+#pragma unroll
+    for (int k = 0; k < kPB; k++) acc[k] = 0.0;
+    const double *A = ops + (int64_t)o * P * P;
+    for (int c0 = 0; c0 < P; c0 += kCW) apply_chunk(A, P, c0, P - c0 < kCW ? P - c0 : kCW, sh, xs_, row, acc);
+    if (row < P)
+        for (int k = 0; k < kPB; k++) {
+            int32_t par = p0 + k;
+            if (par < le) part[((int64_t)o * (le - lb) + (par - lb)) * P + row] = acc[k];
+        }
+}
+
+__global__ void k_m2m_sum(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ part,
+                          double *__restrict__ M) {
+    const int P = ncoef(p);
+    const int64_t n = (int64_t)(le - lb) * P;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t par = lb + (int32_t)(i / P);
+        if (g.c.child[par] < 0) continue;
+        double s = 0.0;
+        for (int o = 0; o < 8; o++) s += part[(int64_t)o * n + i];
+        M[(int64_t)par * P + (i % P)] = s;
+    }
+}
+
+// L2L: block (parent chunk of kPB, octant o) adds into the children of
+// octant o (each child has one parent and one octant: no conflicts).
+__global__ void k_l2l(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ ops,
+                      double *__restrict__ L) {
+    extern __shared__ double dyn[];
+    const int P = ncoef(p);
+    double *xp = dyn, *sh = dyn + kPB * P;
+    const int o = blockIdx.y;
+    const int32_t p0 = lb + blockIdx.x * kPB;
+    const int row = threadIdx.x;
+    for (int k = 0; k < kPB; k++) {
+        int32_t par = p0 + k;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) xp[k * P + i] = par < le ? L[(int64_t)par * P + i] : 0.0;
+    }
+    double acc[kPB];
+#pragma unroll
+    for (int k = 0; k < kPB; k++) acc[k] = 0.0;
+    const double *B = ops + (int64_t)o * P * P;
+    for (int c0 = 0; c0 < P; c0 += kCW) apply_chunk(B, P, c0, P - c0 < kCW ? P - c0 : kCW, sh, xp, row, acc);
+    if (row < P)
+        for (int k = 0; k < kPB; k++) {
+            int32_t par = p0 + k;
+            if (par >= le) break;
+            int32_t ch = child_in_octant(g.c, par, o);
+            if (ch >= 0) L[(int64_t)ch * P + row] += acc[k];
+        }
 }
 
 // Local coefficient L~_n^m for any m (negative via conjugate symmetry).
@@ -248,20 +337,42 @@ __global__ void k_finalize(int64_t n, const uint32_t *__restrict__ perm, const d
     }
 }
 
-// E_k = 1/2 sum_(i in k) q_i phi_i, one block per instance, fixed order.
-__global__ void k_energy(const int64_t *__restrict__ offsets, const double *__restrict__ qs,
-                         const double *__restrict__ pn, const double *__restrict__ pf, double *__restrict__ energy) {
+// E_k = 1/2 sum_(i in k) q_i phi_i in a fixed order: per-chunk partial sums
+// (chunks never straddle instances), then per-instance sums of the chunks.
+constexpr int kEnergyChunk = 8192;
+
+__global__ void __launch_bounds__(256) k_energy_part(const int64_t *__restrict__ offsets, int n_inst,
+                                                     const int32_t *__restrict__ chunk_off, const double *__restrict__ qs,
+                                                     const double *__restrict__ pn, const double *__restrict__ pf,
+                                                     double *__restrict__ part) {
     __shared__ double red[256];
-    int k = blockIdx.x;
+    int j = blockIdx.x;
+    // instance of chunk j: largest k with chunk_off[k] <= j
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (chunk_off[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    int64_t b = offsets[lo] + (int64_t)(j - chunk_off[lo]) * kEnergyChunk;
+    int64_t e = b + kEnergyChunk < offsets[lo + 1] ? b + kEnergyChunk : offsets[lo + 1];
     double s = 0.0;
-    for (int64_t r = offsets[k] + threadIdx.x; r < offsets[k + 1]; r += 256) s += qs[r] * (pn[r] + pf[r]);
+    for (int64_t r = b + threadIdx.x; r < e; r += 256) s += qs[r] * (pn[r] + pf[r]);
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) energy[k] = 0.5 * red[0];
+    if (threadIdx.x == 0) part[j] = red[0];
+}
+
+__global__ void k_energy_sum(int n_inst, const int32_t *__restrict__ chunk_off, const double *__restrict__ part,
+                             double *__restrict__ energy) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    double s = 0.0;
+    for (int j = chunk_off[k]; j < chunk_off[k + 1]; j++) s += part[j];
+    energy[k] = 0.5 * s;
 }
 
 }  // namespace
@@ -334,8 +445,8 @@ std::vector<double> build_translation_ops(int p, int dir) {
             for (int n = 0; n <= p; n++)
                 for (int m = 0; m <= n; m++) {
                     cd v = out[(size_t)n * (p + 1) + m];
-                    A[(size_t)cidx_re(n, m) * P + col] = v.real();
-                    if (m > 0) A[(size_t)cidx_im(n, m) * P + col] = v.imag();
+                    A[(size_t)col * P + cidx_re(n, m)] = v.real();
+                    if (m > 0) A[(size_t)col * P + cidx_im(n, m)] = v.imag();
                 }
         }
     }
@@ -346,21 +457,40 @@ void launch_p2m(Geometry g, int32_t ncell, int p, const double *xs, const double
                 const double *qs, double *M, hipStream_t s) {
     int64_t work = (int64_t)ncell * (p + 1);
     if (work == 0) return;
-    hipLaunchKernelGGL(k_p2m, dim3(grid_for(work, 128, 1 << 30)), dim3(128), 0, s, g, ncell, p, xs, ys, zs, qs, M);
+    dim3 grid(grid_for(work, 128, 1 << 30)), block(128);
+#define FMM_P2M_CASE(PP)                                                                  \
+    case PP:                                                                              \
+        hipLaunchKernelGGL(k_p2m<PP>, grid, block, 0, s, g, ncell, xs, ys, zs, qs, M);    \
+        break;
+    switch (p) {
+        FMM_P2M_CASE(0) FMM_P2M_CASE(1) FMM_P2M_CASE(2) FMM_P2M_CASE(3) FMM_P2M_CASE(4) FMM_P2M_CASE(5)
+        FMM_P2M_CASE(6) FMM_P2M_CASE(7) FMM_P2M_CASE(8) FMM_P2M_CASE(9) FMM_P2M_CASE(10) FMM_P2M_CASE(11)
+        FMM_P2M_CASE(12) FMM_P2M_CASE(13) FMM_P2M_CASE(14) FMM_P2M_CASE(15) FMM_P2M_CASE(16)
+        default: throw HipError{hipErrorInvalidValue, "p2m: unsupported order"};
+    }
+#undef FMM_P2M_CASE
     FMM_LAUNCH_CHECK();
 }
 
-void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, hipStream_t s) {
-    int64_t work = (int64_t)(le - lb) * ncoef(p);
-    if (work <= 0) return;
-    hipLaunchKernelGGL(k_m2m, dim3(grid_for(work, 128, 1 << 30)), dim3(128), 0, s, g, lb, le, p, ops, M);
+static int rows_block(int p) { return ((ncoef(p) + 63) / 64) * 64; }
+
+void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, double *part,
+                      hipStream_t s) {
+    if (le <= lb) return;
+    size_t lds = (size_t)(kPB + kCW) * ncoef(p) * sizeof(double);
+    dim3 grid((le - lb + kPB - 1) / kPB, 8);
+    hipLaunchKernelGGL(k_m2m, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, ops, M, part);
+    FMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_m2m_sum, dim3(grid_for((int64_t)(le - lb) * ncoef(p), 256, 4096)), dim3(256), 0, s, g, lb, le, p,
+                       part, M);
     FMM_LAUNCH_CHECK();
 }
 
 void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *L, hipStream_t s) {
-    int64_t work = (int64_t)(le - lb) * ncoef(p);
-    if (work <= 0) return;
-    hipLaunchKernelGGL(k_l2l, dim3(grid_for(work, 128, 1 << 30)), dim3(128), 0, s, g, lb, le, p, ops, L);
+    if (le <= lb) return;
+    size_t lds = (size_t)(kPB + kCW) * ncoef(p) * sizeof(double);
+    dim3 grid((le - lb + kPB - 1) / kPB, 8);
+    hipLaunchKernelGGL(k_l2l, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, ops, L);
     FMM_LAUNCH_CHECK();
 }
 
@@ -381,9 +511,21 @@ void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const do
     FMM_LAUNCH_CHECK();
 }
 
-void launch_energy(const int64_t *d_offsets, int n_inst, const double *qs, const double *phi_near,
-                   const double *phi_far, double *energy, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy, dim3(n_inst), dim3(256), 0, s, d_offsets, qs, phi_near, phi_far, energy);
+std::vector<int32_t> energy_chunks(const std::vector<int64_t> &offsets) {
+    std::vector<int32_t> co(offsets.size(), 0);
+    for (size_t k = 0; k + 1 < offsets.size(); k++)
+        co[k + 1] = co[k] + (int32_t)((offsets[k + 1] - offsets[k] + kEnergyChunk - 1) / kEnergyChunk);
+    return co;
+}
+
+void launch_energy(const int64_t *d_offsets, int n_inst, const int32_t *d_chunk_off, int32_t nchunk, const double *qs,
+                   const double *phi_near, const double *phi_far, double *part, double *energy, hipStream_t s) {
+    if (nchunk > 0) {
+        hipLaunchKernelGGL(k_energy_part, dim3(nchunk), dim3(256), 0, s, d_offsets, n_inst, d_chunk_off, qs, phi_near,
+                           phi_far, part);
+        FMM_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_energy_sum, dim3(grid_for(n_inst, 64)), dim3(64), 0, s, n_inst, d_chunk_off, part, energy);
     FMM_LAUNCH_CHECK();
 }
 

@@ -30,60 +30,100 @@ __device__ inline bool mac_exact(int la, int ax, int ay, int az, int lb, int bx,
     return 3ull * b * b * s * s < a * a * d2;
 }
 
-__global__ void k_traverse(CellArrays c, const int2 *__restrict__ fin, int32_t nf, int2 *__restrict__ fout,
-                           int32_t capf, PairBuf pb, int32_t *__restrict__ counters, uint32_t ta, uint32_t tb) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x) {
-        int2 pr = fin[i];
-        int32_t A = pr.x, B = pr.y;
-        int la = c.level[A], lb = c.level[B];
-        int32_t chA = c.child[A], chB = c.child[B];
-        bool leafA = chA < 0, leafB = chB < 0;
-        if (A != B && mac_exact(la, c.ix[A], c.iy[A], c.iz[A], lb, c.ix[B], c.iy[B], c.iz[B], ta, tb)) {
-            int32_t slot = atomicAdd(&counters[1], 1);
-            if (slot < pb.cap_m2l) pb.m2l[slot] = ((uint64_t)(uint32_t)A << 32) | (uint32_t)B;
-        } else if (leafA && leafB) {
-            int32_t slot = atomicAdd(&counters[2], 1);
-            if (slot < pb.cap_p2p) pb.p2p[slot] = ((uint64_t)(uint32_t)A << 32) | (uint32_t)B;
-        } else if (!leafB && (leafA || la > lb)) {
-            int k = c.nchild[B];
-            int32_t slot = atomicAdd(&counters[0], k);
-            for (int j = 0; j < k; j++)
-                if (slot + j < capf) fout[slot + j] = make_int2(A, chB + j);
-        } else {
-            int k = c.nchild[A];
-            int32_t slot = atomicAdd(&counters[0], k);
-            for (int j = 0; j < k; j++)
-                if (slot + j < capf) fout[slot + j] = make_int2(chA + j, B);
-        }
-    }
+// One BFS step.  The frontier size is read from device memory (clamped to
+// the buffer capacity), so all steps are enqueued without host round trips.
+// Each workgroup stages its accepted pairs and its next-frontier pairs in
+// LDS and reserves global space with one atomic per flush: same-address
+// atomics are few, and global writes are contiguous.
+constexpr int kTravThreads = 256;
+constexpr int kBufM = 2048;   // staged M2L keys
+constexpr int kBufP = 1024;   // staged P2P keys
+constexpr int kBufF = 4096;   // staged frontier pairs (one tile adds at most 8 per thread)
+
+template <class K>
+__device__ inline void flush_keys(K *__restrict__ buf, int32_t &cnt, K *__restrict__ out, int32_t cap,
+                                  int32_t *__restrict__ gcount, int32_t *sh_base) {
+    if (threadIdx.x == 0) *sh_base = atomicAdd(gcount, cnt);
+    __syncthreads();
+    int32_t base = *sh_base;
+    for (int j = threadIdx.x; j < cnt; j += kTravThreads)
+        if (base + j < cap) out[base + j] = buf[j];
+    __syncthreads();
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
 }
 
+template <class K>
+__global__ void __launch_bounds__(kTravThreads) k_traverse(CellArrays c, const int2 *__restrict__ fin,
+                                                           const int32_t *__restrict__ nf_in, int2 *__restrict__ fout,
+                                                           int32_t *__restrict__ nf_out, int32_t capf,
+                                                           K *__restrict__ m2l, K *__restrict__ p2p, int32_t cap_m2l,
+                                                           int32_t cap_p2p, int32_t *__restrict__ n_m2l,
+                                                           int32_t *__restrict__ n_p2p, int bits, uint32_t ta,
+                                                           uint32_t tb) {
+    __shared__ K bm[kBufM];
+    __shared__ K bp[kBufP];
+    __shared__ int2 bf[kBufF];
+    __shared__ int32_t cm, cp, cf, base_sh;
+    int32_t nf = *nf_in;
+    nf = nf < capf ? nf : capf;
+    if (threadIdx.x == 0) cm = cp = cf = 0;
+    __syncthreads();
+    const int32_t stride = gridDim.x * kTravThreads;
+    for (int32_t base = blockIdx.x * kTravThreads; base < nf; base += stride) {
+        int32_t i = base + threadIdx.x;
+        if (i < nf) {
+            int2 pr = fin[i];
+            int32_t A = pr.x, B = pr.y;
+            int la = c.level[A], lb = c.level[B];
+            int32_t chA = c.child[A], chB = c.child[B];
+            bool leafA = chA < 0, leafB = chB < 0;
+            const K key = ((K)(uint32_t)A << bits) | (K)(uint32_t)B;
+            if (A != B && mac_exact(la, c.ix[A], c.iy[A], c.iz[A], lb, c.ix[B], c.iy[B], c.iz[B], ta, tb)) {
+                bm[atomicAdd(&cm, 1)] = key;
+            } else if (leafA && leafB) {
+                bp[atomicAdd(&cp, 1)] = key;
+            } else if (!leafB && (leafA || la > lb)) {
+                int k = c.nchild[B];
+                int32_t o = atomicAdd(&cf, k);
+                for (int j = 0; j < k; j++) bf[o + j] = make_int2(A, chB + j);
+            } else {
+                int k = c.nchild[A];
+                int32_t o = atomicAdd(&cf, k);
+                for (int j = 0; j < k; j++) bf[o + j] = make_int2(chA + j, B);
+            }
+        }
+        __syncthreads();
+        // a tile adds at most 256 keys per list and 2048 frontier pairs
+        if (cm > kBufM - kTravThreads) flush_keys<K>(bm, cm, m2l, cap_m2l, n_m2l, &base_sh);
+        if (cp > kBufP - kTravThreads) flush_keys<K>(bp, cp, p2p, cap_p2p, n_p2p, &base_sh);
+        if (cf > kBufF - 8 * kTravThreads) flush_keys<int2>(bf, cf, fout, capf, nf_out, &base_sh);
+    }
+    __syncthreads();
+    if (cm > 0) flush_keys<K>(bm, cm, m2l, cap_m2l, n_m2l, &base_sh);
+    if (cp > 0) flush_keys<K>(bp, cp, p2p, cap_p2p, n_p2p, &base_sh);
+    if (cf > 0) flush_keys<int2>(bf, cf, fout, capf, nf_out, &base_sh);
+}
+
+// counters: [0] = #M2L, [1] = #P2P, [2 + k] = size of frontier k.
 __global__ void k_init_frontier(const int64_t *__restrict__ offsets, int n_inst, int2 *__restrict__ front,
                                 int32_t *__restrict__ counters) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int32_t nf = 0;
     for (int k = 0; k < n_inst; k++)
         if (offsets[k + 1] > offsets[k]) front[nf++] = make_int2(k, k);
-    counters[0] = nf;
-    counters[1] = 0;
-    counters[2] = 0;
+    counters[2] = nf;
 }
 
-__global__ void k_repack(uint64_t *__restrict__ pairs, int64_t n, int bits) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t v = pairs[i];
-        pairs[i] = ((v >> 32) << bits) | (v & 0xffffffffull);
-    }
-}
-
-__global__ void k_csr(const uint64_t *__restrict__ sorted, int64_t n, int bits, int32_t ncell, int32_t *__restrict__ ptr,
+template <class K>
+__global__ void k_csr(const K *__restrict__ sorted, int64_t n, int bits, int32_t ncell, int32_t *__restrict__ ptr,
                       int32_t *__restrict__ src) {
-    const uint64_t mask = (1ull << bits) - 1;
+    const K mask = (K)(((uint64_t)1 << bits) - 1);
     int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = tid; i < n; i += stride) src[i] = (int32_t)(sorted[i] & mask);
     for (int64_t cidx = tid; cidx <= ncell; cidx += stride) {
-        uint64_t want = (uint64_t)cidx << bits;
+        K want = (K)((uint64_t)cidx << bits);
         int64_t a = 0, b = n;
         while (a < b) {
             int64_t mid = (a + b) >> 1;
@@ -95,11 +135,17 @@ __global__ void k_csr(const uint64_t *__restrict__ sorted, int64_t n, int bits, 
 
 }  // namespace
 
-void launch_traverse(CellArrays c, const int2 *fin, int32_t nf, int2 *fout, int32_t capf, PairBuf pb,
-                     int32_t *counters, uint32_t theta_num, uint32_t theta_den, hipStream_t s) {
-    if (nf <= 0) return;
-    hipLaunchKernelGGL(k_traverse, dim3(grid_for(nf, 256, 16384)), dim3(256), 0, s, c, fin, nf, fout, capf, pb, counters,
-                       theta_num, theta_den);
+void launch_traverse(CellArrays c, const int2 *fin, const int32_t *nf_in, int2 *fout, int32_t *nf_out, int32_t capf,
+                     PairBuf pb, int32_t *counters, int bits, uint32_t theta_num, uint32_t theta_den, hipStream_t s) {
+    dim3 grid(1024), block(kTravThreads);
+    if (pb.key32)
+        hipLaunchKernelGGL(k_traverse<uint32_t>, grid, block, 0, s, c, fin, nf_in, fout, nf_out, capf,
+                           (uint32_t *)pb.m2l, (uint32_t *)pb.p2p, pb.cap_m2l, pb.cap_p2p, counters, counters + 1, bits,
+                           theta_num, theta_den);
+    else
+        hipLaunchKernelGGL(k_traverse<uint64_t>, grid, block, 0, s, c, fin, nf_in, fout, nf_out, capf,
+                           (uint64_t *)pb.m2l, (uint64_t *)pb.p2p, pb.cap_m2l, pb.cap_p2p, counters, counters + 1, bits,
+                           theta_num, theta_den);
     FMM_LAUNCH_CHECK();
 }
 
@@ -108,16 +154,15 @@ void launch_init_frontier(const int64_t *d_offsets, int n_inst, int2 *front, int
     FMM_LAUNCH_CHECK();
 }
 
-void launch_repack(uint64_t *pairs, int64_t n, int bits, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_repack, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, pairs, n, bits);
-    FMM_LAUNCH_CHECK();
-}
-
-void launch_csr(const uint64_t *sorted, int64_t n, int bits, int32_t ncell, int32_t *ptr, int32_t *src,
+void launch_csr(const void *sorted, bool key32, int64_t n, int bits, int32_t ncell, int32_t *ptr, int32_t *src,
                 hipStream_t s) {
     int64_t work = n > ncell + 1 ? n : ncell + 1;
-    hipLaunchKernelGGL(k_csr, dim3(grid_for(work, 256, 16384)), dim3(256), 0, s, sorted, n, bits, ncell, ptr, src);
+    if (key32)
+        hipLaunchKernelGGL(k_csr<uint32_t>, dim3(grid_for(work, 256, 16384)), dim3(256), 0, s, (const uint32_t *)sorted, n,
+                           bits, ncell, ptr, src);
+    else
+        hipLaunchKernelGGL(k_csr<uint64_t>, dim3(grid_for(work, 256, 16384)), dim3(256), 0, s, (const uint64_t *)sorted, n,
+                           bits, ncell, ptr, src);
     FMM_LAUNCH_CHECK();
 }
 

@@ -5,7 +5,6 @@
 
 namespace fmm {
 
-constexpr int kGroup = 32;                                   // targets per MFMA column block
 constexpr int kRhoMax = 24;                                  // |rho_i| covered by the dense class table
 constexpr int kRhoSpan = 2 * kRhoMax + 1;
 constexpr int kDenseKeys = 3 * kRhoSpan * kRhoSpan * kRhoSpan;  // delta in {-1, 0, 1}
@@ -13,8 +12,8 @@ constexpr int kDenseKeys = 3 * kRhoSpan * kRhoSpan * kRhoSpan;  // delta in {-1,
 void m2l_dense_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *src, int32_t *pkey,
                     int32_t *used, hipStream_t s);
 void m2l_alloc_slots(const int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, hipStream_t s);
-void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int KS, float *frags,
-                   hipStream_t s);
+void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int KS4, int64_t fragsz,
+                   float *frags, hipStream_t s);
 void m2l_cid_tables(const int32_t *used_scan, const int32_t *used, const int32_t *slot_of, int32_t *cid_of,
                     int32_t *slot_of_cid, hipStream_t s);
 void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int32_t *pcid, int32_t *xflag,
@@ -30,16 +29,14 @@ void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, 
                     int4 *tasks, hipStream_t s);
 void m2l_extra(const int32_t *xflag, const int32_t *xscan, int64_t npair, const int32_t *src, const int32_t *ptr,
                int32_t ncell, int32_t *xsrc, int32_t *xptr, hipStream_t s);
-void to_f32(const double *in, float *out, int64_t n, hipStream_t s);
 void m2l_mfma(const int4 *tasks, int32_t ntask, const int32_t *gtarget, const int32_t *ecls, const int32_t *esrc,
               const int32_t *slot_of_cid, const float *frags, const float *M32, int p, double *L, hipStream_t s);
 
-// ---- p2p_fp32.hip
-void p2p_leaf_list(CellArrays c, int32_t ncell, int32_t *flag, int32_t *leaves, int32_t *tmp, int32_t *d_count,
-                   hipStream_t s);
+// ---- p2p_fp32.hip (preparation of the P2P tasks)
+void p2p_leaf_list(CellArrays c, int32_t ncell, const int32_t *p2p_ptr, const int32_t *p2p_src, int32_t *buf,
+                   int32_t *leaves, int32_t *tmp, int32_t *d_count, hipStream_t s);
 void p2p_prepare(Geometry g, int64_t n, const int32_t *leaf_of, const double *xs, const double *ys,
                  const double *zs, const double *qs, float4 *pf, hipStream_t s);
-void p2p_fp32(Geometry g, const int32_t *leaves, int32_t nleaves, const int32_t *ptr, const int32_t *src,
-              const float4 *pf, double *phi, double *fld, hipStream_t s);
+void cell_centres(Geometry g, int32_t ncell, double *centre, hipStream_t s);
 
 }  // namespace fmm

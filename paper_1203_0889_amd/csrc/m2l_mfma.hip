@@ -13,15 +13,13 @@
 // across builds.  Pairs with |delta| >= 2 are nearly one class each and go
 // to the per-pair FP64 kernel instead.
 //
-// Batching: targets are grouped 32 at a time (same level and octant, Morton
-// order, so neighbouring targets share their class sets).  A group's entries
-// are its distinct classes in class order, each with the source cell of
-// every target slot (-1 if absent).  One wave applies T_c to the 32 gathered
-// multipoles with v_mfma_f32_32x32x2_f32: A operand = T_c fragments
-// (pre-swizzled so each wave load is one contiguous 256-byte line), B operand
-// = M~ of the slot's source, C = the 32 targets' local expansions in FP32
-// accumulators.  Results are added into the FP64 locals.
+// Batching: targets are grouped 128 at a time (same level and octant,
+// Morton order, so neighbouring targets share their class sets).  A group's
+// entries are its distinct classes in class order, each with the source
+// cell of every target slot (-1 if absent).  The work queue applies each
+// entry's T_c to the gathered multipoles on the matrix cores.
 #include "m2l_mfma.h"
+#include "queue.h"
 
 #include <stdexcept>
 
@@ -77,8 +75,8 @@ __global__ void k_alloc_slots(const int32_t *__restrict__ used, int32_t nkeys, i
 // Build the FP32 operator fragments of each new class: one workgroup per
 // class.  Lane m computes column m of I_n^m (n <= 2p) in FP64.
 __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ new_keys, int32_t nnew,
-                                                   const int32_t *__restrict__ slot_of, int p, int RT, int KS,
-                                                   float *__restrict__ frags) {
+                                                   const int32_t *__restrict__ slot_of, int p, int RT, int KS4,
+                                                   int64_t fragsz, float *__restrict__ frags) {
     __shared__ double Ire[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2], Iim[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2];
     int32_t j = blockIdx.x;
     if (j >= nnew) return;
@@ -128,13 +126,16 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
     }
     __syncthreads();
     const int P = ncoef(p);
-    float *out = frags + (int64_t)slot_of[k] * RT * KS * 64;
-    const int total = RT * KS * 64;
+    // fragment order: float index ((rt * NQ + q) * 64 + lane) * 4 + u holds
+    // T[rt * 32 + lane % 32][(lane / 32) * KS4 + 4 q + u]  (NQ = KS4 / 4)
+    const int NQ = KS4 / 4;
+    float *out = frags + (int64_t)slot_of[k] * fragsz;
+    const int total = (int)fragsz;   // RT * KS4 * 64 used, the rest is zero padding
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
-        int lane = f & 63, ks = (f >> 6) % KS, rt = (f >> 6) / KS;
-        int row = rt * 32 + (lane & 31), col = 2 * ks + (lane >> 5);
+        int u = f & 3, lane = (f >> 2) & 63, q = (f >> 8) % NQ, rt = (f >> 8) / NQ;
+        int row = rt * 32 + (lane & 31), col = (lane >> 5) * KS4 + 4 * q + u;
         double v = 0.0;
-        if (row < P && col < P) {
+        if (f < RT * KS4 * 64 && row < P && col < P) {
             // output (n, m, part) and input (kk, l, part) of the real layouts
             int n = 0;
             while ((n + 1) * (n + 1) <= row) n++;
@@ -217,7 +218,33 @@ __global__ void k_target_keys(CellArrays c, int32_t ncell, const int32_t *__rest
 }
 
 // Per group (workgroup): mark the classes of its targets in an LDS bitmap;
-// mode 0 counts them, mode 1 writes the entries.
+// mode 0 counts them, mode 1 writes the entries.  The (target, pair)
+// iteration is flattened over the group so all threads stay busy.
+__device__ inline void group_pairs(const uint64_t *__restrict__ tsorted, int t0, int nt, const int32_t *__restrict__ ptr,
+                                   int32_t *pre, int32_t *tgt) {
+    // pre[s] = first flattened index of slot s, tgt[s] = target cell
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int s = 0; s < nt; s++) {
+            int32_t A = (int32_t)(tsorted[t0 + s] & 0xffffffffull);
+            tgt[s] = A;
+            pre[s] = run;
+            run += ptr[A + 1] - ptr[A];
+        }
+        pre[nt] = run;
+    }
+    __syncthreads();
+}
+
+__device__ inline int slot_of_index(const int32_t *pre, int nt, int32_t idx) {
+    int lo = 0, hi = nt - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ void __launch_bounds__(256) k_group_entries(int mode, const uint64_t *__restrict__ tsorted, int32_t ntarget,
                                                        const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
                                                        const int32_t *__restrict__ pcid, int32_t ncid,
@@ -225,19 +252,19 @@ __global__ void __launch_bounds__(256) k_group_entries(int mode, const uint64_t 
                                                        int32_t *__restrict__ ecls, int32_t *__restrict__ esrc,
                                                        int32_t *__restrict__ gtarget) {
     extern __shared__ uint32_t bits[];
-    __shared__ int32_t wbase[1024 + 1];
+    __shared__ int32_t wbase[256 + 1];
+    __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L];
     const int g = blockIdx.x;
     const int nwords = (ncid + 31) / 32;
     for (int w = threadIdx.x; w < nwords; w += blockDim.x) bits[w] = 0u;
-    __syncthreads();
-    int t0 = g * kGroup;
-    int nt = ntarget - t0 < kGroup ? ntarget - t0 : kGroup;
-    for (int s = 0; s < nt; s++) {
-        int32_t A = (int32_t)(tsorted[t0 + s] & 0xffffffffull);
-        for (int32_t e = ptr[A] + threadIdx.x; e < ptr[A + 1]; e += blockDim.x) {
-            int32_t cid = pcid[e];
-            if (cid >= 0) atomicOr(&bits[cid >> 5], 1u << (cid & 31));
-        }
+    int t0 = g * kGroupM2L;
+    int nt = ntarget - t0 < kGroupM2L ? ntarget - t0 : kGroupM2L;
+    group_pairs(tsorted, t0, nt, ptr, pre, tgt);
+    const int32_t total = pre[nt];
+    for (int32_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int s = slot_of_index(pre, nt, idx);
+        int32_t cid = pcid[ptr[tgt[s]] + (idx - pre[s])];
+        if (cid >= 0) atomicOr(&bits[cid >> 5], 1u << (cid & 31));
     }
     __syncthreads();
     if (mode == 0) {
@@ -250,15 +277,12 @@ __global__ void __launch_bounds__(256) k_group_entries(int mode, const uint64_t 
         if (threadIdx.x == 0) gcount[g] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
         return;
     }
-    // mode 1: exclusive popcount prefix over words, chunked by 1024 words
+    // mode 1: exclusive popcount prefix over words; thread t owns a contiguous word range
     const int32_t base = goff[g];
-    if (threadIdx.x < kGroup) gtarget[g * kGroup + threadIdx.x] =
-        threadIdx.x < nt ? (int32_t)(tsorted[t0 + threadIdx.x] & 0xffffffffull) : -1;
-    // serial-per-thread chunks: thread t owns words [t*per, (t+1)*per)
+    if (threadIdx.x < kGroupM2L) gtarget[g * kGroupM2L + threadIdx.x] = threadIdx.x < nt ? tgt[threadIdx.x] : -1;
     int per = (nwords + blockDim.x - 1) / blockDim.x;
     int mine = 0;
     for (int w = threadIdx.x * per; w < (int)(threadIdx.x + 1) * per && w < nwords; w++) mine += __popc(bits[w]);
-    // block exclusive scan of `mine`
     wbase[threadIdx.x] = mine;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -271,7 +295,6 @@ __global__ void __launch_bounds__(256) k_group_entries(int mode, const uint64_t 
         wbase[blockDim.x] = run;
     }
     __syncthreads();
-    // word prefix stored back into a second region of `bits` (after nwords)
     uint32_t *wpre = bits + nwords;
     {
         int run = wbase[threadIdx.x];
@@ -281,16 +304,15 @@ __global__ void __launch_bounds__(256) k_group_entries(int mode, const uint64_t 
         }
     }
     __syncthreads();
-    for (int s = 0; s < nt; s++) {
-        int32_t A = (int32_t)(tsorted[t0 + s] & 0xffffffffull);
-        for (int32_t e = ptr[A] + threadIdx.x; e < ptr[A + 1]; e += blockDim.x) {
-            int32_t cid = pcid[e];
-            if (cid < 0) continue;
-            uint32_t wv = bits[cid >> 5] & ((1u << (cid & 31)) - 1u);
-            int32_t ent = base + (int32_t)wpre[cid >> 5] + __popc(wv);
-            ecls[ent] = cid;
-            esrc[(int64_t)ent * kGroup + s] = src[e];
-        }
+    for (int32_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int s = slot_of_index(pre, nt, idx);
+        int32_t e = ptr[tgt[s]] + (idx - pre[s]);
+        int32_t cid = pcid[e];
+        if (cid < 0) continue;
+        uint32_t wv = bits[cid >> 5] & ((1u << (cid & 31)) - 1u);
+        int32_t ent = base + (int32_t)wpre[cid >> 5] + __popc(wv);
+        ecls[ent] = cid;
+        esrc[(int64_t)ent * kGroupM2L + s] = src[e];
     }
 }
 
@@ -319,53 +341,6 @@ __global__ void k_extra_ptr(const int32_t *__restrict__ ptr, int32_t ncell, cons
     for (int32_t A = blockIdx.x * blockDim.x + threadIdx.x; A <= ncell; A += gridDim.x * blockDim.x) xptr[A] = xscan[ptr[A]];
 }
 
-__global__ void k_to_f32(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (float)in[i];
-}
-
-// One wave per task (group, entry range).  RT row tiles of 32.
-template <int RT>
-__global__ void __launch_bounds__(256) k_m2l_mfma(const int4 *__restrict__ tasks, int32_t ntask,
-                                                  const int32_t *__restrict__ gtarget, const int32_t *__restrict__ ecls,
-                                                  const int32_t *__restrict__ esrc, const int32_t *__restrict__ slot_of_cid,
-                                                  const float *__restrict__ frags, const float *__restrict__ M32, int P,
-                                                  int KS, double *__restrict__ L) {
-    const int lane = threadIdx.x & 63;
-    const int32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= ntask) return;
-    int4 task = tasks[t];
-    f16v acc[RT];
-#pragma unroll
-    for (int r = 0; r < RT; r++)
-        for (int i = 0; i < 16; i++) acc[r][i] = 0.f;
-    const int col = lane & 31, khalf = lane >> 5;
-    for (int32_t e = task.y; e < task.z; e++) {
-        int32_t cid = ecls[e];
-        int32_t s = esrc[(int64_t)e * kGroup + col];
-        const float *Tf = frags + (int64_t)slot_of_cid[cid] * RT * KS * 64 + lane;
-        const float *Ms = M32 + (int64_t)(s < 0 ? 0 : s) * P;
-        for (int ks = 0; ks < KS; ks++) {
-            int kk = 2 * ks + khalf;
-            float b = (s >= 0 && kk < P) ? Ms[kk] : 0.f;
-#pragma unroll
-            for (int r = 0; r < RT; r++) {
-                float a = Tf[(r * KS + ks) * 64];
-                acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[r], 0, 0, 0);
-            }
-        }
-    }
-    int32_t A = gtarget[task.x * kGroup + col];
-    if (A < 0) return;
-    double *Lc = L + (int64_t)A * P;
-#pragma unroll
-    for (int r = 0; r < RT; r++)
-        for (int i = 0; i < 16; i++) {
-            int row = r * 32 + 8 * (i >> 2) + 4 * khalf + (i & 3);
-            if (row < P) atomicAdd(&Lc[row], (double)acc[r][i]);
-        }
-}
-
 }  // namespace
 
 void m2l_dense_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *src, int32_t *pkey,
@@ -381,10 +356,10 @@ void m2l_alloc_slots(const int32_t *used, int32_t *slot_of, int32_t *nslots, int
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int KS, float *frags,
-                   hipStream_t s) {
+void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int KS4, int64_t fragsz,
+                   float *frags, hipStream_t s) {
     if (nnew <= 0) return;
-    hipLaunchKernelGGL(k_build_ops, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, KS, frags);
+    hipLaunchKernelGGL(k_build_ops, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, KS4, fragsz, frags);
     FMM_LAUNCH_CHECK();
 }
 
@@ -416,7 +391,7 @@ size_t m2l_group_lds(int32_t ncid) {
 void m2l_group_entries(int mode, const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
                        const int32_t *pcid, int32_t ncid, int32_t *gcount, const int32_t *goff, int32_t *ecls,
                        int32_t *esrc, int32_t *gtarget, hipStream_t s) {
-    int32_t ngroup = (ntarget + kGroup - 1) / kGroup;
+    int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
     if (ngroup <= 0) return;
     if (m2l_group_lds(ncid) > 60 * 1024) throw std::runtime_error("too many M2L classes for the group builder");
     hipLaunchKernelGGL(k_group_entries, dim3(ngroup), dim3(256), m2l_group_lds(ncid), s, mode, tsorted, ntarget, ptr, src,
@@ -449,37 +424,5 @@ void m2l_extra(const int32_t *xflag, const int32_t *xscan, int64_t npair, const 
     FMM_LAUNCH_CHECK();
 }
 
-void to_f32(const double *in, float *out, int64_t n, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, in, out, n);
-    FMM_LAUNCH_CHECK();
-}
-
-void m2l_mfma(const int4 *tasks, int32_t ntask, const int32_t *gtarget, const int32_t *ecls, const int32_t *esrc,
-              const int32_t *slot_of_cid, const float *frags, const float *M32, int p, double *L, hipStream_t s) {
-    if (ntask <= 0) return;
-    const int P = ncoef(p), RT = (P + 31) / 32, KS = (P + 1) / 2;
-    dim3 grid((ntask + 3) / 4), block(256);
-#define FMM_M2L_CASE(R)                                                                                         \
-    case R:                                                                                                     \
-        hipLaunchKernelGGL(k_m2l_mfma<R>, grid, block, 0, s, tasks, ntask, gtarget, ecls, esrc, slot_of_cid, frags, \
-                           M32, P, KS, L);                                                                      \
-        break;
-    switch (RT) {
-        FMM_M2L_CASE(1)
-        FMM_M2L_CASE(2)
-        FMM_M2L_CASE(3)
-        FMM_M2L_CASE(4)
-        FMM_M2L_CASE(5)
-        FMM_M2L_CASE(6)
-        FMM_M2L_CASE(7)
-        FMM_M2L_CASE(8)
-        FMM_M2L_CASE(9)
-        FMM_M2L_CASE(10)
-        default: throw HipError{hipErrorInvalidValue, "m2l_mfma: unsupported order"};
-    }
-#undef FMM_M2L_CASE
-    FMM_LAUNCH_CHECK();
-}
 
 }  // namespace fmm

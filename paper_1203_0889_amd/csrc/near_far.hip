@@ -4,12 +4,13 @@
 
 #include "m2l_mfma.h"
 #include "near_far.h"
+#include "queue.h"
 
 namespace fmm {
 
 fmm_tuning default_tuning() {
     fmm_tuning t;
-    t.queue_chunk = 64;     // M2L entries per task
+    t.queue_chunk = 48;     // M2L entries per task
     t.p2p_split = 1 << 20;
     t.m2l_block = 32;
     t.grid_per_cu = 2;
@@ -24,11 +25,13 @@ void read_sync(void *h, const void *d, size_t b, hipStream_t s) {
 }  // namespace
 
 void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
-    const int p = a.p, P = ncoef(p), RT = (P + 31) / 32, KS = (P + 1) / 2;
-    const int64_t fragsz = (int64_t)RT * KS * 64;
+    const int p = a.p;
+    if (!queue_supported(p)) throw std::runtime_error("mixed precision supports p <= 12");
+    int RT, KS4;
+    queue_layout(p, &RT, &KS4);
+    const int64_t fragsz = queue_frag_floats(p);
     const int32_t ncell = a.ncell;
     const int64_t npair = a.nm2l;
-    if (P > 320) throw std::runtime_error("order too high for the MFMA M2L");
     // ---- persistent class tables
     if (st.p != p) {
         FMM_HIP_CHECK(st.slot_of.grow(kDenseKeys * 4));
@@ -62,7 +65,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     read_sync(ns, st.nslots.ptr, 8, s);
     if (ns[0] > st.nslot_total) {
         FMM_HIP_CHECK(st.frags.grow_keep((size_t)ns[0] * fragsz * 4, s));
-        m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, KS, st.frags.as<float>(), s);
+        m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, KS4, fragsz, st.frags.as<float>(), s);
         st.nslot_total = ns[0];
     }
     // compact class ids in dense-key order
@@ -89,13 +92,13 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     st.ncid = h3[0];
     st.nextra = h3[1];
     st.ntarget = h3[2];
-    st.ngroup = (st.ntarget + kGroup - 1) / kGroup;
+    st.ngroup = (st.ntarget + kGroupM2L - 1) / kGroupM2L;
     const int32_t ng = std::max(st.ngroup, 1);
     FMM_HIP_CHECK(st.gcount.grow((size_t)(ng + 1) * 4));
     FMM_HIP_CHECK(st.goff.grow((size_t)(ng + 1) * 4));
     FMM_HIP_CHECK(st.tcount.grow((size_t)(ng + 1) * 4));
     FMM_HIP_CHECK(st.toff.grow((size_t)(ng + 1) * 4));
-    FMM_HIP_CHECK(st.gtarget.grow((size_t)ng * kGroup * 4));
+    FMM_HIP_CHECK(st.gtarget.grow((size_t)ng * kGroupM2L * 4));
     FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, scan_tmp_elems(ng + 1) * 4)));
     m2l_group_entries(0, st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
                       st.gcount.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, s);
@@ -110,10 +113,10 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     st.nentries = st.ngroup > 0 ? h2[0] : 0;
     st.ntask = st.ngroup > 0 ? h2[1] : 0;
     FMM_HIP_CHECK(st.ecls.grow((size_t)std::max(st.nentries, 1) * 4));
-    FMM_HIP_CHECK(st.esrc.grow((size_t)std::max(st.nentries, 1) * kGroup * 4));
+    FMM_HIP_CHECK(st.esrc.grow((size_t)std::max(st.nentries, 1) * kGroupM2L * 4));
     FMM_HIP_CHECK(st.tasks.grow((size_t)std::max(st.ntask, 1) * sizeof(int4)));
     if (st.nentries > 0)
-        FMM_HIP_CHECK(hipMemsetAsync(st.esrc.ptr, 0xff, (size_t)st.nentries * kGroup * 4, s));
+        FMM_HIP_CHECK(hipMemsetAsync(st.esrc.ptr, 0xff, (size_t)st.nentries * kGroupM2L * 4, s));
     m2l_group_entries(1, st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
                       st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(), st.esrc.as<int32_t>(),
                       st.gtarget.as<int32_t>(), s);
@@ -124,10 +127,14 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.xptr.grow((size_t)(ncell + 1) * 4));
     m2l_extra(st.xflag.as<int32_t>(), st.xscan.as<int32_t>(), npair, a.m2l_src, a.m2l_ptr, ncell, st.xsrc.as<int32_t>(),
               st.xptr.as<int32_t>(), s);
-    // ---- P2P leaf list
-    FMM_HIP_CHECK(st.leafbuf.grow((size_t)(2 * ncell + 2) * 4));
+    // ---- P2P leaf list (costliest first) and cell centres
+    FMM_HIP_CHECK(st.leafbuf.grow((size_t)4 * (ncell + 1) * 4));
     FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
-    p2p_leaf_list(a.g.c, ncell, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(), st.tmp.as<int32_t>(), cnt + 5, s);
+    FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, radix_tmp_elems(ncell) * 4)));
+    p2p_leaf_list(a.g.c, ncell, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
+                  st.tmp.as<int32_t>(), cnt + 5, s);
+    FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
+    cell_centres(a.g, ncell, st.centre.as<double>(), s);
     int32_t nl;
     read_sync(&nl, cnt + 5, 4, s);
     st.nleaves = nl;
@@ -137,23 +144,51 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
 void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
     const int P = ncoef(a.p);
+    int RT, KS4;
+    queue_layout(a.p, &RT, &KS4);
     const int32_t ncell = a.ncell;
-    FMM_HIP_CHECK(st.M32.grow((size_t)std::max(ncell, 1) * P * 4));
+    FMM_HIP_CHECK(st.M32.grow((size_t)(ncell + 1) * 2 * KS4 * 4));
     FMM_HIP_CHECK(st.pf.grow((size_t)std::max<int64_t>(a.n, 1) * sizeof(float4)));
-    to_f32(a.M, st.M32.as<float>(), (int64_t)ncell * P, s);
+    FMM_HIP_CHECK(st.cnt.grow(16 * 4));
+    queue_pad_multipoles(a.M, ncell, a.p, st.M32.as<float>(), s);
     FMM_HIP_CHECK(hipMemsetAsync(a.L, 0, (size_t)ncell * P * 8, s));
-    m2l_mfma(st.tasks.as<int4>(), st.ntask, st.gtarget.as<int32_t>(), st.ecls.as<int32_t>(), st.esrc.as<int32_t>(),
-             st.slot_of_cid.as<int32_t>(), st.frags.as<float>(), st.M32.as<float>(), a.p, a.L, s);
-    if (st.nextra > 0) launch_m2l_fp64_add(a.g, ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, s);
     p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
-    p2p_fp32(a.g, st.leaves.as<int32_t>(), st.nleaves, a.p2p_ptr, a.p2p_src, st.pf.as<float4>(), a.phi, a.fld, s);
+    QueueArgs q;
+    q.c = a.g.c;
+    q.centre = st.centre.as<double>();
+    q.m2l_tasks = st.tasks.as<int4>();
+    q.gtarget = st.gtarget.as<int32_t>();
+    q.ecls = st.ecls.as<int32_t>();
+    q.esrc = st.esrc.as<int32_t>();
+    q.slot_of_cid = st.slot_of_cid.as<int32_t>();
+    q.frags = st.frags.as<float>();
+    q.M32 = st.M32.as<float>();
+    q.zero_row = ncell;
+    q.L = a.L;
+    q.P = P;
+    q.leaves = st.leaves.as<int32_t>();
+    q.nleaves = st.nleaves;
+    q.p2p_ptr = a.p2p_ptr;
+    q.p2p_src = a.p2p_src;
+    q.pf = st.pf.as<float4>();
+    q.phi = a.phi;
+    q.fld = a.fld;
+    q.nm2l_task = st.ntask;
+    q.ntask = st.ntask + (st.nleaves + 3) / 4;
+    q.head = st.cnt.as<int32_t>() + 8;
+    int dev = 0, ncu = 256;
+    FMM_HIP_CHECK(hipGetDevice(&dev));
+    FMM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
+    queue_run(q, a.p, ncu * per_cu, s);
+    if (st.nextra > 0) launch_m2l_fp64_add(a.g, ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, s);
 }
 
 void release_near_far(NearFarState &st) {
     DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.used_scan, &st.cid_of,
                      &st.slot_of_cid, &st.pkey, &st.pcid, &st.xflag, &st.xscan, &st.tkey, &st.tkey_alt, &st.has,
                      &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
-                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt};
+                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre};
     for (DevBuf *b : all) b->release();
     st.p = -1;
     st.built = false;

@@ -88,9 +88,10 @@ struct fmm_plan {
     DevBuf front[2], m2l_pairs, p2p_pairs, pair_alt, m2l_ptr, m2l_src, p2p_ptr, p2p_src;
     int64_t cap_front = 0, cap_m2l = 0, cap_p2p = 0;
     // expansions and fields
-    DevBuf M, L, ops_m2m, ops_l2l;
+    DevBuf M, L, ops_m2m, ops_l2l, m2m_part;
     int ops_p = -1;
-    DevBuf phi_near, fld_near, phi_far, fld_far;
+    DevBuf phi_near, fld_near, phi_far, fld_far, echunk, epart;
+    int32_t nechunk = 0;
     fmm::NearFarState nf;
     fmm_tuning tuning;
     hipEvent_t ev_beg[ST_COUNT] = {}, ev_end[ST_COUNT] = {};
@@ -186,6 +187,13 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         FMM_HIP_CHECK(p->rank.grow(nn * 4));
         FMM_HIP_CHECK(p->ralt.grow(nn * 4));
     }
+    {
+        std::vector<int32_t> co = fmm::energy_chunks(p->h_off);
+        p->nechunk = co.back();
+        FMM_HIP_CHECK(p->echunk.grow(co.size() * 4));
+        FMM_HIP_CHECK(p->epart.grow((size_t)std::max(p->nechunk, 1) * 8));
+        FMM_HIP_CHECK(hipMemcpyAsync(p->echunk.ptr, co.data(), co.size() * 4, hipMemcpyHostToDevice, s));
+    }
     const double *pbox = p->prm.box_min;
     double ubox[4] = {pbox[0], pbox[1], pbox[2], p->prm.box_side};
     bool user = (p->prm.flags & FMM_FLAG_USER_BOX) != 0;
@@ -240,80 +248,77 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     sync_read(p, &bad, p->flag.ptr, sizeof(int));
     if (bad) throw std::invalid_argument("non-finite particle coordinate");
 
-    // ---- dual tree traversal, breadth first
+    // ---- dual tree traversal, breadth first: every step is enqueued at once
+    // (sizes stay on the device); one read-back checks capacities and the
+    // whole traversal is rerun with larger buffers if any overflowed.
     const int64_t ncell = p->ncell;
+    const int bits = bits_for(ncell);
+    const bool key32 = 2 * bits <= 32;
+    const size_t ksz = key32 ? 4 : 8;
+    const int nlevels = (int)p->level_begin.size() - 1;
+    const int nsteps = 2 * nlevels + 1;
     if (p->cap_front < 1024) p->cap_front = std::max<int64_t>(4096, 8 * ncell);
     p->cap_front = std::max<int64_t>(p->cap_front, 2 * (int64_t)ni);
     if (p->cap_m2l < 1024) p->cap_m2l = std::max<int64_t>(4096, 64 * ncell);
     if (p->cap_p2p < 1024) p->cap_p2p = std::max<int64_t>(4096, 32 * ncell);
-    FMM_HIP_CHECK(p->front[0].grow(p->cap_front * sizeof(int2)));
-    FMM_HIP_CHECK(p->front[1].grow(p->cap_front * sizeof(int2)));
-    FMM_HIP_CHECK(p->m2l_pairs.grow(p->cap_m2l * 8));
-    FMM_HIP_CHECK(p->p2p_pairs.grow(p->cap_p2p * 8));
-    FMM_HIP_CHECK(p->counters.grow(8 * sizeof(int32_t)));
+    FMM_HIP_CHECK(p->counters.grow((size_t)(nsteps + 4) * sizeof(int32_t)));
     int32_t *ctr = p->counters.as<int32_t>();
-    fmm::launch_init_frontier(p->off.as<int64_t>(), ni, p->front[0].as<int2>(), ctr, s);
-    int32_t hc[3];
-    sync_read(p, hc, ctr, 3 * sizeof(int32_t));
-    int32_t nf = hc[0], have_m2l = 0, have_p2p = 0;
-    int cur = 0;
-    uint32_t ta = (uint32_t)p->prm.theta_num, tb = (uint32_t)p->prm.theta_den;
-    while (nf > 0) {
-        for (;;) {
-            int32_t reset[3] = {0, have_m2l, have_p2p};
-            FMM_HIP_CHECK(hipMemcpyAsync(ctr, reset, sizeof(reset), hipMemcpyHostToDevice, s));
-            fmm::PairBuf pb{p->m2l_pairs.as<uint64_t>(), p->p2p_pairs.as<uint64_t>(), (int32_t)p->cap_m2l,
-                            (int32_t)p->cap_p2p};
-            fmm::launch_traverse(cells_of(p), p->front[cur].as<int2>(), nf, p->front[cur ^ 1].as<int2>(),
-                                 (int32_t)p->cap_front, pb, ctr, ta, tb, s);
-            sync_read(p, hc, ctr, 3 * sizeof(int32_t));
-            bool redo = false;
-            if (hc[0] > p->cap_front) {
-                p->cap_front = (int64_t)hc[0] * 2;
-                // the current frontier must survive: keep front[cur]
-                FMM_HIP_CHECK(p->front[cur].grow_keep(p->cap_front * sizeof(int2), s));
-                FMM_HIP_CHECK(p->front[cur ^ 1].grow(p->cap_front * sizeof(int2)));
-                redo = true;
-            }
-            if (hc[1] > p->cap_m2l) {
-                p->cap_m2l = (int64_t)hc[1] * 2;
-                FMM_HIP_CHECK(p->m2l_pairs.grow_keep(p->cap_m2l * 8, s));
-                redo = true;
-            }
-            if (hc[2] > p->cap_p2p) {
-                p->cap_p2p = (int64_t)hc[2] * 2;
-                FMM_HIP_CHECK(p->p2p_pairs.grow_keep(p->cap_p2p * 8, s));
-                redo = true;
-            }
-            if (!redo) break;
+    std::vector<int32_t> hc(nsteps + 3);
+    const uint32_t ta = (uint32_t)p->prm.theta_num, tb = (uint32_t)p->prm.theta_den;
+    for (int attempt = 0;; attempt++) {
+        FMM_HIP_CHECK(p->front[0].grow(p->cap_front * sizeof(int2)));
+        FMM_HIP_CHECK(p->front[1].grow(p->cap_front * sizeof(int2)));
+        FMM_HIP_CHECK(p->m2l_pairs.grow(p->cap_m2l * ksz));
+        FMM_HIP_CHECK(p->p2p_pairs.grow(p->cap_p2p * ksz));
+        FMM_HIP_CHECK(hipMemsetAsync(ctr, 0, (size_t)(nsteps + 3) * sizeof(int32_t), s));
+        fmm::launch_init_frontier(p->off.as<int64_t>(), ni, p->front[0].as<int2>(), ctr, s);
+        fmm::PairBuf pb{p->m2l_pairs.ptr, p->p2p_pairs.ptr, (int32_t)p->cap_m2l, (int32_t)p->cap_p2p, key32};
+        for (int k = 0; k < nsteps; k++)
+            fmm::launch_traverse(cells_of(p), p->front[k & 1].as<int2>(), ctr + 2 + k, p->front[(k + 1) & 1].as<int2>(),
+                                 ctr + 3 + k, (int32_t)p->cap_front, pb, ctr, bits, ta, tb, s);
+        sync_read(p, hc.data(), ctr, (size_t)(nsteps + 3) * sizeof(int32_t));
+        int64_t fmax = *std::max_element(hc.begin() + 2, hc.end());
+        bool over = false;
+        if (fmax > p->cap_front) {
+            p->cap_front = fmax + fmax / 2;
+            over = true;
         }
-        have_m2l = hc[1];
-        have_p2p = hc[2];
-        nf = hc[0];
-        cur ^= 1;
+        if (hc[0] > p->cap_m2l) {
+            p->cap_m2l = (int64_t)hc[0] + hc[0] / 4;
+            over = true;
+        }
+        if (hc[1] > p->cap_p2p) {
+            p->cap_p2p = (int64_t)hc[1] + hc[1] / 4;
+            over = true;
+        }
+        if (!over) break;
+        if (attempt > 4) throw std::runtime_error("traversal capacity did not converge");
     }
-    p->nm2l = have_m2l;
-    p->np2p = have_p2p;
+    if (hc[nsteps + 2] != 0) throw std::runtime_error("traversal did not terminate in the expected number of steps");
+    p->nm2l = hc[0];
+    p->np2p = hc[1];
     mark(p, ST_LISTS);
 
     // ---- canonical CSR lists sorted by (target, source)
-    int bits = bits_for(ncell);
     int64_t mx = std::max<int64_t>(std::max(p->nm2l, p->np2p), 1);
-    FMM_HIP_CHECK(p->pair_alt.grow(mx * 8));
+    FMM_HIP_CHECK(p->pair_alt.grow(mx * ksz));
     FMM_HIP_CHECK(p->tmp.grow(std::max(p->tmp.bytes, fmm::radix_tmp_elems(mx) * sizeof(int32_t))));
     FMM_HIP_CHECK(p->m2l_ptr.grow((ncell + 1) * 4));
     FMM_HIP_CHECK(p->p2p_ptr.grow((ncell + 1) * 4));
     FMM_HIP_CHECK(p->m2l_src.grow(std::max<int64_t>(p->nm2l, 1) * 4));
     FMM_HIP_CHECK(p->p2p_src.grow(std::max<int64_t>(p->np2p, 1) * 4));
-    uint64_t *lists[2] = {p->m2l_pairs.as<uint64_t>(), p->p2p_pairs.as<uint64_t>()};
+    void *lists[2] = {p->m2l_pairs.ptr, p->p2p_pairs.ptr};
     int64_t cnts[2] = {p->nm2l, p->np2p};
     int32_t *ptrs[2] = {p->m2l_ptr.as<int32_t>(), p->p2p_ptr.as<int32_t>()};
     int32_t *srcs[2] = {p->m2l_src.as<int32_t>(), p->p2p_src.as<int32_t>()};
     for (int t = 0; t < 2; t++) {
-        fmm::launch_repack(lists[t], cnts[t], bits, s);
-        fmm::radix_sort_u64(lists[t], nullptr, p->pair_alt.as<uint64_t>(), nullptr, cnts[t], 0, 2 * bits,
-                            p->tmp.as<int32_t>(), s);
-        fmm::launch_csr(lists[t], cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], s);
+        if (key32)
+            fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, p->pair_alt.as<uint32_t>(), nullptr, cnts[t], 0, 2 * bits,
+                                p->tmp.as<int32_t>(), s);
+        else
+            fmm::radix_sort_u64((uint64_t *)lists[t], nullptr, p->pair_alt.as<uint64_t>(), nullptr, cnts[t], 0, 2 * bits,
+                                p->tmp.as<int32_t>(), s);
+        fmm::launch_csr(lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], s);
     }
     mark(p, ST_CSR);
     // leaves
@@ -377,9 +382,12 @@ void do_upward(fmm_plan *p) {
                     p->qs.as<double>(), p->M.as<double>(), s);
     mark(p, ST_P2M);
     int depth = (int)p->level_begin.size() - 1;  // number of levels present
+    int32_t widest = 1;
+    for (int l = 0; l + 1 < depth; l++) widest = std::max(widest, p->level_begin[l + 1] - p->level_begin[l]);
+    FMM_HIP_CHECK(p->m2m_part.grow((size_t)8 * widest * P * 8));
     for (int l = depth - 2; l >= 0; l--)
         fmm::launch_m2m_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_m2m.as<double>(),
-                              p->M.as<double>(), s);
+                              p->M.as<double>(), p->m2m_part.as<double>(), s);
     mark(p, ST_M2M);
 }
 
@@ -410,7 +418,7 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         mark(p, ST_P2P);
     }
     int depth = (int)p->level_begin.size() - 1;
-    for (int l = 1; l < depth; l++)
+    for (int l = 0; l + 1 < depth; l++)  // parents of level l push to level l + 1
         fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_l2l.as<double>(),
                               p->L.as<double>(), s);
     mark(p, ST_L2L);
@@ -421,8 +429,8 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
                          p->fld_near.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), phi, field, force,
                          s);
     if (energy)
-        fmm::launch_energy(p->off.as<int64_t>(), p->n_inst, p->qs.as<double>(), p->phi_near.as<double>(),
-                           p->phi_far.as<double>(), energy, s);
+        fmm::launch_energy(p->off.as<int64_t>(), p->n_inst, p->echunk.as<int32_t>(), p->nechunk, p->qs.as<double>(),
+                           p->phi_near.as<double>(), p->phi_far.as<double>(), p->epart.as<double>(), energy, s);
     mark(p, ST_OUT);
 }
 
@@ -515,7 +523,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
                      &p->ikey, &p->ialt, &p->rank, &p->ralt, &p->tmp, &p->xs, &p->ys, &p->zs, &p->qs,
                      &p->leaf_of, &p->bounds, &p->nch, &p->counters, &p->front[0], &p->front[1], &p->m2l_pairs,
                      &p->p2p_pairs, &p->pair_alt, &p->m2l_ptr, &p->m2l_src, &p->p2p_ptr, &p->p2p_src, &p->M,
-                     &p->L, &p->ops_m2m, &p->ops_l2l, &p->phi_near, &p->fld_near, &p->phi_far, &p->fld_far};
+                     &p->L, &p->ops_m2m, &p->ops_l2l, &p->m2m_part, &p->phi_near, &p->fld_near, &p->phi_far, &p->fld_far, &p->echunk, &p->epart};
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
     fmm::release_near_far(p->nf);

@@ -35,21 +35,21 @@ void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, hipStream_t s
 
 // ---- lists.hip
 struct PairBuf {
-    uint64_t *m2l;  // packed (target << 32) | source, unsorted
-    uint64_t *p2p;
+    void *m2l;      // keys (target << bits) | source, uint32 if key32 else uint64, unsorted
+    void *p2p;
     int32_t cap_m2l, cap_p2p;
+    bool key32;
 };
-// One breadth-first step of the dual tree traversal: consumes nf frontier
-// pairs, appends accepted M2L / P2P pairs and the split pairs of the next
-// frontier.  counters[0] = next frontier size, [1] = #M2L, [2] = #P2P (all
-// counted even past capacity, so the host can detect overflow).
-void launch_traverse(CellArrays c, const int2 *fin, int32_t nf, int2 *fout, int32_t capf, PairBuf pb,
-                     int32_t *counters, uint32_t theta_num, uint32_t theta_den, hipStream_t s);
+// One breadth-first step of the dual tree traversal: consumes the frontier
+// whose size is *nf_in, appends accepted M2L / P2P pairs (counters[0],
+// counters[1]) and the split pairs of the next frontier (*nf_out).  Counts
+// keep growing past capacity so the host can detect overflow and rerun.
+void launch_traverse(CellArrays c, const int2 *fin, const int32_t *nf_in, int2 *fout, int32_t *nf_out, int32_t capf,
+                     PairBuf pb, int32_t *counters, int bits, uint32_t theta_num, uint32_t theta_den, hipStream_t s);
+// counters[2] = number of roots put in the first frontier.
 void launch_init_frontier(const int64_t *d_offsets, int n_inst, int2 *front, int32_t *counters, hipStream_t s);
-// Repack (target << 32 | source) into (target << bits | source) for sorting.
-void launch_repack(uint64_t *pairs, int64_t n, int bits, hipStream_t s);
-// CSR from pairs sorted by (target, source) packed with `bits`.
-void launch_csr(const uint64_t *sorted, int64_t n, int bits, int32_t ncell, int32_t *ptr, int32_t *src,
+// CSR from pair keys sorted by (target, source).
+void launch_csr(const void *sorted, bool key32, int64_t n, int bits, int32_t ncell, int32_t *ptr, int32_t *src,
                 hipStream_t s);
 
 // ---- expansions.hip  (FP64, scaled solid harmonics)
@@ -59,12 +59,14 @@ struct Geometry {
 };
 void launch_p2m(Geometry g, int32_t ncell, int p, const double *xs, const double *ys, const double *zs,
                 const double *qs, double *M, hipStream_t s);
-void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, hipStream_t s);
+// part: scratch of 8 * (le - lb) * (p+1)^2 doubles.
+void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, double *part,
+                      hipStream_t s);
 void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *L, hipStream_t s);
 void launch_l2p(Geometry g, int64_t n, int p, const int32_t *leaf_of, const double *xs, const double *ys,
                 const double *zs, const double *L, double *phi, double *fld, hipStream_t s);
 // Host: M2M (dir 0) or L2L (dir 1) operator matrices for the 8 octants,
-// row-major P x P each (P = (p+1)^2), acting on the real coefficient layout.
+// column-major P x P each (P = (p+1)^2), acting on the real coefficient layout.
 std::vector<double> build_translation_ops(int p, int dir);
 
 // ---- near / far field, FP64 plain path
@@ -80,7 +82,9 @@ void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, c
 void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,
                      const double *fld_near, const double *phi_far, const double *fld_far, double *phi, double *field,
                      double *force, hipStream_t s);
-void launch_energy(const int64_t *d_offsets, int n_inst, const double *qs, const double *phi_near,
-                   const double *phi_far, double *energy, hipStream_t s);
+// Energy chunk table: chunk_off[k] = first chunk of instance k (size n_inst + 1).
+std::vector<int32_t> energy_chunks(const std::vector<int64_t> &offsets);
+void launch_energy(const int64_t *d_offsets, int n_inst, const int32_t *d_chunk_off, int32_t nchunk, const double *qs,
+                   const double *phi_near, const double *phi_far, double *part, double *energy, hipStream_t s);
 
 }  // namespace fmm
