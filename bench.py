@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-n", type=int, default=131072, help="particles in the CPU oracle sample")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -78,6 +80,15 @@ def main():
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     field = torch.empty((n, 3), dtype=torch.float64, device=dev)
     energy = torch.empty(1, dtype=torch.float64, device=dev)
+
+    if a.copy_calib_mib > 0:
+        nel = a.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         plan.build_tree(dpos, dq)

@@ -41,6 +41,9 @@ struct HipError {
 // *d_total (device) when non-null.  tmp must hold scan_tmp_elems(n) ints.
 size_t scan_tmp_elems(int64_t n);
 void exclusive_scan_i32(int32_t *d_data, int64_t n, int32_t *d_total, int32_t *d_tmp, hipStream_t s);
+// Out-of-place variant (d_in may equal d_out).  d_total may point at d_out[n].
+void exclusive_scan_oop(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t *d_total, int32_t *d_tmp,
+                        hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over bits [bit_lo, bit_hi).
 // kin/vin and kalt/valt are ping-pong buffers of n elements; the sorted

@@ -20,10 +20,14 @@ void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int
                   hipStream_t s);
 void m2l_target_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *xscan, uint64_t *tkey,
                      int32_t *has, hipStream_t s);
-size_t m2l_group_lds(int32_t ncid);
-void m2l_group_entries(int mode, const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
-                       const int32_t *pcid, int32_t ncid, int32_t *gcount, const int32_t *goff, int32_t *ecls,
-                       int32_t *esrc, int32_t *gtarget, hipStream_t s);
+// Entries of the 128-target groups: count (class bitmap per group in
+// gbits, ngroup x ceil(ncid/32) words, and word prefixes in gwpre), then
+// fill (after goff = exclusive scan of gcount).
+void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcid, int32_t ncid,
+                     uint32_t *gbits, uint32_t *gwpre, int32_t *gcount, hipStream_t s);
+void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
+                    const int32_t *pcid, int32_t ncid, const uint32_t *gbits, const uint32_t *gwpre,
+                    const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget, hipStream_t s);
 void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *tcount, hipStream_t s);
 void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, int chunk, const int32_t *toff,
                     int4 *tasks, hipStream_t s);

@@ -217,25 +217,13 @@ __global__ void k_target_keys(CellArrays c, int32_t ncell, const int32_t *__rest
     }
 }
 
-// Per group (workgroup): mark the classes of its targets in an LDS bitmap;
-// mode 0 counts them, mode 1 writes the entries.  The (target, pair)
-// iteration is flattened over the group so all threads stay busy.
-__device__ inline void group_pairs(const uint64_t *__restrict__ tsorted, int t0, int nt, const int32_t *__restrict__ ptr,
-                                   int32_t *pre, int32_t *tgt) {
-    // pre[s] = first flattened index of slot s, tgt[s] = target cell
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int s = 0; s < nt; s++) {
-            int32_t A = (int32_t)(tsorted[t0 + s] & 0xffffffffull);
-            tgt[s] = A;
-            pre[s] = run;
-            run += ptr[A + 1] - ptr[A];
-        }
-        pre[nt] = run;
-    }
-    __syncthreads();
-}
+// Group entries in three steps, each spread over kSplit workgroups per
+// group:  (1) mark the classes of the group's pairs in a global bitmap,
+// (2) per group, exclusive popcount prefix over its bitmap words (entry
+// rank of every class), (3) write every pair's source into its entry slot.
+constexpr int kSplit = 8;
 
+// slot (target) of flattened pair index idx: pre[s] <= idx < pre[s+1]
 __device__ inline int slot_of_index(const int32_t *pre, int nt, int32_t idx) {
     int lo = 0, hi = nt - 1;
     while (lo < hi) {
@@ -245,73 +233,108 @@ __device__ inline int slot_of_index(const int32_t *pre, int nt, int32_t idx) {
     return lo;
 }
 
-__global__ void __launch_bounds__(256) k_group_entries(int mode, const uint64_t *__restrict__ tsorted, int32_t ntarget,
-                                                       const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
-                                                       const int32_t *__restrict__ pcid, int32_t ncid,
-                                                       int32_t *__restrict__ gcount, const int32_t *__restrict__ goff,
-                                                       int32_t *__restrict__ ecls, int32_t *__restrict__ esrc,
-                                                       int32_t *__restrict__ gtarget) {
-    extern __shared__ uint32_t bits[];
-    __shared__ int32_t wbase[256 + 1];
+__device__ inline void load_group(const uint64_t *__restrict__ tsorted, int32_t ntarget, int g,
+                                  const int32_t *__restrict__ ptr, int32_t *pre, int32_t *tgt, int *nt_out) {
+    const int t0 = g * kGroupM2L;
+    const int nt = ntarget - t0 < kGroupM2L ? ntarget - t0 : kGroupM2L;
+    if (threadIdx.x < nt) {
+        int32_t A = (int32_t)(tsorted[t0 + threadIdx.x] & 0xffffffffull);
+        tgt[threadIdx.x] = A;
+        pre[threadIdx.x + 1] = ptr[A + 1] - ptr[A];
+    }
+    if (threadIdx.x == 0) pre[0] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 1; i <= nt; i++) pre[i] += pre[i - 1];
+    __syncthreads();
+    *nt_out = nt;
+}
+
+__global__ void __launch_bounds__(256) k_group_mark(const uint64_t *__restrict__ tsorted, int32_t ntarget,
+                                                    const int32_t *__restrict__ ptr, const int32_t *__restrict__ pcid,
+                                                    int nwords, uint32_t *__restrict__ gbits) {
+    extern __shared__ uint32_t lbits[];
     __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L];
     const int g = blockIdx.x;
-    const int nwords = (ncid + 31) / 32;
-    for (int w = threadIdx.x; w < nwords; w += blockDim.x) bits[w] = 0u;
-    int t0 = g * kGroupM2L;
-    int nt = ntarget - t0 < kGroupM2L ? ntarget - t0 : kGroupM2L;
-    group_pairs(tsorted, t0, nt, ptr, pre, tgt);
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) lbits[w] = 0u;
+    int nt;
+    load_group(tsorted, ntarget, g, ptr, pre, tgt, &nt);
     const int32_t total = pre[nt];
-    for (int32_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    for (int32_t idx = blockIdx.y * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
         int s = slot_of_index(pre, nt, idx);
         int32_t cid = pcid[ptr[tgt[s]] + (idx - pre[s])];
-        if (cid >= 0) atomicOr(&bits[cid >> 5], 1u << (cid & 31));
+        if (cid >= 0) atomicOr(&lbits[cid >> 5], 1u << (cid & 31));
     }
     __syncthreads();
-    if (mode == 0) {
-        int cnt = 0;
-        for (int w = threadIdx.x; w < nwords; w += blockDim.x) cnt += __popc(bits[w]);
-        for (int d = 32; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d, 64);  // wave sum
-        __shared__ int wsum[4];
-        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = cnt;
-        __syncthreads();
-        if (threadIdx.x == 0) gcount[g] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        return;
-    }
-    // mode 1: exclusive popcount prefix over words; thread t owns a contiguous word range
-    const int32_t base = goff[g];
-    if (threadIdx.x < kGroupM2L) gtarget[g * kGroupM2L + threadIdx.x] = threadIdx.x < nt ? tgt[threadIdx.x] : -1;
-    int per = (nwords + blockDim.x - 1) / blockDim.x;
+    uint32_t *bits = gbits + (int64_t)g * nwords;
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x)
+        if (lbits[w]) atomicOr(&bits[w], lbits[w]);
+}
+
+// One workgroup per group: gwpre[g][w] = entries before word w; gcount[g].
+__global__ void __launch_bounds__(256) k_group_prefix(int nwords, const uint32_t *__restrict__ gbits,
+                                                      uint32_t *__restrict__ gwpre, int32_t *__restrict__ gcount) {
+    __shared__ int32_t part[257];
+    const int g = blockIdx.x;
+    const uint32_t *bits = gbits + (int64_t)g * nwords;
+    uint32_t *wpre = gwpre + (int64_t)g * nwords;
+    const int per = (nwords + 255) / 256;
     int mine = 0;
     for (int w = threadIdx.x * per; w < (int)(threadIdx.x + 1) * per && w < nwords; w++) mine += __popc(bits[w]);
-    wbase[threadIdx.x] = mine;
+    part[threadIdx.x] = mine;
     __syncthreads();
     if (threadIdx.x == 0) {
         int run = 0;
-        for (int i = 0; i < (int)blockDim.x; i++) {
-            int v = wbase[i];
-            wbase[i] = run;
+        for (int i = 0; i < 256; i++) {
+            int v = part[i];
+            part[i] = run;
             run += v;
         }
-        wbase[blockDim.x] = run;
+        part[256] = run;
+        gcount[g] = run;
     }
     __syncthreads();
-    uint32_t *wpre = bits + nwords;
-    {
-        int run = wbase[threadIdx.x];
-        for (int w = threadIdx.x * per; w < (int)(threadIdx.x + 1) * per && w < nwords; w++) {
-            wpre[w] = run;
-            run += __popc(bits[w]);
+    int run = part[threadIdx.x];
+    for (int w = threadIdx.x * per; w < (int)(threadIdx.x + 1) * per && w < nwords; w++) {
+        wpre[w] = run;
+        run += __popc(bits[w]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__ tsorted, int32_t ntarget,
+                                                    const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                                                    const int32_t *__restrict__ pcid, int nwords,
+                                                    const uint32_t *__restrict__ gbits,
+                                                    const uint32_t *__restrict__ gwpre,
+                                                    const int32_t *__restrict__ goff, int32_t *__restrict__ ecls,
+                                                    int32_t *__restrict__ esrc, int32_t *__restrict__ gtarget) {
+    __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L];
+    const int g = blockIdx.x;
+    int nt;
+    load_group(tsorted, ntarget, g, ptr, pre, tgt, &nt);
+    if (blockIdx.y == 0 && threadIdx.x < kGroupM2L)
+        gtarget[(int64_t)g * kGroupM2L + threadIdx.x] = threadIdx.x < nt ? tgt[threadIdx.x] : -1;
+    const int32_t total = pre[nt];
+    const uint32_t *bits = gbits + (int64_t)g * nwords;
+    const uint32_t *wpre = gwpre + (int64_t)g * nwords;
+    const int32_t base = goff[g];
+    if (blockIdx.y == 0)
+        for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
+            uint32_t b = bits[w];
+            int32_t ent = base + (int32_t)wpre[w];
+            while (b) {
+                int bit = __ffs(b) - 1;
+                ecls[ent++] = w * 32 + bit;
+                b &= b - 1;
+            }
         }
-    }
-    __syncthreads();
-    for (int32_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    for (int32_t idx = blockIdx.y * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
         int s = slot_of_index(pre, nt, idx);
         int32_t e = ptr[tgt[s]] + (idx - pre[s]);
         int32_t cid = pcid[e];
         if (cid < 0) continue;
         uint32_t wv = bits[cid >> 5] & ((1u << (cid & 31)) - 1u);
         int32_t ent = base + (int32_t)wpre[cid >> 5] + __popc(wv);
-        ecls[ent] = cid;
         esrc[(int64_t)ent * kGroupM2L + s] = src[e];
     }
 }
@@ -383,19 +406,28 @@ void m2l_target_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int3
     FMM_LAUNCH_CHECK();
 }
 
-size_t m2l_group_lds(int32_t ncid) {
-    int nwords = (ncid + 31) / 32;
-    return (size_t)(2 * nwords + 1) * sizeof(uint32_t);
+void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcid, int32_t ncid,
+                     uint32_t *gbits, uint32_t *gwpre, int32_t *gcount, hipStream_t s) {
+    const int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
+    if (ngroup <= 0) return;
+    const int nwords = (ncid + 31) / 32;
+    FMM_HIP_CHECK(hipMemsetAsync(gbits, 0, (size_t)ngroup * nwords * 4, s));
+    if ((size_t)nwords * 4 > 48 * 1024) throw std::runtime_error("too many M2L classes for the group builder");
+    hipLaunchKernelGGL(k_group_mark, dim3(ngroup, kSplit), dim3(256), (size_t)nwords * 4, s, tsorted, ntarget, ptr, pcid,
+                       nwords, gbits);
+    FMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_group_prefix, dim3(ngroup), dim3(256), 0, s, nwords, gbits, gwpre, gcount);
+    FMM_LAUNCH_CHECK();
 }
 
-void m2l_group_entries(int mode, const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
-                       const int32_t *pcid, int32_t ncid, int32_t *gcount, const int32_t *goff, int32_t *ecls,
-                       int32_t *esrc, int32_t *gtarget, hipStream_t s) {
-    int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
+void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
+                    const int32_t *pcid, int32_t ncid, const uint32_t *gbits, const uint32_t *gwpre,
+                    const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget, hipStream_t s) {
+    const int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
     if (ngroup <= 0) return;
-    if (m2l_group_lds(ncid) > 60 * 1024) throw std::runtime_error("too many M2L classes for the group builder");
-    hipLaunchKernelGGL(k_group_entries, dim3(ngroup), dim3(256), m2l_group_lds(ncid), s, mode, tsorted, ntarget, ptr, src,
-                       pcid, ncid, gcount, goff, ecls, esrc, gtarget);
+    const int nwords = (ncid + 31) / 32;
+    hipLaunchKernelGGL(k_group_fill, dim3(ngroup, kSplit), dim3(256), 0, s, tsorted, ntarget, ptr, src, pcid, nwords, gbits,
+                       gwpre, goff, ecls, esrc, gtarget);
     FMM_LAUNCH_CHECK();
 }
 

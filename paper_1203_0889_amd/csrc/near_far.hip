@@ -69,16 +69,15 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
         st.nslot_total = ns[0];
     }
     // compact class ids in dense-key order
-    FMM_HIP_CHECK(hipMemcpyAsync(st.used_scan.ptr, st.used.ptr, kDenseKeys * 4, hipMemcpyDeviceToDevice, s));
-    exclusive_scan_i32(st.used_scan.as<int32_t>(), kDenseKeys, cnt + 0, st.tmp.as<int32_t>(), s);
+    exclusive_scan_oop(st.used.as<int32_t>(), st.used_scan.as<int32_t>(), kDenseKeys, cnt + 0, st.tmp.as<int32_t>(), s);
     m2l_cid_tables(st.used_scan.as<int32_t>(), st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.cid_of.as<int32_t>(),
                    st.slot_of_cid.as<int32_t>(), s);
     m2l_pair_cid(st.pkey.as<int32_t>(), npair, st.cid_of.as<int32_t>(), st.pcid.as<int32_t>(), st.xflag.as<int32_t>(), s);
     // exclusive scan over npair + 1 elements (the last one zero): xscan[npair]
     // = number of pairs left to the per-pair kernel
-    FMM_HIP_CHECK(hipMemcpyAsync(st.xscan.ptr, st.xflag.ptr, npair * 4, hipMemcpyDeviceToDevice, s));
-    FMM_HIP_CHECK(hipMemsetAsync(st.xscan.as<int32_t>() + npair, 0, 4, s));
-    exclusive_scan_i32(st.xscan.as<int32_t>(), npair + 1, cnt + 1, st.tmp.as<int32_t>(), s);
+    exclusive_scan_oop(st.xflag.as<int32_t>(), st.xscan.as<int32_t>(), npair, st.xscan.as<int32_t>() + npair,
+                       st.tmp.as<int32_t>(), s);
+    FMM_HIP_CHECK(hipMemcpyAsync(cnt + 1, st.xscan.as<int32_t>() + npair, 4, hipMemcpyDeviceToDevice, s));
     // ---- targets sorted by (level, octant, cell)
     FMM_HIP_CHECK(st.tkey.grow((size_t)(ncell + 1) * 8));
     FMM_HIP_CHECK(st.tkey_alt.grow((size_t)(ncell + 1) * 8));
@@ -100,14 +99,15 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.toff.grow((size_t)(ng + 1) * 4));
     FMM_HIP_CHECK(st.gtarget.grow((size_t)ng * kGroupM2L * 4));
     FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, scan_tmp_elems(ng + 1) * 4)));
-    m2l_group_entries(0, st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
-                      st.gcount.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, s);
-    FMM_HIP_CHECK(hipMemcpyAsync(st.goff.ptr, st.gcount.ptr, (size_t)st.ngroup * 4, hipMemcpyDeviceToDevice, s));
-    exclusive_scan_i32(st.goff.as<int32_t>(), st.ngroup, cnt + 3, st.tmp.as<int32_t>(), s);
+    const size_t gwords = (size_t)ng * ((st.ncid + 31) / 32 + 1);
+    FMM_HIP_CHECK(st.gbits.grow(gwords * 4));
+    FMM_HIP_CHECK(st.gwpre.grow(gwords * 4));
+    m2l_group_count(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, st.pcid.as<int32_t>(), st.ncid,
+                    st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.gcount.as<int32_t>(), s);
+    exclusive_scan_oop(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, cnt + 3, st.tmp.as<int32_t>(), s);
     const int chunk = std::max(1, a.tuning.queue_chunk);
     m2l_task_counts(st.gcount.as<int32_t>(), st.ngroup, chunk, st.tcount.as<int32_t>(), s);
-    FMM_HIP_CHECK(hipMemcpyAsync(st.toff.ptr, st.tcount.ptr, (size_t)st.ngroup * 4, hipMemcpyDeviceToDevice, s));
-    exclusive_scan_i32(st.toff.as<int32_t>(), st.ngroup, cnt + 4, st.tmp.as<int32_t>(), s);
+    exclusive_scan_oop(st.tcount.as<int32_t>(), st.toff.as<int32_t>(), st.ngroup, cnt + 4, st.tmp.as<int32_t>(), s);
     int32_t h2[2];
     read_sync(h2, cnt + 3, 8, s);
     st.nentries = st.ngroup > 0 ? h2[0] : 0;
@@ -117,9 +117,9 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.tasks.grow((size_t)std::max(st.ntask, 1) * sizeof(int4)));
     if (st.nentries > 0)
         FMM_HIP_CHECK(hipMemsetAsync(st.esrc.ptr, 0xff, (size_t)st.nentries * kGroupM2L * 4, s));
-    m2l_group_entries(1, st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
-                      st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(), st.esrc.as<int32_t>(),
-                      st.gtarget.as<int32_t>(), s);
+    m2l_group_fill(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
+                   st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(),
+                   st.esrc.as<int32_t>(), st.gtarget.as<int32_t>(), s);
     m2l_make_tasks(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, chunk, st.toff.as<int32_t>(),
                    st.tasks.as<int4>(), s);
     // ---- pairs left to the per-pair kernel (|delta| >= 2 or far displacement)
@@ -188,7 +188,7 @@ void release_near_far(NearFarState &st) {
     DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.used_scan, &st.cid_of,
                      &st.slot_of_cid, &st.pkey, &st.pcid, &st.xflag, &st.xscan, &st.tkey, &st.tkey_alt, &st.has,
                      &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
-                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre};
+                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre};
     for (DevBuf *b : all) b->release();
     st.p = -1;
     st.built = false;

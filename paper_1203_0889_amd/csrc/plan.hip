@@ -229,8 +229,7 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         int32_t *off = nch + (ncur + 1);
         fmm::launch_tree_count(cells_of(p), lb, le, p->prm.ncrit, p->prm.max_level, p->keys.as<uint64_t>(),
                                p->bounds.as<int32_t>(), nch, s);
-        FMM_HIP_CHECK(hipMemcpyAsync(off, nch, ncur * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        fmm::exclusive_scan_i32(off, ncur, off + ncur, p->tmp.as<int32_t>(), s);
+        fmm::exclusive_scan_oop(nch, off, ncur, off + ncur, p->tmp.as<int32_t>(), s);
         int32_t total = 0;
         sync_read(p, &total, off + ncur, sizeof(int32_t));
         if (total == 0) break;
@@ -241,12 +240,13 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         p->level_begin.push_back(le);
     }
     p->ncell = le;
-    fmm::launch_leaf_of(cells_of(p), (int32_t)p->ncell, p->leaf_of.as<int32_t>(), s);
+    fmm::launch_leaf_of(cells_of(p), (int32_t)p->ncell, p->leaf_of.as<int32_t>(), p->flag.as<int32_t>() + 1, s);
     mark(p, ST_TREE);
 
-    int bad = 0;
-    sync_read(p, &bad, p->flag.ptr, sizeof(int));
-    if (bad) throw std::invalid_argument("non-finite particle coordinate");
+    int hf[2] = {0, 0};  // [0] = non-finite input seen, [1] = number of leaves
+    sync_read(p, hf, p->flag.ptr, 2 * sizeof(int));
+    if (hf[0]) throw std::invalid_argument("non-finite particle coordinate");
+    p->nleaf = hf[1];
 
     // ---- dual tree traversal, breadth first: every step is enqueued at once
     // (sizes stay on the device); one read-back checks capacities and the
@@ -321,12 +321,7 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         fmm::launch_csr(lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], s);
     }
     mark(p, ST_CSR);
-    // leaves
-    {
-        std::vector<int32_t> ch(ncell);
-        sync_read(p, ch.data(), p->cb[6].ptr, ncell * sizeof(int32_t));
-        p->nleaf = std::count(ch.begin(), ch.end(), -1);
-    }
+
     if (p->prm.precision == FMM_PREC_MIXED) {
         fmm::build_near_far_mixed(p->nf, nf_args(p), s);
         mark(p, ST_CSR);

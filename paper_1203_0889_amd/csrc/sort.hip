@@ -45,6 +45,39 @@ __device__ inline int block_exclusive_scan(int v, int *total) {
     return base + inc - v;
 }
 
+// Small inputs (n <= kSmallScan): one workgroup of 1024 threads, 8 items each.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallScan = kSmallThreads * kScanItems;
+
+__global__ void __launch_bounds__(kSmallThreads) k_scan_small(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                              int64_t n, int32_t *__restrict__ total) {
+    __shared__ int wsum[kSmallThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t base = (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        v[i] = base + i < n ? in[base + i] : 0;
+        s += v[i];
+    }
+    int inc = wave_inclusive_scan(s);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int i = 0; i < kSmallThreads / 64; i++) {
+        if (i < w) pre += wsum[i];
+        tot += wsum[i];
+    }
+    pre += inc - s;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        if (base + i < n) out[base + i] = pre;
+        pre += v[i];
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
 __global__ void k_scan_reduce(const int32_t *__restrict__ data, int64_t n, int32_t *__restrict__ sums) {
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int s = 0;
@@ -81,20 +114,21 @@ __global__ void k_scan_top(int32_t *__restrict__ sums, int64_t nb, int32_t *__re
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ void k_scan_down(int32_t *__restrict__ data, int64_t n, const int32_t *__restrict__ sums) {
+__global__ void k_scan_down(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
+                            const int32_t *__restrict__ sums) {
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
     int s = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; i++) {
-        v[i] = base + i < n ? data[base + i] : 0;
+        v[i] = base + i < n ? in[base + i] : 0;
         s += v[i];
     }
     int tot;
     int pre = block_exclusive_scan(s, &tot) + sums[blockIdx.x];
 #pragma unroll
     for (int i = 0; i < kScanItems; i++) {
-        if (base + i < n) data[base + i] = pre;
+        if (base + i < n) out[base + i] = pre;
         pre += v[i];
     }
 }
@@ -223,16 +257,26 @@ size_t scan_tmp_elems(int64_t n) {
 }
 
 void exclusive_scan_i32(int32_t *d_data, int64_t n, int32_t *d_total, int32_t *d_tmp, hipStream_t s) {
+    exclusive_scan_oop(d_data, d_data, n, d_total, d_tmp, s);
+}
+
+void exclusive_scan_oop(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t *d_total, int32_t *d_tmp,
+                        hipStream_t s) {
     if (n <= 0) {
         if (d_total) FMM_HIP_CHECK(hipMemsetAsync(d_total, 0, sizeof(int32_t), s));
         return;
     }
+    if (n <= kSmallScan) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallThreads), 0, s, d_in, d_out, n, d_total);
+        FMM_LAUNCH_CHECK();
+        return;
+    }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_data, n, d_tmp);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_in, n, d_tmp);
     FMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, d_tmp, nb, d_total);
     FMM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_data, n, d_tmp);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_in, d_out, n, d_tmp);
     FMM_LAUNCH_CHECK();
 }
 

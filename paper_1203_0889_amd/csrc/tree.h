@@ -31,7 +31,8 @@ void launch_tree_count(CellArrays c, int32_t lb, int32_t le, int ncrit, int max_
                        int32_t *bounds, int32_t *nch, hipStream_t s);
 void launch_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t *bounds, const int32_t *nch,
                        const int32_t *off, hipStream_t s);
-void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, hipStream_t s);
+// leaf_of[r] = leaf cell of sorted particle r; *nleaf = number of leaves.
+void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, int32_t *nleaf, hipStream_t s);
 
 // ---- lists.hip
 struct PairBuf {

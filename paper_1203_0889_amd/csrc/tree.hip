@@ -248,9 +248,10 @@ __global__ void k_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t
     }
 }
 
-__global__ void k_leaf_of(CellArrays c, int32_t ncell, int32_t *__restrict__ leaf_of) {
+__global__ void k_leaf_of(CellArrays c, int32_t ncell, int32_t *__restrict__ leaf_of, int32_t *__restrict__ nleaf) {
     for (int32_t cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
         if (c.child[cell] >= 0) continue;
+        atomicAdd(nleaf, 1);
         int32_t f = c.first[cell], e = f + c.count[cell];
         for (int32_t r = f; r < e; r++) leaf_of[r] = cell;
     }
@@ -323,8 +324,9 @@ void launch_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t *boun
     FMM_LAUNCH_CHECK();
 }
 
-void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, hipStream_t s) {
-    hipLaunchKernelGGL(k_leaf_of, dim3(grid_for(ncell, 256, 8192)), dim3(256), 0, s, c, ncell, leaf_of);
+void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, int32_t *nleaf, hipStream_t s) {
+    FMM_HIP_CHECK(hipMemsetAsync(nleaf, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_leaf_of, dim3(grid_for(ncell, 256, 8192)), dim3(256), 0, s, c, ncell, leaf_of, nleaf);
     FMM_LAUNCH_CHECK();
 }
 
