@@ -157,10 +157,8 @@ fmm_status fmm_copy_lists(const fmm_plan *plan, int64_t *m2l_ptr, int32_t *m2l_s
  * Results do not depend on them, only speed.
  */
 typedef struct {
-    int32_t queue_chunk;   /* P2P tasks claimed per atomic grab (>= 1) */
-    int32_t p2p_split;     /* max source leaves per P2P task (>= 1) */
-    int32_t m2l_block;     /* targets per M2L MFMA tile column block (16 or 32) */
-    int32_t grid_per_cu;   /* persistent workgroups per compute unit (1..8) */
+    int32_t m2l_task_entries; /* M2L class entries per work-queue task (1..128) */
+    int32_t grid_per_cu;      /* persistent work-queue workgroups per compute unit (1..8) */
 } fmm_tuning;
 
 fmm_status fmm_get_tuning(const fmm_plan *plan, fmm_tuning *tuning);

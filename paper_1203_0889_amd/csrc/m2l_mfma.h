@@ -18,7 +18,7 @@ void m2l_cid_tables(const int32_t *used_scan, const int32_t *used, const int32_t
                     int32_t *slot_of_cid, hipStream_t s);
 void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int32_t *pcid, int32_t *xflag,
                   hipStream_t s);
-void m2l_target_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *xscan, uint64_t *tkey,
+void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *xscan, uint64_t *tkey,
                      int32_t *has, hipStream_t s);
 // Entries of the 128-target groups: count (class bitmap per group in
 // gbits, ngroup x ceil(ncid/32) words, and word prefixes in gwpre), then
@@ -29,16 +29,21 @@ void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr
                     const int32_t *pcid, int32_t ncid, const uint32_t *gbits, const uint32_t *gwpre,
                     const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget, hipStream_t s);
 void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *tcount, hipStream_t s);
+// M2L tasks ordered by (XCD, chunk index, task); xcd_count[x] = tasks of XCD x.
 void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, int chunk, const int32_t *toff,
-                    int4 *tasks, hipStream_t s);
+                    const uint64_t *tsorted, int32_t ntask, int4 *tasks, int4 *tasks_alt, uint64_t *tkeys,
+                    uint64_t *tkeys_alt, uint32_t *tidx, uint32_t *tidx_alt, int32_t *xcd_count, int32_t *tmp,
+                    hipStream_t s);
 void m2l_extra(const int32_t *xflag, const int32_t *xscan, int64_t npair, const int32_t *src, const int32_t *ptr,
                int32_t ncell, int32_t *xsrc, int32_t *xptr, hipStream_t s);
 void m2l_mfma(const int4 *tasks, int32_t ntask, const int32_t *gtarget, const int32_t *ecls, const int32_t *esrc,
               const int32_t *slot_of_cid, const float *frags, const float *M32, int p, double *L, hipStream_t s);
 
 // ---- p2p_fp32.hip (preparation of the P2P tasks)
-void p2p_leaf_list(CellArrays c, int32_t ncell, const int32_t *p2p_ptr, const int32_t *p2p_src, int32_t *buf,
-                   int32_t *leaves, int32_t *tmp, int32_t *d_count, hipStream_t s);
+// Leaves ordered by (spatial eighth, cost descending); d_count[0] = number
+// of leaves, d_count[1 + x] = leaves in eighth x.
+void p2p_leaf_list(CellArrays c, int32_t ncell, int64_t n, const int32_t *p2p_ptr, const int32_t *p2p_src,
+                   int32_t *buf, int32_t *leaves, int32_t *tmp, int32_t *d_count, hipStream_t s);
 void p2p_prepare(Geometry g, int64_t n, const int32_t *leaf_of, const double *xs, const double *ys,
                  const double *zs, const double *qs, float4 *pf, hipStream_t s);
 void cell_centres(Geometry g, int32_t ncell, double *centre, hipStream_t s);

@@ -13,7 +13,7 @@
 // across builds.  Pairs with |delta| >= 2 are nearly one class each and go
 // to the per-pair FP64 kernel instead.
 //
-// Batching: targets are grouped 128 at a time (same level and octant,
+// Batching: targets are grouped 64 at a time, one wave each (same level and octant,
 // Morton order, so neighbouring targets share their class sets).  A group's
 // entries are its distinct classes in class order, each with the source
 // cell of every target slot (-1 if absent).  The work queue applies each
@@ -205,15 +205,20 @@ __global__ void k_cid_tables(const int32_t *__restrict__ used_scan, const int32_
     }
 }
 
-// Sort key of every cell that has batched M2L pairs: (level, octant, cell).
-__global__ void k_target_keys(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr,
+// Sort key of every cell that has batched M2L pairs: (level, spatial eighth
+// of the particle order, octant, cell).  The eighth (bits 35..37) later
+// selects the XCD whose task list the group joins.
+__global__ void k_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *__restrict__ ptr,
                               const int32_t *__restrict__ xscan, uint64_t *__restrict__ tkey,
                               int32_t *__restrict__ has) {
     for (int32_t A = blockIdx.x * blockDim.x + threadIdx.x; A < ncell; A += gridDim.x * blockDim.x) {
         int32_t nb = (ptr[A + 1] - ptr[A]) - (xscan[ptr[A + 1]] - xscan[ptr[A]]);
         has[A] = nb > 0;
         int oct = (c.ix[A] & 1) | ((c.iy[A] & 1) << 1) | ((c.iz[A] & 1) << 2);
-        tkey[A] = nb > 0 ? (((uint64_t)c.level[A] << 35) | ((uint64_t)oct << 32) | (uint32_t)A) : ~0ull;
+        int c8 = n > 0 ? (int)(((int64_t)c.first[A] * 8) / n) : 0;
+        c8 = c8 > 7 ? 7 : c8;
+        tkey[A] = nb > 0 ? (((uint64_t)c.level[A] << 38) | ((uint64_t)c8 << 35) | ((uint64_t)oct << 32) | (uint32_t)A)
+                         : ~0ull;
     }
 }
 
@@ -340,12 +345,29 @@ __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__
 }
 
 // Tasks: each group's entries split into chunks of `chunk`.
+// Tasks of a group: its entries cut into chunks.  Each task also gets a
+// sort key (XCD of the group, chunk index, task) so that every XCD runs its
+// own groups chunk by chunk: concurrent workgroups then share class
+// operators in that XCD's L2.
 __global__ void k_make_tasks(const int32_t *__restrict__ gcount, const int32_t *__restrict__ goff, int32_t ngroup,
-                             int chunk, const int32_t *__restrict__ toff, int4 *__restrict__ tasks) {
+                             int chunk, const int32_t *__restrict__ toff, const uint64_t *__restrict__ tsorted,
+                             int4 *__restrict__ tasks, uint64_t *__restrict__ tkeys, uint32_t *__restrict__ tidx,
+                             int32_t *__restrict__ xcd_count) {
     for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroup; g += gridDim.x * blockDim.x) {
         int32_t n = gcount[g], t = toff[g];
-        for (int32_t e = 0; e < n; e += chunk) tasks[t++] = make_int4(g, goff[g] + e, goff[g] + (e + chunk < n ? e + chunk : n), 0);
+        int xcd = (int)((tsorted[(int64_t)g * kGroupM2L] >> 35) & 7ull);
+        for (int32_t e = 0, j = 0; e < n; e += chunk, j++, t++) {
+            tasks[t] = make_int4(g, goff[g] + e, goff[g] + (e + chunk < n ? e + chunk : n), 0);
+            tkeys[t] = ((uint64_t)xcd << 56) | ((uint64_t)j << 32) | (uint32_t)t;
+            tidx[t] = (uint32_t)t;
+            atomicAdd(&xcd_count[xcd], 1);
+        }
     }
+}
+
+__global__ void k_permute_tasks(const uint32_t *__restrict__ order, int32_t ntask, const int4 *__restrict__ in,
+                                int4 *__restrict__ out) {
+    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntask; t += gridDim.x * blockDim.x) out[t] = in[order[t]];
 }
 
 __global__ void k_task_counts(const int32_t *__restrict__ gcount, int32_t ngroup, int chunk, int32_t *__restrict__ tcount) {
@@ -400,9 +422,10 @@ void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_target_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *xscan, uint64_t *tkey,
+void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *xscan, uint64_t *tkey,
                      int32_t *has, hipStream_t s) {
-    hipLaunchKernelGGL(k_target_keys, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, ptr, xscan, tkey, has);
+    hipLaunchKernelGGL(k_target_keys, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, n, ptr, xscan, tkey,
+                       has);
     FMM_LAUNCH_CHECK();
 }
 
@@ -438,10 +461,16 @@ void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *
 }
 
 void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, int chunk, const int32_t *toff,
-                    int4 *tasks, hipStream_t s) {
-    if (ngroup <= 0) return;
+                    const uint64_t *tsorted, int32_t ntask, int4 *tasks, int4 *tasks_alt, uint64_t *tkeys,
+                    uint64_t *tkeys_alt, uint32_t *tidx, uint32_t *tidx_alt, int32_t *xcd_count, int32_t *tmp,
+                    hipStream_t s) {
+    FMM_HIP_CHECK(hipMemsetAsync(xcd_count, 0, 8 * sizeof(int32_t), s));
+    if (ngroup <= 0 || ntask <= 0) return;
     hipLaunchKernelGGL(k_make_tasks, dim3(grid_for(ngroup, 256, 4096)), dim3(256), 0, s, gcount, goff, ngroup, chunk,
-                       toff, tasks);
+                       toff, tsorted, tasks_alt, tkeys, tidx, xcd_count);
+    FMM_LAUNCH_CHECK();
+    radix_sort_u64(tkeys, tidx, tkeys_alt, tidx_alt, ntask, 0, 64, tmp, s);
+    hipLaunchKernelGGL(k_permute_tasks, dim3(grid_for(ntask, 256, 4096)), dim3(256), 0, s, tidx, ntask, tasks_alt, tasks);
     FMM_LAUNCH_CHECK();
 }
 

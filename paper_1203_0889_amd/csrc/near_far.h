@@ -27,6 +27,7 @@ struct NearFarState {
     DevBuf used, slot_of, nslots, new_keys, frags, used_scan, cid_of, slot_of_cid;
     DevBuf pkey, pcid, xflag, xscan, tkey, tkey_alt, has, gcount, goff, tcount, toff;
     DevBuf ecls, esrc, gtarget, tasks, xsrc, xptr, leafbuf, leaves, pf, M32, tmp, cnt, centre, gbits, gwpre;
+    DevBuf tasks_alt, tkeys, tidx, lists;
     int p = -1;
     int32_t nslot_total = 0, ncid = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0, nleaves = 0;
     bool built = false;

@@ -10,9 +10,7 @@ namespace fmm {
 
 fmm_tuning default_tuning() {
     fmm_tuning t;
-    t.queue_chunk = 48;     // M2L entries per task
-    t.p2p_split = 1 << 20;
-    t.m2l_block = 32;
+    t.m2l_task_entries = 96;
     t.grid_per_cu = 2;
     return t;
 }
@@ -82,8 +80,9 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.tkey.grow((size_t)(ncell + 1) * 8));
     FMM_HIP_CHECK(st.tkey_alt.grow((size_t)(ncell + 1) * 8));
     FMM_HIP_CHECK(st.has.grow((size_t)(ncell + 1) * 4));
-    m2l_target_keys(a.g.c, ncell, a.m2l_ptr, st.xscan.as<int32_t>(), st.tkey.as<uint64_t>(), st.has.as<int32_t>(), s);
-    radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 0, 40,
+    m2l_target_keys(a.g.c, ncell, a.n, a.m2l_ptr, st.xscan.as<int32_t>(), st.tkey.as<uint64_t>(), st.has.as<int32_t>(),
+                    s);
+    radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 0, 43,
                    st.tmp.as<int32_t>(), s);
     exclusive_scan_i32(st.has.as<int32_t>(), ncell, cnt + 2, st.tmp.as<int32_t>(), s);
     int32_t h3[3];
@@ -105,7 +104,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     m2l_group_count(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, st.pcid.as<int32_t>(), st.ncid,
                     st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.gcount.as<int32_t>(), s);
     exclusive_scan_oop(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, cnt + 3, st.tmp.as<int32_t>(), s);
-    const int chunk = std::max(1, a.tuning.queue_chunk);
+    const int chunk = std::max(1, std::min(kMaxTaskEntries, a.tuning.m2l_task_entries));
     m2l_task_counts(st.gcount.as<int32_t>(), st.ngroup, chunk, st.tcount.as<int32_t>(), s);
     exclusive_scan_oop(st.tcount.as<int32_t>(), st.toff.as<int32_t>(), st.ngroup, cnt + 4, st.tmp.as<int32_t>(), s);
     int32_t h2[2];
@@ -114,30 +113,50 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     st.ntask = st.ngroup > 0 ? h2[1] : 0;
     FMM_HIP_CHECK(st.ecls.grow((size_t)std::max(st.nentries, 1) * 4));
     FMM_HIP_CHECK(st.esrc.grow((size_t)std::max(st.nentries, 1) * kGroupM2L * 4));
-    FMM_HIP_CHECK(st.tasks.grow((size_t)std::max(st.ntask, 1) * sizeof(int4)));
+    const size_t nt1 = (size_t)std::max(st.ntask, 1);
+    FMM_HIP_CHECK(st.tasks.grow(nt1 * sizeof(int4)));
+    FMM_HIP_CHECK(st.tasks_alt.grow(nt1 * sizeof(int4)));
+    FMM_HIP_CHECK(st.tkeys.grow(nt1 * 8 * 2));
+    FMM_HIP_CHECK(st.tidx.grow(nt1 * 4 * 2));
+    FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, radix_tmp_elems(nt1) * 4)));
     if (st.nentries > 0)
         FMM_HIP_CHECK(hipMemsetAsync(st.esrc.ptr, 0xff, (size_t)st.nentries * kGroupM2L * 4, s));
     m2l_group_fill(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
                    st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(),
                    st.esrc.as<int32_t>(), st.gtarget.as<int32_t>(), s);
     m2l_make_tasks(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, chunk, st.toff.as<int32_t>(),
-                   st.tasks.as<int4>(), s);
+                   st.tkey.as<uint64_t>(), st.ntask, st.tasks.as<int4>(), st.tasks_alt.as<int4>(),
+                   st.tkeys.as<uint64_t>(), st.tkeys.as<uint64_t>() + nt1, st.tidx.as<uint32_t>(),
+                   st.tidx.as<uint32_t>() + nt1, cnt + 16, st.tmp.as<int32_t>(), s);
     // ---- pairs left to the per-pair kernel (|delta| >= 2 or far displacement)
     FMM_HIP_CHECK(st.xsrc.grow((size_t)std::max(st.nextra, 1) * 4));
     FMM_HIP_CHECK(st.xptr.grow((size_t)(ncell + 1) * 4));
     m2l_extra(st.xflag.as<int32_t>(), st.xscan.as<int32_t>(), npair, a.m2l_src, a.m2l_ptr, ncell, st.xsrc.as<int32_t>(),
               st.xptr.as<int32_t>(), s);
-    // ---- P2P leaf list (costliest first) and cell centres
+    // ---- P2P leaves (by spatial eighth, costliest first) and cell centres
     FMM_HIP_CHECK(st.leafbuf.grow((size_t)4 * (ncell + 1) * 4));
     FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
     FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, radix_tmp_elems(ncell) * 4)));
-    p2p_leaf_list(a.g.c, ncell, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
-                  st.tmp.as<int32_t>(), cnt + 5, s);
+    p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
+                  st.tmp.as<int32_t>(), cnt + 24, s);
     FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
     cell_centres(a.g, ncell, st.centre.as<double>(), s);
-    int32_t nl;
-    read_sync(&nl, cnt + 5, 4, s);
-    st.nleaves = nl;
+    // ---- the 16 task lists (M2L and P2P per XCD)
+    int32_t hc[17];
+    read_sync(hc, cnt + 16, sizeof(hc), s);  // [0..7] M2L tasks per XCD, [8] leaves, [9..16] leaves per XCD
+    st.nleaves = hc[8];
+    int4 lists[16];
+    int32_t mt = 0, lf = 0;
+    for (int x = 0; x < 8; x++) {
+        lists[2 * x] = make_int4(mt, hc[x], 0, 0);
+        mt += hc[x];
+        int32_t nl = hc[9 + x];
+        lists[2 * x + 1] = make_int4(0, nl, lf, 0);
+        lf += nl;
+    }
+    FMM_HIP_CHECK(st.lists.grow(sizeof(lists)));
+    FMM_HIP_CHECK(hipMemcpyAsync(st.lists.ptr, lists, sizeof(lists), hipMemcpyHostToDevice, s));
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
     st.built = true;
 }
 
@@ -149,7 +168,7 @@ void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     const int32_t ncell = a.ncell;
     FMM_HIP_CHECK(st.M32.grow((size_t)(ncell + 1) * 2 * KS4 * 4));
     FMM_HIP_CHECK(st.pf.grow((size_t)std::max<int64_t>(a.n, 1) * sizeof(float4)));
-    FMM_HIP_CHECK(st.cnt.grow(16 * 4));
+    FMM_HIP_CHECK(st.cnt.grow(64 * 4));
     queue_pad_multipoles(a.M, ncell, a.p, st.M32.as<float>(), s);
     FMM_HIP_CHECK(hipMemsetAsync(a.L, 0, (size_t)ncell * P * 8, s));
     p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
@@ -173,9 +192,8 @@ void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     q.pf = st.pf.as<float4>();
     q.phi = a.phi;
     q.fld = a.fld;
-    q.nm2l_task = st.ntask;
-    q.ntask = st.ntask + (st.nleaves + 3) / 4;
-    q.head = st.cnt.as<int32_t>() + 8;
+    q.lists = st.lists.as<int4>();
+    q.heads = st.cnt.as<int32_t>() + 40;
     int dev = 0, ncu = 256;
     FMM_HIP_CHECK(hipGetDevice(&dev));
     FMM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -188,7 +206,7 @@ void release_near_far(NearFarState &st) {
     DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.used_scan, &st.cid_of,
                      &st.slot_of_cid, &st.pkey, &st.pcid, &st.xflag, &st.xscan, &st.tkey, &st.tkey_alt, &st.has,
                      &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
-                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre};
+                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists};
     for (DevBuf *b : all) b->release();
     st.p = -1;
     st.built = false;

@@ -26,21 +26,34 @@ __global__ void k_centres(Geometry g, int32_t ncell, double *__restrict__ centre
     }
 }
 
-// Leaf cost = targets x sources over its P2P list; sort key = ~cost so an
-// ascending sort puts the costliest first.
-__global__ void k_leaf_cost(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr,
-                            const int32_t *__restrict__ src, int32_t *__restrict__ flag, uint32_t *__restrict__ key,
+// Leaf cost = targets x sources over its P2P list.  Sort key = (spatial
+// eighth of the particle order) << 29 | (2^29 - 1 - cost): ascending order
+// groups leaves by eighth (the XCD that runs them) and puts the costliest
+// first within each.  Non-leaves get the largest key.
+__global__ void k_leaf_cost(CellArrays c, int32_t ncell, int64_t n, const int32_t *__restrict__ ptr,
+                            const int32_t *__restrict__ src, int32_t *__restrict__ count8, uint32_t *__restrict__ key,
                             uint32_t *__restrict__ val) {
+    __shared__ int32_t lc[9];
+    if (threadIdx.x < 9) lc[threadIdx.x] = 0;
+    __syncthreads();
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += gridDim.x * blockDim.x) {
         bool leaf = c.child[i] < 0 && c.count[i] > 0;
-        flag[i] = leaf ? 1 : 0;
         uint64_t cost = 0;
-        if (leaf)
+        int c8 = 0;
+        if (leaf) {
             for (int32_t e = ptr[i]; e < ptr[i + 1]; e++) cost += (uint64_t)c.count[src[e]];
-        cost *= (uint64_t)c.count[i];
-        key[i] = leaf ? ~(uint32_t)(cost > 0xfffffffeull ? 0xfffffffeull : cost) : 0xffffffffu;
+            cost *= (uint64_t)c.count[i];
+            c8 = (int)(((int64_t)c.first[i] * 8) / n);
+            c8 = c8 > 7 ? 7 : c8;
+            atomicAdd(&lc[0], 1);
+            atomicAdd(&lc[1 + c8], 1);
+        }
+        const uint64_t cmax = (1ull << 29) - 1;
+        key[i] = leaf ? (((uint32_t)c8 << 29) | (uint32_t)(cmax - (cost > cmax - 1 ? cmax - 1 : cost))) : 0xffffffffu;
         val[i] = (uint32_t)i;
     }
+    __syncthreads();
+    if (threadIdx.x < 9 && lc[threadIdx.x]) atomicAdd(&count8[threadIdx.x], lc[threadIdx.x]);
 }
 
 __global__ void k_p2p_prepare(Geometry g, int64_t n, const int32_t *__restrict__ leaf_of,
@@ -55,20 +68,18 @@ __global__ void k_p2p_prepare(Geometry g, int64_t n, const int32_t *__restrict__
 
 }  // namespace
 
-// buf holds 4 * (ncell + 1) ints: flag, keys, values, alternate keys/values.
-void p2p_leaf_list(CellArrays c, int32_t ncell, const int32_t *p2p_ptr, const int32_t *p2p_src, int32_t *buf,
-                   int32_t *leaves, int32_t *tmp, int32_t *d_count, hipStream_t s) {
-    int32_t *flag = buf;
+// buf holds 4 * (ncell + 1) ints: keys, values, alternate keys/values.
+void p2p_leaf_list(CellArrays c, int32_t ncell, int64_t n, const int32_t *p2p_ptr, const int32_t *p2p_src,
+                   int32_t *buf, int32_t *leaves, int32_t *tmp, int32_t *d_count, hipStream_t s) {
     uint32_t *key = (uint32_t *)(buf + (ncell + 1));
     uint32_t *kalt = (uint32_t *)(buf + 2 * (ncell + 1));
     uint32_t *valt = (uint32_t *)(buf + 3 * (ncell + 1));
     uint32_t *val = (uint32_t *)leaves;
-    hipLaunchKernelGGL(k_leaf_cost, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, p2p_ptr, p2p_src, flag,
-                       key, val);
+    FMM_HIP_CHECK(hipMemsetAsync(d_count, 0, 9 * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_leaf_cost, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, n, p2p_ptr, p2p_src,
+                       d_count, key, val);
     FMM_LAUNCH_CHECK();
     radix_sort_u32(key, val, kalt, valt, ncell, 0, 32, tmp, s);
-    // the number of leaves: sum of flags (flags become scratch for the scan)
-    exclusive_scan_i32(flag, ncell, d_count, tmp, s);
 }
 
 void p2p_prepare(Geometry g, int64_t n, const int32_t *leaf_of, const double *xs, const double *ys,

@@ -660,8 +660,7 @@ fmm_status fmm_get_tuning(const fmm_plan *p, fmm_tuning *t) {
 
 fmm_status fmm_set_tuning(fmm_plan *p, const fmm_tuning *t) {
     if (!p || !t) return FMM_ERR_INVALID_ARG;
-    if (t->queue_chunk < 1 || t->p2p_split < 1 || (t->m2l_block != 16 && t->m2l_block != 32) || t->grid_per_cu < 1 ||
-        t->grid_per_cu > 8)
+    if (t->m2l_task_entries < 1 || t->m2l_task_entries > 128 || t->grid_per_cu < 1 || t->grid_per_cu > 8)
         return fail(p, FMM_ERR_INVALID_ARG, "tuning out of range");
     p->tuning = *t;
     return FMM_OK;

@@ -5,7 +5,8 @@
 
 namespace fmm {
 
-constexpr int kGroupM2L = 128;  // targets per M2L task group (4 waves x 32)
+constexpr int kGroupM2L = 64;   // targets per M2L task group (one wave, two MFMA column tiles)
+constexpr int kMaxTaskEntries = 128;  // class entries per M2L task (the wave keeps two slots per lane)
 
 struct QueueArgs {
     CellArrays c;
@@ -28,9 +29,11 @@ struct QueueArgs {
     const int32_t *p2p_ptr, *p2p_src;
     const float4 *pf;          // particles: (x, y, z) - own leaf centre, q
     double *phi, *fld;         // FP64 near field per sorted particle
-    // queue
-    int32_t nm2l_task, ntask;  // tasks [0, nm2l_task) are M2L, the rest P2P (4 leaves each)
-    int32_t *head;             // claim counter (zeroed before launch)
+    // queue: 16 task lists, list 2x = M2L tasks of XCD x, list 2x+1 = P2P
+    // tasks of XCD x.  lists[L] = (first M2L task, task count, first leaf, 0);
+    // P2P task t of a list is leaf first + t.
+    const int4 *lists;
+    int32_t *heads;            // 16 claim counters (zeroed before launch)
 };
 
 bool queue_supported(int p);

@@ -2,25 +2,27 @@
 //
 // The paper schedules M2L and P2P work as tasks of adjustable granularity
 // on a multicore runtime (Sec. 3, 4); here one persistent kernel plays that
-// role on the GPU.  Workgroups (4 waves) claim tasks from a global counter
-// until the list is exhausted; tasks are ordered largest first.
-//   * M2L task: a group of 128 target cells (same level and octant, Morton
-//     order) and a range of its class entries.  Per entry the class
-//     operator T_c (FP32, pre-swizzled MFMA fragments) is staged in LDS and
-//     shared by the 4 waves; each wave owns 32 targets and runs
-//     v_mfma_f32_32x32x2_f32 with A = T_c, B = the 32 gathered multipoles.
-//     The next entry's operator and multipoles are prefetched into
-//     registers while the current one is applied.  Results are added into
-//     the FP64 local expansions.
-//   * P2P task: 4 target leaves, one per wave.  Sources are staged in the
-//     wave's private LDS tile as float4 relative to the target centre.  A
-//     leaf of nt targets is covered by one pass per set bit b of nt, with
-//     2^b targets x 64/2^b source streams, so every lane works whatever nt
-//     is; streams are combined with cross-lane shuffles.
-// Target-owned writes (each target cell or particle belongs to one task)
-// keep the P2P results deterministic; M2L partial sums of one target may
-// come from several tasks and are added with FP64 atomics.
+// role on the GPU.  Every wave is an independent worker: it claims tasks from
+// device-side lists with an atomic counter until the lists are exhausted.
+// There are no workgroup barriers, so waves of different task types share a
+// SIMD and the matrix cores (M2L) overlap the vector ALUs (P2P).
+//   * M2L task: a group of 64 target cells (same level and octant, Morton
+//     order) and a range of its class entries.  For each entry the wave runs
+//     v_mfma_f32_32x32x2_f32 with A = the class operator T_c (FP32,
+//     pre-swizzled fragments, one 1 KB line per wave load) and B = the
+//     multipoles of the class's sources, two 32-column tiles per operator
+//     fragment; operator and multipole loads run two k-steps ahead, across
+//     entries.  The targets' local expansions accumulate in FP32 AGPRs and
+//     are added into the FP64 locals at the end of the task.
+//   * P2P task: one target leaf.  Sources are staged in the wave's LDS tile
+//     as float4 relative to the target centre; a leaf of nt targets is
+//     covered by at most two passes of 2^b targets x 64/2^b source streams;
+//     streams are combined with cross-lane shuffles.
+// Lists are kept per XCD (spatially contiguous tasks, so the XCD's L2 holds
+// their operators and multipoles); a wave drains its XCD's lists, then steals.
 #include "queue.h"
+
+#include <algorithm>
 
 namespace fmm {
 
@@ -36,7 +38,7 @@ __device__ inline void wave_sync() {
 }
 
 // ------------------------------------------------------------------ P2P
-constexpr int kP2PTile = 512;  // float4 sources per wave tile (8 KB)
+constexpr int kP2PTile = 256;  // float4 sources per wave tile (4 KB)
 
 // A leaf of nt <= 64 targets is covered by at most two passes: pass 0
 // takes the first T0 = 2^floor(log2 nt) targets, pass 1 the remaining
@@ -51,6 +53,23 @@ struct Pass {
 };
 
 template <bool kMask>
+__device__ inline void p2p_one(float4 v, float xt, float yt, float zt, float &a0, float &a1, float &a2, float &a3) {
+    float dx = xt - v.x, dy = yt - v.y, dz = zt - v.z;
+    float r2 = dx * dx + dy * dy + dz * dz;
+    float ri = __builtin_amdgcn_rsqf(r2);
+    if (kMask) ri = r2 > 0.f ? ri : 0.f;
+    float qr = v.w * ri;
+    float w = qr * ri * ri;
+    a0 += qr;
+    a1 += dx * w;
+    a2 += dy * w;
+    a3 += dz * w;
+}
+
+// Sources j = s, s + S, ... of the tile against this lane's target.  Eight
+// LDS reads are issued before their arithmetic so that their latency
+// overlaps (one wait per batch instead of one per source).
+template <bool kMask>
 __device__ inline void p2p_pass(const float4 *__restrict__ tile, int count, Pass &ps, int lane) {
     if (ps.lg < 0) return;
     const int S = 64 >> ps.lg;
@@ -58,35 +77,22 @@ __device__ inline void p2p_pass(const float4 *__restrict__ tile, int count, Pass
     const float xt = ps.x, yt = ps.y, zt = ps.z;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
     int j = s;
-    for (; j + 3 * S < count; j += 4 * S) {
+    for (; j + 7 * S < count; j += 8 * S) {
+        float4 v[8];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            float4 v = tile[j + u * S];
-            float dx = xt - v.x, dy = yt - v.y, dz = zt - v.z;
-            float r2 = dx * dx + dy * dy + dz * dz;
-            float ri = __builtin_amdgcn_rsqf(r2);
-            if (kMask) ri = r2 > 0.f ? ri : 0.f;
-            float qr = v.w * ri;
-            float w = qr * ri * ri;
-            a0 += qr;
-            a1 += dx * w;
-            a2 += dy * w;
-            a3 += dz * w;
-        }
+        for (int u = 0; u < 8; u++) v[u] = tile[j + u * S];
+#pragma unroll
+        for (int u = 0; u < 8; u++) p2p_one<kMask>(v[u], xt, yt, zt, a0, a1, a2, a3);
     }
-    for (; j < count; j += S) {
-        float4 v = tile[j];
-        float dx = xt - v.x, dy = yt - v.y, dz = zt - v.z;
-        float r2 = dx * dx + dy * dy + dz * dz;
-        float ri = __builtin_amdgcn_rsqf(r2);
-        if (kMask) ri = r2 > 0.f ? ri : 0.f;
-        float qr = v.w * ri;
-        float w = qr * ri * ri;
-        a0 += qr;
-        a1 += dx * w;
-        a2 += dy * w;
-        a3 += dz * w;
+    if (j + 3 * S < count) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = tile[j + u * S];
+#pragma unroll
+        for (int u = 0; u < 4; u++) p2p_one<kMask>(v[u], xt, yt, zt, a0, a1, a2, a3);
+        j += 4 * S;
     }
+    for (; j < count; j += S) p2p_one<kMask>(tile[j], xt, yt, zt, a0, a1, a2, a3);
     ps.ph += a0;
     ps.ex += a1;
     ps.ey += a2;
@@ -223,104 +229,159 @@ __device__ void p2p_leaf(const QueueArgs &a, int32_t A, float4 *__restrict__ til
 }
 
 // ------------------------------------------------------------------ M2L
-// B operand: lane (col, kh) walks row s of the padded multipoles from
-// element kh * KS4, one float4 per 4 k-steps, with a 2-deep lookahead that
-// runs across entries.  Absent sources point at an all-zero row.
+// first multipole float4 of this lane's half-row of cell s (s < 0: zero row)
+__device__ inline const v4f *mrow(const QueueArgs &a, const v4f *m4, int32_t s, int ps4) {
+    return m4 + (int64_t)(s < 0 ? a.zero_row : s) * ps4;
+}
+
+// One wave, kGroupM2L = 32 NB targets (NB column tiles of 32).  Lane
+// (col = lane % 32, kh = lane / 32) holds, per k-step q, operator element
+// T[r * 32 + col][kh * KS4 + 4 q + u] (4 u's in a float4, one per MFMA) and,
+// for tile b, multipole element M~_src(b * 32 + col)[kh * KS4 + 4 q + u].
+// Each operator fragment feeds NB MFMAs.  Entry metadata never sits on the
+// critical path: the operator slots of all the task's entries are loaded
+// once (lane l holds entries l and 64 + l, read back with readlane), and the
+// source cells of entry e + 2 are loaded while entry e runs.
 template <int RT, int KS4>
-__device__ void m2l_task(const QueueArgs &a, int4 task, float4 *__restrict__ Ts) {
-    constexpr int NQ = KS4 / 4;                        // float4 per lane per row tile
-    constexpr int PER = (RT * NQ * 64 + 255) / 256;    // operator float4 per thread
-    constexpr int NF4P = PER * 256;                    // padded float4 per class operator
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+__device__ void m2l_wave(const QueueArgs &a, int4 task, int lane) {
+    constexpr int NQ = KS4 / 4;                        // float4 k-steps per entry
+    constexpr int NB = kGroupM2L / 32;                 // column tiles
+    static_assert(NQ >= 2, "the load window needs two k-steps per entry");
+    constexpr int NF4P = ((RT * NQ * 64 + 255) / 256) * 256;  // padded float4 per class operator
     const int col = lane & 31, kh = lane >> 5;
-    const int PS = 2 * KS4;                            // padded multipole row stride
-    const v4f *frag4 = reinterpret_cast<const v4f *>(a.frags) + tid;
-    v4f *Tsv = reinterpret_cast<v4f *>(Ts);
-    const float4 *m4 = reinterpret_cast<const float4 *>(a.M32) + kh * NQ;
-    f16v acc[RT];
+    const int PS4 = KS4 / 2;                           // float4 per padded multipole row
+    const v4f *frag4 = reinterpret_cast<const v4f *>(a.frags) + lane;
+    const v4f *m4 = reinterpret_cast<const v4f *>(a.M32) + kh * NQ;
+    const int32_t *gsrc = a.esrc + col;
+    const int32_t e0 = task.y, ne = task.z - task.y;   // wave-uniform
+    // operator slots of the task's entries
+    int32_t slot_lo = 0, slot_hi = 0;
+    if (lane < ne) slot_lo = a.slot_of_cid[a.ecls[e0 + lane]];
+    if (64 + lane < ne) slot_hi = a.slot_of_cid[a.ecls[e0 + 64 + lane]];
+    auto slot = [&](int i) {
+        return i < 64 ? __builtin_amdgcn_readlane(slot_lo, i) : __builtin_amdgcn_readlane(slot_hi, i - 64);
+    };
+    f16v acc[RT][NB];
 #pragma unroll
     for (int r = 0; r < RT; r++)
 #pragma unroll
-        for (int i = 0; i < 16; i++) acc[r][i] = 0.f;
-    v4f tpre[PER];
-    // first entry: operator to LDS, multipole window
-    {
-        const v4f *src = frag4 + (int64_t)a.slot_of_cid[a.ecls[task.y]] * NF4P;
+        for (int b = 0; b < NB; b++)
 #pragma unroll
-        for (int i = 0; i < PER; i++) tpre[i] = src[i * 256];
+            for (int i = 0; i < 16; i++) acc[r][b][i] = 0.f;
+    const v4f *T = frag4 + (int64_t)slot(0) * NF4P;
+    const v4f *R[NB];
+    int32_t sn[NB];                                    // source cells of entry i + 1
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        R[b] = mrow(a, m4, gsrc[(int64_t)e0 * kGroupM2L + b * 32], PS4);
+        sn[b] = ne > 1 ? gsrc[(int64_t)(e0 + 1) * kGroupM2L + b * 32] : -1;
     }
-    int32_t s0 = a.esrc[(int64_t)task.y * kGroupM2L + w * 32 + col];
-    const float4 *row = m4 + (int64_t)(s0 < 0 ? a.zero_row : s0) * (PS / 4);
-    float4 w0 = row[0], w1 = NQ > 1 ? row[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // two-step window: A fragments (RT row tiles) and B fragments (NB
+    // column tiles) of steps q and q + 1
+    v4f a0[RT], a1[RT], b0[NB], b1[NB];
 #pragma unroll
-    for (int i = 0; i < PER; i++) Tsv[tid + i * 256] = tpre[i];
-    __syncthreads();
-    for (int32_t e = task.y; e < task.z; e++) {
-        const bool more = e + 1 < task.z;
-        const float4 *nrow = row;
+    for (int r = 0; r < RT; r++) {
+        a0[r] = T[(r * NQ) * 64];
+        a1[r] = T[(r * NQ + 1) * 64];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        b0[b] = R[b][0];
+        b1[b] = R[b][1];
+    }
+    for (int i = 0; i < ne; i++) {
+        const bool more = i + 1 < ne;
+        const v4f *nT = T;
+        const v4f *nR[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) nR[b] = R[b];
         if (more) {
-            const v4f *src = frag4 + (int64_t)a.slot_of_cid[a.ecls[e + 1]] * NF4P;
+            nT = frag4 + (int64_t)slot(i + 1) * NF4P;
 #pragma unroll
-            for (int i = 0; i < PER; i++) tpre[i] = src[i * 256];
-            int32_t s1 = a.esrc[(int64_t)(e + 1) * kGroupM2L + w * 32 + col];
-            nrow = m4 + (int64_t)(s1 < 0 ? a.zero_row : s1) * (PS / 4);
+            for (int b = 0; b < NB; b++) {
+                nR[b] = mrow(a, m4, sn[b], PS4);
+                sn[b] = i + 2 < ne ? gsrc[(int64_t)(e0 + i + 2) * kGroupM2L + b * 32] : -1;
+            }
         }
 #pragma unroll
         for (int q = 0; q < NQ; q++) {
-            const float4 cur = w0;
-            w0 = w1;
-            if (q + 2 < NQ) w1 = row[q + 2];
-            else if (more) w1 = nrow[q + 2 - NQ];
+            v4f ca[RT], cb[NB];
 #pragma unroll
             for (int r = 0; r < RT; r++) {
-                float4 av = Ts[(r * NQ + q) * 64 + lane];
-                acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, cur.x, acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, cur.y, acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, cur.z, acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, cur.w, acc[r], 0, 0, 0);
+                ca[r] = a0[r];
+                a0[r] = a1[r];
             }
-        }
-        row = nrow;
-        __syncthreads();
-        if (more) {
 #pragma unroll
-            for (int i = 0; i < PER; i++) Tsv[tid + i * 256] = tpre[i];
+            for (int b = 0; b < NB; b++) {
+                cb[b] = b0[b];
+                b0[b] = b1[b];
+            }
+            if (q + 2 < NQ) {
+#pragma unroll
+                for (int b = 0; b < NB; b++) b1[b] = R[b][q + 2];
+#pragma unroll
+                for (int r = 0; r < RT; r++) a1[r] = T[(r * NQ + q + 2) * 64];
+            } else if (more) {
+#pragma unroll
+                for (int b = 0; b < NB; b++) b1[b] = nR[b][q + 2 - NQ];
+#pragma unroll
+                for (int r = 0; r < RT; r++) a1[r] = nT[(r * NQ + q + 2 - NQ) * 64];
+            }
+            // keep the loads of step q + 2 ahead of the MFMAs of step q (the
+            // scheduler would otherwise sink them to their uses)
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int r = 0; r < RT; r++)
+#pragma unroll
+                for (int b = 0; b < NB; b++) {
+                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[r].x, cb[b].x, acc[r][b], 0, 0, 0);
+                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[r].y, cb[b].y, acc[r][b], 0, 0, 0);
+                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[r].z, cb[b].z, acc[r][b], 0, 0, 0);
+                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[r].w, cb[b].w, acc[r][b], 0, 0, 0);
+                }
         }
-        __syncthreads();
+        T = nT;
+#pragma unroll
+        for (int b = 0; b < NB; b++) R[b] = nR[b];
     }
-    const int32_t A = a.gtarget[(int64_t)task.x * kGroupM2L + w * 32 + col];
-    if (A < 0) return;
-    double *Lc = a.L + (int64_t)A * a.P;
 #pragma unroll
-    for (int r = 0; r < RT; r++)
+    for (int b = 0; b < NB; b++) {
+        const int32_t A = a.gtarget[(int64_t)task.x * kGroupM2L + b * 32 + col];
+        if (A < 0) continue;
+        double *Lc = a.L + (int64_t)A * a.P;
 #pragma unroll
-        for (int i = 0; i < 16; i++) {
-            int row_i = r * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-            if (row_i < a.P) atomicAdd(&Lc[row_i], (double)acc[r][i]);
-        }
+        for (int r = 0; r < RT; r++)
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                int row_i = r * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+                if (row_i < a.P) atomicAdd(&Lc[row_i], (double)acc[r][b][i]);
+            }
+    }
 }
 
 // ------------------------------------------------------------------ queue
 template <int RT, int KS4>
 __global__ void __launch_bounds__(256) k_queue(QueueArgs a) {
-    constexpr int kTsF4 = ((RT * (KS4 / 4) * 64 + 255) / 256) * 256;
-    constexpr int kLdsF4 = kTsF4 > 4 * kP2PTile ? kTsF4 : 4 * kP2PTile;
-    __shared__ float4 lds[kLdsF4];
-    __shared__ int32_t task_sh;
+    __shared__ float4 lds[4 * kP2PTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (;;) {
-        if (threadIdx.x == 0) task_sh = atomicAdd(a.head, 1);
-        __syncthreads();
-        const int32_t t = task_sh;
-        __syncthreads();
-        if (t >= a.ntask) break;
-        if (t < a.nm2l_task) {
-            m2l_task<RT, KS4>(a, a.m2l_tasks[t], lds);
-        } else {
-            int32_t li = (t - a.nm2l_task) * 4 + w;
-            if (li < a.nleaves) p2p_leaf(a, a.leaves[li], lds + w * kP2PTile, lane);
+    // Workgroups go round-robin over the 8 XCDs.  Waves drain their own
+    // XCD's lists first, then steal from other XCDs.  The task type a wave
+    // starts with alternates with its wave slot on the SIMD (HW_ID bits 3:0),
+    // so the waves sharing a SIMD mix matrix-core and vector work.
+    const int x = blockIdx.x & 7;
+    const int role = __builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (3 << 11)) & 1;
+    float4 *tile = lds + w * kP2PTile;
+    for (int k = 0; k < 16; k++) {
+        const int L = (((x + (k >> 1)) & 7) << 1) | ((k & 1) ^ role);
+        const int4 li = a.lists[L];
+        for (;;) {
+            int32_t t = 0;
+            if (lane == 0) t = atomicAdd(&a.heads[L], 1);
+            t = __builtin_amdgcn_readfirstlane(t);      // lane 0's claim, wave-uniform
+            if (t >= li.y) break;
+            if ((L & 1) == 0) m2l_wave<RT, KS4>(a, a.m2l_tasks[li.x + t], lane);
+            else p2p_leaf(a, a.leaves[li.z + t], tile, lane);
         }
-        __syncthreads();
     }
 }
 
@@ -341,7 +402,8 @@ bool queue_supported(int p) { return p >= 0 && p <= 12; }
 void queue_layout(int p, int *RT, int *KS4) {
     const int P = ncoef(p);
     *RT = (P + 31) / 32;
-    *KS4 = (((P + 1) / 2 + 3) / 4) * 4;
+    // at least two float4 k-steps per entry: the M2L load window spans two
+    *KS4 = std::max(8, (((P + 1) / 2 + 3) / 4) * 4);
 }
 
 int64_t queue_frag_floats(int p) {
@@ -360,15 +422,14 @@ void queue_pad_multipoles(const double *M, int32_t ncell, int p, float *M32, hip
 }
 
 void queue_run(const QueueArgs &a, int p, int nworkgroups, hipStream_t s) {
-    if (a.ntask <= 0) return;
-    FMM_HIP_CHECK(hipMemsetAsync(a.head, 0, sizeof(int32_t), s));
+    FMM_HIP_CHECK(hipMemsetAsync(a.heads, 0, 16 * sizeof(int32_t), s));
     dim3 grid(nworkgroups), block(256);
 #define FMM_Q(PP, R, K)                                                   \
     case PP:                                                              \
         hipLaunchKernelGGL((k_queue<R, K>), grid, block, 0, s, a);        \
         break;
     switch (p) {
-        FMM_Q(0, 1, 4) FMM_Q(1, 1, 4) FMM_Q(2, 1, 8) FMM_Q(3, 1, 8) FMM_Q(4, 1, 16) FMM_Q(5, 2, 20)
+        FMM_Q(0, 1, 8) FMM_Q(1, 1, 8) FMM_Q(2, 1, 8) FMM_Q(3, 1, 8) FMM_Q(4, 1, 16) FMM_Q(5, 2, 20)
         FMM_Q(6, 2, 28) FMM_Q(7, 2, 32) FMM_Q(8, 3, 44) FMM_Q(9, 4, 52) FMM_Q(10, 4, 64) FMM_Q(11, 5, 72)
         FMM_Q(12, 6, 88)
         default: throw HipError{hipErrorInvalidValue, "queue: unsupported order"};
