@@ -1,19 +1,20 @@
-// M2L as a dense contraction on the FP32 matrix cores (the multipole-to-local
+// M2L as a dense contraction on the matrix cores (the multipole-to-local
 // stage of Sec. 2.1, applied hundreds of times per cell).
 //
 // With level-scaled coefficients the M2L operator of a pair (A <- B) depends
 // only on its class c = (delta, rho): delta = level(A) - level(B) and rho =
 // (C_A - C_B) / min(S_A, S_B), the integer displacement of the centres in
 // units of the smaller cell (half grid units C, cell sides S).  The real
-// operator T_c ((p+1)^2 x (p+1)^2, FP32) is built once per class from the
-// irregular solid harmonics I_n^m(rho / (2 S_A / S_min)):
+// operator T_c ((p+1)^2 x (p+1)^2) is built once per class in FP64 from the
+// irregular solid harmonics I_n^m(rho / (2 S_A / S_min)) and stored as two
+// bf16 pieces (the rounding of each entry and of its remainder):
 //   L~_n^m += (-1)^n sum_k 2^(delta k) sum_l M~_k^l I_(n+k)^(m+l)
 // Classes with |delta| <= 1 (all pairs of a uniform tree, >95% of an
 // adaptive one) index a dense table; their operators are cached in the plan
 // across builds.  Pairs with |delta| >= 2 are nearly one class each and go
 // to the per-pair FP64 kernel instead.
 //
-// Batching: targets are grouped 64 at a time, one wave each (same level and octant,
+// Batching: targets are grouped 256 at a time (same level and octant,
 // Morton order, so neighbouring targets share their class sets).  A group's
 // entries are its distinct classes in class order, each with the source
 // cell of every target slot (-1 if absent).  The work queue applies each
@@ -27,7 +28,12 @@ namespace fmm {
 
 namespace {
 
-typedef float f16v __attribute__((ext_vector_type(16)));
+// bf16 bits of x, rounded to nearest even (finite inputs)
+__device__ inline uint32_t bf16_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ inline float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
 
 __device__ inline int dense_key(int delta, int rx, int ry, int rz) {
     if (delta < -1 || delta > 1) return -1;
@@ -75,8 +81,8 @@ __global__ void k_alloc_slots(const int32_t *__restrict__ used, int32_t nkeys, i
 // Build the FP32 operator fragments of each new class: one workgroup per
 // class.  Lane m computes column m of I_n^m (n <= 2p) in FP64.
 __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ new_keys, int32_t nnew,
-                                                   const int32_t *__restrict__ slot_of, int p, int RT, int KS4,
-                                                   int64_t fragsz, float *__restrict__ frags) {
+                                                   const int32_t *__restrict__ slot_of, int p, int RT,
+                                                   int64_t op_elems, uint16_t *__restrict__ ops) {
     __shared__ double Ire[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2], Iim[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2];
     int32_t j = blockIdx.x;
     if (j >= nnew) return;
@@ -126,16 +132,17 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
     }
     __syncthreads();
     const int P = ncoef(p);
-    // fragment order: float index ((rt * NQ + q) * 64 + lane) * 4 + u holds
-    // T[rt * 32 + lane % 32][(lane / 32) * KS4 + 4 q + u]  (NQ = KS4 / 4)
-    const int NQ = KS4 / 4;
-    float *out = frags + (int64_t)slot_of[k] * fragsz;
-    const int total = (int)fragsz;   // RT * KS4 * 64 used, the rest is zero padding
+    // Block order: block ((s RT + r) 2 + piece) of 64 lanes x 8 bf16; lane
+    // holds T[r 32 + lane % 32][16 s + 8 (lane / 32) + t], t < 8, piece 0 =
+    // bf16 rounding of the value, piece 1 = bf16 rounding of the remainder.
+    const int NK = 2 * RT;
+    uint16_t *out = ops + (int64_t)slot_of[k] * op_elems;
+    const int total = NK * RT * 64 * 8;  // values (each written as two pieces)
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
-        int u = f & 3, lane = (f >> 2) & 63, q = (f >> 8) % NQ, rt = (f >> 8) / NQ;
-        int row = rt * 32 + (lane & 31), col = (lane >> 5) * KS4 + 4 * q + u;
+        const int t = f & 7, lane = (f >> 3) & 63, r = (f >> 9) % RT, sk = (f >> 9) / RT;
+        const int row = r * 32 + (lane & 31), col = 16 * sk + 8 * (lane >> 5) + t;
         double v = 0.0;
-        if (f < RT * KS4 * 64 && row < P && col < P) {
+        if (row < P && col < P) {
             // output (n, m, part) and input (kk, l, part) of the real layouts
             int n = 0;
             while ((n + 1) * (n + 1) <= row) n++;
@@ -179,7 +186,11 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
             v *= ldexp(1.0, delta * kk);
             if (n & 1) v = -v;
         }
-        out[f] = (float)v;
+        const uint32_t hi = bf16_bits((float)v);
+        const uint32_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
+        const int64_t blk = (int64_t)(sk * RT + r) * 2;
+        out[((blk * 64) + lane) * 8 + t] = (uint16_t)hi;
+        out[(((blk + 1) * 64) + lane) * 8 + t] = (uint16_t)lo;
     }
 }
 
@@ -401,10 +412,10 @@ void m2l_alloc_slots(const int32_t *used, int32_t *slot_of, int32_t *nslots, int
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int KS4, int64_t fragsz,
-                   float *frags, hipStream_t s) {
+void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int64_t op_elems,
+                   uint16_t *ops, hipStream_t s) {
     if (nnew <= 0) return;
-    hipLaunchKernelGGL(k_build_ops, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, KS4, fragsz, frags);
+    hipLaunchKernelGGL(k_build_ops, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, op_elems, ops);
     FMM_LAUNCH_CHECK();
 }
 

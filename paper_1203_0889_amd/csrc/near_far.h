@@ -1,5 +1,5 @@
 // Internal interface of the mixed-precision near/far field stage: P2P tasks
-// (FP32 VALU) and class-batched M2L tasks (FP32 MFMA).
+// (FP32 VALU) and class-batched M2L tasks (split-bf16 MFMA, FP32 accumulation).
 #pragma once
 
 #include "../../include/fmm.h"

@@ -25,9 +25,8 @@ void read_sync(void *h, const void *d, size_t b, hipStream_t s) {
 void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     const int p = a.p;
     if (!queue_supported(p)) throw std::runtime_error("mixed precision supports p <= 12");
-    int RT, KS4;
-    queue_layout(p, &RT, &KS4);
-    const int64_t fragsz = queue_frag_floats(p);
+    const int RT = queue_row_tiles(p);
+    const int64_t op_elems = queue_op_elems(p);
     const int32_t ncell = a.ncell;
     const int64_t npair = a.nm2l;
     // ---- persistent class tables
@@ -62,8 +61,9 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     int32_t ns[2];
     read_sync(ns, st.nslots.ptr, 8, s);
     if (ns[0] > st.nslot_total) {
-        FMM_HIP_CHECK(st.frags.grow_keep((size_t)ns[0] * fragsz * 4, s));
-        m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, KS4, fragsz, st.frags.as<float>(), s);
+        FMM_HIP_CHECK(st.frags.grow_keep((size_t)ns[0] * op_elems * 2, s));
+        m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, op_elems,
+                      st.frags.as<uint16_t>(), s);
         st.nslot_total = ns[0];
     }
     // compact class ids in dense-key order
@@ -163,13 +163,11 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
 void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
     const int P = ncoef(a.p);
-    int RT, KS4;
-    queue_layout(a.p, &RT, &KS4);
     const int32_t ncell = a.ncell;
-    FMM_HIP_CHECK(st.M32.grow((size_t)(ncell + 1) * 2 * KS4 * 4));
+    FMM_HIP_CHECK(st.M32.grow((size_t)(ncell + 1) * queue_mrow_elems(a.p) * 2));
     FMM_HIP_CHECK(st.pf.grow((size_t)std::max<int64_t>(a.n, 1) * sizeof(float4)));
     FMM_HIP_CHECK(st.cnt.grow(64 * 4));
-    queue_pad_multipoles(a.M, ncell, a.p, st.M32.as<float>(), s);
+    queue_split_multipoles(a.M, ncell, a.p, st.M32.as<uint16_t>(), s);
     FMM_HIP_CHECK(hipMemsetAsync(a.L, 0, (size_t)ncell * P * 8, s));
     p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
     QueueArgs q;
@@ -180,8 +178,8 @@ void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     q.ecls = st.ecls.as<int32_t>();
     q.esrc = st.esrc.as<int32_t>();
     q.slot_of_cid = st.slot_of_cid.as<int32_t>();
-    q.frags = st.frags.as<float>();
-    q.M32 = st.M32.as<float>();
+    q.ops = st.frags.as<uint16_t>();
+    q.Mb = st.M32.as<uint16_t>();
     q.zero_row = ncell;
     q.L = a.L;
     q.P = P;

@@ -5,20 +5,20 @@
 
 namespace fmm {
 
-constexpr int kGroupM2L = 64;   // targets per M2L task group (one wave, two MFMA column tiles)
-constexpr int kMaxTaskEntries = 128;  // class entries per M2L task (the wave keeps two slots per lane)
+constexpr int kGroupM2L = 256;  // targets per M2L task group (4 waves x 64)
+constexpr int kMaxTaskEntries = 128;  // class entries per M2L task (a wave keeps two slots per lane)
 
 struct QueueArgs {
     CellArrays c;
     const double *centre;      // per cell geometric centre (x, y, z), FP64
     // M2L
     const int4 *m2l_tasks;     // (group, entry begin, entry end, 0)
-    const int32_t *gtarget;    // group x 128 target cells (-1 = empty slot)
+    const int32_t *gtarget;    // group x kGroupM2L target cells (-1 = empty slot)
     const int32_t *ecls;       // entry -> compact class id
-    const int32_t *esrc;       // entry x 128 source cells (-1 = absent)
+    const int32_t *esrc;       // entry x kGroupM2L source cells (-1 = absent)
     const int32_t *slot_of_cid;
-    const float *frags;        // class operators, MFMA fragment order
-    const float *M32;          // multipoles, FP32, row stride 2 * KS4 (zero padded),
+    const uint16_t *ops;       // class operators, split bf16 MFMA blocks (queue_op_elems per class)
+    const uint16_t *Mb;        // multipoles, split bf16 rows (queue_mrow_elems per cell),
                                //   plus one all-zero row at index zero_row
     int32_t zero_row;
     double *L;                 // FP64 local expansions (accumulated)
@@ -37,13 +37,18 @@ struct QueueArgs {
 };
 
 bool queue_supported(int p);
-// Row tiles of 32 and padded half-K (multiple of 4) of the MFMA layout.
-void queue_layout(int p, int *RT, int *KS4);
-// Floats per class operator in the fragment store (padded to whole
-// 256-thread float4 loads; the padding is zero).
-int64_t queue_frag_floats(int p);
-// M32 must hold (ncell + 1) rows of 2 * KS4 floats; row ncell is zero.
-void queue_pad_multipoles(const double *M, int32_t ncell, int p, float *M32, hipStream_t s);
+// Row tiles of 32 of the M2L operator; the contraction dimension is padded
+// to 32 RT as well (2 RT MFMA k-steps of 16).
+int queue_row_tiles(int p);
+// bf16 elements per class operator: 2 RT k-steps x RT row tiles x 2 pieces
+// (hi, lo) x 64 lanes x 8.
+int64_t queue_op_elems(int p);
+// bf16 elements per multipole row: 2 RT k-steps x 4 (hi, lo for each half
+// of the k-step) x 8.
+int64_t queue_mrow_elems(int p);
+// Split the FP64 multipoles into bf16 (hi, lo) rows; Mb must hold ncell + 1
+// rows, row ncell is written as zero.
+void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb, hipStream_t s);
 void queue_run(const QueueArgs &a, int p, int nworkgroups, hipStream_t s);
 
 }  // namespace fmm

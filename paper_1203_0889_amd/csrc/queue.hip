@@ -2,24 +2,29 @@
 //
 // The paper schedules M2L and P2P work as tasks of adjustable granularity
 // on a multicore runtime (Sec. 3, 4); here one persistent kernel plays that
-// role on the GPU.  Every wave is an independent worker: it claims tasks from
-// device-side lists with an atomic counter until the lists are exhausted.
-// There are no workgroup barriers, so waves of different task types share a
-// SIMD and the matrix cores (M2L) overlap the vector ALUs (P2P).
-//   * M2L task: a group of 64 target cells (same level and octant, Morton
-//     order) and a range of its class entries.  For each entry the wave runs
-//     v_mfma_f32_32x32x2_f32 with A = the class operator T_c (FP32,
-//     pre-swizzled fragments, one 1 KB line per wave load) and B = the
-//     multipoles of the class's sources, two 32-column tiles per operator
-//     fragment; operator and multipole loads run two k-steps ahead, across
-//     entries.  The targets' local expansions accumulate in FP32 AGPRs and
-//     are added into the FP64 locals at the end of the task.
-//   * P2P task: one target leaf.  Sources are staged in the wave's LDS tile
-//     as float4 relative to the target centre; a leaf of nt targets is
-//     covered by at most two passes of 2^b targets x 64/2^b source streams;
-//     streams are combined with cross-lane shuffles.
-// Lists are kept per XCD (spatially contiguous tasks, so the XCD's L2 holds
-// their operators and multipoles); a wave drains its XCD's lists, then steals.
+// role on the GPU.  Workgroups claim tasks from device-side lists with
+// atomic counters until the lists are exhausted.
+//   * M2L task (one workgroup): a group of 256 target cells (same level and
+//     octant, Morton order; 64 per wave) and a range of its class entries.
+//     For each entry the waves contract the class operator T_c with the
+//     multipoles of the class's sources on the matrix cores
+//     (v_mfma_f32_32x32x16_bf16).  Operator and multipoles are each split
+//     into two bf16 pieces x = x_hi + x_lo; three products (hi.hi, hi.lo,
+//     lo.hi) accumulate in FP32, which keeps about 16 significant bits of
+//     every product; the dropped lo.lo term is below 2^-16 of it.  The
+//     operator is staged through a three-deep LDS ring shared by the four
+//     waves (one barrier per two k-steps); multipoles stream from L2 two
+//     k-steps ahead.  The targets' local expansions accumulate in FP32 AGPRs
+//     and are added into the FP64 locals at the end of the task.
+//   * P2P task (one wave): one target leaf.  Sources are staged in the
+//     wave's LDS tile as float4 relative to the target centre; a leaf of nt
+//     targets is covered by at most two passes of 2^b targets x 64/2^b
+//     source streams; streams are combined with cross-lane shuffles.
+// Matrix-core and vector work of waves that share a SIMD do not overlap on
+// this chip, so the two task types simply share the machine.  Lists are kept
+// per XCD (spatially contiguous tasks, so the XCD's L2 holds their operators
+// and multipoles); a workgroup drains its XCD's lists, then steals.  Half
+// of the workgroups start with M2L tasks, half with P2P tasks.
 #include "queue.h"
 
 #include <algorithm>
@@ -229,38 +234,86 @@ __device__ void p2p_leaf(const QueueArgs &a, int32_t A, float4 *__restrict__ til
 }
 
 // ------------------------------------------------------------------ M2L
-// first multipole float4 of this lane's half-row of cell s (s < 0: zero row)
-__device__ inline const v4f *mrow(const QueueArgs &a, const v4f *m4, int32_t s, int ps4) {
-    return m4 + (int64_t)(s < 0 ? a.zero_row : s) * ps4;
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ inline bf8 as_bf8(v4f v) { return __builtin_bit_cast(bf8, v); }
+
+// LDS barrier that waits only for this wave's LDS traffic (global loads in
+// flight stay in flight).
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// One wave, kGroupM2L = 32 NB targets (NB column tiles of 32).  Lane
-// (col = lane % 32, kh = lane / 32) holds, per k-step q, operator element
-// T[r * 32 + col][kh * KS4 + 4 q + u] (4 u's in a float4, one per MFMA) and,
-// for tile b, multipole element M~_src(b * 32 + col)[kh * KS4 + 4 q + u].
-// Each operator fragment feeds NB MFMAs.  Entry metadata never sits on the
-// critical path: the operator slots of all the task's entries are loaded
-// once (lane l holds entries l and 64 + l, read back with readlane), and the
-// source cells of entry e + 2 are loaded while entry e runs.
-template <int RT, int KS4>
-__device__ void m2l_wave(const QueueArgs &a, int4 task, int lane) {
-    constexpr int NQ = KS4 / 4;                        // float4 k-steps per entry
-    constexpr int NB = kGroupM2L / 32;                 // column tiles
-    static_assert(NQ >= 2, "the load window needs two k-steps per entry");
-    constexpr int NF4P = ((RT * NQ * 64 + 255) / 256) * 256;  // padded float4 per class operator
+// one multipole k-step for a lane: bf16 pieces hi and lo of its 8 k values
+struct MStep {
+    v4f h, l;
+};
+
+// first float4 of this lane's k-half in multipole row s (s < 0: zero row)
+__device__ inline const v4f *mrow(const QueueArgs &a, const v4f *mb4, int32_t s, int nk) {
+    return mb4 + (int64_t)(s < 0 ? a.zero_row : s) * nk * 4;
+}
+
+__device__ inline MStep mload(const v4f *row, int step) {
+    MStep m;
+    m.h = row[step * 4];
+    m.l = row[step * 4 + 2];
+    return m;
+}
+
+template <int RT>
+constexpr int ring_f4() { return 3 * (2 * RT * 2) * 64; }  // three stages of 2 k-steps x RT tiles x 2 pieces
+
+// One M2L task by the whole workgroup.  Wave w owns target slots
+// [64 w, 64 w + 64) as two MFMA column tiles.  Lane (col = lane % 32,
+// kh = lane / 32) holds, per k-step s, operator values
+// T[r 32 + col][16 s + 8 kh + t] and multipole values M~_src[16 s + 8 kh + t],
+// t < 8, each as bf16 hi and lo pieces.
+//
+// Operator staging: the operator of an entry is 2 RT k-steps, grouped in
+// stages of two k-steps (4 RT blocks of 1 KB).  Stage J of the task sits in
+// ring buffer J % 3.  At the start of stage J every wave writes its quarter
+// of stage J + 1 (loaded into registers one stage earlier) and passes a
+// barrier; stage J itself was published by the previous barrier, and the
+// buffer written (J + 1) % 3 = (J - 2) % 3 was last read before it.
+template <int RT>
+__device__ void m2l_group(const QueueArgs &a, int4 task, int w, int lane, v4f *ring) {
+    constexpr int NK = 2 * RT;            // k-steps of 16 per entry
+    constexpr int SK = 2;                 // k-steps per stage
+    constexpr int NS = NK / SK;           // stages per entry (= RT)
+    constexpr int SB = SK * RT * 2;       // 1 KB blocks per stage
+    constexpr int OB = NK * RT * 2;       // blocks per class operator
+    constexpr int NB = 2;                 // column tiles per wave
     const int col = lane & 31, kh = lane >> 5;
-    const int PS4 = KS4 / 2;                           // float4 per padded multipole row
-    const v4f *frag4 = reinterpret_cast<const v4f *>(a.frags) + lane;
-    const v4f *m4 = reinterpret_cast<const v4f *>(a.M32) + kh * NQ;
-    const int32_t *gsrc = a.esrc + col;
-    const int32_t e0 = task.y, ne = task.z - task.y;   // wave-uniform
-    // operator slots of the task's entries
+    const v4f *ops4 = reinterpret_cast<const v4f *>(a.ops) + lane;
+    const v4f *mb4 = reinterpret_cast<const v4f *>(a.Mb) + kh;
+    const int32_t *gsrc = a.esrc + w * 64 + col;
+    const int32_t e0 = task.y, ne = task.z - task.y;   // workgroup-uniform
     int32_t slot_lo = 0, slot_hi = 0;
     if (lane < ne) slot_lo = a.slot_of_cid[a.ecls[e0 + lane]];
     if (64 + lane < ne) slot_hi = a.slot_of_cid[a.ecls[e0 + 64 + lane]];
     auto slot = [&](int i) {
         return i < 64 ? __builtin_amdgcn_readlane(slot_lo, i) : __builtin_amdgcn_readlane(slot_hi, i - 64);
     };
+    // this wave's blocks of stage J: w + 4 q, q < RT
+    auto stage_src = [&](int J) {
+        const int i = J / NS, g = J - i * NS;
+        return ops4 + ((int64_t)slot(i) * OB + g * SB + w) * 64;
+    };
+    const int nstage = ne * NS;
+    v4f stg[RT];
+    {
+        const v4f *src = stage_src(0);
+#pragma unroll
+        for (int q = 0; q < RT; q++) ring[(w + 4 * q) * 64 + lane] = src[4 * q * 64];
+        if (nstage > 1) {
+            src = stage_src(1);
+#pragma unroll
+            for (int q = 0; q < RT; q++) stg[q] = src[4 * q * 64];
+        }
+    }
     f16v acc[RT][NB];
 #pragma unroll
     for (int r = 0; r < RT; r++)
@@ -268,85 +321,85 @@ __device__ void m2l_wave(const QueueArgs &a, int4 task, int lane) {
         for (int b = 0; b < NB; b++)
 #pragma unroll
             for (int i = 0; i < 16; i++) acc[r][b][i] = 0.f;
-    const v4f *T = frag4 + (int64_t)slot(0) * NF4P;
-    const v4f *R[NB];
-    int32_t sn[NB];                                    // source cells of entry i + 1
+    // multipole rows of the current and the next entry; sources of entry + 2
+    const v4f *R[NB], *nR[NB];
+    int32_t sn[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        R[b] = mrow(a, m4, gsrc[(int64_t)e0 * kGroupM2L + b * 32], PS4);
+        R[b] = mrow(a, mb4, gsrc[(int64_t)e0 * kGroupM2L + b * 32], NK);
+        nR[b] = R[b];
         sn[b] = ne > 1 ? gsrc[(int64_t)(e0 + 1) * kGroupM2L + b * 32] : -1;
     }
-    // two-step window: A fragments (RT row tiles) and B fragments (NB
-    // column tiles) of steps q and q + 1
-    v4f a0[RT], a1[RT], b0[NB], b1[NB];
-#pragma unroll
-    for (int r = 0; r < RT; r++) {
-        a0[r] = T[(r * NQ) * 64];
-        a1[r] = T[(r * NQ + 1) * 64];
-    }
+    // two-step multipole window
+    MStep m0[NB], m1[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        b0[b] = R[b][0];
-        b1[b] = R[b][1];
+        m0[b] = mload(R[b], 0);
+        m1[b] = mload(R[b], 1);
     }
-    for (int i = 0; i < ne; i++) {
-        const bool more = i + 1 < ne;
-        const v4f *nT = T;
-        const v4f *nR[NB];
+    for (int J = 0; J < nstage; J++) {
+        const int i = J / NS, g = J - i * NS;
+        if (J + 1 < nstage) {
+            v4f *dst = ring + ((J + 1) % 3) * SB * 64;
 #pragma unroll
-        for (int b = 0; b < NB; b++) nR[b] = R[b];
-        if (more) {
-            nT = frag4 + (int64_t)slot(i + 1) * NF4P;
+            for (int q = 0; q < RT; q++) dst[(w + 4 * q) * 64 + lane] = stg[q];
+        }
+        lds_barrier();
+        if (J + 2 < nstage) {
+            const v4f *src = stage_src(J + 2);
+#pragma unroll
+            for (int q = 0; q < RT; q++) stg[q] = src[4 * q * 64];
+        }
+        const bool more = i + 1 < ne;
+        if (g == 0 && more) {
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                nR[b] = mrow(a, m4, sn[b], PS4);
+                nR[b] = mrow(a, mb4, sn[b], NK);
                 sn[b] = i + 2 < ne ? gsrc[(int64_t)(e0 + i + 2) * kGroupM2L + b * 32] : -1;
             }
         }
+        const v4f *rb = ring + (J % 3) * SB * 64 + lane;
 #pragma unroll
-        for (int q = 0; q < NQ; q++) {
-            v4f ca[RT], cb[NB];
-#pragma unroll
-            for (int r = 0; r < RT; r++) {
-                ca[r] = a0[r];
-                a0[r] = a1[r];
-            }
+        for (int t = 0; t < SK; t++) {
+            const int s = g * SK + t;
+            MStep cm[NB];
 #pragma unroll
             for (int b = 0; b < NB; b++) {
-                cb[b] = b0[b];
-                b0[b] = b1[b];
+                cm[b] = m0[b];
+                m0[b] = m1[b];
             }
-            if (q + 2 < NQ) {
+            if (s + 2 < NK) {
 #pragma unroll
-                for (int b = 0; b < NB; b++) b1[b] = R[b][q + 2];
-#pragma unroll
-                for (int r = 0; r < RT; r++) a1[r] = T[(r * NQ + q + 2) * 64];
+                for (int b = 0; b < NB; b++) m1[b] = mload(R[b], s + 2);
             } else if (more) {
 #pragma unroll
-                for (int b = 0; b < NB; b++) b1[b] = nR[b][q + 2 - NQ];
-#pragma unroll
-                for (int r = 0; r < RT; r++) a1[r] = nT[(r * NQ + q + 2 - NQ) * 64];
+                for (int b = 0; b < NB; b++) m1[b] = mload(nR[b], s + 2 - NK);
             }
-            // keep the loads of step q + 2 ahead of the MFMAs of step q (the
-            // scheduler would otherwise sink them to their uses)
+            // keep the multipole loads ahead of this step's MFMAs
             __builtin_amdgcn_sched_barrier(0);
+            v4f ah[RT], al[RT];
+#pragma unroll
+            for (int r = 0; r < RT; r++) {
+                ah[r] = rb[((t * RT + r) * 2) * 64];
+                al[r] = rb[((t * RT + r) * 2 + 1) * 64];
+            }
 #pragma unroll
             for (int r = 0; r < RT; r++)
 #pragma unroll
                 for (int b = 0; b < NB; b++) {
-                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[r].x, cb[b].x, acc[r][b], 0, 0, 0);
-                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[r].y, cb[b].y, acc[r][b], 0, 0, 0);
-                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[r].z, cb[b].z, acc[r][b], 0, 0, 0);
-                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ca[r].w, cb[b].w, acc[r][b], 0, 0, 0);
+                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(al[r]), as_bf8(cm[b].h), acc[r][b], 0, 0, 0);
+                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(ah[r]), as_bf8(cm[b].l), acc[r][b], 0, 0, 0);
+                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(ah[r]), as_bf8(cm[b].h), acc[r][b], 0, 0, 0);
                 }
         }
-        T = nT;
+        if (g == NS - 1) {
 #pragma unroll
-        for (int b = 0; b < NB; b++) R[b] = nR[b];
+            for (int b = 0; b < NB; b++) R[b] = nR[b];
+        }
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const int32_t A = a.gtarget[(int64_t)task.x * kGroupM2L + b * 32 + col];
+        const int32_t A = a.gtarget[(int64_t)task.x * kGroupM2L + w * 64 + b * 32 + col];
         if (A < 0) continue;
         double *Lc = a.L + (int64_t)A * a.P;
 #pragma unroll
@@ -360,38 +413,77 @@ __device__ void m2l_wave(const QueueArgs &a, int4 task, int lane) {
 }
 
 // ------------------------------------------------------------------ queue
-template <int RT, int KS4>
+template <int RT>
+constexpr int queue_lds_f4() { return ring_f4<RT>() > 4 * kP2PTile ? ring_f4<RT>() : 4 * kP2PTile; }
+
+template <int RT>
 __global__ void __launch_bounds__(256) k_queue(QueueArgs a) {
-    __shared__ float4 lds[4 * kP2PTile];
+    __shared__ v4f lds[queue_lds_f4<RT>()];
+    __shared__ int32_t claim;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    // Workgroups go round-robin over the 8 XCDs.  Waves drain their own
-    // XCD's lists first, then steal from other XCDs.  The task type a wave
-    // starts with alternates with its wave slot on the SIMD (HW_ID bits 3:0),
-    // so the waves sharing a SIMD mix matrix-core and vector work.
+    // Workgroups go round-robin over the 8 XCDs.  The workgroup slot on
+    // its compute unit (HW_ID bits 19:16) picks the task type it starts
+    // with, so the workgroups sharing a compute unit mix the two types.
     const int x = blockIdx.x & 7;
-    const int role = __builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (3 << 11)) & 1;
-    float4 *tile = lds + w * kP2PTile;
-    for (int k = 0; k < 16; k++) {
-        const int L = (((x + (k >> 1)) & 7) << 1) | ((k & 1) ^ role);
-        const int4 li = a.lists[L];
-        for (;;) {
-            int32_t t = 0;
-            if (lane == 0) t = atomicAdd(&a.heads[L], 1);
-            t = __builtin_amdgcn_readfirstlane(t);      // lane 0's claim, wave-uniform
-            if (t >= li.y) break;
-            if ((L & 1) == 0) m2l_wave<RT, KS4>(a, a.m2l_tasks[li.x + t], lane);
-            else p2p_leaf(a, a.leaves[li.z + t], tile, lane);
+    const int role = __builtin_amdgcn_s_getreg((4 << 0) | (16 << 6) | (3 << 11)) & 1;
+    for (int ph = 0; ph < 2; ph++) {
+        if ((ph ^ role) == 0) {
+            for (int k = 0; k < 8; k++) {
+                const int L = ((x + k) & 7) << 1;
+                const int4 li = a.lists[L];
+                for (;;) {
+                    __syncthreads();
+                    if (threadIdx.x == 0) claim = atomicAdd(&a.heads[L], 1);
+                    __syncthreads();
+                    const int32_t t = __builtin_amdgcn_readfirstlane(claim);
+                    if (t >= li.y) break;
+                    m2l_group<RT>(a, a.m2l_tasks[li.x + t], w, lane, lds);
+                }
+            }
+        } else {
+            float4 *tile = reinterpret_cast<float4 *>(lds) + w * kP2PTile;
+            for (int k = 0; k < 8; k++) {
+                const int L = (((x + k) & 7) << 1) | 1;
+                const int4 li = a.lists[L];
+                for (;;) {
+                    int32_t t = 0;
+                    if (lane == 0) t = atomicAdd(&a.heads[L], 1);
+                    t = __builtin_amdgcn_readfirstlane(t);      // lane 0's claim, wave-uniform
+                    if (t >= li.y) break;
+                    p2p_leaf(a, a.leaves[li.z + t], tile, lane);
+                }
+            }
         }
+        __syncthreads();   // the LDS changes role
     }
 }
 
 // ------------------------------------------------------------------ prep
-__global__ void k_pad_f32(const double *__restrict__ in, int32_t ncell, int P, int PS, float *__restrict__ out) {
-    int64_t n = (int64_t)(ncell + 1) * PS;  // row ncell stays zero (absent sources)
+__device__ inline uint32_t bf16_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ inline float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Row c, k-step s, quarter q (0: hi of k-half 0, 1: hi of k-half 1, 2: lo
+// of k-half 0, 3: lo of k-half 1) holds 8 bf16 of k = 16 s + 8 (q & 1) + t.
+__global__ void k_split_multipoles(const double *__restrict__ M, int32_t ncell, int P, int NK,
+                                   uint4 *__restrict__ Mb) {
+    const int64_t n = (int64_t)(ncell + 1) * NK * 4;  // row ncell stays zero (absent sources)
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t c = i / PS;
-        int j = (int)(i - c * PS);
-        out[i] = (j < P && c < ncell) ? (float)in[c * P + j] : 0.f;
+        const int q = (int)(i & 3);
+        const int64_t cs = i >> 2;
+        const int64_t c = cs / NK;
+        const int sk = (int)(cs - c * NK);
+        uint32_t h[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int k = 16 * sk + 8 * (q & 1) + t;
+            const double v = (c < ncell && k < P) ? M[c * P + k] : 0.0;
+            const uint32_t hi = bf16_bits((float)v);
+            h[t] = (q & 2) ? bf16_bits((float)(v - (double)bf16_value(hi))) : hi;
+        }
+        Mb[i] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
     }
 }
 
@@ -399,39 +491,33 @@ __global__ void k_pad_f32(const double *__restrict__ in, int32_t ncell, int P, i
 
 bool queue_supported(int p) { return p >= 0 && p <= 12; }
 
-void queue_layout(int p, int *RT, int *KS4) {
-    const int P = ncoef(p);
-    *RT = (P + 31) / 32;
-    // at least two float4 k-steps per entry: the M2L load window spans two
-    *KS4 = std::max(8, (((P + 1) / 2 + 3) / 4) * 4);
+int queue_row_tiles(int p) { return (ncoef(p) + 31) / 32; }
+
+int64_t queue_op_elems(int p) {
+    const int RT = queue_row_tiles(p);
+    return (int64_t)(2 * RT) * RT * 2 * 64 * 8;
 }
 
-int64_t queue_frag_floats(int p) {
-    int RT, KS4;
-    queue_layout(p, &RT, &KS4);
-    int64_t per = ((int64_t)RT * (KS4 / 4) * 64 + 255) / 256;
-    return per * 256 * 4;
-}
+int64_t queue_mrow_elems(int p) { return (int64_t)(2 * queue_row_tiles(p)) * 4 * 8; }
 
-void queue_pad_multipoles(const double *M, int32_t ncell, int p, float *M32, hipStream_t s) {
-    int RT, KS4;
-    queue_layout(p, &RT, &KS4);
-    int64_t n = (int64_t)(ncell + 1) * 2 * KS4;
-    hipLaunchKernelGGL(k_pad_f32, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, M, ncell, ncoef(p), 2 * KS4, M32);
+void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb, hipStream_t s) {
+    const int NK = 2 * queue_row_tiles(p);
+    const int64_t n = (int64_t)(ncell + 1) * NK * 4;
+    hipLaunchKernelGGL(k_split_multipoles, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, M, ncell, ncoef(p), NK,
+                       reinterpret_cast<uint4 *>(Mb));
     FMM_LAUNCH_CHECK();
 }
 
 void queue_run(const QueueArgs &a, int p, int nworkgroups, hipStream_t s) {
     FMM_HIP_CHECK(hipMemsetAsync(a.heads, 0, 16 * sizeof(int32_t), s));
     dim3 grid(nworkgroups), block(256);
-#define FMM_Q(PP, R, K)                                                   \
+#define FMM_Q(PP, R)                                                      \
     case PP:                                                              \
-        hipLaunchKernelGGL((k_queue<R, K>), grid, block, 0, s, a);        \
+        hipLaunchKernelGGL((k_queue<R>), grid, block, 0, s, a);           \
         break;
     switch (p) {
-        FMM_Q(0, 1, 8) FMM_Q(1, 1, 8) FMM_Q(2, 1, 8) FMM_Q(3, 1, 8) FMM_Q(4, 1, 16) FMM_Q(5, 2, 20)
-        FMM_Q(6, 2, 28) FMM_Q(7, 2, 32) FMM_Q(8, 3, 44) FMM_Q(9, 4, 52) FMM_Q(10, 4, 64) FMM_Q(11, 5, 72)
-        FMM_Q(12, 6, 88)
+        FMM_Q(0, 1) FMM_Q(1, 1) FMM_Q(2, 1) FMM_Q(3, 1) FMM_Q(4, 1) FMM_Q(5, 2) FMM_Q(6, 2) FMM_Q(7, 2) FMM_Q(8, 3)
+        FMM_Q(9, 4) FMM_Q(10, 4) FMM_Q(11, 5) FMM_Q(12, 6)
         default: throw HipError{hipErrorInvalidValue, "queue: unsupported order"};
     }
 #undef FMM_Q
