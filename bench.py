@@ -23,8 +23,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X published peaks
-PEAK = {"fp32_valu": 157.3e12, "fp32_mfma": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
+PEAK = {"fp32_valu": 157.3e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "fp64": 78.6e12, "hbm": 8.0e12}
 P2P_FLOP = 20          # per particle pair: potential + field, one reciprocal square root counted once
+M2L_SPLIT_PRODUCTS = 3  # bf16 products per FP32-accurate product in the mixed M2L (hi.hi, hi.lo, lo.hi)
+QUEUE_SOURCES = ("paper_1203_0889_amd/csrc/queue.hip", "paper_1203_0889_amd/csrc/queue.h")
+TRAFFIC_PROFILE = "profiles/k_queue_uniform1m_p8_traffic.txt"
+
+
+def source_hash(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(workload):
+    """HBM bytes per queue launch from the committed PMC summary, if it was
+    taken on this workload and on the current queue kernel source."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("workload") != workload or fields.get("source_sha256_16") != source_hash(QUEUE_SOURCES):
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def m2l_flop(p):
@@ -40,7 +72,7 @@ def parse():
     ap.add_argument("--workload", default="uniform1m_p8")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-n", type=int, default=131072, help="particles in the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=524288, help="particles in the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -123,11 +155,18 @@ def main():
     t_p2p = stage_avg.get("p2p", 0.0) * 1e-3
     t_m2l = stage_avg.get("m2l", 0.0) * 1e-3
     if a.precision == "mixed":
-        # M2L and P2P run fused in one work-queue launch: the stage time covers both
-        tq = t_m2l
+        # M2L and P2P run in one work-queue launch (stage "queue", HIP events
+        # on the plan's stream).  Its ALU bound: P2P on the FP32 vector units
+        # plus M2L on the bf16 matrix cores at three products per FP32-accurate
+        # product; the two do not issue concurrently on a SIMD, so their
+        # minimum times add.
+        tq = stage_avg.get("queue", 0.0) * 1e-3
+        t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
+        traffic = committed_traffic(a.workload)
         roof = {"bound": "alu", "achieved": (p2p_flop + m2l_f) / tq / 1e12 if tq > 0 else None,
-                "peak": PEAK["fp32_valu"] / 1e12, "unit": "TFLOP/s", "traffic": None,
-                "kernel": "near_far work queue (P2P FP32 VALU + M2L FP32 MFMA)"}
+                "peak": (p2p_flop + m2l_f) / t_min / 1e12, "unit": "TFLOP/s", "traffic": traffic,
+                "kernel": "k_queue (P2P FP32 VALU + M2L split-bf16 MFMA)", "kernel_ms": tq * 1e3,
+                "peak_basis": "P2P flop / 157.3 TF fp32 vector + 3 x M2L flop / 2.5 PF bf16 dense MFMA"}
     else:
         dom, t, f = ("p2p", t_p2p, p2p_flop) if t_p2p >= t_m2l else ("m2l", t_m2l, m2l_f)
         roof = {"bound": "alu", "achieved": f / t / 1e12 if t > 0 else None, "peak": PEAK["fp64"] / 1e12,

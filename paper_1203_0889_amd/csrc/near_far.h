@@ -36,8 +36,12 @@ struct NearFarState {
 fmm_tuning default_tuning();
 // Build-time part (after the lists): classes, operators, groups, tasks.
 void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s);
-// Evaluate-time part: M2L (MFMA + per-pair remainder) and P2P.
-void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+// Evaluate-time part, in stream order: inputs of the queue (bf16 multipoles,
+// FP32 particles, zeroed locals), the work-queue kernel (M2L and P2P tasks),
+// then the per-pair FP64 M2L of the pairs outside the class table.
+void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 void release_near_far(NearFarState &st);
 
 }  // namespace fmm

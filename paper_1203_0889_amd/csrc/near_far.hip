@@ -160,7 +160,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     st.built = true;
 }
 
-void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
     const int P = ncoef(a.p);
     const int32_t ncell = a.ncell;
@@ -170,6 +170,11 @@ void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     queue_split_multipoles(a.M, ncell, a.p, st.M32.as<uint16_t>(), s);
     FMM_HIP_CHECK(hipMemsetAsync(a.L, 0, (size_t)ncell * P * 8, s));
     p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
+}
+
+void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    const int P = ncoef(a.p);
+    const int32_t ncell = a.ncell;
     QueueArgs q;
     q.c = a.g.c;
     q.centre = st.centre.as<double>();
@@ -197,7 +202,11 @@ void run_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     FMM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
     queue_run(q, a.p, ncu * per_cu, s);
-    if (st.nextra > 0) launch_m2l_fp64_add(a.g, ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, s);
+}
+
+void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    if (st.nextra > 0)
+        launch_m2l_fp64_add(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, s);
 }
 
 void release_near_far(NearFarState &st) {

@@ -60,10 +60,13 @@ enum { kStateCreated = 0, kStateBuilt = 1, kStateUp = 2, kStateEval = 3 };
 
 enum Stage {
     ST_BOX = 0, ST_SORT, ST_TREE, ST_LISTS, ST_CSR, ST_P2M, ST_M2M, ST_M2L, ST_P2P, ST_L2L, ST_L2P, ST_OUT,
-    ST_COUNT
+    ST_NF_PREP, ST_QUEUE, ST_M2L_REST, ST_COUNT
 };
+// FP64 path: m2l, p2p.  Mixed path: nf_prep (bf16 multipoles, FP32
+// particles, zeroed locals), queue (the work-queue kernel: M2L and P2P
+// tasks), m2l_rest (per-pair FP64 M2L of the pairs outside the class table).
 static const char *kStageNames[16] = {"bbox_keys", "sort", "tree", "traverse", "csr", "p2m", "m2m", "m2l", "p2p",
-                                      "l2l", "l2p", "output", "", "", "", ""};
+                                      "l2l", "l2p", "output", "nf_prep", "queue", "m2l_rest", ""};
 
 struct fmm_plan {
     fmm_params prm;
@@ -408,9 +411,12 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         mark(p, ST_P2P);
     } else {
         fmm::NearFarArgs a = nf_args(p);
-        fmm::run_near_far_mixed(p->nf, a, s);
-        mark(p, ST_M2L);
-        mark(p, ST_P2P);
+        fmm::near_far_prepare(p->nf, a, s);
+        mark(p, ST_NF_PREP);
+        fmm::near_far_queue(p->nf, a, s);
+        mark(p, ST_QUEUE);
+        fmm::near_far_rest(p->nf, a, s);
+        mark(p, ST_M2L_REST);
     }
     int depth = (int)p->level_begin.size() - 1;
     for (int l = 0; l + 1 < depth; l++)  // parents of level l push to level l + 1
