@@ -49,14 +49,22 @@ typedef enum {
 
 typedef enum {
     FMM_PREC_FP64 = 0,  /* every stage in FP64 (the plain GPU path) */
-    FMM_PREC_MIXED = 1  /* P2P on FP32 VALU, M2L on FP32 MFMA with FP32
-                           accumulation; tree, P2M, M2M, L2L, L2P and the
+    FMM_PREC_MIXED = 1  /* P2P on FP32 VALU; M2L on bf16 MFMA with split
+                           operands (x = x_hi + x_lo, three products, FP32
+                           accumulation); tree, P2M, M2M, L2L, L2P and the
                            per-particle / per-cell accumulation in FP64 */
 } fmm_precision;
 
 enum {
-    FMM_FLAG_USER_BOX = 1u << 0 /* use params.box_min / box_side for every
-                                   instance instead of the tight bounding cube */
+    FMM_FLAG_USER_BOX = 1u << 0,     /* use params.box_min / box_side for every
+                                        instance instead of the tight bounding cube */
+    FMM_FLAG_KEEP_TOPOLOGY = 1u << 1 /* a later fmm_build_tree with the same n_inst
+                                        and offsets keeps the box, keys, tree and
+                                        lists of the previous build and only takes
+                                        the new positions and charges (gathered by
+                                        the stored sort permutation): a frozen
+                                        topology, as finite-difference checks of
+                                        the adjoint need */
 };
 
 typedef struct {
@@ -116,11 +124,20 @@ fmm_status fmm_upward(fmm_plan *plan);
 fmm_status fmm_evaluate(fmm_plan *plan, double *phi, double *field, double *force, double *energy);
 
 /*
- * Adjoint: gradient of the FMM total energy, sum_k g_k E_k, with respect to
- * positions and charges.  Requires fmm_evaluate on the same plan.
+ * Adjoint: gradient of the FMM total energy, sum_k g_k E_k with
+ * E_k = 1/2 q_k^T A q_k, with respect to positions and charges, where A is
+ * the matrix the FMM applies (P2M, M2M, M2L, L2L, L2P and P2P over the built
+ * lists; not symmetric, since M2L is non-mutual, Sec. 4).  Computed exactly
+ * for that A, in the plan's precision: with w = g q and psi = A^T w (a
+ * transposed evaluation: L2P^T, L2L^T, M2L^T, P2P^T, M2M^T, P2M^T),
+ *   grad_q_i   = (g_i phi_i + psi_i) / 2
+ *   grad_pos_i = -q_i (g_i E_i + E^psi_i) / 2,   E^psi = -grad psi.
+ * The box and cell geometry are held fixed (the topology of the build).
+ * Requires fmm_evaluate on the same plan; its first call after a build also
+ * builds the transposed lists.
  *   grad_energy  device FP64 (n_inst) upstream weights g_k
- *   grad_pos     device FP64 (N, 3)  (NULL skips)
- *   grad_q       device FP64 (N)     (NULL skips)
+ *   grad_pos     device FP64 (N, 3), input order (NULL skips)
+ *   grad_q       device FP64 (N), input order (NULL skips)
  */
 fmm_status fmm_backward(fmm_plan *plan, const double *grad_energy, double *grad_pos, double *grad_q);
 

@@ -6,10 +6,13 @@ include/fmm.h); `fmm` is its Python binding, `autograd` the
 torch.autograd.Function around it, `workloads` the seeded input generators.
 """
 
-__all__ = ["Plan", "evaluate", "load_library"]
+__all__ = ["Plan", "evaluate", "load_library", "FMMEnergy", "fmm_energy"]
 
 
 def __getattr__(name):
+    if name in ("FMMEnergy", "fmm_energy"):
+        from . import autograd as _ag
+        return getattr(_ag, name)
     if name in __all__:
         from . import fmm as _fmm
         return getattr(_fmm, name)

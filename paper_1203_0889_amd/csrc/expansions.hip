@@ -314,6 +314,63 @@ __global__ void k_l2p(Geometry g, int64_t n, int p, const int32_t *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------- adjoint
+// P2M stores C_k(u) = (Re R_n^m(u), -Im R_n^m(u)) per unit charge, and L2P
+// evaluates phi = sum_k L_k B_k(u) with B_k = (s_k / S) C_k, s_k = 1 for
+// m = 0, 2 for Re and -2 for Im of m > 0 (the +-m terms of a real field).
+// Hence the transposed stages reuse those kernels with a diagonal scaling:
+//   L2P^T(w) = diag(s_k / S) P2M(w),   P2M^T(mu) = L2P(diag(S / s_k) mu).
+// dir = 0 multiplies leaf rows by s_k / S, dir = 1 by S / s_k.
+__global__ void k_dual_scale(Geometry g, int32_t ncell, int p, double *__restrict__ X, int dir) {
+    const int P = ncoef(p);
+    const int64_t total = (int64_t)ncell * P;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t cell = (int32_t)(i / P);
+        if (g.c.child[cell] >= 0) continue;
+        const int k = (int)(i - (int64_t)cell * P);
+        int n = 0;
+        while ((n + 1) * (n + 1) <= k) n++;
+        const int off = k - n * n;
+        const double sk = off == 0 ? 1.0 : ((off & 1) ? 2.0 : -2.0);
+        const int l = g.c.level[cell];
+        const double S = ldexp(g.box[4 * g.c.inst[cell] + 3], -l);
+        X[i] *= dir == 0 ? sk / S : S / sk;
+    }
+}
+
+// Adjoint weights w_i = g_(instance of i) q_i (sorted order).
+__global__ void k_adjoint_weights(int64_t n, const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ inst,
+                                  const double *__restrict__ gE, const double *__restrict__ qs, double *__restrict__ w) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = gE[inst[leaf_of[i]]] * qs[i];
+}
+
+// E = sum_k g_k 1/2 q^T A q per instance, A the FMM's (non-symmetric) matrix:
+//   dE/dq_i = 1/2 g q-phi term + 1/2 (A^T w)_i   = 1/2 (g_i phi_i + psi_i)
+//   dE/dx_i = 1/2 g_i q_i grad phi(x_i) + 1/2 q_i grad psi(x_i)
+//           = -1/2 q_i (g_i E_i + E^psi_i),
+// with psi = A^T w (w = g q) and E^psi = -grad psi, both from the transposed
+// evaluation.  Written in input order.
+__global__ void k_adjoint_finalize(int64_t n, const uint32_t *__restrict__ perm, const int32_t *__restrict__ leaf_of,
+                                   const int32_t *__restrict__ inst, const double *__restrict__ gE,
+                                   const double *__restrict__ qs, const double *__restrict__ pn,
+                                   const double *__restrict__ fn, const double *__restrict__ pf,
+                                   const double *__restrict__ ff, const double *__restrict__ sn,
+                                   const double *__restrict__ en, const double *__restrict__ sf,
+                                   const double *__restrict__ ef, double *__restrict__ grad_pos,
+                                   double *__restrict__ grad_q) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double g = gE[inst[leaf_of[i]]];
+        const int64_t o = perm[i];
+        if (grad_q) grad_q[o] = 0.5 * (g * (pn[i] + pf[i]) + (sn[i] + sf[i]));
+        if (grad_pos) {
+            const double hq = -0.5 * qs[i];
+            for (int d = 0; d < 3; d++)
+                grad_pos[3 * o + d] = hq * (g * (fn[3 * i + d] + ff[3 * i + d]) + (en[3 * i + d] + ef[3 * i + d]));
+        }
+    }
+}
+
 __global__ void k_finalize(int64_t n, const uint32_t *__restrict__ perm, const double *__restrict__ qs,
                            const double *__restrict__ pn, const double *__restrict__ fn, const double *__restrict__ pf,
                            const double *__restrict__ ff, double *__restrict__ phi, double *__restrict__ field,
@@ -509,6 +566,42 @@ void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const do
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, n, perm, qs, phi_near, fld_near,
                        phi_far, fld_far, phi, field, force);
     FMM_LAUNCH_CHECK();
+}
+
+void launch_dual_scale(Geometry g, int32_t ncell, int p, double *X, int dir, hipStream_t s) {
+    const int64_t total = (int64_t)ncell * ncoef(p);
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_dual_scale, dim3(grid_for(total, 256, 16384)), dim3(256), 0, s, g, ncell, p, X, dir);
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_adjoint_weights(Geometry g, int64_t n, const int32_t *leaf_of, const double *gE, const double *qs,
+                            double *w, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_adjoint_weights, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, n, leaf_of, g.c.inst, gE, qs,
+                       w);
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_adjoint_finalize(Geometry g, int64_t n, const uint32_t *perm, const int32_t *leaf_of, const double *gE,
+                             const double *qs, const double *phi_near, const double *fld_near, const double *phi_far,
+                             const double *fld_far, const double *psi_near, const double *epsi_near,
+                             const double *psi_far, const double *epsi_far, double *grad_pos, double *grad_q,
+                             hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_adjoint_finalize, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, n, perm, leaf_of, g.c.inst,
+                       gE, qs, phi_near, fld_near, phi_far, fld_far, psi_near, epsi_near, psi_far, epsi_far, grad_pos,
+                       grad_q);
+    FMM_LAUNCH_CHECK();
+}
+
+std::vector<double> transpose_ops(const std::vector<double> &ops, int p) {
+    const int P = ncoef(p);
+    std::vector<double> t(ops.size());
+    for (int o = 0; o < 8; o++)
+        for (int r = 0; r < P; r++)
+            for (int c = 0; c < P; c++) t[(size_t)o * P * P + (size_t)c * P + r] = ops[(size_t)o * P * P + (size_t)r * P + c];
+    return t;
 }
 
 std::vector<int32_t> energy_chunks(const std::vector<int64_t> &offsets) {

@@ -212,7 +212,151 @@ __global__ void __launch_bounds__(kM2L64Threads)
     }
 }
 
+// ---------------------------------------------------------------- M2L adjoint
+// One wave per source cell B, walking the pairs (A <- B) of the forward list
+// (the transposed CSR).  The forward map on the stored real coefficients is
+//   S_n^m = sum_k c_nk sum_(l=-k..k) M~_k^l I_(n+k)^(m+l),  c_nk = (-1)^n 2^(delta k),
+// with L_re(n, m) = Re S_n^m and L_im(n, m) = Im S_n^m (m > 0).  Writing the
+// dual of L as U_n^m = u_re + i u_im (U_n^0 real), the real inner product
+// <u, S(M)> equals <v, M> for
+//   V_k^l = sum_(n, m >= 0) c_nk [U_n^m conj(I_(n+k)^(m+l)) + (-1)^l conj(U_n^m) I_(n+k)^(m-l)]
+// (l > 0; v_re = Re V, v_im = Im V) and v_re(k, 0) = Re V_k^0 / 2 (the two
+// terms coincide for l = 0, where M~_k^0 is real).
+__global__ void __launch_bounds__(kM2L64Threads)
+    k_m2l_fp64_adjoint(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr,
+                       const int32_t *__restrict__ src, const double *__restrict__ Lam, double *__restrict__ Mu,
+                       int add) {
+    __shared__ double Ire[kMaxI], Iim[kMaxI];
+    __shared__ double Us[ncoef(kMaxP)];
+    int32_t B = blockIdx.x;
+    if (B >= ncell) return;
+    if (add && ptr[B] == ptr[B + 1]) return;
+    const int lane = threadIdx.x;
+    const int P = ncoef(p);
+    const int NC = (p + 1) * (p + 2) / 2;
+    int ok_[3], ol_[3];
+    double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
+    for (int s = 0; s < 3; s++) {
+        int j = lane + 64 * s;
+        ok_[s] = -1;
+        ol_[s] = 0;
+        if (j < NC) {
+            int n = 0;
+            while ((n + 1) * (n + 2) / 2 <= j) n++;
+            ok_[s] = n;
+            ol_[s] = j - n * (n + 1) / 2;
+        }
+    }
+    const int lb = c.level[B];
+    const int64_t SB = (int64_t)1 << (kLevels - lb);
+    const int64_t cbx = (2 * (int64_t)c.ix[B] + 1) * SB, cby = (2 * (int64_t)c.iy[B] + 1) * SB,
+                  cbz = (2 * (int64_t)c.iz[B] + 1) * SB;
+    for (int32_t e = ptr[B]; e < ptr[B + 1]; e++) {
+        const int32_t A = src[e];
+        const int la = c.level[A];
+        const int64_t SA = (int64_t)1 << (kLevels - la);
+        // the forward pair's rho = (C_A - C_B) / (2 S_A), exact
+        double rx = ldexp((double)((2 * (int64_t)c.ix[A] + 1) * SA - cbx), -(kLevels - la + 1));
+        double ry = ldexp((double)((2 * (int64_t)c.iy[A] + 1) * SA - cby), -(kLevels - la + 1));
+        double rz = ldexp((double)((2 * (int64_t)c.iz[A] + 1) * SA - cbz), -(kLevels - la + 1));
+        const int delta = la - lb;
+        __syncthreads();
+        for (int i = lane; i < P; i += 64) Us[i] = Lam[(int64_t)A * P + i];
+        if (lane <= 2 * p) {
+            int m = lane, nmax = 2 * p;
+            double r2 = rx * rx + ry * ry + rz * rz;
+            double ir2 = 1.0 / r2;
+            double mr = 1.0 / sqrt(r2), mi = 0.0;
+            for (int j = 1; j <= m; j++) {
+                double f = (2 * j - 1) * ir2;
+                double nr = (mr * rx - mi * ry) * f, ni = (mr * ry + mi * rx) * f;
+                mr = nr;
+                mi = ni;
+            }
+            Ire[tri(m, m)] = mr;
+            Iim[tri(m, m)] = mi;
+            double pr = 0, pi = 0, cr = mr, ci = mi;
+            for (int n = m + 1; n <= nmax; n++) {
+                double nr, ni;
+                if (n == m + 1) {
+                    double f = (2 * m + 1) * rz * ir2;
+                    nr = f * cr;
+                    ni = f * ci;
+                } else {
+                    double a = (2 * n - 1) * rz, b = (double)((n - 1) * (n - 1) - m * m);
+                    nr = (a * cr - b * pr) * ir2;
+                    ni = (a * ci - b * pi) * ir2;
+                }
+                Ire[tri(n, m)] = nr;
+                Iim[tri(n, m)] = ni;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+            }
+        }
+        __syncthreads();
+        for (int s = 0; s < 3; s++) {
+            const int k = ok_[s];
+            if (k < 0) continue;
+            const int l = ol_[s];
+            const double fk = ldexp(1.0, delta * k);
+            const double sl = (l & 1) ? -1.0 : 1.0;
+            double vr = 0, vi = 0;
+            for (int n = 0; n <= p; n++) {
+                const double cn = (n & 1) ? -fk : fk;
+                double tr = 0, ti = 0;
+                for (int m = 0; m <= n; m++) {
+                    const double ur = Us[cidx_re(n, m)], ui = m > 0 ? Us[cidx_im(n, m)] : 0.0;
+                    const int nn = n + k;
+                    // I1 = I_nn^(m+l)
+                    const double i1r = Ire[tri(nn, m + l)], i1i = Iim[tri(nn, m + l)];
+                    // I2 = I_nn^(m-l), negative order by I^-mu = (-1)^mu conj(I^mu)
+                    const int mu = m - l, amu = mu < 0 ? -mu : mu;
+                    double i2r = Ire[tri(nn, amu)], i2i = Iim[tri(nn, amu)];
+                    if (mu < 0) {
+                        i2i = -i2i;
+                        if (amu & 1) {
+                            i2r = -i2r;
+                            i2i = -i2i;
+                        }
+                    }
+                    // U conj(I1) + sl conj(U) I2
+                    tr += (ur * i1r + ui * i1i) + sl * (ur * i2r + ui * i2i);
+                    ti += (ui * i1r - ur * i1i) + sl * (ur * i2i - ui * i2r);
+                }
+                vr += cn * tr;
+                vi += cn * ti;
+            }
+            accr[s] += vr;
+            acci[s] += vi;
+        }
+    }
+    double *out = Mu + (int64_t)B * P;
+    for (int s = 0; s < 3; s++) {
+        const int k = ok_[s];
+        if (k < 0) continue;
+        const int l = ol_[s];
+        const double vr = l == 0 ? 0.5 * accr[s] : accr[s];
+        if (add) {
+            out[cidx_re(k, l)] += vr;
+            if (l > 0) out[cidx_im(k, l)] += acci[s];
+        } else {
+            out[cidx_re(k, l)] = vr;
+            if (l > 0) out[cidx_im(k, l)] = acci[s];
+        }
+    }
+}
+
 }  // namespace
+
+void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *ptr_t, const int32_t *src_t,
+                             const double *Lam, double *Mu, int add, hipStream_t s) {
+    if (ncell == 0) return;
+    hipLaunchKernelGGL(k_m2l_fp64_adjoint, dim3(ncell), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr_t, src_t, Lam,
+                       Mu, add);
+    FMM_LAUNCH_CHECK();
+}
 
 void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
                      const double *ys, const double *zs, const double *qs, double *phi, double *fld, hipStream_t s) {

@@ -133,7 +133,38 @@ __global__ void k_csr(const K *__restrict__ sorted, int64_t n, int bits, int32_t
     }
 }
 
+// Pair keys of the transposed list: (other << bits) | owner for every entry
+// of the CSR list (owner, other).  One wave per owner cell.
+template <class K>
+__global__ void k_swap_pairs(const int32_t *__restrict__ ptr, const int32_t *__restrict__ src, int32_t ncell, int bits,
+                             K *__restrict__ out) {
+    const int32_t waves = (int32_t)(gridDim.x * (blockDim.x / 64));
+    for (int32_t A = (int32_t)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64); A < ncell; A += waves)
+        for (int32_t e = ptr[A] + (int32_t)(threadIdx.x & 63); e < ptr[A + 1]; e += 64)
+            out[e] = ((K)src[e] << bits) | (K)A;
+}
+
 }  // namespace
+
+void transpose_csr(const int32_t *ptr, const int32_t *src, int32_t ncell, int64_t npair, int bits, bool key32,
+                   void *keys, void *alt, int32_t *tmp, int32_t *ptr_t, int32_t *src_t, hipStream_t s) {
+    if (key32) {
+        if (npair > 0) {
+            hipLaunchKernelGGL(k_swap_pairs<uint32_t>, dim3(grid_for((int64_t)ncell * 64, 256, 4096)), dim3(256), 0, s,
+                               ptr, src, ncell, bits, (uint32_t *)keys);
+            FMM_LAUNCH_CHECK();
+        }
+        radix_sort_u32((uint32_t *)keys, nullptr, (uint32_t *)alt, nullptr, npair, 0, 2 * bits, tmp, s);
+    } else {
+        if (npair > 0) {
+            hipLaunchKernelGGL(k_swap_pairs<uint64_t>, dim3(grid_for((int64_t)ncell * 64, 256, 4096)), dim3(256), 0, s,
+                               ptr, src, ncell, bits, (uint64_t *)keys);
+            FMM_LAUNCH_CHECK();
+        }
+        radix_sort_u64((uint64_t *)keys, nullptr, (uint64_t *)alt, nullptr, npair, 0, 2 * bits, tmp, s);
+    }
+    launch_csr(keys, key32, npair, bits, ncell, ptr_t, src_t, s);
+}
 
 void launch_traverse(CellArrays c, const int2 *fin, const int32_t *nf_in, int2 *fout, int32_t *nf_out, int32_t capf,
                      PairBuf pb, int32_t *counters, int bits, uint32_t theta_num, uint32_t theta_den, hipStream_t s) {

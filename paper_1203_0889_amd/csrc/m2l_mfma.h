@@ -13,9 +13,11 @@ void m2l_dense_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32
                     int32_t *used, hipStream_t s);
 void m2l_alloc_slots(const int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, hipStream_t s);
 // Split-bf16 operator blocks of the new classes (op_elems bf16 per class,
-// RT row tiles, layout as the work queue reads it).
+// RT row tiles, layout as the work queue reads it).  transposed: the keys
+// come from transposed pairs (owner = forward source) and each block holds
+// the transpose of the forward pair's operator.
 void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int64_t op_elems,
-                   uint16_t *ops, hipStream_t s);
+                   bool transposed, uint16_t *ops, hipStream_t s);
 void m2l_cid_tables(const int32_t *used_scan, const int32_t *used, const int32_t *slot_of, int32_t *cid_of,
                     int32_t *slot_of_cid, hipStream_t s);
 void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int32_t *pcid, int32_t *xflag,

@@ -82,7 +82,7 @@ __global__ void k_alloc_slots(const int32_t *__restrict__ used, int32_t nkeys, i
 // class.  Lane m computes column m of I_n^m (n <= 2p) in FP64.
 __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ new_keys, int32_t nnew,
                                                    const int32_t *__restrict__ slot_of, int p, int RT,
-                                                   int64_t op_elems, uint16_t *__restrict__ ops) {
+                                                   int64_t op_elems, int transposed, uint16_t *__restrict__ ops) {
     __shared__ double Ire[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2], Iim[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2];
     int32_t j = blockIdx.x;
     if (j >= nnew) return;
@@ -93,6 +93,15 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
     t /= kRhoSpan;
     int rx = t % kRhoSpan - kRhoMax;
     int delta = t / kRhoSpan - 1;
+    if (transposed) {
+        // key of a transposed pair (owner B, partner A): the forward pair
+        // A <- B has the opposite level difference and displacement, and the
+        // store holds the transpose of its operator
+        delta = -delta;
+        rx = -rx;
+        ry = -ry;
+        rz = -rz;
+    }
     // rho in units of the target side: (C_A - C_B) / (2 S_A) = r_int * S_min / (2 S_A)
     double sc = delta >= 0 ? 0.5 : ldexp(0.5, delta);  // S_min / S_A = 2^min(0, delta)
     double x = rx * sc, y = ry * sc, z = rz * sc;
@@ -140,7 +149,8 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
     const int total = NK * RT * 64 * 8;  // values (each written as two pieces)
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
         const int t = f & 7, lane = (f >> 3) & 63, r = (f >> 9) % RT, sk = (f >> 9) / RT;
-        const int row = r * 32 + (lane & 31), col = 16 * sk + 8 * (lane >> 5) + t;
+        const int orow = r * 32 + (lane & 31), ocol = 16 * sk + 8 * (lane >> 5) + t;
+        const int row = transposed ? ocol : orow, col = transposed ? orow : ocol;  // entry of the forward T
         double v = 0.0;
         if (row < P && col < P) {
             // output (n, m, part) and input (kk, l, part) of the real layouts
@@ -413,9 +423,10 @@ void m2l_alloc_slots(const int32_t *used, int32_t *slot_of, int32_t *nslots, int
 }
 
 void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int64_t op_elems,
-                   uint16_t *ops, hipStream_t s) {
+                   bool transposed, uint16_t *ops, hipStream_t s) {
     if (nnew <= 0) return;
-    hipLaunchKernelGGL(k_build_ops, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, op_elems, ops);
+    hipLaunchKernelGGL(k_build_ops, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, op_elems,
+                       transposed ? 1 : 0, ops);
     FMM_LAUNCH_CHECK();
 }
 

@@ -19,6 +19,10 @@ struct NearFarArgs {
     double *L;         // FP64 locals (output, overwritten)
     double *phi, *fld; // FP64 near field per sorted particle (output)
     fmm_tuning tuning;
+    // Adjoint use: the lists are the transposed ones (owner = forward
+    // source), M holds the duals of the locals, L receives the duals of the
+    // multipoles, qs the adjoint weights; operators are stored transposed.
+    bool transposed = false;
 };
 
 // Device workspaces of this stage, owned by the plan.  The class operator

@@ -62,7 +62,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     read_sync(ns, st.nslots.ptr, 8, s);
     if (ns[0] > st.nslot_total) {
         FMM_HIP_CHECK(st.frags.grow_keep((size_t)ns[0] * op_elems * 2, s));
-        m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, op_elems,
+        m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, op_elems, a.transposed,
                       st.frags.as<uint16_t>(), s);
         st.nslot_total = ns[0];
     }
@@ -205,7 +205,10 @@ void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
 }
 
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
-    if (st.nextra > 0)
+    if (st.nextra <= 0) return;
+    if (a.transposed)
+        launch_m2l_fp64_adjoint(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, 1, s);
+    else
         launch_m2l_fp64_add(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, s);
 }
 

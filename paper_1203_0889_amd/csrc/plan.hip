@@ -93,6 +93,11 @@ struct fmm_plan {
     // expansions and fields
     DevBuf M, L, ops_m2m, ops_l2l, m2m_part;
     int ops_p = -1;
+    // adjoint: transposed octant matrices and lists, duals, transposed fields
+    DevBuf ops_m2m_t, ops_l2l_t, m2l_t_ptr, m2l_t_src, p2p_t_ptr, p2p_t_src, tkeys, tkeys_alt;
+    DevBuf lam, mu, wts, psi_near, epsi_near, psi_far, epsi_far;
+    bool adj_ready = false;
+    fmm::NearFarState nf_t;
     DevBuf phi_near, fld_near, phi_far, fld_far, echunk, epart;
     int32_t nechunk = 0;
     fmm::NearFarState nf;
@@ -361,10 +366,15 @@ void ensure_ops(fmm_plan *p) {
     if (p->ops_p == pp) return;
     const int P = fmm::ncoef(pp);
     std::vector<double> a = fmm::build_translation_ops(pp, 0), b = fmm::build_translation_ops(pp, 1);
+    std::vector<double> at = fmm::transpose_ops(a, pp), bt = fmm::transpose_ops(b, pp);
     FMM_HIP_CHECK(p->ops_m2m.grow(a.size() * 8));
     FMM_HIP_CHECK(p->ops_l2l.grow(b.size() * 8));
+    FMM_HIP_CHECK(p->ops_m2m_t.grow(at.size() * 8));
+    FMM_HIP_CHECK(p->ops_l2l_t.grow(bt.size() * 8));
     FMM_HIP_CHECK(hipMemcpy(p->ops_m2m.ptr, a.data(), a.size() * 8, hipMemcpyHostToDevice));
     FMM_HIP_CHECK(hipMemcpy(p->ops_l2l.ptr, b.data(), b.size() * 8, hipMemcpyHostToDevice));
+    FMM_HIP_CHECK(hipMemcpy(p->ops_m2m_t.ptr, at.data(), at.size() * 8, hipMemcpyHostToDevice));
+    FMM_HIP_CHECK(hipMemcpy(p->ops_l2l_t.ptr, bt.data(), bt.size() * 8, hipMemcpyHostToDevice));
     (void)P;
     p->ops_p = pp;
 }
@@ -435,6 +445,110 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     mark(p, ST_OUT);
 }
 
+// Frozen-topology rebuild: new positions and charges through the stored
+// permutation; box, keys, tree, lists and task tables stay.
+void do_refresh(fmm_plan *p, const double *pos, const double *q) {
+    hipStream_t s = p->stream;
+    FMM_HIP_CHECK(hipMemsetAsync(p->flag.ptr, 0, 16 * sizeof(int), s));
+    fmm::launch_bbox(pos, p->n, p->off.as<int64_t>(), p->n_inst, p->ord.as<unsigned long long>(), p->flag.as<int>(), s);
+    fmm::launch_gather(pos, q, p->idx.as<uint32_t>(), p->n, p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
+                       p->qs.as<double>(), s);
+    int bad = 0;
+    sync_read(p, &bad, p->flag.ptr, sizeof(int));
+    if (bad) throw std::invalid_argument("non-finite particle coordinate");
+}
+
+fmm::NearFarArgs nf_args_adjoint(fmm_plan *p) {
+    fmm::NearFarArgs a = nf_args(p);
+    a.m2l_ptr = p->m2l_t_ptr.as<int32_t>();
+    a.m2l_src = p->m2l_t_src.as<int32_t>();
+    a.p2p_ptr = p->p2p_t_ptr.as<int32_t>();
+    a.p2p_src = p->p2p_t_src.as<int32_t>();
+    a.qs = p->wts.as<double>();
+    a.M = p->lam.as<double>();
+    a.L = p->mu.as<double>();
+    a.phi = p->psi_near.as<double>();
+    a.fld = p->epsi_near.as<double>();
+    a.transposed = true;
+    return a;
+}
+
+// Transposed M2L and P2P lists (and, mixed, the transposed queue tables).
+void build_adjoint(fmm_plan *p) {
+    hipStream_t s = p->stream;
+    const int32_t ncell = (int32_t)p->ncell;
+    const int bits = bits_for(ncell);
+    const bool key32 = 2 * bits <= 32;
+    const size_t ksz = key32 ? 4 : 8;
+    const int64_t mx = std::max<int64_t>(std::max(p->nm2l, p->np2p), 1);
+    FMM_HIP_CHECK(p->tkeys.grow(mx * ksz));
+    FMM_HIP_CHECK(p->tkeys_alt.grow(mx * ksz));
+    FMM_HIP_CHECK(p->tmp.grow(std::max(p->tmp.bytes, fmm::radix_tmp_elems(mx) * sizeof(int32_t))));
+    FMM_HIP_CHECK(p->m2l_t_ptr.grow(((size_t)ncell + 1) * 4));
+    FMM_HIP_CHECK(p->p2p_t_ptr.grow(((size_t)ncell + 1) * 4));
+    FMM_HIP_CHECK(p->m2l_t_src.grow(std::max<int64_t>(p->nm2l, 1) * 4));
+    FMM_HIP_CHECK(p->p2p_t_src.grow(std::max<int64_t>(p->np2p, 1) * 4));
+    fmm::transpose_csr(p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), ncell, p->nm2l, bits, key32, p->tkeys.ptr,
+                       p->tkeys_alt.ptr, p->tmp.as<int32_t>(), p->m2l_t_ptr.as<int32_t>(), p->m2l_t_src.as<int32_t>(),
+                       s);
+    fmm::transpose_csr(p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(), ncell, p->np2p, bits, key32, p->tkeys.ptr,
+                       p->tkeys_alt.ptr, p->tmp.as<int32_t>(), p->p2p_t_ptr.as<int32_t>(), p->p2p_t_src.as<int32_t>(),
+                       s);
+    if (p->prm.precision == FMM_PREC_MIXED) fmm::build_near_far_mixed(p->nf_t, nf_args_adjoint(p), s);
+    p->adj_ready = true;
+}
+
+void do_backward(fmm_plan *p, const double *gE, double *grad_pos, double *grad_q) {
+    hipStream_t s = p->stream;
+    const int pp = p->prm.p;
+    const int P = fmm::ncoef(pp);
+    const int32_t ncell = (int32_t)p->ncell;
+    const size_t nn = (size_t)std::max<int64_t>(p->n, 1);
+    ensure_ops(p);
+    if (!p->adj_ready) build_adjoint(p);
+    FMM_HIP_CHECK(p->lam.grow((size_t)std::max(ncell, 1) * P * 8));
+    FMM_HIP_CHECK(p->mu.grow((size_t)std::max(ncell, 1) * P * 8));
+    FMM_HIP_CHECK(p->wts.grow(nn * 8));
+    FMM_HIP_CHECK(p->psi_near.grow(nn * 8));
+    FMM_HIP_CHECK(p->epsi_near.grow(nn * 24));
+    FMM_HIP_CHECK(p->psi_far.grow(nn * 8));
+    FMM_HIP_CHECK(p->epsi_far.grow(nn * 24));
+    fmm::Geometry g = geom(p);
+    fmm::launch_adjoint_weights(g, p->n, p->leaf_of.as<int32_t>(), gE, p->qs.as<double>(), p->wts.as<double>(), s);
+    // L2P^T at the leaves, then L2L^T up the tree
+    fmm::launch_p2m(g, ncell, pp, p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(), p->wts.as<double>(),
+                    p->lam.as<double>(), s);
+    fmm::launch_dual_scale(g, ncell, pp, p->lam.as<double>(), 0, s);
+    const int depth = (int)p->level_begin.size() - 1;
+    for (int l = depth - 2; l >= 0; l--)
+        fmm::launch_m2m_level(g, p->level_begin[l], p->level_begin[l + 1], pp, p->ops_l2l_t.as<double>(),
+                              p->lam.as<double>(), p->m2m_part.as<double>(), s);
+    // M2L^T and P2P^T
+    if (p->prm.precision == FMM_PREC_FP64) {
+        fmm::launch_m2l_fp64_adjoint(g, ncell, pp, p->m2l_t_ptr.as<int32_t>(), p->m2l_t_src.as<int32_t>(),
+                                     p->lam.as<double>(), p->mu.as<double>(), 0, s);
+        fmm::launch_p2p_fp64(g, ncell, p->p2p_t_ptr.as<int32_t>(), p->p2p_t_src.as<int32_t>(), p->xs.as<double>(),
+                             p->ys.as<double>(), p->zs.as<double>(), p->wts.as<double>(), p->psi_near.as<double>(),
+                             p->epsi_near.as<double>(), s);
+    } else {
+        fmm::NearFarArgs a = nf_args_adjoint(p);
+        fmm::near_far_prepare(p->nf_t, a, s);
+        fmm::near_far_queue(p->nf_t, a, s);
+        fmm::near_far_rest(p->nf_t, a, s);
+    }
+    // M2M^T down the tree, then P2M^T at the particles
+    for (int l = 0; l + 1 < depth; l++)
+        fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], pp, p->ops_m2m_t.as<double>(),
+                              p->mu.as<double>(), s);
+    fmm::launch_dual_scale(g, ncell, pp, p->mu.as<double>(), 1, s);
+    fmm::launch_l2p(g, p->n, pp, p->leaf_of.as<int32_t>(), p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
+                    p->mu.as<double>(), p->psi_far.as<double>(), p->epsi_far.as<double>(), s);
+    fmm::launch_adjoint_finalize(g, p->n, p->idx.as<uint32_t>(), p->leaf_of.as<int32_t>(), gE, p->qs.as<double>(),
+                                 p->phi_near.as<double>(), p->fld_near.as<double>(), p->phi_far.as<double>(),
+                                 p->fld_far.as<double>(), p->psi_near.as<double>(), p->epsi_near.as<double>(),
+                                 p->psi_far.as<double>(), p->epsi_far.as<double>(), grad_pos, grad_q, s);
+}
+
 template <class F>
 fmm_status guarded(fmm_plan *p, F &&f) {
     try {
@@ -464,7 +578,7 @@ fmm_status check_params(const fmm_params *q, std::string *why) {
     if (q->max_level < 1 || q->max_level > fmm::kLevels) return *why = "max_level must be in [1, 21]", FMM_ERR_INVALID_ARG;
     if (q->precision != FMM_PREC_FP64 && q->precision != FMM_PREC_MIXED)
         return *why = "unknown precision", FMM_ERR_INVALID_ARG;
-    if (q->flags & ~(uint32_t)FMM_FLAG_USER_BOX) return *why = "unknown flag", FMM_ERR_INVALID_ARG;
+    if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY)) return *why = "unknown flag", FMM_ERR_INVALID_ARG;
     if ((q->flags & FMM_FLAG_USER_BOX) &&
         !(q->box_side > 0 && std::isfinite(q->box_side) && std::isfinite(q->box_min[0]) &&
           std::isfinite(q->box_min[1]) && std::isfinite(q->box_min[2])))
@@ -528,6 +642,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
     fmm::release_near_far(p->nf);
+    fmm::release_near_far(p->nf_t);
     for (int i = 0; i < ST_COUNT; i++) {
         if (p->ev_beg[i]) hipEventDestroy(p->ev_beg[i]);
         if (p->ev_end[i]) hipEventDestroy(p->ev_end[i]);
@@ -545,8 +660,16 @@ fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, c
     int64_t n = offsets[n_inst];
     if (n >= ((int64_t)1 << 31) - 1) return fail(p, FMM_ERR_INVALID_ARG, "too many particles (limit 2^31 - 2)");
     if (n > 0 && (!pos || !q)) return fail(p, FMM_ERR_INVALID_ARG, "pos and q required");
+    const bool keep = (p->prm.flags & FMM_FLAG_KEEP_TOPOLOGY) && p->state >= kStateBuilt && n_inst == p->n_inst &&
+                      std::equal(offsets, offsets + n_inst + 1, p->h_off.begin());
     return guarded(p, [&]() -> fmm_status {
+        if (keep && n > 0) {
+            p->state = kStateBuilt;
+            do_refresh(p, pos, q);
+            return FMM_OK;
+        }
         p->state = kStateCreated;
+        p->adj_ready = false;
         p->n = n;
         p->n_inst = n_inst;
         p->h_off.assign(offsets, offsets + n_inst + 1);
@@ -582,9 +705,11 @@ fmm_status fmm_backward(fmm_plan *p, const double *grad_energy, double *grad_pos
     if (!p) return FMM_ERR_INVALID_ARG;
     if (p->state < kStateEval) return fail(p, FMM_ERR_STATE, "fmm_backward before fmm_evaluate");
     if (!grad_energy) return fail(p, FMM_ERR_INVALID_ARG, "grad_energy required");
-    (void)grad_pos;
-    (void)grad_q;
-    return fail(p, FMM_ERR_UNSUPPORTED, "adjoint not available in this build");
+    if (p->n == 0) return FMM_OK;
+    return guarded(p, [&]() -> fmm_status {
+        do_backward(p, grad_energy, grad_pos, grad_q);
+        return FMM_OK;
+    });
 }
 
 fmm_status fmm_sync(fmm_plan *p) {

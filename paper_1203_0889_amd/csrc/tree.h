@@ -52,6 +52,11 @@ void launch_init_frontier(const int64_t *d_offsets, int n_inst, int2 *front, int
 // CSR from pair keys sorted by (target, source).
 void launch_csr(const void *sorted, bool key32, int64_t n, int bits, int32_t ncell, int32_t *ptr, int32_t *src,
                 hipStream_t s);
+// Transposed CSR of a pair list: (ptr, src) lists, per owner cell, its
+// partners; (ptr_t, src_t) lists, per partner, its owners, sorted.  keys and
+// alt hold npair keys of 4 (key32) or 8 bytes; tmp radix_tmp_elems(npair).
+void transpose_csr(const int32_t *ptr, const int32_t *src, int32_t ncell, int64_t npair, int bits, bool key32,
+                   void *keys, void *alt, int32_t *tmp, int32_t *ptr_t, int32_t *src_t, hipStream_t s);
 
 // ---- expansions.hip  (FP64, scaled solid harmonics)
 struct Geometry {
@@ -70,6 +75,23 @@ void launch_l2p(Geometry g, int64_t n, int p, const int32_t *leaf_of, const doub
 // column-major P x P each (P = (p+1)^2), acting on the real coefficient layout.
 std::vector<double> build_translation_ops(int p, int dir);
 
+// ---- adjoint helpers (expansions.hip)
+// Leaf rows of X scaled by s_k / S (dir 0: L2P^T from P2M) or S / s_k
+// (dir 1: P2M^T through L2P); s_k = 1 (m = 0), 2 (Re), -2 (Im).
+void launch_dual_scale(Geometry g, int32_t ncell, int p, double *X, int dir, hipStream_t s);
+// w_i = gE[instance(i)] q_i, sorted order.
+void launch_adjoint_weights(Geometry g, int64_t n, const int32_t *leaf_of, const double *gE, const double *qs,
+                            double *w, hipStream_t s);
+// grad_q = (g phi + psi) / 2, grad_pos = -q (g E + E_psi) / 2, in input order
+// (either output may be NULL).
+void launch_adjoint_finalize(Geometry g, int64_t n, const uint32_t *perm, const int32_t *leaf_of, const double *gE,
+                             const double *qs, const double *phi_near, const double *fld_near, const double *phi_far,
+                             const double *fld_far, const double *psi_near, const double *epsi_near,
+                             const double *psi_far, const double *epsi_far, double *grad_pos, double *grad_q,
+                             hipStream_t s);
+// Transposes of the 8 column-major octant matrices (same layout).
+std::vector<double> transpose_ops(const std::vector<double> &ops, int p);
+
 // ---- near / far field, FP64 plain path
 void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
                      const double *ys, const double *zs, const double *qs, double *phi, double *fld, hipStream_t s);
@@ -78,6 +100,12 @@ void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const
 // Same kernel, adding into L (used for the pairs the MFMA path leaves out).
 void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
                          double *L, hipStream_t s);
+// Adjoint of the M2L stage over the transposed list (ptr_t, src_t): for every
+// pair (A <- B) of the forward list, Mu_B += T_(A<-B)^T Lam_A, with T the real
+// (p+1)^2 x (p+1)^2 matrix the forward kernel applies.  Owner = source cell B.
+// add = 0 overwrites Mu (cells without pairs get zero), add = 1 accumulates.
+void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *ptr_t, const int32_t *src_t,
+                             const double *Lam, double *Mu, int add, hipStream_t s);
 
 // ---- output
 void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,

@@ -22,6 +22,7 @@ STATUS = {0: "FMM_OK", -1: "FMM_ERR_INVALID_ARG", -2: "FMM_ERR_STATE", -3: "FMM_
           -4: "FMM_ERR_DEVICE", -5: "FMM_ERR_CAPACITY", -6: "FMM_ERR_UNSUPPORTED"}
 PREC = {"fp64": 0, "mixed": 1}
 FLAG_USER_BOX = 1
+FLAG_KEEP_TOPOLOGY = 2
 
 # every symbol include/fmm.h declares
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
@@ -101,7 +102,7 @@ class Plan:
     """One FMM plan: owns the tree, lists and expansions on one device/stream."""
 
     def __init__(self, p=8, ncrit=64, theta=(1, 2), max_level=21, precision="mixed", device=None, stream=None,
-                 box=None):
+                 box=None, keep_topology=False):
         self._lib = load_library()
         prm = fmm_params()
         self._lib.fmm_default_params(ctypes.byref(prm))
@@ -113,6 +114,8 @@ class Plan:
             prm.flags |= FLAG_USER_BOX
             prm.box_min[0], prm.box_min[1], prm.box_min[2] = map(float, box[:3])
             prm.box_side = float(box[3])
+        if keep_topology:
+            prm.flags |= FLAG_KEEP_TOPOLOGY
         self.params = prm
         if device is None:
             device = torch.cuda.current_device()
@@ -182,6 +185,8 @@ class Plan:
         self._call(self._lib.fmm_evaluate, _ptr(phi), _ptr(field), _ptr(force), _ptr(energy))
 
     def backward(self, grad_energy, want_pos=True, want_q=True):
+        """Gradient of sum_k grad_energy[k] E_k (the FMM's energies) with
+        respect to positions and charges: (grad_pos (N, 3), grad_q (N,))."""
         dev = torch.device("cuda", self.device)
         _check_dev(grad_energy, "grad_energy")
         gp = torch.empty((self.n, 3), dtype=torch.float64, device=dev) if want_pos else None
