@@ -141,6 +141,26 @@ fmm_status fmm_evaluate(fmm_plan *plan, double *phi, double *field, double *forc
  */
 fmm_status fmm_backward(fmm_plan *plan, const double *grad_energy, double *grad_pos, double *grad_q);
 
+/*
+ * Record the numeric part of a solve into a HIP graph owned by the plan:
+ * fmm_upward, fmm_evaluate into the given outputs and, when grad_energy is
+ * non-NULL, fmm_backward into grad_pos / grad_q (arguments as for those
+ * calls; the pointers are baked into the graph and must stay valid while it
+ * is used).  The tree and lists of the last fmm_build_tree are fixed in the
+ * graph: a replay recomputes everything downstream of the sorted particle
+ * data, e.g. after a frozen-topology fmm_build_tree (FMM_FLAG_KEEP_TOPOLOGY)
+ * with new charges or positions.  The build itself is not captured: it reads
+ * tree and list sizes back to size its buffers and launches.  Runs the
+ * sequence once eagerly (sizing every workspace), synchronises, then
+ * captures on the plan's stream.  A full rebuild or fmm_destroy drops the
+ * graph.
+ */
+fmm_status fmm_graph_capture(fmm_plan *plan, double *phi, double *field, double *force, double *energy,
+                             const double *grad_energy, double *grad_pos, double *grad_q);
+
+/* Replay the captured graph on the plan's stream (asynchronous). */
+fmm_status fmm_graph_launch(fmm_plan *plan);
+
 /* Wait for the plan's stream; returns the first device-detected error
  * recorded since the last call (e.g. FMM_ERR_CAPACITY), else FMM_OK. */
 fmm_status fmm_sync(fmm_plan *plan);

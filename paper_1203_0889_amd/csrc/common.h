@@ -55,6 +55,11 @@ void radix_sort_u64(uint64_t *kin, uint32_t *vin, uint64_t *kalt, uint32_t *valt
 void radix_sort_u32(uint32_t *kin, uint32_t *vin, uint32_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
                     int bit_hi, int32_t *d_tmp, hipStream_t s);
 
+// Zero `bytes` bytes (a multiple of 4) at a 4-byte aligned device address
+// with a kernel: unlike hipMemsetAsync it may be captured in a HIP graph and
+// replayed.
+void fill_zero(void *ptr, size_t bytes, hipStream_t s);
+
 inline int grid_for(int64_t n, int threads, int cap = 65535 * 4) {
     int64_t g = (n + threads - 1) / threads;
     if (g < 1) g = 1;

@@ -168,7 +168,7 @@ void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     FMM_HIP_CHECK(st.pf.grow((size_t)std::max<int64_t>(a.n, 1) * sizeof(float4)));
     FMM_HIP_CHECK(st.cnt.grow(64 * 4));
     queue_split_multipoles(a.M, ncell, a.p, st.M32.as<uint16_t>(), s);
-    FMM_HIP_CHECK(hipMemsetAsync(a.L, 0, (size_t)ncell * P * 8, s));
+    fill_zero(a.L, (size_t)ncell * P * 8, s);
     p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
 }
 

@@ -107,6 +107,10 @@ struct fmm_plan {
     hipEvent_t last_ev = nullptr;
     bool ev_ok = false;
     bool ev_used[ST_COUNT] = {};
+    // HIP graph of the numeric part of a solve (fmm_graph_capture)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool capturing = false;
 };
 
 namespace {
@@ -134,17 +138,24 @@ void ensure_cells(fmm_plan *p, int64_t want) {
 // Stage timing: record() opens a stage; mark() closes one, timed from the
 // most recent event (the opening one, or the end of the previous stage).
 void record(fmm_plan *p, int stage) {
-    if (!p->ev_ok) return;
+    if (!p->ev_ok || p->capturing) return;
     hipEventRecord(p->ev_beg[stage], p->stream);
     p->last_ev = p->ev_beg[stage];
 }
 
 void mark(fmm_plan *p, int stage) {
-    if (!p->ev_ok || !p->last_ev) return;
+    if (!p->ev_ok || !p->last_ev || p->capturing) return;
     hipEventRecord(p->ev_end[stage], p->stream);
     p->beg_of[stage] = p->last_ev;
     p->last_ev = p->ev_end[stage];
     p->ev_used[stage] = true;
+}
+
+void drop_graph(fmm_plan *p) {
+    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
 }
 
 void sync_read(fmm_plan *p, void *host, const void *dev, size_t bytes) {
@@ -638,7 +649,11 @@ fmm_status fmm_destroy(fmm_plan *p) {
                      &p->ikey, &p->ialt, &p->rank, &p->ralt, &p->tmp, &p->xs, &p->ys, &p->zs, &p->qs,
                      &p->leaf_of, &p->bounds, &p->nch, &p->counters, &p->front[0], &p->front[1], &p->m2l_pairs,
                      &p->p2p_pairs, &p->pair_alt, &p->m2l_ptr, &p->m2l_src, &p->p2p_ptr, &p->p2p_src, &p->M,
-                     &p->L, &p->ops_m2m, &p->ops_l2l, &p->m2m_part, &p->phi_near, &p->fld_near, &p->phi_far, &p->fld_far, &p->echunk, &p->epart};
+                     &p->L, &p->ops_m2m, &p->ops_l2l, &p->m2m_part, &p->phi_near, &p->fld_near, &p->phi_far,
+                     &p->fld_far, &p->echunk, &p->epart, &p->ops_m2m_t, &p->ops_l2l_t, &p->m2l_t_ptr,
+                     &p->m2l_t_src, &p->p2p_t_ptr, &p->p2p_t_src, &p->tkeys, &p->tkeys_alt, &p->lam, &p->mu,
+                     &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far};
+    drop_graph(p);
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
     fmm::release_near_far(p->nf);
@@ -670,6 +685,7 @@ fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, c
         }
         p->state = kStateCreated;
         p->adj_ready = false;
+        drop_graph(p);
         p->n = n;
         p->n_inst = n_inst;
         p->h_off.assign(offsets, offsets + n_inst + 1);
@@ -708,6 +724,68 @@ fmm_status fmm_backward(fmm_plan *p, const double *grad_energy, double *grad_pos
     if (p->n == 0) return FMM_OK;
     return guarded(p, [&]() -> fmm_status {
         do_backward(p, grad_energy, grad_pos, grad_q);
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_graph_capture(fmm_plan *p, double *phi, double *field, double *force, double *energy,
+                             const double *grad_energy, double *grad_pos, double *grad_q) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateBuilt) return fail(p, FMM_ERR_STATE, "fmm_graph_capture before fmm_build_tree");
+    if (p->n == 0) return fail(p, FMM_ERR_INVALID_ARG, "nothing to capture (N = 0)");
+    return guarded(p, [&]() -> fmm_status {
+        drop_graph(p);
+        // one eager pass sizes every workspace and builds the adjoint tables
+        do_upward(p);
+        do_evaluate(p, phi, field, force, energy);
+        p->state = kStateEval;
+        if (grad_energy) do_backward(p, grad_energy, grad_pos, grad_q);
+        FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+        // The plan's stream may be the legacy null stream, which cannot be
+        // captured: record on a private stream (default priority), replay on
+        // the plan's stream.
+        hipStream_t cs = nullptr;
+        FMM_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipStream_t saved = p->stream;
+        p->stream = cs;
+        p->capturing = true;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        hipGraph_t g = nullptr;
+        if (e == hipSuccess) {
+            try {
+                do_upward(p);
+                do_evaluate(p, phi, field, force, energy);
+                if (grad_energy) do_backward(p, grad_energy, grad_pos, grad_q);
+            } catch (...) {
+                hipStreamEndCapture(cs, &g);
+                if (g) hipGraphDestroy(g);
+                p->capturing = false;
+                p->stream = saved;
+                hipStreamDestroy(cs);
+                throw;
+            }
+            e = hipStreamEndCapture(cs, &g);
+        }
+        p->capturing = false;
+        p->stream = saved;
+        hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            throw fmm::HipError{e, "stream capture"};
+        }
+        p->graph = g;
+        FMM_HIP_CHECK(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_graph_launch(fmm_plan *p) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (!p->graph_exec) return fail(p, FMM_ERR_STATE, "fmm_graph_launch without a captured graph");
+    if (p->state < kStateBuilt) return fail(p, FMM_ERR_STATE, "fmm_graph_launch after the tree was dropped");
+    return guarded(p, [&]() -> fmm_status {
+        FMM_HIP_CHECK(hipGraphLaunch(p->graph_exec, p->stream));
+        p->state = kStateEval;
         return FMM_OK;
     });
 }

@@ -509,7 +509,7 @@ void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb,
 }
 
 void queue_run(const QueueArgs &a, int p, int nworkgroups, hipStream_t s) {
-    FMM_HIP_CHECK(hipMemsetAsync(a.heads, 0, 16 * sizeof(int32_t), s));
+    fill_zero(a.heads, 16 * sizeof(int32_t), s);
     dim3 grid(nworkgroups), block(256);
 #define FMM_Q(PP, R)                                                      \
     case PP:                                                              \

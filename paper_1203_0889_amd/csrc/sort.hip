@@ -251,6 +251,20 @@ void radix_sort_impl(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, 
 
 }  // namespace
 
+namespace {
+__global__ void k_fill_zero(uint32_t *__restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+}  // namespace
+
+void fill_zero(void *ptr, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, (uint32_t *)ptr, n);
+    FMM_LAUNCH_CHECK();
+}
+
 size_t scan_tmp_elems(int64_t n) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     return (size_t)(nb + 1);

@@ -27,7 +27,8 @@ FLAG_KEEP_TOPOLOGY = 2
 # every symbol include/fmm.h declares
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
            "fmm_backward", "fmm_sync", "fmm_get_counts", "fmm_copy_tree", "fmm_copy_lists", "fmm_get_tuning",
-           "fmm_set_tuning", "fmm_get_stage_times", "fmm_status_string", "fmm_last_error")
+           "fmm_set_tuning", "fmm_get_stage_times", "fmm_status_string", "fmm_last_error", "fmm_graph_capture",
+           "fmm_graph_launch")
 
 
 class fmm_params(ctypes.Structure):
@@ -68,6 +69,8 @@ def load_library():
     lib.fmm_evaluate.argtypes = [vp, vp, vp, vp, vp]
     lib.fmm_backward.argtypes = [vp, vp, vp, vp]
     lib.fmm_sync.argtypes = [vp]
+    lib.fmm_graph_capture.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_graph_launch.argtypes = [vp]
     lib.fmm_get_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64)]
     lib.fmm_copy_tree.argtypes = [vp, vp, vp, vp]
     lib.fmm_copy_lists.argtypes = [vp, vp, vp, vp, vp]
@@ -193,6 +196,18 @@ class Plan:
         gq = torch.empty(self.n, dtype=torch.float64, device=dev) if want_q else None
         self._call(self._lib.fmm_backward, _ptr(grad_energy), _ptr(gp), _ptr(gq))
         return gp, gq
+
+    # ---- HIP graph of upward + evaluate (+ backward)
+    def graph_capture(self, phi=None, field=None, force=None, energy=None, grad_energy=None, grad_pos=None,
+                      grad_q=None):
+        """Capture upward + evaluate (+ backward when grad_energy is given)
+        into a HIP graph writing into the given tensors."""
+        self._graph_refs = (phi, field, force, energy, grad_energy, grad_pos, grad_q)
+        self._call(self._lib.fmm_graph_capture, _ptr(phi), _ptr(field), _ptr(force), _ptr(energy), _ptr(grad_energy),
+                   _ptr(grad_pos), _ptr(grad_q))
+
+    def graph_launch(self):
+        self._call(self._lib.fmm_graph_launch)
 
     # ---- introspection
     def sync(self):
