@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--workload", default="uniform1m_p8")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default work-queue tuning")
     ap.add_argument("--cpu-n", type=int, default=524288, help="particles in the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM byte counters)")
@@ -126,6 +127,14 @@ def main():
         plan.build_tree(dpos, dq)
         plan.upward()
         plan.evaluate_into(phi=phi, field=field, energy=energy)
+
+    tuning = plan.get_tuning()
+    if not a.no_autotune and a.precision == "mixed":
+        # set-up, not timed: pick the work-queue setting on this workload
+        plan.build_tree(dpos, dq)
+        plan.upward()
+        tuning, tq_ms = plan.autotune(repeats=2)
+        print("bench: autotuned %s (queue %.3f ms)" % (tuning, tq_ms), file=sys.stderr, flush=True)
 
     for _ in range(a.warmup):
         step()
@@ -191,6 +200,7 @@ def main():
                    "theta": "%d/%d" % tuple(w["theta"]), "precision": a.precision,
                    "distribution": w["dist"]},
         "stages_ms": {k: round(v, 4) for k, v in stage_avg.items()},
+        "tuning": tuning,
         "work": {"ncell": counts["ncell"], "nleaf": counts["nleaf"], "m2l_pairs": counts["nm2l"],
                  "p2p_pairs": counts["np2p"], "p2p_interactions": inter, "p2p_flop": p2p_flop, "m2l_flop": m2l_f},
         "roofline": roof,

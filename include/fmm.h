@@ -199,7 +199,22 @@ typedef struct {
 } fmm_tuning;
 
 fmm_status fmm_get_tuning(const fmm_plan *plan, fmm_tuning *tuning);
+/* Takes effect at the next fmm_build_tree (task tables are built there). */
 fmm_status fmm_set_tuning(fmm_plan *plan, const fmm_tuning *tuning);
+
+/*
+ * Autotuner of the work queue (the paper tunes its task granularity Q,
+ * Sec. 5): on the plan's current tree and multipoles (after fmm_upward),
+ * times the queue kernel for m2l_task_entries in {32, 64, 96, 128} and
+ * grid_per_cu in {1, 2, 3, 4} (the task tables are rebuilt per
+ * m2l_task_entries; each setting takes the fastest of `repeats` >= 1 runs,
+ * HIP events around the kernel), keeps the fastest setting and rebuilds the
+ * tables with it.  Outputs (host, may be NULL): the chosen tuning and its
+ * kernel time in ms.  Leaves the plan as after fmm_upward (call
+ * fmm_evaluate again); drops a captured graph.  The FP64 path has no queue:
+ * the call then only reports the current tuning and time -1.
+ */
+fmm_status fmm_autotune(fmm_plan *plan, int32_t repeats, fmm_tuning *best, double *best_ms);
 
 /* Per-stage device times of the last build / upward / evaluate in ms,
  * measured with HIP events on the plan's stream.  times: host double[16],

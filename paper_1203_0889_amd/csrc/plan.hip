@@ -875,6 +875,67 @@ fmm_status fmm_set_tuning(fmm_plan *p, const fmm_tuning *t) {
     return FMM_OK;
 }
 
+fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *best_ms) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (repeats < 1) return fail(p, FMM_ERR_INVALID_ARG, "repeats must be >= 1");
+    if (p->state < kStateUp) return fail(p, FMM_ERR_STATE, "fmm_autotune before fmm_upward");
+    if (p->prm.precision != FMM_PREC_MIXED || p->n == 0) {
+        if (best) *best = p->tuning;
+        if (best_ms) *best_ms = -1.0;
+        return FMM_OK;
+    }
+    return guarded(p, [&]() -> fmm_status {
+        hipStream_t s = p->stream;
+        drop_graph(p);
+        p->adj_ready = false;
+        static const int kEntries[] = {32, 64, 96, 128};
+        static const int kGrid[] = {1, 2, 3, 4};
+        hipEvent_t e0, e1;
+        FMM_HIP_CHECK(hipEventCreate(&e0));
+        FMM_HIP_CHECK(hipEventCreate(&e1));
+        fmm_tuning keep = p->tuning, top = keep;
+        float top_ms = -1.0f;
+        try {
+            for (int ce : kEntries) {
+                p->tuning.m2l_task_entries = ce;
+                fmm::build_near_far_mixed(p->nf, nf_args(p), s);
+                for (int cg : kGrid) {
+                    p->tuning.grid_per_cu = cg;
+                    fmm::NearFarArgs a = nf_args(p);
+                    float t_min = -1.0f;
+                    for (int r = 0; r < repeats; r++) {
+                        fmm::near_far_prepare(p->nf, a, s);
+                        FMM_HIP_CHECK(hipEventRecord(e0, s));
+                        fmm::near_far_queue(p->nf, a, s);
+                        FMM_HIP_CHECK(hipEventRecord(e1, s));
+                        FMM_HIP_CHECK(hipEventSynchronize(e1));
+                        float ms = 0.0f;
+                        FMM_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                        if (t_min < 0.0f || ms < t_min) t_min = ms;
+                    }
+                    if (top_ms < 0.0f || t_min < top_ms) {
+                        top_ms = t_min;
+                        top = p->tuning;
+                    }
+                }
+            }
+            p->tuning = top;
+            fmm::build_near_far_mixed(p->nf, nf_args(p), s);
+        } catch (...) {
+            p->tuning = keep;
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            throw;
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        p->state = kStateUp;
+        if (best) *best = top;
+        if (best_ms) *best_ms = top_ms;
+        return FMM_OK;
+    });
+}
+
 fmm_status fmm_get_stage_times(const fmm_plan *cp, double *times, const char **names) {
     fmm_plan *p = const_cast<fmm_plan *>(cp);
     if (!p || !times) return FMM_ERR_INVALID_ARG;

@@ -28,7 +28,7 @@ FLAG_KEEP_TOPOLOGY = 2
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
            "fmm_backward", "fmm_sync", "fmm_get_counts", "fmm_copy_tree", "fmm_copy_lists", "fmm_get_tuning",
            "fmm_set_tuning", "fmm_get_stage_times", "fmm_status_string", "fmm_last_error", "fmm_graph_capture",
-           "fmm_graph_launch")
+           "fmm_graph_launch", "fmm_autotune")
 
 
 class fmm_params(ctypes.Structure):
@@ -71,6 +71,7 @@ def load_library():
     lib.fmm_sync.argtypes = [vp]
     lib.fmm_graph_capture.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.fmm_graph_launch.argtypes = [vp]
+    lib.fmm_autotune.argtypes = [vp, i32, P(fmm_tuning), P(ctypes.c_double)]
     lib.fmm_get_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64)]
     lib.fmm_copy_tree.argtypes = [vp, vp, vp, vp]
     lib.fmm_copy_lists.argtypes = [vp, vp, vp, vp, vp]
@@ -249,6 +250,14 @@ class Plan:
         t = fmm_tuning()
         self._call(self._lib.fmm_get_tuning, ctypes.byref(t))
         return {f: getattr(t, f) for f, _ in fmm_tuning._fields_}
+
+    def autotune(self, repeats=3):
+        """Sweep the work-queue settings on the current tree and multipoles
+        (after upward); keeps the fastest.  Returns (tuning dict, queue ms)."""
+        t = fmm_tuning()
+        ms = ctypes.c_double()
+        self._call(self._lib.fmm_autotune, ctypes.c_int32(int(repeats)), ctypes.byref(t), ctypes.byref(ms))
+        return {f: getattr(t, f) for f, _ in fmm_tuning._fields_}, ms.value
 
     def set_tuning(self, **kw):
         t = fmm_tuning()

@@ -83,3 +83,8 @@ def test_python_binding_validates_tensors():
     import torch
     with pytest.raises((TypeError, ValueError)):
         fmm._check_dev(torch.zeros(4, 3, dtype=torch.float64), "pos", shape_tail=(3,))   # host tensor
+
+
+def test_autotune_rejects_null_plan():
+    lib = fmm.load_library()
+    assert lib.fmm_autotune(None, 1, None, None) == -1

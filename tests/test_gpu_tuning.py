@@ -1,0 +1,58 @@
+"""The work-queue autotuner (fmm_autotune): it picks a setting from its
+candidate set, reports a positive kernel time, leaves the plan ready for
+fmm_evaluate, and the tuned results agree with the default setting's up to
+the FP32 rounding of the regrouped task sums."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1203_0889_amd import fmm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_autotune_mixed():
+    pos, q = W.uniform_cube(200000, 51)
+    plan = fmm.Plan(p=8, ncrit=64, theta=(1, 2), precision="mixed", device=0)
+    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    plan.upward()
+    ref = {k: v.cpu().numpy() for k, v in plan.evaluate().items() if v is not None}
+    tuning, ms = plan.autotune(repeats=2)
+    print("autotune:", tuning, ms, flush=True)
+    assert tuning["m2l_task_entries"] in (32, 64, 96, 128)
+    assert tuning["grid_per_cu"] in (1, 2, 3, 4)
+    assert ms > 0
+    assert plan.get_tuning() == tuning
+    out = {k: v.cpu().numpy() for k, v in plan.evaluate().items() if v is not None}
+    torch.cuda.synchronize()
+    assert rel(out["phi"], ref["phi"]) < 1e-6 and rel(out["field"], ref["field"]) < 1e-6
+    # a later build keeps the tuned setting
+    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    plan.upward()
+    out2 = {k: v.cpu().numpy() for k, v in plan.evaluate().items() if v is not None}
+    assert plan.get_tuning() == tuning
+    assert rel(out2["phi"], ref["phi"]) < 1e-6
+
+
+def test_autotune_fp64_reports_no_queue():
+    pos, q = W.uniform_cube(5000, 52)
+    plan = fmm.Plan(p=4, ncrit=64, theta=(1, 2), precision="fp64", device=0)
+    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    plan.upward()
+    tuning, ms = plan.autotune()
+    assert ms == -1.0
+
+
+def test_tuning_validation():
+    plan = fmm.Plan(p=4, precision="mixed", device=0)
+    with pytest.raises(fmm.FMMError):
+        plan.set_tuning(m2l_task_entries=0)
+    with pytest.raises(fmm.FMMError):
+        plan.set_tuning(grid_per_cu=9)
+    with pytest.raises(fmm.FMMError) as ei:
+        plan.autotune()
+    assert ei.value.status == -2
