@@ -69,9 +69,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="uniform1m_p8")
+    ap.add_argument("--workload", default="uniform1m_p8",
+                    help="uniform1m_p8 (default), plummer1m_p8, plummer4m_p10, uniform4k_p4 or batch256_p6")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--adjoint", action="store_true", help="time forward energy + fmm_backward per step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing leg")
+    ap.add_argument("--no-error", action="store_true", help="skip the error check against the direct sum")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default work-queue tuning")
     ap.add_argument("--cpu-n", type=int, default=524288, help="particles in the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -79,33 +82,99 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(pos, q, w, sample_idx, n_cpu):
-    """CPU leg: the FP64 oracle timed on a bounded sample of the same
-    workload, plus the oracle direct sum on the error sample."""
+def cpu_baseline(w, n_cpu):
+    """CPU leg: the FP64 oracle FMM timed on a bounded sample of the same
+    workload (same generator, p, ncrit, theta)."""
     import oracle
     from paper_1203_0889_amd import workloads as W
-    sub_pos, sub_q = W.uniform_cube(n_cpu, w["seed"]) if w["dist"] == "uniform" else W.plummer(n_cpu, w["seed"])
+    if w["dist"] == "uniform":
+        sub_pos, sub_q = W.uniform_cube(n_cpu, w["seed"])
+    else:
+        sub_pos, sub_q = W.plummer(n_cpu, w["seed"], equal_charges=w["dist"] == "plummer_equal")
     t0 = time.perf_counter()
     oracle.fmm(sub_pos, sub_q, w["p"], w["ncrit"], *w["theta"])
     t1 = time.perf_counter()
-    phi_d, fld_d = oracle.direct(pos, q, sample_idx)
-    base = {"value": n_cpu / (t1 - t0), "unit": "particles/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": n_cpu / (t1 - t0), "unit": "particles/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "oracle FMM (FP64, Cartesian Taylor, same p/ncrit/theta, %s) on N=%d instead of %d; %.2f s"
-                      % (w["dist"], n_cpu, len(q), t1 - t0)}
-    return base, phi_d, fld_d
+                      % (w["dist"], n_cpu, w["n"], t1 - t0)}
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d refused)" % a.gpus, file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_1203_0889_amd import fmm, workloads as W
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
+
+def queue_roofline(plan, stage_avg, p, n, precision, workload):
+    """Roofline of the dominant kernel and the algorithmic work of one evaluation."""
+    counts = plan.counts()
+    _, _, cells = plan.copy_tree()
+    mp, ms_, pp, ps = plan.copy_lists()
+    cnt = cells[:, 5]
+    tgt = np.repeat(np.arange(len(cnt)), np.diff(pp))
+    inter = int(np.sum(cnt[tgt] * cnt[ps])) - n
+    p2p_flop = P2P_FLOP * inter
+    m2l_f = m2l_flop(p) * counts["nm2l"]
+    t_p2p = stage_avg.get("p2p", 0.0) * 1e-3
+    t_m2l = stage_avg.get("m2l", 0.0) * 1e-3
+    if precision == "mixed":
+        # M2L and P2P run in one work-queue launch (stage "queue", HIP events
+        # on the plan's stream).  Its ALU bound: P2P on the FP32 vector units
+        # plus M2L on the bf16 matrix cores at three products per FP32-accurate
+        # product; the two do not issue concurrently on a SIMD, so their
+        # minimum times add.
+        tq = stage_avg.get("queue", 0.0) * 1e-3
+        t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
+        roof = {"bound": "alu", "achieved": (p2p_flop + m2l_f) / tq / 1e12 if tq > 0 else None,
+                "peak": (p2p_flop + m2l_f) / t_min / 1e12, "unit": "TFLOP/s", "traffic": committed_traffic(workload),
+                "kernel": "k_queue (P2P FP32 VALU + M2L split-bf16 MFMA)", "kernel_ms": tq * 1e3,
+                "peak_basis": "P2P flop / 157.3 TF fp32 vector + 3 x M2L flop / 2.5 PF bf16 dense MFMA"}
+    else:
+        dom, t, f = ("p2p", t_p2p, p2p_flop) if t_p2p >= t_m2l else ("m2l", t_m2l, m2l_f)
+        roof = {"bound": "alu", "achieved": f / t / 1e12 if t > 0 else None, "peak": PEAK["fp64"] / 1e12,
+                "unit": "TFLOP/s", "traffic": None, "kernel": "%s fp64" % dom}
+    if roof["achieved"] is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    work = {"ncell": counts["ncell"], "nleaf": counts["nleaf"], "m2l_pairs": counts["nm2l"],
+            "p2p_pairs": counts["np2p"], "p2p_interactions": inter, "p2p_flop": p2p_flop, "m2l_flop": m2l_f}
+    return roof, work
+
+
+def timed(step, plan, steps, warmup, torch):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stage_sum = {}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        for k, v in plan.stage_times().items():    # HIP events on the plan's stream
+            stage_sum[k] = stage_sum.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, {k: v / steps for k, v in stage_sum.items()}
+
+
+def calib_copy(mib, torch, dev):
+    if mib <= 0:
+        return
+    nel = mib * (1 << 20) // 4
+    src = torch.ones(nel, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def base_result(a, value, ms, unit_metric):
+    return {"metric": unit_metric, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64" if a.precision == "mixed" else "f64", "data": "synthetic"}
+
+
+def run_single(a, torch, fmm, W):
     pos, q, w = W.make(a.workload)
     n = len(q)
-    print("bench: workload %s N=%d precision %s" % (a.workload, n, a.precision), file=sys.stderr, flush=True)
+    print("bench: workload %s N=%d precision %s%s" % (a.workload, n, a.precision, " + adjoint" if a.adjoint else ""),
+          file=sys.stderr, flush=True)
     dev = torch.device("cuda", 0)
     dpos = torch.from_numpy(pos).to(dev)
     dq = torch.from_numpy(q).to(dev)
@@ -113,20 +182,10 @@ def main():
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     field = torch.empty((n, 3), dtype=torch.float64, device=dev)
     energy = torch.empty(1, dtype=torch.float64, device=dev)
-
-    if a.copy_calib_mib > 0:
-        nel = a.copy_calib_mib * (1 << 20) // 4
-        src = torch.ones(nel, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    def step():
-        plan.build_tree(dpos, dq)
-        plan.upward()
-        plan.evaluate_into(phi=phi, field=field, energy=energy)
+    gE = torch.ones(1, dtype=torch.float64, device=dev)
+    grads = [None, None]
+    bw_ms = [0.0]
+    calib_copy(a.copy_calib_mib, torch, dev)
 
     tuning = plan.get_tuning()
     if not a.no_autotune and a.precision == "mixed":
@@ -136,84 +195,152 @@ def main():
         tuning, tq_ms = plan.autotune(repeats=2)
         print("bench: autotuned %s (queue %.3f ms)" % (tuning, tq_ms), file=sys.stderr, flush=True)
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    stage_sum = {}
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-        for k, v in plan.stage_times().items():    # HIP events on the plan's stream
-            stage_sum[k] = stage_sum.get(k, 0.0) + v
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / a.steps
-    stage_avg = {k: v / a.steps for k, v in stage_sum.items()}
+    ev = [torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+
+    def step():
+        plan.build_tree(dpos, dq)
+        plan.upward()
+        plan.evaluate_into(phi=phi, field=field, energy=energy)
+        if a.adjoint:
+            ev[0].record()
+            grads[0], grads[1] = plan.backward(gE)
+            ev[1].record()
+            ev[1].synchronize()
+            bw_ms[0] += ev[0].elapsed_time(ev[1])
+
+    ms, stage_avg = timed(step, plan, a.steps, a.warmup, torch)
+    if a.adjoint:
+        stage_avg["backward"] = bw_ms[0] / (a.steps + a.warmup)
     print("bench: %.3f ms/step; stages %s" % (ms, json.dumps({k: round(v, 4) for k, v in stage_avg.items()})),
           file=sys.stderr, flush=True)
-
-    counts = plan.counts()
-    # algorithmic work of one evaluation
-    _, _, cells = plan.copy_tree()
-    mp, ms_, pp, ps = plan.copy_lists()
-    cnt = cells[:, 5]
-    tgt = np.repeat(np.arange(len(cnt)), np.diff(pp))
-    inter = int(np.sum(cnt[tgt] * cnt[ps])) - n
-    p2p_flop = P2P_FLOP * inter
-    m2l_f = m2l_flop(w["p"]) * counts["nm2l"]
-    t_p2p = stage_avg.get("p2p", 0.0) * 1e-3
-    t_m2l = stage_avg.get("m2l", 0.0) * 1e-3
-    if a.precision == "mixed":
-        # M2L and P2P run in one work-queue launch (stage "queue", HIP events
-        # on the plan's stream).  Its ALU bound: P2P on the FP32 vector units
-        # plus M2L on the bf16 matrix cores at three products per FP32-accurate
-        # product; the two do not issue concurrently on a SIMD, so their
-        # minimum times add.
-        tq = stage_avg.get("queue", 0.0) * 1e-3
-        t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
-        traffic = committed_traffic(a.workload)
-        roof = {"bound": "alu", "achieved": (p2p_flop + m2l_f) / tq / 1e12 if tq > 0 else None,
-                "peak": (p2p_flop + m2l_f) / t_min / 1e12, "unit": "TFLOP/s", "traffic": traffic,
-                "kernel": "k_queue (P2P FP32 VALU + M2L split-bf16 MFMA)", "kernel_ms": tq * 1e3,
-                "peak_basis": "P2P flop / 157.3 TF fp32 vector + 3 x M2L flop / 2.5 PF bf16 dense MFMA"}
+    roof, work = queue_roofline(plan, stage_avg, w["p"], n, a.precision, a.workload)
+    if a.adjoint:
+        metric = "particles/s per FMM energy + gradient (forward + fmm_backward), %s" % a.workload
     else:
-        dom, t, f = ("p2p", t_p2p, p2p_flop) if t_p2p >= t_m2l else ("m2l", t_m2l, m2l_f)
-        roof = {"bound": "alu", "achieved": f / t / 1e12 if t > 0 else None, "peak": PEAK["fp64"] / 1e12,
-                "unit": "TFLOP/s", "traffic": None, "kernel": "%s fp64" % dom}
-    if roof["achieved"] is not None:
-        roof["frac"] = roof["achieved"] / roof["peak"]
-
-    result = {
-        "metric": "particles/s per FMM evaluation at N=1M, rel. L2 error <=1e-4 vs FP64 direct",
-        "value": n / (ms * 1e-3),
-        "unit": "particles/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if a.precision == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {"workload": a.workload, "n": n, "p": w["p"], "ncrit": w["ncrit"],
-                   "theta": "%d/%d" % tuple(w["theta"]), "precision": a.precision,
-                   "distribution": w["dist"]},
-        "stages_ms": {k: round(v, 4) for k, v in stage_avg.items()},
-        "tuning": tuning,
-        "work": {"ncell": counts["ncell"], "nleaf": counts["nleaf"], "m2l_pairs": counts["nm2l"],
-                 "p2p_pairs": counts["np2p"], "p2p_interactions": inter, "p2p_flop": p2p_flop, "m2l_flop": m2l_f},
-        "roofline": roof,
-    }
+        metric = "particles/s per FMM evaluation at N=1M, rel. L2 error \u22641e-4 vs FP64 direct"
+        if a.workload != "uniform1m_p8":
+            metric = "particles/s per FMM evaluation, %s" % a.workload
+    result = base_result(a, n / (ms * 1e-3), ms, metric)
+    result["config"] = {"workload": a.workload, "n": n, "p": w["p"], "ncrit": w["ncrit"],
+                        "theta": "%d/%d" % tuple(w["theta"]), "precision": a.precision, "distribution": w["dist"],
+                        "adjoint": bool(a.adjoint)}
+    result["stages_ms"] = {k: round(v, 4) for k, v in stage_avg.items()}
+    result["tuning"] = tuning
+    result["work"] = work
+    result["roofline"] = roof
     if not a.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(w, min(a.cpu_n, n))
+    if not a.no_error:
+        import oracle
         sample = W.error_sample(n, w["seed"])
-        base, phi_d, fld_d = cpu_baseline(pos, q, w, sample, a.cpu_n)
-        result["cpu_baseline"] = base
-        ph = phi.cpu().numpy()[sample]
-        fl = field.cpu().numpy()[sample]
-        result["error"] = {"phi_rel_l2": float(np.linalg.norm(ph - phi_d) / np.linalg.norm(phi_d)),
-                           "field_rel_l2": float(np.linalg.norm(fl - fld_d) / np.linalg.norm(fld_d)),
-                           "sample": len(sample)}
+        phi_d, fld_d = oracle.direct(pos, q, sample)
+        err = {"phi_rel_l2": rel_l2(phi.cpu().numpy()[sample], phi_d),
+               "field_rel_l2": rel_l2(field.cpu().numpy()[sample], fld_d), "sample": len(sample)}
+        if a.adjoint:
+            # dE/dq = phi, dE/dx = -F of the exact (symmetric) direct sum
+            err["grad_q_rel_l2"] = rel_l2(grads[1].cpu().numpy()[sample], phi_d)
+            err["grad_pos_rel_l2"] = rel_l2(grads[0].cpu().numpy()[sample], -q[sample, None] * fld_d)
+        result["error"] = err
+    return result
+
+
+def run_batch(a, torch, fmm, W):
+    """256 instances (N_k = round(2^(10 + 6u)), even k uniform, odd k Plummer),
+    p = 6, ncrit = 64, theta = 1/2: one batched solve (one forest, one build,
+    one queue launch) per step, against 256 sequential single-instance solves
+    and against replays of the batched plan's captured graph."""
+    n_inst, p, ncrit, theta = 256, 6, 64, (1, 2)
+    pos, q, offsets = W.batch(n_inst, 5)
+    n = len(q)
+    offs = [int(o) for o in offsets]
+    print("bench: workload batch256_p6 N=%d in %d instances" % (n, n_inst), file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    dpos = torch.from_numpy(pos).to(dev)
+    dq = torch.from_numpy(q).to(dev)
+    plan = fmm.Plan(p=p, ncrit=ncrit, theta=theta, precision=a.precision, device=0)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    field = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    energy = torch.empty(n_inst, dtype=torch.float64, device=dev)
+    tuning = plan.get_tuning()
+    if not a.no_autotune and a.precision == "mixed":
+        plan.build_tree(dpos, dq, offs)
+        plan.upward()
+        tuning, _ = plan.autotune(repeats=2)
+
+    def step():
+        plan.build_tree(dpos, dq, offs)
+        plan.upward()
+        plan.evaluate_into(phi=phi, field=field, energy=energy)
+
+    ms, stage_avg = timed(step, plan, a.steps, a.warmup, torch)
+    roof, work = queue_roofline(plan, stage_avg, p, n, a.precision, "batch256_p6")
+    # graph replay of upward + evaluate on the built forest
+    plan.graph_capture(phi=phi, field=field, energy=energy)
+    for _ in range(a.warmup):
+        plan.graph_launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        plan.graph_launch()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    # 256 sequential single-instance solves (same tuning), one warm pass first
+    singles = [fmm.Plan(p=p, ncrit=ncrit, theta=theta, precision=a.precision, device=0) for _ in range(n_inst)]
+    for s_ in singles:
+        s_.set_tuning(**tuning)
+    views = [(dpos[offs[k]:offs[k + 1]], dq[offs[k]:offs[k + 1]]) for k in range(n_inst)]
+    sphi = torch.empty(n, dtype=torch.float64, device=dev)
+    sfld = torch.empty((n, 3), dtype=torch.float64, device=dev)
+
+    def sequential():
+        for k, s_ in enumerate(singles):
+            s_.build_tree(views[k][0], views[k][1])
+            s_.upward()
+            s_.evaluate_into(phi=sphi[offs[k]:offs[k + 1]], field=sfld[offs[k]:offs[k + 1]])
+
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sequential()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    print("bench: batched %.3f ms, graph replay %.3f ms, sequential %.3f ms" % (ms, graph_ms, seq_ms),
+          file=sys.stderr, flush=True)
+    result = base_result(a, n / (ms * 1e-3), ms, "particles/s, 256 instances solved as one batch (sum N_k / time)")
+    result["config"] = {"workload": "batch256_p6", "n": n, "instances": n_inst, "p": p, "ncrit": ncrit,
+                        "theta": "1/2", "precision": a.precision, "distribution": "even k uniform, odd k Plummer"}
+    result["stages_ms"] = {k: round(v, 4) for k, v in stage_avg.items()}
+    result["tuning"] = tuning
+    result["work"] = work
+    result["roofline"] = roof
+    result["sequential"] = {"ms": seq_ms, "particles_per_s": n / (seq_ms * 1e-3), "speedup_of_batch": seq_ms / ms}
+    result["graph_replay_upward_evaluate"] = {"ms": graph_ms, "particles_per_s": n / (graph_ms * 1e-3)}
+    if not a.no_error:
+        import oracle
+        errs = []
+        ph, fl = phi.cpu().numpy(), field.cpu().numpy()
+        for k in range(0, n_inst, 32):    # every 32nd instance: full direct sum if small, else 1024 targets
+            lo, hi = offs[k], offs[k + 1]
+            nk = hi - lo
+            tg = np.arange(nk) if nk <= 8192 else np.sort(np.random.default_rng(k).choice(nk, 1024, replace=False))
+            pd, fd = oracle.direct(pos[lo:hi], q[lo:hi], tg)
+            errs.append((rel_l2(ph[lo:hi][tg], pd), rel_l2(fl[lo:hi][tg], fd)))
+        result["error"] = {"phi_rel_l2_max": max(e[0] for e in errs), "field_rel_l2_max": max(e[1] for e in errs),
+                           "instances_checked": len(errs)}
+    return result
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d refused)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1203_0889_amd import fmm, workloads as W
+    if a.workload == "batch256_p6":
+        result = run_batch(a, torch, fmm, W)
+    else:
+        result = run_single(a, torch, fmm, W)
     print(json.dumps(result), flush=True)
 
 

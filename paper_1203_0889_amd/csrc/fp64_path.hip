@@ -67,34 +67,47 @@ __global__ void __launch_bounds__(kP2P64Threads)
 }
 
 // ---------------------------------------------------------------- M2L
-// One wave per target cell.  Per source cell B (class offset rho = (c_A -
-// c_B) / S_A, level difference delta = l_A - l_B):
-//   L~_n^m += (-1)^n sum_(k <= p) 2^(delta k) sum_l M~_k^l I_(n+k)^(m+l)(rho)
-// with the irregular solid harmonics (m >= 0, r^2 = |rho|^2, zeta = x + iy)
+// Per-pair M2L in FP64, balanced over pairs: a wave takes kPairChunk
+// consecutive entries of a CSR pair list, finds the owner of its first entry
+// by binary search, accumulates while the owner stays the same and adds each
+// owner's run into the output with FP64 atomics (so an owner with thousands
+// of pairs, like a large leaf facing a dense region, is spread over many
+// waves).  Per pair, with rho the class offset (c_A - c_B) / S_A and
+// delta = l_A - l_B of the forward pair A <- B:
+//   forward:  L~_n^m += (-1)^n sum_(k <= p) 2^(delta k) sum_l M~_k^l I_(n+k)^(m+l)(rho)
+//   adjoint:  the transpose of that real map (see below), owner = B.
+// The irregular solid harmonics (m >= 0, r^2 = |rho|^2, zeta = x + iy)
 //   I_0^0 = 1/r,  I_m^m = (2m-1) zeta I_(m-1)^(m-1) / r^2,
 //   I_(m+1)^m = (2m+1) z I_m^m / r^2,
 //   I_n^m = ((2n-1) z I_(n-1)^m - ((n-1)^2 - m^2) I_(n-2)^m) / r^2,
-// I_n^(-m) = (-1)^m conj(I_n^m).  Lane m evaluates column m of I into LDS,
-// then every lane accumulates its outputs (n, m) over all (k, l).
+// I_n^(-m) = (-1)^m conj(I_n^m): lane m evaluates column m into LDS, then
+// every lane accumulates its outputs over all input coefficients.
+//
+// Adjoint.  The forward map on the stored real coefficients is
+//   S_n^m = sum_k c_nk sum_(l=-k..k) M~_k^l I_(n+k)^(m+l),  c_nk = (-1)^n 2^(delta k),
+// with L_re(n, m) = Re S_n^m and L_im(n, m) = Im S_n^m (m > 0).  Writing the
+// dual of L as U_n^m = u_re + i u_im (U_n^0 real), the real inner product
+// <u, S(M)> equals <v, M> for
+//   V_k^l = sum_(n, m >= 0) c_nk [U_n^m conj(I_(n+k)^(m+l)) + (-1)^l conj(U_n^m) I_(n+k)^(m-l)]
+// (l > 0; v_re = Re V, v_im = Im V) and v_re(k, 0) = Re V_k^0 / 2 (the two
+// terms coincide for l = 0, where M~_k^0 is real).
 constexpr int kM2L64Threads = 64;
+constexpr int kPairChunk = 16;
 constexpr int kMaxI = (2 * kMaxP + 1) * (2 * kMaxP + 2) / 2;
 
 __device__ inline int tri(int n, int m) { return n * (n + 1) / 2 + m; }
 
+template <bool kAdjoint>
 __global__ void __launch_bounds__(kM2L64Threads)
-    k_m2l_fp64(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
-               const double *__restrict__ M, double *__restrict__ L, int accumulate) {
+    k_m2l_pairs(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                int64_t npair, const double *__restrict__ In, double *__restrict__ Out) {
     __shared__ double Ire[kMaxI], Iim[kMaxI];
-    __shared__ double Ms[ncoef(kMaxP)];
-    int32_t A = blockIdx.x;
-    if (A >= ncell) return;
-    if (accumulate && ptr[A] == ptr[A + 1]) return;
+    __shared__ double Xs[ncoef(kMaxP)];
     const int lane = threadIdx.x;
     const int P = ncoef(p);
     const int NC = (p + 1) * (p + 2) / 2;
     // this lane's outputs: complex index j = lane, lane + 64, lane + 128
     int on[3], om[3];
-    double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
     for (int s = 0; s < 3; s++) {
         int j = lane + 64 * s;
         on[s] = -1;
@@ -106,256 +119,181 @@ __global__ void __launch_bounds__(kM2L64Threads)
             om[s] = j - n * (n + 1) / 2;
         }
     }
-    int la = c.level[A];
-    int64_t SA = (int64_t)1 << (kLevels - la);
-    int64_t cax = (2 * (int64_t)c.ix[A] + 1) * SA, cay = (2 * (int64_t)c.iy[A] + 1) * SA,
-            caz = (2 * (int64_t)c.iz[A] + 1) * SA;
-    for (int32_t e = ptr[A]; e < ptr[A + 1]; e++) {
-        int32_t B = src[e];
-        int lb = c.level[B];
-        int64_t SB = (int64_t)1 << (kLevels - lb);
-        // rho in units of the target side: (C_A - C_B) / (2 S_A), exact
-        double rx = ldexp((double)(cax - (2 * (int64_t)c.ix[B] + 1) * SB), -(kLevels - la + 1));
-        double ry = ldexp((double)(cay - (2 * (int64_t)c.iy[B] + 1) * SB), -(kLevels - la + 1));
-        double rz = ldexp((double)(caz - (2 * (int64_t)c.iz[B] + 1) * SB), -(kLevels - la + 1));
-        int delta = la - lb;
-        __syncthreads();
-        for (int i = lane; i < P; i += 64) Ms[i] = M[(int64_t)B * P + i];
-        if (lane <= 2 * p) {
-            int m = lane, nmax = 2 * p;
-            double r2 = rx * rx + ry * ry + rz * rz;
-            double ir2 = 1.0 / r2;
-            double mr = 1.0 / sqrt(r2), mi = 0.0;  // I_m^m
-            for (int j = 1; j <= m; j++) {
-                double f = (2 * j - 1) * ir2;
-                double nr = (mr * rx - mi * ry) * f, ni = (mr * ry + mi * rx) * f;
-                mr = nr;
-                mi = ni;
+    const int64_t nchunk = (npair + kPairChunk - 1) / kPairChunk;
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int64_t e0 = ch * kPairChunk, e1 = e0 + kPairChunk < npair ? e0 + kPairChunk : npair;
+        // owner of e0: the last cell O with ptr[O] <= e0
+        int32_t lo = 0, hi = ncell;
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) >> 1;
+            if (ptr[mid] <= e0) lo = mid; else hi = mid - 1;
+        }
+        int32_t O = lo;
+        double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
+        auto flush = [&](int32_t owner) {
+            double *out = Out + (int64_t)owner * P;
+            for (int s = 0; s < 3; s++) {
+                const int n = on[s];
+                if (n < 0) continue;
+                const int m = om[s];
+                double vr = accr[s];
+                if (kAdjoint && m == 0) vr *= 0.5;
+                atomicAdd(&out[cidx_re(n, m)], vr);
+                if (m > 0) atomicAdd(&out[cidx_im(n, m)], acci[s]);
+                accr[s] = acci[s] = 0.0;
             }
-            Ire[tri(m, m)] = mr;
-            Iim[tri(m, m)] = mi;
-            double pr = 0, pi = 0, cr = mr, ci = mi;
-            for (int n = m + 1; n <= nmax; n++) {
-                double nr, ni;
-                if (n == m + 1) {
-                    double f = (2 * m + 1) * rz * ir2;
-                    nr = f * cr;
-                    ni = f * ci;
+        };
+        for (int64_t e = e0; e < e1; e++) {
+            if (e >= ptr[O + 1]) {
+                flush(O);
+                while (e >= ptr[O + 1]) O++;
+            }
+            const int32_t other = src[e];
+            const int32_t A = kAdjoint ? other : O, B = kAdjoint ? O : other;
+            const int la = c.level[A], lb = c.level[B];
+            const int64_t SA = (int64_t)1 << (kLevels - la), SB = (int64_t)1 << (kLevels - lb);
+            // rho in units of the target side: (C_A - C_B) / (2 S_A), exact
+            const double rx = ldexp((double)((2 * (int64_t)c.ix[A] + 1) * SA - (2 * (int64_t)c.ix[B] + 1) * SB),
+                                    -(kLevels - la + 1));
+            const double ry = ldexp((double)((2 * (int64_t)c.iy[A] + 1) * SA - (2 * (int64_t)c.iy[B] + 1) * SB),
+                                    -(kLevels - la + 1));
+            const double rz = ldexp((double)((2 * (int64_t)c.iz[A] + 1) * SA - (2 * (int64_t)c.iz[B] + 1) * SB),
+                                    -(kLevels - la + 1));
+            const int delta = la - lb;
+            __syncthreads();
+            for (int i = lane; i < P; i += 64) Xs[i] = In[(int64_t)other * P + i];
+            if (lane <= 2 * p) {
+                int m = lane, nmax = 2 * p;
+                double r2 = rx * rx + ry * ry + rz * rz;
+                double ir2 = 1.0 / r2;
+                double mr = 1.0 / sqrt(r2), mi = 0.0;  // I_m^m
+                for (int j = 1; j <= m; j++) {
+                    double f = (2 * j - 1) * ir2;
+                    double nr = (mr * rx - mi * ry) * f, ni = (mr * ry + mi * rx) * f;
+                    mr = nr;
+                    mi = ni;
+                }
+                Ire[tri(m, m)] = mr;
+                Iim[tri(m, m)] = mi;
+                double pr = 0, pi = 0, cr = mr, ci = mi;
+                for (int n = m + 1; n <= nmax; n++) {
+                    double nr, ni;
+                    if (n == m + 1) {
+                        double f = (2 * m + 1) * rz * ir2;
+                        nr = f * cr;
+                        ni = f * ci;
+                    } else {
+                        double aa = (2 * n - 1) * rz, bb = (double)((n - 1) * (n - 1) - m * m);
+                        nr = (aa * cr - bb * pr) * ir2;
+                        ni = (aa * ci - bb * pi) * ir2;
+                    }
+                    Ire[tri(n, m)] = nr;
+                    Iim[tri(n, m)] = ni;
+                    pr = cr;
+                    pi = ci;
+                    cr = nr;
+                    ci = ni;
+                }
+            }
+            __syncthreads();
+            for (int s = 0; s < 3; s++) {
+                const int n = on[s];
+                if (n < 0) continue;
+                const int m = om[s];
+                double sr = 0, si = 0;
+                if (!kAdjoint) {
+                    for (int k = 0; k <= p; k++) {
+                        const double fk = ldexp(1.0, delta * k);
+                        double tr = 0, ti = 0;
+                        for (int l = -k; l <= k; l++) {
+                            const int al = l < 0 ? -l : l;
+                            double mre = Xs[cidx_re(k, al)], mim = al > 0 ? Xs[cidx_im(k, al)] : 0.0;
+                            if (l < 0) {
+                                mim = -mim;
+                                if (al & 1) {
+                                    mre = -mre;
+                                    mim = -mim;
+                                }
+                            }
+                            const int nn = n + k, mm = m + l;
+                            const int amm = mm < 0 ? -mm : mm;
+                            double ire = Ire[tri(nn, amm)], iim = Iim[tri(nn, amm)];
+                            if (mm < 0) {
+                                iim = -iim;
+                                if (amm & 1) {
+                                    ire = -ire;
+                                    iim = -iim;
+                                }
+                            }
+                            tr += mre * ire - mim * iim;
+                            ti += mre * iim + mim * ire;
+                        }
+                        sr += fk * tr;
+                        si += fk * ti;
+                    }
+                    if (n & 1) {
+                        sr = -sr;
+                        si = -si;
+                    }
                 } else {
-                    double a = (2 * n - 1) * rz, b = (double)((n - 1) * (n - 1) - m * m);
-                    nr = (a * cr - b * pr) * ir2;
-                    ni = (a * ci - b * pi) * ir2;
-                }
-                Ire[tri(n, m)] = nr;
-                Iim[tri(n, m)] = ni;
-                pr = cr;
-                pi = ci;
-                cr = nr;
-                ci = ni;
-            }
-        }
-        __syncthreads();
-        for (int s = 0; s < 3; s++) {
-            int n = on[s];
-            if (n < 0) continue;
-            int m = om[s];
-            double sr = 0, si = 0;
-            for (int k = 0; k <= p; k++) {
-                double fk = ldexp(1.0, delta * k);
-                double tr = 0, ti = 0;
-                for (int l = -k; l <= k; l++) {
-                    int al = l < 0 ? -l : l;
-                    double mre = Ms[cidx_re(k, al)], mim = al > 0 ? Ms[cidx_im(k, al)] : 0.0;
-                    if (l < 0) {
-                        mim = -mim;
-                        if (al & 1) {
-                            mre = -mre;
-                            mim = -mim;
+                    // output (k, l) = (n, m) of this lane; inputs (nu, mu) of the dual
+                    const int k = n, l = m;
+                    const double fk = ldexp(1.0, delta * k);
+                    const double sl = (l & 1) ? -1.0 : 1.0;
+                    for (int nu = 0; nu <= p; nu++) {
+                        const double cn = (nu & 1) ? -fk : fk;
+                        double tr = 0, ti = 0;
+                        for (int mu = 0; mu <= nu; mu++) {
+                            const double ur = Xs[cidx_re(nu, mu)], ui = mu > 0 ? Xs[cidx_im(nu, mu)] : 0.0;
+                            const int nn = nu + k;
+                            const double i1r = Ire[tri(nn, mu + l)], i1i = Iim[tri(nn, mu + l)];
+                            const int d = mu - l, ad = d < 0 ? -d : d;
+                            double i2r = Ire[tri(nn, ad)], i2i = Iim[tri(nn, ad)];
+                            if (d < 0) {
+                                i2i = -i2i;
+                                if (ad & 1) {
+                                    i2r = -i2r;
+                                    i2i = -i2i;
+                                }
+                            }
+                            // U conj(I1) + sl conj(U) I2
+                            tr += (ur * i1r + ui * i1i) + sl * (ur * i2r + ui * i2i);
+                            ti += (ui * i1r - ur * i1i) + sl * (ur * i2i - ui * i2r);
                         }
+                        sr += cn * tr;
+                        si += cn * ti;
                     }
-                    int nn = n + k, mm = m + l;
-                    int amm = mm < 0 ? -mm : mm;
-                    double ire = Ire[tri(nn, amm)], iim = Iim[tri(nn, amm)];
-                    if (mm < 0) {
-                        iim = -iim;
-                        if (amm & 1) {
-                            ire = -ire;
-                            iim = -iim;
-                        }
-                    }
-                    tr += mre * ire - mim * iim;
-                    ti += mre * iim + mim * ire;
                 }
-                sr += fk * tr;
-                si += fk * ti;
-            }
-            if (n & 1) {
-                sr = -sr;
-                si = -si;
-            }
-            accr[s] += sr;
-            acci[s] += si;
-        }
-    }
-    double *out = L + (int64_t)A * P;
-    for (int s = 0; s < 3; s++) {
-        int n = on[s];
-        if (n < 0) continue;
-        int m = om[s];
-        if (accumulate) {
-            out[cidx_re(n, m)] += accr[s];
-            if (m > 0) out[cidx_im(n, m)] += acci[s];
-        } else {
-            out[cidx_re(n, m)] = accr[s];
-            if (m > 0) out[cidx_im(n, m)] = acci[s];
-        }
-    }
-}
-
-// ---------------------------------------------------------------- M2L adjoint
-// One wave per source cell B, walking the pairs (A <- B) of the forward list
-// (the transposed CSR).  The forward map on the stored real coefficients is
-//   S_n^m = sum_k c_nk sum_(l=-k..k) M~_k^l I_(n+k)^(m+l),  c_nk = (-1)^n 2^(delta k),
-// with L_re(n, m) = Re S_n^m and L_im(n, m) = Im S_n^m (m > 0).  Writing the
-// dual of L as U_n^m = u_re + i u_im (U_n^0 real), the real inner product
-// <u, S(M)> equals <v, M> for
-//   V_k^l = sum_(n, m >= 0) c_nk [U_n^m conj(I_(n+k)^(m+l)) + (-1)^l conj(U_n^m) I_(n+k)^(m-l)]
-// (l > 0; v_re = Re V, v_im = Im V) and v_re(k, 0) = Re V_k^0 / 2 (the two
-// terms coincide for l = 0, where M~_k^0 is real).
-__global__ void __launch_bounds__(kM2L64Threads)
-    k_m2l_fp64_adjoint(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr,
-                       const int32_t *__restrict__ src, const double *__restrict__ Lam, double *__restrict__ Mu,
-                       int add) {
-    __shared__ double Ire[kMaxI], Iim[kMaxI];
-    __shared__ double Us[ncoef(kMaxP)];
-    int32_t B = blockIdx.x;
-    if (B >= ncell) return;
-    if (add && ptr[B] == ptr[B + 1]) return;
-    const int lane = threadIdx.x;
-    const int P = ncoef(p);
-    const int NC = (p + 1) * (p + 2) / 2;
-    int ok_[3], ol_[3];
-    double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
-    for (int s = 0; s < 3; s++) {
-        int j = lane + 64 * s;
-        ok_[s] = -1;
-        ol_[s] = 0;
-        if (j < NC) {
-            int n = 0;
-            while ((n + 1) * (n + 2) / 2 <= j) n++;
-            ok_[s] = n;
-            ol_[s] = j - n * (n + 1) / 2;
-        }
-    }
-    const int lb = c.level[B];
-    const int64_t SB = (int64_t)1 << (kLevels - lb);
-    const int64_t cbx = (2 * (int64_t)c.ix[B] + 1) * SB, cby = (2 * (int64_t)c.iy[B] + 1) * SB,
-                  cbz = (2 * (int64_t)c.iz[B] + 1) * SB;
-    for (int32_t e = ptr[B]; e < ptr[B + 1]; e++) {
-        const int32_t A = src[e];
-        const int la = c.level[A];
-        const int64_t SA = (int64_t)1 << (kLevels - la);
-        // the forward pair's rho = (C_A - C_B) / (2 S_A), exact
-        double rx = ldexp((double)((2 * (int64_t)c.ix[A] + 1) * SA - cbx), -(kLevels - la + 1));
-        double ry = ldexp((double)((2 * (int64_t)c.iy[A] + 1) * SA - cby), -(kLevels - la + 1));
-        double rz = ldexp((double)((2 * (int64_t)c.iz[A] + 1) * SA - cbz), -(kLevels - la + 1));
-        const int delta = la - lb;
-        __syncthreads();
-        for (int i = lane; i < P; i += 64) Us[i] = Lam[(int64_t)A * P + i];
-        if (lane <= 2 * p) {
-            int m = lane, nmax = 2 * p;
-            double r2 = rx * rx + ry * ry + rz * rz;
-            double ir2 = 1.0 / r2;
-            double mr = 1.0 / sqrt(r2), mi = 0.0;
-            for (int j = 1; j <= m; j++) {
-                double f = (2 * j - 1) * ir2;
-                double nr = (mr * rx - mi * ry) * f, ni = (mr * ry + mi * rx) * f;
-                mr = nr;
-                mi = ni;
-            }
-            Ire[tri(m, m)] = mr;
-            Iim[tri(m, m)] = mi;
-            double pr = 0, pi = 0, cr = mr, ci = mi;
-            for (int n = m + 1; n <= nmax; n++) {
-                double nr, ni;
-                if (n == m + 1) {
-                    double f = (2 * m + 1) * rz * ir2;
-                    nr = f * cr;
-                    ni = f * ci;
-                } else {
-                    double a = (2 * n - 1) * rz, b = (double)((n - 1) * (n - 1) - m * m);
-                    nr = (a * cr - b * pr) * ir2;
-                    ni = (a * ci - b * pi) * ir2;
-                }
-                Ire[tri(n, m)] = nr;
-                Iim[tri(n, m)] = ni;
-                pr = cr;
-                pi = ci;
-                cr = nr;
-                ci = ni;
+                accr[s] += sr;
+                acci[s] += si;
             }
         }
-        __syncthreads();
-        for (int s = 0; s < 3; s++) {
-            const int k = ok_[s];
-            if (k < 0) continue;
-            const int l = ol_[s];
-            const double fk = ldexp(1.0, delta * k);
-            const double sl = (l & 1) ? -1.0 : 1.0;
-            double vr = 0, vi = 0;
-            for (int n = 0; n <= p; n++) {
-                const double cn = (n & 1) ? -fk : fk;
-                double tr = 0, ti = 0;
-                for (int m = 0; m <= n; m++) {
-                    const double ur = Us[cidx_re(n, m)], ui = m > 0 ? Us[cidx_im(n, m)] : 0.0;
-                    const int nn = n + k;
-                    // I1 = I_nn^(m+l)
-                    const double i1r = Ire[tri(nn, m + l)], i1i = Iim[tri(nn, m + l)];
-                    // I2 = I_nn^(m-l), negative order by I^-mu = (-1)^mu conj(I^mu)
-                    const int mu = m - l, amu = mu < 0 ? -mu : mu;
-                    double i2r = Ire[tri(nn, amu)], i2i = Iim[tri(nn, amu)];
-                    if (mu < 0) {
-                        i2i = -i2i;
-                        if (amu & 1) {
-                            i2r = -i2r;
-                            i2i = -i2i;
-                        }
-                    }
-                    // U conj(I1) + sl conj(U) I2
-                    tr += (ur * i1r + ui * i1i) + sl * (ur * i2r + ui * i2i);
-                    ti += (ui * i1r - ur * i1i) + sl * (ur * i2i - ui * i2r);
-                }
-                vr += cn * tr;
-                vi += cn * ti;
-            }
-            accr[s] += vr;
-            acci[s] += vi;
-        }
-    }
-    double *out = Mu + (int64_t)B * P;
-    for (int s = 0; s < 3; s++) {
-        const int k = ok_[s];
-        if (k < 0) continue;
-        const int l = ol_[s];
-        const double vr = l == 0 ? 0.5 * accr[s] : accr[s];
-        if (add) {
-            out[cidx_re(k, l)] += vr;
-            if (l > 0) out[cidx_im(k, l)] += acci[s];
-        } else {
-            out[cidx_re(k, l)] = vr;
-            if (l > 0) out[cidx_im(k, l)] = acci[s];
-        }
+        flush(O);
     }
 }
 
 }  // namespace
 
-void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *ptr_t, const int32_t *src_t,
-                             const double *Lam, double *Mu, int add, hipStream_t s) {
-    if (ncell == 0) return;
-    hipLaunchKernelGGL(k_m2l_fp64_adjoint, dim3(ncell), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr_t, src_t, Lam,
-                       Mu, add);
+namespace {
+void launch_pairs(bool adjoint, Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
+                  const double *In, double *Out, hipStream_t s) {
+    if (ncell == 0 || npair <= 0) return;
+    const int64_t nchunk = (npair + kPairChunk - 1) / kPairChunk;
+    const int grid = (int)(nchunk < 65536 ? nchunk : 65536);
+    if (adjoint)
+        hipLaunchKernelGGL(k_m2l_pairs<true>, dim3(grid), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, npair,
+                           In, Out);
+    else
+        hipLaunchKernelGGL(k_m2l_pairs<false>, dim3(grid), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, npair,
+                           In, Out);
     FMM_LAUNCH_CHECK();
+}
+}  // namespace
+
+void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *ptr_t, const int32_t *src_t,
+                             int64_t npair, const double *Lam, double *Mu, int add, hipStream_t s) {
+    if (!add) fill_zero(Mu, (size_t)ncell * ncoef(p) * sizeof(double), s);
+    launch_pairs(true, g, ncell, p, ptr_t, src_t, npair, Lam, Mu, s);
 }
 
 void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
@@ -366,18 +304,15 @@ void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_
     FMM_LAUNCH_CHECK();
 }
 
-void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
-                     double *L, hipStream_t s) {
-    if (ncell == 0) return;
-    hipLaunchKernelGGL(k_m2l_fp64, dim3(ncell), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, M, L, 0);
-    FMM_LAUNCH_CHECK();
+void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
+                     const double *M, double *L, hipStream_t s) {
+    fill_zero(L, (size_t)ncell * ncoef(p) * sizeof(double), s);
+    launch_pairs(false, g, ncell, p, ptr, src, npair, M, L, s);
 }
 
-void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
-                         double *L, hipStream_t s) {
-    if (ncell == 0) return;
-    hipLaunchKernelGGL(k_m2l_fp64, dim3(ncell), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, M, L, 1);
-    FMM_LAUNCH_CHECK();
+void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
+                         const double *M, double *L, hipStream_t s) {
+    launch_pairs(false, g, ncell, p, ptr, src, npair, M, L, s);
 }
 
 }  // namespace fmm

@@ -48,7 +48,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.pcid.grow(np1 * 4));
     FMM_HIP_CHECK(st.xflag.grow(np1 * 4));
     FMM_HIP_CHECK(st.xscan.grow(np1 * 4));
-    FMM_HIP_CHECK(st.cnt.grow(16 * 4));
+    FMM_HIP_CHECK(st.cnt.grow(64 * 4));  // [0..4] sizes, [16..32] per-XCD counts, [40..55] queue heads
     int64_t tmp_elems = std::max<int64_t>({(int64_t)scan_tmp_elems(kDenseKeys + 1), (int64_t)scan_tmp_elems(np1),
                                            (int64_t)radix_tmp_elems(ncell + 1), (int64_t)scan_tmp_elems(ncell + 1)});
     FMM_HIP_CHECK(st.tmp.grow(tmp_elems * 4));
@@ -162,6 +162,8 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
 
 void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
+    if (a.n > 0 && (!a.M || !a.L || !a.phi || !a.fld || !a.qs))
+        throw std::runtime_error("mixed near/far stage: an input or output workspace is missing");
     const int P = ncoef(a.p);
     const int32_t ncell = a.ncell;
     FMM_HIP_CHECK(st.M32.grow((size_t)(ncell + 1) * queue_mrow_elems(a.p) * 2));
@@ -173,6 +175,9 @@ void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
 }
 
 void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
+    if (a.n > 0 && (!a.L || !a.phi || !a.fld || !st.M32.ptr || !st.pf.ptr))
+        throw std::runtime_error("mixed near/far stage: queue inputs not prepared");
     const int P = ncoef(a.p);
     const int32_t ncell = a.ncell;
     QueueArgs q;
@@ -207,9 +212,10 @@ void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (st.nextra <= 0) return;
     if (a.transposed)
-        launch_m2l_fp64_adjoint(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, 1, s);
+        launch_m2l_fp64_adjoint(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), st.nextra, a.M, a.L,
+                                1, s);
     else
-        launch_m2l_fp64_add(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), a.M, a.L, s);
+        launch_m2l_fp64_add(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), st.nextra, a.M, a.L, s);
 }
 
 void release_near_far(NearFarState &st) {

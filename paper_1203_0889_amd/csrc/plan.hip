@@ -410,8 +410,8 @@ void do_upward(fmm_plan *p) {
     mark(p, ST_M2M);
 }
 
-void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double *energy) {
-    hipStream_t s = p->stream;
+// Workspaces of the evaluate stage (locals, near and far fields).
+void ensure_eval_buffers(fmm_plan *p) {
     const int P = fmm::ncoef(p->prm.p);
     const size_t nn = (size_t)std::max<int64_t>(p->n, 1);
     FMM_HIP_CHECK(p->L.grow((size_t)std::max<int64_t>(p->ncell, 1) * P * 8));
@@ -419,11 +419,17 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     FMM_HIP_CHECK(p->fld_near.grow(nn * 24));
     FMM_HIP_CHECK(p->phi_far.grow(nn * 8));
     FMM_HIP_CHECK(p->fld_far.grow(nn * 24));
+}
+
+void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double *energy) {
+    hipStream_t s = p->stream;
+    ensure_eval_buffers(p);
     fmm::Geometry g = geom(p);
     const int32_t ncell = (int32_t)p->ncell;
     record(p, ST_M2L);
     if (p->prm.precision == FMM_PREC_FP64) {
-        fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->M.as<double>(),
+        fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
+                             p->M.as<double>(),
                              p->L.as<double>(), s);
         mark(p, ST_M2L);
         fmm::launch_p2p_fp64(g, ncell, p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(), p->xs.as<double>(),
@@ -536,7 +542,7 @@ void do_backward(fmm_plan *p, const double *gE, double *grad_pos, double *grad_q
                               p->lam.as<double>(), p->m2m_part.as<double>(), s);
     // M2L^T and P2P^T
     if (p->prm.precision == FMM_PREC_FP64) {
-        fmm::launch_m2l_fp64_adjoint(g, ncell, pp, p->m2l_t_ptr.as<int32_t>(), p->m2l_t_src.as<int32_t>(),
+        fmm::launch_m2l_fp64_adjoint(g, ncell, pp, p->m2l_t_ptr.as<int32_t>(), p->m2l_t_src.as<int32_t>(), p->nm2l,
                                      p->lam.as<double>(), p->mu.as<double>(), 0, s);
         fmm::launch_p2p_fp64(g, ncell, p->p2p_t_ptr.as<int32_t>(), p->p2p_t_src.as<int32_t>(), p->xs.as<double>(),
                              p->ys.as<double>(), p->zs.as<double>(), p->wts.as<double>(), p->psi_near.as<double>(),
@@ -888,6 +894,7 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
         hipStream_t s = p->stream;
         drop_graph(p);
         p->adj_ready = false;
+        ensure_eval_buffers(p);   // the queue writes the locals and the near field
         static const int kEntries[] = {32, 64, 96, 128};
         static const int kGrid[] = {1, 2, 3, 4};
         hipEvent_t e0, e1;

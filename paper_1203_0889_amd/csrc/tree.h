@@ -95,17 +95,19 @@ std::vector<double> transpose_ops(const std::vector<double> &ops, int p);
 // ---- near / far field, FP64 plain path
 void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
                      const double *ys, const double *zs, const double *qs, double *phi, double *fld, hipStream_t s);
-void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
-                     double *L, hipStream_t s);
-// Same kernel, adding into L (used for the pairs the MFMA path leaves out).
-void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, const double *M,
-                         double *L, hipStream_t s);
+// Per-pair FP64 M2L over the CSR list (ptr, src) of npair pairs (target-owned),
+// balanced over pairs; overwrites L (cells without pairs get zero).
+void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
+                     const double *M, double *L, hipStream_t s);
+// Same, adding into L (used for the pairs the MFMA path leaves out).
+void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
+                         const double *M, double *L, hipStream_t s);
 // Adjoint of the M2L stage over the transposed list (ptr_t, src_t): for every
 // pair (A <- B) of the forward list, Mu_B += T_(A<-B)^T Lam_A, with T the real
 // (p+1)^2 x (p+1)^2 matrix the forward kernel applies.  Owner = source cell B.
 // add = 0 overwrites Mu (cells without pairs get zero), add = 1 accumulates.
 void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *ptr_t, const int32_t *src_t,
-                             const double *Lam, double *Mu, int add, hipStream_t s);
+                             int64_t npair, const double *Lam, double *Mu, int add, hipStream_t s);
 
 // ---- output
 void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,

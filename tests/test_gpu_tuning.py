@@ -56,3 +56,21 @@ def test_tuning_validation():
     with pytest.raises(fmm.FMMError) as ei:
         plan.autotune()
     assert ei.value.status == -2
+
+
+def test_autotune_right_after_upward():
+    """Regression: the autotuner must size the evaluate workspaces itself
+    (here no fmm_evaluate has run on the plan yet)."""
+    pos, q = W.uniform_cube(60000, 53)
+    plan = fmm.Plan(p=8, ncrit=64, theta=(1, 2), precision="mixed", device=0)
+    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    plan.upward()
+    tuning, ms = plan.autotune(repeats=1)
+    assert ms > 0
+    out = plan.evaluate()
+    ref = fmm.Plan(p=8, ncrit=64, theta=(1, 2), precision="mixed", device=0)
+    ref.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    ref.upward()
+    r = ref.evaluate()
+    torch.cuda.synchronize()
+    assert rel(out["phi"].cpu().numpy(), r["phi"].cpu().numpy()) < 1e-6
