@@ -41,11 +41,15 @@ __device__ inline int dense_key(int delta, int rx, int ry, int rz) {
     return (((delta + 1) * kRhoSpan + (rx + kRhoMax)) * kRhoSpan + (ry + kRhoMax)) * kRhoSpan + (rz + kRhoMax);
 }
 
-// Class key of every M2L pair in CSR order; marks used dense keys.
+// Class key of every M2L pair in CSR order (one wave per owner cell);
+// marks used dense keys (read first: nearly every key is already marked, and
+// a read leaves the cache line shared) and counts the owner's pairs outside
+// the table in xcount[A].
 __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr,
                                const int32_t *__restrict__ src, int32_t *__restrict__ pkey,
-                               int32_t *__restrict__ used) {
+                               int32_t *__restrict__ used, int32_t *__restrict__ xcount) {
     for (int32_t A = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; A < ncell; A += gridDim.x * blockDim.x / 64) {
+        int nx = 0;
         int la = c.level[A];
         int64_t SA = (int64_t)1 << (kLevels - la);
         int64_t ca[3] = {(2 * (int64_t)c.ix[A] + 1) * SA, (2 * (int64_t)c.iy[A] + 1) * SA,
@@ -60,8 +64,15 @@ __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__res
             int rz = (int)((ca[2] - (2 * (int64_t)c.iz[B] + 1) * SB) / smin);
             int k = dense_key(la - lb, rx, ry, rz);
             pkey[e] = k;
-            if (k >= 0) used[k] = 1;
+            if (k >= 0) {
+                if (!used[k]) used[k] = 1;
+            } else {
+                nx++;
+            }
         }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) nx += __shfl_xor(nx, d, 64);
+        if ((threadIdx.x & 63) == 0) xcount[A] = nx;
     }
 }
 
@@ -206,11 +217,10 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
 
 // Compact id of a pair's class (rank of its dense key among used keys).
 __global__ void k_pair_cid(const int32_t *__restrict__ pkey, int64_t npair, const int32_t *__restrict__ cid_of,
-                           int32_t *__restrict__ pcid, int32_t *__restrict__ xflag) {
+                           int32_t *__restrict__ pcid) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npair; e += (int64_t)gridDim.x * blockDim.x) {
         int k = pkey[e];
         pcid[e] = k >= 0 ? cid_of[k] : -1;
-        xflag[e] = k < 0 ? 1 : 0;
     }
 }
 
@@ -230,10 +240,10 @@ __global__ void k_cid_tables(const int32_t *__restrict__ used_scan, const int32_
 // of the particle order, octant, cell).  The eighth (bits 35..37) later
 // selects the XCD whose task list the group joins.
 __global__ void k_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *__restrict__ ptr,
-                              const int32_t *__restrict__ xscan, uint64_t *__restrict__ tkey,
+                              const int32_t *__restrict__ xptr, uint64_t *__restrict__ tkey,
                               int32_t *__restrict__ has) {
     for (int32_t A = blockIdx.x * blockDim.x + threadIdx.x; A < ncell; A += gridDim.x * blockDim.x) {
-        int32_t nb = (ptr[A + 1] - ptr[A]) - (xscan[ptr[A + 1]] - xscan[ptr[A]]);
+        int32_t nb = (ptr[A + 1] - ptr[A]) - (xptr[A + 1] - xptr[A]);
         has[A] = nb > 0;
         int oct = (c.ix[A] & 1) | ((c.iy[A] & 1) << 1) | ((c.iz[A] & 1) << 2);
         int c8 = n > 0 ? (int)(((int64_t)c.first[A] * 8) / n) : 0;
@@ -248,6 +258,19 @@ __global__ void k_target_keys(CellArrays c, int32_t ncell, int64_t n, const int3
 // (2) per group, exclusive popcount prefix over its bitmap words (entry
 // rank of every class), (3) write every pair's source into its entry slot.
 constexpr int kSplit = 8;
+
+// Block b of a group kernel -> (group, split).  Workgroups are dispatched
+// round-robin over the 8 XCDs (XCD = b mod 8), so mapping the kSplit blocks
+// of group g to b = ((g / 8) kSplit + split) 8 + g mod 8 keeps a group on one
+// XCD: its entry rows are then written through a single L2, which merges the
+// scattered slot writes into whole lines before they go to memory.
+__device__ inline void group_split_of(int b, int *g, int *split) {
+    const int i = b >> 3;
+    *g = (i / kSplit) * 8 + (b & 7);
+    *split = i % kSplit;
+}
+
+inline int group_blocks(int32_t ngroup) { return ((ngroup + 7) / 8) * 8 * kSplit; }
 
 // slot (target) of flattened pair index idx: pre[s] <= idx < pre[s+1]
 __device__ inline int slot_of_index(const int32_t *pre, int nt, int32_t idx) {
@@ -281,12 +304,14 @@ __global__ void __launch_bounds__(256) k_group_mark(const uint64_t *__restrict__
                                                     int nwords, uint32_t *__restrict__ gbits) {
     extern __shared__ uint32_t lbits[];
     __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L];
-    const int g = blockIdx.x;
+    int g, split;
+    group_split_of(blockIdx.x, &g, &split);
+    if (g * kGroupM2L >= ntarget) return;
     for (int w = threadIdx.x; w < nwords; w += blockDim.x) lbits[w] = 0u;
     int nt;
     load_group(tsorted, ntarget, g, ptr, pre, tgt, &nt);
     const int32_t total = pre[nt];
-    for (int32_t idx = blockIdx.y * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
+    for (int32_t idx = split * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
         int s = slot_of_index(pre, nt, idx);
         int32_t cid = pcid[ptr[tgt[s]] + (idx - pre[s])];
         if (cid >= 0) atomicOr(&lbits[cid >> 5], 1u << (cid & 31));
@@ -335,16 +360,18 @@ __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__
                                                     const int32_t *__restrict__ goff, int32_t *__restrict__ ecls,
                                                     int32_t *__restrict__ esrc, int32_t *__restrict__ gtarget) {
     __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L];
-    const int g = blockIdx.x;
+    int g, split;
+    group_split_of(blockIdx.x, &g, &split);
+    if (g * kGroupM2L >= ntarget) return;
     int nt;
     load_group(tsorted, ntarget, g, ptr, pre, tgt, &nt);
-    if (blockIdx.y == 0 && threadIdx.x < kGroupM2L)
+    if (split == 0 && threadIdx.x < kGroupM2L)
         gtarget[(int64_t)g * kGroupM2L + threadIdx.x] = threadIdx.x < nt ? tgt[threadIdx.x] : -1;
     const int32_t total = pre[nt];
     const uint32_t *bits = gbits + (int64_t)g * nwords;
     const uint32_t *wpre = gwpre + (int64_t)g * nwords;
     const int32_t base = goff[g];
-    if (blockIdx.y == 0)
+    if (split == 0)
         for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
             uint32_t b = bits[w];
             int32_t ent = base + (int32_t)wpre[w];
@@ -354,7 +381,7 @@ __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__
                 b &= b - 1;
             }
         }
-    for (int32_t idx = blockIdx.y * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
+    for (int32_t idx = split * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
         int s = slot_of_index(pre, nt, idx);
         int32_t e = ptr[tgt[s]] + (idx - pre[s]);
         int32_t cid = pcid[e];
@@ -371,15 +398,18 @@ __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__
 // own groups chunk by chunk: concurrent workgroups then share class
 // operators in that XCD's L2.
 __global__ void k_make_tasks(const int32_t *__restrict__ gcount, const int32_t *__restrict__ goff, int32_t ngroup,
-                             int chunk, const int32_t *__restrict__ toff, const uint64_t *__restrict__ tsorted,
-                             int4 *__restrict__ tasks, uint64_t *__restrict__ tkeys, uint32_t *__restrict__ tidx,
+                             int chunk, int jbits, const int32_t *__restrict__ toff,
+                             const uint64_t *__restrict__ tsorted, int4 *__restrict__ tasks,
+                             uint64_t *__restrict__ tkeys, uint32_t *__restrict__ tidx,
                              int32_t *__restrict__ xcd_count) {
     for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroup; g += gridDim.x * blockDim.x) {
         int32_t n = gcount[g], t = toff[g];
         int xcd = (int)((tsorted[(int64_t)g * kGroupM2L] >> 35) & 7ull);
         for (int32_t e = 0, j = 0; e < n; e += chunk, j++, t++) {
             tasks[t] = make_int4(g, goff[g] + e, goff[g] + (e + chunk < n ? e + chunk : n), 0);
-            tkeys[t] = ((uint64_t)xcd << 56) | ((uint64_t)j << 32) | (uint32_t)t;
+            // t is already in (group, chunk) order: a stable sort on the
+            // (XCD, chunk index) bits above it yields (XCD, chunk, task)
+            tkeys[t] = ((uint64_t)xcd << (32 + jbits)) | ((uint64_t)j << 32) | (uint32_t)t;
             tidx[t] = (uint32_t)t;
             atomicAdd(&xcd_count[xcd], 1);
         }
@@ -396,23 +426,31 @@ __global__ void k_task_counts(const int32_t *__restrict__ gcount, int32_t ngroup
         tcount[g] = (gcount[g] + chunk - 1) / chunk;
 }
 
-__global__ void k_compact_extra(const int32_t *__restrict__ xflag, const int32_t *__restrict__ xscan, int64_t npair,
-                                const int32_t *__restrict__ src, int32_t *__restrict__ xsrc) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npair; e += (int64_t)gridDim.x * blockDim.x)
-        if (xflag[e]) xsrc[xscan[e]] = src[e];
-}
-
-__global__ void k_extra_ptr(const int32_t *__restrict__ ptr, int32_t ncell, const int32_t *__restrict__ xscan,
-                            int32_t *__restrict__ xptr) {
-    for (int32_t A = blockIdx.x * blockDim.x + threadIdx.x; A <= ncell; A += gridDim.x * blockDim.x) xptr[A] = xscan[ptr[A]];
+// The pairs outside the class table, per owner in list order: one wave per
+// owner, a ballot and prefix count place each flagged pair at xptr[A] + rank.
+__global__ void k_compact_extra(const int32_t *__restrict__ ptr, int32_t ncell, const int32_t *__restrict__ src,
+                                const int32_t *__restrict__ pkey, const int32_t *__restrict__ xptr,
+                                int32_t *__restrict__ xsrc) {
+    const int lane = threadIdx.x & 63;
+    for (int32_t A = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; A < ncell; A += gridDim.x * blockDim.x / 64) {
+        if (xptr[A + 1] == xptr[A]) continue;
+        int32_t base = xptr[A];
+        for (int32_t e0 = ptr[A]; e0 < ptr[A + 1]; e0 += 64) {
+            const int32_t e = e0 + lane;
+            const bool x = e < ptr[A + 1] && pkey[e] < 0;
+            const unsigned long long m = __ballot(x);
+            if (x) xsrc[base + __popcll(m & ((1ull << lane) - 1ull))] = src[e];
+            base += __popcll(m);
+        }
+    }
 }
 
 }  // namespace
 
 void m2l_dense_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *src, int32_t *pkey,
-                    int32_t *used, hipStream_t s) {
+                    int32_t *used, int32_t *xcount, hipStream_t s) {
     hipLaunchKernelGGL(k_pair_classes, dim3(grid_for((int64_t)ncell * 64, 256, 16384)), dim3(256), 0, s, c, ncell, ptr,
-                       src, pkey, used);
+                       src, pkey, used, xcount);
     FMM_LAUNCH_CHECK();
 }
 
@@ -437,16 +475,15 @@ void m2l_cid_tables(const int32_t *used_scan, const int32_t *used, const int32_t
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int32_t *pcid, int32_t *xflag,
-                  hipStream_t s) {
+void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int32_t *pcid, hipStream_t s) {
     if (npair <= 0) return;
-    hipLaunchKernelGGL(k_pair_cid, dim3(grid_for(npair, 256, 16384)), dim3(256), 0, s, pkey, npair, cid_of, pcid, xflag);
+    hipLaunchKernelGGL(k_pair_cid, dim3(grid_for(npair, 256, 16384)), dim3(256), 0, s, pkey, npair, cid_of, pcid);
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *xscan, uint64_t *tkey,
+void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *xptr, uint64_t *tkey,
                      int32_t *has, hipStream_t s) {
-    hipLaunchKernelGGL(k_target_keys, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, n, ptr, xscan, tkey,
+    hipLaunchKernelGGL(k_target_keys, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, n, ptr, xptr, tkey,
                        has);
     FMM_LAUNCH_CHECK();
 }
@@ -458,8 +495,8 @@ void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *pt
     const int nwords = (ncid + 31) / 32;
     FMM_HIP_CHECK(hipMemsetAsync(gbits, 0, (size_t)ngroup * nwords * 4, s));
     if ((size_t)nwords * 4 > 48 * 1024) throw std::runtime_error("too many M2L classes for the group builder");
-    hipLaunchKernelGGL(k_group_mark, dim3(ngroup, kSplit), dim3(256), (size_t)nwords * 4, s, tsorted, ntarget, ptr, pcid,
-                       nwords, gbits);
+    hipLaunchKernelGGL(k_group_mark, dim3(group_blocks(ngroup)), dim3(256), (size_t)nwords * 4, s, tsorted, ntarget,
+                       ptr, pcid, nwords, gbits);
     FMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_group_prefix, dim3(ngroup), dim3(256), 0, s, nwords, gbits, gwpre, gcount);
     FMM_LAUNCH_CHECK();
@@ -471,8 +508,8 @@ void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr
     const int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
     if (ngroup <= 0) return;
     const int nwords = (ncid + 31) / 32;
-    hipLaunchKernelGGL(k_group_fill, dim3(ngroup, kSplit), dim3(256), 0, s, tsorted, ntarget, ptr, src, pcid, nwords, gbits,
-                       gwpre, goff, ecls, esrc, gtarget);
+    hipLaunchKernelGGL(k_group_fill, dim3(group_blocks(ngroup)), dim3(256), 0, s, tsorted, ntarget, ptr, src, pcid,
+                       nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
     FMM_LAUNCH_CHECK();
 }
 
@@ -482,28 +519,28 @@ void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, int chunk, const int32_t *toff,
+void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, int chunk, int32_t max_entries,
+                    const int32_t *toff,
                     const uint64_t *tsorted, int32_t ntask, int4 *tasks, int4 *tasks_alt, uint64_t *tkeys,
                     uint64_t *tkeys_alt, uint32_t *tidx, uint32_t *tidx_alt, int32_t *xcd_count, int32_t *tmp,
                     hipStream_t s) {
     FMM_HIP_CHECK(hipMemsetAsync(xcd_count, 0, 8 * sizeof(int32_t), s));
     if (ngroup <= 0 || ntask <= 0) return;
+    int jbits = 1;
+    while ((1 << jbits) <= max_entries / chunk + 1) jbits++;
     hipLaunchKernelGGL(k_make_tasks, dim3(grid_for(ngroup, 256, 4096)), dim3(256), 0, s, gcount, goff, ngroup, chunk,
-                       toff, tsorted, tasks_alt, tkeys, tidx, xcd_count);
+                       jbits, toff, tsorted, tasks_alt, tkeys, tidx, xcd_count);
     FMM_LAUNCH_CHECK();
-    radix_sort_u64(tkeys, tidx, tkeys_alt, tidx_alt, ntask, 0, 64, tmp, s);
+    radix_sort_u64(tkeys, tidx, tkeys_alt, tidx_alt, ntask, 32, 32 + jbits + 3, tmp, s);
     hipLaunchKernelGGL(k_permute_tasks, dim3(grid_for(ntask, 256, 4096)), dim3(256), 0, s, tidx, ntask, tasks_alt, tasks);
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_extra(const int32_t *xflag, const int32_t *xscan, int64_t npair, const int32_t *src, const int32_t *ptr,
-               int32_t ncell, int32_t *xsrc, int32_t *xptr, hipStream_t s) {
-    if (npair > 0) {
-        hipLaunchKernelGGL(k_compact_extra, dim3(grid_for(npair, 256, 16384)), dim3(256), 0, s, xflag, xscan, npair, src,
-                           xsrc);
-        FMM_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_extra_ptr, dim3(grid_for(ncell + 1, 256, 4096)), dim3(256), 0, s, ptr, ncell, xscan, xptr);
+void m2l_extra(const int32_t *ptr, int32_t ncell, const int32_t *src, const int32_t *pkey, const int32_t *xptr,
+               int32_t *xsrc, hipStream_t s) {
+    if (ncell <= 0) return;
+    hipLaunchKernelGGL(k_compact_extra, dim3(grid_for((int64_t)ncell * 64, 256, 16384)), dim3(256), 0, s, ptr, ncell, src,
+                       pkey, xptr, xsrc);
     FMM_LAUNCH_CHECK();
 }
 

@@ -29,7 +29,7 @@ struct NearFarArgs {
 // store (slot_of, frags) persists across builds of the same plan.
 struct NearFarState {
     DevBuf used, slot_of, nslots, new_keys, frags, used_scan, cid_of, slot_of_cid;
-    DevBuf pkey, pcid, xflag, xscan, tkey, tkey_alt, has, gcount, goff, tcount, toff;
+    DevBuf pkey, pcid, xcount, tkey, tkey_alt, has, gcount, goff, tcount, toff;
     DevBuf ecls, esrc, gtarget, tasks, xsrc, xptr, leafbuf, leaves, pf, M32, tmp, cnt, centre, gbits, gwpre;
     DevBuf tasks_alt, tkeys, tidx, lists;
     int p = -1;

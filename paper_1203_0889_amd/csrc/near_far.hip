@@ -46,8 +46,8 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     const size_t np1 = (size_t)std::max<int64_t>(npair, 1) + 1;
     FMM_HIP_CHECK(st.pkey.grow(np1 * 4));
     FMM_HIP_CHECK(st.pcid.grow(np1 * 4));
-    FMM_HIP_CHECK(st.xflag.grow(np1 * 4));
-    FMM_HIP_CHECK(st.xscan.grow(np1 * 4));
+    FMM_HIP_CHECK(st.xcount.grow(((size_t)ncell + 1) * 4));   // per-owner counts of pairs outside the table
+    FMM_HIP_CHECK(st.xptr.grow(((size_t)ncell + 1) * 4));
     FMM_HIP_CHECK(st.cnt.grow(64 * 4));  // [0..4] sizes, [16..32] per-XCD counts, [40..55] queue heads
     int64_t tmp_elems = std::max<int64_t>({(int64_t)scan_tmp_elems(kDenseKeys + 1), (int64_t)scan_tmp_elems(np1),
                                            (int64_t)radix_tmp_elems(ncell + 1), (int64_t)scan_tmp_elems(ncell + 1)});
@@ -55,7 +55,8 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     int32_t *cnt = st.cnt.as<int32_t>();
 
     FMM_HIP_CHECK(hipMemsetAsync(st.used.ptr, 0, kDenseKeys * 4, s));
-    m2l_dense_keys(a.g.c, ncell, a.m2l_ptr, a.m2l_src, st.pkey.as<int32_t>(), st.used.as<int32_t>(), s);
+    m2l_dense_keys(a.g.c, ncell, a.m2l_ptr, a.m2l_src, st.pkey.as<int32_t>(), st.used.as<int32_t>(),
+                   st.xcount.as<int32_t>(), s);
     FMM_HIP_CHECK(hipMemsetAsync(st.nslots.as<int32_t>() + 1, 0, 4, s));
     m2l_alloc_slots(st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.nslots.as<int32_t>(), st.new_keys.as<int32_t>(), s);
     int32_t ns[2];
@@ -70,19 +71,21 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     exclusive_scan_oop(st.used.as<int32_t>(), st.used_scan.as<int32_t>(), kDenseKeys, cnt + 0, st.tmp.as<int32_t>(), s);
     m2l_cid_tables(st.used_scan.as<int32_t>(), st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.cid_of.as<int32_t>(),
                    st.slot_of_cid.as<int32_t>(), s);
-    m2l_pair_cid(st.pkey.as<int32_t>(), npair, st.cid_of.as<int32_t>(), st.pcid.as<int32_t>(), st.xflag.as<int32_t>(), s);
-    // exclusive scan over npair + 1 elements (the last one zero): xscan[npair]
-    // = number of pairs left to the per-pair kernel
-    exclusive_scan_oop(st.xflag.as<int32_t>(), st.xscan.as<int32_t>(), npair, st.xscan.as<int32_t>() + npair,
+    m2l_pair_cid(st.pkey.as<int32_t>(), npair, st.cid_of.as<int32_t>(), st.pcid.as<int32_t>(), s);
+    // CSR offsets of the pairs left to the per-pair kernel; xptr[ncell] (and
+    // cnt[1]) = their number
+    exclusive_scan_oop(st.xcount.as<int32_t>(), st.xptr.as<int32_t>(), ncell, st.xptr.as<int32_t>() + ncell,
                        st.tmp.as<int32_t>(), s);
-    FMM_HIP_CHECK(hipMemcpyAsync(cnt + 1, st.xscan.as<int32_t>() + npair, 4, hipMemcpyDeviceToDevice, s));
+    FMM_HIP_CHECK(hipMemcpyAsync(cnt + 1, st.xptr.as<int32_t>() + ncell, 4, hipMemcpyDeviceToDevice, s));
     // ---- targets sorted by (level, octant, cell)
     FMM_HIP_CHECK(st.tkey.grow((size_t)(ncell + 1) * 8));
     FMM_HIP_CHECK(st.tkey_alt.grow((size_t)(ncell + 1) * 8));
     FMM_HIP_CHECK(st.has.grow((size_t)(ncell + 1) * 4));
-    m2l_target_keys(a.g.c, ncell, a.n, a.m2l_ptr, st.xscan.as<int32_t>(), st.tkey.as<uint64_t>(), st.has.as<int32_t>(),
+    m2l_target_keys(a.g.c, ncell, a.n, a.m2l_ptr, st.xptr.as<int32_t>(), st.tkey.as<uint64_t>(), st.has.as<int32_t>(),
                     s);
-    radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 0, 43,
+    // the keys are written in cell order: a stable sort on the (level,
+    // eighth, octant) bits 32..42 keeps cells in order within each class
+    radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 32, 43,
                    st.tmp.as<int32_t>(), s);
     exclusive_scan_i32(st.has.as<int32_t>(), ncell, cnt + 2, st.tmp.as<int32_t>(), s);
     int32_t h3[3];
@@ -124,15 +127,14 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     m2l_group_fill(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
                    st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(),
                    st.esrc.as<int32_t>(), st.gtarget.as<int32_t>(), s);
-    m2l_make_tasks(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, chunk, st.toff.as<int32_t>(),
+    m2l_make_tasks(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, chunk, std::max(st.ncid, 1),
+                   st.toff.as<int32_t>(),
                    st.tkey.as<uint64_t>(), st.ntask, st.tasks.as<int4>(), st.tasks_alt.as<int4>(),
                    st.tkeys.as<uint64_t>(), st.tkeys.as<uint64_t>() + nt1, st.tidx.as<uint32_t>(),
                    st.tidx.as<uint32_t>() + nt1, cnt + 16, st.tmp.as<int32_t>(), s);
     // ---- pairs left to the per-pair kernel (|delta| >= 2 or far displacement)
     FMM_HIP_CHECK(st.xsrc.grow((size_t)std::max(st.nextra, 1) * 4));
-    FMM_HIP_CHECK(st.xptr.grow((size_t)(ncell + 1) * 4));
-    m2l_extra(st.xflag.as<int32_t>(), st.xscan.as<int32_t>(), npair, a.m2l_src, a.m2l_ptr, ncell, st.xsrc.as<int32_t>(),
-              st.xptr.as<int32_t>(), s);
+    m2l_extra(a.m2l_ptr, ncell, a.m2l_src, st.pkey.as<int32_t>(), st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), s);
     // ---- P2P leaves (by spatial eighth, costliest first) and cell centres
     FMM_HIP_CHECK(st.leafbuf.grow((size_t)4 * (ncell + 1) * 4));
     FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
@@ -220,7 +222,7 @@ void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
 
 void release_near_far(NearFarState &st) {
     DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.used_scan, &st.cid_of,
-                     &st.slot_of_cid, &st.pkey, &st.pcid, &st.xflag, &st.xscan, &st.tkey, &st.tkey_alt, &st.has,
+                     &st.slot_of_cid, &st.pkey, &st.pcid, &st.xcount, &st.tkey, &st.tkey_alt, &st.has,
                      &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
                      &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists};
     for (DevBuf *b : all) b->release();

@@ -26,31 +26,41 @@ __global__ void k_centres(Geometry g, int32_t ncell, double *__restrict__ centre
     }
 }
 
-// Leaf cost = targets x sources over its P2P list.  Sort key = (spatial
-// eighth of the particle order) << 29 | (2^29 - 1 - cost): ascending order
-// groups leaves by eighth (the XCD that runs them) and puts the costliest
-// first within each.  Non-leaves get the largest key.
+// Leaf cost = targets x sources over its P2P list (one wave per cell).  Sort
+// key (16 bits) = (spatial eighth of the particle order) << 13 |
+// (8191 - q), q = 1 + min(8190, 200 log2(cost + 1)): ascending order groups
+// leaves by eighth (the XCD that runs them) and puts the costliest first
+// within each (to the resolution of q; equal keys keep cell order).
+// Non-leaves get 0xffff, after every leaf.
 __global__ void k_leaf_cost(CellArrays c, int32_t ncell, int64_t n, const int32_t *__restrict__ ptr,
                             const int32_t *__restrict__ src, int32_t *__restrict__ count8, uint32_t *__restrict__ key,
                             uint32_t *__restrict__ val) {
     __shared__ int32_t lc[9];
     if (threadIdx.x < 9) lc[threadIdx.x] = 0;
     __syncthreads();
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += gridDim.x * blockDim.x) {
-        bool leaf = c.child[i] < 0 && c.count[i] > 0;
+    const int lane = threadIdx.x & 63;
+    for (int32_t i = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; i < ncell; i += gridDim.x * blockDim.x / 64) {
+        const bool leaf = c.child[i] < 0 && c.count[i] > 0;
         uint64_t cost = 0;
-        int c8 = 0;
-        if (leaf) {
-            for (int32_t e = ptr[i]; e < ptr[i + 1]; e++) cost += (uint64_t)c.count[src[e]];
-            cost *= (uint64_t)c.count[i];
-            c8 = (int)(((int64_t)c.first[i] * 8) / n);
-            c8 = c8 > 7 ? 7 : c8;
-            atomicAdd(&lc[0], 1);
-            atomicAdd(&lc[1 + c8], 1);
+        if (leaf)
+            for (int32_t e = ptr[i] + lane; e < ptr[i + 1]; e += 64) cost += (uint64_t)c.count[src[e]];
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) cost += __shfl_xor(cost, d, 64);
+        if (lane == 0) {
+            uint32_t k = 0xffffu;
+            if (leaf) {
+                cost *= (uint64_t)c.count[i];
+                int c8 = (int)(((int64_t)c.first[i] * 8) / n);
+                c8 = c8 > 7 ? 7 : c8;
+                const double lq = 200.0 * log2((double)cost + 1.0);
+                const uint32_t q = 1u + (uint32_t)(lq < 8190.0 ? lq : 8190.0);
+                k = ((uint32_t)c8 << 13) | (8191u - q);
+                atomicAdd(&lc[0], 1);
+                atomicAdd(&lc[1 + c8], 1);
+            }
+            key[i] = k;
+            val[i] = (uint32_t)i;
         }
-        const uint64_t cmax = (1ull << 29) - 1;
-        key[i] = leaf ? (((uint32_t)c8 << 29) | (uint32_t)(cmax - (cost > cmax - 1 ? cmax - 1 : cost))) : 0xffffffffu;
-        val[i] = (uint32_t)i;
     }
     __syncthreads();
     if (threadIdx.x < 9 && lc[threadIdx.x]) atomicAdd(&count8[threadIdx.x], lc[threadIdx.x]);
@@ -76,10 +86,10 @@ void p2p_leaf_list(CellArrays c, int32_t ncell, int64_t n, const int32_t *p2p_pt
     uint32_t *valt = (uint32_t *)(buf + 3 * (ncell + 1));
     uint32_t *val = (uint32_t *)leaves;
     FMM_HIP_CHECK(hipMemsetAsync(d_count, 0, 9 * sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_leaf_cost, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, n, p2p_ptr, p2p_src,
-                       d_count, key, val);
+    hipLaunchKernelGGL(k_leaf_cost, dim3(grid_for((int64_t)ncell * 64, 256, 16384)), dim3(256), 0, s, c, ncell, n,
+                       p2p_ptr, p2p_src, d_count, key, val);
     FMM_LAUNCH_CHECK();
-    radix_sort_u32(key, val, kalt, valt, ncell, 0, 32, tmp, s);
+    radix_sort_u32(key, val, kalt, valt, ncell, 0, 16, tmp, s);
 }
 
 void p2p_prepare(Geometry g, int64_t n, const int32_t *leaf_of, const double *xs, const double *ys,

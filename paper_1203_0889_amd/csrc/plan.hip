@@ -60,13 +60,14 @@ enum { kStateCreated = 0, kStateBuilt = 1, kStateUp = 2, kStateEval = 3 };
 
 enum Stage {
     ST_BOX = 0, ST_SORT, ST_TREE, ST_LISTS, ST_CSR, ST_P2M, ST_M2M, ST_M2L, ST_P2P, ST_L2L, ST_L2P, ST_OUT,
-    ST_NF_PREP, ST_QUEUE, ST_M2L_REST, ST_COUNT
+    ST_NF_PREP, ST_QUEUE, ST_M2L_REST, ST_NF_BUILD, ST_COUNT
 };
-// FP64 path: m2l, p2p.  Mixed path: nf_prep (bf16 multipoles, FP32
-// particles, zeroed locals), queue (the work-queue kernel: M2L and P2P
-// tasks), m2l_rest (per-pair FP64 M2L of the pairs outside the class table).
+// FP64 path: m2l, p2p.  Mixed path: nf_build (class tables, groups and
+// task lists, at build time), nf_prep (bf16 multipoles, FP32 particles,
+// zeroed locals), queue (the work-queue kernel: M2L and P2P tasks),
+// m2l_rest (per-pair FP64 M2L of the pairs outside the class table).
 static const char *kStageNames[16] = {"bbox_keys", "sort", "tree", "traverse", "csr", "p2m", "m2m", "m2l", "p2p",
-                                      "l2l", "l2p", "output", "nf_prep", "queue", "m2l_rest", ""};
+                                      "l2l", "l2p", "output", "nf_prep", "queue", "m2l_rest", "nf_build"};
 
 struct fmm_plan {
     fmm_params prm;
@@ -343,7 +344,7 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
 
     if (p->prm.precision == FMM_PREC_MIXED) {
         fmm::build_near_far_mixed(p->nf, nf_args(p), s);
-        mark(p, ST_CSR);
+        mark(p, ST_NF_BUILD);
     }
 }
 
