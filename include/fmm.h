@@ -185,6 +185,8 @@ fmm_status fmm_copy_tree(const fmm_plan *plan, uint64_t *keys, int64_t *perm, in
  * Copy the interaction lists, sorted by (target cell, source cell), as CSR
  * over target cells (synchronous).  host int64 m2l_ptr[ncell + 1],
  * int32 m2l_src[nm2l], p2p_ptr[ncell + 1], p2p_src[np2p].  Any may be NULL.
+ * (On the device the lists are grouped by target only; the sources of each
+ * target are sorted here, on the host.)
  */
 fmm_status fmm_copy_lists(const fmm_plan *plan, int64_t *m2l_ptr, int32_t *m2l_src, int64_t *p2p_ptr,
                           int32_t *p2p_src);

@@ -154,14 +154,14 @@ void transpose_csr(const int32_t *ptr, const int32_t *src, int32_t ncell, int64_
                                ptr, src, ncell, bits, (uint32_t *)keys);
             FMM_LAUNCH_CHECK();
         }
-        radix_sort_u32((uint32_t *)keys, nullptr, (uint32_t *)alt, nullptr, npair, 0, 2 * bits, tmp, s);
+        radix_sort_u32((uint32_t *)keys, nullptr, (uint32_t *)alt, nullptr, npair, bits, 2 * bits, tmp, s);
     } else {
         if (npair > 0) {
             hipLaunchKernelGGL(k_swap_pairs<uint64_t>, dim3(grid_for((int64_t)ncell * 64, 256, 4096)), dim3(256), 0, s,
                                ptr, src, ncell, bits, (uint64_t *)keys);
             FMM_LAUNCH_CHECK();
         }
-        radix_sort_u64((uint64_t *)keys, nullptr, (uint64_t *)alt, nullptr, npair, 0, 2 * bits, tmp, s);
+        radix_sort_u64((uint64_t *)keys, nullptr, (uint64_t *)alt, nullptr, npair, bits, 2 * bits, tmp, s);
     }
     launch_csr(keys, key32, npair, bits, ncell, ptr_t, src_t, s);
 }

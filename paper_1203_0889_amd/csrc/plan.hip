@@ -319,7 +319,11 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     p->np2p = hc[1];
     mark(p, ST_LISTS);
 
-    // ---- canonical CSR lists sorted by (target, source)
+    // ---- CSR lists grouped by target.  Only the target bits are sorted:
+    // every consumer is indifferent to the order of a target's sources
+    // (classes are deduplicated per group, the FP64 path and the queue add
+    // with atomics or in FP32), and fmm_copy_lists sorts each target's
+    // sources when it returns the canonical (target, source) order.
     int64_t mx = std::max<int64_t>(std::max(p->nm2l, p->np2p), 1);
     FMM_HIP_CHECK(p->pair_alt.grow(mx * ksz));
     FMM_HIP_CHECK(p->tmp.grow(std::max(p->tmp.bytes, fmm::radix_tmp_elems(mx) * sizeof(int32_t))));
@@ -333,11 +337,11 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     int32_t *srcs[2] = {p->m2l_src.as<int32_t>(), p->p2p_src.as<int32_t>()};
     for (int t = 0; t < 2; t++) {
         if (key32)
-            fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, p->pair_alt.as<uint32_t>(), nullptr, cnts[t], 0, 2 * bits,
-                                p->tmp.as<int32_t>(), s);
+            fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, p->pair_alt.as<uint32_t>(), nullptr, cnts[t], bits,
+                                2 * bits, p->tmp.as<int32_t>(), s);
         else
-            fmm::radix_sort_u64((uint64_t *)lists[t], nullptr, p->pair_alt.as<uint64_t>(), nullptr, cnts[t], 0, 2 * bits,
-                                p->tmp.as<int32_t>(), s);
+            fmm::radix_sort_u64((uint64_t *)lists[t], nullptr, p->pair_alt.as<uint64_t>(), nullptr, cnts[t], bits,
+                                2 * bits, p->tmp.as<int32_t>(), s);
         fmm::launch_csr(lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], s);
     }
     mark(p, ST_CSR);
@@ -852,18 +856,21 @@ fmm_status fmm_copy_lists(const fmm_plan *cp, int64_t *m2l_ptr, int32_t *m2l_src
         const int64_t nc1 = p->ncell + 1;
         std::vector<int32_t> tmp(nc1);
         int64_t *outs[2] = {m2l_ptr, p2p_ptr};
+        int32_t *srcs[2] = {m2l_src, p2p_src};
         DevBuf *ptrs[2] = {&p->m2l_ptr, &p->p2p_ptr};
+        DevBuf *dsrc[2] = {&p->m2l_src, &p->p2p_src};
+        const int64_t cnts[2] = {p->nm2l, p->np2p};
         for (int t = 0; t < 2; t++) {
-            if (!outs[t]) continue;
+            if (!outs[t] && !srcs[t]) continue;
             FMM_HIP_CHECK(hipMemcpyAsync(tmp.data(), ptrs[t]->ptr, nc1 * 4, hipMemcpyDeviceToHost, p->stream));
+            if (srcs[t] && cnts[t] > 0)
+                FMM_HIP_CHECK(hipMemcpyAsync(srcs[t], dsrc[t]->ptr, cnts[t] * 4, hipMemcpyDeviceToHost, p->stream));
             FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
-            for (int64_t i = 0; i < nc1; i++) outs[t][i] = tmp[i];
+            if (outs[t])
+                for (int64_t i = 0; i < nc1; i++) outs[t][i] = tmp[i];
+            if (srcs[t])   // canonical order: each target's sources ascending
+                for (int64_t i = 0; i + 1 < nc1; i++) std::sort(srcs[t] + tmp[i], srcs[t] + tmp[i + 1]);
         }
-        if (m2l_src && p->nm2l > 0)
-            FMM_HIP_CHECK(hipMemcpyAsync(m2l_src, p->m2l_src.ptr, p->nm2l * 4, hipMemcpyDeviceToHost, p->stream));
-        if (p2p_src && p->np2p > 0)
-            FMM_HIP_CHECK(hipMemcpyAsync(p2p_src, p->p2p_src.ptr, p->np2p * 4, hipMemcpyDeviceToHost, p->stream));
-        FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
         return FMM_OK;
     });
 }

@@ -159,6 +159,11 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const K *__restrict__ ki
     counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
 }
 
+// Scatter of one pass.  Each block ranks its tile stably (per wave with
+// ballots over the digit bits, then across the waves), places the tile in
+// LDS in digit order, and writes it out in that order: consecutive threads
+// then write consecutive addresses of one digit run instead of up to 64
+// different lines per store.
 template <class K>
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                            K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
@@ -166,12 +171,18 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
                                                            int nblocks) {
     __shared__ int wcount[kRsWaves][256];
     __shared__ int wbase[kRsWaves][256];
+    __shared__ int lstart[257];
+    __shared__ int gbase[256];
+    __shared__ int wsum[kRsWaves];
+    __shared__ K skey[kRsTile];
+    __shared__ uint32_t sval[kRsTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int mask = (1 << nbits) - 1;
     for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&wcount[0][0])[i] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kRsWaveTile + lane;
+    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+    const int64_t base = tile0 + (int64_t)w * kRsWaveTile + lane;
     K key[kRsItems];
     uint32_t val[kRsItems];
     int rank[kRsItems];
@@ -196,13 +207,28 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
     }
     __syncthreads();
     {
-        int d = threadIdx.x;  // 256 threads == 256 digits
-        int run = offs[(int64_t)d * nblocks + blockIdx.x];
+        // thread d: block count of digit d, wave offsets within the digit,
+        // then an exclusive scan over the 256 digits (block-local starts)
+        const int d = threadIdx.x;
+        int run = 0;
 #pragma unroll
         for (int ww = 0; ww < kRsWaves; ww++) {
             wbase[ww][d] = run;
             run += wcount[ww][d];
         }
+        int inc = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) wsum[w] = inc;
+        gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+        __syncthreads();
+        int before = 0;
+        for (int ww = 0; ww < w; ww++) before += wsum[ww];
+        lstart[d] = before + inc - run;
+        if (d == 255) lstart[256] = before + inc;
     }
     __syncthreads();
 #pragma unroll
@@ -210,10 +236,19 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
         int64_t i = base + it * 64;
         if (i < n) {
             int d = (int)((key[it] >> shift) & (K)mask);
-            int pos = wbase[w][d] + rank[it];
-            kout[pos] = key[it];
-            if (vout) vout[pos] = val[it];
+            int lp = lstart[d] + wbase[w][d] + rank[it];
+            skey[lp] = key[it];
+            sval[lp] = val[it];
         }
+    }
+    __syncthreads();
+    const int tile_n = lstart[256];
+    for (int lp = threadIdx.x; lp < tile_n; lp += kRsThreads) {
+        const K k = skey[lp];
+        const int d = (int)((k >> shift) & (K)mask);
+        const int pos = gbase[d] + (lp - lstart[d]);
+        kout[pos] = k;
+        if (vout) vout[pos] = sval[lp];
     }
 }
 

@@ -53,7 +53,8 @@ void launch_init_frontier(const int64_t *d_offsets, int n_inst, int2 *front, int
 void launch_csr(const void *sorted, bool key32, int64_t n, int bits, int32_t ncell, int32_t *ptr, int32_t *src,
                 hipStream_t s);
 // Transposed CSR of a pair list: (ptr, src) lists, per owner cell, its
-// partners; (ptr_t, src_t) lists, per partner, its owners, sorted.  keys and
+// partners; (ptr_t, src_t) lists, per partner, its owners (grouped by
+// partner; the order within a group is not fixed).  keys and
 // alt hold npair keys of 4 (key32) or 8 bytes; tmp radix_tmp_elems(npair).
 void transpose_csr(const int32_t *ptr, const int32_t *src, int32_t ncell, int64_t npair, int bits, bool key32,
                    void *keys, void *alt, int32_t *tmp, int32_t *ptr_t, int32_t *src_t, hipStream_t s);
