@@ -110,7 +110,8 @@ __device__ inline int octant_of(const CellArrays &c, int32_t cell) {
 // M2M and L2L, octant-major.  A block owns kPB parents of one level and a
 // thread owns one coefficient row; for each octant o the block applies the
 // matrix of o (column-major, so a wave reads consecutive rows) to the kPB
-// vectors staged in LDS.  Each matrix column is read once per kPB parents.
+// vectors staged in LDS (parent-minor, so one 16-byte LDS read feeds two
+// parents).  Each matrix column is read once per kPB parents.
 constexpr int kPB = 16;
 
 __device__ inline int32_t child_in_octant(const CellArrays &c, int32_t parent, int o) {
@@ -122,7 +123,8 @@ __device__ inline int32_t child_in_octant(const CellArrays &c, int32_t parent, i
     return -1;
 }
 
-constexpr int kCW = 32;  // operator columns staged in LDS at a time
+constexpr int kCW = 32;  // operator columns staged in LDS at a time (at most; fewer at high p)
+constexpr size_t kTransLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 // Bulk copy global -> LDS with several loads in flight per thread.
 __device__ inline void stage(double *__restrict__ dst, const double *__restrict__ src, int n) {
@@ -138,8 +140,8 @@ __device__ inline void stage(double *__restrict__ dst, const double *__restrict_
     for (; i < n; i += step) dst[i] = src[i];
 }
 
-// acc[k] += sum_(i in [c0, c0+cw)) Op[i][row] * x[k][i] with the operator's
-// column chunk staged in LDS.
+// acc[k] += sum_(i in [c0, c0+cw)) Op[i][row] * x[i][k] with the operator's
+// column chunk staged in LDS; x is column-major over the kPB parents.
 __device__ inline void apply_chunk(const double *__restrict__ op, int P, int c0, int cw, double *__restrict__ sh,
                                    const double *__restrict__ x, int row, double *acc) {
     __syncthreads();
@@ -147,16 +149,24 @@ __device__ inline void apply_chunk(const double *__restrict__ op, int P, int c0,
     __syncthreads();
     if (row < P)
         for (int i = 0; i < cw; i++) {
-            double a = sh[i * P + row];
+            const double a = sh[i * P + row];
+            const double2 *xc = reinterpret_cast<const double2 *>(x + (int64_t)(c0 + i) * kPB);
 #pragma unroll
-            for (int k = 0; k < kPB; k++) acc[k] += a * x[k * P + c0 + i];
+            for (int k = 0; k < kPB / 2; k++) {
+                const double2 v = xc[k];
+                acc[2 * k] += a * v.x;
+                acc[2 * k + 1] += a * v.y;
+            }
         }
 }
 
 // M2M: block (parent chunk of kPB, octant o) writes the octant's
 // contribution to part[o][parent][row]; k_m2m_sum adds the 8 parts in a
 // fixed order (deterministic).
-__global__ void k_m2m(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ ops,
+constexpr int kTransMaxThreads = 320;  // rows_block(p) for p <= 16
+
+__global__ void __launch_bounds__(kTransMaxThreads) k_m2m(Geometry g, int32_t lb, int32_t le, int p, int cw,
+                                                          const double *__restrict__ ops,
                       const double *__restrict__ M, double *__restrict__ part) {
     extern __shared__ double dyn[];
     __shared__ int32_t kid[kPB];
@@ -172,13 +182,13 @@ __global__ void k_m2m(Geometry g, int32_t lb, int32_t le, int p, const double *_
     __syncthreads();
     for (int k = 0; k < kPB; k++) {
         int32_t ch = kid[k];
-        for (int i = threadIdx.x; i < P; i += blockDim.x) xs_[k * P + i] = ch >= 0 ? M[(int64_t)ch * P + i] : 0.0;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) xs_[i * kPB + k] = ch >= 0 ? M[(int64_t)ch * P + i] : 0.0;
     }
     double acc[kPB];
 #pragma unroll
     for (int k = 0; k < kPB; k++) acc[k] = 0.0;
     const double *A = ops + (int64_t)o * P * P;
-    for (int c0 = 0; c0 < P; c0 += kCW) apply_chunk(A, P, c0, P - c0 < kCW ? P - c0 : kCW, sh, xs_, row, acc);
+    for (int c0 = 0; c0 < P; c0 += cw) apply_chunk(A, P, c0, P - c0 < cw ? P - c0 : cw, sh, xs_, row, acc);
     if (row < P)
         for (int k = 0; k < kPB; k++) {
             int32_t par = p0 + k;
@@ -201,30 +211,35 @@ __global__ void k_m2m_sum(Geometry g, int32_t lb, int32_t le, int p, const doubl
 
 // L2L: block (parent chunk of kPB, octant o) adds into the children of
 // octant o (each child has one parent and one octant: no conflicts).
-__global__ void k_l2l(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ ops,
-                      double *__restrict__ L) {
+__global__ void __launch_bounds__(kTransMaxThreads) k_l2l(Geometry g, int32_t lb, int32_t le, int p, int cw,
+                                                          const double *__restrict__ ops, double *__restrict__ L) {
     extern __shared__ double dyn[];
+    __shared__ int32_t kid[kPB];
     const int P = ncoef(p);
     double *xp = dyn, *sh = dyn + kPB * P;
     const int o = blockIdx.y;
     const int32_t p0 = lb + blockIdx.x * kPB;
     const int row = threadIdx.x;
+    if (threadIdx.x < kPB) {
+        const int32_t par = p0 + threadIdx.x;
+        kid[threadIdx.x] = par < le ? child_in_octant(g.c, par, o) : -1;
+    }
     for (int k = 0; k < kPB; k++) {
         int32_t par = p0 + k;
-        for (int i = threadIdx.x; i < P; i += blockDim.x) xp[k * P + i] = par < le ? L[(int64_t)par * P + i] : 0.0;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) xp[i * kPB + k] = par < le ? L[(int64_t)par * P + i] : 0.0;
     }
     double acc[kPB];
 #pragma unroll
     for (int k = 0; k < kPB; k++) acc[k] = 0.0;
     const double *B = ops + (int64_t)o * P * P;
-    for (int c0 = 0; c0 < P; c0 += kCW) apply_chunk(B, P, c0, P - c0 < kCW ? P - c0 : kCW, sh, xp, row, acc);
-    if (row < P)
+    for (int c0 = 0; c0 < P; c0 += cw) apply_chunk(B, P, c0, P - c0 < cw ? P - c0 : cw, sh, xp, row, acc);
+    if (row < P) {
+#pragma unroll
         for (int k = 0; k < kPB; k++) {
-            int32_t par = p0 + k;
-            if (par >= le) break;
-            int32_t ch = child_in_octant(g.c, par, o);
+            const int32_t ch = kid[k];
             if (ch >= 0) L[(int64_t)ch * P + row] += acc[k];
         }
+    }
 }
 
 // Local coefficient L~_n^m for any m (negative via conjugate symmetry).
@@ -248,10 +263,13 @@ __device__ inline Cplx lget(const double *Lc, int p, int n, int m) {
 //   d/du (z)       = sum     L~_(n+1)^m   conj(R_n^m(u))
 //   d/du (x + i y) = sum     L~_(n+1)^(m+1) conj(R_n^m(u))
 // and E = -(1/S^2) grad_u.
-__global__ void k_l2p(Geometry g, int64_t n, int p, const int32_t *__restrict__ leaf_of, const double *__restrict__ xs,
-                      const double *__restrict__ ys, const double *__restrict__ zs, const double *__restrict__ L,
-                      double *__restrict__ phi, double *__restrict__ fld) {
-    const int P = ncoef(p);
+template <int PP>
+__global__ void __launch_bounds__(128) k_l2p(Geometry g, int64_t n, const int32_t *__restrict__ leaf_of,
+                                             const double *__restrict__ xs, const double *__restrict__ ys,
+                                             const double *__restrict__ zs, const double *__restrict__ L,
+                                             double *__restrict__ phi, double *__restrict__ fld) {
+    constexpr int p = PP;
+    constexpr int P = ncoef(PP);
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         int32_t cell = leaf_of[r];
         double c[3], side;
@@ -265,6 +283,7 @@ __global__ void k_l2p(Geometry g, int64_t n, int p, const int32_t *__restrict__ 
         Cplx zeta = {ux, uy};
         Cplx rmm = {1.0, 0.0};
         Cplx a0 = {0, 0}, gz = {0, 0}, gxy = {0, 0};
+#pragma unroll
         for (int m = 0; m <= p; m++) {
             if (m > 0) {
                 rmm = cmul(rmm, zeta);
@@ -272,6 +291,7 @@ __global__ void k_l2p(Geometry g, int64_t n, int p, const int32_t *__restrict__ 
                 rmm.im /= 2 * m;
             }
             Cplx r2m = {0.0, 0.0}, r1m = {0.0, 0.0};
+#pragma unroll
             for (int nn = m; nn <= p; nn++) {
                 Cplx rn;
                 if (nn == m) {
@@ -531,12 +551,30 @@ void launch_p2m(Geometry g, int32_t ncell, int p, const double *xs, const double
 
 static int rows_block(int p) { return ((ncoef(p) + 63) / 64) * 64; }
 
+// Operator columns per LDS chunk and the dynamic LDS of a translation block
+// (kPB parent vectors + cw operator columns), within the 160 KB of a CU.
+static int trans_cw(int p) {
+    const size_t P = ncoef(p);
+    const size_t room = kTransLds - 1024 - kPB * P * sizeof(double);  // static LDS aside
+    const size_t cw = room / (P * sizeof(double));
+    return (int)(cw < (size_t)kCW ? (cw < 1 ? 1 : cw) : kCW);
+}
+
+static size_t trans_lds(int p, int cw) { return (size_t)(kPB + cw) * ncoef(p) * sizeof(double); }
+
+static void allow_lds(const void *fn, size_t bytes) {
+    if (bytes > 64 * 1024)
+        FMM_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
 void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, double *part,
                       hipStream_t s) {
     if (le <= lb) return;
-    size_t lds = (size_t)(kPB + kCW) * ncoef(p) * sizeof(double);
+    const int cw = trans_cw(p);
+    const size_t lds = trans_lds(p, cw);
+    allow_lds(reinterpret_cast<const void *>(&k_m2m), lds);
     dim3 grid((le - lb + kPB - 1) / kPB, 8);
-    hipLaunchKernelGGL(k_m2m, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, ops, M, part);
+    hipLaunchKernelGGL(k_m2m, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, cw, ops, M, part);
     FMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_m2m_sum, dim3(grid_for((int64_t)(le - lb) * ncoef(p), 256, 4096)), dim3(256), 0, s, g, lb, le, p,
                        part, M);
@@ -545,17 +583,29 @@ void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *o
 
 void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *L, hipStream_t s) {
     if (le <= lb) return;
-    size_t lds = (size_t)(kPB + kCW) * ncoef(p) * sizeof(double);
+    const int cw = trans_cw(p);
+    const size_t lds = trans_lds(p, cw);
+    allow_lds(reinterpret_cast<const void *>(&k_l2l), lds);
     dim3 grid((le - lb + kPB - 1) / kPB, 8);
-    hipLaunchKernelGGL(k_l2l, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, ops, L);
+    hipLaunchKernelGGL(k_l2l, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, cw, ops, L);
     FMM_LAUNCH_CHECK();
 }
 
 void launch_l2p(Geometry g, int64_t n, int p, const int32_t *leaf_of, const double *xs, const double *ys,
                 const double *zs, const double *L, double *phi, double *fld, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_l2p, dim3(grid_for(n, 128, 1 << 20)), dim3(128), 0, s, g, n, p, leaf_of, xs, ys, zs, L, phi,
-                       fld);
+    dim3 grid(grid_for(n, 128, 1 << 20)), block(128);
+#define FMM_L2P_CASE(PP)                                                                        \
+    case PP:                                                                                    \
+        hipLaunchKernelGGL(k_l2p<PP>, grid, block, 0, s, g, n, leaf_of, xs, ys, zs, L, phi, fld); \
+        break;
+    switch (p) {
+        FMM_L2P_CASE(0) FMM_L2P_CASE(1) FMM_L2P_CASE(2) FMM_L2P_CASE(3) FMM_L2P_CASE(4) FMM_L2P_CASE(5)
+        FMM_L2P_CASE(6) FMM_L2P_CASE(7) FMM_L2P_CASE(8) FMM_L2P_CASE(9) FMM_L2P_CASE(10) FMM_L2P_CASE(11)
+        FMM_L2P_CASE(12) FMM_L2P_CASE(13) FMM_L2P_CASE(14) FMM_L2P_CASE(15) FMM_L2P_CASE(16)
+        default: throw HipError{hipErrorInvalidValue, "l2p: unsupported order"};
+    }
+#undef FMM_L2P_CASE
     FMM_LAUNCH_CHECK();
 }
 
