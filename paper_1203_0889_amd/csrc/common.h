@@ -55,6 +55,22 @@ void radix_sort_u64(uint64_t *kin, uint32_t *vin, uint64_t *kalt, uint32_t *valt
 void radix_sort_u32(uint32_t *kin, uint32_t *vin, uint32_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
                     int bit_hi, int32_t *d_tmp, hipStream_t s);
 
+// Small device-to-host reads without a stream synchronisation: a one-thread
+// kernel copies the values into pinned, mapped host memory and then raises a
+// sequence flag there (system-scope release); the host spins on the flag,
+// checking the stream for errors while it waits.  Falls back to a copy and a
+// stream synchronisation for reads above kHostReadMax values or when the
+// pinned buffer could not be allocated.
+constexpr int kHostReadMax = 64;  // int32 values per fast read
+struct HostReader {
+    int32_t *h = nullptr;  // pinned host: [0] flag, [16 ..] data
+    int32_t *d = nullptr;  // device view of h
+    int32_t seq = 0;
+    void init();           // best effort: on failure reads use the fallback
+    void release();
+    void read(void *host, const void *dev, size_t bytes, hipStream_t s);  // throws HipError
+};
+
 // Zero `bytes` bytes (a multiple of 4) at a 4-byte aligned device address
 // with a kernel: unlike hipMemsetAsync it may be captured in a HIP graph and
 // replayed.

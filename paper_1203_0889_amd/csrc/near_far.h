@@ -23,6 +23,7 @@ struct NearFarArgs {
     // source), M holds the duals of the locals, L receives the duals of the
     // multipoles, qs the adjoint weights; operators are stored transposed.
     bool transposed = false;
+    HostReader *reader = nullptr;  // fast device-to-host reads (optional)
 };
 
 // Device workspaces of this stage, owned by the plan.  The class operator
@@ -33,7 +34,7 @@ struct NearFarState {
     DevBuf ecls, esrc, gtarget, tasks, xsrc, xptr, leafbuf, leaves, pf, M32, tmp, cnt, centre, gbits, gwpre;
     DevBuf tasks_alt, tkeys, tidx, lists;
     int p = -1;
-    int32_t nslot_total = 0, ncid = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0, nleaves = 0;
+    int32_t nslot_total = 0, ncid = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0;
     bool built = false;
 };
 

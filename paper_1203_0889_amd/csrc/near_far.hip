@@ -16,9 +16,28 @@ fmm_tuning default_tuning() {
 }
 
 namespace {
-void read_sync(void *h, const void *d, size_t b, hipStream_t s) {
-    FMM_HIP_CHECK(hipMemcpyAsync(h, d, b, hipMemcpyDeviceToHost, s));
-    FMM_HIP_CHECK(hipStreamSynchronize(s));
+void read_sync(const NearFarArgs &a, void *h, const void *d, size_t b, hipStream_t s) {
+    if (a.reader) {
+        a.reader->read(h, d, b, s);
+    } else {
+        FMM_HIP_CHECK(hipMemcpyAsync(h, d, b, hipMemcpyDeviceToHost, s));
+        FMM_HIP_CHECK(hipStreamSynchronize(s));
+    }
+}
+
+// The 16 task lists from the per-XCD counts (cnt[16..23] M2L tasks,
+// cnt[25..32] leaves): list 2x = (first task, count, 0, 0), list 2x + 1 =
+// (0, leaves, first leaf, 0).
+__global__ void k_make_lists(const int32_t *__restrict__ hc, int4 *__restrict__ lists) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t mt = 0, lf = 0;
+    for (int x = 0; x < 8; x++) {
+        lists[2 * x] = make_int4(mt, hc[x], 0, 0);
+        mt += hc[x];
+        const int32_t nl = hc[9 + x];
+        lists[2 * x + 1] = make_int4(0, nl, lf, 0);
+        lf += nl;
+    }
 }
 }  // namespace
 
@@ -60,7 +79,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(hipMemsetAsync(st.nslots.as<int32_t>() + 1, 0, 4, s));
     m2l_alloc_slots(st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.nslots.as<int32_t>(), st.new_keys.as<int32_t>(), s);
     int32_t ns[2];
-    read_sync(ns, st.nslots.ptr, 8, s);
+    read_sync(a, ns, st.nslots.ptr, 8, s);
     if (ns[0] > st.nslot_total) {
         FMM_HIP_CHECK(st.frags.grow_keep((size_t)ns[0] * op_elems * 2, s));
         m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, op_elems, a.transposed,
@@ -89,7 +108,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                    st.tmp.as<int32_t>(), s);
     exclusive_scan_i32(st.has.as<int32_t>(), ncell, cnt + 2, st.tmp.as<int32_t>(), s);
     int32_t h3[3];
-    read_sync(h3, cnt, 12, s);
+    read_sync(a, h3, cnt, 12, s);
     st.ncid = h3[0];
     st.nextra = h3[1];
     st.ntarget = h3[2];
@@ -111,7 +130,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     m2l_task_counts(st.gcount.as<int32_t>(), st.ngroup, chunk, st.tcount.as<int32_t>(), s);
     exclusive_scan_oop(st.tcount.as<int32_t>(), st.toff.as<int32_t>(), st.ngroup, cnt + 4, st.tmp.as<int32_t>(), s);
     int32_t h2[2];
-    read_sync(h2, cnt + 3, 8, s);
+    read_sync(a, h2, cnt + 3, 8, s);
     st.nentries = st.ngroup > 0 ? h2[0] : 0;
     st.ntask = st.ngroup > 0 ? h2[1] : 0;
     FMM_HIP_CHECK(st.ecls.grow((size_t)std::max(st.nentries, 1) * 4));
@@ -143,22 +162,10 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                   st.tmp.as<int32_t>(), cnt + 24, s);
     FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
     cell_centres(a.g, ncell, st.centre.as<double>(), s);
-    // ---- the 16 task lists (M2L and P2P per XCD)
-    int32_t hc[17];
-    read_sync(hc, cnt + 16, sizeof(hc), s);  // [0..7] M2L tasks per XCD, [8] leaves, [9..16] leaves per XCD
-    st.nleaves = hc[8];
-    int4 lists[16];
-    int32_t mt = 0, lf = 0;
-    for (int x = 0; x < 8; x++) {
-        lists[2 * x] = make_int4(mt, hc[x], 0, 0);
-        mt += hc[x];
-        int32_t nl = hc[9 + x];
-        lists[2 * x + 1] = make_int4(0, nl, lf, 0);
-        lf += nl;
-    }
-    FMM_HIP_CHECK(st.lists.grow(sizeof(lists)));
-    FMM_HIP_CHECK(hipMemcpyAsync(st.lists.ptr, lists, sizeof(lists), hipMemcpyHostToDevice, s));
-    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    // ---- the 16 task lists (M2L and P2P per XCD), built on the device
+    FMM_HIP_CHECK(st.lists.grow(16 * sizeof(int4)));
+    hipLaunchKernelGGL(k_make_lists, dim3(1), dim3(64), 0, s, cnt + 16, st.lists.as<int4>());
+    FMM_LAUNCH_CHECK();
     st.built = true;
 }
 
@@ -196,7 +203,6 @@ void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     q.L = a.L;
     q.P = P;
     q.leaves = st.leaves.as<int32_t>();
-    q.nleaves = st.nleaves;
     q.p2p_ptr = a.p2p_ptr;
     q.p2p_src = a.p2p_src;
     q.pf = st.pf.as<float4>();

@@ -99,6 +99,7 @@ struct fmm_plan {
     DevBuf lam, mu, wts, psi_near, epsi_near, psi_far, epsi_far;
     bool adj_ready = false;
     fmm::NearFarState nf_t;
+    fmm::HostReader reader;
     DevBuf phi_near, fld_near, phi_far, fld_far, echunk, epart;
     int32_t nechunk = 0;
     fmm::NearFarState nf;
@@ -159,10 +160,7 @@ void drop_graph(fmm_plan *p) {
     p->graph = nullptr;
 }
 
-void sync_read(fmm_plan *p, void *host, const void *dev, size_t bytes) {
-    FMM_HIP_CHECK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, p->stream));
-    FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
-}
+void sync_read(fmm_plan *p, void *host, const void *dev, size_t bytes) { p->reader.read(host, dev, bytes, p->stream); }
 
 int bits_for(int64_t n) {
     int b = 1;
@@ -374,6 +372,7 @@ fmm::NearFarArgs nf_args(fmm_plan *p) {
     a.phi = p->phi_near.as<double>();
     a.fld = p->fld_near.as<double>();
     a.tuning = p->tuning;
+    a.reader = &p->reader;
     return a;
 }
 
@@ -644,6 +643,7 @@ fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fm
         delete p;
         return FMM_ERR_DEVICE;
     }
+    p->reader.init();
     p->ev_ok = true;
     for (int i = 0; i < ST_COUNT; i++)
         if (hipEventCreate(&p->ev_beg[i]) != hipSuccess || hipEventCreate(&p->ev_end[i]) != hipSuccess)
@@ -669,6 +669,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
     for (auto &b : p->cb) b.release();
     fmm::release_near_far(p->nf);
     fmm::release_near_far(p->nf_t);
+    p->reader.release();
     for (int i = 0; i < ST_COUNT; i++) {
         if (p->ev_beg[i]) hipEventDestroy(p->ev_beg[i]);
         if (p->ev_end[i]) hipEventDestroy(p->ev_end[i]);

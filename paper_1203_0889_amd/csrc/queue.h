@@ -24,8 +24,7 @@ struct QueueArgs {
     double *L;                 // FP64 local expansions (accumulated)
     int P;
     // P2P
-    const int32_t *leaves;     // leaf cells, costliest first
-    int32_t nleaves;
+    const int32_t *leaves;     // leaf cells, by XCD, costliest first
     const int32_t *p2p_ptr, *p2p_src;
     const float4 *pf;          // particles: (x, y, z) - own leaf centre, q
     double *phi, *fld;         // FP64 near field per sorted particle

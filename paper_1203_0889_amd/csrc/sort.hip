@@ -8,6 +8,8 @@
 // input order and the sort is stable.
 #include "common.h"
 
+#include <cstring>
+
 namespace fmm {
 
 namespace {
@@ -287,11 +289,68 @@ void radix_sort_impl(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, 
 }  // namespace
 
 namespace {
+// One thread: the values, then a system-scope fence and the flag.
+__global__ void k_host_read(const int32_t *__restrict__ src, int n, int32_t *dst, int32_t seq) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i < n; i++) dst[16 + i] = src[i];
+    __threadfence_system();
+    __hip_atomic_store(&dst[0], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void k_fill_zero(uint32_t *__restrict__ p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
 }
 }  // namespace
+
+void HostReader::init() {
+    if (h) return;
+    void *ph = nullptr;
+    if (hipHostMalloc(&ph, (16 + kHostReadMax) * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    void *pd = nullptr;
+    if (hipHostGetDevicePointer(&pd, ph, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(ph);
+        return;
+    }
+    h = static_cast<int32_t *>(ph);
+    d = static_cast<int32_t *>(pd);
+    __atomic_store_n(&h[0], 0, __ATOMIC_RELEASE);
+    seq = 0;
+}
+
+void HostReader::release() {
+    if (h) (void)hipHostFree(h);
+    h = d = nullptr;
+}
+
+void HostReader::read(void *host, const void *dev, size_t bytes, hipStream_t s) {
+    if (!h || bytes > kHostReadMax * sizeof(int32_t) || (bytes & 3)) {
+        FMM_HIP_CHECK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+        FMM_HIP_CHECK(hipStreamSynchronize(s));
+        return;
+    }
+    seq = seq == 0x7fffffff ? 1 : seq + 1;
+    hipLaunchKernelGGL(k_host_read, dim3(1), dim3(64), 0, s, (const int32_t *)dev, (int)(bytes / 4), d, seq);
+    FMM_LAUNCH_CHECK();
+    for (uint64_t it = 0;; it++) {
+        if (__atomic_load_n(&h[0], __ATOMIC_ACQUIRE) == seq) break;
+        if ((it & 255) == 255) {
+            hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {  // the stream drained: the flag is visible by now
+                if (__atomic_load_n(&h[0], __ATOMIC_ACQUIRE) == seq) break;
+                throw HipError{hipErrorUnknown, "host read: flag missing after the stream drained"};
+            }
+            if (e != hipErrorNotReady) throw HipError{e, "host read"};
+        }
+        __builtin_ia32_pause();
+    }
+    std::memcpy(host, h + 16, bytes);
+}
 
 void fill_zero(void *ptr, size_t bytes, hipStream_t s) {
     const int64_t n = (int64_t)(bytes / 4);
