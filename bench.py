@@ -116,8 +116,10 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload):
     t_p2p = stage_avg.get("p2p", 0.0) * 1e-3
     t_m2l = stage_avg.get("m2l", 0.0) * 1e-3
     if precision == "mixed":
-        # M2L and P2P run in one work-queue launch (stage "queue", HIP events
-        # on the plan's stream).  Its ALU bound: P2P on the FP32 vector units
+        # M2L and P2P run in the work queue: k_queue on the plan's stream
+        # with the P2P-only k_p2p_side beside it on a forked stream (stage
+        # "queue", HIP events on the plan's stream around fork and join).
+        # Its ALU bound: P2P on the FP32 vector units
         # plus M2L on the bf16 matrix cores at three products per FP32-accurate
         # product; the two do not issue concurrently on a SIMD, so their
         # minimum times add.
@@ -125,7 +127,7 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload):
         t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
         roof = {"bound": "alu", "achieved": (p2p_flop + m2l_f) / tq / 1e12 if tq > 0 else None,
                 "peak": (p2p_flop + m2l_f) / t_min / 1e12, "unit": "TFLOP/s", "traffic": committed_traffic(workload),
-                "kernel": "k_queue (P2P FP32 VALU + M2L split-bf16 MFMA)", "kernel_ms": tq * 1e3,
+                "kernel": "k_queue + k_p2p_side (P2P FP32 VALU + M2L split-bf16 MFMA)", "kernel_ms": tq * 1e3,
                 "peak_basis": "P2P flop / 157.3 TF fp32 vector + 3 x M2L flop / 2.5 PF bf16 dense MFMA"}
     else:
         dom, t, f = ("p2p", t_p2p, p2p_flop) if t_p2p >= t_m2l else ("m2l", t_m2l, m2l_f)

@@ -198,6 +198,11 @@ fmm_status fmm_copy_lists(const fmm_plan *plan, int64_t *m2l_ptr, int32_t *m2l_s
 typedef struct {
     int32_t m2l_task_entries; /* M2L class entries per work-queue task (1..128) */
     int32_t grid_per_cu;      /* persistent work-queue workgroups per compute unit (1..8) */
+    int32_t p2p_per_cu;       /* P2P-only workgroups per compute unit launched beside the
+                                 work queue on a second stream of the plan (0..8); with 0
+                                 the work-queue workgroups of a compute unit alternate
+                                 between starting with M2L and with P2P tasks, otherwise
+                                 all of them start with M2L */
 } fmm_tuning;
 
 fmm_status fmm_get_tuning(const fmm_plan *plan, fmm_tuning *tuning);
@@ -207,10 +212,11 @@ fmm_status fmm_set_tuning(fmm_plan *plan, const fmm_tuning *tuning);
 /*
  * Autotuner of the work queue (the paper tunes its task granularity Q,
  * Sec. 5): on the plan's current tree and multipoles (after fmm_upward),
- * times the queue kernel for m2l_task_entries in {32, 64, 96, 128} and
- * grid_per_cu in {1, 2, 3, 4} (the task tables are rebuilt per
- * m2l_task_entries; each setting takes the fastest of `repeats` >= 1 runs,
- * HIP events around the kernel), keeps the fastest setting and rebuilds the
+ * times the queue for m2l_task_entries in {32, 64, 96, 128} and
+ * (grid_per_cu, p2p_per_cu) in {(1, 1), (1, 2), (1, 3), (2, 0), (3, 0)}
+ * (the task tables are rebuilt per m2l_task_entries; each setting takes the
+ * fastest of `repeats` >= 1 runs, HIP events on the plan's stream around the
+ * queue's kernels), keeps the fastest setting and rebuilds the
  * tables with it.  Outputs (host, may be NULL): the chosen tuning and its
  * kernel time in ms.  Leaves the plan as after fmm_upward (call
  * fmm_evaluate again); drops a captured graph.  The FP64 path has no queue:

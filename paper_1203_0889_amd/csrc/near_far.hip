@@ -10,8 +10,9 @@ namespace fmm {
 
 fmm_tuning default_tuning() {
     fmm_tuning t;
-    t.m2l_task_entries = 96;
-    t.grid_per_cu = 2;
+    t.m2l_task_entries = 128;
+    t.grid_per_cu = 1;
+    t.p2p_per_cu = 2;
     return t;
 }
 
@@ -213,8 +214,15 @@ void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     int dev = 0, ncu = 256;
     FMM_HIP_CHECK(hipGetDevice(&dev));
     FMM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
-    queue_run(q, a.p, ncu * per_cu, s);
+    const int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
+    const int side_per_cu = std::max(0, std::min(8, a.tuning.p2p_per_cu));
+    if (side_per_cu > 0 && !st.side) {
+        // default priority, like the plan's stream
+        FMM_HIP_CHECK(hipStreamCreateWithFlags(&st.side, hipStreamNonBlocking));
+        FMM_HIP_CHECK(hipEventCreateWithFlags(&st.fork, hipEventDisableTiming));
+        FMM_HIP_CHECK(hipEventCreateWithFlags(&st.join, hipEventDisableTiming));
+    }
+    queue_run(q, a.p, ncu * per_cu, ncu * side_per_cu, st.side, st.fork, st.join, s);
 }
 
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
@@ -232,6 +240,14 @@ void release_near_far(NearFarState &st) {
                      &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
                      &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists};
     for (DevBuf *b : all) b->release();
+    if (st.side) {
+        (void)hipStreamSynchronize(st.side);
+        (void)hipStreamDestroy(st.side);
+        (void)hipEventDestroy(st.fork);
+        (void)hipEventDestroy(st.join);
+    }
+    st.side = nullptr;
+    st.fork = st.join = nullptr;
     st.p = -1;
     st.built = false;
 }

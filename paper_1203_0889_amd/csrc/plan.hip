@@ -884,7 +884,8 @@ fmm_status fmm_get_tuning(const fmm_plan *p, fmm_tuning *t) {
 
 fmm_status fmm_set_tuning(fmm_plan *p, const fmm_tuning *t) {
     if (!p || !t) return FMM_ERR_INVALID_ARG;
-    if (t->m2l_task_entries < 1 || t->m2l_task_entries > 128 || t->grid_per_cu < 1 || t->grid_per_cu > 8)
+    if (t->m2l_task_entries < 1 || t->m2l_task_entries > 128 || t->grid_per_cu < 1 || t->grid_per_cu > 8 ||
+        t->p2p_per_cu < 0 || t->p2p_per_cu > 8)
         return fail(p, FMM_ERR_INVALID_ARG, "tuning out of range");
     p->tuning = *t;
     return FMM_OK;
@@ -905,7 +906,8 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
         p->adj_ready = false;
         ensure_eval_buffers(p);   // the queue writes the locals and the near field
         static const int kEntries[] = {32, 64, 96, 128};
-        static const int kGrid[] = {1, 2, 3, 4};
+        // (work-queue, P2P side) workgroups per compute unit
+        static const int kShape[][2] = {{1, 1}, {1, 2}, {1, 3}, {2, 0}, {3, 0}};
         hipEvent_t e0, e1;
         FMM_HIP_CHECK(hipEventCreate(&e0));
         FMM_HIP_CHECK(hipEventCreate(&e1));
@@ -915,8 +917,9 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
             for (int ce : kEntries) {
                 p->tuning.m2l_task_entries = ce;
                 fmm::build_near_far_mixed(p->nf, nf_args(p), s);
-                for (int cg : kGrid) {
-                    p->tuning.grid_per_cu = cg;
+                for (const auto &sh : kShape) {
+                    p->tuning.grid_per_cu = sh[0];
+                    p->tuning.p2p_per_cu = sh[1];
                     fmm::NearFarArgs a = nf_args(p);
                     float t_min = -1.0f;
                     for (int r = 0; r < repeats; r++) {

@@ -33,6 +33,7 @@ struct QueueArgs {
     // P2P task t of a list is leaf first + t.
     const int4 *lists;
     int32_t *heads;            // 16 claim counters (zeroed before launch)
+    int32_t role_split;        // set by queue_run
 };
 
 bool queue_supported(int p);
@@ -48,6 +49,13 @@ int64_t queue_mrow_elems(int p);
 // Split the FP64 multipoles into bf16 (hi, lo) rows; Mb must hold ncell + 1
 // rows, row ncell is written as zero.
 void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb, hipStream_t s);
-void queue_run(const QueueArgs &a, int p, int nworkgroups, hipStream_t s);
+// The work queue on stream s: nworkgroups persistent workgroups of k_queue
+// and, if nside > 0, nside P2P-only workgroups on the stream `side`, forked
+// from and joined back into s with the events fork and join.  Without side
+// workgroups the k_queue workgroups sharing a compute unit alternate which
+// task type they start with; with them every k_queue workgroup starts with
+// M2L and the side kernel drains the P2P tasks beside it.
+void queue_run(const QueueArgs &a, int p, int nworkgroups, int nside, hipStream_t side, hipEvent_t fork,
+               hipEvent_t join, hipStream_t s);
 
 }  // namespace fmm

@@ -416,16 +416,32 @@ __device__ void m2l_group(const QueueArgs &a, int4 task, int w, int lane, v4f *r
 template <int RT>
 constexpr int queue_lds_f4() { return ring_f4<RT>() > 4 * kP2PTile ? ring_f4<RT>() : 4 * kP2PTile; }
 
+// All P2P tasks this wave can claim, own XCD's list first.
+__device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__restrict__ tile) {
+    for (int k = 0; k < 8; k++) {
+        const int L = (((x + k) & 7) << 1) | 1;
+        const int4 li = a.lists[L];
+        for (;;) {
+            int32_t t = 0;
+            if (lane == 0) t = atomicAdd(&a.heads[L], 1);
+            t = __builtin_amdgcn_readfirstlane(t);      // lane 0's claim, wave-uniform
+            if (t >= li.y) break;
+            p2p_leaf(a, a.leaves[li.z + t], tile, lane);
+        }
+    }
+}
+
 template <int RT>
 __global__ void __launch_bounds__(256) k_queue(QueueArgs a) {
     __shared__ v4f lds[queue_lds_f4<RT>()];
     __shared__ int32_t claim;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    // Workgroups go round-robin over the 8 XCDs.  The workgroup slot on
-    // its compute unit (HW_ID bits 19:16) picks the task type it starts
-    // with, so the workgroups sharing a compute unit mix the two types.
+    // Workgroups go round-robin over the 8 XCDs.  With role_split the
+    // workgroup slot on its compute unit (HW_ID bits 19:16) picks the task
+    // type it starts with, so the workgroups sharing a compute unit mix the
+    // two types; otherwise every workgroup starts with M2L.
     const int x = blockIdx.x & 7;
-    const int role = __builtin_amdgcn_s_getreg((4 << 0) | (16 << 6) | (3 << 11)) & 1;
+    const int role = a.role_split ? (__builtin_amdgcn_s_getreg((4 << 0) | (16 << 6) | (3 << 11)) & 1) : 0;
     for (int ph = 0; ph < 2; ph++) {
         if ((ph ^ role) == 0) {
             for (int k = 0; k < 8; k++) {
@@ -441,21 +457,20 @@ __global__ void __launch_bounds__(256) k_queue(QueueArgs a) {
                 }
             }
         } else {
-            float4 *tile = reinterpret_cast<float4 *>(lds) + w * kP2PTile;
-            for (int k = 0; k < 8; k++) {
-                const int L = (((x + k) & 7) << 1) | 1;
-                const int4 li = a.lists[L];
-                for (;;) {
-                    int32_t t = 0;
-                    if (lane == 0) t = atomicAdd(&a.heads[L], 1);
-                    t = __builtin_amdgcn_readfirstlane(t);      // lane 0's claim, wave-uniform
-                    if (t >= li.y) break;
-                    p2p_leaf(a, a.leaves[li.z + t], tile, lane);
-                }
-            }
+            p2p_phase(a, x, lane, reinterpret_cast<float4 *>(lds) + w * kP2PTile);
         }
         __syncthreads();   // the LDS changes role
     }
+}
+
+// P2P tasks only, from the same lists and claim counters as k_queue.  Its
+// waves need about half the registers of k_queue's (no MFMA accumulators),
+// so launched beside k_queue they give each SIMD more P2P waves to hide
+// latency with while the M2L tasks run.
+__global__ void __launch_bounds__(256) k_p2p_side(QueueArgs a) {
+    __shared__ float4 tiles[4 * kP2PTile];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    p2p_phase(a, blockIdx.x & 7, lane, tiles + w * kP2PTile);
 }
 
 // ------------------------------------------------------------------ prep
@@ -508,8 +523,20 @@ void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb,
     FMM_LAUNCH_CHECK();
 }
 
-void queue_run(const QueueArgs &a, int p, int nworkgroups, hipStream_t s) {
+void queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, hipStream_t side, hipEvent_t fork,
+               hipEvent_t join, hipStream_t s) {
+    if (nworkgroups < 1 || nside < 0 || (nside > 0 && (!side || !fork || !join)))
+        throw HipError{hipErrorInvalidValue, "queue: bad launch configuration"};
+    QueueArgs a = a_in;
+    a.role_split = nside == 0;
     fill_zero(a.heads, 16 * sizeof(int32_t), s);
+    if (nside > 0) {
+        // fork: the side stream starts after everything queued on s so far
+        FMM_HIP_CHECK(hipEventRecord(fork, s));
+        FMM_HIP_CHECK(hipStreamWaitEvent(side, fork, 0));
+        hipLaunchKernelGGL(k_p2p_side, dim3(nside), dim3(256), 0, side, a);
+        FMM_LAUNCH_CHECK();
+    }
     dim3 grid(nworkgroups), block(256);
 #define FMM_Q(PP, R)                                                      \
     case PP:                                                              \
@@ -522,6 +549,11 @@ void queue_run(const QueueArgs &a, int p, int nworkgroups, hipStream_t s) {
     }
 #undef FMM_Q
     FMM_LAUNCH_CHECK();
+    if (nside > 0) {
+        // join: work queued on s after this waits for the side kernel too
+        FMM_HIP_CHECK(hipEventRecord(join, side));
+        FMM_HIP_CHECK(hipStreamWaitEvent(s, join, 0));
+    }
 }
 
 }  // namespace fmm

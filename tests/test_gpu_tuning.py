@@ -24,7 +24,7 @@ def test_autotune_mixed():
     tuning, ms = plan.autotune(repeats=2)
     print("autotune:", tuning, ms, flush=True)
     assert tuning["m2l_task_entries"] in (32, 64, 96, 128)
-    assert tuning["grid_per_cu"] in (1, 2, 3, 4)
+    assert (tuning["grid_per_cu"], tuning["p2p_per_cu"]) in ((1, 1), (1, 2), (1, 3), (2, 0), (3, 0))
     assert ms > 0
     assert plan.get_tuning() == tuning
     out = {k: v.cpu().numpy() for k, v in plan.evaluate().items() if v is not None}
@@ -53,6 +53,10 @@ def test_tuning_validation():
         plan.set_tuning(m2l_task_entries=0)
     with pytest.raises(fmm.FMMError):
         plan.set_tuning(grid_per_cu=9)
+    with pytest.raises(fmm.FMMError):
+        plan.set_tuning(p2p_per_cu=9)
+    with pytest.raises(fmm.FMMError):
+        plan.set_tuning(p2p_per_cu=-1)
     with pytest.raises(fmm.FMMError) as ei:
         plan.autotune()
     assert ei.value.status == -2
@@ -74,3 +78,28 @@ def test_autotune_right_after_upward():
     r = ref.evaluate()
     torch.cuda.synchronize()
     assert rel(out["phi"].cpu().numpy(), r["phi"].cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("dist", ["uniform", "plummer"])
+def test_launch_shapes_agree(dist):
+    """The queue with and without the P2P side kernel, and with several
+    workgroup counts, on one tree: the near field is summed per leaf in a
+    fixed order, and the locals differ only by the order of FP64 atomic
+    additions of FP32 task sums.  (The launch shape is read at evaluate
+    time; the task tables depend only on m2l_task_entries.)"""
+    n = 150000
+    pos, q = W.uniform_cube(n, 61) if dist == "uniform" else W.plummer(n, 62)
+    plan = fmm.Plan(p=8, ncrit=64, theta=(1, 2), precision="mixed", device=0)
+    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    ref = None
+    for shape in ((1, 2), (2, 0), (1, 1), (3, 0), (1, 3), (4, 4)):
+        plan.set_tuning(grid_per_cu=shape[0], p2p_per_cu=shape[1])
+        plan.upward()
+        out = {k: v.cpu().numpy() for k, v in plan.evaluate().items() if v is not None}
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = out
+            continue
+        e = (rel(out["phi"], ref["phi"]), rel(out["field"], ref["field"]))
+        print(dist, "shape", shape, e, flush=True)
+        assert max(e) < 1e-12
