@@ -75,20 +75,22 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(CellArrays c, const i
         if (i < nf) {
             int2 pr = fin[i];
             int32_t A = pr.x, B = pr.y;
-            int la = c.level[A], lb = c.level[B];
-            int32_t chA = c.child[A], chB = c.child[B];
+            const int4 ra = c.rec[A], rb = c.rec[B];
+            int la = rec_level(ra), lb = rec_level(rb);
+            int32_t chA = rec_child(ra), chB = rec_child(rb);
             bool leafA = chA < 0, leafB = chB < 0;
             const K key = ((K)(uint32_t)A << bits) | (K)(uint32_t)B;
-            if (A != B && mac_exact(la, c.ix[A], c.iy[A], c.iz[A], lb, c.ix[B], c.iy[B], c.iz[B], ta, tb)) {
+            if (A != B &&
+                mac_exact(la, rec_ix(ra), rec_iy(ra), rec_iz(ra), lb, rec_ix(rb), rec_iy(rb), rec_iz(rb), ta, tb)) {
                 bm[atomicAdd(&cm, 1)] = key;
             } else if (leafA && leafB) {
                 bp[atomicAdd(&cp, 1)] = key;
             } else if (!leafB && (leafA || la > lb)) {
-                int k = c.nchild[B];
+                int k = rec_nchild(rb);
                 int32_t o = atomicAdd(&cf, k);
                 for (int j = 0; j < k; j++) bf[o + j] = make_int2(A, chB + j);
             } else {
-                int k = c.nchild[A];
+                int k = rec_nchild(ra);
                 int32_t o = atomicAdd(&cf, k);
                 for (int j = 0; j < k; j++) bf[o + j] = make_int2(chA + j, B);
             }

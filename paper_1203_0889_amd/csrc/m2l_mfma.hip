@@ -50,18 +50,22 @@ __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__res
                                int32_t *__restrict__ used, int32_t *__restrict__ xcount) {
     for (int32_t A = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; A < ncell; A += gridDim.x * blockDim.x / 64) {
         int nx = 0;
-        int la = c.level[A];
-        int64_t SA = (int64_t)1 << (kLevels - la);
-        int64_t ca[3] = {(2 * (int64_t)c.ix[A] + 1) * SA, (2 * (int64_t)c.iy[A] + 1) * SA,
-                         (2 * (int64_t)c.iz[A] + 1) * SA};
+        const int4 ra = c.rec[A];
+        const int la = rec_level(ra);
+        const int64_t SA = (int64_t)1 << (kLevels - la);
+        const int64_t ca[3] = {(2 * (int64_t)rec_ix(ra) + 1) * SA, (2 * (int64_t)rec_iy(ra) + 1) * SA,
+                               (2 * (int64_t)rec_iz(ra) + 1) * SA};
         for (int32_t e = ptr[A] + (threadIdx.x & 63); e < ptr[A + 1]; e += 64) {
             int32_t B = src[e];
-            int lb = c.level[B];
-            int64_t SB = (int64_t)1 << (kLevels - lb);
-            int64_t smin = SA < SB ? SA : SB;
-            int rx = (int)((ca[0] - (2 * (int64_t)c.ix[B] + 1) * SB) / smin);
-            int ry = (int)((ca[1] - (2 * (int64_t)c.iy[B] + 1) * SB) / smin);
-            int rz = (int)((ca[2] - (2 * (int64_t)c.iz[B] + 1) * SB) / smin);
+            const int4 rb = c.rec[B];
+            const int lb = rec_level(rb);
+            const int64_t SB = (int64_t)1 << (kLevels - lb);
+            // both centres are multiples of the smaller half-size 2^sh: the
+            // division by it is an exact arithmetic shift
+            const int sh = kLevels - (la > lb ? la : lb);
+            int rx = (int)((ca[0] - (2 * (int64_t)rec_ix(rb) + 1) * SB) >> sh);
+            int ry = (int)((ca[1] - (2 * (int64_t)rec_iy(rb) + 1) * SB) >> sh);
+            int rz = (int)((ca[2] - (2 * (int64_t)rec_iz(rb) + 1) * SB) >> sh);
             int k = dense_key(la - lb, rx, ry, rz);
             pkey[e] = k;
             if (k >= 0) {

@@ -83,7 +83,7 @@ struct fmm_plan {
     DevBuf keys, kalt, idx, valt, ikey, ialt, rank, ralt, tmp;
     DevBuf xs, ys, zs, qs, leaf_of;
     // tree
-    DevBuf cb[10];
+    DevBuf cb[10], crec;
     int64_t cell_cap = 0;
     DevBuf bounds, nch, counters;
     int64_t ncell = 0, nleaf = 0, nm2l = 0, np2p = 0;
@@ -126,6 +126,7 @@ fmm::CellArrays cells_of(fmm_plan *p) {
     fmm::CellArrays c;
     int32_t **f[10] = {&c.level, &c.ix, &c.iy, &c.iz, &c.first, &c.count, &c.child, &c.nchild, &c.parent, &c.inst};
     for (int i = 0; i < 10; i++) *f[i] = p->cb[i].as<int32_t>();
+    c.rec = p->crec.as<int4>();
     return c;
 }
 
@@ -134,6 +135,8 @@ void ensure_cells(fmm_plan *p, int64_t want) {
     for (int i = 0; i < 10; i++) FMM_HIP_CHECK(p->cb[i].grow_keep((size_t)want * sizeof(int32_t), p->stream));
     int64_t cap = (int64_t)(p->cb[0].bytes / sizeof(int32_t));
     for (int i = 1; i < 10; i++) cap = std::min<int64_t>(cap, (int64_t)(p->cb[i].bytes / sizeof(int32_t)));
+    // the records cover the same capacity (written after the tree is complete)
+    FMM_HIP_CHECK(p->crec.grow((size_t)cap * sizeof(int4)));
     p->cell_cap = cap;
 }
 
@@ -258,6 +261,7 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         p->level_begin.push_back(le);
     }
     p->ncell = le;
+    if ((size_t)p->ncell * sizeof(int4) > p->crec.bytes) throw std::runtime_error("cell records smaller than the tree");
     fmm::launch_leaf_of(cells_of(p), (int32_t)p->ncell, p->leaf_of.as<int32_t>(), p->flag.as<int32_t>() + 1, s);
     mark(p, ST_TREE);
 
@@ -667,6 +671,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
     drop_graph(p);
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
+    p->crec.release();
     fmm::release_near_far(p->nf);
     fmm::release_near_far(p->nf_t);
     p->reader.release();

@@ -12,7 +12,18 @@ struct CellArrays {
     int32_t *first, *count;         // particle range in sorted order
     int32_t *child, *nchild;        // first child (-1 for leaves), number of children
     int32_t *parent, *inst;         // parent cell (-1 for roots), instance
+    // The fields the traversal and the class keys read, one 16-byte record
+    // per cell (one load instead of six gathers): (ix | level << 24,
+    // iy | nchild << 24, iz, child).  Coordinates are below 2^21.
+    int4 *rec;
 };
+
+__device__ inline int rec_level(int4 r) { return r.x >> 24; }
+__device__ inline int rec_ix(int4 r) { return r.x & 0xffffff; }
+__device__ inline int rec_iy(int4 r) { return r.y & 0xffffff; }
+__device__ inline int rec_iz(int4 r) { return r.z; }
+__device__ inline int rec_nchild(int4 r) { return r.y >> 24; }
+__device__ inline int rec_child(int4 r) { return r.w; }
 
 // ---- tree.hip
 void launch_bbox(const double *pos, int64_t n, const int64_t *d_offsets, int n_inst, unsigned long long *d_ord,

@@ -250,6 +250,8 @@ __global__ void k_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t
 
 __global__ void k_leaf_of(CellArrays c, int32_t ncell, int32_t *__restrict__ leaf_of, int32_t *__restrict__ nleaf) {
     for (int32_t cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
+        c.rec[cell] = make_int4(c.ix[cell] | (c.level[cell] << 24), c.iy[cell] | (c.nchild[cell] << 24), c.iz[cell],
+                                c.child[cell]);
         if (c.child[cell] >= 0) continue;
         atomicAdd(nleaf, 1);
         int32_t f = c.first[cell], e = f + c.count[cell];
