@@ -30,29 +30,63 @@ __device__ inline bool mac_exact(int la, int ax, int ay, int az, int lb, int bx,
     return 3ull * b * b * s * s < a * a * d2;
 }
 
-// One BFS step.  The frontier size is read from device memory (clamped to
-// the buffer capacity), so all steps are enqueued without host round trips.
-// Each workgroup stages its accepted pairs and its next-frontier pairs in
-// LDS and reserves global space with one atomic per flush: same-address
-// atomics are few, and global writes are contiguous.
+// One BFS step, two tree levels deep.  Every frontier pair is decided;
+// a pair that is split has its (at most 8) child pairs decided at once, in
+// the same thread, and only the child pairs that must be split again go to
+// the next frontier.  Compared with one level per step this halves the
+// steps and keeps the pairs that resolve at the next level (most of the
+// last levels' pairs) out of the frontier buffers.  The frontier size is
+// read from device memory (clamped to the buffer capacity), so all steps
+// are enqueued without host round trips.  Each workgroup stages its
+// accepted pairs and its next-frontier pairs in LDS and reserves global
+// space with one atomic per flush: same-address atomics are few, and
+// global writes are contiguous.
 constexpr int kTravThreads = 256;
-constexpr int kBufM = 2048;   // staged M2L keys
-constexpr int kBufP = 1024;   // staged P2P keys
-constexpr int kBufF = 4096;   // staged frontier pairs (one tile adds at most 8 per thread)
+constexpr int kTileOut = 8 * kTravThreads;   // most entries one tile adds to one buffer
+constexpr int kBufM = kTileOut + 1024;       // staged M2L keys (flushed above 1024)
+constexpr int kBufP = kTileOut + 1024;       // staged P2P keys (flushed above 1024)
+constexpr int kBufF = kTileOut;              // staged frontier pairs (flushed every tile)
+
+// Barrier for LDS traffic only: global loads in flight (the prefetched
+// pairs and records of the next tiles) stay in flight.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 template <class K>
 __device__ inline void flush_keys(K *__restrict__ buf, int32_t &cnt, K *__restrict__ out, int32_t cap,
                                   int32_t *__restrict__ gcount, int32_t *sh_base) {
     if (threadIdx.x == 0) *sh_base = atomicAdd(gcount, cnt);
-    __syncthreads();
+    lds_barrier();
     int32_t base = *sh_base;
     for (int j = threadIdx.x; j < cnt; j += kTravThreads)
         if (base + j < cap) out[base + j] = buf[j];
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
+    lds_barrier();
 }
 
+// The pure decision of one pair: M2L, P2P, or split (staged in LDS).
+template <class K>
+__device__ inline void decide(int32_t A, int32_t B, int4 ra, int4 rb, int bits, uint32_t ta, uint32_t tb,
+                              K *__restrict__ bm, int32_t &cm, K *__restrict__ bp, int32_t &cp, bool &split) {
+    split = false;
+    const K key = ((K)(uint32_t)A << bits) | (K)(uint32_t)B;
+    if (A != B && mac_exact(rec_level(ra), rec_ix(ra), rec_iy(ra), rec_iz(ra), rec_level(rb), rec_ix(rb), rec_iy(rb),
+                            rec_iz(rb), ta, tb))
+        bm[atomicAdd(&cm, 1)] = key;
+    else if (rec_child(ra) < 0 && rec_child(rb) < 0)
+        bp[atomicAdd(&cp, 1)] = key;
+    else
+        split = true;
+}
+
+// Each thread takes one frontier pair per tile.  The loads are software
+// pipelined: while a tile is decided, the records of the next tile and the
+// pair of the one after are in flight (indices clamped to the last pair, so
+// every load is unconditional and in bounds).
 template <class K>
 __global__ void __launch_bounds__(kTravThreads) k_traverse(CellArrays c, const int2 *__restrict__ fin,
                                                            const int32_t *__restrict__ nf_in, int2 *__restrict__ fout,
@@ -67,41 +101,52 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(CellArrays c, const i
     __shared__ int32_t cm, cp, cf, base_sh;
     int32_t nf = *nf_in;
     nf = nf < capf ? nf : capf;
+    if (nf <= 0) return;
     if (threadIdx.x == 0) cm = cp = cf = 0;
-    __syncthreads();
+    lds_barrier();
     const int32_t stride = gridDim.x * kTravThreads;
-    for (int32_t base = blockIdx.x * kTravThreads; base < nf; base += stride) {
-        int32_t i = base + threadIdx.x;
+    const int32_t last = nf - 1;
+    int32_t i = blockIdx.x * kTravThreads + threadIdx.x;
+    int2 pr = fin[i < last ? i : last];
+    int4 ra = c.rec[pr.x], rb = c.rec[pr.y];
+    int2 pn = fin[i + stride < last ? i + stride : last];
+    for (int32_t base = blockIdx.x * kTravThreads; base < nf; base += stride, i += stride) {
+        const int4 na = c.rec[pn.x], nb = c.rec[pn.y];
+        const int2 pnn = fin[i + 2 * stride < last ? i + 2 * stride : last];
         if (i < nf) {
-            int2 pr = fin[i];
-            int32_t A = pr.x, B = pr.y;
-            const int4 ra = c.rec[A], rb = c.rec[B];
-            int la = rec_level(ra), lb = rec_level(rb);
-            int32_t chA = rec_child(ra), chB = rec_child(rb);
-            bool leafA = chA < 0, leafB = chB < 0;
-            const K key = ((K)(uint32_t)A << bits) | (K)(uint32_t)B;
-            if (A != B &&
-                mac_exact(la, rec_ix(ra), rec_iy(ra), rec_iz(ra), lb, rec_ix(rb), rec_iy(rb), rec_iz(rb), ta, tb)) {
-                bm[atomicAdd(&cm, 1)] = key;
-            } else if (leafA && leafB) {
-                bp[atomicAdd(&cp, 1)] = key;
-            } else if (!leafB && (leafA || la > lb)) {
-                int k = rec_nchild(rb);
-                int32_t o = atomicAdd(&cf, k);
-                for (int j = 0; j < k; j++) bf[o + j] = make_int2(A, chB + j);
-            } else {
-                int k = rec_nchild(ra);
-                int32_t o = atomicAdd(&cf, k);
-                for (int j = 0; j < k; j++) bf[o + j] = make_int2(chA + j, B);
+            const int32_t A = pr.x, B = pr.y;
+            bool split;
+            decide<K>(A, B, ra, rb, bits, ta, tb, bm, cm, bp, cp, split);
+            if (split) {
+                // split the source if it is not a leaf and the target is a
+                // leaf or smaller; otherwise the target (ties split the target)
+                const bool sb = rec_child(rb) >= 0 && (rec_child(ra) < 0 || rec_level(ra) > rec_level(rb));
+                const int4 rs = sb ? rb : ra, ro = sb ? ra : rb;
+                const int32_t first = rec_child(rs), k = rec_nchild(rs), other = sb ? A : B;
+                int4 rc[8];
+#pragma unroll
+                for (int j = 0; j < 8; j++) rc[j] = c.rec[first + (j < k ? j : k - 1)];
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    if (j < k) {
+                        const int32_t X = sb ? other : first + j, Y = sb ? first + j : other;
+                        bool again;
+                        decide<K>(X, Y, sb ? ro : rc[j], sb ? rc[j] : ro, bits, ta, tb, bm, cm, bp, cp, again);
+                        if (again) bf[atomicAdd(&cf, 1)] = make_int2(X, Y);
+                    }
+                }
             }
         }
-        __syncthreads();
-        // a tile adds at most 256 keys per list and 2048 frontier pairs
-        if (cm > kBufM - kTravThreads) flush_keys<K>(bm, cm, m2l, cap_m2l, n_m2l, &base_sh);
-        if (cp > kBufP - kTravThreads) flush_keys<K>(bp, cp, p2p, cap_p2p, n_p2p, &base_sh);
-        if (cf > kBufF - 8 * kTravThreads) flush_keys<int2>(bf, cf, fout, capf, nf_out, &base_sh);
+        lds_barrier();
+        if (cm > kBufM - kTileOut) flush_keys<K>(bm, cm, m2l, cap_m2l, n_m2l, &base_sh);
+        if (cp > kBufP - kTileOut) flush_keys<K>(bp, cp, p2p, cap_p2p, n_p2p, &base_sh);
+        if (cf > kBufF - kTileOut) flush_keys<int2>(bf, cf, fout, capf, nf_out, &base_sh);
+        pr = pn;
+        ra = na;
+        rb = nb;
+        pn = pnn;
     }
-    __syncthreads();
+    lds_barrier();
     if (cm > 0) flush_keys<K>(bm, cm, m2l, cap_m2l, n_m2l, &base_sh);
     if (cp > 0) flush_keys<K>(bp, cp, p2p, cap_p2p, n_p2p, &base_sh);
     if (cf > 0) flush_keys<int2>(bf, cf, fout, capf, nf_out, &base_sh);
