@@ -286,14 +286,19 @@ __device__ inline int slot_of_index(const int32_t *pre, int nt, int32_t idx) {
     return lo;
 }
 
+// The group's targets (tgt), the first list entry of each (fst), and the
+// exclusive prefix of their pair counts (pre, nt + 1 values), in LDS.
 __device__ inline void load_group(const uint64_t *__restrict__ tsorted, int32_t ntarget, int g,
-                                  const int32_t *__restrict__ ptr, int32_t *pre, int32_t *tgt, int *nt_out) {
+                                  const int32_t *__restrict__ ptr, int32_t *pre, int32_t *tgt, int32_t *fst,
+                                  int *nt_out) {
     const int t0 = g * kGroupM2L;
     const int nt = ntarget - t0 < kGroupM2L ? ntarget - t0 : kGroupM2L;
     if (threadIdx.x < nt) {
         int32_t A = (int32_t)(tsorted[t0 + threadIdx.x] & 0xffffffffull);
         tgt[threadIdx.x] = A;
-        pre[threadIdx.x + 1] = ptr[A + 1] - ptr[A];
+        const int32_t f = ptr[A];
+        fst[threadIdx.x] = f;
+        pre[threadIdx.x + 1] = ptr[A + 1] - f;
     }
     if (threadIdx.x == 0) pre[0] = 0;
     __syncthreads();
@@ -307,17 +312,17 @@ __global__ void __launch_bounds__(256) k_group_mark(const uint64_t *__restrict__
                                                     const int32_t *__restrict__ ptr, const int32_t *__restrict__ pcid,
                                                     int nwords, uint32_t *__restrict__ gbits) {
     extern __shared__ uint32_t lbits[];
-    __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L];
+    __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L], fst[kGroupM2L];
     int g, split;
     group_split_of(blockIdx.x, &g, &split);
     if (g * kGroupM2L >= ntarget) return;
     for (int w = threadIdx.x; w < nwords; w += blockDim.x) lbits[w] = 0u;
     int nt;
-    load_group(tsorted, ntarget, g, ptr, pre, tgt, &nt);
+    load_group(tsorted, ntarget, g, ptr, pre, tgt, fst, &nt);
     const int32_t total = pre[nt];
     for (int32_t idx = split * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
         int s = slot_of_index(pre, nt, idx);
-        int32_t cid = pcid[ptr[tgt[s]] + (idx - pre[s])];
+        int32_t cid = pcid[fst[s] + (idx - pre[s])];
         if (cid >= 0) atomicOr(&lbits[cid >> 5], 1u << (cid & 31));
     }
     __syncthreads();
@@ -356,6 +361,9 @@ __global__ void __launch_bounds__(256) k_group_prefix(int nwords, const uint32_t
     }
 }
 
+// kLds: the group's class bitmap and word prefixes are staged in LDS
+// (dynamic, 2 nwords words) instead of read from global memory per pair.
+template <bool kLds>
 __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__ tsorted, int32_t ntarget,
                                                     const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
                                                     const int32_t *__restrict__ pcid, int nwords,
@@ -363,17 +371,25 @@ __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__
                                                     const uint32_t *__restrict__ gwpre,
                                                     const int32_t *__restrict__ goff, int32_t *__restrict__ ecls,
                                                     int32_t *__restrict__ esrc, int32_t *__restrict__ gtarget) {
-    __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L];
+    extern __shared__ uint32_t ltab[];
+    __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L], fst[kGroupM2L];
     int g, split;
     group_split_of(blockIdx.x, &g, &split);
     if (g * kGroupM2L >= ntarget) return;
+    const uint32_t *gb = gbits + (int64_t)g * nwords;
+    const uint32_t *gw = gwpre + (int64_t)g * nwords;
+    if (kLds)
+        for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
+            ltab[w] = gb[w];
+            ltab[nwords + w] = gw[w];
+        }
     int nt;
-    load_group(tsorted, ntarget, g, ptr, pre, tgt, &nt);
+    load_group(tsorted, ntarget, g, ptr, pre, tgt, fst, &nt);   // its barriers cover the staging too
     if (split == 0 && threadIdx.x < kGroupM2L)
         gtarget[(int64_t)g * kGroupM2L + threadIdx.x] = threadIdx.x < nt ? tgt[threadIdx.x] : -1;
     const int32_t total = pre[nt];
-    const uint32_t *bits = gbits + (int64_t)g * nwords;
-    const uint32_t *wpre = gwpre + (int64_t)g * nwords;
+    const uint32_t *bits = kLds ? ltab : gb;
+    const uint32_t *wpre = kLds ? ltab + nwords : gw;
     const int32_t base = goff[g];
     if (split == 0)
         for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
@@ -387,7 +403,7 @@ __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__
         }
     for (int32_t idx = split * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
         int s = slot_of_index(pre, nt, idx);
-        int32_t e = ptr[tgt[s]] + (idx - pre[s]);
+        int32_t e = fst[s] + (idx - pre[s]);
         int32_t cid = pcid[e];
         if (cid < 0) continue;
         uint32_t wv = bits[cid >> 5] & ((1u << (cid & 31)) - 1u);
@@ -512,8 +528,13 @@ void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr
     const int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
     if (ngroup <= 0) return;
     const int nwords = (ncid + 31) / 32;
-    hipLaunchKernelGGL(k_group_fill, dim3(group_blocks(ngroup)), dim3(256), 0, s, tsorted, ntarget, ptr, src, pcid,
-                       nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
+    const size_t tab = (size_t)2 * nwords * 4;
+    if (tab <= 32768)
+        hipLaunchKernelGGL(k_group_fill<true>, dim3(group_blocks(ngroup)), dim3(256), tab, s, tsorted, ntarget, ptr,
+                           src, pcid, nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
+    else
+        hipLaunchKernelGGL(k_group_fill<false>, dim3(group_blocks(ngroup)), dim3(256), 0, s, tsorted, ntarget, ptr, src,
+                           pcid, nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
     FMM_LAUNCH_CHECK();
 }
 

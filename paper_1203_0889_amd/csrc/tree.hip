@@ -187,37 +187,40 @@ __global__ void k_roots(const int64_t *__restrict__ offsets, int n_inst, CellArr
 
 // For each cell of the current level: octant boundaries of its children
 // (lower bounds of each level-(l+1) digit within its sorted key range) and
-// the number of non-empty children, or 0 if it stays a leaf.
+// the number of non-empty children, or 0 if it stays a leaf.  Eight lanes
+// per cell: lane o searches the lower bound of digit o on its own, so the
+// seven searches run side by side instead of one after another.
 __global__ void k_tree_count(CellArrays c, int32_t lb, int32_t le, int ncrit, int max_level,
                              const uint64_t *__restrict__ skeys, int32_t *__restrict__ bounds,
                              int32_t *__restrict__ nch) {
-    int32_t cell = lb + blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= le) return;
-    int32_t j = cell - lb;
-    int level = c.level[cell];
-    int32_t first = c.first[cell], count = c.count[cell];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t cell = lb + (int32_t)(t >> 3);
+    const int o = (int)(t & 7);
+    if (cell >= le) return;   // the 8 lanes of a cell leave together
+    const int32_t j = cell - lb;
+    const int level = c.level[cell];
+    const int32_t first = c.first[cell], count = c.count[cell];
     if (count <= ncrit || level >= max_level) {
-        nch[j] = 0;
+        if (o == 0) nch[j] = 0;
         return;
     }
-    int shift = 3 * (kLevels - (level + 1));
-    int32_t lo = first, end = first + count;
-    int nonempty = 0;
-    bounds[9 * j] = first;
-    for (int o = 1; o < 8; o++) {
-        // first index in [lo, end) whose digit is >= o
-        int32_t a = lo, b = end;
+    const int shift = 3 * (kLevels - (level + 1));
+    const int32_t end = first + count;
+    // first index in [first, end) whose digit is >= o
+    int32_t a = first, b = end;
+    if (o > 0)
         while (a < b) {
             int32_t mid = a + ((b - a) >> 1);
             int dig = (int)((skeys[mid] >> shift) & 7ull);
             if (dig < o) a = mid + 1; else b = mid;
         }
-        bounds[9 * j + o] = a;
-        lo = a;
-    }
-    bounds[9 * j + 8] = end;
-    for (int o = 0; o < 8; o++) nonempty += bounds[9 * j + o + 1] > bounds[9 * j + o];
-    nch[j] = nonempty;
+    bounds[9 * j + o] = a;
+    if (o == 7) bounds[9 * j + 8] = end;
+    // child o is non-empty iff the next bound is larger
+    const int32_t next = __shfl_down(a, 1, 8);
+    const bool ne = (o == 7 ? end : next) > a;
+    const uint64_t m = __ballot(ne);
+    if (o == 0) nch[j] = __popcll((m >> (threadIdx.x & 63 & ~7)) & 0xffull);
 }
 
 __global__ void k_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t *__restrict__ bounds,
@@ -315,8 +318,8 @@ void launch_roots(const int64_t *d_offsets, int n_inst, CellArrays c, hipStream_
 
 void launch_tree_count(CellArrays c, int32_t lb, int32_t le, int ncrit, int max_level, const uint64_t *skeys,
                        int32_t *bounds, int32_t *nch, hipStream_t s) {
-    hipLaunchKernelGGL(k_tree_count, dim3(grid_for(le - lb, 128, 1 << 30)), dim3(128), 0, s, c, lb, le, ncrit, max_level,
-                       skeys, bounds, nch);
+    hipLaunchKernelGGL(k_tree_count, dim3(grid_for((int64_t)(le - lb) * 8, 128, 1 << 30)), dim3(128), 0, s, c, lb, le,
+                       ncrit, max_level, skeys, bounds, nch);
     FMM_LAUNCH_CHECK();
 }
 
