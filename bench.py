@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-error", action="store_true", help="skip the error check against the direct sum")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default work-queue tuning")
     ap.add_argument("--cpu-n", type=int, default=524288, help="particles in the CPU oracle sample")
+    ap.add_argument("--trace", action="store_true",
+                    help="after the timed steps, one evaluation with the device task trace: summary in the line")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -230,6 +232,18 @@ def run_single(a, torch, fmm, W):
     result["tuning"] = tuning
     result["work"] = work
     result["roofline"] = roof
+    if a.trace and a.precision == "mixed":
+        # outside the timed region: a second plan with the task trace on
+        from paper_1203_0889_amd import trace as T
+        tp = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0, trace=True)
+        tp.set_tuning(**tuning)
+        for _ in range(2):
+            tp.build_tree(dpos, dq)
+            tp.upward()
+            tp.evaluate_into(phi=phi, field=field, energy=energy)
+        result["trace"] = T.summarize(tp.trace())
+        print("bench: task trace %s" % json.dumps(result["trace"]), file=sys.stderr, flush=True)
+        tp.close()
     if not a.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w, min(a.cpu_n, n))
     if not a.no_error:

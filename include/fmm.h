@@ -58,13 +58,16 @@ typedef enum {
 enum {
     FMM_FLAG_USER_BOX = 1u << 0,     /* use params.box_min / box_side for every
                                         instance instead of the tight bounding cube */
-    FMM_FLAG_KEEP_TOPOLOGY = 1u << 1 /* a later fmm_build_tree with the same n_inst
+    FMM_FLAG_KEEP_TOPOLOGY = 1u << 1, /* a later fmm_build_tree with the same n_inst
                                         and offsets keeps the box, keys, tree and
                                         lists of the previous build and only takes
                                         the new positions and charges (gathered by
                                         the stored sort permutation): a frozen
                                         topology, as finite-difference checks of
                                         the adjoint need */
+    FMM_FLAG_TRACE = 1u << 2          /* mixed precision: the work queue of
+                                        fmm_evaluate records one fmm_task_record
+                                        per task it runs (fmm_get_trace) */
 };
 
 typedef struct {
@@ -228,6 +231,32 @@ fmm_status fmm_autotune(fmm_plan *plan, int32_t repeats, fmm_tuning *best, doubl
  * measured with HIP events on the plan's stream.  times: host double[16],
  * names: optional host array of 16 const char* filled with stage names. */
 fmm_status fmm_get_stage_times(const fmm_plan *plan, double *times, const char **names);
+
+/*
+ * Device task trace (the per-task timeline the paper draws for its runtime,
+ * Sec. 5): with FMM_FLAG_TRACE, every task the work queue of the last
+ * fmm_evaluate ran, in completion order.  Times are ticks of the device's
+ * constant 100 MHz real-time clock (s_memrealtime), from the claim of the
+ * task to its completion (for an M2L task: all four waves of its workgroup
+ * done).  hw_id is the raw HW_ID register of the recording wave: compute
+ * unit bits 11:8, SIMD 5:4, shader array 12, shader engine 15:13; xcc is the
+ * XCD.
+ */
+typedef struct {
+    uint64_t start, end;
+    int32_t kind;    /* 0 = M2L task (one workgroup), 1 = P2P task (one wave) */
+    int32_t task;    /* M2L: index in the plan's task table; P2P: target leaf cell */
+    int32_t kernel;  /* 0 = k_queue, 1 = k_p2p_side */
+    uint32_t hw_id;
+    uint32_t xcc;
+    uint32_t reserved;
+} fmm_task_record;
+
+/* Copy up to cap records of the last traced queue run to host memory
+ * (synchronous); *count (host, may be NULL) receives the number recorded.
+ * Without FMM_FLAG_TRACE, or before fmm_evaluate, *count = 0.  The FP64
+ * path has no queue and records nothing. */
+fmm_status fmm_get_trace(const fmm_plan *plan, fmm_task_record *records, int64_t cap, int64_t *count);
 
 const char *fmm_status_string(fmm_status status);
 /* Last error message of this plan (host-side detail), never NULL. */

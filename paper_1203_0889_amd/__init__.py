@@ -3,7 +3,8 @@ after Ltaief & Yokota, "Data-Driven Execution of Fast Multipole Methods".
 
 The compute path is the HIP library libfmm_mi355x.so (C ABI in
 include/fmm.h); `fmm` is its Python binding, `autograd` the
-torch.autograd.Function around it, `workloads` the seeded input generators.
+torch.autograd.Function around it, `trace` summaries of the device task
+trace, `workloads` the seeded input generators.
 """
 
 __all__ = ["Plan", "evaluate", "load_library", "FMMEnergy", "fmm_energy"]

@@ -24,6 +24,10 @@ struct NearFarArgs {
     // multipoles, qs the adjoint weights; operators are stored transposed.
     bool transposed = false;
     HostReader *reader = nullptr;  // fast device-to-host reads (optional)
+    // task trace of the queue (optional): records, counter, capacity
+    fmm_task_record *trace = nullptr;
+    int32_t *trace_count = nullptr;
+    int32_t trace_cap = 0;
 };
 
 // Device workspaces of this stage, owned by the plan.  The class operator

@@ -211,6 +211,10 @@ void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     q.fld = a.fld;
     q.lists = st.lists.as<int4>();
     q.heads = st.cnt.as<int32_t>() + 40;
+    q.trace = a.trace && a.trace_count && a.trace_cap > 0 ? a.trace : nullptr;
+    q.trace_count = a.trace_count;
+    q.trace_cap = a.trace_cap;
+    if (q.trace) fill_zero(a.trace_count, sizeof(int32_t), s);
     int dev = 0, ncu = 256;
     FMM_HIP_CHECK(hipGetDevice(&dev));
     FMM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));

@@ -101,6 +101,9 @@ struct fmm_plan {
     fmm::NearFarState nf_t;
     fmm::HostReader reader;
     DevBuf phi_near, fld_near, phi_far, fld_far, echunk, epart;
+    DevBuf trace, trace_count;   // task trace of the forward queue (FMM_FLAG_TRACE)
+    int32_t trace_cap = 0;
+    bool traced = false;
     int32_t nechunk = 0;
     fmm::NearFarState nf;
     fmm_tuning tuning;
@@ -446,6 +449,17 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         mark(p, ST_P2P);
     } else {
         fmm::NearFarArgs a = nf_args(p);
+        if (p->prm.flags & FMM_FLAG_TRACE) {
+            // one record per task: M2L tasks plus target leaves
+            const int64_t cap = (int64_t)p->nf.ntask + p->nleaf;
+            FMM_HIP_CHECK(p->trace.grow((size_t)std::max<int64_t>(cap, 1) * sizeof(fmm_task_record)));
+            FMM_HIP_CHECK(p->trace_count.grow(sizeof(int32_t)));
+            p->trace_cap = (int32_t)cap;
+            a.trace = p->trace.as<fmm_task_record>();
+            a.trace_count = p->trace_count.as<int32_t>();
+            a.trace_cap = p->trace_cap;
+            p->traced = true;
+        }
         fmm::near_far_prepare(p->nf, a, s);
         mark(p, ST_NF_PREP);
         fmm::near_far_queue(p->nf, a, s);
@@ -603,7 +617,8 @@ fmm_status check_params(const fmm_params *q, std::string *why) {
     if (q->max_level < 1 || q->max_level > fmm::kLevels) return *why = "max_level must be in [1, 21]", FMM_ERR_INVALID_ARG;
     if (q->precision != FMM_PREC_FP64 && q->precision != FMM_PREC_MIXED)
         return *why = "unknown precision", FMM_ERR_INVALID_ARG;
-    if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY)) return *why = "unknown flag", FMM_ERR_INVALID_ARG;
+    if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY | FMM_FLAG_TRACE))
+        return *why = "unknown flag", FMM_ERR_INVALID_ARG;
     if ((q->flags & FMM_FLAG_USER_BOX) &&
         !(q->box_side > 0 && std::isfinite(q->box_side) && std::isfinite(q->box_min[0]) &&
           std::isfinite(q->box_min[1]) && std::isfinite(q->box_min[2])))
@@ -667,7 +682,8 @@ fmm_status fmm_destroy(fmm_plan *p) {
                      &p->L, &p->ops_m2m, &p->ops_l2l, &p->m2m_part, &p->phi_near, &p->fld_near, &p->phi_far,
                      &p->fld_far, &p->echunk, &p->epart, &p->ops_m2m_t, &p->ops_l2l_t, &p->m2l_t_ptr,
                      &p->m2l_t_src, &p->p2p_t_ptr, &p->p2p_t_src, &p->tkeys, &p->tkeys_alt, &p->lam, &p->mu,
-                     &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far};
+                     &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far, &p->trace,
+                     &p->trace_count};
     drop_graph(p);
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
@@ -702,6 +718,7 @@ fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, c
         }
         p->state = kStateCreated;
         p->adj_ready = false;
+        p->traced = false;
         drop_graph(p);
         p->n = n;
         p->n_inst = n_inst;
@@ -956,6 +973,24 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
         p->state = kStateUp;
         if (best) *best = top;
         if (best_ms) *best_ms = top_ms;
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_get_trace(const fmm_plan *cp, fmm_task_record *records, int64_t cap, int64_t *count) {
+    fmm_plan *p = const_cast<fmm_plan *>(cp);
+    if (!p || cap < 0 || (cap > 0 && !records)) return FMM_ERR_INVALID_ARG;
+    return guarded(p, [&]() -> fmm_status {
+        int32_t n = 0;
+        if (p->traced && p->trace_count.ptr) {
+            FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+            FMM_HIP_CHECK(hipMemcpy(&n, p->trace_count.ptr, sizeof(int32_t), hipMemcpyDeviceToHost));
+            n = std::min(n, p->trace_cap);
+        }
+        if (count) *count = n;
+        const int64_t m = std::min<int64_t>(n, cap);
+        if (m > 0)
+            FMM_HIP_CHECK(hipMemcpy(records, p->trace.ptr, (size_t)m * sizeof(fmm_task_record), hipMemcpyDeviceToHost));
         return FMM_OK;
     });
 }

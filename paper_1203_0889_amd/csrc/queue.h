@@ -1,6 +1,7 @@
 // Internal interface of the persistent work-queue kernel (M2L + P2P tasks).
 #pragma once
 
+#include "../../include/fmm.h"
 #include "tree.h"
 
 namespace fmm {
@@ -34,6 +35,11 @@ struct QueueArgs {
     const int4 *lists;
     int32_t *heads;            // 16 claim counters (zeroed before launch)
     int32_t role_split;        // set by queue_run
+    // task trace (null: off): records, their counter (zeroed before the
+    // launch) and capacity; records past the capacity are dropped
+    fmm_task_record *trace;
+    int32_t *trace_count;
+    int32_t trace_cap;
 };
 
 bool queue_supported(int p);

@@ -12,6 +12,7 @@ the library is missing, loading fails with an error.
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -23,12 +24,13 @@ STATUS = {0: "FMM_OK", -1: "FMM_ERR_INVALID_ARG", -2: "FMM_ERR_STATE", -3: "FMM_
 PREC = {"fp64": 0, "mixed": 1}
 FLAG_USER_BOX = 1
 FLAG_KEEP_TOPOLOGY = 2
+FLAG_TRACE = 4
 
 # every symbol include/fmm.h declares
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
            "fmm_backward", "fmm_sync", "fmm_get_counts", "fmm_copy_tree", "fmm_copy_lists", "fmm_get_tuning",
            "fmm_set_tuning", "fmm_get_stage_times", "fmm_status_string", "fmm_last_error", "fmm_graph_capture",
-           "fmm_graph_launch", "fmm_autotune")
+           "fmm_graph_launch", "fmm_autotune", "fmm_get_trace")
 
 
 class fmm_params(ctypes.Structure):
@@ -39,6 +41,17 @@ class fmm_params(ctypes.Structure):
 
 class fmm_tuning(ctypes.Structure):
     _fields_ = [("m2l_task_entries", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("p2p_per_cu", ctypes.c_int32)]
+
+
+class fmm_task_record(ctypes.Structure):
+    _fields_ = [("start", ctypes.c_uint64), ("end", ctypes.c_uint64), ("kind", ctypes.c_int32),
+                ("task", ctypes.c_int32), ("kernel", ctypes.c_int32), ("hw_id", ctypes.c_uint32),
+                ("xcc", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+# the same layout as a numpy record (ticks of the 100 MHz device clock)
+TASK_DTYPE = np.dtype([("start", "<u8"), ("end", "<u8"), ("kind", "<i4"), ("task", "<i4"), ("kernel", "<i4"),
+                       ("hw_id", "<u4"), ("xcc", "<u4"), ("reserved", "<u4")])
 
 
 class FMMError(RuntimeError):
@@ -78,6 +91,7 @@ def load_library():
     lib.fmm_get_tuning.argtypes = [vp, P(fmm_tuning)]
     lib.fmm_set_tuning.argtypes = [vp, P(fmm_tuning)]
     lib.fmm_get_stage_times.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_char_p)]
+    lib.fmm_get_trace.argtypes = [vp, vp, i64, P(i64)]
     lib.fmm_status_string.argtypes = [ctypes.c_int]
     lib.fmm_status_string.restype = ctypes.c_char_p
     lib.fmm_last_error.argtypes = [vp]
@@ -106,7 +120,7 @@ class Plan:
     """One FMM plan: owns the tree, lists and expansions on one device/stream."""
 
     def __init__(self, p=8, ncrit=64, theta=(1, 2), max_level=21, precision="mixed", device=None, stream=None,
-                 box=None, keep_topology=False):
+                 box=None, keep_topology=False, trace=False):
         self._lib = load_library()
         prm = fmm_params()
         self._lib.fmm_default_params(ctypes.byref(prm))
@@ -120,6 +134,8 @@ class Plan:
             prm.box_side = float(box[3])
         if keep_topology:
             prm.flags |= FLAG_KEEP_TOPOLOGY
+        if trace:
+            prm.flags |= FLAG_TRACE
         self.params = prm
         if device is None:
             device = torch.cuda.current_device()
@@ -245,6 +261,15 @@ class Plan:
         names = (ctypes.c_char_p * 16)()
         self._call(self._lib.fmm_get_stage_times, t, names)
         return {names[i].decode(): t[i] for i in range(16) if names[i] and names[i].decode()}
+
+    def trace(self):
+        """Task records of the last traced evaluate (numpy array of TASK_DTYPE)."""
+        n = ctypes.c_int64()
+        self._call(self._lib.fmm_get_trace, None, 0, ctypes.byref(n))
+        out = np.zeros(n.value, dtype=TASK_DTYPE)
+        if n.value:
+            self._call(self._lib.fmm_get_trace, ctypes.c_void_p(out.ctypes.data), n.value, ctypes.byref(n))
+        return out[:n.value]
 
     def get_tuning(self):
         t = fmm_tuning()

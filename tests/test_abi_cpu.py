@@ -88,3 +88,39 @@ def test_python_binding_validates_tensors():
 def test_autotune_rejects_null_plan():
     lib = fmm.load_library()
     assert lib.fmm_autotune(None, 1, None, None) == -1
+
+
+def test_trace_rejects_null_plan_and_bad_capacity():
+    lib = fmm.load_library()
+    n = ctypes.c_int64(7)
+    assert lib.fmm_get_trace(None, None, 0, ctypes.byref(n)) == -1
+
+
+def test_trace_record_layout_matches_header():
+    # fmm_task_record: two uint64 then six 32-bit fields, 40 bytes
+    assert ctypes.sizeof(fmm.fmm_task_record) == 40
+    assert fmm.TASK_DTYPE.itemsize == 40
+    assert [f for f, _ in fmm.fmm_task_record._fields_] == list(fmm.TASK_DTYPE.names)
+
+
+def test_trace_summary_on_synthetic_records():
+    """Host logic of the trace summary: two compute units, one M2L task
+    (4 waves) on the first and two P2P tasks on the second."""
+    import numpy as np
+    from paper_1203_0889_amd import trace
+    rec = np.zeros(3, dtype=fmm.TASK_DTYPE)
+    rec["start"] = [1000, 1000, 1500]
+    rec["end"] = [2000, 1400, 2500]          # ticks: 10, 4 and 10 us
+    rec["kind"] = [0, 1, 1]
+    rec["kernel"] = [0, 1, 1]
+    rec["hw_id"] = [3 << 8, 5 << 8, 5 << 8]   # CU 3 and CU 5
+    rec["xcc"] = [0, 0, 0]
+    s = trace.summarize(rec)
+    assert s["tasks"] == 3 and s["compute_units"] == 2
+    assert abs(s["span_us"] - 15.0) < 1e-9
+    assert s["m2l"]["tasks"] == 1 and abs(s["m2l"]["mean_us"] - 10.0) < 1e-9
+    assert s["p2p"]["tasks"] == 2 and s["p2p"]["by_side_kernel"] == 2
+    # busy wave-time: CU 3 = 4 x 10 us, CU 5 = 4 + 10 us
+    assert abs(s["cu_busy_wave_us"]["max"] - 40.0) < 1e-9 and abs(s["cu_busy_wave_us"]["min"] - 14.0) < 1e-9
+    assert abs(s["cu_busy_imbalance"] - 40.0 / 27.0) < 1e-12
+    assert trace.summarize(rec[:0]) == {"tasks": 0}
