@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-error", action="store_true", help="skip the error check against the direct sum")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default work-queue tuning")
     ap.add_argument("--cpu-n", type=int, default=524288, help="particles in the CPU oracle sample")
+    ap.add_argument("--sweep", action="store_true",
+                    help="granularity sweep (the paper's Q experiment): M2L entries per task x N x p, one JSON line")
     ap.add_argument("--trace", action="store_true",
                     help="after the timed steps, one evaluation with the device task trace: summary in the line")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -346,6 +348,45 @@ def run_batch(a, torch, fmm, W):
     return result
 
 
+def run_sweep(a, torch, fmm, W):
+    """The paper's granularity experiment (Sec. 5) on the GPU queue: uniform
+    cubes of N = 1e5, 1e6, 1e7 particles, p = 6 and 9 (ncrit 64, theta 1/2,
+    mixed), M2L class entries per task in {16, 32, 64, 128} (the task size,
+    the analogue of Q) with the default launch shape.  Per point: the mean of
+    3 timed steps (build + upward + evaluate, HIP events per stage) and the
+    balance of one traced evaluation."""
+    from paper_1203_0889_amd import trace as T
+    dev = torch.device("cuda", 0)
+    rows = []
+    for n in (100000, 1000000, 10000000):
+        pos, q = W.uniform_cube(n, 2)
+        dpos, dq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
+        for p in (6, 9):
+            for entries in (16, 32, 64, 128):
+                row = {"n": n, "p": p, "m2l_task_entries": entries}
+                for traced in (False, True):
+                    plan = fmm.Plan(p=p, ncrit=64, theta=(1, 2), precision="mixed", device=0, trace=traced)
+                    plan.set_tuning(m2l_task_entries=entries, grid_per_cu=1, p2p_per_cu=2)
+
+                    def step():
+                        plan.build_tree(dpos, dq)
+                        plan.upward()
+                        plan.evaluate(force=False, energy=False)
+                    if traced:
+                        step()
+                        s = T.summarize(plan.trace())
+                        row.update({"m2l_tasks": s["m2l"]["tasks"], "m2l_task_median_us": s["m2l"]["median_us"],
+                                    "cu_busy_imbalance": s["cu_busy_imbalance"],
+                                    "tail_us": s["cu_last_end_us"]["max"] - s["cu_last_end_us"]["min"]})
+                    else:
+                        ms, st = timed(step, plan, 3, 1, torch)
+                        row.update({"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3), "queue_ms": st["queue"]})
+                    plan.close()
+                print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
+                rows.append(row)
+    return {"sweep": "M2L class entries per task x N x p, uniform, ncrit 64, theta 1/2, mixed", "rows": rows}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -353,7 +394,9 @@ def main():
         sys.exit(2)
     import torch
     from paper_1203_0889_amd import fmm, workloads as W
-    if a.workload == "batch256_p6":
+    if a.sweep:
+        result = run_sweep(a, torch, fmm, W)
+    elif a.workload == "batch256_p6":
         result = run_batch(a, torch, fmm, W)
     else:
         result = run_single(a, torch, fmm, W)
