@@ -321,13 +321,20 @@ __device__ void m2l_group(const QueueArgs &a, int4 task, int w, int lane, v4f *r
         for (int b = 0; b < NB; b++)
 #pragma unroll
             for (int i = 0; i < 16; i++) acc[r][b][i] = 0.f;
-    // multipole rows of the current and the next entry; sources of entry + 2
+    // multipole rows of the current and the next entry; sources of entry + 2.
+    // live[b]: some target of column tile b has a source in the current
+    // entry (wave-uniform); a tile with none skips its MFMAs (at the domain
+    // boundary about a fifth of the tiles of an entry are empty).
     const v4f *R[NB], *nR[NB];
     int32_t sn[NB];
+    bool live[NB], nlive[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        R[b] = mrow(a, mb4, gsrc[(int64_t)e0 * kGroupM2L + b * 32], NK);
+        const int32_t s0 = gsrc[(int64_t)e0 * kGroupM2L + b * 32];
+        R[b] = mrow(a, mb4, s0, NK);
+        live[b] = __ballot(s0 >= 0) != 0;
         nR[b] = R[b];
+        nlive[b] = live[b];
         sn[b] = ne > 1 ? gsrc[(int64_t)(e0 + 1) * kGroupM2L + b * 32] : -1;
     }
     // two-step multipole window
@@ -355,6 +362,7 @@ __device__ void m2l_group(const QueueArgs &a, int4 task, int w, int lane, v4f *r
 #pragma unroll
             for (int b = 0; b < NB; b++) {
                 nR[b] = mrow(a, mb4, sn[b], NK);
+                nlive[b] = __ballot(sn[b] >= 0) != 0;
                 sn[b] = i + 2 < ne ? gsrc[(int64_t)(e0 + i + 2) * kGroupM2L + b * 32] : -1;
             }
         }
@@ -384,17 +392,21 @@ __device__ void m2l_group(const QueueArgs &a, int4 task, int w, int lane, v4f *r
                 al[r] = rb[((t * RT + r) * 2 + 1) * 64];
             }
 #pragma unroll
-            for (int r = 0; r < RT; r++)
+            for (int b = 0; b < NB; b++)
+                if (live[b])
 #pragma unroll
-                for (int b = 0; b < NB; b++) {
-                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(al[r]), as_bf8(cm[b].h), acc[r][b], 0, 0, 0);
-                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(ah[r]), as_bf8(cm[b].l), acc[r][b], 0, 0, 0);
-                    acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(ah[r]), as_bf8(cm[b].h), acc[r][b], 0, 0, 0);
-                }
+                    for (int r = 0; r < RT; r++) {
+                        acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(al[r]), as_bf8(cm[b].h), acc[r][b], 0, 0, 0);
+                        acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(ah[r]), as_bf8(cm[b].l), acc[r][b], 0, 0, 0);
+                        acc[r][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(ah[r]), as_bf8(cm[b].h), acc[r][b], 0, 0, 0);
+                    }
         }
         if (g == NS - 1) {
 #pragma unroll
-            for (int b = 0; b < NB; b++) R[b] = nR[b];
+            for (int b = 0; b < NB; b++) {
+                R[b] = nR[b];
+                live[b] = nlive[b];
+            }
         }
     }
 #pragma unroll
@@ -452,7 +464,7 @@ __device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__
 }
 
 template <int RT>
-__global__ void __launch_bounds__(256) k_queue(QueueArgs a) {
+__global__ void __launch_bounds__(256, (RT <= 3 ? 2 : 1)) k_queue(QueueArgs a) {
     __shared__ v4f lds[queue_lds_f4<RT>()];
     __shared__ int32_t claim;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
