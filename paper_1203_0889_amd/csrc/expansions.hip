@@ -242,6 +242,57 @@ __global__ void __launch_bounds__(kTransMaxThreads) k_l2l(Geometry g, int32_t lb
     }
 }
 
+// Levels with few parents: one block per (parent, octant), a thread per
+// row, the operator read straight from global memory (it stays in L2) and
+// the one vector in LDS.  A block then waits for about one pass of loads
+// instead of a staging round trip per operator chunk, which dominated the
+// top levels (tens of microseconds each whatever their size).  The sum runs
+// over the columns in the same order with one accumulator, as in k_m2m and
+// k_l2l, so both forms give the same values.
+constexpr int32_t kSmallLevel = 256;   // parents per level up to which these are used
+constexpr int kMaxCoef = 17 * 17;      // (p + 1)^2 for p <= 16
+
+__global__ void __launch_bounds__(kTransMaxThreads) k_m2m_small(Geometry g, int32_t lb, int32_t le, int p,
+                                                                const double *__restrict__ ops,
+                                                                const double *__restrict__ M, double *__restrict__ part) {
+    __shared__ double x[kMaxCoef];
+    const int P = ncoef(p);
+    const int o = blockIdx.y;
+    const int32_t par = lb + blockIdx.x;
+    const int row = threadIdx.x;
+    const int32_t ch = child_in_octant(g.c, par, o);   // the same in every thread
+    double *out = part + ((int64_t)o * (le - lb) + (par - lb)) * P;
+    if (ch < 0) {
+        if (row < P) out[row] = 0.0;
+        return;
+    }
+    for (int i = threadIdx.x; i < P; i += blockDim.x) x[i] = M[(int64_t)ch * P + i];
+    __syncthreads();
+    if (row >= P) return;
+    const double *A = ops + (int64_t)o * P * P + row;
+    double acc = 0.0;
+    for (int i = 0; i < P; i++) acc += A[(int64_t)i * P] * x[i];
+    out[row] = acc;
+}
+
+__global__ void __launch_bounds__(kTransMaxThreads) k_l2l_small(Geometry g, int32_t lb, int32_t le, int p,
+                                                                const double *__restrict__ ops, double *__restrict__ L) {
+    __shared__ double x[kMaxCoef];
+    const int P = ncoef(p);
+    const int o = blockIdx.y;
+    const int32_t par = lb + blockIdx.x;
+    const int row = threadIdx.x;
+    const int32_t ch = child_in_octant(g.c, par, o);
+    if (ch < 0) return;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) x[i] = L[(int64_t)par * P + i];
+    __syncthreads();
+    if (row >= P) return;
+    const double *B = ops + (int64_t)o * P * P + row;
+    double acc = 0.0;
+    for (int i = 0; i < P; i++) acc += B[(int64_t)i * P] * x[i];
+    L[(int64_t)ch * P + row] += acc;
+}
+
 // Local coefficient L~_n^m for any m (negative via conjugate symmetry).
 __device__ inline Cplx lget(const double *Lc, int p, int n, int m) {
     if (n > p || m > n || -m > n) return {0.0, 0.0};
@@ -570,11 +621,15 @@ static void allow_lds(const void *fn, size_t bytes) {
 void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, double *part,
                       hipStream_t s) {
     if (le <= lb) return;
-    const int cw = trans_cw(p);
-    const size_t lds = trans_lds(p, cw);
-    allow_lds(reinterpret_cast<const void *>(&k_m2m), lds);
-    dim3 grid((le - lb + kPB - 1) / kPB, 8);
-    hipLaunchKernelGGL(k_m2m, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, cw, ops, M, part);
+    if (le - lb <= kSmallLevel) {
+        hipLaunchKernelGGL(k_m2m_small, dim3(le - lb, 8), dim3(rows_block(p)), 0, s, g, lb, le, p, ops, M, part);
+    } else {
+        const int cw = trans_cw(p);
+        const size_t lds = trans_lds(p, cw);
+        allow_lds(reinterpret_cast<const void *>(&k_m2m), lds);
+        dim3 grid((le - lb + kPB - 1) / kPB, 8);
+        hipLaunchKernelGGL(k_m2m, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, cw, ops, M, part);
+    }
     FMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_m2m_sum, dim3(grid_for((int64_t)(le - lb) * ncoef(p), 256, 4096)), dim3(256), 0, s, g, lb, le, p,
                        part, M);
@@ -583,11 +638,15 @@ void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *o
 
 void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *L, hipStream_t s) {
     if (le <= lb) return;
-    const int cw = trans_cw(p);
-    const size_t lds = trans_lds(p, cw);
-    allow_lds(reinterpret_cast<const void *>(&k_l2l), lds);
-    dim3 grid((le - lb + kPB - 1) / kPB, 8);
-    hipLaunchKernelGGL(k_l2l, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, cw, ops, L);
+    if (le - lb <= kSmallLevel) {
+        hipLaunchKernelGGL(k_l2l_small, dim3(le - lb, 8), dim3(rows_block(p)), 0, s, g, lb, le, p, ops, L);
+    } else {
+        const int cw = trans_cw(p);
+        const size_t lds = trans_lds(p, cw);
+        allow_lds(reinterpret_cast<const void *>(&k_l2l), lds);
+        dim3 grid((le - lb + kPB - 1) / kPB, 8);
+        hipLaunchKernelGGL(k_l2l, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, cw, ops, L);
+    }
     FMM_LAUNCH_CHECK();
 }
 
