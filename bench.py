@@ -145,18 +145,24 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload):
 
 
 def timed(step, plan, steps, warmup, torch):
+    """Mean wall time of `steps` steps (synchronised before and after, no
+    synchronisation inside), then the per-stage HIP-event times averaged over
+    `max(warmup, 1)` further steps, read after each of those steps."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    stage_sum = {}
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
-        for k, v in plan.stage_times().items():    # HIP events on the plan's stream
-            stage_sum[k] = stage_sum.get(k, 0.0) + v
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return (t1 - t0) * 1e3 / steps, {k: v / steps for k, v in stage_sum.items()}
+    stage_sum = {}
+    nstage = max(warmup, 1)
+    for _ in range(nstage):
+        step()
+        for k, v in plan.stage_times().items():    # HIP events on the plan's stream
+            stage_sum[k] = stage_sum.get(k, 0.0) + v
+    return (t1 - t0) * 1e3 / steps, {k: v / nstage for k, v in stage_sum.items()}
 
 
 def calib_copy(mib, torch, dev):
@@ -216,7 +222,7 @@ def run_single(a, torch, fmm, W):
 
     ms, stage_avg = timed(step, plan, a.steps, a.warmup, torch)
     if a.adjoint:
-        stage_avg["backward"] = bw_ms[0] / (a.steps + a.warmup)
+        stage_avg["backward"] = bw_ms[0] / (a.steps + a.warmup + max(a.warmup, 1))
     print("bench: %.3f ms/step; stages %s" % (ms, json.dumps({k: round(v, 4) for k, v in stage_avg.items()})),
           file=sys.stderr, flush=True)
     roof, work = queue_roofline(plan, stage_avg, w["p"], n, a.precision, a.workload)

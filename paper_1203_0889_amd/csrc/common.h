@@ -69,6 +69,14 @@ struct HostReader {
     void init();           // best effort: on failure reads use the fallback
     void release();
     void read(void *host, const void *dev, size_t bytes, hipStream_t s);  // throws HipError
+    // The same in two halves: begin enqueues the copy, end waits for it.
+    // Work enqueued on s in between keeps the GPU busy while the host waits
+    // (one read outstanding at a time).
+    void begin(const void *dev, size_t bytes, hipStream_t s);
+    void end(void *host, hipStream_t s);
+    const void *pend_dev = nullptr;
+    size_t pend_bytes = 0;
+    bool pend_fallback = false;
 };
 
 // Zero `bytes` bytes (a multiple of 4) at a 4-byte aligned device address

@@ -36,7 +36,7 @@ struct NearFarState {
     DevBuf used, slot_of, nslots, new_keys, frags, used_scan, cid_of, slot_of_cid;
     DevBuf pkey, pcid, xcount, tkey, tkey_alt, has, gcount, goff, tcount, toff;
     DevBuf ecls, esrc, gtarget, tasks, xsrc, xptr, leafbuf, leaves, pf, M32, tmp, cnt, centre, gbits, gwpre;
-    DevBuf tasks_alt, tkeys, tidx, lists;
+    DevBuf tasks_alt, tkeys, tidx, lists, tmp2;
     // stream and events of the P2P side kernel (created on first use)
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;

@@ -17,14 +17,26 @@ fmm_tuning default_tuning() {
 }
 
 namespace {
-void read_sync(const NearFarArgs &a, void *h, const void *d, size_t b, hipStream_t s) {
-    if (a.reader) {
-        a.reader->read(h, d, b, s);
-    } else {
-        FMM_HIP_CHECK(hipMemcpyAsync(h, d, b, hipMemcpyDeviceToHost, s));
-        FMM_HIP_CHECK(hipStreamSynchronize(s));
+// Device-to-host reads in two halves (see HostReader): work enqueued
+// between read_begin and read_end runs while the host waits.
+struct Reader {
+    const NearFarArgs &a;
+    const void *d = nullptr;
+    size_t b = 0;
+    void begin(const void *dev, size_t bytes, hipStream_t s) {
+        d = dev;
+        b = bytes;
+        if (a.reader) a.reader->begin(dev, bytes, s);
     }
-}
+    void end(void *host, hipStream_t s) {
+        if (a.reader) {
+            a.reader->end(host, s);
+        } else {
+            FMM_HIP_CHECK(hipMemcpyAsync(host, d, b, hipMemcpyDeviceToHost, s));
+            FMM_HIP_CHECK(hipStreamSynchronize(s));
+        }
+    }
+};
 
 // The 16 task lists from the per-XCD counts (cnt[16..23] M2L tasks,
 // cnt[25..32] leaves): list 2x = (first task, count, 0, 0), list 2x + 1 =
@@ -79,14 +91,8 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                    st.xcount.as<int32_t>(), s);
     FMM_HIP_CHECK(hipMemsetAsync(st.nslots.as<int32_t>() + 1, 0, 4, s));
     m2l_alloc_slots(st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.nslots.as<int32_t>(), st.new_keys.as<int32_t>(), s);
-    int32_t ns[2];
-    read_sync(a, ns, st.nslots.ptr, 8, s);
-    if (ns[0] > st.nslot_total) {
-        FMM_HIP_CHECK(st.frags.grow_keep((size_t)ns[0] * op_elems * 2, s));
-        m2l_build_ops(st.new_keys.as<int32_t>(), ns[1], st.slot_of.as<int32_t>(), p, RT, op_elems, a.transposed,
-                      st.frags.as<uint16_t>(), s);
-        st.nslot_total = ns[0];
-    }
+    // slot counts next to the sizes below: one read for all of them
+    FMM_HIP_CHECK(hipMemcpyAsync(cnt + 5, st.nslots.ptr, 8, hipMemcpyDeviceToDevice, s));
     // compact class ids in dense-key order
     exclusive_scan_oop(st.used.as<int32_t>(), st.used_scan.as<int32_t>(), kDenseKeys, cnt + 0, st.tmp.as<int32_t>(), s);
     m2l_cid_tables(st.used_scan.as<int32_t>(), st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.cid_of.as<int32_t>(),
@@ -108,11 +114,28 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 32, 43,
                    st.tmp.as<int32_t>(), s);
     exclusive_scan_i32(st.has.as<int32_t>(), ncell, cnt + 2, st.tmp.as<int32_t>(), s);
-    int32_t h3[3];
-    read_sync(a, h3, cnt, 12, s);
-    st.ncid = h3[0];
-    st.nextra = h3[1];
-    st.ntarget = h3[2];
+    Reader rd{a};
+    rd.begin(cnt, 7 * 4, s);
+    // while the host waits: the P2P leaves (by spatial eighth, costliest
+    // first) and the cell centres, which need none of the sizes
+    FMM_HIP_CHECK(st.leafbuf.grow((size_t)4 * (ncell + 1) * 4));
+    FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
+    FMM_HIP_CHECK(st.tmp2.grow(radix_tmp_elems(ncell) * 4));
+    p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
+                  st.tmp2.as<int32_t>(), cnt + 24, s);
+    FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
+    cell_centres(a.g, ncell, st.centre.as<double>(), s);
+    int32_t h7[7];
+    rd.end(h7, s);
+    if (h7[5] > st.nslot_total) {
+        FMM_HIP_CHECK(st.frags.grow_keep((size_t)h7[5] * op_elems * 2, s));
+        m2l_build_ops(st.new_keys.as<int32_t>(), h7[6], st.slot_of.as<int32_t>(), p, RT, op_elems, a.transposed,
+                      st.frags.as<uint16_t>(), s);
+        st.nslot_total = h7[5];
+    }
+    st.ncid = h7[0];
+    st.nextra = h7[1];
+    st.ntarget = h7[2];
     st.ngroup = (st.ntarget + kGroupM2L - 1) / kGroupM2L;
     const int32_t ng = std::max(st.ngroup, 1);
     FMM_HIP_CHECK(st.gcount.grow((size_t)(ng + 1) * 4));
@@ -130,8 +153,13 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     const int chunk = std::max(1, std::min(kMaxTaskEntries, a.tuning.m2l_task_entries));
     m2l_task_counts(st.gcount.as<int32_t>(), st.ngroup, chunk, st.tcount.as<int32_t>(), s);
     exclusive_scan_oop(st.tcount.as<int32_t>(), st.toff.as<int32_t>(), st.ngroup, cnt + 4, st.tmp.as<int32_t>(), s);
+    rd.begin(cnt + 3, 8, s);
+    // while the host waits: the pairs left to the per-pair kernel
+    // (|delta| >= 2 or far displacement), whose number is known
+    FMM_HIP_CHECK(st.xsrc.grow((size_t)std::max(st.nextra, 1) * 4));
+    m2l_extra(a.m2l_ptr, ncell, a.m2l_src, st.pkey.as<int32_t>(), st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), s);
     int32_t h2[2];
-    read_sync(a, h2, cnt + 3, 8, s);
+    rd.end(h2, s);
     st.nentries = st.ngroup > 0 ? h2[0] : 0;
     st.ntask = st.ngroup > 0 ? h2[1] : 0;
     FMM_HIP_CHECK(st.ecls.grow((size_t)std::max(st.nentries, 1) * 4));
@@ -152,17 +180,6 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                    st.tkey.as<uint64_t>(), st.ntask, st.tasks.as<int4>(), st.tasks_alt.as<int4>(),
                    st.tkeys.as<uint64_t>(), st.tkeys.as<uint64_t>() + nt1, st.tidx.as<uint32_t>(),
                    st.tidx.as<uint32_t>() + nt1, cnt + 16, st.tmp.as<int32_t>(), s);
-    // ---- pairs left to the per-pair kernel (|delta| >= 2 or far displacement)
-    FMM_HIP_CHECK(st.xsrc.grow((size_t)std::max(st.nextra, 1) * 4));
-    m2l_extra(a.m2l_ptr, ncell, a.m2l_src, st.pkey.as<int32_t>(), st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), s);
-    // ---- P2P leaves (by spatial eighth, costliest first) and cell centres
-    FMM_HIP_CHECK(st.leafbuf.grow((size_t)4 * (ncell + 1) * 4));
-    FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
-    FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, radix_tmp_elems(ncell) * 4)));
-    p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
-                  st.tmp.as<int32_t>(), cnt + 24, s);
-    FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
-    cell_centres(a.g, ncell, st.centre.as<double>(), s);
     // ---- the 16 task lists (M2L and P2P per XCD), built on the device
     FMM_HIP_CHECK(st.lists.grow(16 * sizeof(int4)));
     hipLaunchKernelGGL(k_make_lists, dim3(1), dim3(64), 0, s, cnt + 16, st.lists.as<int4>());
@@ -242,7 +259,7 @@ void release_near_far(NearFarState &st) {
     DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.used_scan, &st.cid_of,
                      &st.slot_of_cid, &st.pkey, &st.pcid, &st.xcount, &st.tkey, &st.tkey_alt, &st.has,
                      &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
-                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists};
+                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists, &st.tmp2};
     for (DevBuf *b : all) b->release();
     if (st.side) {
         (void)hipStreamSynchronize(st.side);

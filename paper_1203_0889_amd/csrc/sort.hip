@@ -329,14 +329,27 @@ void HostReader::release() {
 }
 
 void HostReader::read(void *host, const void *dev, size_t bytes, hipStream_t s) {
-    if (!h || bytes > kHostReadMax * sizeof(int32_t) || (bytes & 3)) {
-        FMM_HIP_CHECK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
-        FMM_HIP_CHECK(hipStreamSynchronize(s));
-        return;
-    }
+    begin(dev, bytes, s);
+    end(host, s);
+}
+
+void HostReader::begin(const void *dev, size_t bytes, hipStream_t s) {
+    pend_dev = dev;
+    pend_bytes = bytes;
+    pend_fallback = !h || bytes > kHostReadMax * sizeof(int32_t) || (bytes & 3);
+    if (pend_fallback) return;   // copied synchronously by end()
     seq = seq == 0x7fffffff ? 1 : seq + 1;
     hipLaunchKernelGGL(k_host_read, dim3(1), dim3(64), 0, s, (const int32_t *)dev, (int)(bytes / 4), d, seq);
     FMM_LAUNCH_CHECK();
+}
+
+void HostReader::end(void *host, hipStream_t s) {
+    const size_t bytes = pend_bytes;
+    if (pend_fallback) {
+        FMM_HIP_CHECK(hipMemcpyAsync(host, pend_dev, bytes, hipMemcpyDeviceToHost, s));
+        FMM_HIP_CHECK(hipStreamSynchronize(s));
+        return;
+    }
     for (uint64_t it = 0;; it++) {
         if (__atomic_load_n(&h[0], __ATOMIC_ACQUIRE) == seq) break;
         if ((it & 255) == 255) {
