@@ -71,10 +71,24 @@ __global__ void k_p2m(Geometry g, int32_t ncell, const double *__restrict__ xs, 
 #pragma unroll
     for (int n = 0; n <= PP; n++) ar[n] = ai[n] = 0.0;
     int32_t f = g.c.first[cell], e = f + g.c.count[cell];
+    // the next particle's loads are issued before this one's arithmetic
+    double nx = 0.0, ny = 0.0, nz = 0.0, nq = 0.0;
+    if (f < e) {
+        nx = xs[f];
+        ny = ys[f];
+        nz = zs[f];
+        nq = qs[f];
+    }
     for (int32_t r = f; r < e; r++) {
-        double ux = (xs[r] - c[0]) * inv_side, uy = (ys[r] - c[1]) * inv_side, uz = (zs[r] - c[2]) * inv_side;
+        const double px = nx, py = ny, pz = nz, q = nq;
+        if (r + 1 < e) {
+            nx = xs[r + 1];
+            ny = ys[r + 1];
+            nz = zs[r + 1];
+            nq = qs[r + 1];
+        }
+        double ux = (px - c[0]) * inv_side, uy = (py - c[1]) * inv_side, uz = (pz - c[2]) * inv_side;
         double r2 = ux * ux + uy * uy + uz * uz;
-        double q = qs[r];
         Cplx cur = {dmm, 0.0};
         for (int i = 1; i <= m; i++) cur = cmul(cur, Cplx{ux, uy});
         Cplx prev = {0.0, 0.0};
@@ -326,9 +340,13 @@ __global__ void __launch_bounds__(128) k_l2p(Geometry g, int64_t n, const int32_
         double c[3], side;
         int l;
         cell_frame(g, cell, c, &side, &l);
-        double ux = ldexp((xs[r] - c[0]) / side, l);
-        double uy = ldexp((ys[r] - c[1]) / side, l);
-        double uz = ldexp((zs[r] - c[2]) / side, l);
+        // multiplications by reciprocals (the divisors are compile-time
+        // constants after unrolling, or one per particle): FP64 divisions
+        // cost about ten instructions each and there are ~90 per particle
+        const double inv_side = ldexp(1.0 / side, l);
+        double ux = (xs[r] - c[0]) * inv_side;
+        double uy = (ys[r] - c[1]) * inv_side;
+        double uz = (zs[r] - c[2]) * inv_side;
         double r2 = ux * ux + uy * uy + uz * uz;
         const double *Lc = L + (int64_t)cell * P;
         Cplx zeta = {ux, uy};
@@ -338,8 +356,9 @@ __global__ void __launch_bounds__(128) k_l2p(Geometry g, int64_t n, const int32_
         for (int m = 0; m <= p; m++) {
             if (m > 0) {
                 rmm = cmul(rmm, zeta);
-                rmm.re /= 2 * m;
-                rmm.im /= 2 * m;
+                const double h = 1.0 / (2 * m);
+                rmm.re *= h;
+                rmm.im *= h;
             }
             Cplx r2m = {0.0, 0.0}, r1m = {0.0, 0.0};
 #pragma unroll
@@ -350,8 +369,8 @@ __global__ void __launch_bounds__(128) k_l2p(Geometry g, int64_t n, const int32_
                 } else if (nn == m + 1) {
                     rn = {uz * r1m.re, uz * r1m.im};
                 } else {
-                    double a = (2 * nn - 1) * uz, den = (double)((nn + m) * (nn - m));
-                    rn = {(a * r1m.re - r2 * r2m.re) / den, (a * r1m.im - r2 * r2m.im) / den};
+                    const double a = (2 * nn - 1) * uz, rden = 1.0 / (double)((nn + m) * (nn - m));
+                    rn = {(a * r1m.re - r2 * r2m.re) * rden, (a * r1m.im - r2 * r2m.im) * rden};
                 }
                 r2m = r1m;
                 r1m = rn;

@@ -33,37 +33,65 @@ __global__ void k_centres(Geometry g, int32_t ncell, double *__restrict__ centre
 // within each (to the resolution of q; equal keys keep cell order).
 // Non-leaves get 0xffff, after every leaf.
 __global__ void k_leaf_cost(CellArrays c, int32_t ncell, int64_t n, const int32_t *__restrict__ ptr,
-                            const int32_t *__restrict__ src, int32_t *__restrict__ count8, uint32_t *__restrict__ key,
-                            uint32_t *__restrict__ val) {
-    __shared__ int32_t lc[9];
-    if (threadIdx.x < 9) lc[threadIdx.x] = 0;
-    __syncthreads();
+                            const int32_t *__restrict__ src, uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
     const int lane = threadIdx.x & 63;
+    const float inv_n8 = 8.0f / (float)n;
     for (int32_t i = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; i < ncell; i += gridDim.x * blockDim.x / 64) {
         const bool leaf = c.child[i] < 0 && c.count[i] > 0;
         uint64_t cost = 0;
-        if (leaf)
-            for (int32_t e = ptr[i] + lane; e < ptr[i + 1]; e += 64) cost += (uint64_t)c.count[src[e]];
+        if (leaf) {
+            // four 64-entry chunks at once (all their loads in flight), then
+            // the rest of a long list chunk by chunk
+            const int32_t e0 = ptr[i], e1 = ptr[i + 1];
+            int32_t sidx[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int32_t e = e0 + u * 64 + lane;
+                sidx[u] = e < e1 ? src[e] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (sidx[u] >= 0) cost += (uint64_t)c.count[sidx[u]];
+            for (int32_t e = e0 + 256 + lane; e < e1; e += 64) cost += (uint64_t)c.count[src[e]];
+        }
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) cost += __shfl_xor(cost, d, 64);
         if (lane == 0) {
             uint32_t k = 0xffffu;
             if (leaf) {
+                // an ordering heuristic only: FP32 log2 and a floating-point
+                // eighth (a 64-bit integer division or an FP64 log2 costs
+                // a wave hundreds of instructions)
                 cost *= (uint64_t)c.count[i];
-                int c8 = (int)(((int64_t)c.first[i] * 8) / n);
+                int c8 = (int)((float)c.first[i] * inv_n8);
                 c8 = c8 > 7 ? 7 : c8;
-                const double lq = 200.0 * log2((double)cost + 1.0);
-                const uint32_t q = 1u + (uint32_t)(lq < 8190.0 ? lq : 8190.0);
+                const float lq = 200.0f * __log2f((float)cost + 1.0f);
+                const uint32_t q = 1u + (uint32_t)(lq < 8190.0f ? lq : 8190.0f);
                 k = ((uint32_t)c8 << 13) | (8191u - q);
-                atomicAdd(&lc[0], 1);
-                atomicAdd(&lc[1 + c8], 1);
             }
             key[i] = k;
             val[i] = (uint32_t)i;
         }
     }
+}
+
+// From the sorted keys: count[0] = leaves, count[1 + x] = leaves of eighth
+// x (lower bounds of the eighth boundaries; no atomics).
+__global__ void k_leaf_counts(const uint32_t *__restrict__ skey, int32_t ncell, int32_t *__restrict__ count) {
+    __shared__ int32_t lb[9];
+    const int x = threadIdx.x;
+    if (x < 9) {
+        const uint32_t want = x < 8 ? (uint32_t)x << 13 : 0xffffu;   // first key of eighth x; non-leaves
+        int32_t a = 0, b = ncell;
+        while (a < b) {
+            const int32_t mid = a + ((b - a) >> 1);
+            if (skey[mid] < want) a = mid + 1; else b = mid;
+        }
+        lb[x] = a;
+    }
     __syncthreads();
-    if (threadIdx.x < 9 && lc[threadIdx.x]) atomicAdd(&count8[threadIdx.x], lc[threadIdx.x]);
+    if (x == 0) count[0] = lb[8];
+    else if (x < 9) count[x] = lb[x] - lb[x - 1];
 }
 
 __global__ void k_p2p_prepare(Geometry g, int64_t n, const int32_t *__restrict__ leaf_of,
@@ -85,11 +113,16 @@ void p2p_leaf_list(CellArrays c, int32_t ncell, int64_t n, const int32_t *p2p_pt
     uint32_t *kalt = (uint32_t *)(buf + 2 * (ncell + 1));
     uint32_t *valt = (uint32_t *)(buf + 3 * (ncell + 1));
     uint32_t *val = (uint32_t *)leaves;
-    FMM_HIP_CHECK(hipMemsetAsync(d_count, 0, 9 * sizeof(int32_t), s));
+    if (ncell <= 0) {
+        fill_zero(d_count, 9 * sizeof(int32_t), s);
+        return;
+    }
     hipLaunchKernelGGL(k_leaf_cost, dim3(grid_for((int64_t)ncell * 64, 256, 16384)), dim3(256), 0, s, c, ncell, n,
-                       p2p_ptr, p2p_src, d_count, key, val);
+                       p2p_ptr, p2p_src, key, val);
     FMM_LAUNCH_CHECK();
     radix_sort_u32(key, val, kalt, valt, ncell, 0, 16, tmp, s);
+    hipLaunchKernelGGL(k_leaf_counts, dim3(1), dim3(64), 0, s, key, ncell, d_count);
+    FMM_LAUNCH_CHECK();
 }
 
 void p2p_prepare(Geometry g, int64_t n, const int32_t *leaf_of, const double *xs, const double *ys,
