@@ -43,9 +43,15 @@ __device__ inline bool mac_exact(int la, int ax, int ay, int az, int lb, int bx,
 // global writes are contiguous.
 constexpr int kTravThreads = 256;
 constexpr int kTileOut = 8 * kTravThreads;   // most entries one tile adds to one buffer
-constexpr int kBufM = kTileOut + 1024;       // staged M2L keys (flushed above 1024)
-constexpr int kBufP = kTileOut + 1024;       // staged P2P keys (flushed above 1024)
-constexpr int kBufF = kTileOut;              // staged frontier pairs (flushed every tile)
+// Staging sizes: flushes reserve global space with same-address atomics,
+// which serialise across the chip, so the buffers are as large as two
+// workgroups per compute unit allow (32-bit keys: 80 KB of LDS).
+template <class K>
+struct TravBuf {
+    static constexpr int M = sizeof(K) == 4 ? 4 * kTileOut : kTileOut + 1024;   // M2L keys
+    static constexpr int P = sizeof(K) == 4 ? 2 * kTileOut : kTileOut + 1024;   // P2P keys
+    static constexpr int F = sizeof(K) == 4 ? 2 * kTileOut - 64 : kTileOut;     // next-frontier pairs
+};
 
 // Barrier for LDS traffic only: global loads in flight (the prefetched
 // pairs and records of the next tiles) stay in flight.
@@ -95,9 +101,9 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(CellArrays c, const i
                                                            int32_t cap_p2p, int32_t *__restrict__ n_m2l,
                                                            int32_t *__restrict__ n_p2p, int bits, uint32_t ta,
                                                            uint32_t tb) {
-    __shared__ K bm[kBufM];
-    __shared__ K bp[kBufP];
-    __shared__ int2 bf[kBufF];
+    __shared__ K bm[TravBuf<K>::M];
+    __shared__ K bp[TravBuf<K>::P];
+    __shared__ int2 bf[TravBuf<K>::F];
     __shared__ int32_t cm, cp, cf, base_sh;
     int32_t nf = *nf_in;
     nf = nf < capf ? nf : capf;
@@ -138,9 +144,9 @@ __global__ void __launch_bounds__(kTravThreads) k_traverse(CellArrays c, const i
             }
         }
         lds_barrier();
-        if (cm > kBufM - kTileOut) flush_keys<K>(bm, cm, m2l, cap_m2l, n_m2l, &base_sh);
-        if (cp > kBufP - kTileOut) flush_keys<K>(bp, cp, p2p, cap_p2p, n_p2p, &base_sh);
-        if (cf > kBufF - kTileOut) flush_keys<int2>(bf, cf, fout, capf, nf_out, &base_sh);
+        if (cm > TravBuf<K>::M - kTileOut) flush_keys<K>(bm, cm, m2l, cap_m2l, n_m2l, &base_sh);
+        if (cp > TravBuf<K>::P - kTileOut) flush_keys<K>(bp, cp, p2p, cap_p2p, n_p2p, &base_sh);
+        if (cf > TravBuf<K>::F - kTileOut) flush_keys<int2>(bf, cf, fout, capf, nf_out, &base_sh);
         pr = pn;
         ra = na;
         rb = nb;
