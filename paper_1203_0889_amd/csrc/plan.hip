@@ -91,6 +91,9 @@ struct fmm_plan {
     // lists
     DevBuf front[2], m2l_pairs, p2p_pairs, pair_alt, m2l_ptr, m2l_src, p2p_ptr, p2p_src;
     int64_t cap_front = 0, cap_m2l = 0, cap_p2p = 0;
+    DevBuf levdev;              // level starts of the device-driven octree build
+    int depth_hint = 0;         // levels of the last tree
+    int64_t ncell_hint = 0;     // cells of the last tree
     // expansions and fields
     DevBuf M, L, ops_m2m, ops_l2l, m2m_part;
     int ops_p = -1;
@@ -238,31 +241,56 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
                        p->qs.as<double>(), s);
     mark(p, ST_SORT);
 
-    // ---- octree, level by level
-    ensure_cells(p, std::max<int64_t>(2 * ni, n / std::max(1, p->prm.ncrit) * 3 + 64));
-    fmm::launch_roots(p->off.as<int64_t>(), ni, cells_of(p), s);
-    p->level_begin.assign(1, 0);
-    int32_t lb = 0, le = ni;
-    p->level_begin.push_back(le);
-    for (int level = 0; level < p->prm.max_level && le > lb; level++) {
-        int64_t ncur = le - lb;
-        FMM_HIP_CHECK(p->bounds.grow((size_t)ncur * 9 * sizeof(int32_t)));
-        FMM_HIP_CHECK(p->nch.grow((size_t)(ncur + 1) * sizeof(int32_t) * 2));
-        FMM_HIP_CHECK(p->tmp.grow(std::max(p->tmp.bytes, fmm::scan_tmp_elems(ncur) * sizeof(int32_t))));
+    // ---- octree, level by level on the device: batches of levels are
+    // enqueued with their sizes kept on the device, and one host read per
+    // batch returns the level starts (a tree larger than the cell capacity
+    // is rebuilt with more).
+    ensure_cells(p, std::max<int64_t>({2 * ni, n / std::max(1, p->prm.ncrit) * 3 + 64, p->ncell_hint}));
+    const int nlev = p->prm.max_level + 3;
+    FMM_HIP_CHECK(p->levdev.grow((size_t)(nlev + 1) * sizeof(int32_t)));
+    int32_t *lev = p->levdev.as<int32_t>();
+    std::vector<int32_t> hl(nlev + 1);
+    int32_t le = ni;
+    for (int attempt = 0;; attempt++) {
+        const int32_t cap = (int32_t)std::min<int64_t>(p->cell_cap, ((int64_t)1 << 31) - 1);
+        FMM_HIP_CHECK(p->bounds.grow((size_t)cap * 9 * sizeof(int32_t)));
+        FMM_HIP_CHECK(p->nch.grow((size_t)(cap + 1) * sizeof(int32_t) * 2 + 64));
+        FMM_HIP_CHECK(p->tmp.grow(std::max(p->tmp.bytes, fmm::scan_tmp_elems(cap) * sizeof(int32_t))));
         int32_t *nch = p->nch.as<int32_t>();
-        int32_t *off = nch + (ncur + 1);
-        fmm::launch_tree_count(cells_of(p), lb, le, p->prm.ncrit, p->prm.max_level, p->keys.as<uint64_t>(),
-                               p->bounds.as<int32_t>(), nch, s);
-        fmm::exclusive_scan_oop(nch, off, ncur, off + ncur, p->tmp.as<int32_t>(), s);
-        int32_t total = 0;
-        sync_read(p, &total, off + ncur, sizeof(int32_t));
-        if (total == 0) break;
-        ensure_cells(p, (int64_t)le + total);
-        fmm::launch_tree_write(cells_of(p), lb, le, p->bounds.as<int32_t>(), nch, off, s);
-        lb = le;
-        le = le + total;
-        p->level_begin.push_back(le);
+        int32_t *off = nch + (cap + 1);
+        int32_t *total = off + (cap + 1);
+        fmm::launch_roots(p->off.as<int64_t>(), ni, cells_of(p), s);
+        fmm::launch_tree_levels_init(lev, ni, nlev, s);
+        // levels 0 .. max_level - 1 can have children; the depth of the
+        // last tree (or of a uniform one) sets the first batch
+        int level = 0;
+        int batch = p->depth_hint > 0 ? p->depth_hint + 1 : 2;
+        if (p->depth_hint <= 0)
+            for (int64_t m = std::max(1, p->prm.ncrit); m < n; m *= 8) batch++;
+        bool over = false;
+        for (;;) {
+            const int stop = std::min(level + batch, p->prm.max_level);
+            for (; level < stop; level++)
+                fmm::launch_tree_level_dev(cells_of(p), lev, level, nlev, p->prm.ncrit, p->prm.max_level,
+                                           p->keys.as<uint64_t>(), p->bounds.as<int32_t>(), nch, off, total, cap,
+                                           p->tmp.as<int32_t>(), s);
+            sync_read(p, hl.data(), lev, (size_t)(nlev + 1) * sizeof(int32_t));
+            if (hl[nlev]) {
+                over = true;
+                break;
+            }
+            if (level >= p->prm.max_level || hl[level + 1] == hl[level]) break;   // the last level had no children
+            batch = 2;
+        }
+        if (!over) break;
+        if (attempt > 8) throw std::runtime_error("octree: cell capacity did not converge");
+        ensure_cells(p, (int64_t)p->cell_cap * 2);
     }
+    p->level_begin.assign(1, 0);
+    for (int l = 1; l < nlev && hl[l] > hl[l - 1]; l++) p->level_begin.push_back(hl[l]);
+    le = p->level_begin.back();
+    p->depth_hint = (int)p->level_begin.size() - 1;
+    p->ncell_hint = le;
     p->ncell = le;
     if ((size_t)p->ncell * sizeof(int4) > p->crec.bytes) throw std::runtime_error("cell records smaller than the tree");
     fmm::launch_leaf_of(cells_of(p), (int32_t)p->ncell, p->leaf_of.as<int32_t>(), p->flag.as<int32_t>() + 1, s);
@@ -688,6 +716,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
     p->crec.release();
+    p->levdev.release();
     fmm::release_near_far(p->nf);
     fmm::release_near_far(p->nf_t);
     p->reader.release();

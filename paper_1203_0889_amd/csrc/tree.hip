@@ -251,6 +251,86 @@ __global__ void k_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t
     }
 }
 
+// Device-driven levels: the cell range of level l is [lev[l], lev[l + 1]),
+// read on the device, so a batch of levels is enqueued without host reads.
+__global__ void k_tree_levels_init(int32_t *__restrict__ lev, int n_inst, int nlev) {
+    for (int i = threadIdx.x; i < nlev; i += blockDim.x) lev[i] = i == 0 ? 0 : n_inst;   // later levels start empty
+    if (threadIdx.x == 0) lev[nlev] = 0;                                        // overflow flag
+}
+
+__global__ void k_tree_count_dev(CellArrays c, const int32_t *__restrict__ lev, int level, int ncrit, int max_level,
+                                 const uint64_t *__restrict__ skeys, int32_t *__restrict__ bounds,
+                                 int32_t *__restrict__ nch) {
+    const int32_t lb = lev[level], le = lev[level + 1];
+    const int64_t nt = (int64_t)(le - lb) * 8;
+    // the 8 lanes of a cell are in one iteration and leave the loop together
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t cell = lb + (int32_t)(t >> 3);
+        const int o = (int)(t & 7);
+        const int32_t j = cell - lb;
+        const int level_c = c.level[cell];
+        const int32_t first = c.first[cell], count = c.count[cell];
+        if (count <= ncrit || level_c >= max_level) {
+            if (o == 0) nch[j] = 0;
+            continue;
+        }
+        const int shift = 3 * (kLevels - (level_c + 1));
+        const int32_t end = first + count;
+        int32_t a = first, b = end;
+        if (o > 0)
+            while (a < b) {
+                int32_t mid = a + ((b - a) >> 1);
+                int dig = (int)((skeys[mid] >> shift) & 7ull);
+                if (dig < o) a = mid + 1; else b = mid;
+            }
+        bounds[9 * j + o] = a;
+        if (o == 7) bounds[9 * j + 8] = end;
+        const int32_t next = __shfl_down(a, 1, 8);
+        const bool ne = (o == 7 ? end : next) > a;
+        const uint64_t m = __ballot(ne);
+        if (o == 0) nch[j] = __popcll((m >> (threadIdx.x & 63 & ~7)) & 0xffull);
+    }
+}
+
+// Children of level `level`; lev[level + 2] = end of the new level.  A tree
+// larger than cap cells stops here: the flag lev[nlev] is set, nothing is
+// written past cap, and the new level is left empty.
+__global__ void k_tree_write_dev(CellArrays c, int32_t *__restrict__ lev, int level, int nlev,
+                                 const int32_t *__restrict__ bounds, const int32_t *__restrict__ nch,
+                                 const int32_t *__restrict__ off, const int32_t *__restrict__ total, int32_t cap) {
+    const int32_t lb = lev[level], le = lev[level + 1];
+    const bool over = (int64_t)le + *total > cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        lev[level + 2] = over ? le : le + *total;
+        if (over) lev[nlev] = 1;
+    }
+    if (over) return;
+    for (int32_t cell = lb + blockIdx.x * blockDim.x + threadIdx.x; cell < le; cell += gridDim.x * blockDim.x) {
+        const int32_t j = cell - lb;
+        if (nch[j] == 0) continue;
+        int32_t dst = le + off[j];
+        c.child[cell] = dst;
+        c.nchild[cell] = nch[j];
+        const int lv = c.level[cell] + 1;
+        const int32_t px = c.ix[cell], py = c.iy[cell], pz = c.iz[cell], inst = c.inst[cell];
+        for (int o = 0; o < 8; o++) {
+            const int32_t a = bounds[9 * j + o], b = bounds[9 * j + o + 1];
+            if (b <= a) continue;
+            c.level[dst] = lv;
+            c.ix[dst] = 2 * px + (o & 1);
+            c.iy[dst] = 2 * py + ((o >> 1) & 1);
+            c.iz[dst] = 2 * pz + ((o >> 2) & 1);
+            c.first[dst] = a;
+            c.count[dst] = b - a;
+            c.child[dst] = -1;
+            c.nchild[dst] = 0;
+            c.parent[dst] = cell;
+            c.inst[dst] = inst;
+            dst++;
+        }
+    }
+}
+
 __global__ void k_leaf_of(CellArrays c, int32_t ncell, int32_t *__restrict__ leaf_of, int32_t *__restrict__ nleaf) {
     for (int32_t cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x) {
         c.rec[cell] = make_int4(c.ix[cell] | (c.level[cell] << 24), c.iy[cell] | (c.nchild[cell] << 24), c.iz[cell],
@@ -326,6 +406,24 @@ void launch_tree_count(CellArrays c, int32_t lb, int32_t le, int ncrit, int max_
 void launch_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t *bounds, const int32_t *nch,
                        const int32_t *off, hipStream_t s) {
     hipLaunchKernelGGL(k_tree_write, dim3(grid_for(le - lb, 128, 1 << 30)), dim3(128), 0, s, c, lb, le, bounds, nch, off);
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_tree_levels_init(int32_t *lev, int n_inst, int nlev, hipStream_t s) {
+    hipLaunchKernelGGL(k_tree_levels_init, dim3(1), dim3(64), 0, s, lev, n_inst, nlev);
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_tree_level_dev(CellArrays c, int32_t *lev, int level, int nlev, int ncrit, int max_level,
+                           const uint64_t *skeys, int32_t *bounds, int32_t *nch, int32_t *off, int32_t *total,
+                           int32_t cap, int32_t *scan_tmp, hipStream_t s) {
+    const int grid = grid_for((int64_t)cap * 8, 128, 4096);
+    hipLaunchKernelGGL(k_tree_count_dev, dim3(grid), dim3(128), 0, s, c, lev, level, ncrit, max_level, skeys, bounds,
+                       nch);
+    FMM_LAUNCH_CHECK();
+    exclusive_scan_dev(nch, off, lev + level, cap, total, scan_tmp, s);
+    hipLaunchKernelGGL(k_tree_write_dev, dim3(grid_for(cap, 128, 4096)), dim3(128), 0, s, c, lev, level, nlev, bounds,
+                       nch, off, total, cap);
     FMM_LAUNCH_CHECK();
 }
 
