@@ -296,11 +296,9 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     fmm::launch_leaf_of(cells_of(p), (int32_t)p->ncell, p->leaf_of.as<int32_t>(), p->flag.as<int32_t>() + 1, s);
     mark(p, ST_TREE);
 
-    int hf[2] = {0, 0};  // [0] = non-finite input seen, [1] = number of leaves
-    sync_read(p, hf, p->flag.ptr, 2 * sizeof(int));
-    if (hf[0]) throw std::invalid_argument("non-finite particle coordinate");
-    p->nleaf = hf[1];
-
+    // the non-finite flag and the leaf count are read back with the
+    // traversal's sizes (the traversal runs on any tree, even one built from
+    // non-finite coordinates, which is then rejected)
     // ---- dual tree traversal, breadth first: every step is enqueued at once
     // (sizes stay on the device); one read-back checks capacities and the
     // whole traversal is rerun with larger buffers if any overflowed.
@@ -314,9 +312,9 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     p->cap_front = std::max<int64_t>(p->cap_front, 2 * (int64_t)ni);
     if (p->cap_m2l < 1024) p->cap_m2l = std::max<int64_t>(4096, 64 * ncell);
     if (p->cap_p2p < 1024) p->cap_p2p = std::max<int64_t>(4096, 32 * ncell);
-    FMM_HIP_CHECK(p->counters.grow((size_t)(nsteps + 4) * sizeof(int32_t)));
+    FMM_HIP_CHECK(p->counters.grow((size_t)(nsteps + 6) * sizeof(int32_t)));
     int32_t *ctr = p->counters.as<int32_t>();
-    std::vector<int32_t> hc(nsteps + 3);
+    std::vector<int32_t> hc(nsteps + 5);
     const uint32_t ta = (uint32_t)p->prm.theta_num, tb = (uint32_t)p->prm.theta_den;
     for (int attempt = 0;; attempt++) {
         FMM_HIP_CHECK(p->front[0].grow(p->cap_front * sizeof(int2)));
@@ -329,8 +327,11 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         for (int k = 0; k < nsteps; k++)
             fmm::launch_traverse(cells_of(p), p->front[k & 1].as<int2>(), ctr + 2 + k, p->front[(k + 1) & 1].as<int2>(),
                                  ctr + 3 + k, (int32_t)p->cap_front, pb, ctr, bits, ta, tb, s);
-        sync_read(p, hc.data(), ctr, (size_t)(nsteps + 3) * sizeof(int32_t));
-        int64_t fmax = *std::max_element(hc.begin() + 2, hc.end());
+        FMM_HIP_CHECK(hipMemcpyAsync(ctr + nsteps + 3, p->flag.ptr, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        sync_read(p, hc.data(), ctr, (size_t)(nsteps + 5) * sizeof(int32_t));
+        if (hc[nsteps + 3]) throw std::invalid_argument("non-finite particle coordinate");
+        p->nleaf = hc[nsteps + 4];
+        int64_t fmax = *std::max_element(hc.begin() + 2, hc.begin() + nsteps + 3);
         bool over = false;
         if (fmax > p->cap_front) {
             p->cap_front = fmax + fmax / 2;
