@@ -235,7 +235,9 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const K *__restrict__ ki
 // LDS in digit order, and writes it out in that order: consecutive threads
 // then write consecutive addresses of one digit run instead of up to 64
 // different lines per store.
-template <class K>
+// kVals: values travel with the keys (without them the tile's value
+// staging is left out, which leaves LDS for more workgroups per CU).
+template <class K, bool kVals>
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                            K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
                                                            int shift, int nbits, const int32_t *__restrict__ offs,
@@ -246,7 +248,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
     __shared__ int gbase[256];
     __shared__ int wsum[kRsWaves];
     __shared__ K skey[kRsTile];
-    __shared__ uint32_t sval[kRsTile];
+    __shared__ uint32_t sval[kVals ? kRsTile : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int mask = (1 << nbits) - 1;
     for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&wcount[0][0])[i] = 0;
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
         bool valid = i < n;
         K k = valid ? kin[i] : (K)0;
         key[it] = k;
-        val[it] = (valid && vin) ? vin[i] : 0u;
+        val[it] = (kVals && valid) ? vin[i] : 0u;
         int d = (int)((k >> shift) & (K)mask);
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; b++) {
@@ -309,7 +311,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
             int d = (int)((key[it] >> shift) & (K)mask);
             int lp = lstart[d] + wbase[w][d] + rank[it];
             skey[lp] = key[it];
-            sval[lp] = val[it];
+            if (kVals) sval[lp] = val[it];
         }
     }
     __syncthreads();
@@ -319,7 +321,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
         const int d = (int)((k >> shift) & (K)mask);
         const int pos = gbase[d] + (lp - lstart[d]);
         kout[pos] = k;
-        if (vout) vout[pos] = sval[lp];
+        if (kVals) vout[pos] = sval[lp];
     }
 }
 
@@ -338,8 +340,12 @@ void radix_sort_impl(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, 
         hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(kRsThreads), 0, s, ka, n, shift, nbits, counts, nblocks);
         FMM_LAUNCH_CHECK();
         exclusive_scan_i32(counts, (int64_t)256 * nblocks, nullptr, scan_tmp, s);
-        hipLaunchKernelGGL(k_rs_scatter<K>, dim3(nblocks), dim3(kRsThreads), 0, s, ka, va, kb, vb, n, shift, nbits,
-                           counts, nblocks);
+        if (va)
+            hipLaunchKernelGGL((k_rs_scatter<K, true>), dim3(nblocks), dim3(kRsThreads), 0, s, ka, va, kb, vb, n, shift,
+                               nbits, counts, nblocks);
+        else
+            hipLaunchKernelGGL((k_rs_scatter<K, false>), dim3(nblocks), dim3(kRsThreads), 0, s, ka, va, kb, vb, n, shift,
+                               nbits, counts, nblocks);
         FMM_LAUNCH_CHECK();
         K *tk = ka;
         ka = kb;
