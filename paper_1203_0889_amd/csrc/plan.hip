@@ -92,6 +92,11 @@ struct fmm_plan {
     DevBuf front[2], m2l_pairs, p2p_pairs, pair_alt, m2l_ptr, m2l_src, p2p_ptr, p2p_src;
     int64_t cap_front = 0, cap_m2l = 0, cap_p2p = 0;
     DevBuf levdev;              // level starts of the device-driven octree build
+    // upward pass run by fmm_build_tree on a second stream, beside the
+    // near/far build (fmm_upward then has nothing left to do)
+    hipStream_t up_side = nullptr;
+    hipEvent_t up_fork = nullptr, up_join = nullptr;
+    bool upward_fresh = false;
     int depth_hint = 0;         // levels of the last tree
     int64_t ncell_hint = 0;     // cells of the last tree
     // expansions and fields
@@ -185,6 +190,7 @@ fmm::Geometry geom(fmm_plan *p) {
 }
 
 fmm::NearFarArgs nf_args(fmm_plan *p);
+void start_upward(fmm_plan *p);
 
 void do_build(fmm_plan *p, const double *pos, const double *q) {
     hipStream_t s = p->stream;
@@ -380,10 +386,12 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     }
     mark(p, ST_CSR);
 
+    if (p->n > 0) start_upward(p);
     if (p->prm.precision == FMM_PREC_MIXED) {
         fmm::build_near_far_mixed(p->nf, nf_args(p), s);
         mark(p, ST_NF_BUILD);
     }
+    if (p->upward_fresh) FMM_HIP_CHECK(hipStreamWaitEvent(s, p->up_join, 0));   // join the upward pass
 }
 
 fmm::NearFarArgs nf_args(fmm_plan *p) {
@@ -430,24 +438,60 @@ void ensure_ops(fmm_plan *p) {
     p->ops_p = pp;
 }
 
-void do_upward(fmm_plan *p) {
-    hipStream_t s = p->stream;
+// P2M and M2M on stream s; with `side` the stage events are recorded on s
+// directly (it is not the plan's stream).
+void upward_kernels(fmm_plan *p, hipStream_t s, bool side) {
     const int P = fmm::ncoef(p->prm.p);
     ensure_ops(p);
     FMM_HIP_CHECK(p->M.grow((size_t)std::max<int64_t>(p->ncell, 1) * P * 8));
-    fmm::Geometry g = geom(p);
-    record(p, ST_P2M);
-    fmm::launch_p2m(g, (int32_t)p->ncell, p->prm.p, p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
-                    p->qs.as<double>(), p->M.as<double>(), s);
-    mark(p, ST_P2M);
     int depth = (int)p->level_begin.size() - 1;  // number of levels present
     int32_t widest = 1;
     for (int l = 0; l + 1 < depth; l++) widest = std::max(widest, p->level_begin[l + 1] - p->level_begin[l]);
     FMM_HIP_CHECK(p->m2m_part.grow((size_t)8 * widest * P * 8));
+    fmm::Geometry g = geom(p);
+    const bool timed = side && p->ev_ok && !p->capturing;
+    if (timed) FMM_HIP_CHECK(hipEventRecord(p->ev_beg[ST_P2M], s));
+    else record(p, ST_P2M);
+    fmm::launch_p2m(g, (int32_t)p->ncell, p->prm.p, p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
+                    p->qs.as<double>(), p->M.as<double>(), s);
+    if (timed) FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_P2M], s));
+    else mark(p, ST_P2M);
     for (int l = depth - 2; l >= 0; l--)
         fmm::launch_m2m_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_m2m.as<double>(),
                               p->M.as<double>(), p->m2m_part.as<double>(), s);
-    mark(p, ST_M2M);
+    if (timed) {
+        FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_M2M], s));
+        p->beg_of[ST_P2M] = p->ev_beg[ST_P2M];
+        p->beg_of[ST_M2M] = p->ev_end[ST_P2M];
+        p->ev_used[ST_P2M] = p->ev_used[ST_M2M] = true;
+    } else {
+        mark(p, ST_M2M);
+    }
+}
+
+void do_upward(fmm_plan *p) {
+    if (p->upward_fresh && !p->capturing) {   // done by fmm_build_tree, nothing changed since
+        p->upward_fresh = false;
+        return;
+    }
+    p->upward_fresh = false;
+    upward_kernels(p, p->stream, false);
+}
+
+// The upward pass needs only the sorted particles and the tree, so a full
+// build starts it on a second stream (default priority) before the
+// near/far build and joins it back at the end of the build.
+void start_upward(fmm_plan *p) {
+    if (!p->up_side) {
+        FMM_HIP_CHECK(hipStreamCreateWithFlags(&p->up_side, hipStreamNonBlocking));
+        FMM_HIP_CHECK(hipEventCreateWithFlags(&p->up_fork, hipEventDisableTiming));
+        FMM_HIP_CHECK(hipEventCreateWithFlags(&p->up_join, hipEventDisableTiming));
+    }
+    FMM_HIP_CHECK(hipEventRecord(p->up_fork, p->stream));
+    FMM_HIP_CHECK(hipStreamWaitEvent(p->up_side, p->up_fork, 0));
+    upward_kernels(p, p->up_side, true);
+    FMM_HIP_CHECK(hipEventRecord(p->up_join, p->up_side));
+    p->upward_fresh = true;
 }
 
 // Workspaces of the evaluate stage (locals, near and far fields).
@@ -517,6 +561,7 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
 // permutation; box, keys, tree, lists and task tables stay.
 void do_refresh(fmm_plan *p, const double *pos, const double *q) {
     hipStream_t s = p->stream;
+    p->upward_fresh = false;   // new particles: fmm_upward recomputes
     FMM_HIP_CHECK(hipMemsetAsync(p->flag.ptr, 0, 16 * sizeof(int), s));
     fmm::launch_bbox(pos, p->n, p->off.as<int64_t>(), p->n_inst, p->ord.as<unsigned long long>(), p->flag.as<int>(), s);
     fmm::launch_gather(pos, q, p->idx.as<uint32_t>(), p->n, p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
@@ -704,6 +749,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
     if (!p) return FMM_OK;
     hipSetDevice(p->device);
     hipStreamSynchronize(p->stream);
+    if (p->up_side) hipStreamSynchronize(p->up_side);   // an upward pass of an interrupted build
     DevBuf *all[] = {&p->off, &p->ord, &p->flag, &p->box, &p->scale, &p->keys, &p->kalt, &p->idx, &p->valt,
                      &p->ikey, &p->ialt, &p->rank, &p->ralt, &p->tmp, &p->xs, &p->ys, &p->zs, &p->qs,
                      &p->leaf_of, &p->bounds, &p->nch, &p->counters, &p->front[0], &p->front[1], &p->m2l_pairs,
@@ -718,6 +764,11 @@ fmm_status fmm_destroy(fmm_plan *p) {
     for (auto &b : p->cb) b.release();
     p->crec.release();
     p->levdev.release();
+    if (p->up_side) {
+        (void)hipStreamDestroy(p->up_side);
+        (void)hipEventDestroy(p->up_fork);
+        (void)hipEventDestroy(p->up_join);
+    }
     fmm::release_near_far(p->nf);
     fmm::release_near_far(p->nf_t);
     p->reader.release();
