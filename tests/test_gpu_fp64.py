@@ -189,3 +189,34 @@ def test_repeated_builds_reuse_plan():
         phi_ref, fld_ref, _ = oracle.fmm(pos, q, 6, 32, 1, 2)
         assert rel(out["phi"].cpu().numpy(), phi_ref) < 1e-11
         assert rel(out["field"].cpu().numpy(), fld_ref) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rebuilds_that_outgrow_the_last_tree(prec):
+    """One plan, trees of very different size and depth in a row: a small
+    uniform tree, then a deep Plummer tree with far more cells than the
+    last one (the octree's cell capacity and level batches are sized from
+    the previous tree, so this takes the capacity retry and extra level
+    batches), then a small one again.  Tree and lists stay bit-exact and the
+    potentials match the oracle."""
+    plan = fmm.Plan(p=6, ncrit=8, theta=(1, 2), precision=prec, device=0)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    for dist, n, seed in (("uniform", 3000, 31), ("plummer", 40000, 32), ("uniform", 2500, 33)):
+        say("rebuild", prec, dist, n)
+        pos, q = make(dist, n, seed)
+        plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+        plan.upward()
+        out = plan.evaluate()
+        torch.cuda.synchronize()
+        T = oracle.Tree(pos, 8)
+        T.lists(1, 2)
+        _, _, cells = plan.copy_tree()
+        assert cells.shape[0] == T.ncell and np.array_equal(cells[:, :9], T.cells)
+        mp, ms, pp, ps = plan.copy_lists()
+        for ptr, src, ref in ((mp, ms, T.m2l), (pp, ps, T.p2p)):
+            assert np.array_equal(np.repeat(np.arange(T.ncell), np.diff(ptr)), ref[:, 0])
+            assert np.array_equal(src, ref[:, 1])
+        phi_ref, _ = T.fmm(q, 6)
+        e = rel(out["phi"].cpu().numpy(), phi_ref)
+        say("  depth", int(cells[:, 0].max()), "cells", T.ncell, "phi rel", e)
+        assert e < tol
