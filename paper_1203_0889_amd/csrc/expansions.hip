@@ -126,7 +126,7 @@ __device__ inline int octant_of(const CellArrays &c, int32_t cell) {
 // matrix of o (column-major, so a wave reads consecutive rows) to the kPB
 // vectors staged in LDS (parent-minor, so one 16-byte LDS read feeds two
 // parents).  Each matrix column is read once per kPB parents.
-constexpr int kPB = 16;
+constexpr int kPB = 8;   // 16 and 4 measured slower on the wide levels
 
 __device__ inline int32_t child_in_octant(const CellArrays &c, int32_t parent, int o) {
     int32_t ch = c.child[parent];
