@@ -129,10 +129,16 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload):
         # minimum times add.
         tq = stage_avg.get("queue", 0.0) * 1e-3
         t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
+        # the same bound with the FP32 vector rate without packed FP32 (half
+        # of 157.3 TF; packed FP32 instructions are disabled in this build)
+        t_np = p2p_flop / (PEAK["fp32_valu"] / 2) + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
         roof = {"bound": "alu", "achieved": (p2p_flop + m2l_f) / tq / 1e12 if tq > 0 else None,
                 "peak": (p2p_flop + m2l_f) / t_min / 1e12, "unit": "TFLOP/s", "traffic": committed_traffic(workload),
                 "kernel": "k_queue + k_p2p_side (P2P FP32 VALU + M2L split-bf16 MFMA)", "kernel_ms": tq * 1e3,
-                "peak_basis": "P2P flop / 157.3 TF fp32 vector + 3 x M2L flop / 2.5 PF bf16 dense MFMA"}
+                "peak_basis": "P2P flop / 157.3 TF fp32 vector + 3 x M2L flop / 2.5 PF bf16 dense MFMA",
+                "peak_nonpacked_fp32": (p2p_flop + m2l_f) / t_np / 1e12}
+        if tq > 0:
+            roof["frac_nonpacked_fp32"] = (p2p_flop + m2l_f) / tq / 1e12 / roof["peak_nonpacked_fp32"]
     else:
         dom, t, f = ("p2p", t_p2p, p2p_flop) if t_p2p >= t_m2l else ("m2l", t_m2l, m2l_f)
         roof = {"bound": "alu", "achieved": f / t / 1e12 if t > 0 else None, "peak": PEAK["fp64"] / 1e12,
