@@ -2,8 +2,9 @@
 // octree, Sec. 2.2, and of the interaction-pair lists).
 //
 // Radix sort: 8-bit digits; per pass three launches -- per-tile digit
-// histograms, one exclusive scan over the (digit-major, tile-minor) count
-// table, and a stable scatter.  Inside a tile each wave64 ranks its keys with
+// histograms, a scan of each digit's row of the (digit-major, tile-minor)
+// count table with the row totals, and a stable scatter that scans the 256
+// digit totals itself.  Inside a tile each wave64 ranks its keys with
 // ballot-based peer masks (lanes holding the same digit), so ranks follow the
 // input order and the sort is stable.
 #include "common.h"
@@ -208,11 +209,19 @@ __global__ void k_scan_down_dev(const int32_t *__restrict__ in, int32_t *__restr
 
 constexpr int kRsThreads = 256;
 constexpr int kRsWaves = kRsThreads / 64;
-constexpr int kRsItems = 16;
+constexpr int kRsItems = 16;   // keys per thread (tiles of 32 keys per thread were slower)
 constexpr int kRsTile = kRsThreads * kRsItems;
-constexpr int kRsWaveTile = 64 * kRsItems;
 
-template <class K>
+// Tile of a workgroup.  Workgroups are dealt to the 8 XCDs in turn, so this
+// gives each XCD a contiguous run of tiles: the runs of one digit that
+// neighbouring tiles write then meet in one L2.
+__device__ inline int rs_tile(int b, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Per-tile digit counts, digit-major: counts[d * nblocks + tile].
+template <class K, int Items>
 __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const K *__restrict__ kin, int64_t n, int shift,
                                                         int nbits, int32_t *__restrict__ counts, int nblocks) {
     __shared__ int hist[256];
@@ -220,53 +229,91 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_hist(const K *__restrict__ ki
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int mask = (1 << nbits) - 1;
-    int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kRsWaveTile + lane;
-#pragma unroll 4
-    for (int it = 0; it < kRsItems; it++) {
-        int64_t i = base + it * 64;
-        if (i < n) atomicAdd(&hist[(int)((kin[i] >> shift) & (K)mask)], 1);
+    const int t = rs_tile(blockIdx.x, nblocks);
+    const int64_t base = (int64_t)t * (kRsThreads * Items) + (int64_t)w * (64 * Items) + lane;
+    int dig[Items];
+#pragma unroll
+    for (int it = 0; it < Items; it++) {
+        const int64_t i = base + it * 64;
+        dig[it] = i < n ? (int)((kin[i] >> shift) & (K)mask) : -1;
     }
+#pragma unroll
+    for (int it = 0; it < Items; it++)
+        if (dig[it] >= 0) atomicAdd(&hist[dig[it]], 1);
     __syncthreads();
-    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+    counts[(int64_t)threadIdx.x * nblocks + t] = hist[threadIdx.x];
+}
+
+// Workgroup d: exclusive scan of digit d's row of the count table (the
+// tile-order start of each tile's run within digit d) and the row total.
+__global__ void __launch_bounds__(kScanThreads) k_rs_rowscan(int32_t *__restrict__ counts, int nblocks,
+                                                             int32_t *__restrict__ totals) {
+    int32_t *row = counts + (int64_t)blockIdx.x * nblocks;
+    int carry = 0;
+    for (int c = 0; c < nblocks; c += kScanTile) {
+        const int b0 = c + threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) {
+            v[i] = b0 + i < nblocks ? row[b0 + i] : 0;
+            sum += v[i];
+        }
+        int tot;
+        int pre = block_exclusive_scan(sum, &tot) + carry;
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) {
+            if (b0 + i < nblocks) row[b0 + i] = pre;
+            pre += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 // Scatter of one pass.  Each block ranks its tile stably (per wave with
 // ballots over the digit bits, then across the waves), places the tile in
 // LDS in digit order, and writes it out in that order: consecutive threads
 // then write consecutive addresses of one digit run instead of up to 64
-// different lines per store.
+// different lines per store.  A digit's global start is the exclusive scan
+// of the digit totals (done here, per block) plus the tile's row prefix.
 // kVals: values travel with the keys (without them the tile's value
 // staging is left out, which leaves LDS for more workgroups per CU).
-template <class K, bool kVals>
+template <class K, bool kVals, int Items>
 __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                            K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
                                                            int shift, int nbits, const int32_t *__restrict__ offs,
-                                                           int nblocks) {
+                                                           const int32_t *__restrict__ totals, int nblocks) {
+    constexpr int kTile = kRsThreads * Items;
     __shared__ int wcount[kRsWaves][256];
     __shared__ int wbase[kRsWaves][256];
     __shared__ int lstart[257];
     __shared__ int gbase[256];
     __shared__ int wsum[kRsWaves];
-    __shared__ K skey[kRsTile];
-    __shared__ uint32_t sval[kVals ? kRsTile : 1];
+    __shared__ int wtot[kRsWaves];
+    __shared__ K skey[kTile];
+    __shared__ uint32_t sval[kVals ? kTile : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int mask = (1 << nbits) - 1;
     for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&wcount[0][0])[i] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
-    const int64_t base = tile0 + (int64_t)w * kRsWaveTile + lane;
-    K key[kRsItems];
-    uint32_t val[kRsItems];
-    int rank[kRsItems];
+    const int t = rs_tile(blockIdx.x, nblocks);
+    const int64_t base = (int64_t)t * kTile + (int64_t)w * (64 * Items) + lane;
+    K key[Items];
+    uint32_t val[Items];
+    int rank[Items];
 #pragma unroll
-    for (int it = 0; it < kRsItems; it++) {
+    for (int it = 0; it < Items; it++) {
         int64_t i = base + it * 64;
         bool valid = i < n;
-        K k = valid ? kin[i] : (K)0;
-        key[it] = k;
+        key[it] = valid ? kin[i] : (K)0;
         val[it] = (kVals && valid) ? vin[i] : 0u;
-        int d = (int)((k >> shift) & (K)mask);
+    }
+#pragma unroll
+    for (int it = 0; it < Items; it++) {
+        bool valid = base + it * 64 < n;
+        int d = (int)((key[it] >> shift) & (K)mask);
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; b++) {
             uint64_t m = __ballot((d >> b) & 1);
@@ -281,7 +328,8 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
     __syncthreads();
     {
         // thread d: block count of digit d, wave offsets within the digit,
-        // then an exclusive scan over the 256 digits (block-local starts)
+        // then exclusive scans over the 256 digits of the block counts
+        // (block-local starts) and of the digit totals (global starts)
         const int d = threadIdx.x;
         int run = 0;
 #pragma unroll
@@ -289,23 +337,34 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
             wbase[ww][d] = run;
             run += wcount[ww][d];
         }
-        int inc = run;
+        const int tot = totals[d];
+        int inc = run, tinc = tot;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            int t = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += t;
+            int a = __shfl_up(inc, o, 64), b = __shfl_up(tinc, o, 64);
+            if (lane >= o) {
+                inc += a;
+                tinc += b;
+            }
         }
-        if (lane == 63) wsum[w] = inc;
-        gbase[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+        if (lane == 63) {
+            wsum[w] = inc;
+            wtot[w] = tinc;
+        }
+        const int row = offs[(int64_t)d * nblocks + t];
         __syncthreads();
-        int before = 0;
-        for (int ww = 0; ww < w; ww++) before += wsum[ww];
+        int before = 0, tbefore = 0;
+        for (int ww = 0; ww < w; ww++) {
+            before += wsum[ww];
+            tbefore += wtot[ww];
+        }
         lstart[d] = before + inc - run;
+        gbase[d] = tbefore + tinc - tot + row;
         if (d == 255) lstart[256] = before + inc;
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kRsItems; it++) {
+    for (int it = 0; it < Items; it++) {
         int64_t i = base + it * 64;
         if (i < n) {
             int d = (int)((key[it] >> shift) & (K)mask);
@@ -325,27 +384,25 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
     }
 }
 
-template <class K>
-void radix_sort_impl(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, int bit_lo, int bit_hi,
-                     int32_t *d_tmp, hipStream_t s) {
-    if (n <= 1 || bit_hi <= bit_lo) return;
+template <class K, bool kVals>
+void radix_passes(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, int bit_lo, int bit_hi, int32_t *d_tmp,
+                  hipStream_t s) {
+    constexpr int Items = kRsItems;
     const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
-    int32_t *counts = d_tmp;
-    int32_t *scan_tmp = d_tmp + (int64_t)256 * nblocks;
+    int32_t *totals = d_tmp;
+    int32_t *counts = d_tmp + 256;
     K *ka = kin, *kb = kalt;
-    uint32_t *va = vin, *vb = vin ? valt : nullptr;
+    uint32_t *va = vin, *vb = kVals ? valt : nullptr;
     int passes = 0;
     for (int shift = bit_lo; shift < bit_hi; shift += 8) {
         int nbits = bit_hi - shift < 8 ? bit_hi - shift : 8;
-        hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(kRsThreads), 0, s, ka, n, shift, nbits, counts, nblocks);
+        hipLaunchKernelGGL((k_rs_hist<K, Items>), dim3(nblocks), dim3(kRsThreads), 0, s, ka, n, shift, nbits, counts,
+                           nblocks);
         FMM_LAUNCH_CHECK();
-        exclusive_scan_i32(counts, (int64_t)256 * nblocks, nullptr, scan_tmp, s);
-        if (va)
-            hipLaunchKernelGGL((k_rs_scatter<K, true>), dim3(nblocks), dim3(kRsThreads), 0, s, ka, va, kb, vb, n, shift,
-                               nbits, counts, nblocks);
-        else
-            hipLaunchKernelGGL((k_rs_scatter<K, false>), dim3(nblocks), dim3(kRsThreads), 0, s, ka, va, kb, vb, n, shift,
-                               nbits, counts, nblocks);
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kScanThreads), 0, s, counts, nblocks, totals);
+        FMM_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_rs_scatter<K, kVals, Items>), dim3(nblocks), dim3(kRsThreads), 0, s, ka, va, kb, vb, n,
+                           shift, nbits, counts, totals, nblocks);
         FMM_LAUNCH_CHECK();
         K *tk = ka;
         ka = kb;
@@ -357,8 +414,18 @@ void radix_sort_impl(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, 
     }
     if (passes & 1) {
         FMM_HIP_CHECK(hipMemcpyAsync(kin, ka, n * sizeof(K), hipMemcpyDeviceToDevice, s));
-        if (vin) FMM_HIP_CHECK(hipMemcpyAsync(vin, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        if (kVals) FMM_HIP_CHECK(hipMemcpyAsync(vin, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     }
+}
+
+template <class K>
+void radix_sort_impl(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, int bit_lo, int bit_hi,
+                     int32_t *d_tmp, hipStream_t s) {
+    if (n <= 1 || bit_hi <= bit_lo) return;
+    if (vin)
+        radix_passes<K, true>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s);
+    else
+        radix_passes<K, false>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s);
 }
 
 }  // namespace
@@ -489,7 +556,7 @@ void exclusive_scan_dev(const int32_t *d_in, int32_t *d_out, const int32_t *d_ra
 
 size_t radix_tmp_elems(int64_t n) {
     int64_t nblocks = (n + kRsTile - 1) / kRsTile;
-    return (size_t)(256 * nblocks) + scan_tmp_elems(256 * nblocks) + 64;
+    return (size_t)(256 * nblocks) + 256 + 64;
 }
 
 void radix_sort_u64(uint64_t *kin, uint32_t *vin, uint64_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
