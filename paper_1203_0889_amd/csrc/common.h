@@ -44,10 +44,6 @@ void exclusive_scan_i32(int32_t *d_data, int64_t n, int32_t *d_total, int32_t *d
 // Out-of-place variant (d_in may equal d_out).  d_total may point at d_out[n].
 void exclusive_scan_oop(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t *d_total, int32_t *d_tmp,
                         hipStream_t s);
-// The same with the length on the device: n = d_range[1] - d_range[0], at
-// most n_max (which sizes the launches); tmp holds scan_tmp_elems(n_max).
-void exclusive_scan_dev(const int32_t *d_in, int32_t *d_out, const int32_t *d_range, int64_t n_max,
-                        int32_t *d_total, int32_t *d_tmp, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs over bits [bit_lo, bit_hi).
 // kin/vin and kalt/valt are ping-pong buffers of n elements; the sorted

@@ -261,10 +261,9 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         const int32_t cap = (int32_t)std::min<int64_t>(p->cell_cap, ((int64_t)1 << 31) - 1);
         FMM_HIP_CHECK(p->bounds.grow((size_t)cap * 9 * sizeof(int32_t)));
         FMM_HIP_CHECK(p->nch.grow((size_t)(cap + 1) * sizeof(int32_t) * 2 + 64));
-        FMM_HIP_CHECK(p->tmp.grow(std::max(p->tmp.bytes, fmm::scan_tmp_elems(cap) * sizeof(int32_t))));
         int32_t *nch = p->nch.as<int32_t>();
-        int32_t *off = nch + (cap + 1);
-        int32_t *total = off + (cap + 1);
+        int32_t *csum = nch + (cap + 1);
+        int32_t *total = csum + (cap + 1);
         fmm::launch_roots(p->off.as<int64_t>(), ni, cells_of(p), s);
         fmm::launch_tree_levels_init(lev, ni, nlev, s);
         // levels 0 .. max_level - 1 can have children; the depth of the
@@ -278,8 +277,8 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
             const int stop = std::min(level + batch, p->prm.max_level);
             for (; level < stop; level++)
                 fmm::launch_tree_level_dev(cells_of(p), lev, level, nlev, p->prm.ncrit, p->prm.max_level,
-                                           p->keys.as<uint64_t>(), p->bounds.as<int32_t>(), nch, off, total, cap,
-                                           p->tmp.as<int32_t>(), s);
+                                           p->keys.as<uint64_t>(), p->bounds.as<int32_t>(), nch, csum, total, cap,
+                                           s);
             sync_read(p, hl.data(), lev, (size_t)(nlev + 1) * sizeof(int32_t));
             if (hl[nlev]) {
                 over = true;

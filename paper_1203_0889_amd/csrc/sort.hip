@@ -137,74 +137,6 @@ __global__ void k_scan_down(const int32_t *__restrict__ in, int32_t *__restrict_
     }
 }
 
-// Scans whose length lives on the device: n = range[1] - range[0] (a level's
-// cell range), at most n_max; grids are sized for n_max and blocks past n
-// return at once.
-__device__ inline int64_t dev_len(const int32_t *range) { return (int64_t)range[1] - range[0]; }
-
-__global__ void k_scan_reduce_dev(const int32_t *__restrict__ data, const int32_t *__restrict__ range,
-                                  int32_t *__restrict__ sums) {
-    const int64_t n = dev_len(range);
-    const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    if (blockIdx.x >= nb) return;
-    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int sum = 0;
-#pragma unroll
-    for (int i = 0; i < kScanItems; i++)
-        if (base + i < n) sum += data[base + i];
-    int tot;
-    block_exclusive_scan(sum, &tot);
-    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
-__global__ void k_scan_top_dev(int32_t *__restrict__ sums, const int32_t *__restrict__ range,
-                               int32_t *__restrict__ total) {
-    const int64_t nb = (dev_len(range) + kScanTile - 1) / kScanTile;
-    int carry = 0;
-    for (int64_t c = 0; c < nb; c += kScanTile) {
-        int64_t base = c + (int64_t)threadIdx.x * kScanItems;
-        int v[kScanItems];
-        int sum = 0;
-#pragma unroll
-        for (int i = 0; i < kScanItems; i++) {
-            v[i] = base + i < nb ? sums[base + i] : 0;
-            sum += v[i];
-        }
-        int tot;
-        int pre = block_exclusive_scan(sum, &tot) + carry;
-#pragma unroll
-        for (int i = 0; i < kScanItems; i++) {
-            if (base + i < nb) sums[base + i] = pre;
-            pre += v[i];
-        }
-        carry += tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && total) *total = carry;
-}
-
-__global__ void k_scan_down_dev(const int32_t *__restrict__ in, int32_t *__restrict__ out,
-                                const int32_t *__restrict__ range, const int32_t *__restrict__ sums) {
-    const int64_t n = dev_len(range);
-    const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    if (blockIdx.x >= nb) return;
-    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int sum = 0;
-#pragma unroll
-    for (int i = 0; i < kScanItems; i++) {
-        v[i] = base + i < n ? in[base + i] : 0;
-        sum += v[i];
-    }
-    int tot;
-    int pre = block_exclusive_scan(sum, &tot) + sums[blockIdx.x];
-#pragma unroll
-    for (int i = 0; i < kScanItems; i++) {
-        if (base + i < n) out[base + i] = pre;
-        pre += v[i];
-    }
-}
-
 // ---------------------------------------------------------------- radix sort
 
 constexpr int kRsThreads = 256;
@@ -540,17 +472,6 @@ void exclusive_scan_oop(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t 
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, d_tmp, nb, d_total);
     FMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_in, d_out, n, d_tmp);
-    FMM_LAUNCH_CHECK();
-}
-
-void exclusive_scan_dev(const int32_t *d_in, int32_t *d_out, const int32_t *d_range, int64_t n_max,
-                        int32_t *d_total, int32_t *d_tmp, hipStream_t s) {
-    const int64_t nb = std::max<int64_t>(1, (n_max + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_scan_reduce_dev, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_in, d_range, d_tmp);
-    FMM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_top_dev, dim3(1), dim3(kScanThreads), 0, s, d_tmp, d_range, d_total);
-    FMM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_down_dev, dim3((unsigned)nb), dim3(kScanThreads), 0, s, d_in, d_out, d_range, d_tmp);
     FMM_LAUNCH_CHECK();
 }
 

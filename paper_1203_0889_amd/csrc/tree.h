@@ -45,13 +45,13 @@ void launch_tree_write(CellArrays c, int32_t lb, int32_t le, const int32_t *boun
 // Device-driven octree levels.  lev[0 .. nlev) are level starts (level l =
 // cells [lev[l], lev[l + 1])), lev[nlev] an overflow flag; init sets level 0
 // to the n_inst roots.  One level step: child counts, their scan (length
-// on the device) and the children, with lev[level + 2] set on the device;
-// a tree past cap cells sets the flag and stops growing.  bounds holds
-// 9 cap ints, nch and off cap + 1, total one, scan_tmp scan_tmp_elems(cap).
+// on the device, in chunks of cells) and the children, with lev[level + 2]
+// set on the device; a tree past cap cells sets the flag and stops growing.
+// bounds holds 9 cap ints, nch cap + 1, csum (chunk sums) cap + 1, total one.
 void launch_tree_levels_init(int32_t *lev, int n_inst, int nlev, hipStream_t s);
 void launch_tree_level_dev(CellArrays c, int32_t *lev, int level, int nlev, int ncrit, int max_level,
-                           const uint64_t *skeys, int32_t *bounds, int32_t *nch, int32_t *off, int32_t *total,
-                           int32_t cap, int32_t *scan_tmp, hipStream_t s);
+                           const uint64_t *skeys, int32_t *bounds, int32_t *nch, int32_t *csum, int32_t *total,
+                           int32_t cap, hipStream_t s);
 // leaf_of[r] = leaf cell of sorted particle r; *nleaf = number of leaves.
 void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, int32_t *nleaf, hipStream_t s);
 

@@ -258,59 +258,149 @@ __global__ void k_tree_levels_init(int32_t *__restrict__ lev, int n_inst, int nl
     if (threadIdx.x == 0) lev[nlev] = 0;                                        // overflow flag
 }
 
-__global__ void k_tree_count_dev(CellArrays c, const int32_t *__restrict__ lev, int level, int ncrit, int max_level,
-                                 const uint64_t *__restrict__ skeys, int32_t *__restrict__ bounds,
-                                 int32_t *__restrict__ nch) {
+// The per-level scan of child counts works on chunks of kTreeChunk cells:
+// the count kernel writes each chunk's sum, one workgroup scans the chunk
+// sums, and the write kernel finishes each cell's offset inside its chunk.
+constexpr int kTreeChunk = 32;
+constexpr int kTreeCountThreads = kTreeChunk * 8;   // 8 lanes per cell
+constexpr int kChunkScanThreads = 1024;
+
+// Child ranges of the cells of level `level` (8 lanes per cell, binary
+// searches over the sorted keys), their number of non-empty children, and
+// the per-chunk sums of those numbers.
+__global__ void __launch_bounds__(kTreeCountThreads) k_tree_count_dev(CellArrays c, const int32_t *__restrict__ lev,
+                                                                      int level, int ncrit, int max_level,
+                                                                      const uint64_t *__restrict__ skeys,
+                                                                      int32_t *__restrict__ bounds,
+                                                                      int32_t *__restrict__ nch,
+                                                                      int32_t *__restrict__ csum) {
+    __shared__ int wsum[kTreeCountThreads / 64];
     const int32_t lb = lev[level], le = lev[level + 1];
-    const int64_t nt = (int64_t)(le - lb) * 8;
-    // the 8 lanes of a cell are in one iteration and leave the loop together
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t cell = lb + (int32_t)(t >> 3);
-        const int o = (int)(t & 7);
-        const int32_t j = cell - lb;
-        const int level_c = c.level[cell];
-        const int32_t first = c.first[cell], count = c.count[cell];
-        if (count <= ncrit || level_c >= max_level) {
-            if (o == 0) nch[j] = 0;
-            continue;
-        }
-        const int shift = 3 * (kLevels - (level_c + 1));
-        const int32_t end = first + count;
-        int32_t a = first, b = end;
-        if (o > 0)
-            while (a < b) {
-                int32_t mid = a + ((b - a) >> 1);
-                int dig = (int)((skeys[mid] >> shift) & 7ull);
-                if (dig < o) a = mid + 1; else b = mid;
+    const int32_t ncl = le - lb;
+    const int32_t nchunk = (ncl + kTreeChunk - 1) / kTreeChunk;
+    const int o = threadIdx.x & 7, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int32_t ci = blockIdx.x; ci < nchunk; ci += gridDim.x) {   // uniform over the workgroup
+        const int32_t j = ci * kTreeChunk + (int32_t)(threadIdx.x >> 3);
+        int mine = 0;
+        if (j < ncl) {
+            const int32_t cell = lb + j;
+            const int level_c = c.level[cell];
+            const int32_t first = c.first[cell], count = c.count[cell];
+            if (count <= ncrit || level_c >= max_level) {
+                if (o == 0) nch[j] = 0;
+            } else {   // uniform over the cell's 8 lanes
+                const int shift = 3 * (kLevels - (level_c + 1));
+                const int32_t end = first + count;
+                int32_t a = first, b = end;
+                if (o > 0)
+                    while (a < b) {
+                        int32_t mid = a + ((b - a) >> 1);
+                        int dig = (int)((skeys[mid] >> shift) & 7ull);
+                        if (dig < o) a = mid + 1; else b = mid;
+                    }
+                bounds[9 * j + o] = a;
+                if (o == 7) bounds[9 * j + 8] = end;
+                const int32_t next = __shfl_down(a, 1, 8);
+                const bool ne = (o == 7 ? end : next) > a;
+                const uint64_t m = __ballot(ne);
+                if (o == 0) {
+                    mine = __popcll((m >> (lane & ~7)) & 0xffull);
+                    nch[j] = mine;
+                }
             }
-        bounds[9 * j + o] = a;
-        if (o == 7) bounds[9 * j + 8] = end;
-        const int32_t next = __shfl_down(a, 1, 8);
-        const bool ne = (o == 7 ? end : next) > a;
-        const uint64_t m = __ballot(ne);
-        if (o == 0) nch[j] = __popcll((m >> (threadIdx.x & 63 & ~7)) & 0xffull);
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) mine += __shfl_xor(mine, d, 64);
+        if (lane == 0) wsum[w] = mine;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+#pragma unroll
+            for (int i = 0; i < kTreeCountThreads / 64; i++) t += wsum[i];
+            csum[ci] = t;
+        }
+        __syncthreads();
     }
+}
+
+// One workgroup: exclusive scan of the chunk sums in place; *total = the
+// number of cells of the next level.
+__global__ void __launch_bounds__(kChunkScanThreads) k_tree_chunk_scan(const int32_t *__restrict__ lev, int level,
+                                                                       int32_t *__restrict__ csum,
+                                                                       int32_t *__restrict__ total) {
+    constexpr int kItems = 4, kStep = kChunkScanThreads * kItems;
+    __shared__ int wsum[kChunkScanThreads / 64];
+    const int32_t ncl = lev[level + 1] - lev[level];
+    const int32_t nchunk = (ncl + kTreeChunk - 1) / kTreeChunk;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int carry = 0;
+    for (int32_t c0 = 0; c0 < nchunk; c0 += kStep) {
+        const int32_t b0 = c0 + threadIdx.x * kItems;
+        int v[kItems], sum = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            v[i] = b0 + i < nchunk ? csum[b0 + i] : 0;
+            sum += v[i];
+        }
+        int inc = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            int t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        int before = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < kChunkScanThreads / 64; i++) {
+            if (i < w) before += wsum[i];
+            tot += wsum[i];
+        }
+        int pre = carry + before + inc - sum;
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            if (b0 + i < nchunk) csum[b0 + i] = pre;
+            pre += v[i];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
 }
 
 // Children of level `level`; lev[level + 2] = end of the new level.  A tree
 // larger than cap cells stops here: the flag lev[nlev] is set, nothing is
-// written past cap, and the new level is left empty.
-__global__ void k_tree_write_dev(CellArrays c, int32_t *__restrict__ lev, int level, int nlev,
-                                 const int32_t *__restrict__ bounds, const int32_t *__restrict__ nch,
-                                 const int32_t *__restrict__ off, const int32_t *__restrict__ total, int32_t cap) {
+// written past cap, and the new level is left empty.  One thread per cell;
+// a chunk's cells sit in consecutive lanes, which scan their child counts.
+__global__ void __launch_bounds__(256) k_tree_write_dev(CellArrays c, int32_t *__restrict__ lev, int level, int nlev,
+                                                        const int32_t *__restrict__ bounds,
+                                                        const int32_t *__restrict__ nch,
+                                                        const int32_t *__restrict__ cscan,
+                                                        const int32_t *__restrict__ total, int32_t cap) {
+    static_assert(256 % kTreeChunk == 0 && kTreeChunk <= 64, "chunks must not straddle waves");
     const int32_t lb = lev[level], le = lev[level + 1];
+    const int32_t ncl = le - lb;
     const bool over = (int64_t)le + *total > cap;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         lev[level + 2] = over ? le : le + *total;
         if (over) lev[nlev] = 1;
     }
     if (over) return;
-    for (int32_t cell = lb + blockIdx.x * blockDim.x + threadIdx.x; cell < le; cell += gridDim.x * blockDim.x) {
-        const int32_t j = cell - lb;
-        if (nch[j] == 0) continue;
-        int32_t dst = le + off[j];
+    const int sub = threadIdx.x & (kTreeChunk - 1);
+    for (int32_t j0 = blockIdx.x * 256; j0 < ncl; j0 += gridDim.x * 256) {
+        const int32_t j = j0 + (int32_t)threadIdx.x;
+        const int v = j < ncl ? nch[j] : 0;
+        int inc = v;
+#pragma unroll
+        for (int d = 1; d < kTreeChunk; d <<= 1) {
+            int t = __shfl_up(inc, d, kTreeChunk);
+            if (sub >= d) inc += t;
+        }
+        if (v == 0) continue;
+        const int32_t cell = lb + j;
+        int32_t dst = le + cscan[j / kTreeChunk] + inc - v;
         c.child[cell] = dst;
-        c.nchild[cell] = nch[j];
+        c.nchild[cell] = v;
         const int lv = c.level[cell] + 1;
         const int32_t px = c.ix[cell], py = c.iy[cell], pz = c.iz[cell], inst = c.inst[cell];
         for (int o = 0; o < 8; o++) {
@@ -415,15 +505,16 @@ void launch_tree_levels_init(int32_t *lev, int n_inst, int nlev, hipStream_t s) 
 }
 
 void launch_tree_level_dev(CellArrays c, int32_t *lev, int level, int nlev, int ncrit, int max_level,
-                           const uint64_t *skeys, int32_t *bounds, int32_t *nch, int32_t *off, int32_t *total,
-                           int32_t cap, int32_t *scan_tmp, hipStream_t s) {
-    const int grid = grid_for((int64_t)cap * 8, 128, 4096);
-    hipLaunchKernelGGL(k_tree_count_dev, dim3(grid), dim3(128), 0, s, c, lev, level, ncrit, max_level, skeys, bounds,
-                       nch);
+                           const uint64_t *skeys, int32_t *bounds, int32_t *nch, int32_t *csum, int32_t *total,
+                           int32_t cap, hipStream_t s) {
+    const int64_t nchunk_max = ((int64_t)cap + kTreeChunk - 1) / kTreeChunk;
+    hipLaunchKernelGGL(k_tree_count_dev, dim3(grid_for(nchunk_max, 1, 4096)), dim3(kTreeCountThreads), 0, s, c, lev,
+                       level, ncrit, max_level, skeys, bounds, nch, csum);
     FMM_LAUNCH_CHECK();
-    exclusive_scan_dev(nch, off, lev + level, cap, total, scan_tmp, s);
-    hipLaunchKernelGGL(k_tree_write_dev, dim3(grid_for(cap, 128, 4096)), dim3(128), 0, s, c, lev, level, nlev, bounds,
-                       nch, off, total, cap);
+    hipLaunchKernelGGL(k_tree_chunk_scan, dim3(1), dim3(kChunkScanThreads), 0, s, lev, level, csum, total);
+    FMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_tree_write_dev, dim3(grid_for(cap, 256, 4096)), dim3(256), 0, s, c, lev, level, nlev, bounds,
+                       nch, csum, total, cap);
     FMM_LAUNCH_CHECK();
 }
 
