@@ -9,32 +9,35 @@ constexpr int kRhoMax = 24;                                  // |rho_i| covered 
 constexpr int kRhoSpan = 2 * kRhoMax + 1;
 constexpr int kDenseKeys = 3 * kRhoSpan * kRhoSpan * kRhoSpan;  // delta in {-1, 0, 1}
 
-// Dense class key of every pair (-1 outside the table), used keys marked,
-// xcount[A] = the owner's pairs outside the table.
-void m2l_dense_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *src, int32_t *pkey,
-                    int32_t *used, int32_t *xcount, hipStream_t s);
-void m2l_alloc_slots(const int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, hipStream_t s);
+// Class code of every pair: its operator slot (>= 0), -1 outside the dense
+// table, -2 - key for a class that has no slot yet (its key is marked in
+// used); xcount[A] = the owner's pairs outside the table.
+void m2l_pair_codes(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *src, const int32_t *slot_of,
+                    int32_t *pcode, int32_t *used, int32_t *xcount, hipStream_t s);
+// Slots for the marked keys (nslots[0] = slots in use, new_keys[0 ..
+// nslots[1]) = the keys given one now); clears the marks.
+void m2l_alloc_slots(int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, hipStream_t s);
 // Split-bf16 operator blocks of the new classes (op_elems bf16 per class,
 // RT row tiles, layout as the work queue reads it).  transposed: the keys
 // come from transposed pairs (owner = forward source) and each block holds
 // the transpose of the forward pair's operator.
 void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int64_t op_elems,
                    bool transposed, uint16_t *ops, hipStream_t s);
-void m2l_cid_tables(const int32_t *used_scan, const int32_t *used, const int32_t *slot_of, int32_t *cid_of,
-                    int32_t *slot_of_cid, hipStream_t s);
-void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int32_t *pcid, hipStream_t s);
 // Sort keys (level, eighth, octant, cell) of the cells with table pairs;
 // xptr = exclusive scan of the per-owner counts of pairs outside the table.
 void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *xptr, uint64_t *tkey,
                      int32_t *has, hipStream_t s);
-// Entries of the target groups: count (class bitmap per group in
-// gbits, ngroup x ceil(ncid/32) words, and word prefixes in gwpre), then
-// fill (after goff = exclusive scan of gcount).
-void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcid, int32_t ncid,
-                     uint32_t *gbits, uint32_t *gwpre, int32_t *gcount, hipStream_t s);
+// Entries of the target groups, one per distinct operator slot: count
+// (slot bitmap per group in gbits, ngroup x ceil(nslot/32) words, and word
+// prefixes in gwpre), then fill (after goff = exclusive scan of gcount);
+// ecls[entry] = the entry's operator slot.
+void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcode,
+                     const int32_t *slot_of, int32_t nslot, uint32_t *gbits, uint32_t *gwpre, int32_t *gcount,
+                     hipStream_t s);
 void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
-                    const int32_t *pcid, int32_t ncid, const uint32_t *gbits, const uint32_t *gwpre,
-                    const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget, hipStream_t s);
+                    const int32_t *pcode, const int32_t *slot_of, int32_t nslot, const uint32_t *gbits,
+                    const uint32_t *gwpre, const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget,
+                    hipStream_t s);
 void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *tcount, hipStream_t s);
 // M2L tasks ordered by (XCD, chunk index, task); xcd_count[x] = tasks of XCD x.
 // max_entries bounds the entries of a group (it sizes the chunk-index bits).
@@ -44,7 +47,7 @@ void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, 
                     uint64_t *tkeys_alt, uint32_t *tidx, uint32_t *tidx_alt, int32_t *xcd_count, int32_t *tmp,
                     hipStream_t s);
 // The pairs outside the table as a CSR list (xptr, xsrc), in list order.
-void m2l_extra(const int32_t *ptr, int32_t ncell, const int32_t *src, const int32_t *pkey, const int32_t *xptr,
+void m2l_extra(const int32_t *ptr, int32_t ncell, const int32_t *src, const int32_t *pcode, const int32_t *xptr,
                int32_t *xsrc, hipStream_t s);
 
 // ---- p2p_fp32.hip (preparation of the P2P tasks)

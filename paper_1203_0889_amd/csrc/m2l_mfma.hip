@@ -16,9 +16,10 @@
 //
 // Batching: targets are grouped 256 at a time (same level and octant,
 // Morton order, so neighbouring targets share their class sets).  A group's
-// entries are its distinct classes in class order, each with the source
-// cell of every target slot (-1 if absent).  The work queue applies each
-// entry's T_c to the gathered multipoles on the matrix cores.
+// entries are its distinct classes in the order of their operator slots,
+// each with the source cell of every target slot (-1 if absent).  The work
+// queue applies each entry's T_c to the gathered multipoles on the matrix
+// cores.
 #include "m2l_mfma.h"
 #include "queue.h"
 
@@ -41,13 +42,15 @@ __device__ inline int dense_key(int delta, int rx, int ry, int rz) {
     return (((delta + 1) * kRhoSpan + (rx + kRhoMax)) * kRhoSpan + (ry + kRhoMax)) * kRhoSpan + (rz + kRhoMax);
 }
 
-// Class key of every M2L pair in CSR order (one wave per owner cell);
-// marks used dense keys (read first: nearly every key is already marked, and
-// a read leaves the cache line shared) and counts the owner's pairs outside
-// the table in xcount[A].
+// Class code of every M2L pair in CSR order (one wave per owner cell): the
+// operator slot of its class (>= 0), -1 for a pair outside the dense table,
+// or -2 - key for a class without a slot yet, whose key is then marked in
+// `used` (read first: a read leaves the cache line shared) for the slot
+// allocation; such codes are resolved through slot_of afterwards.  xcount[A]
+// counts the owner's pairs outside the table.
 __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr,
-                               const int32_t *__restrict__ src, int32_t *__restrict__ pkey,
-                               int32_t *__restrict__ used, int32_t *__restrict__ xcount) {
+                               const int32_t *__restrict__ src, const int32_t *__restrict__ slot_of,
+                               int32_t *__restrict__ pcode, int32_t *__restrict__ used, int32_t *__restrict__ xcount) {
     for (int32_t A = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; A < ncell; A += gridDim.x * blockDim.x / 64) {
         int nx = 0;
         const int4 ra = c.rec[A];
@@ -66,13 +69,18 @@ __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__res
             int rx = (int)((ca[0] - (2 * (int64_t)rec_ix(rb) + 1) * SB) >> sh);
             int ry = (int)((ca[1] - (2 * (int64_t)rec_iy(rb) + 1) * SB) >> sh);
             int rz = (int)((ca[2] - (2 * (int64_t)rec_iz(rb) + 1) * SB) >> sh);
-            int k = dense_key(la - lb, rx, ry, rz);
-            pkey[e] = k;
+            const int k = dense_key(la - lb, rx, ry, rz);
+            int code = -1;
             if (k >= 0) {
-                if (!used[k]) used[k] = 1;
+                code = slot_of[k];
+                if (code < 0) {
+                    code = -2 - k;
+                    if (!used[k]) used[k] = 1;
+                }
             } else {
                 nx++;
             }
+            pcode[e] = code;
         }
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) nx += __shfl_xor(nx, d, 64);
@@ -80,17 +88,25 @@ __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__res
     }
 }
 
-// New dense keys get a slot in the operator store.
-__global__ void k_alloc_slots(const int32_t *__restrict__ used, int32_t nkeys, int32_t *__restrict__ slot_of,
+// Marked dense keys get a slot in the operator store; the marks are
+// cleared for the next build.
+__global__ void k_alloc_slots(int32_t *__restrict__ used, int32_t nkeys, int32_t *__restrict__ slot_of,
                               int32_t *__restrict__ nslots, int32_t *__restrict__ new_keys) {
     for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nkeys; k += gridDim.x * blockDim.x) {
-        if (used[k] && slot_of[k] < 0) {
+        if (!used[k]) continue;
+        used[k] = 0;
+        if (slot_of[k] < 0) {
             int32_t s = atomicAdd(&nslots[0], 1);
             slot_of[k] = s;
             int32_t j = atomicAdd(&nslots[1], 1);
             new_keys[j] = k;
         }
     }
+}
+
+// operator slot of a pair code (-1: outside the table)
+__device__ inline int32_t code_slot(int32_t code, const int32_t *__restrict__ slot_of) {
+    return code < -1 ? slot_of[-2 - code] : code;
 }
 
 // Build the FP32 operator fragments of each new class: one workgroup per
@@ -219,27 +235,6 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
     }
 }
 
-// Compact id of a pair's class (rank of its dense key among used keys).
-__global__ void k_pair_cid(const int32_t *__restrict__ pkey, int64_t npair, const int32_t *__restrict__ cid_of,
-                           int32_t *__restrict__ pcid) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npair; e += (int64_t)gridDim.x * blockDim.x) {
-        int k = pkey[e];
-        pcid[e] = k >= 0 ? cid_of[k] : -1;
-    }
-}
-
-__global__ void k_cid_tables(const int32_t *__restrict__ used_scan, const int32_t *__restrict__ used, int32_t nkeys,
-                             const int32_t *__restrict__ slot_of, int32_t *__restrict__ cid_of,
-                             int32_t *__restrict__ slot_of_cid) {
-    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nkeys; k += gridDim.x * blockDim.x) {
-        if (used[k]) {
-            int32_t c = used_scan[k];
-            cid_of[k] = c;
-            slot_of_cid[c] = slot_of[k];
-        }
-    }
-}
-
 // Sort key of every cell that has batched M2L pairs: (level, spatial eighth
 // of the particle order, octant, cell).  The eighth (bits 35..37) later
 // selects the XCD whose task list the group joins.
@@ -309,8 +304,9 @@ __device__ inline void load_group(const uint64_t *__restrict__ tsorted, int32_t 
 }
 
 __global__ void __launch_bounds__(256) k_group_mark(const uint64_t *__restrict__ tsorted, int32_t ntarget,
-                                                    const int32_t *__restrict__ ptr, const int32_t *__restrict__ pcid,
-                                                    int nwords, uint32_t *__restrict__ gbits) {
+                                                    const int32_t *__restrict__ ptr, const int32_t *__restrict__ pcode,
+                                                    const int32_t *__restrict__ slot_of, int nwords,
+                                                    uint32_t *__restrict__ gbits) {
     extern __shared__ uint32_t lbits[];
     __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L], fst[kGroupM2L];
     int g, split;
@@ -322,7 +318,7 @@ __global__ void __launch_bounds__(256) k_group_mark(const uint64_t *__restrict__
     const int32_t total = pre[nt];
     for (int32_t idx = split * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
         int s = slot_of_index(pre, nt, idx);
-        int32_t cid = pcid[fst[s] + (idx - pre[s])];
+        const int32_t cid = code_slot(pcode[fst[s] + (idx - pre[s])], slot_of);
         if (cid >= 0) atomicOr(&lbits[cid >> 5], 1u << (cid & 31));
     }
     __syncthreads();
@@ -366,7 +362,8 @@ __global__ void __launch_bounds__(256) k_group_prefix(int nwords, const uint32_t
 template <bool kLds>
 __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__ tsorted, int32_t ntarget,
                                                     const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
-                                                    const int32_t *__restrict__ pcid, int nwords,
+                                                    const int32_t *__restrict__ pcode,
+                                                    const int32_t *__restrict__ slot_of, int nwords,
                                                     const uint32_t *__restrict__ gbits,
                                                     const uint32_t *__restrict__ gwpre,
                                                     const int32_t *__restrict__ goff, int32_t *__restrict__ ecls,
@@ -404,7 +401,7 @@ __global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__
     for (int32_t idx = split * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
         int s = slot_of_index(pre, nt, idx);
         int32_t e = fst[s] + (idx - pre[s]);
-        int32_t cid = pcid[e];
+        const int32_t cid = code_slot(pcode[e], slot_of);
         if (cid < 0) continue;
         uint32_t wv = bits[cid >> 5] & ((1u << (cid & 31)) - 1u);
         int32_t ent = base + (int32_t)wpre[cid >> 5] + __popc(wv);
@@ -449,7 +446,7 @@ __global__ void k_task_counts(const int32_t *__restrict__ gcount, int32_t ngroup
 // The pairs outside the class table, per owner in list order: one wave per
 // owner, a ballot and prefix count place each flagged pair at xptr[A] + rank.
 __global__ void k_compact_extra(const int32_t *__restrict__ ptr, int32_t ncell, const int32_t *__restrict__ src,
-                                const int32_t *__restrict__ pkey, const int32_t *__restrict__ xptr,
+                                const int32_t *__restrict__ pcode, const int32_t *__restrict__ xptr,
                                 int32_t *__restrict__ xsrc) {
     const int lane = threadIdx.x & 63;
     for (int32_t A = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; A < ncell; A += gridDim.x * blockDim.x / 64) {
@@ -457,7 +454,7 @@ __global__ void k_compact_extra(const int32_t *__restrict__ ptr, int32_t ncell, 
         int32_t base = xptr[A];
         for (int32_t e0 = ptr[A]; e0 < ptr[A + 1]; e0 += 64) {
             const int32_t e = e0 + lane;
-            const bool x = e < ptr[A + 1] && pkey[e] < 0;
+            const bool x = e < ptr[A + 1] && pcode[e] == -1;
             const unsigned long long m = __ballot(x);
             if (x) xsrc[base + __popcll(m & ((1ull << lane) - 1ull))] = src[e];
             base += __popcll(m);
@@ -467,14 +464,14 @@ __global__ void k_compact_extra(const int32_t *__restrict__ ptr, int32_t ncell, 
 
 }  // namespace
 
-void m2l_dense_keys(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *src, int32_t *pkey,
-                    int32_t *used, int32_t *xcount, hipStream_t s) {
+void m2l_pair_codes(CellArrays c, int32_t ncell, const int32_t *ptr, const int32_t *src, const int32_t *slot_of,
+                    int32_t *pcode, int32_t *used, int32_t *xcount, hipStream_t s) {
     hipLaunchKernelGGL(k_pair_classes, dim3(grid_for((int64_t)ncell * 64, 256, 16384)), dim3(256), 0, s, c, ncell, ptr,
-                       src, pkey, used, xcount);
+                       src, slot_of, pcode, used, xcount);
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_alloc_slots(const int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, hipStream_t s) {
+void m2l_alloc_slots(int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, hipStream_t s) {
     hipLaunchKernelGGL(k_alloc_slots, dim3(grid_for(kDenseKeys, 256, 4096)), dim3(256), 0, s, used, kDenseKeys, slot_of,
                        nslots, new_keys);
     FMM_LAUNCH_CHECK();
@@ -488,19 +485,6 @@ void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_cid_tables(const int32_t *used_scan, const int32_t *used, const int32_t *slot_of, int32_t *cid_of,
-                    int32_t *slot_of_cid, hipStream_t s) {
-    hipLaunchKernelGGL(k_cid_tables, dim3(grid_for(kDenseKeys, 256, 4096)), dim3(256), 0, s, used_scan, used, kDenseKeys,
-                       slot_of, cid_of, slot_of_cid);
-    FMM_LAUNCH_CHECK();
-}
-
-void m2l_pair_cid(const int32_t *pkey, int64_t npair, const int32_t *cid_of, int32_t *pcid, hipStream_t s) {
-    if (npair <= 0) return;
-    hipLaunchKernelGGL(k_pair_cid, dim3(grid_for(npair, 256, 16384)), dim3(256), 0, s, pkey, npair, cid_of, pcid);
-    FMM_LAUNCH_CHECK();
-}
-
 void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *xptr, uint64_t *tkey,
                      int32_t *has, hipStream_t s) {
     hipLaunchKernelGGL(k_target_keys, dim3(grid_for(ncell, 256, 4096)), dim3(256), 0, s, c, ncell, n, ptr, xptr, tkey,
@@ -508,33 +492,35 @@ void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr,
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcid, int32_t ncid,
-                     uint32_t *gbits, uint32_t *gwpre, int32_t *gcount, hipStream_t s) {
+void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcode,
+                     const int32_t *slot_of, int32_t nslot, uint32_t *gbits, uint32_t *gwpre, int32_t *gcount,
+                     hipStream_t s) {
     const int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
     if (ngroup <= 0) return;
-    const int nwords = (ncid + 31) / 32;
+    const int nwords = (nslot + 31) / 32;
     FMM_HIP_CHECK(hipMemsetAsync(gbits, 0, (size_t)ngroup * nwords * 4, s));
     if ((size_t)nwords * 4 > 48 * 1024) throw std::runtime_error("too many M2L classes for the group builder");
     hipLaunchKernelGGL(k_group_mark, dim3(group_blocks(ngroup)), dim3(256), (size_t)nwords * 4, s, tsorted, ntarget,
-                       ptr, pcid, nwords, gbits);
+                       ptr, pcode, slot_of, nwords, gbits);
     FMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_group_prefix, dim3(ngroup), dim3(256), 0, s, nwords, gbits, gwpre, gcount);
     FMM_LAUNCH_CHECK();
 }
 
 void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
-                    const int32_t *pcid, int32_t ncid, const uint32_t *gbits, const uint32_t *gwpre,
-                    const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget, hipStream_t s) {
+                    const int32_t *pcode, const int32_t *slot_of, int32_t nslot, const uint32_t *gbits,
+                    const uint32_t *gwpre, const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget,
+                    hipStream_t s) {
     const int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
     if (ngroup <= 0) return;
-    const int nwords = (ncid + 31) / 32;
+    const int nwords = (nslot + 31) / 32;
     const size_t tab = (size_t)2 * nwords * 4;
     if (tab <= 32768)
         hipLaunchKernelGGL(k_group_fill<true>, dim3(group_blocks(ngroup)), dim3(256), tab, s, tsorted, ntarget, ptr,
-                           src, pcid, nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
+                           src, pcode, slot_of, nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
     else
         hipLaunchKernelGGL(k_group_fill<false>, dim3(group_blocks(ngroup)), dim3(256), 0, s, tsorted, ntarget, ptr, src,
-                           pcid, nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
+                           pcode, slot_of, nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
     FMM_LAUNCH_CHECK();
 }
 
@@ -561,11 +547,11 @@ void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, 
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_extra(const int32_t *ptr, int32_t ncell, const int32_t *src, const int32_t *pkey, const int32_t *xptr,
+void m2l_extra(const int32_t *ptr, int32_t ncell, const int32_t *src, const int32_t *pcode, const int32_t *xptr,
                int32_t *xsrc, hipStream_t s) {
     if (ncell <= 0) return;
     hipLaunchKernelGGL(k_compact_extra, dim3(grid_for((int64_t)ncell * 64, 256, 16384)), dim3(256), 0, s, ptr, ncell, src,
-                       pkey, xptr, xsrc);
+                       pcode, xptr, xsrc);
     FMM_LAUNCH_CHECK();
 }
 

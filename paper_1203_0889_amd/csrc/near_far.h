@@ -33,15 +33,15 @@ struct NearFarArgs {
 // Device workspaces of this stage, owned by the plan.  The class operator
 // store (slot_of, frags) persists across builds of the same plan.
 struct NearFarState {
-    DevBuf used, slot_of, nslots, new_keys, frags, used_scan, cid_of, slot_of_cid;
-    DevBuf pkey, pcid, xcount, tkey, tkey_alt, has, gcount, goff, tcount, toff;
+    DevBuf used, slot_of, nslots, new_keys, frags;
+    DevBuf pcode, xcount, tkey, tkey_alt, has, gcount, goff, tcount, toff;
     DevBuf ecls, esrc, gtarget, tasks, xsrc, xptr, leafbuf, leaves, pf, M32, tmp, cnt, centre, gbits, gwpre;
     DevBuf tasks_alt, tkeys, tidx, lists, tmp2;
     // stream and events of the P2P side kernel (created on first use)
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     int p = -1;
-    int32_t nslot_total = 0, ncid = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0;
+    int32_t nslot_total = 0, nslot = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0;
     bool built = false;
 };
 

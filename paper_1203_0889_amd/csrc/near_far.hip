@@ -61,43 +61,35 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     const int64_t op_elems = queue_op_elems(p);
     const int32_t ncell = a.ncell;
     const int64_t npair = a.nm2l;
-    // ---- persistent class tables
+    // ---- persistent class tables (slot_of, the operator store, and the
+    // key marks, which the slot allocation clears after each build)
     if (st.p != p) {
         FMM_HIP_CHECK(st.slot_of.grow(kDenseKeys * 4));
         FMM_HIP_CHECK(hipMemsetAsync(st.slot_of.ptr, 0xff, kDenseKeys * 4, s));
         FMM_HIP_CHECK(st.nslots.grow(2 * 4));
         FMM_HIP_CHECK(hipMemsetAsync(st.nslots.ptr, 0, 2 * 4, s));
+        FMM_HIP_CHECK(st.used.grow(kDenseKeys * 4));
+        FMM_HIP_CHECK(hipMemsetAsync(st.used.ptr, 0, kDenseKeys * 4, s));
         st.nslot_total = 0;
         st.p = p;
     }
-    FMM_HIP_CHECK(st.used.grow(kDenseKeys * 4));
     FMM_HIP_CHECK(st.new_keys.grow(kDenseKeys * 4));
-    FMM_HIP_CHECK(st.used_scan.grow((kDenseKeys + 1) * 4));
-    FMM_HIP_CHECK(st.cid_of.grow(kDenseKeys * 4));
-    FMM_HIP_CHECK(st.slot_of_cid.grow(kDenseKeys * 4));
     const size_t np1 = (size_t)std::max<int64_t>(npair, 1) + 1;
-    FMM_HIP_CHECK(st.pkey.grow(np1 * 4));
-    FMM_HIP_CHECK(st.pcid.grow(np1 * 4));
+    FMM_HIP_CHECK(st.pcode.grow(np1 * 4));
     FMM_HIP_CHECK(st.xcount.grow(((size_t)ncell + 1) * 4));   // per-owner counts of pairs outside the table
     FMM_HIP_CHECK(st.xptr.grow(((size_t)ncell + 1) * 4));
     FMM_HIP_CHECK(st.cnt.grow(64 * 4));  // [0..4] sizes, [16..32] per-XCD counts, [40..55] queue heads
-    int64_t tmp_elems = std::max<int64_t>({(int64_t)scan_tmp_elems(kDenseKeys + 1), (int64_t)scan_tmp_elems(np1),
-                                           (int64_t)radix_tmp_elems(ncell + 1), (int64_t)scan_tmp_elems(ncell + 1)});
+    int64_t tmp_elems = std::max<int64_t>({(int64_t)scan_tmp_elems(np1), (int64_t)radix_tmp_elems(ncell + 1),
+                                           (int64_t)scan_tmp_elems(ncell + 1)});
     FMM_HIP_CHECK(st.tmp.grow(tmp_elems * 4));
     int32_t *cnt = st.cnt.as<int32_t>();
 
-    FMM_HIP_CHECK(hipMemsetAsync(st.used.ptr, 0, kDenseKeys * 4, s));
-    m2l_dense_keys(a.g.c, ncell, a.m2l_ptr, a.m2l_src, st.pkey.as<int32_t>(), st.used.as<int32_t>(),
-                   st.xcount.as<int32_t>(), s);
+    m2l_pair_codes(a.g.c, ncell, a.m2l_ptr, a.m2l_src, st.slot_of.as<int32_t>(), st.pcode.as<int32_t>(),
+                   st.used.as<int32_t>(), st.xcount.as<int32_t>(), s);
     FMM_HIP_CHECK(hipMemsetAsync(st.nslots.as<int32_t>() + 1, 0, 4, s));
     m2l_alloc_slots(st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.nslots.as<int32_t>(), st.new_keys.as<int32_t>(), s);
     // slot counts next to the sizes below: one read for all of them
     FMM_HIP_CHECK(hipMemcpyAsync(cnt + 5, st.nslots.ptr, 8, hipMemcpyDeviceToDevice, s));
-    // compact class ids in dense-key order
-    exclusive_scan_oop(st.used.as<int32_t>(), st.used_scan.as<int32_t>(), kDenseKeys, cnt + 0, st.tmp.as<int32_t>(), s);
-    m2l_cid_tables(st.used_scan.as<int32_t>(), st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.cid_of.as<int32_t>(),
-                   st.slot_of_cid.as<int32_t>(), s);
-    m2l_pair_cid(st.pkey.as<int32_t>(), npair, st.cid_of.as<int32_t>(), st.pcid.as<int32_t>(), s);
     // CSR offsets of the pairs left to the per-pair kernel; xptr[ncell] (and
     // cnt[1]) = their number
     exclusive_scan_oop(st.xcount.as<int32_t>(), st.xptr.as<int32_t>(), ncell, st.xptr.as<int32_t>() + ncell,
@@ -133,7 +125,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                       st.frags.as<uint16_t>(), s);
         st.nslot_total = h7[5];
     }
-    st.ncid = h7[0];
+    st.nslot = h7[5];
     st.nextra = h7[1];
     st.ntarget = h7[2];
     st.ngroup = (st.ntarget + kGroupM2L - 1) / kGroupM2L;
@@ -144,11 +136,11 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.toff.grow((size_t)(ng + 1) * 4));
     FMM_HIP_CHECK(st.gtarget.grow((size_t)ng * kGroupM2L * 4));
     FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, scan_tmp_elems(ng + 1) * 4)));
-    const size_t gwords = (size_t)ng * ((st.ncid + 31) / 32 + 1);
+    const size_t gwords = (size_t)ng * ((st.nslot + 31) / 32 + 1);
     FMM_HIP_CHECK(st.gbits.grow(gwords * 4));
     FMM_HIP_CHECK(st.gwpre.grow(gwords * 4));
-    m2l_group_count(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, st.pcid.as<int32_t>(), st.ncid,
-                    st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.gcount.as<int32_t>(), s);
+    m2l_group_count(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, st.pcode.as<int32_t>(), st.slot_of.as<int32_t>(),
+                    st.nslot, st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.gcount.as<int32_t>(), s);
     exclusive_scan_oop(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, cnt + 3, st.tmp.as<int32_t>(), s);
     const int chunk = std::max(1, std::min(kMaxTaskEntries, a.tuning.m2l_task_entries));
     m2l_task_counts(st.gcount.as<int32_t>(), st.ngroup, chunk, st.tcount.as<int32_t>(), s);
@@ -157,7 +149,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     // while the host waits: the pairs left to the per-pair kernel
     // (|delta| >= 2 or far displacement), whose number is known
     FMM_HIP_CHECK(st.xsrc.grow((size_t)std::max(st.nextra, 1) * 4));
-    m2l_extra(a.m2l_ptr, ncell, a.m2l_src, st.pkey.as<int32_t>(), st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), s);
+    m2l_extra(a.m2l_ptr, ncell, a.m2l_src, st.pcode.as<int32_t>(), st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), s);
     int32_t h2[2];
     rd.end(h2, s);
     st.nentries = st.ngroup > 0 ? h2[0] : 0;
@@ -172,10 +164,10 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, radix_tmp_elems(nt1) * 4)));
     if (st.nentries > 0)
         FMM_HIP_CHECK(hipMemsetAsync(st.esrc.ptr, 0xff, (size_t)st.nentries * kGroupM2L * 4, s));
-    m2l_group_fill(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcid.as<int32_t>(), st.ncid,
-                   st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(),
+    m2l_group_fill(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcode.as<int32_t>(),
+                   st.slot_of.as<int32_t>(), st.nslot, st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(),
                    st.esrc.as<int32_t>(), st.gtarget.as<int32_t>(), s);
-    m2l_make_tasks(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, chunk, std::max(st.ncid, 1),
+    m2l_make_tasks(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, chunk, std::max(st.nslot, 1),
                    st.toff.as<int32_t>(),
                    st.tkey.as<uint64_t>(), st.ntask, st.tasks.as<int4>(), st.tasks_alt.as<int4>(),
                    st.tkeys.as<uint64_t>(), st.tkeys.as<uint64_t>() + nt1, st.tidx.as<uint32_t>(),
@@ -214,7 +206,6 @@ void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     q.gtarget = st.gtarget.as<int32_t>();
     q.ecls = st.ecls.as<int32_t>();
     q.esrc = st.esrc.as<int32_t>();
-    q.slot_of_cid = st.slot_of_cid.as<int32_t>();
     q.ops = st.frags.as<uint16_t>();
     q.Mb = st.M32.as<uint16_t>();
     q.zero_row = ncell;
@@ -256,9 +247,8 @@ void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
 }
 
 void release_near_far(NearFarState &st) {
-    DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.used_scan, &st.cid_of,
-                     &st.slot_of_cid, &st.pkey, &st.pcid, &st.xcount, &st.tkey, &st.tkey_alt, &st.has,
-                     &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
+    DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.pcode, &st.xcount, &st.tkey,
+                     &st.tkey_alt, &st.has, &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
                      &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists, &st.tmp2};
     for (DevBuf *b : all) b->release();
     if (st.side) {

@@ -15,9 +15,8 @@ struct QueueArgs {
     // M2L
     const int4 *m2l_tasks;     // (group, entry begin, entry end, 0)
     const int32_t *gtarget;    // group x kGroupM2L target cells (-1 = empty slot)
-    const int32_t *ecls;       // entry -> compact class id
+    const int32_t *ecls;       // entry -> operator slot of its class
     const int32_t *esrc;       // entry x kGroupM2L source cells (-1 = absent)
-    const int32_t *slot_of_cid;
     const uint16_t *ops;       // class operators, split bf16 MFMA blocks (queue_op_elems per class)
     const uint16_t *Mb;        // multipoles, split bf16 rows (queue_mrow_elems per cell),
                                //   plus one all-zero row at index zero_row

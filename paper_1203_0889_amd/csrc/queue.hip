@@ -292,8 +292,8 @@ __device__ void m2l_group(const QueueArgs &a, int4 task, int w, int lane, v4f *r
     const int32_t *gsrc = a.esrc + w * 64 + col;
     const int32_t e0 = task.y, ne = task.z - task.y;   // workgroup-uniform
     int32_t slot_lo = 0, slot_hi = 0;
-    if (lane < ne) slot_lo = a.slot_of_cid[a.ecls[e0 + lane]];
-    if (64 + lane < ne) slot_hi = a.slot_of_cid[a.ecls[e0 + 64 + lane]];
+    if (lane < ne) slot_lo = a.ecls[e0 + lane];
+    if (64 + lane < ne) slot_hi = a.ecls[e0 + 64 + lane];
     auto slot = [&](int i) {
         return i < 64 ? __builtin_amdgcn_readlane(slot_lo, i) : __builtin_amdgcn_readlane(slot_hi, i - 64);
     };
