@@ -30,14 +30,15 @@ void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr,
 // Entries of the target groups, one per distinct operator slot: count
 // (slot bitmap per group in gbits, ngroup x ceil(nslot/32) words, and word
 // prefixes in gwpre), then fill (after goff = exclusive scan of gcount);
-// ecls[entry] = the entry's operator slot.
+// ecls[entry] = the entry's operator slot, esrc[entry][slot] its sources
+// (every element written, -1 where the target has no pair of the class).
 void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcode,
                      const int32_t *slot_of, int32_t nslot, uint32_t *gbits, uint32_t *gwpre, int32_t *gcount,
                      hipStream_t s);
 void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
                     const int32_t *pcode, const int32_t *slot_of, int32_t nslot, const uint32_t *gbits,
-                    const uint32_t *gwpre, const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget,
-                    hipStream_t s);
+                    const uint32_t *gwpre, const int32_t *goff, const int32_t *gcount, int32_t *ecls, int32_t *esrc,
+                    int32_t *gtarget, hipStream_t s);
 void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *tcount, hipStream_t s);
 // M2L tasks ordered by (XCD, chunk index, task); xcd_count[x] = tasks of XCD x.
 // max_entries bounds the entries of a group (it sizes the chunk-index bits).

@@ -51,6 +51,8 @@ __device__ inline int dense_key(int delta, int rx, int ry, int rz) {
 __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr,
                                const int32_t *__restrict__ src, const int32_t *__restrict__ slot_of,
                                int32_t *__restrict__ pcode, int32_t *__restrict__ used, int32_t *__restrict__ xcount) {
+    constexpr int U = 4;   // rounds of 64 pairs whose loads are issued together
+    const int lane = threadIdx.x & 63;
     for (int32_t A = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; A < ncell; A += gridDim.x * blockDim.x / 64) {
         int nx = 0;
         const int4 ra = c.rec[A];
@@ -58,33 +60,42 @@ __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__res
         const int64_t SA = (int64_t)1 << (kLevels - la);
         const int64_t ca[3] = {(2 * (int64_t)rec_ix(ra) + 1) * SA, (2 * (int64_t)rec_iy(ra) + 1) * SA,
                                (2 * (int64_t)rec_iz(ra) + 1) * SA};
-        for (int32_t e = ptr[A] + (threadIdx.x & 63); e < ptr[A + 1]; e += 64) {
-            int32_t B = src[e];
-            const int4 rb = c.rec[B];
-            const int lb = rec_level(rb);
-            const int64_t SB = (int64_t)1 << (kLevels - lb);
-            // both centres are multiples of the smaller half-size 2^sh: the
-            // division by it is an exact arithmetic shift
-            const int sh = kLevels - (la > lb ? la : lb);
-            int rx = (int)((ca[0] - (2 * (int64_t)rec_ix(rb) + 1) * SB) >> sh);
-            int ry = (int)((ca[1] - (2 * (int64_t)rec_iy(rb) + 1) * SB) >> sh);
-            int rz = (int)((ca[2] - (2 * (int64_t)rec_iz(rb) + 1) * SB) >> sh);
-            const int k = dense_key(la - lb, rx, ry, rz);
-            int code = -1;
-            if (k >= 0) {
-                code = slot_of[k];
-                if (code < 0) {
-                    code = -2 - k;
-                    if (!used[k]) used[k] = 1;
+        const int32_t end = ptr[A + 1];
+        for (int32_t e0 = ptr[A] + lane; e0 < end; e0 += 64 * U) {
+            int32_t B[U];
+            int4 rb[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) B[u] = e0 + 64 * u < end ? src[e0 + 64 * u] : -1;
+#pragma unroll
+            for (int u = 0; u < U; u++) rb[u] = c.rec[B[u] >= 0 ? B[u] : A];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                if (B[u] < 0) continue;
+                const int lb = rec_level(rb[u]);
+                const int64_t SB = (int64_t)1 << (kLevels - lb);
+                // both centres are multiples of the smaller half-size 2^sh:
+                // the division by it is an exact arithmetic shift
+                const int sh = kLevels - (la > lb ? la : lb);
+                const int rx = (int)((ca[0] - (2 * (int64_t)rec_ix(rb[u]) + 1) * SB) >> sh);
+                const int ry = (int)((ca[1] - (2 * (int64_t)rec_iy(rb[u]) + 1) * SB) >> sh);
+                const int rz = (int)((ca[2] - (2 * (int64_t)rec_iz(rb[u]) + 1) * SB) >> sh);
+                const int k = dense_key(la - lb, rx, ry, rz);
+                int code = -1;
+                if (k >= 0) {
+                    code = slot_of[k];
+                    if (code < 0) {
+                        code = -2 - k;
+                        if (!used[k]) used[k] = 1;
+                    }
+                } else {
+                    nx++;
                 }
-            } else {
-                nx++;
+                pcode[e0 + 64 * u] = code;
             }
-            pcode[e] = code;
         }
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) nx += __shfl_xor(nx, d, 64);
-        if ((threadIdx.x & 63) == 0) xcount[A] = nx;
+        if (lane == 0) xcount[A] = nx;
     }
 }
 
@@ -256,71 +267,77 @@ __global__ void k_target_keys(CellArrays c, int32_t ncell, int64_t n, const int3
 // group:  (1) mark the classes of the group's pairs in a global bitmap,
 // (2) per group, exclusive popcount prefix over its bitmap words (entry
 // rank of every class), (3) write every pair's source into its entry slot.
+// In (1) each wave walks the pair lists of whole targets (target slots
+// split, split + kSplit, ... go to the waves of the split's workgroup in
+// turn).  In (3), spread over kFillSplit workgroups per group, workgroup
+// `split` owns 8 consecutive target slots: 32 bytes of every entry row.
+// It places its targets' sources in an LDS tile of entry rows and writes
+// the tile out row by row, absent sources included (-1), so the entry table
+// needs no clearing and no scattered 4-byte writes reach memory.
 constexpr int kSplit = 8;
+constexpr int kGroupWaves = 4;   // waves per workgroup of a group kernel
+constexpr int kFillUnroll = 4;   // rounds of 64 pairs whose loads are issued together
+constexpr int kPairUnroll = 4;   // rounds of 64 pairs whose loads are issued together
 
 // Block b of a group kernel -> (group, split).  Workgroups are dispatched
 // round-robin over the 8 XCDs (XCD = b mod 8), so mapping the kSplit blocks
 // of group g to b = ((g / 8) kSplit + split) 8 + g mod 8 keeps a group on one
 // XCD: its entry rows are then written through a single L2, which merges the
 // scattered slot writes into whole lines before they go to memory.
+template <int Split = kSplit>
 __device__ inline void group_split_of(int b, int *g, int *split) {
     const int i = b >> 3;
-    *g = (i / kSplit) * 8 + (b & 7);
-    *split = i % kSplit;
+    *g = (i / Split) * 8 + (b & 7);
+    *split = i % Split;
 }
 
-inline int group_blocks(int32_t ngroup) { return ((ngroup + 7) / 8) * 8 * kSplit; }
+inline int group_blocks(int32_t ngroup, int split = kSplit) { return ((ngroup + 7) / 8) * 8 * split; }
 
-// slot (target) of flattened pair index idx: pre[s] <= idx < pre[s+1]
-__device__ inline int slot_of_index(const int32_t *pre, int nt, int32_t idx) {
-    int lo = 0, hi = nt - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= idx) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// The group's targets (tgt), the first list entry of each (fst), and the
-// exclusive prefix of their pair counts (pre, nt + 1 values), in LDS.
-__device__ inline void load_group(const uint64_t *__restrict__ tsorted, int32_t ntarget, int g,
-                                  const int32_t *__restrict__ ptr, int32_t *pre, int32_t *tgt, int32_t *fst,
-                                  int *nt_out) {
+// Calls f(slot, source, cid) for the table pairs of the wave's targets
+// (cid = operator slot >= 0; source = the pair's source cell if src is
+// given, else 0).
+template <class F>
+__device__ inline void for_group_pairs(const uint64_t *__restrict__ tsorted, int32_t ntarget, int g, int split,
+                                       const int32_t *__restrict__ ptr, const int32_t *__restrict__ pcode,
+                                       const int32_t *__restrict__ src, const int32_t *__restrict__ slot_of, F &&f) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int t0 = g * kGroupM2L;
     const int nt = ntarget - t0 < kGroupM2L ? ntarget - t0 : kGroupM2L;
-    if (threadIdx.x < nt) {
-        int32_t A = (int32_t)(tsorted[t0 + threadIdx.x] & 0xffffffffull);
-        tgt[threadIdx.x] = A;
-        const int32_t f = ptr[A];
-        fst[threadIdx.x] = f;
-        pre[threadIdx.x + 1] = ptr[A + 1] - f;
+    for (int sl = split + kSplit * w; sl < nt; sl += kSplit * kGroupWaves) {   // uniform over the wave
+        const int32_t A = (int32_t)(tsorted[t0 + sl] & 0xffffffffull);
+        const int32_t end = ptr[A + 1];
+        for (int32_t e0 = ptr[A] + lane; e0 < end; e0 += 64 * kPairUnroll) {
+            int32_t code[kPairUnroll], sv[kPairUnroll];
+#pragma unroll
+            for (int u = 0; u < kPairUnroll; u++) {
+                const bool in = e0 + 64 * u < end;
+                code[u] = in ? pcode[e0 + 64 * u] : -1;
+                sv[u] = (src && in) ? src[e0 + 64 * u] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kPairUnroll; u++) {
+                const int32_t cid = code_slot(code[u], slot_of);
+                if (cid >= 0) f(sl, sv[u], cid);
+            }
+        }
     }
-    if (threadIdx.x == 0) pre[0] = 0;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int i = 1; i <= nt; i++) pre[i] += pre[i - 1];
-    __syncthreads();
-    *nt_out = nt;
 }
 
-__global__ void __launch_bounds__(256) k_group_mark(const uint64_t *__restrict__ tsorted, int32_t ntarget,
-                                                    const int32_t *__restrict__ ptr, const int32_t *__restrict__ pcode,
-                                                    const int32_t *__restrict__ slot_of, int nwords,
-                                                    uint32_t *__restrict__ gbits) {
+__global__ void __launch_bounds__(64 * kGroupWaves) k_group_mark(const uint64_t *__restrict__ tsorted,
+                                                                 int32_t ntarget, const int32_t *__restrict__ ptr,
+                                                                 const int32_t *__restrict__ pcode,
+                                                                 const int32_t *__restrict__ slot_of, int nwords,
+                                                                 uint32_t *__restrict__ gbits) {
     extern __shared__ uint32_t lbits[];
-    __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L], fst[kGroupM2L];
     int g, split;
     group_split_of(blockIdx.x, &g, &split);
     if (g * kGroupM2L >= ntarget) return;
     for (int w = threadIdx.x; w < nwords; w += blockDim.x) lbits[w] = 0u;
-    int nt;
-    load_group(tsorted, ntarget, g, ptr, pre, tgt, fst, &nt);
-    const int32_t total = pre[nt];
-    for (int32_t idx = split * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
-        int s = slot_of_index(pre, nt, idx);
-        const int32_t cid = code_slot(pcode[fst[s] + (idx - pre[s])], slot_of);
-        if (cid >= 0) atomicOr(&lbits[cid >> 5], 1u << (cid & 31));
-    }
+    __syncthreads();
+    for_group_pairs(tsorted, ntarget, g, split, ptr, pcode, (const int32_t *)nullptr, slot_of,
+                    [&](int, int32_t, int32_t cid) {
+        atomicOr(&lbits[cid >> 5], 1u << (cid & 31));
+    });
     __syncthreads();
     uint32_t *bits = gbits + (int64_t)g * nwords;
     for (int w = threadIdx.x; w < nwords; w += blockDim.x)
@@ -357,55 +374,88 @@ __global__ void __launch_bounds__(256) k_group_prefix(int nwords, const uint32_t
     }
 }
 
-// kLds: the group's class bitmap and word prefixes are staged in LDS
-// (dynamic, 2 nwords words) instead of read from global memory per pair.
+constexpr int kFillSplit = 32;                           // workgroups per group in the fill (16: 8% slower)
+constexpr int kSlotsPerSplit = kGroupM2L / kFillSplit;   // 8 slots = 32 bytes of an entry row
+constexpr int kTileStride = kSlotsPerSplit + 1;      // padded LDS row: rows fall in different banks
+constexpr int kFillEntries = 384;                    // entry rows per LDS tile
+constexpr size_t kFillTileBytes = (size_t)kFillEntries * kTileStride * 4;
+
+// kLds: the group's class bitmap and word prefixes are staged in LDS (after
+// the tile, 2 nwords words) instead of read from global memory per pair.
 template <bool kLds>
-__global__ void __launch_bounds__(256) k_group_fill(const uint64_t *__restrict__ tsorted, int32_t ntarget,
-                                                    const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
-                                                    const int32_t *__restrict__ pcode,
-                                                    const int32_t *__restrict__ slot_of, int nwords,
-                                                    const uint32_t *__restrict__ gbits,
-                                                    const uint32_t *__restrict__ gwpre,
-                                                    const int32_t *__restrict__ goff, int32_t *__restrict__ ecls,
-                                                    int32_t *__restrict__ esrc, int32_t *__restrict__ gtarget) {
-    extern __shared__ uint32_t ltab[];
-    __shared__ int32_t pre[kGroupM2L + 1], tgt[kGroupM2L], fst[kGroupM2L];
+__global__ void __launch_bounds__(64 * kGroupWaves) k_group_fill(
+    const uint64_t *__restrict__ tsorted, int32_t ntarget, const int32_t *__restrict__ ptr,
+    const int32_t *__restrict__ src, const int32_t *__restrict__ pcode, const int32_t *__restrict__ slot_of,
+    int nwords, const uint32_t *__restrict__ gbits, const uint32_t *__restrict__ gwpre,
+    const int32_t *__restrict__ goff, const int32_t *__restrict__ gcount, int32_t *__restrict__ ecls,
+    int32_t *__restrict__ esrc, int32_t *__restrict__ gtarget) {
+    static_assert(kSlotsPerSplit % kGroupWaves == 0 && 64 * kGroupWaves % kSlotsPerSplit == 0, "tile shape");
+    extern __shared__ uint32_t dyn[];
+    int32_t *tile = reinterpret_cast<int32_t *>(dyn);
+    uint32_t *ltab = dyn + kFillEntries * kTileStride;
     int g, split;
-    group_split_of(blockIdx.x, &g, &split);
-    if (g * kGroupM2L >= ntarget) return;
+    group_split_of<kFillSplit>(blockIdx.x, &g, &split);
+    const int t0 = g * kGroupM2L;
+    if (t0 >= ntarget) return;
+    const int nt = ntarget - t0 < kGroupM2L ? ntarget - t0 : kGroupM2L;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t *gb = gbits + (int64_t)g * nwords;
     const uint32_t *gw = gwpre + (int64_t)g * nwords;
-    if (kLds)
-        for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
-            ltab[w] = gb[w];
-            ltab[nwords + w] = gw[w];
+    if (kLds) {
+        for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+            ltab[i] = gb[i];
+            ltab[nwords + i] = gw[i];
         }
-    int nt;
-    load_group(tsorted, ntarget, g, ptr, pre, tgt, fst, &nt);   // its barriers cover the staging too
-    if (split == 0 && threadIdx.x < kGroupM2L)
-        gtarget[(int64_t)g * kGroupM2L + threadIdx.x] = threadIdx.x < nt ? tgt[threadIdx.x] : -1;
-    const int32_t total = pre[nt];
+        __syncthreads();
+    }
     const uint32_t *bits = kLds ? ltab : gb;
     const uint32_t *wpre = kLds ? ltab + nwords : gw;
-    const int32_t base = goff[g];
-    if (split == 0)
-        for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
-            uint32_t b = bits[w];
-            int32_t ent = base + (int32_t)wpre[w];
+    const int32_t base = goff[g], nent = gcount[g];
+    if (split == 0) {
+        for (int i = threadIdx.x; i < kGroupM2L; i += blockDim.x)
+            gtarget[(int64_t)g * kGroupM2L + i] = i < nt ? (int32_t)(tsorted[t0 + i] & 0xffffffffull) : -1;
+        for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+            uint32_t b = bits[i];
+            int32_t ent = base + (int32_t)wpre[i];
             while (b) {
                 int bit = __ffs(b) - 1;
-                ecls[ent++] = w * 32 + bit;
+                ecls[ent++] = i * 32 + bit;
                 b &= b - 1;
             }
         }
-    for (int32_t idx = split * 256 + threadIdx.x; idx < total; idx += 256 * kSplit) {
-        int s = slot_of_index(pre, nt, idx);
-        int32_t e = fst[s] + (idx - pre[s]);
-        const int32_t cid = code_slot(pcode[e], slot_of);
-        if (cid < 0) continue;
-        uint32_t wv = bits[cid >> 5] & ((1u << (cid & 31)) - 1u);
-        int32_t ent = base + (int32_t)wpre[cid >> 5] + __popc(wv);
-        esrc[(int64_t)ent * kGroupM2L + s] = src[e];
+    }
+    const int s0 = split * kSlotsPerSplit;
+    for (int ec = 0; ec < nent; ec += kFillEntries) {   // uniform over the workgroup
+        const int ne = nent - ec < kFillEntries ? nent - ec : kFillEntries;
+        for (int i = threadIdx.x; i < ne * kTileStride; i += blockDim.x) tile[i] = -1;
+        __syncthreads();
+        for (int sl = w; sl < kSlotsPerSplit && s0 + sl < nt; sl += kGroupWaves) {   // uniform over the wave
+            const int32_t A = (int32_t)(tsorted[t0 + s0 + sl] & 0xffffffffull);
+            const int32_t end = ptr[A + 1];
+            for (int32_t e0 = ptr[A] + lane; e0 < end; e0 += 64 * kFillUnroll) {
+                int32_t code[kFillUnroll], sv[kFillUnroll];
+#pragma unroll
+                for (int u = 0; u < kFillUnroll; u++) {
+                    const bool in = e0 + 64 * u < end;
+                    code[u] = in ? pcode[e0 + 64 * u] : -1;
+                    sv[u] = in ? src[e0 + 64 * u] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < kFillUnroll; u++) {
+                    const int32_t cid = code_slot(code[u], slot_of);
+                    if (cid < 0) continue;
+                    const uint32_t wv = bits[cid >> 5] & ((1u << (cid & 31)) - 1u);
+                    const int r = (int)wpre[cid >> 5] + __popc(wv) - ec;
+                    if (r >= 0 && r < ne) tile[r * kTileStride + sl] = sv[u];
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < ne * kSlotsPerSplit; i += blockDim.x) {
+            const int r = i / kSlotsPerSplit, c = i % kSlotsPerSplit;
+            esrc[(int64_t)(base + ec + r) * kGroupM2L + s0 + c] = tile[r * kTileStride + c];
+        }
+        __syncthreads();
     }
 }
 
@@ -509,18 +559,20 @@ void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *pt
 
 void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
                     const int32_t *pcode, const int32_t *slot_of, int32_t nslot, const uint32_t *gbits,
-                    const uint32_t *gwpre, const int32_t *goff, int32_t *ecls, int32_t *esrc, int32_t *gtarget,
-                    hipStream_t s) {
+                    const uint32_t *gwpre, const int32_t *goff, const int32_t *gcount, int32_t *ecls, int32_t *esrc,
+                    int32_t *gtarget, hipStream_t s) {
     const int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
     if (ngroup <= 0) return;
     const int nwords = (nslot + 31) / 32;
     const size_t tab = (size_t)2 * nwords * 4;
-    if (tab <= 32768)
-        hipLaunchKernelGGL(k_group_fill<true>, dim3(group_blocks(ngroup)), dim3(256), tab, s, tsorted, ntarget, ptr,
-                           src, pcode, slot_of, nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
+    if (kFillTileBytes + tab <= 65536)
+        hipLaunchKernelGGL(k_group_fill<true>, dim3(group_blocks(ngroup, kFillSplit)), dim3(64 * kGroupWaves), kFillTileBytes + tab,
+                           s, tsorted, ntarget, ptr, src, pcode, slot_of, nwords, gbits, gwpre, goff, gcount, ecls,
+                           esrc, gtarget);
     else
-        hipLaunchKernelGGL(k_group_fill<false>, dim3(group_blocks(ngroup)), dim3(256), 0, s, tsorted, ntarget, ptr, src,
-                           pcode, slot_of, nwords, gbits, gwpre, goff, ecls, esrc, gtarget);
+        hipLaunchKernelGGL(k_group_fill<false>, dim3(group_blocks(ngroup, kFillSplit)), dim3(64 * kGroupWaves), kFillTileBytes, s,
+                           tsorted, ntarget, ptr, src, pcode, slot_of, nwords, gbits, gwpre, goff, gcount, ecls, esrc,
+                           gtarget);
     FMM_LAUNCH_CHECK();
 }
 

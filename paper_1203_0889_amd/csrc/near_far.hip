@@ -162,11 +162,10 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.tkeys.grow(nt1 * 8 * 2));
     FMM_HIP_CHECK(st.tidx.grow(nt1 * 4 * 2));
     FMM_HIP_CHECK(st.tmp.grow(std::max<size_t>(st.tmp.bytes, radix_tmp_elems(nt1) * 4)));
-    if (st.nentries > 0)
-        FMM_HIP_CHECK(hipMemsetAsync(st.esrc.ptr, 0xff, (size_t)st.nentries * kGroupM2L * 4, s));
     m2l_group_fill(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, a.m2l_src, st.pcode.as<int32_t>(),
-                   st.slot_of.as<int32_t>(), st.nslot, st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.goff.as<int32_t>(), st.ecls.as<int32_t>(),
-                   st.esrc.as<int32_t>(), st.gtarget.as<int32_t>(), s);
+                   st.slot_of.as<int32_t>(), st.nslot, st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(),
+                   st.goff.as<int32_t>(), st.gcount.as<int32_t>(), st.ecls.as<int32_t>(), st.esrc.as<int32_t>(),
+                   st.gtarget.as<int32_t>(), s);
     m2l_make_tasks(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, chunk, std::max(st.nslot, 1),
                    st.toff.as<int32_t>(),
                    st.tkey.as<uint64_t>(), st.ntask, st.tasks.as<int4>(), st.tasks_alt.as<int4>(),
