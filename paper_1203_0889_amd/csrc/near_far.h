@@ -28,6 +28,9 @@ struct NearFarArgs {
     fmm_task_record *trace = nullptr;
     int32_t *trace_count = nullptr;
     int32_t trace_cap = 0;
+    // set when build_p2p_leaves already ran on another stream: the build
+    // waits for this event instead of building the P2P leaf order itself
+    hipEvent_t p2p_ready = nullptr;
 };
 
 // Device workspaces of this stage, owned by the plan.  The class operator
@@ -48,6 +51,8 @@ struct NearFarState {
 fmm_tuning default_tuning();
 // Build-time part (after the lists): classes, operators, groups, tasks.
 void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+// The P2P leaf order alone (needs only the P2P lists), for a second stream.
+void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // Evaluate-time part, in stream order: inputs of the queue (bf16 multipoles,
 // FP32 particles, zeroed locals), the work-queue kernel (M2L and P2P tasks),
 // then the per-pair FP64 M2L of the pairs outside the class table.

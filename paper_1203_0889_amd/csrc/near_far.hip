@@ -109,12 +109,9 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     Reader rd{a};
     rd.begin(cnt, 7 * 4, s);
     // while the host waits: the P2P leaves (by spatial eighth, costliest
-    // first) and the cell centres, which need none of the sizes
-    FMM_HIP_CHECK(st.leafbuf.grow((size_t)4 * (ncell + 1) * 4));
-    FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
-    FMM_HIP_CHECK(st.tmp2.grow(radix_tmp_elems(ncell) * 4));
-    p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
-                  st.tmp2.as<int32_t>(), cnt + 24, s);
+    // first; unless already built on another stream) and the cell centres,
+    // which need none of the sizes
+    if (!a.p2p_ready) build_p2p_leaves(st, a, s);
     FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
     cell_centres(a.g, ncell, st.centre.as<double>(), s);
     int32_t h7[7];
@@ -172,10 +169,21 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                    st.tkeys.as<uint64_t>(), st.tkeys.as<uint64_t>() + nt1, st.tidx.as<uint32_t>(),
                    st.tidx.as<uint32_t>() + nt1, cnt + 16, st.tmp.as<int32_t>(), s);
     // ---- the 16 task lists (M2L and P2P per XCD), built on the device
+    if (a.p2p_ready) FMM_HIP_CHECK(hipStreamWaitEvent(s, a.p2p_ready, 0));
     FMM_HIP_CHECK(st.lists.grow(16 * sizeof(int4)));
     hipLaunchKernelGGL(k_make_lists, dim3(1), dim3(64), 0, s, cnt + 16, st.lists.as<int4>());
     FMM_LAUNCH_CHECK();
     st.built = true;
+}
+
+void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    const int32_t ncell = a.ncell;
+    FMM_HIP_CHECK(st.cnt.grow(64 * 4));   // the per-eighth leaf counts go to cnt[24 .. 32]
+    FMM_HIP_CHECK(st.leafbuf.grow((size_t)4 * (ncell + 1) * 4));
+    FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
+    FMM_HIP_CHECK(st.tmp2.grow(radix_tmp_elems(ncell) * 4));
+    p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
+                  st.tmp2.as<int32_t>(), st.cnt.as<int32_t>() + 24, s);
 }
 
 void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {

@@ -90,13 +90,16 @@ struct fmm_plan {
     std::vector<int32_t> level_begin;  // level l cells: [level_begin[l], level_begin[l+1])
     // lists
     DevBuf front[2], m2l_pairs, p2p_pairs, pair_alt, m2l_ptr, m2l_src, p2p_ptr, p2p_src;
+    DevBuf pair_alt2, tmp2;     // scratch of the P2P pair sort (second stream)
     int64_t cap_front = 0, cap_m2l = 0, cap_p2p = 0;
     DevBuf levdev;              // level starts of the device-driven octree build
-    // upward pass run by fmm_build_tree on a second stream, beside the
-    // near/far build (fmm_upward then has nothing left to do)
+    // second stream of fmm_build_tree: the upward pass (fmm_upward then has
+    // nothing left to do) and the P2P lists, beside the traversal and the
+    // M2L lists on the plan stream; up_join marks the end of its work
     hipStream_t up_side = nullptr;
-    hipEvent_t up_fork = nullptr, up_join = nullptr;
+    hipEvent_t up_fork = nullptr, up_join = nullptr, p2p_fork = nullptr, p2p_done = nullptr;
     bool upward_fresh = false;
+    bool side_pending = false;  // the plan stream has yet to wait for up_join
     int depth_hint = 0;         // levels of the last tree
     int64_t ncell_hint = 0;     // cells of the last tree
     // expansions and fields
@@ -191,6 +194,7 @@ fmm::Geometry geom(fmm_plan *p) {
 
 fmm::NearFarArgs nf_args(fmm_plan *p);
 void start_upward(fmm_plan *p);
+void ensure_side(fmm_plan *p);
 
 void do_build(fmm_plan *p, const double *pos, const double *q) {
     hipStream_t s = p->stream;
@@ -300,6 +304,15 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     if ((size_t)p->ncell * sizeof(int4) > p->crec.bytes) throw std::runtime_error("cell records smaller than the tree");
     fmm::launch_leaf_of(cells_of(p), (int32_t)p->ncell, p->leaf_of.as<int32_t>(), p->flag.as<int32_t>() + 1, s);
     mark(p, ST_TREE);
+    // work on the second stream (the P2P lists, the upward pass): this
+    // stream waits for it when the build returns (or throws)
+    struct JoinSide {
+        fmm_plan *p;
+        ~JoinSide() {
+            if (p->side_pending) (void)hipStreamWaitEvent(p->stream, p->up_join, 0);
+            p->side_pending = false;
+        }
+    } join_side{p};
 
     // the non-finite flag and the leaf count are read back with the
     // traversal's sizes (the traversal runs on any tree, even one built from
@@ -370,27 +383,47 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     FMM_HIP_CHECK(p->p2p_ptr.grow((ncell + 1) * 4));
     FMM_HIP_CHECK(p->m2l_src.grow(std::max<int64_t>(p->nm2l, 1) * 4));
     FMM_HIP_CHECK(p->p2p_src.grow(std::max<int64_t>(p->np2p, 1) * 4));
+    // the P2P list (and, mixed, its leaf order) on the second stream with
+    // scratch of its own, the M2L list here
+    FMM_HIP_CHECK(p->pair_alt2.grow(std::max<int64_t>(p->np2p, 1) * ksz));
+    FMM_HIP_CHECK(p->tmp2.grow(fmm::radix_tmp_elems(std::max<int64_t>(p->np2p, 1)) * sizeof(int32_t)));
+    ensure_side(p);
+    FMM_HIP_CHECK(hipEventRecord(p->p2p_fork, s));
+    FMM_HIP_CHECK(hipStreamWaitEvent(p->up_side, p->p2p_fork, 0));
+    p->side_pending = true;
     void *lists[2] = {p->m2l_pairs.ptr, p->p2p_pairs.ptr};
+    void *alts[2] = {p->pair_alt.ptr, p->pair_alt2.ptr};
+    int32_t *tmps[2] = {p->tmp.as<int32_t>(), p->tmp2.as<int32_t>()};
     int64_t cnts[2] = {p->nm2l, p->np2p};
     int32_t *ptrs[2] = {p->m2l_ptr.as<int32_t>(), p->p2p_ptr.as<int32_t>()};
     int32_t *srcs[2] = {p->m2l_src.as<int32_t>(), p->p2p_src.as<int32_t>()};
-    for (int t = 0; t < 2; t++) {
+    hipStream_t on[2] = {s, p->up_side};
+    for (int t = 1; t >= 0; t--) {
         if (key32)
-            fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, p->pair_alt.as<uint32_t>(), nullptr, cnts[t], bits,
-                                2 * bits, p->tmp.as<int32_t>(), s);
+            fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, (uint32_t *)alts[t], nullptr, cnts[t], bits, 2 * bits,
+                                tmps[t], on[t]);
         else
-            fmm::radix_sort_u64((uint64_t *)lists[t], nullptr, p->pair_alt.as<uint64_t>(), nullptr, cnts[t], bits,
-                                2 * bits, p->tmp.as<int32_t>(), s);
-        fmm::launch_csr(lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], s);
+            fmm::radix_sort_u64((uint64_t *)lists[t], nullptr, (uint64_t *)alts[t], nullptr, cnts[t], bits, 2 * bits,
+                                tmps[t], on[t]);
+        fmm::launch_csr(lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], on[t]);
+        if (t == 1) {
+            if (p->prm.precision == FMM_PREC_MIXED) fmm::build_p2p_leaves(p->nf, nf_args(p), p->up_side);
+            FMM_HIP_CHECK(hipEventRecord(p->p2p_done, p->up_side));
+            FMM_HIP_CHECK(hipEventRecord(p->up_join, p->up_side));
+        }
     }
     mark(p, ST_CSR);
 
-    if (p->n > 0) start_upward(p);
+    // the upward pass needs only the tree; started here it runs beside the
+    // near/far build (started before the traversal it slowed the traversal
+    // by more than it saved)
+    if (n > 0) start_upward(p);
     if (p->prm.precision == FMM_PREC_MIXED) {
-        fmm::build_near_far_mixed(p->nf, nf_args(p), s);
+        fmm::NearFarArgs a = nf_args(p);
+        a.p2p_ready = p->p2p_done;   // the P2P leaf order, built on the second stream
+        fmm::build_near_far_mixed(p->nf, a, s);
         mark(p, ST_NF_BUILD);
     }
-    if (p->upward_fresh) FMM_HIP_CHECK(hipStreamWaitEvent(s, p->up_join, 0));   // join the upward pass
 }
 
 fmm::NearFarArgs nf_args(fmm_plan *p) {
@@ -480,14 +513,20 @@ void do_upward(fmm_plan *p) {
 // The upward pass needs only the sorted particles and the tree, so a full
 // build starts it on a second stream (default priority) before the
 // near/far build and joins it back at the end of the build.
+void ensure_side(fmm_plan *p) {
+    if (p->up_side) return;
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&p->up_side, hipStreamNonBlocking));   // default priority
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->up_fork, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->up_join, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->p2p_fork, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->p2p_done, hipEventDisableTiming));
+}
+
 void start_upward(fmm_plan *p) {
-    if (!p->up_side) {
-        FMM_HIP_CHECK(hipStreamCreateWithFlags(&p->up_side, hipStreamNonBlocking));
-        FMM_HIP_CHECK(hipEventCreateWithFlags(&p->up_fork, hipEventDisableTiming));
-        FMM_HIP_CHECK(hipEventCreateWithFlags(&p->up_join, hipEventDisableTiming));
-    }
+    ensure_side(p);
     FMM_HIP_CHECK(hipEventRecord(p->up_fork, p->stream));
     FMM_HIP_CHECK(hipStreamWaitEvent(p->up_side, p->up_fork, 0));
+    p->side_pending = true;
     upward_kernels(p, p->up_side, true);
     FMM_HIP_CHECK(hipEventRecord(p->up_join, p->up_side));
     p->upward_fresh = true;
@@ -757,7 +796,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
                      &p->fld_far, &p->echunk, &p->epart, &p->ops_m2m_t, &p->ops_l2l_t, &p->m2l_t_ptr,
                      &p->m2l_t_src, &p->p2p_t_ptr, &p->p2p_t_src, &p->tkeys, &p->tkeys_alt, &p->lam, &p->mu,
                      &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far, &p->trace,
-                     &p->trace_count};
+                     &p->trace_count, &p->pair_alt2, &p->tmp2};
     drop_graph(p);
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
@@ -767,6 +806,8 @@ fmm_status fmm_destroy(fmm_plan *p) {
         (void)hipStreamDestroy(p->up_side);
         (void)hipEventDestroy(p->up_fork);
         (void)hipEventDestroy(p->up_join);
+        (void)hipEventDestroy(p->p2p_fork);
+        (void)hipEventDestroy(p->p2p_done);
     }
     fmm::release_near_far(p->nf);
     fmm::release_near_far(p->nf_t);
