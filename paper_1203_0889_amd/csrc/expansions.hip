@@ -332,7 +332,7 @@ template <int PP>
 __global__ void __launch_bounds__(128) k_l2p(Geometry g, int64_t n, const int32_t *__restrict__ leaf_of,
                                              const double *__restrict__ xs, const double *__restrict__ ys,
                                              const double *__restrict__ zs, const double *__restrict__ L,
-                                             double *__restrict__ phi, double *__restrict__ fld) {
+                                             double *__restrict__ phi, double *__restrict__ fld, FinalOut out) {
     constexpr int p = PP;
     constexpr int P = ncoef(PP);
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
@@ -396,11 +396,30 @@ __global__ void __launch_bounds__(128) k_l2p(Geometry g, int64_t n, const int32_
             }
         }
         double invS = ldexp(1.0 / side, l);
-        phi[r] = a0.re * invS;
+        const double pf = a0.re * invS;
         double e2 = invS * invS;
-        fld[3 * r] = -gxy.re * e2;
-        fld[3 * r + 1] = -gxy.im * e2;
-        fld[3 * r + 2] = -gz.re * e2;
+        const double fx = -gxy.re * e2, fy = -gxy.im * e2, fz = -gz.re * e2;
+        phi[r] = pf;
+        fld[3 * r] = fx;
+        fld[3 * r + 1] = fy;
+        fld[3 * r + 2] = fz;
+        if (out.perm) {   // uniform: the evaluation's outputs, in input order
+            const int64_t i = out.perm[r];
+            const double ex = out.fld_near[3 * r] + fx, ey = out.fld_near[3 * r + 1] + fy,
+                         ez = out.fld_near[3 * r + 2] + fz;
+            if (out.phi) out.phi[i] = out.phi_near[r] + pf;
+            if (out.field) {
+                out.field[3 * i] = ex;
+                out.field[3 * i + 1] = ey;
+                out.field[3 * i + 2] = ez;
+            }
+            if (out.force) {
+                const double q = out.qs[r];
+                out.force[3 * i] = q * ex;
+                out.force[3 * i + 1] = q * ey;
+                out.force[3 * i + 2] = q * ez;
+            }
+        }
     }
 }
 
@@ -461,29 +480,6 @@ __global__ void k_adjoint_finalize(int64_t n, const uint32_t *__restrict__ perm,
     }
 }
 
-__global__ void k_finalize(int64_t n, const uint32_t *__restrict__ perm, const double *__restrict__ qs,
-                           const double *__restrict__ pn, const double *__restrict__ fn, const double *__restrict__ pf,
-                           const double *__restrict__ ff, double *__restrict__ phi, double *__restrict__ field,
-                           double *__restrict__ force) {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        int64_t i = perm[r];
-        double ph = pn[r] + pf[r];
-        double ex = fn[3 * r] + ff[3 * r], ey = fn[3 * r + 1] + ff[3 * r + 1], ez = fn[3 * r + 2] + ff[3 * r + 2];
-        if (phi) phi[i] = ph;
-        if (field) {
-            field[3 * i] = ex;
-            field[3 * i + 1] = ey;
-            field[3 * i + 2] = ez;
-        }
-        if (force) {
-            double q = qs[r];
-            force[3 * i] = q * ex;
-            force[3 * i + 1] = q * ey;
-            force[3 * i + 2] = q * ez;
-        }
-    }
-}
-
 // E_k = 1/2 sum_(i in k) q_i phi_i in a fixed order: per-chunk partial sums
 // (chunks never straddle instances), then per-instance sums of the chunks.
 constexpr int kEnergyChunk = 8192;
@@ -513,13 +509,17 @@ __global__ void __launch_bounds__(256) k_energy_part(const int64_t *__restrict__
     if (threadIdx.x == 0) part[j] = red[0];
 }
 
-__global__ void k_energy_sum(int n_inst, const int32_t *__restrict__ chunk_off, const double *__restrict__ part,
-                             double *__restrict__ energy) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per instance: lane l sums chunks l, l + 64, ... in order, then
+// a fixed butterfly adds the 64 lane sums.
+__global__ void __launch_bounds__(64) k_energy_sum(int n_inst, const int32_t *__restrict__ chunk_off,
+                                                   const double *__restrict__ part, double *__restrict__ energy) {
+    const int k = blockIdx.x;
     if (k >= n_inst) return;
     double s = 0.0;
-    for (int j = chunk_off[k]; j < chunk_off[k + 1]; j++) s += part[j];
-    energy[k] = 0.5 * s;
+    for (int j = chunk_off[k] + (int)threadIdx.x; j < chunk_off[k + 1]; j += 64) s += part[j];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (threadIdx.x == 0) energy[k] = 0.5 * s;
 }
 
 }  // namespace
@@ -670,12 +670,12 @@ void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *o
 }
 
 void launch_l2p(Geometry g, int64_t n, int p, const int32_t *leaf_of, const double *xs, const double *ys,
-                const double *zs, const double *L, double *phi, double *fld, hipStream_t s) {
+                const double *zs, const double *L, double *phi, double *fld, hipStream_t s, const FinalOut &out) {
     if (n == 0) return;
     dim3 grid(grid_for(n, 128, 1 << 20)), block(128);
-#define FMM_L2P_CASE(PP)                                                                        \
-    case PP:                                                                                    \
-        hipLaunchKernelGGL(k_l2p<PP>, grid, block, 0, s, g, n, leaf_of, xs, ys, zs, L, phi, fld); \
+#define FMM_L2P_CASE(PP)                                                                             \
+    case PP:                                                                                         \
+        hipLaunchKernelGGL(k_l2p<PP>, grid, block, 0, s, g, n, leaf_of, xs, ys, zs, L, phi, fld, out); \
         break;
     switch (p) {
         FMM_L2P_CASE(0) FMM_L2P_CASE(1) FMM_L2P_CASE(2) FMM_L2P_CASE(3) FMM_L2P_CASE(4) FMM_L2P_CASE(5)
@@ -684,15 +684,6 @@ void launch_l2p(Geometry g, int64_t n, int p, const int32_t *leaf_of, const doub
         default: throw HipError{hipErrorInvalidValue, "l2p: unsupported order"};
     }
 #undef FMM_L2P_CASE
-    FMM_LAUNCH_CHECK();
-}
-
-void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,
-                     const double *fld_near, const double *phi_far, const double *fld_far, double *phi, double *field,
-                     double *force, hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, n, perm, qs, phi_near, fld_near,
-                       phi_far, fld_far, phi, field, force);
     FMM_LAUNCH_CHECK();
 }
 
@@ -746,7 +737,7 @@ void launch_energy(const int64_t *d_offsets, int n_inst, const int32_t *d_chunk_
                            phi_far, part);
         FMM_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_energy_sum, dim3(grid_for(n_inst, 64)), dim3(64), 0, s, n_inst, d_chunk_off, part, energy);
+    hipLaunchKernelGGL(k_energy_sum, dim3(n_inst), dim3(64), 0, s, n_inst, d_chunk_off, part, energy);
     FMM_LAUNCH_CHECK();
 }
 

@@ -398,7 +398,7 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     int32_t *ptrs[2] = {p->m2l_ptr.as<int32_t>(), p->p2p_ptr.as<int32_t>()};
     int32_t *srcs[2] = {p->m2l_src.as<int32_t>(), p->p2p_src.as<int32_t>()};
     hipStream_t on[2] = {s, p->up_side};
-    for (int t = 1; t >= 0; t--) {
+    for (int t = 0; t < 2; t++) {   // the M2L sort (the longer chain) is enqueued first
         if (key32)
             fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, (uint32_t *)alts[t], nullptr, cnts[t], bits, 2 * bits,
                                 tmps[t], on[t]);
@@ -583,12 +583,19 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_l2l.as<double>(),
                               p->L.as<double>(), s);
     mark(p, ST_L2L);
+    // L2P also writes the outputs (near + far, input order); the far field
+    // stays for the energy and a later fmm_backward
+    fmm::FinalOut out;
+    out.perm = p->idx.as<uint32_t>();
+    out.qs = p->qs.as<double>();
+    out.phi_near = p->phi_near.as<double>();
+    out.fld_near = p->fld_near.as<double>();
+    out.phi = phi;
+    out.field = field;
+    out.force = force;
     fmm::launch_l2p(g, p->n, p->prm.p, p->leaf_of.as<int32_t>(), p->xs.as<double>(), p->ys.as<double>(),
-                    p->zs.as<double>(), p->L.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), s);
+                    p->zs.as<double>(), p->L.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), s, out);
     mark(p, ST_L2P);
-    fmm::launch_finalize(p->n, p->idx.as<uint32_t>(), p->qs.as<double>(), p->phi_near.as<double>(),
-                         p->fld_near.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), phi, field, force,
-                         s);
     if (energy)
         fmm::launch_energy(p->off.as<int64_t>(), p->n_inst, p->echunk.as<int32_t>(), p->nechunk, p->qs.as<double>(),
                            p->phi_near.as<double>(), p->phi_far.as<double>(), p->epart.as<double>(), energy, s);

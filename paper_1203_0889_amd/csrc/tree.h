@@ -91,8 +91,20 @@ void launch_p2m(Geometry g, int32_t ncell, int p, const double *xs, const double
 void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, double *part,
                       hipStream_t s);
 void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *L, hipStream_t s);
+// The outputs of an evaluation, written by the L2P kernel once a particle's
+// far field is known: near + far field in input order (perm[r] = input index
+// of sorted particle r); force = q E.  Null members are not written; a null
+// perm writes none of them.
+struct FinalOut {
+    const uint32_t *perm = nullptr;
+    const double *qs = nullptr, *phi_near = nullptr, *fld_near = nullptr;
+    double *phi = nullptr, *field = nullptr, *force = nullptr;
+};
+// Far field of every sorted particle into phi / fld (and, with out.perm,
+// the outputs as described above).
 void launch_l2p(Geometry g, int64_t n, int p, const int32_t *leaf_of, const double *xs, const double *ys,
-                const double *zs, const double *L, double *phi, double *fld, hipStream_t s);
+                const double *zs, const double *L, double *phi, double *fld, hipStream_t s,
+                const FinalOut &out = FinalOut());
 // Host: M2M (dir 0) or L2L (dir 1) operator matrices for the 8 octants,
 // column-major P x P each (P = (p+1)^2), acting on the real coefficient layout.
 std::vector<double> build_translation_ops(int p, int dir);
@@ -132,9 +144,6 @@ void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *pt
                              int64_t npair, const double *Lam, double *Mu, int add, hipStream_t s);
 
 // ---- output
-void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,
-                     const double *fld_near, const double *phi_far, const double *fld_far, double *phi, double *field,
-                     double *force, hipStream_t s);
 // Energy chunk table: chunk_off[k] = first chunk of instance k (size n_inst + 1).
 std::vector<int32_t> energy_chunks(const std::vector<int64_t> &offsets);
 void launch_energy(const int64_t *d_offsets, int n_inst, const int32_t *d_chunk_off, int32_t nchunk, const double *qs,
