@@ -50,10 +50,12 @@ void exclusive_scan_oop(const int32_t *d_in, int32_t *d_out, int64_t n, int32_t 
 // result ends in kin/vin.  vin may be null (keys only).  tmp must hold
 // radix_tmp_elems(n) ints.
 size_t radix_tmp_elems(int64_t n);
+// With in_alt given, an odd number of passes leaves the result in kalt/valt
+// (*in_alt = true) instead of copying it back.
 void radix_sort_u64(uint64_t *kin, uint32_t *vin, uint64_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
-                    int bit_hi, int32_t *d_tmp, hipStream_t s);
+                    int bit_hi, int32_t *d_tmp, hipStream_t s, bool *in_alt = nullptr);
 void radix_sort_u32(uint32_t *kin, uint32_t *vin, uint32_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
-                    int bit_hi, int32_t *d_tmp, hipStream_t s);
+                    int bit_hi, int32_t *d_tmp, hipStream_t s, bool *in_alt = nullptr);
 
 // Small device-to-host reads without a stream synchronisation: a one-thread
 // kernel copies the values into pinned, mapped host memory and then raises a

@@ -201,22 +201,23 @@ __global__ void k_swap_pairs(const int32_t *__restrict__ ptr, const int32_t *__r
 
 void transpose_csr(const int32_t *ptr, const int32_t *src, int32_t ncell, int64_t npair, int bits, bool key32,
                    void *keys, void *alt, int32_t *tmp, int32_t *ptr_t, int32_t *src_t, hipStream_t s) {
+    bool in_alt = false;   // an odd number of passes leaves the sorted pairs in alt
     if (key32) {
         if (npair > 0) {
             hipLaunchKernelGGL(k_swap_pairs<uint32_t>, dim3(grid_for((int64_t)ncell * 64, 256, 4096)), dim3(256), 0, s,
                                ptr, src, ncell, bits, (uint32_t *)keys);
             FMM_LAUNCH_CHECK();
         }
-        radix_sort_u32((uint32_t *)keys, nullptr, (uint32_t *)alt, nullptr, npair, bits, 2 * bits, tmp, s);
+        radix_sort_u32((uint32_t *)keys, nullptr, (uint32_t *)alt, nullptr, npair, bits, 2 * bits, tmp, s, &in_alt);
     } else {
         if (npair > 0) {
             hipLaunchKernelGGL(k_swap_pairs<uint64_t>, dim3(grid_for((int64_t)ncell * 64, 256, 4096)), dim3(256), 0, s,
                                ptr, src, ncell, bits, (uint64_t *)keys);
             FMM_LAUNCH_CHECK();
         }
-        radix_sort_u64((uint64_t *)keys, nullptr, (uint64_t *)alt, nullptr, npair, bits, 2 * bits, tmp, s);
+        radix_sort_u64((uint64_t *)keys, nullptr, (uint64_t *)alt, nullptr, npair, bits, 2 * bits, tmp, s, &in_alt);
     }
-    launch_csr(keys, key32, npair, bits, ncell, ptr_t, src_t, s);
+    launch_csr(in_alt ? alt : keys, key32, npair, bits, ncell, ptr_t, src_t, s);
 }
 
 void launch_traverse(CellArrays c, const int2 *fin, const int32_t *nf_in, int2 *fout, int32_t *nf_out, int32_t capf,

@@ -594,8 +594,10 @@ void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, 
     hipLaunchKernelGGL(k_make_tasks, dim3(grid_for(ngroup, 256, 4096)), dim3(256), 0, s, gcount, goff, ngroup, chunk,
                        jbits, toff, tsorted, tasks_alt, tkeys, tidx, xcd_count);
     FMM_LAUNCH_CHECK();
-    radix_sort_u64(tkeys, tidx, tkeys_alt, tidx_alt, ntask, 32, 32 + jbits + 3, tmp, s);
-    hipLaunchKernelGGL(k_permute_tasks, dim3(grid_for(ntask, 256, 4096)), dim3(256), 0, s, tidx, ntask, tasks_alt, tasks);
+    bool in_alt = false;
+    radix_sort_u64(tkeys, tidx, tkeys_alt, tidx_alt, ntask, 32, 32 + jbits + 3, tmp, s, &in_alt);
+    hipLaunchKernelGGL(k_permute_tasks, dim3(grid_for(ntask, 256, 4096)), dim3(256), 0, s, in_alt ? tidx_alt : tidx,
+                       ntask, tasks_alt, tasks);
     FMM_LAUNCH_CHECK();
 }
 

@@ -399,13 +399,14 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     int32_t *srcs[2] = {p->m2l_src.as<int32_t>(), p->p2p_src.as<int32_t>()};
     hipStream_t on[2] = {s, p->up_side};
     for (int t = 0; t < 2; t++) {   // the M2L sort (the longer chain) is enqueued first
+        bool in_alt = false;   // an odd number of passes leaves the sorted pairs in the scratch buffer
         if (key32)
             fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, (uint32_t *)alts[t], nullptr, cnts[t], bits, 2 * bits,
-                                tmps[t], on[t]);
+                                tmps[t], on[t], &in_alt);
         else
             fmm::radix_sort_u64((uint64_t *)lists[t], nullptr, (uint64_t *)alts[t], nullptr, cnts[t], bits, 2 * bits,
-                                tmps[t], on[t]);
-        fmm::launch_csr(lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], on[t]);
+                                tmps[t], on[t], &in_alt);
+        fmm::launch_csr(in_alt ? alts[t] : lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], on[t]);
         if (t == 1) {
             if (p->prm.precision == FMM_PREC_MIXED) fmm::build_p2p_leaves(p->nf, nf_args(p), p->up_side);
             FMM_HIP_CHECK(hipEventRecord(p->p2p_done, p->up_side));
@@ -416,7 +417,8 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
 
     // the upward pass needs only the tree; started here it runs beside the
     // near/far build (started before the traversal it slowed the traversal
-    // by more than it saved)
+    // by more than it saved; started after the build's per-pair class pass
+    // it gained nothing measurable)
     if (n > 0) start_upward(p);
     if (p->prm.precision == FMM_PREC_MIXED) {
         fmm::NearFarArgs a = nf_args(p);

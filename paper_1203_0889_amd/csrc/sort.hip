@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const K *__restrict__
 
 template <class K, bool kVals>
 void radix_passes(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, int bit_lo, int bit_hi, int32_t *d_tmp,
-                  hipStream_t s) {
+                  hipStream_t s, bool *in_alt) {
     constexpr int Items = kRsItems;
     const int nblocks = (int)((n + kRsTile - 1) / kRsTile);
     int32_t *totals = d_tmp;
@@ -344,7 +344,9 @@ void radix_passes(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, int
         vb = tv;
         passes++;
     }
-    if (passes & 1) {
+    if (in_alt) {
+        *in_alt = (passes & 1) != 0;
+    } else if (passes & 1) {
         FMM_HIP_CHECK(hipMemcpyAsync(kin, ka, n * sizeof(K), hipMemcpyDeviceToDevice, s));
         if (kVals) FMM_HIP_CHECK(hipMemcpyAsync(vin, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     }
@@ -352,12 +354,13 @@ void radix_passes(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, int
 
 template <class K>
 void radix_sort_impl(K *kin, uint32_t *vin, K *kalt, uint32_t *valt, int64_t n, int bit_lo, int bit_hi,
-                     int32_t *d_tmp, hipStream_t s) {
+                     int32_t *d_tmp, hipStream_t s, bool *in_alt) {
+    if (in_alt) *in_alt = false;
     if (n <= 1 || bit_hi <= bit_lo) return;
     if (vin)
-        radix_passes<K, true>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s);
+        radix_passes<K, true>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s, in_alt);
     else
-        radix_passes<K, false>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s);
+        radix_passes<K, false>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s, in_alt);
 }
 
 }  // namespace
@@ -481,13 +484,13 @@ size_t radix_tmp_elems(int64_t n) {
 }
 
 void radix_sort_u64(uint64_t *kin, uint32_t *vin, uint64_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
-                    int bit_hi, int32_t *d_tmp, hipStream_t s) {
-    radix_sort_impl<uint64_t>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s);
+                    int bit_hi, int32_t *d_tmp, hipStream_t s, bool *in_alt) {
+    radix_sort_impl<uint64_t>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s, in_alt);
 }
 
 void radix_sort_u32(uint32_t *kin, uint32_t *vin, uint32_t *kalt, uint32_t *valt, int64_t n, int bit_lo,
-                    int bit_hi, int32_t *d_tmp, hipStream_t s) {
-    radix_sort_impl<uint32_t>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s);
+                    int bit_hi, int32_t *d_tmp, hipStream_t s, bool *in_alt) {
+    radix_sort_impl<uint32_t>(kin, vin, kalt, valt, n, bit_lo, bit_hi, d_tmp, s, in_alt);
 }
 
 }  // namespace fmm
