@@ -121,12 +121,10 @@ __device__ inline int octant_of(const CellArrays &c, int32_t cell) {
     return (c.ix[cell] & 1) | ((c.iy[cell] & 1) << 1) | ((c.iz[cell] & 1) << 2);
 }
 
-// M2M and L2L, octant-major.  A block owns kPB parents of one level and a
-// thread owns one coefficient row; for each octant o the block applies the
-// matrix of o (column-major, so a wave reads consecutive rows) to the kPB
-// vectors staged in LDS (parent-minor, so one 16-byte LDS read feeds two
-// parents).  Each matrix column is read once per kPB parents.
-constexpr int kPB = 8;   // 16 and 4 measured slower on the wide levels
+// M2M and L2L, octant-major: for each octant o a dense (p+1)^2 x (p+1)^2
+// operator (column-major) applied to the vectors of a level; wide levels in
+// a register-tiled kernel, levels of at most kSmallLevel parents one block
+// per (parent, octant).
 
 __device__ inline int32_t child_in_octant(const CellArrays &c, int32_t parent, int o) {
     int32_t ch = c.child[parent];
@@ -137,78 +135,7 @@ __device__ inline int32_t child_in_octant(const CellArrays &c, int32_t parent, i
     return -1;
 }
 
-constexpr int kCW = 32;  // operator columns staged in LDS at a time (at most; fewer at high p)
-constexpr size_t kTransLds = 160 * 1024;  // LDS per workgroup on gfx950
-
-// Bulk copy global -> LDS with several loads in flight per thread.
-__device__ inline void stage(double *__restrict__ dst, const double *__restrict__ src, int n) {
-    int i = threadIdx.x;
-    const int step = blockDim.x;
-    for (; i + 3 * step < n; i += 4 * step) {
-        double a0 = src[i], a1 = src[i + step], a2 = src[i + 2 * step], a3 = src[i + 3 * step];
-        dst[i] = a0;
-        dst[i + step] = a1;
-        dst[i + 2 * step] = a2;
-        dst[i + 3 * step] = a3;
-    }
-    for (; i < n; i += step) dst[i] = src[i];
-}
-
-// acc[k] += sum_(i in [c0, c0+cw)) Op[i][row] * x[i][k] with the operator's
-// column chunk staged in LDS; x is column-major over the kPB parents.
-__device__ inline void apply_chunk(const double *__restrict__ op, int P, int c0, int cw, double *__restrict__ sh,
-                                   const double *__restrict__ x, int row, double *acc) {
-    __syncthreads();
-    stage(sh, op + (int64_t)c0 * P, cw * P);
-    __syncthreads();
-    if (row < P)
-        for (int i = 0; i < cw; i++) {
-            const double a = sh[i * P + row];
-            const double2 *xc = reinterpret_cast<const double2 *>(x + (int64_t)(c0 + i) * kPB);
-#pragma unroll
-            for (int k = 0; k < kPB / 2; k++) {
-                const double2 v = xc[k];
-                acc[2 * k] += a * v.x;
-                acc[2 * k + 1] += a * v.y;
-            }
-        }
-}
-
-// M2M: block (parent chunk of kPB, octant o) writes the octant's
-// contribution to part[o][parent][row]; k_m2m_sum adds the 8 parts in a
-// fixed order (deterministic).
 constexpr int kTransMaxThreads = 320;  // rows_block(p) for p <= 16
-
-__global__ void __launch_bounds__(kTransMaxThreads) k_m2m(Geometry g, int32_t lb, int32_t le, int p, int cw,
-                                                          const double *__restrict__ ops,
-                      const double *__restrict__ M, double *__restrict__ part) {
-    extern __shared__ double dyn[];
-    __shared__ int32_t kid[kPB];
-    const int P = ncoef(p);
-    double *xs_ = dyn, *sh = dyn + kPB * P;
-    const int o = blockIdx.y;
-    const int32_t p0 = lb + blockIdx.x * kPB;
-    const int row = threadIdx.x;
-    if (threadIdx.x < kPB) {
-        int32_t par = p0 + threadIdx.x;
-        kid[threadIdx.x] = par < le ? child_in_octant(g.c, par, o) : -1;
-    }
-    __syncthreads();
-    for (int k = 0; k < kPB; k++) {
-        int32_t ch = kid[k];
-        for (int i = threadIdx.x; i < P; i += blockDim.x) xs_[i * kPB + k] = ch >= 0 ? M[(int64_t)ch * P + i] : 0.0;
-    }
-    double acc[kPB];
-#pragma unroll
-    for (int k = 0; k < kPB; k++) acc[k] = 0.0;
-    const double *A = ops + (int64_t)o * P * P;
-    for (int c0 = 0; c0 < P; c0 += cw) apply_chunk(A, P, c0, P - c0 < cw ? P - c0 : cw, sh, xs_, row, acc);
-    if (row < P)
-        for (int k = 0; k < kPB; k++) {
-            int32_t par = p0 + k;
-            if (par < le) part[((int64_t)o * (le - lb) + (par - lb)) * P + row] = acc[k];
-        }
-}
 
 __global__ void k_m2m_sum(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ part,
                           double *__restrict__ M) {
@@ -223,35 +150,138 @@ __global__ void k_m2m_sum(Geometry g, int32_t lb, int32_t le, int p, const doubl
     }
 }
 
-// L2L: block (parent chunk of kPB, octant o) adds into the children of
-// octant o (each child has one parent and one octant: no conflicts).
-__global__ void __launch_bounds__(kTransMaxThreads) k_l2l(Geometry g, int32_t lb, int32_t le, int p, int cw,
-                                                          const double *__restrict__ ops, double *__restrict__ L) {
+// Wide levels, register-tiled: block (npb parents, octant o), 256 threads;
+// a thread owns a tile of kTR rows x kTP parents.  Per chunk of cw columns
+// the block stages the operator columns (rows padded to Pp = kTR
+// ceil(P / kTR), zeros below P) and the matching rows of the npb input
+// vectors in LDS; each k then costs a thread kTR + kTP LDS values for
+// kTR kTP FMAs.  Sums run over the columns in order with one accumulator
+// per output, like the small-level kernels, so both give the same values.
+//   M2M (kL2L = false): input = the octant-o children's M, output
+//       part[o][parent][row] (zero without such a child);
+//   L2L (kL2L = true): input = the parents' L, output added into the
+//       octant-o children's L.
+// Measured at p = 8 on the 4,096-parent level (L2L / M2M): 4 x 8 tiles,
+// 64 parents per block, 60 KB of LDS: 56 / 83 us; 4 x 4 tiles, 32 parents,
+// 36 KB: 45 / 60 us; 4 x 4, 16 parents, 24 KB: 60 / 81 us.  The kernel
+// waits on memory about half of its time (SQ_WAIT_ANY).
+constexpr int kTR = 4, kTP = 4, kTileThreads = 256;
+constexpr int kTileMaxParents = 32;
+constexpr int kTileRoomKB = 36;
+
+struct TileShape {
+    int Pp, npb, xs, cw;   // padded rows, parents per block, LDS row stride of the inputs, columns per chunk
+};
+
+template <bool kL2L>
+__global__ void __launch_bounds__(kTileThreads) k_trans_tiled(Geometry g, int32_t lb, int32_t le, int p, TileShape ts,
+                                                              const double *__restrict__ ops,
+                                                              const double *__restrict__ in, double *__restrict__ out) {
     extern __shared__ double dyn[];
-    __shared__ int32_t kid[kPB];
+    __shared__ int32_t kid[kTileThreads];
     const int P = ncoef(p);
-    double *xp = dyn, *sh = dyn + kPB * P;
+    const int Pp = ts.Pp, npb = ts.npb, XS = ts.xs, cw = ts.cw;
+    double *opS = dyn;              // cw x Pp, column-major
+    double *xS = dyn + cw * Pp;     // cw x XS, k-major
     const int o = blockIdx.y;
-    const int32_t p0 = lb + blockIdx.x * kPB;
-    const int row = threadIdx.x;
-    if (threadIdx.x < kPB) {
+    const int32_t p0 = lb + blockIdx.x * npb;
+    const int PG = npb / kTP, RG = Pp / kTR;
+    const int rg = threadIdx.x / PG, pg = threadIdx.x - rg * PG;
+    const bool active = rg < RG;
+    if (threadIdx.x < npb) {
         const int32_t par = p0 + threadIdx.x;
         kid[threadIdx.x] = par < le ? child_in_octant(g.c, par, o) : -1;
     }
-    for (int k = 0; k < kPB; k++) {
-        int32_t par = p0 + k;
-        for (int i = threadIdx.x; i < P; i += blockDim.x) xp[i * kPB + k] = par < le ? L[(int64_t)par * P + i] : 0.0;
+    double acc[kTR][kTP];
+#pragma unroll
+    for (int i = 0; i < kTR; i++)
+#pragma unroll
+        for (int j = 0; j < kTP; j++) acc[i][j] = 0.0;
+    const double *A = ops + (int64_t)o * P * P;
+    for (int c0 = 0; c0 < P; c0 += cw) {
+        const int w = P - c0 < cw ? P - c0 : cw;
+        __syncthreads();   // kid ready; the last chunk's reads done
+        // staging: kStageBatch loads in flight per thread before their stores
+        constexpr int kStageBatch = 8;
+        const int nop = w * Pp, nx = npb * w;
+        for (int i0 = threadIdx.x; i0 < nop; i0 += kTileThreads * kStageBatch) {
+            double v[kStageBatch];
+#pragma unroll
+            for (int b = 0; b < kStageBatch; b++) {
+                const int i = i0 + b * kTileThreads;
+                const int k = i / Pp, r = i - k * Pp;
+                v[b] = (i < nop && r < P) ? A[(int64_t)(c0 + k) * P + r] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < kStageBatch; b++)
+                if (i0 + b * kTileThreads < nop) opS[i0 + b * kTileThreads] = v[b];
+        }
+        for (int i0 = threadIdx.x; i0 < nx; i0 += kTileThreads * kStageBatch) {
+            double v[kStageBatch];
+#pragma unroll
+            for (int b = 0; b < kStageBatch; b++) {
+                const int i = i0 + b * kTileThreads;
+                const int j = i / w, k = i - j * w;   // consecutive threads read consecutive coefficients
+                const int32_t src = i >= nx ? -1 : (kL2L ? (p0 + j < le ? p0 + j : -1) : kid[j]);
+                v[b] = src >= 0 ? in[(int64_t)src * P + c0 + k] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < kStageBatch; b++) {
+                const int i = i0 + b * kTileThreads;
+                if (i < nx) {
+                    const int j = i / w, k = i - j * w;
+                    xS[k * XS + j] = v[b];
+                }
+            }
+        }
+        __syncthreads();
+        if (active)
+            for (int k = 0; k < w; k++) {
+                double a[kTR], x[kTP];
+#pragma unroll
+                for (int i = 0; i < kTR; i++) a[i] = opS[k * Pp + kTR * rg + i];
+#pragma unroll
+                for (int j = 0; j < kTP; j++) x[j] = xS[k * XS + kTP * pg + j];
+#pragma unroll
+                for (int i = 0; i < kTR; i++)
+#pragma unroll
+                    for (int j = 0; j < kTP; j++) acc[i][j] += a[i] * x[j];
+            }
     }
-    double acc[kPB];
+    if (!active) return;
+    if (kL2L) {   // all the children's old values in flight before the adds
+        int32_t ch[kTP];
+        double old[kTR][kTP];
 #pragma unroll
-    for (int k = 0; k < kPB; k++) acc[k] = 0.0;
-    const double *B = ops + (int64_t)o * P * P;
-    for (int c0 = 0; c0 < P; c0 += cw) apply_chunk(B, P, c0, P - c0 < cw ? P - c0 : cw, sh, xp, row, acc);
-    if (row < P) {
+        for (int j = 0; j < kTP; j++) {
+            const int jj = kTP * pg + j;
+            ch[j] = p0 + jj < le ? kid[jj] : -1;
 #pragma unroll
-        for (int k = 0; k < kPB; k++) {
-            const int32_t ch = kid[k];
-            if (ch >= 0) L[(int64_t)ch * P + row] += acc[k];
+            for (int i = 0; i < kTR; i++) {
+                const int r = kTR * rg + i;
+                old[i][j] = (ch[j] >= 0 && r < P) ? out[(int64_t)ch[j] * P + r] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kTP; j++)
+#pragma unroll
+            for (int i = 0; i < kTR; i++) {
+                const int r = kTR * rg + i;
+                if (ch[j] >= 0 && r < P) out[(int64_t)ch[j] * P + r] = old[i][j] + acc[i][j];
+            }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < kTP; j++) {
+        const int jj = kTP * pg + j;
+        const int32_t par = p0 + jj;
+        if (par >= le) continue;
+        {
+#pragma unroll
+            for (int i = 0; i < kTR; i++) {
+                const int r = kTR * rg + i;
+                if (r < P) out[((int64_t)o * (le - lb) + (par - lb)) * P + r] = acc[i][j];
+            }
         }
     }
 }
@@ -261,8 +291,8 @@ __global__ void __launch_bounds__(kTransMaxThreads) k_l2l(Geometry g, int32_t lb
 // the one vector in LDS.  A block then waits for about one pass of loads
 // instead of a staging round trip per operator chunk, which dominated the
 // top levels (tens of microseconds each whatever their size).  The sum runs
-// over the columns in the same order with one accumulator, as in k_m2m and
-// k_l2l, so both forms give the same values.
+// over the columns in the same order with one accumulator, as in the
+// register-tiled kernel, so both forms give the same values.
 constexpr int32_t kSmallLevel = 256;   // parents per level up to which these are used
 constexpr int kMaxCoef = 17 * 17;      // (p + 1)^2 for p <= 16
 
@@ -621,16 +651,25 @@ void launch_p2m(Geometry g, int32_t ncell, int p, const double *xs, const double
 
 static int rows_block(int p) { return ((ncoef(p) + 63) / 64) * 64; }
 
-// Operator columns per LDS chunk and the dynamic LDS of a translation block
-// (kPB parent vectors + cw operator columns), within the 160 KB of a CU.
-static int trans_cw(int p) {
-    const size_t P = ncoef(p);
-    const size_t room = kTransLds - 1024 - kPB * P * sizeof(double);  // static LDS aside
-    const size_t cw = room / (P * sizeof(double));
-    return (int)(cw < (size_t)kCW ? (cw < 1 ? 1 : cw) : kCW);
+// Shape of the register-tiled wide-level kernel for order p: as many
+// parents per block as 256 threads allow (at most kTileMaxParents), and as
+// many columns per chunk as kTileRoomKB of LDS hold (four blocks per CU).
+static TileShape tile_shape(int p) {
+    TileShape t;
+    const int P = ncoef(p);
+    t.Pp = ((P + kTR - 1) / kTR) * kTR;
+    const int rg = t.Pp / kTR;
+    int pg = kTileThreads / rg;
+    pg = pg > kTileMaxParents / kTP ? kTileMaxParents / kTP : (pg < 1 ? 1 : pg);
+    t.npb = pg * kTP;
+    t.xs = t.npb + 2;   // 16-byte aligned rows that fall in different banks
+    const int room = (kTileRoomKB * 1024) / (int)sizeof(double);
+    int cw = room / (t.Pp + t.xs);
+    t.cw = cw > P ? P : (cw < 1 ? 1 : cw);
+    return t;
 }
 
-static size_t trans_lds(int p, int cw) { return (size_t)(kPB + cw) * ncoef(p) * sizeof(double); }
+static size_t tile_lds(const TileShape &t) { return (size_t)t.cw * (t.Pp + t.xs) * sizeof(double); }
 
 static void allow_lds(const void *fn, size_t bytes) {
     if (bytes > 64 * 1024)
@@ -643,11 +682,11 @@ void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *o
     if (le - lb <= kSmallLevel) {
         hipLaunchKernelGGL(k_m2m_small, dim3(le - lb, 8), dim3(rows_block(p)), 0, s, g, lb, le, p, ops, M, part);
     } else {
-        const int cw = trans_cw(p);
-        const size_t lds = trans_lds(p, cw);
-        allow_lds(reinterpret_cast<const void *>(&k_m2m), lds);
-        dim3 grid((le - lb + kPB - 1) / kPB, 8);
-        hipLaunchKernelGGL(k_m2m, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, cw, ops, M, part);
+        const TileShape t = tile_shape(p);
+        const size_t lds = tile_lds(t);
+        allow_lds(reinterpret_cast<const void *>(&k_trans_tiled<false>), lds);
+        dim3 grid((le - lb + t.npb - 1) / t.npb, 8);
+        hipLaunchKernelGGL(k_trans_tiled<false>, grid, dim3(kTileThreads), lds, s, g, lb, le, p, t, ops, M, part);
     }
     FMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_m2m_sum, dim3(grid_for((int64_t)(le - lb) * ncoef(p), 256, 4096)), dim3(256), 0, s, g, lb, le, p,
@@ -660,11 +699,11 @@ void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *o
     if (le - lb <= kSmallLevel) {
         hipLaunchKernelGGL(k_l2l_small, dim3(le - lb, 8), dim3(rows_block(p)), 0, s, g, lb, le, p, ops, L);
     } else {
-        const int cw = trans_cw(p);
-        const size_t lds = trans_lds(p, cw);
-        allow_lds(reinterpret_cast<const void *>(&k_l2l), lds);
-        dim3 grid((le - lb + kPB - 1) / kPB, 8);
-        hipLaunchKernelGGL(k_l2l, grid, dim3(rows_block(p)), lds, s, g, lb, le, p, cw, ops, L);
+        const TileShape t = tile_shape(p);
+        const size_t lds = tile_lds(t);
+        allow_lds(reinterpret_cast<const void *>(&k_trans_tiled<true>), lds);
+        dim3 grid((le - lb + t.npb - 1) / t.npb, 8);
+        hipLaunchKernelGGL(k_trans_tiled<true>, grid, dim3(kTileThreads), lds, s, g, lb, le, p, t, ops, L, L);
     }
     FMM_LAUNCH_CHECK();
 }
