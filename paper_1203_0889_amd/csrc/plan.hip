@@ -78,6 +78,7 @@ struct fmm_plan {
     int64_t n = 0;
     int32_t n_inst = 0;
     std::vector<int64_t> h_off;
+    std::vector<int64_t> off_on_dev;   // the offsets held by `off` (empty: none)
     // particles
     DevBuf off, ord, flag, box, scale;
     DevBuf keys, kalt, idx, valt, ikey, ialt, rank, ralt, tmp;
@@ -200,8 +201,17 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     hipStream_t s = p->stream;
     const int64_t n = p->n;
     const int ni = p->n_inst;
+    // instance offsets and the energy chunk table on the device: copied only
+    // when they differ from the last build's (a copy from pageable host
+    // memory waits for the stream, which would idle the GPU between steps)
+    const size_t off_bytes = p->off.bytes;
     FMM_HIP_CHECK(p->off.grow((ni + 1) * sizeof(int64_t)));
-    FMM_HIP_CHECK(hipMemcpyAsync(p->off.ptr, p->h_off.data(), (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (p->off.bytes != off_bytes) p->off_on_dev.clear();
+    const bool new_off = p->off_on_dev != p->h_off;
+    if (new_off) {
+        FMM_HIP_CHECK(hipMemcpyAsync(p->off.ptr, p->h_off.data(), (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        p->off_on_dev.clear();   // valid once the chunk table is copied too
+    }
     FMM_HIP_CHECK(p->ord.grow(6 * ni * sizeof(unsigned long long)));
     FMM_HIP_CHECK(p->flag.grow(16 * sizeof(int)));
     FMM_HIP_CHECK(p->box.grow(4 * ni * sizeof(double)));
@@ -224,12 +234,13 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         FMM_HIP_CHECK(p->rank.grow(nn * 4));
         FMM_HIP_CHECK(p->ralt.grow(nn * 4));
     }
-    {
+    if (new_off) {
         std::vector<int32_t> co = fmm::energy_chunks(p->h_off);
         p->nechunk = co.back();
         FMM_HIP_CHECK(p->echunk.grow(co.size() * 4));
         FMM_HIP_CHECK(p->epart.grow((size_t)std::max(p->nechunk, 1) * 8));
         FMM_HIP_CHECK(hipMemcpyAsync(p->echunk.ptr, co.data(), co.size() * 4, hipMemcpyHostToDevice, s));
+        p->off_on_dev = p->h_off;
     }
     const double *pbox = p->prm.box_min;
     double ubox[4] = {pbox[0], pbox[1], pbox[2], p->prm.box_side};
