@@ -358,8 +358,9 @@ __device__ inline Cplx lget(const double *Lc, int p, int n, int m) {
 //   d/du (z)       = sum     L~_(n+1)^m   conj(R_n^m(u))
 //   d/du (x + i y) = sum     L~_(n+1)^(m+1) conj(R_n^m(u))
 // and E = -(1/S^2) grad_u.
+// At least three waves per SIMD (168 registers instead of 169: 102 -> 96 us at p = 8).
 template <int PP>
-__global__ void __launch_bounds__(128) k_l2p(Geometry g, int64_t n, const int32_t *__restrict__ leaf_of,
+__global__ void __launch_bounds__(128, 3) k_l2p(Geometry g, int64_t n, const int32_t *__restrict__ leaf_of,
                                              const double *__restrict__ xs, const double *__restrict__ ys,
                                              const double *__restrict__ zs, const double *__restrict__ L,
                                              double *__restrict__ phi, double *__restrict__ fld, FinalOut out) {
