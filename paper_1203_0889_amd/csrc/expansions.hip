@@ -511,6 +511,30 @@ __global__ void k_adjoint_finalize(int64_t n, const uint32_t *__restrict__ perm,
     }
 }
 
+// The outputs from the near and far fields of every sorted particle r, in
+// input order (perm[r] = input index of r); force = q E.
+__global__ void k_finalize(int64_t n, const uint32_t *__restrict__ perm, const double *__restrict__ qs,
+                           const double *__restrict__ pn, const double *__restrict__ fn, const double *__restrict__ pf,
+                           const double *__restrict__ ff, double *__restrict__ phi, double *__restrict__ field,
+                           double *__restrict__ force) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = perm[r];
+        const double ex = fn[3 * r] + ff[3 * r], ey = fn[3 * r + 1] + ff[3 * r + 1], ez = fn[3 * r + 2] + ff[3 * r + 2];
+        if (phi) phi[i] = pn[r] + pf[r];
+        if (field) {
+            field[3 * i] = ex;
+            field[3 * i + 1] = ey;
+            field[3 * i + 2] = ez;
+        }
+        if (force) {
+            const double q = qs[r];
+            force[3 * i] = q * ex;
+            force[3 * i + 1] = q * ey;
+            force[3 * i + 2] = q * ez;
+        }
+    }
+}
+
 // E_k = 1/2 sum_(i in k) q_i phi_i in a fixed order: per-chunk partial sums
 // (chunks never straddle instances), then per-instance sums of the chunks.
 constexpr int kEnergyChunk = 8192;
@@ -724,6 +748,15 @@ void launch_l2p(Geometry g, int64_t n, int p, const int32_t *leaf_of, const doub
         default: throw HipError{hipErrorInvalidValue, "l2p: unsupported order"};
     }
 #undef FMM_L2P_CASE
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,
+                     const double *fld_near, const double *phi_far, const double *fld_far, double *phi, double *field,
+                     double *force, hipStream_t s) {
+    if (n == 0 || (!phi && !field && !force)) return;
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, n, perm, qs, phi_near, fld_near,
+                       phi_far, fld_far, phi, field, force);
     FMM_LAUNCH_CHECK();
 }
 

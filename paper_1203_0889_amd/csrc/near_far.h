@@ -57,7 +57,10 @@ void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // FP32 particles, zeroed locals), the work-queue kernel (M2L and P2P tasks),
 // then the per-pair FP64 M2L of the pairs outside the class table.
 void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s);
-void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+// defer_join: see queue_run; then near_far_join(st, s) before the near
+// field is read.  Returns whether the join was deferred.
+bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join = false);
+void near_far_join(NearFarState &st, hipStream_t s);
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 void release_near_far(NearFarState &st);
 

@@ -200,7 +200,7 @@ void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
 }
 
-void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join) {
     if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
     if (a.n > 0 && (!a.L || !a.phi || !a.fld || !st.M32.ptr || !st.pf.ptr))
         throw std::runtime_error("mixed near/far stage: queue inputs not prepared");
@@ -241,8 +241,10 @@ void near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
         FMM_HIP_CHECK(hipEventCreateWithFlags(&st.fork, hipEventDisableTiming));
         FMM_HIP_CHECK(hipEventCreateWithFlags(&st.join, hipEventDisableTiming));
     }
-    queue_run(q, a.p, ncu * per_cu, ncu * side_per_cu, st.side, st.fork, st.join, s);
+    return queue_run(q, a.p, ncu * per_cu, ncu * side_per_cu, st.side, st.fork, st.join, s, defer_join);
 }
+
+void near_far_join(NearFarState &st, hipStream_t s) { FMM_HIP_CHECK(hipStreamWaitEvent(s, st.join, 0)); }
 
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (st.nextra <= 0) return;

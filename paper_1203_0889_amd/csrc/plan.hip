@@ -561,6 +561,7 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     ensure_eval_buffers(p);
     fmm::Geometry g = geom(p);
     const int32_t ncell = (int32_t)p->ncell;
+    bool deferred = false;   // the queue's P2P tail still runs on the second stream
     record(p, ST_M2L);
     if (p->prm.precision == FMM_PREC_FP64) {
         fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
@@ -586,8 +587,20 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         }
         fmm::near_far_prepare(p->nf, a, s);
         mark(p, ST_NF_PREP);
-        fmm::near_far_queue(p->nf, a, s);
-        mark(p, ST_QUEUE);
+        // with a P2P side kernel the queue's P2P tail runs on beside the
+        // FP64 M2L rest, L2L and L2P; the near field is joined before the
+        // outputs
+        deferred = fmm::near_far_queue(p->nf, a, s, /*defer_join=*/true);
+        if (!deferred) {
+            mark(p, ST_QUEUE);
+        } else if (p->ev_ok && !p->capturing && p->last_ev) {
+            // the queue stage ends with both kernels (the join, on the side
+            // stream); the next stage begins after k_queue
+            FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_QUEUE], p->nf.side));
+            p->beg_of[ST_QUEUE] = p->last_ev;
+            p->ev_used[ST_QUEUE] = true;
+            record(p, ST_M2L_REST);
+        }
         fmm::near_far_rest(p->nf, a, s);
         mark(p, ST_M2L_REST);
     }
@@ -596,19 +609,28 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_l2l.as<double>(),
                               p->L.as<double>(), s);
     mark(p, ST_L2L);
-    // L2P also writes the outputs (near + far, input order); the far field
-    // stays for the energy and a later fmm_backward
+    // L2P also writes the outputs (near + far, input order) when the near
+    // field is complete; the far field stays for the energy and a later
+    // fmm_backward
     fmm::FinalOut out;
-    out.perm = p->idx.as<uint32_t>();
-    out.qs = p->qs.as<double>();
-    out.phi_near = p->phi_near.as<double>();
-    out.fld_near = p->fld_near.as<double>();
-    out.phi = phi;
-    out.field = field;
-    out.force = force;
+    if (!deferred) {
+        out.perm = p->idx.as<uint32_t>();
+        out.qs = p->qs.as<double>();
+        out.phi_near = p->phi_near.as<double>();
+        out.fld_near = p->fld_near.as<double>();
+        out.phi = phi;
+        out.field = field;
+        out.force = force;
+    }
     fmm::launch_l2p(g, p->n, p->prm.p, p->leaf_of.as<int32_t>(), p->xs.as<double>(), p->ys.as<double>(),
                     p->zs.as<double>(), p->L.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), s, out);
     mark(p, ST_L2P);
+    if (deferred) {
+        fmm::near_far_join(p->nf, s);
+        fmm::launch_finalize(p->n, p->idx.as<uint32_t>(), p->qs.as<double>(), p->phi_near.as<double>(),
+                             p->fld_near.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), phi, field,
+                             force, s);
+    }
     if (energy)
         fmm::launch_energy(p->off.as<int64_t>(), p->n_inst, p->echunk.as<int32_t>(), p->nechunk, p->qs.as<double>(),
                            p->phi_near.as<double>(), p->phi_far.as<double>(), p->epart.as<double>(), energy, s);

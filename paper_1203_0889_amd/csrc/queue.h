@@ -34,6 +34,7 @@ struct QueueArgs {
     const int4 *lists;
     int32_t *heads;            // 16 claim counters (zeroed before launch)
     int32_t role_split;        // set by queue_run
+    int32_t m2l_only;          // set by queue_run: k_queue leaves the P2P tasks to k_p2p_side
     // task trace (null: off): records, their counter (zeroed before the
     // launch) and capacity; records past the capacity are dropped
     fmm_task_record *trace;
@@ -60,7 +61,12 @@ void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb,
 // workgroups the k_queue workgroups sharing a compute unit alternate which
 // task type they start with; with them every k_queue workgroup starts with
 // M2L and the side kernel drains the P2P tasks beside it.
-void queue_run(const QueueArgs &a, int p, int nworkgroups, int nside, hipStream_t side, hipEvent_t fork,
-               hipEvent_t join, hipStream_t s);
+// defer_join (with side workgroups): k_queue runs the M2L tasks only and
+// the side kernel, with nworkgroups more workgroups (they start on the
+// compute units k_queue leaves), drains every P2P task; s does not wait for
+// it: join marks the end of both kernels and the caller waits for it before
+// it reads the near field.  Returns whether the join was deferred.
+bool queue_run(const QueueArgs &a, int p, int nworkgroups, int nside, hipStream_t side, hipEvent_t fork,
+               hipEvent_t join, hipStream_t s, bool defer_join = false);
 
 }  // namespace fmm

@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(256, (RT <= 3 ? 2 : 1)) k_queue(QueueArgs a) {
                     m2l_group<RT>(a, a.m2l_tasks[li.x + t], w, lane, lds);
                 }
             }
-        } else {
+        } else if (!a.m2l_only) {
             p2p_phase(a, x, lane, reinterpret_cast<float4 *>(lds) + w * kP2PTile, 0);
         }
         __syncthreads();   // the LDS changes role
@@ -565,18 +565,20 @@ void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb,
     FMM_LAUNCH_CHECK();
 }
 
-void queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, hipStream_t side, hipEvent_t fork,
-               hipEvent_t join, hipStream_t s) {
+bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, hipStream_t side, hipEvent_t fork,
+               hipEvent_t join, hipStream_t s, bool defer_join) {
     if (nworkgroups < 1 || nside < 0 || (nside > 0 && (!side || !fork || !join)))
         throw HipError{hipErrorInvalidValue, "queue: bad launch configuration"};
+    const bool defer = defer_join && nside > 0;
     QueueArgs a = a_in;
     a.role_split = nside == 0;
+    a.m2l_only = defer ? 1 : 0;
     fill_zero(a.heads, 16 * sizeof(int32_t), s);
     if (nside > 0) {
         // fork: the side stream starts after everything queued on s so far
         FMM_HIP_CHECK(hipEventRecord(fork, s));
         FMM_HIP_CHECK(hipStreamWaitEvent(side, fork, 0));
-        hipLaunchKernelGGL(k_p2p_side, dim3(nside), dim3(256), 0, side, a);
+        hipLaunchKernelGGL(k_p2p_side, dim3(defer ? nside + nworkgroups : nside), dim3(256), 0, side, a);
         FMM_LAUNCH_CHECK();
     }
     dim3 grid(nworkgroups), block(256);
@@ -591,11 +593,18 @@ void queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, hipStre
     }
 #undef FMM_Q
     FMM_LAUNCH_CHECK();
-    if (nside > 0) {
+    if (defer) {
+        // join = the end of both kernels: the side stream also waits for
+        // k_queue (recorded with the fork event, which is free again)
+        FMM_HIP_CHECK(hipEventRecord(fork, s));
+        FMM_HIP_CHECK(hipStreamWaitEvent(side, fork, 0));
+        FMM_HIP_CHECK(hipEventRecord(join, side));
+    } else if (nside > 0) {
         // join: work queued on s after this waits for the side kernel too
         FMM_HIP_CHECK(hipEventRecord(join, side));
         FMM_HIP_CHECK(hipStreamWaitEvent(s, join, 0));
     }
+    return defer;
 }
 
 }  // namespace fmm

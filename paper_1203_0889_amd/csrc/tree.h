@@ -144,6 +144,10 @@ void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *pt
                              int64_t npair, const double *Lam, double *Mu, int add, hipStream_t s);
 
 // ---- output
+// The outputs (near + far field of every sorted particle) in input order.
+void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const double *phi_near,
+                     const double *fld_near, const double *phi_far, const double *fld_far, double *phi, double *field,
+                     double *force, hipStream_t s);
 // Energy chunk table: chunk_off[k] = first chunk of instance k (size n_inst + 1).
 std::vector<int32_t> energy_chunks(const std::vector<int64_t> &offsets);
 void launch_energy(const int64_t *d_offsets, int n_inst, const int32_t *d_chunk_off, int32_t nchunk, const double *qs,
