@@ -537,12 +537,15 @@ __global__ void k_finalize(int64_t n, const uint32_t *__restrict__ perm, const d
 
 // E_k = 1/2 sum_(i in k) q_i phi_i in a fixed order: per-chunk partial sums
 // (chunks never straddle instances), then per-instance sums of the chunks.
-constexpr int kEnergyChunk = 8192;
+// With out.perm set, the same pass also writes the outputs of its particles
+// (near + far, input order; ff = far field), like k_finalize.
+constexpr int kEnergyChunk = 1024;
 
 __global__ void __launch_bounds__(256) k_energy_part(const int64_t *__restrict__ offsets, int n_inst,
                                                      const int32_t *__restrict__ chunk_off, const double *__restrict__ qs,
                                                      const double *__restrict__ pn, const double *__restrict__ pf,
-                                                     double *__restrict__ part) {
+                                                     double *__restrict__ part, FinalOut out,
+                                                     const double *__restrict__ ff) {
     __shared__ double red[256];
     int j = blockIdx.x;
     // instance of chunk j: largest k with chunk_off[k] <= j
@@ -554,7 +557,27 @@ __global__ void __launch_bounds__(256) k_energy_part(const int64_t *__restrict__
     int64_t b = offsets[lo] + (int64_t)(j - chunk_off[lo]) * kEnergyChunk;
     int64_t e = b + kEnergyChunk < offsets[lo + 1] ? b + kEnergyChunk : offsets[lo + 1];
     double s = 0.0;
-    for (int64_t r = b + threadIdx.x; r < e; r += 256) s += qs[r] * (pn[r] + pf[r]);
+    for (int64_t r = b + threadIdx.x; r < e; r += 256) {
+        const double ph = pn[r] + pf[r];
+        s += qs[r] * ph;
+        if (out.perm) {   // uniform
+            const int64_t i = out.perm[r];
+            const double *fn = out.fld_near;
+            const double ex = fn[3 * r] + ff[3 * r], ey = fn[3 * r + 1] + ff[3 * r + 1], ez = fn[3 * r + 2] + ff[3 * r + 2];
+            if (out.phi) out.phi[i] = ph;
+            if (out.field) {
+                out.field[3 * i] = ex;
+                out.field[3 * i + 1] = ey;
+                out.field[3 * i + 2] = ez;
+            }
+            if (out.force) {
+                const double q = qs[r];
+                out.force[3 * i] = q * ex;
+                out.force[3 * i + 1] = q * ey;
+                out.force[3 * i + 2] = q * ez;
+            }
+        }
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -804,10 +827,11 @@ std::vector<int32_t> energy_chunks(const std::vector<int64_t> &offsets) {
 }
 
 void launch_energy(const int64_t *d_offsets, int n_inst, const int32_t *d_chunk_off, int32_t nchunk, const double *qs,
-                   const double *phi_near, const double *phi_far, double *part, double *energy, hipStream_t s) {
+                   const double *phi_near, const double *phi_far, double *part, double *energy, hipStream_t s,
+                   const FinalOut &out, const double *fld_far) {
     if (nchunk > 0) {
         hipLaunchKernelGGL(k_energy_part, dim3(nchunk), dim3(256), 0, s, d_offsets, n_inst, d_chunk_off, qs, phi_near,
-                           phi_far, part);
+                           phi_far, part, out, fld_far);
         FMM_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_energy_sum, dim3(n_inst), dim3(64), 0, s, n_inst, d_chunk_off, part, energy);

@@ -625,15 +625,27 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     fmm::launch_l2p(g, p->n, p->prm.p, p->leaf_of.as<int32_t>(), p->xs.as<double>(), p->ys.as<double>(),
                     p->zs.as<double>(), p->L.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), s, out);
     mark(p, ST_L2P);
+    fmm::FinalOut out_e;   // outputs written by the energy pass (deferred queue with an energy)
     if (deferred) {
         fmm::near_far_join(p->nf, s);
-        fmm::launch_finalize(p->n, p->idx.as<uint32_t>(), p->qs.as<double>(), p->phi_near.as<double>(),
-                             p->fld_near.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), phi, field,
-                             force, s);
+        if (energy && (phi || field || force)) {
+            out_e.perm = p->idx.as<uint32_t>();
+            out_e.qs = p->qs.as<double>();
+            out_e.phi_near = p->phi_near.as<double>();
+            out_e.fld_near = p->fld_near.as<double>();
+            out_e.phi = phi;
+            out_e.field = field;
+            out_e.force = force;
+        } else {
+            fmm::launch_finalize(p->n, p->idx.as<uint32_t>(), p->qs.as<double>(), p->phi_near.as<double>(),
+                                 p->fld_near.as<double>(), p->phi_far.as<double>(), p->fld_far.as<double>(), phi,
+                                 field, force, s);
+        }
     }
     if (energy)
         fmm::launch_energy(p->off.as<int64_t>(), p->n_inst, p->echunk.as<int32_t>(), p->nechunk, p->qs.as<double>(),
-                           p->phi_near.as<double>(), p->phi_far.as<double>(), p->epart.as<double>(), energy, s);
+                           p->phi_near.as<double>(), p->phi_far.as<double>(), p->epart.as<double>(), energy, s, out_e,
+                           p->fld_far.as<double>());
     mark(p, ST_OUT);
 }
 

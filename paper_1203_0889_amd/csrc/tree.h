@@ -150,7 +150,9 @@ void launch_finalize(int64_t n, const uint32_t *perm, const double *qs, const do
                      double *force, hipStream_t s);
 // Energy chunk table: chunk_off[k] = first chunk of instance k (size n_inst + 1).
 std::vector<int32_t> energy_chunks(const std::vector<int64_t> &offsets);
+// With out.perm set (and fld_far), the energy pass also writes the outputs.
 void launch_energy(const int64_t *d_offsets, int n_inst, const int32_t *d_chunk_off, int32_t nchunk, const double *qs,
-                   const double *phi_near, const double *phi_far, double *part, double *energy, hipStream_t s);
+                   const double *phi_near, const double *phi_far, double *part, double *energy, hipStream_t s,
+                   const FinalOut &out = FinalOut(), const double *fld_far = nullptr);
 
 }  // namespace fmm
