@@ -107,3 +107,30 @@ def test_batched_instances_equal_single_solves(precision, tol):
         mine = cells[cells[:, 9] == k]
         assert np.array_equal(mine[:, :4], T.cells[:, :4])   # same cells (level, coords) per instance
         assert out["energy"][k] == pytest.approx(0.5 * np.dot(qk, out["phi"][a:b]), rel=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(1, 2), (2, 0)], ids=["side_kernel_deferred_join", "queue_only"])
+def test_output_subsets_agree(shape):
+    """The outputs do not depend on which of them are asked for: the
+    evaluation writes them from L2P (queue without a P2P side kernel), from
+    the energy pass or from a separate pass after the join (with one).
+    Same plan and tree, so every result must be bit-identical; the force is
+    q E and the energy half the sum of q phi."""
+    say("output subsets", shape)
+    pos, q = W.uniform_cube(20000, 5)
+    plan = fmm.Plan(p=6, ncrit=32, theta=(1, 2), precision="mixed", device=0)
+    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    plan.upward()
+    plan.set_tuning(grid_per_cu=shape[0], p2p_per_cu=shape[1])
+    full = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    no_energy = {k: v.cpu().numpy() for k, v in plan.evaluate(energy=False).items() if v is not None}
+    only_energy = plan.evaluate(phi=False, field=False, force=False)["energy"].cpu().numpy()
+    only_phi = plan.evaluate(field=False, force=False, energy=False)["phi"].cpu().numpy()
+    torch.cuda.synchronize()
+    for k in ("phi", "field", "force"):
+        assert np.array_equal(full[k], no_energy[k]), k
+    assert np.array_equal(full["phi"], only_phi)
+    assert np.array_equal(full["energy"], only_energy)
+    qn = q.astype(np.float64)
+    assert np.allclose(full["force"], qn[:, None] * full["field"], rtol=1e-15, atol=0)
+    assert abs(full["energy"][0] - 0.5 * np.dot(qn, full["phi"])) <= 1e-10 * abs(full["energy"][0])
