@@ -34,12 +34,18 @@ void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr,
 // (every element written, -1 where the target has no pair of the class).
 void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcode,
                      const int32_t *slot_of, int32_t nslot, uint32_t *gbits, uint32_t *gwpre, int32_t *gcount,
-                     hipStream_t s);
+                     int chunk, int32_t *tcount, hipStream_t s);
 void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *src,
                     const int32_t *pcode, const int32_t *slot_of, int32_t nslot, const uint32_t *gbits,
                     const uint32_t *gwpre, const int32_t *goff, const int32_t *gcount, int32_t *ecls, int32_t *esrc,
                     int32_t *gtarget, hipStream_t s);
-void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *tcount, hipStream_t s);
+// *count = the number of targets (keys before the first ~0 of the sorted
+// target keys).
+void m2l_count_targets(const uint64_t *tsorted, int32_t ncell, int32_t *count, hipStream_t s);
+// goff / toff = exclusive scans of gcount / tcount, totals[0..1] their sums;
+// zeroes xcd_count[0..8] (tmp: scan scratch for very many groups).
+void m2l_group_scans(const int32_t *gcount, const int32_t *tcount, int32_t ngroup, int32_t *goff, int32_t *toff,
+                     int32_t *totals, int32_t *xcd_count, int32_t *tmp, hipStream_t s);
 // M2L tasks ordered by (XCD, chunk index, task); xcd_count[x] = tasks of XCD x.
 // max_entries bounds the entries of a group (it sizes the chunk-index bits).
 void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, int chunk, int32_t max_entries,

@@ -51,7 +51,7 @@ __device__ inline int dense_key(int delta, int rx, int ry, int rz) {
 __global__ void k_pair_classes(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr,
                                const int32_t *__restrict__ src, const int32_t *__restrict__ slot_of,
                                int32_t *__restrict__ pcode, int32_t *__restrict__ used, int32_t *__restrict__ xcount) {
-    constexpr int U = 4;   // rounds of 64 pairs whose loads are issued together
+    constexpr int U = 8;   // rounds of 64 pairs whose loads are issued together
     const int lane = threadIdx.x & 63;
     for (int32_t A = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; A < ncell; A += gridDim.x * blockDim.x / 64) {
         int nx = 0;
@@ -344,9 +344,11 @@ __global__ void __launch_bounds__(64 * kGroupWaves) k_group_mark(const uint64_t 
         if (lbits[w]) atomicOr(&bits[w], lbits[w]);
 }
 
-// One workgroup per group: gwpre[g][w] = entries before word w; gcount[g].
+// One workgroup per group: gwpre[g][w] = entries before word w; gcount[g]
+// and the group's task count tcount[g] (its entries in chunks of `chunk`).
 __global__ void __launch_bounds__(256) k_group_prefix(int nwords, const uint32_t *__restrict__ gbits,
-                                                      uint32_t *__restrict__ gwpre, int32_t *__restrict__ gcount) {
+                                                      uint32_t *__restrict__ gwpre, int32_t *__restrict__ gcount,
+                                                      int chunk, int32_t *__restrict__ tcount) {
     __shared__ int32_t part[257];
     const int g = blockIdx.x;
     const uint32_t *bits = gbits + (int64_t)g * nwords;
@@ -365,6 +367,7 @@ __global__ void __launch_bounds__(256) k_group_prefix(int nwords, const uint32_t
         }
         part[256] = run;
         gcount[g] = run;
+        tcount[g] = (run + chunk - 1) / chunk;
     }
     __syncthreads();
     int run = part[threadIdx.x];
@@ -372,6 +375,93 @@ __global__ void __launch_bounds__(256) k_group_prefix(int nwords, const uint32_t
         wpre[w] = run;
         run += __popc(bits[w]);
     }
+}
+
+// The number of targets: the sorted target keys end with the ~0 keys of
+// the cells without table pairs; one workgroup finds the first of them
+// (a coarse pass over 256 evenly spaced keys, then the interval it names).
+__global__ void __launch_bounds__(256) k_count_targets(const uint64_t *__restrict__ tsorted, int32_t ncell,
+                                                       int32_t *__restrict__ count) {
+    __shared__ int32_t first;
+    if (threadIdx.x == 0) first = 256;
+    __syncthreads();
+    const int32_t step = (ncell + 255) / 256;
+    const int32_t i = (int32_t)threadIdx.x * step;
+    if (i < ncell && tsorted[i] == ~0ull) atomicMin(&first, (int)threadIdx.x);
+    __syncthreads();
+    // the first ~0 key lies in ((first - 1) step, first step], or is ncell
+    const int32_t hi = first * step < ncell ? first * step : ncell;
+    const int32_t lo = first > 0 ? (first - 1) * step + 1 : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) first = hi;
+    __syncthreads();
+    for (int32_t j = lo + (int32_t)threadIdx.x; j < hi; j += 256)
+        if (tsorted[j] == ~0ull) atomicMin(&first, (int)j);
+    __syncthreads();
+    if (threadIdx.x == 0) *count = first;
+}
+
+// Exclusive scans of the per-group entry and task counts (goff, toff; the
+// totals to totals[0..1]) in one workgroup, and zeroed per-XCD task
+// counters.  For at most kGroupScanMax groups.
+constexpr int kGroupScanThreads = 1024, kGroupScanItems = 8;
+constexpr int kGroupScanMax = kGroupScanThreads * kGroupScanItems;
+__global__ void __launch_bounds__(kGroupScanThreads) k_group_scans(const int32_t *__restrict__ gcount,
+                                                                   const int32_t *__restrict__ tcount, int32_t ngroup,
+                                                                   int32_t *__restrict__ goff,
+                                                                   int32_t *__restrict__ toff,
+                                                                   int32_t *__restrict__ totals,
+                                                                   int32_t *__restrict__ xcd_count) {
+    __shared__ int32_t ws[2][kGroupScanThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t b0 = threadIdx.x * kGroupScanItems;
+    int va[kGroupScanItems], vb[kGroupScanItems], sa = 0, sb = 0;
+#pragma unroll
+    for (int i = 0; i < kGroupScanItems; i++) {
+        va[i] = b0 + i < ngroup ? gcount[b0 + i] : 0;
+        vb[i] = b0 + i < ngroup ? tcount[b0 + i] : 0;
+        sa += va[i];
+        sb += vb[i];
+    }
+    int ia = sa, ib = sb;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int ta = __shfl_up(ia, d, 64), tb = __shfl_up(ib, d, 64);
+        if (lane >= d) {
+            ia += ta;
+            ib += tb;
+        }
+    }
+    if (lane == 63) {
+        ws[0][w] = ia;
+        ws[1][w] = ib;
+    }
+    __syncthreads();
+    int pa = 0, pb = 0, ta = 0, tb = 0;
+#pragma unroll
+    for (int i = 0; i < kGroupScanThreads / 64; i++) {
+        if (i < w) {
+            pa += ws[0][i];
+            pb += ws[1][i];
+        }
+        ta += ws[0][i];
+        tb += ws[1][i];
+    }
+    pa += ia - sa;
+    pb += ib - sb;
+#pragma unroll
+    for (int i = 0; i < kGroupScanItems; i++)
+        if (b0 + i < ngroup) {
+            goff[b0 + i] = pa;
+            toff[b0 + i] = pb;
+            pa += va[i];
+            pb += vb[i];
+        }
+    if (threadIdx.x == 0) {
+        totals[0] = ta;
+        totals[1] = tb;
+    }
+    if (threadIdx.x < 8) xcd_count[threadIdx.x] = 0;
 }
 
 constexpr int kFillSplit = 32;                           // workgroups per group in the fill (16: 8% slower)
@@ -488,11 +578,6 @@ __global__ void k_permute_tasks(const uint32_t *__restrict__ order, int32_t ntas
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntask; t += gridDim.x * blockDim.x) out[t] = in[order[t]];
 }
 
-__global__ void k_task_counts(const int32_t *__restrict__ gcount, int32_t ngroup, int chunk, int32_t *__restrict__ tcount) {
-    for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroup; g += gridDim.x * blockDim.x)
-        tcount[g] = (gcount[g] + chunk - 1) / chunk;
-}
-
 // The pairs outside the class table, per owner in list order: one wave per
 // owner, a ballot and prefix count place each flagged pair at xptr[A] + rank.
 __global__ void k_compact_extra(const int32_t *__restrict__ ptr, int32_t ncell, const int32_t *__restrict__ src,
@@ -542,9 +627,31 @@ void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr,
     FMM_LAUNCH_CHECK();
 }
 
+void m2l_count_targets(const uint64_t *tsorted, int32_t ncell, int32_t *count, hipStream_t s) {
+    if (ncell <= 0) {
+        fill_zero(count, sizeof(int32_t), s);
+        return;
+    }
+    hipLaunchKernelGGL(k_count_targets, dim3(1), dim3(256), 0, s, tsorted, ncell, count);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_group_scans(const int32_t *gcount, const int32_t *tcount, int32_t ngroup, int32_t *goff, int32_t *toff,
+                     int32_t *totals, int32_t *xcd_count, int32_t *tmp, hipStream_t s) {
+    if (ngroup <= kGroupScanMax) {
+        hipLaunchKernelGGL(k_group_scans, dim3(1), dim3(kGroupScanThreads), 0, s, gcount, tcount, ngroup, goff, toff,
+                           totals, xcd_count);
+        FMM_LAUNCH_CHECK();
+        return;
+    }
+    exclusive_scan_oop(gcount, goff, ngroup, totals, tmp, s);
+    exclusive_scan_oop(tcount, toff, ngroup, totals + 1, tmp, s);
+    fill_zero(xcd_count, 8 * sizeof(int32_t), s);
+}
+
 void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr, const int32_t *pcode,
                      const int32_t *slot_of, int32_t nslot, uint32_t *gbits, uint32_t *gwpre, int32_t *gcount,
-                     hipStream_t s) {
+                     int chunk, int32_t *tcount, hipStream_t s) {
     const int32_t ngroup = (ntarget + kGroupM2L - 1) / kGroupM2L;
     if (ngroup <= 0) return;
     const int nwords = (nslot + 31) / 32;
@@ -553,7 +660,7 @@ void m2l_group_count(const uint64_t *tsorted, int32_t ntarget, const int32_t *pt
     hipLaunchKernelGGL(k_group_mark, dim3(group_blocks(ngroup)), dim3(256), (size_t)nwords * 4, s, tsorted, ntarget,
                        ptr, pcode, slot_of, nwords, gbits);
     FMM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_group_prefix, dim3(ngroup), dim3(256), 0, s, nwords, gbits, gwpre, gcount);
+    hipLaunchKernelGGL(k_group_prefix, dim3(ngroup), dim3(256), 0, s, nwords, gbits, gwpre, gcount, chunk, tcount);
     FMM_LAUNCH_CHECK();
 }
 
@@ -576,19 +683,12 @@ void m2l_group_fill(const uint64_t *tsorted, int32_t ntarget, const int32_t *ptr
     FMM_LAUNCH_CHECK();
 }
 
-void m2l_task_counts(const int32_t *gcount, int32_t ngroup, int chunk, int32_t *tcount, hipStream_t s) {
-    if (ngroup <= 0) return;
-    hipLaunchKernelGGL(k_task_counts, dim3(grid_for(ngroup, 256, 4096)), dim3(256), 0, s, gcount, ngroup, chunk, tcount);
-    FMM_LAUNCH_CHECK();
-}
-
 void m2l_make_tasks(const int32_t *gcount, const int32_t *goff, int32_t ngroup, int chunk, int32_t max_entries,
                     const int32_t *toff,
                     const uint64_t *tsorted, int32_t ntask, int4 *tasks, int4 *tasks_alt, uint64_t *tkeys,
                     uint64_t *tkeys_alt, uint32_t *tidx, uint32_t *tidx_alt, int32_t *xcd_count, int32_t *tmp,
                     hipStream_t s) {
-    FMM_HIP_CHECK(hipMemsetAsync(xcd_count, 0, 8 * sizeof(int32_t), s));
-    if (ngroup <= 0 || ntask <= 0) return;
+    if (ngroup <= 0 || ntask <= 0) return;   // xcd_count was zeroed by m2l_group_scans
     int jbits = 1;
     while ((1 << jbits) <= max_entries / chunk + 1) jbits++;
     hipLaunchKernelGGL(k_make_tasks, dim3(grid_for(ngroup, 256, 4096)), dim3(256), 0, s, gcount, goff, ngroup, chunk,

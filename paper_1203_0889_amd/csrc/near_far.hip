@@ -105,7 +105,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     // eighth, octant) bits 32..42 keeps cells in order within each class
     radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 32, 43,
                    st.tmp.as<int32_t>(), s);
-    exclusive_scan_i32(st.has.as<int32_t>(), ncell, cnt + 2, st.tmp.as<int32_t>(), s);
+    m2l_count_targets(st.tkey.as<uint64_t>(), ncell, cnt + 2, s);
     Reader rd{a};
     rd.begin(cnt, 7 * 4, s);
     // while the host waits: the P2P leaves (by spatial eighth, costliest
@@ -136,12 +136,13 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     const size_t gwords = (size_t)ng * ((st.nslot + 31) / 32 + 1);
     FMM_HIP_CHECK(st.gbits.grow(gwords * 4));
     FMM_HIP_CHECK(st.gwpre.grow(gwords * 4));
-    m2l_group_count(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, st.pcode.as<int32_t>(), st.slot_of.as<int32_t>(),
-                    st.nslot, st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.gcount.as<int32_t>(), s);
-    exclusive_scan_oop(st.gcount.as<int32_t>(), st.goff.as<int32_t>(), st.ngroup, cnt + 3, st.tmp.as<int32_t>(), s);
     const int chunk = std::max(1, std::min(kMaxTaskEntries, a.tuning.m2l_task_entries));
-    m2l_task_counts(st.gcount.as<int32_t>(), st.ngroup, chunk, st.tcount.as<int32_t>(), s);
-    exclusive_scan_oop(st.tcount.as<int32_t>(), st.toff.as<int32_t>(), st.ngroup, cnt + 4, st.tmp.as<int32_t>(), s);
+    m2l_group_count(st.tkey.as<uint64_t>(), st.ntarget, a.m2l_ptr, st.pcode.as<int32_t>(), st.slot_of.as<int32_t>(),
+                    st.nslot, st.gbits.as<uint32_t>(), st.gwpre.as<uint32_t>(), st.gcount.as<int32_t>(), chunk,
+                    st.tcount.as<int32_t>(), s);
+    // entry and task offsets, their totals to cnt[3..4]; zeroes the per-XCD task counts cnt[16..24]
+    m2l_group_scans(st.gcount.as<int32_t>(), st.tcount.as<int32_t>(), st.ngroup, st.goff.as<int32_t>(),
+                    st.toff.as<int32_t>(), cnt + 3, cnt + 16, st.tmp.as<int32_t>(), s);
     rd.begin(cnt + 3, 8, s);
     // while the host waits: the pairs left to the per-pair kernel
     // (|delta| >= 2 or far displacement), whose number is known
