@@ -10,8 +10,12 @@ namespace fmm {
 namespace {
 
 // ---------------------------------------------------------------- P2P
-// One wave per target leaf; a lane per target particle; source particles of
-// every listed source leaf staged through LDS 64 at a time.
+// One wave per target leaf; source particles of every listed source leaf
+// staged through LDS 64 at a time.  A chunk of nt <= 64 / S targets puts S
+// lanes on each target (S a power of two, as large as fits), each taking
+// every S-th staged source; the S partial sums are added with a fixed
+// butterfly at the end, so leaves of 32 or fewer particles keep every lane
+// busy.
 constexpr int kP2P64Threads = 64;
 
 __global__ void __launch_bounds__(kP2P64Threads)
@@ -25,8 +29,13 @@ __global__ void __launch_bounds__(kP2P64Threads)
     int32_t tf = c.first[A], tc = c.count[A];
     int32_t e0 = ptr[A], e1 = ptr[A + 1];
     for (int32_t t0 = 0; t0 < tc; t0 += kP2P64Threads) {
-        int32_t r = tf + t0 + lane;
-        bool active = t0 + lane < tc;
+        const int nt = tc - t0 < kP2P64Threads ? tc - t0 : kP2P64Threads;
+        int T = kP2P64Threads;   // targets per pass: the smallest power of two >= nt
+        while (T / 2 >= nt) T /= 2;
+        const int S = kP2P64Threads / T;
+        const int t = lane & (T - 1), sidx = lane / T;
+        int32_t r = tf + t0 + t;
+        bool active = t < nt;
         double xt = active ? xs[r] : 0.0, yt = active ? ys[r] : 0.0, zt = active ? zs[r] : 0.0;
         double p = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
         for (int32_t e = e0; e < e1; e++) {
@@ -42,11 +51,11 @@ __global__ void __launch_bounds__(kP2P64Threads)
                     sq[lane] = qs[sf + s0 + lane];
                 }
                 __syncthreads();
-                for (int j = 0; j < ns; j++) {
+                for (int j = sidx; j < ns; j += S) {
                     double dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
                     double r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 > 0.0) {
-                        double inv = 1.0 / sqrt(r2);
+                        double inv = rsqrt(r2);
                         double qi = sq[j] * inv;
                         double qi3 = qi * inv * inv;
                         p += qi;
@@ -57,7 +66,13 @@ __global__ void __launch_bounds__(kP2P64Threads)
                 }
             }
         }
-        if (active) {
+        for (int o = kP2P64Threads / 2; o >= T; o >>= 1) {   // the S streams of a target
+            p += __shfl_xor(p, o, kP2P64Threads);
+            ex += __shfl_xor(ex, o, kP2P64Threads);
+            ey += __shfl_xor(ey, o, kP2P64Threads);
+            ez += __shfl_xor(ez, o, kP2P64Threads);
+        }
+        if (active && sidx == 0) {
             phi[r] = p;
             fld[3 * (int64_t)r] = ex;
             fld[3 * (int64_t)r + 1] = ey;
