@@ -41,8 +41,8 @@ struct NearFarState {
     DevBuf ecls, esrc, gtarget, tasks, xsrc, xptr, leafbuf, leaves, pf, M32, tmp, cnt, centre, gbits, gwpre;
     DevBuf tasks_alt, tkeys, tidx, lists, tmp2;
     // stream and events of the P2P side kernel (created on first use)
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t side = nullptr, side2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, after_queue = nullptr, after_side = nullptr;
     int p = -1;
     int32_t nslot_total = 0, nslot = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0;
     bool built = false;
@@ -61,6 +61,8 @@ void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // field is read.  Returns whether the join was deferred.
 bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join = false);
 void near_far_join(NearFarState &st, hipStream_t s);
+// The stream on which a deferred queue's join is recorded.
+hipStream_t near_far_join_stream(const NearFarState &st);
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 void release_near_far(NearFarState &st);
 

@@ -239,13 +239,25 @@ bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool 
     if (side_per_cu > 0 && !st.side) {
         // default priority, like the plan's stream
         FMM_HIP_CHECK(hipStreamCreateWithFlags(&st.side, hipStreamNonBlocking));
+        FMM_HIP_CHECK(hipStreamCreateWithFlags(&st.side2, hipStreamNonBlocking));
         FMM_HIP_CHECK(hipEventCreateWithFlags(&st.fork, hipEventDisableTiming));
         FMM_HIP_CHECK(hipEventCreateWithFlags(&st.join, hipEventDisableTiming));
+        FMM_HIP_CHECK(hipEventCreateWithFlags(&st.after_queue, hipEventDisableTiming));
+        FMM_HIP_CHECK(hipEventCreateWithFlags(&st.after_side, hipEventDisableTiming));
     }
-    return queue_run(q, a.p, ncu * per_cu, ncu * side_per_cu, st.side, st.fork, st.join, s, defer_join);
+    QueueStreams qs;
+    qs.side = st.side;
+    qs.side2 = st.side2;
+    qs.fork = st.fork;
+    qs.join = st.join;
+    qs.after_queue = st.after_queue;
+    qs.after_side = st.after_side;
+    return queue_run(q, a.p, ncu * per_cu, ncu * side_per_cu, qs, s, defer_join);
 }
 
 void near_far_join(NearFarState &st, hipStream_t s) { FMM_HIP_CHECK(hipStreamWaitEvent(s, st.join, 0)); }
+
+hipStream_t near_far_join_stream(const NearFarState &st) { return st.side2; }
 
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (st.nextra <= 0) return;
@@ -263,12 +275,16 @@ void release_near_far(NearFarState &st) {
     for (DevBuf *b : all) b->release();
     if (st.side) {
         (void)hipStreamSynchronize(st.side);
+        (void)hipStreamSynchronize(st.side2);
         (void)hipStreamDestroy(st.side);
+        (void)hipStreamDestroy(st.side2);
         (void)hipEventDestroy(st.fork);
         (void)hipEventDestroy(st.join);
+        (void)hipEventDestroy(st.after_queue);
+        (void)hipEventDestroy(st.after_side);
     }
-    st.side = nullptr;
-    st.fork = st.join = nullptr;
+    st.side = st.side2 = nullptr;
+    st.fork = st.join = st.after_queue = st.after_side = nullptr;
     st.p = -1;
     st.built = false;
 }

@@ -596,7 +596,7 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         } else if (p->ev_ok && !p->capturing && p->last_ev) {
             // the queue stage ends with both kernels (the join, on the side
             // stream); the next stage begins after k_queue
-            FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_QUEUE], p->nf.side));
+            FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_QUEUE], fmm::near_far_join_stream(p->nf)));
             p->beg_of[ST_QUEUE] = p->last_ev;
             p->ev_used[ST_QUEUE] = true;
             record(p, ST_M2L_REST);

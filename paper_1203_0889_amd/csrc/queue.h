@@ -61,12 +61,18 @@ void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb,
 // workgroups the k_queue workgroups sharing a compute unit alternate which
 // task type they start with; with them every k_queue workgroup starts with
 // M2L and the side kernel drains the P2P tasks beside it.
-// defer_join (with side workgroups): k_queue runs the M2L tasks only and
-// the side kernel, with nworkgroups more workgroups (they start on the
-// compute units k_queue leaves), drains every P2P task; s does not wait for
-// it: join marks the end of both kernels and the caller waits for it before
-// it reads the near field.  Returns whether the join was deferred.
-bool queue_run(const QueueArgs &a, int p, int nworkgroups, int nside, hipStream_t side, hipEvent_t fork,
-               hipEvent_t join, hipStream_t s, bool defer_join = false);
+// Streams and events of the side kernels (created by the caller).
+struct QueueStreams {
+    hipStream_t side = nullptr, side2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, after_queue = nullptr, after_side = nullptr;
+};
+// defer_join (with side workgroups): k_queue runs the M2L tasks only and the
+// side kernel drains every P2P task, joined when k_queue ends by nworkgroups
+// more P2P workgroups on side2 (on the compute units k_queue leaves); s does
+// not wait for them: join (recorded on side2) marks the end of all three
+// launches and the caller waits for it before it reads the near field.
+// Returns whether the join was deferred.
+bool queue_run(const QueueArgs &a, int p, int nworkgroups, int nside, const QueueStreams &qs, hipStream_t s,
+               bool defer_join = false);
 
 }  // namespace fmm

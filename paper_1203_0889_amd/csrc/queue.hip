@@ -565,22 +565,25 @@ void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb,
     FMM_LAUNCH_CHECK();
 }
 
-bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, hipStream_t side, hipEvent_t fork,
-               hipEvent_t join, hipStream_t s, bool defer_join) {
-    if (nworkgroups < 1 || nside < 0 || (nside > 0 && (!side || !fork || !join)))
+bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, const QueueStreams &qs, hipStream_t s,
+               bool defer_join) {
+    if (nworkgroups < 1 || nside < 0 || (nside > 0 && (!qs.side || !qs.fork || !qs.join)))
         throw HipError{hipErrorInvalidValue, "queue: bad launch configuration"};
-    const bool defer = defer_join && nside > 0;
+    const bool defer = defer_join && nside > 0 && qs.side2 && qs.after_queue && qs.after_side;
+    hipStream_t side = qs.side;
     QueueArgs a = a_in;
     a.role_split = nside == 0;
     a.m2l_only = defer ? 1 : 0;
     fill_zero(a.heads, 16 * sizeof(int32_t), s);
     if (nside > 0) {
         // fork: the side stream starts after everything queued on s so far
-        FMM_HIP_CHECK(hipEventRecord(fork, s));
-        FMM_HIP_CHECK(hipStreamWaitEvent(side, fork, 0));
-        hipLaunchKernelGGL(k_p2p_side, dim3(defer ? nside + nworkgroups : nside), dim3(256), 0, side, a);
-        FMM_LAUNCH_CHECK();
+        FMM_HIP_CHECK(hipEventRecord(qs.fork, s));
+        FMM_HIP_CHECK(hipStreamWaitEvent(side, qs.fork, 0));
     }
+    // k_queue is submitted before the side kernel, so that its workgroups
+    // (the larger ones) are placed first and the side kernel fills the rest
+    // of each compute unit; the other order can leave no room for k_queue
+    // until side workgroups finish
     dim3 grid(nworkgroups), block(256);
 #define FMM_Q(PP, R)                                                      \
     case PP:                                                              \
@@ -593,16 +596,25 @@ bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, hipStre
     }
 #undef FMM_Q
     FMM_LAUNCH_CHECK();
+    if (nside > 0) {
+        hipLaunchKernelGGL(k_p2p_side, dim3(nside), dim3(256), 0, side, a);
+        FMM_LAUNCH_CHECK();
+    }
     if (defer) {
-        // join = the end of both kernels: the side stream also waits for
-        // k_queue (recorded with the fork event, which is free again)
-        FMM_HIP_CHECK(hipEventRecord(fork, s));
-        FMM_HIP_CHECK(hipStreamWaitEvent(side, fork, 0));
-        FMM_HIP_CHECK(hipEventRecord(join, side));
+        // more P2P workgroups once k_queue is done (launching them with the
+        // side kernel could fill compute units before k_queue's workgroups
+        // are placed); join = the end of all three launches
+        FMM_HIP_CHECK(hipEventRecord(qs.after_queue, s));
+        FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_queue, 0));
+        hipLaunchKernelGGL(k_p2p_side, dim3(nworkgroups), dim3(256), 0, qs.side2, a);
+        FMM_LAUNCH_CHECK();
+        FMM_HIP_CHECK(hipEventRecord(qs.after_side, side));
+        FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_side, 0));
+        FMM_HIP_CHECK(hipEventRecord(qs.join, qs.side2));
     } else if (nside > 0) {
         // join: work queued on s after this waits for the side kernel too
-        FMM_HIP_CHECK(hipEventRecord(join, side));
-        FMM_HIP_CHECK(hipStreamWaitEvent(s, join, 0));
+        FMM_HIP_CHECK(hipEventRecord(qs.join, side));
+        FMM_HIP_CHECK(hipStreamWaitEvent(s, qs.join, 0));
     }
     return defer;
 }
