@@ -1122,7 +1122,8 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
                     for (int r = 0; r < repeats; r++) {
                         fmm::near_far_prepare(p->nf, a, s);
                         FMM_HIP_CHECK(hipEventRecord(e0, s));
-                        fmm::near_far_queue(p->nf, a, s);
+                        // as the evaluation runs it (P2P tail deferred), joined for the timing
+                        if (fmm::near_far_queue(p->nf, a, s, /*defer_join=*/true)) fmm::near_far_join(p->nf, s);
                         FMM_HIP_CHECK(hipEventRecord(e1, s));
                         FMM_HIP_CHECK(hipEventSynchronize(e1));
                         float ms = 0.0f;
