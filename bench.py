@@ -59,6 +59,15 @@ def committed_traffic(workload):
         return None
 
 
+def fixed_tuning(text):
+    """Parse 'key=value,...' into set_tuning keyword arguments."""
+    out = {}
+    for item in text.split(","):
+        k, v = item.split("=")
+        out[k.strip()] = int(v)
+    return out
+
+
 def m2l_flop(p):
     P = (p + 1) ** 2
     return 2 * P * P   # dense real operator applied to one multipole
@@ -76,6 +85,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing leg")
     ap.add_argument("--no-error", action="store_true", help="skip the error check against the direct sum")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default work-queue tuning")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed work-queue tuning, e.g. m2l_task_entries=128,grid_per_cu=1,p2p_per_cu=3 "
+                         "(skips the autotuner; counter runs serialise kernels, which skews its timing)")
     ap.add_argument("--cpu-n", type=int, default=524288, help="particles in the CPU oracle sample")
     ap.add_argument("--sweep", action="store_true",
                     help="granularity sweep (the paper's Q experiment): M2L entries per task x N x p, one JSON line")
@@ -206,7 +218,10 @@ def run_single(a, torch, fmm, W):
     calib_copy(a.copy_calib_mib, torch, dev)
 
     tuning = plan.get_tuning()
-    if not a.no_autotune and a.precision == "mixed":
+    if a.tuning:
+        plan.set_tuning(**fixed_tuning(a.tuning))
+        tuning = plan.get_tuning()
+    elif not a.no_autotune and a.precision == "mixed":
         # set-up, not timed: pick the work-queue setting on this workload
         plan.build_tree(dpos, dq)
         plan.upward()
