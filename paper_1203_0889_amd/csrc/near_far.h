@@ -51,7 +51,8 @@ struct NearFarState {
 fmm_tuning default_tuning();
 // Build-time part (after the lists): classes, operators, groups, tasks.
 void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s);
-// The P2P leaf order alone (needs only the P2P lists), for a second stream.
+// The P2P leaf order and the cell centres (needs only the tree and the P2P
+// lists), for a second stream.
 void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // Evaluate-time part, in stream order: inputs of the queue (bf16 multipoles,
 // FP32 particles, zeroed locals), the work-queue kernel (M2L and P2P tasks),

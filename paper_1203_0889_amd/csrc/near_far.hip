@@ -109,11 +109,9 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     Reader rd{a};
     rd.begin(cnt, 7 * 4, s);
     // while the host waits: the P2P leaves (by spatial eighth, costliest
-    // first; unless already built on another stream) and the cell centres,
-    // which need none of the sizes
+    // first) and the cell centres, which need none of the sizes (unless
+    // already built on another stream)
     if (!a.p2p_ready) build_p2p_leaves(st, a, s);
-    FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
-    cell_centres(a.g, ncell, st.centre.as<double>(), s);
     int32_t h7[7];
     rd.end(h7, s);
     if (h7[5] > st.nslot_total) {
@@ -185,6 +183,9 @@ void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     FMM_HIP_CHECK(st.tmp2.grow(radix_tmp_elems(ncell) * 4));
     p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
                   st.tmp2.as<int32_t>(), st.cnt.as<int32_t>() + 24, s);
+    // the cell centres, which the P2P tasks read (target and source leaf offsets)
+    FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
+    cell_centres(a.g, ncell, st.centre.as<double>(), s);
 }
 
 void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
@@ -201,11 +202,27 @@ void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
 }
 
-bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join) {
-    if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
-    if (a.n > 0 && (!a.L || !a.phi || !a.fld || !st.M32.ptr || !st.pf.ptr))
-        throw std::runtime_error("mixed near/far stage: queue inputs not prepared");
-    const int P = ncoef(a.p);
+namespace {
+
+void ensure_streams(NearFarState &st) {
+    if (st.side) return;
+    // default priority, like the plan's stream
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&st.side, hipStreamNonBlocking));
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&st.side2, hipStreamNonBlocking));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&st.fork, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&st.join, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&st.after_queue, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&st.after_side, hipEventDisableTiming));
+}
+
+int compute_units() {
+    int dev = 0, ncu = 256;
+    FMM_HIP_CHECK(hipGetDevice(&dev));
+    FMM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    return ncu;
+}
+
+QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
     const int32_t ncell = a.ncell;
     QueueArgs q;
     q.c = a.g.c;
@@ -218,7 +235,7 @@ bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool 
     q.Mb = st.M32.as<uint16_t>();
     q.zero_row = ncell;
     q.L = a.L;
-    q.P = P;
+    q.P = ncoef(a.p);
     q.leaves = st.leaves.as<int32_t>();
     q.p2p_ptr = a.p2p_ptr;
     q.p2p_src = a.p2p_src;
@@ -230,21 +247,22 @@ bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool 
     q.trace = a.trace && a.trace_count && a.trace_cap > 0 ? a.trace : nullptr;
     q.trace_count = a.trace_count;
     q.trace_cap = a.trace_cap;
+    return q;
+}
+
+}  // namespace
+
+bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join) {
+    if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
+    if (a.n > 0 && (!a.L || !a.phi || !a.fld || !st.M32.ptr || !st.pf.ptr || !st.centre.ptr || !st.leaves.ptr ||
+                    !st.lists.ptr))
+        throw std::runtime_error("mixed near/far stage: queue inputs not prepared");
+    QueueArgs q = queue_args(st, a);
     if (q.trace) fill_zero(a.trace_count, sizeof(int32_t), s);
-    int dev = 0, ncu = 256;
-    FMM_HIP_CHECK(hipGetDevice(&dev));
-    FMM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int ncu = compute_units();
     const int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
     const int side_per_cu = std::max(0, std::min(8, a.tuning.p2p_per_cu));
-    if (side_per_cu > 0 && !st.side) {
-        // default priority, like the plan's stream
-        FMM_HIP_CHECK(hipStreamCreateWithFlags(&st.side, hipStreamNonBlocking));
-        FMM_HIP_CHECK(hipStreamCreateWithFlags(&st.side2, hipStreamNonBlocking));
-        FMM_HIP_CHECK(hipEventCreateWithFlags(&st.fork, hipEventDisableTiming));
-        FMM_HIP_CHECK(hipEventCreateWithFlags(&st.join, hipEventDisableTiming));
-        FMM_HIP_CHECK(hipEventCreateWithFlags(&st.after_queue, hipEventDisableTiming));
-        FMM_HIP_CHECK(hipEventCreateWithFlags(&st.after_side, hipEventDisableTiming));
-    }
+    if (side_per_cu > 0) ensure_streams(st);
     QueueStreams qs;
     qs.side = st.side;
     qs.side2 = st.side2;
@@ -272,10 +290,12 @@ void release_near_far(NearFarState &st) {
     DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.pcode, &st.xcount, &st.tkey,
                      &st.tkey_alt, &st.has, &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
                      &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists, &st.tmp2};
-    for (DevBuf *b : all) b->release();
-    if (st.side) {
+    if (st.side) {   // the side kernels may still read these buffers
         (void)hipStreamSynchronize(st.side);
         (void)hipStreamSynchronize(st.side2);
+    }
+    for (DevBuf *b : all) b->release();
+    if (st.side) {
         (void)hipStreamDestroy(st.side);
         (void)hipStreamDestroy(st.side2);
         (void)hipEventDestroy(st.fork);
