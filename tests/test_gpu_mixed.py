@@ -71,6 +71,38 @@ def test_mixed_root_leaf_and_single_particle():
     assert out["phi"][0] == 0.0 and np.all(out["field"] == 0.0)
 
 
+# The orders at both ends of the mixed path: p = 0..2 use one 32-row MFMA
+# tile of the class operator, p = 11 and 12 five and six (the largest queue
+# kernel); same FP32 bound against the FP64 oracle FMM as above.
+@pytest.mark.parametrize("p", [0, 1, 2, 11, 12])
+def test_mixed_orders_at_the_ends(p):
+    say("mixed order", p)
+    pos, q = W.uniform_cube(5000, 30 + p)
+    plan, out = gpu_run(pos, q, p, 48, (1, 2), "mixed")
+    phi_ref, fld_ref, _ = oracle.fmm(pos, q, p, 48, 1, 2)
+    e_phi, e_fld = rel(out["phi"], phi_ref), rel(out["field"], fld_ref)
+    say("p", p, "vs oracle FMM: phi", e_phi, "field", e_fld)
+    assert e_phi < 1e-5 and e_fld < 1e-5
+
+
+def test_mixed_coincident_cluster_reaches_max_level():
+    # 24 coincident particles (no leaf can split them below ncrit = 8, so the
+    # tree goes down to level 21) inside a uniform background: the coincident
+    # pairs contribute nothing, and the deep levels give the M2L classes of
+    # large level differences
+    bg, qb = W.uniform_cube(3000, 41)
+    pos = np.concatenate([bg, np.tile(np.array([[0.3, 0.6, 0.45]]), (24, 1))])
+    q = np.concatenate([qb, np.linspace(-1.0, 1.0, 24)])
+    plan, out = gpu_run(pos, q, 6, 8, (1, 2), "mixed")
+    T = oracle.Tree(pos, 8)
+    assert int(T.cells[:, 0].max()) == 21
+    phi_ref, fld_ref, _ = oracle.fmm(pos, q, 6, 8, 1, 2)
+    assert np.all(np.isfinite(out["phi"])) and np.all(np.isfinite(out["field"]))
+    e_phi, e_fld = rel(out["phi"], phi_ref), rel(out["field"], fld_ref)
+    say("coincident cluster vs oracle FMM: phi", e_phi, "field", e_fld)
+    assert e_phi < 1e-5 and e_fld < 1e-5
+
+
 def test_mixed_repeated_builds_reuse_operator_cache():
     plan = fmm.Plan(p=6, ncrit=32, precision="mixed", device=0)
     for n, seed, dist in ((8000, 1, "uniform"), (12000, 2, "plummer"), (5000, 3, "uniform")):
