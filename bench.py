@@ -142,7 +142,7 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload):
         tq = stage_avg.get("queue", 0.0) * 1e-3
         t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
         # the same bound with the FP32 vector rate without packed FP32 (half
-        # of 157.3 TF; packed FP32 instructions are disabled in this build)
+        # of 157.3 TF; packed FP32 instructions are disabled at compile time)
         t_np = p2p_flop / (PEAK["fp32_valu"] / 2) + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
         roof = {"bound": "alu", "achieved": (p2p_flop + m2l_f) / tq / 1e12 if tq > 0 else None,
                 "peak": (p2p_flop + m2l_f) / t_min / 1e12, "unit": "TFLOP/s", "traffic": committed_traffic(workload),
@@ -417,7 +417,7 @@ def run_sweep(a, torch, fmm, W):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d refused)" % a.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus %d refused)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1203_0889_amd import fmm, workloads as W

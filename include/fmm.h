@@ -44,7 +44,7 @@ typedef enum {
     FMM_ERR_OOM = -3,         /* device allocation failed */
     FMM_ERR_DEVICE = -4,      /* a HIP runtime call failed */
     FMM_ERR_CAPACITY = -5,    /* an internal capacity limit was exceeded */
-    FMM_ERR_UNSUPPORTED = -6  /* valid request this build does not provide */
+    FMM_ERR_UNSUPPORTED = -6  /* valid request the library does not provide */
 } fmm_status;
 
 typedef enum {

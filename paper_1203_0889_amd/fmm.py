@@ -69,8 +69,8 @@ def load_library():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("HIP library %s is missing: run __graft_entry__.build() (or "
-                          "python paper_1203_0889_amd/build.py) first" % LIB_PATH)
+        raise ImportError("HIP library %s is missing: build it first "
+                          "(python paper_1203_0889_amd/build.py)" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     P = ctypes.POINTER
