@@ -39,9 +39,10 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-def committed_traffic(workload):
+def committed_traffic(workload, tuning):
     """HBM bytes per queue launch from the committed PMC summary, if it was
-    taken on this workload and on the current queue kernel source."""
+    taken on this workload, at this work-queue tuning and on the current
+    queue kernel source."""
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if not os.path.exists(path):
         return None
@@ -53,10 +54,17 @@ def committed_traffic(workload):
                 fields[k.strip()] = v.strip()
     if fields.get("workload") != workload or fields.get("source_sha256_16") != source_hash(QUEUE_SOURCES):
         return None
+    if fields.get("tuning") != tuning_text(tuning):
+        return None
     try:
         return float(fields["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def tuning_text(t):
+    return "m2l_task_entries=%d,grid_per_cu=%d,p2p_per_cu=%d" % (t["m2l_task_entries"], t["grid_per_cu"],
+                                                                  t["p2p_per_cu"])
 
 
 def fixed_tuning(text):
@@ -88,38 +96,69 @@ def parse():
     ap.add_argument("--tuning", default=None,
                     help="fixed work-queue tuning, e.g. m2l_task_entries=128,grid_per_cu=1,p2p_per_cu=3 "
                          "(skips the autotuner; counter runs serialise kernels, which skews its timing)")
-    ap.add_argument("--cpu-n", type=int, default=524288, help="particles in the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=0,
+                    help="particles in the all-core CPU oracle sample (default: the workload's N)")
+    ap.add_argument("--cpu-n-1core", type=int, default=16384,
+                    help="particles in the single-core CPU oracle sample")
     ap.add_argument("--sweep", action="store_true",
                     help="granularity sweep (the paper's Q experiment): M2L entries per task x N x p, one JSON line")
     ap.add_argument("--trace", action="store_true",
-                    help="after the timed steps, one evaluation with the device task trace: summary in the line")
+                    help="refused: the library does not record the device task trace")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(w, n_cpu):
-    """CPU leg: the FP64 oracle FMM timed on a bounded sample of the same
-    workload (same generator, p, ncrit, theta)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, n_cpu, n_1core):
+    """CPU leg: the FP64 oracle FMM on the host (same generator, p, ncrit,
+    theta): on all the cores OpenMP is given, at n_cpu particles (the
+    workload's N by default), and on one core at n_1core particles."""
     import oracle
     from paper_1203_0889_amd import workloads as W
-    if w["dist"] == "uniform":
-        sub_pos, sub_q = W.uniform_cube(n_cpu, w["seed"])
-    else:
-        sub_pos, sub_q = W.plummer(n_cpu, w["seed"], equal_charges=w["dist"] == "plummer_equal")
+
+    def inputs(n):
+        if w["dist"] == "uniform":
+            return W.uniform_cube(n, w["seed"])
+        return W.plummer(n, w["seed"], equal_charges=w["dist"] == "plummer_equal")
+
+    sub_pos, sub_q = inputs(n_cpu)
     t0 = time.perf_counter()
     oracle.fmm(sub_pos, sub_q, w["p"], w["ncrit"], *w["theta"])
     t1 = time.perf_counter()
-    return {"value": n_cpu / (t1 - t0), "unit": "particles/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "oracle FMM (FP64, Cartesian Taylor, same p/ncrit/theta, %s) on N=%d instead of %d; %.2f s"
-                      % (w["dist"], n_cpu, w["n"], t1 - t0)}
+    cores = oracle.num_threads()
+    out = {"value": n_cpu / (t1 - t0), "unit": "particles/s", "cores": cores, "kind": "oracle",
+           "sample": "oracle FMM (FP64, Cartesian Taylor, OpenMP over targets; same p/ncrit/theta, %s) on N=%d "
+                     "(the workload has N=%d): %.2f s" % (w["dist"], n_cpu, w["n"], t1 - t0),
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    if n_1core > 0:
+        one_pos, one_q = inputs(n_1core)
+        oracle.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            oracle.fmm(one_pos, one_q, w["p"], w["ncrit"], *w["theta"])
+            t1 = time.perf_counter()
+        finally:
+            oracle.set_num_threads(cores)
+        out["one_core"] = {"value": n_1core / (t1 - t0), "unit": "particles/s", "n": n_1core, "s": t1 - t0}
+    return out
 
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def queue_roofline(plan, stage_avg, p, n, precision, workload):
+def queue_roofline(plan, stage_avg, p, n, precision, workload, tuning):
     """Roofline of the dominant kernel and the algorithmic work of one evaluation."""
     counts = plan.counts()
     _, _, cells = plan.copy_tree()
@@ -133,24 +172,31 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload):
     t_m2l = stage_avg.get("m2l", 0.0) * 1e-3
     if precision == "mixed":
         # M2L and P2P run in the work queue: k_queue on the plan's stream
-        # with the P2P-only k_p2p_side beside it on a forked stream (stage
-        # "queue", HIP events on the plan's stream around fork and join).
-        # Its ALU bound: P2P on the FP32 vector units
-        # plus M2L on the bf16 matrix cores at three products per FP32-accurate
-        # product; the two do not issue concurrently on a SIMD, so their
-        # minimum times add.
+        # with the P2P-only k_p2p_side beside it on forked streams (stage
+        # "queue": HIP events from before k_queue on the plan's stream to
+        # the join of the side streams).  Its ALU bound on the method's own
+        # work: P2P flops on the FP32 vector units and M2L flops (2 P^2 per
+        # pair) on the bf16 matrix cores, the dtype of the contraction; the
+        # two do not issue concurrently on a SIMD, so their minimum times add.
         tq = stage_avg.get("queue", 0.0) * 1e-3
-        t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
-        # the same bound with the FP32 vector rate without packed FP32 (half
-        # of 157.3 TF; packed FP32 instructions are disabled at compile time)
-        t_np = p2p_flop / (PEAK["fp32_valu"] / 2) + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
-        roof = {"bound": "alu", "achieved": (p2p_flop + m2l_f) / tq / 1e12 if tq > 0 else None,
-                "peak": (p2p_flop + m2l_f) / t_min / 1e12, "unit": "TFLOP/s", "traffic": committed_traffic(workload),
+        flops = p2p_flop + m2l_f
+        t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f / PEAK["bf16_mfma"]
+        roof = {"bound": "alu", "achieved": flops / tq / 1e12 if tq > 0 else None,
+                "peak": flops / t_min / 1e12, "unit": "TFLOP/s", "traffic": committed_traffic(workload, tuning),
                 "kernel": "k_queue + k_p2p_side (P2P FP32 VALU + M2L split-bf16 MFMA)", "kernel_ms": tq * 1e3,
-                "peak_basis": "P2P flop / 157.3 TF fp32 vector + 3 x M2L flop / 2.5 PF bf16 dense MFMA",
-                "peak_nonpacked_fp32": (p2p_flop + m2l_f) / t_np / 1e12}
+                "peak_basis": "P2P flop / 157.3 TF fp32 vector + M2L flop (2 P^2 per pair) / 2.5 PF bf16 dense MFMA"}
+        # the bound the implementation's own instruction mix allows: three
+        # bf16 products per FP32-accurate M2L product (split operands), and
+        # the FP32 vector rate without packed FP32 (half of 157.3 TF; packed
+        # FP32 instructions are disabled at compile time)
+        t_split = p2p_flop / PEAK["fp32_valu"] + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
+        t_np = p2p_flop / (PEAK["fp32_valu"] / 2) + m2l_f * M2L_SPLIT_PRODUCTS / PEAK["bf16_mfma"]
+        roof["split_products"] = {"peak": flops / t_split / 1e12, "basis": "3 bf16 products per M2L product"}
+        roof["split_products_nonpacked_fp32"] = {"peak": flops / t_np / 1e12,
+                                                 "basis": "3 bf16 products per M2L product, FP32 vector rate 78.65 TF"}
         if tq > 0:
-            roof["frac_nonpacked_fp32"] = (p2p_flop + m2l_f) / tq / 1e12 / roof["peak_nonpacked_fp32"]
+            for k in ("split_products", "split_products_nonpacked_fp32"):
+                roof[k]["frac"] = flops / tq / 1e12 / roof[k]["peak"]
     else:
         dom, t, f = ("p2p", t_p2p, p2p_flop) if t_p2p >= t_m2l else ("m2l", t_m2l, m2l_f)
         roof = {"bound": "alu", "achieved": f / t / 1e12 if t > 0 else None, "peak": PEAK["fp64"] / 1e12,
@@ -197,7 +243,8 @@ def calib_copy(mib, torch, dev):
 def base_result(a, value, ms, unit_metric):
     return {"metric": unit_metric, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": a.steps,
             "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f32+f64" if a.precision == "mixed" else "f64", "data": "synthetic"}
+            "vs_baseline": None, "dtype": "bf16x3-mfma+f32+f64" if a.precision == "mixed" else "f64",
+            "data": "synthetic"}
 
 
 def run_single(a, torch, fmm, W):
@@ -211,6 +258,7 @@ def run_single(a, torch, fmm, W):
     plan = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0)
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     field = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    force = torch.empty((n, 3), dtype=torch.float64, device=dev)
     energy = torch.empty(1, dtype=torch.float64, device=dev)
     gE = torch.ones(1, dtype=torch.float64, device=dev)
     grads = [None, None]
@@ -233,7 +281,7 @@ def run_single(a, torch, fmm, W):
     def step():
         plan.build_tree(dpos, dq)
         plan.upward()
-        plan.evaluate_into(phi=phi, field=field, energy=energy)
+        plan.evaluate_into(phi=phi, field=field, force=force, energy=energy)
         if a.adjoint:
             ev[0].record()
             grads[0], grads[1] = plan.backward(gE)
@@ -246,7 +294,7 @@ def run_single(a, torch, fmm, W):
         stage_avg["backward"] = bw_ms[0] / (a.steps + a.warmup + max(a.warmup, 1))
     print("bench: %.3f ms/step; stages %s" % (ms, json.dumps({k: round(v, 4) for k, v in stage_avg.items()})),
           file=sys.stderr, flush=True)
-    roof, work = queue_roofline(plan, stage_avg, w["p"], n, a.precision, a.workload)
+    roof, work = queue_roofline(plan, stage_avg, w["p"], n, a.precision, a.workload, tuning)
     if a.adjoint:
         metric = "particles/s per FMM energy + gradient (forward + fmm_backward), %s" % a.workload
     else:
@@ -261,20 +309,8 @@ def run_single(a, torch, fmm, W):
     result["tuning"] = tuning
     result["work"] = work
     result["roofline"] = roof
-    if a.trace and a.precision == "mixed":
-        # outside the timed region: a second plan with the task trace on
-        from paper_1203_0889_amd import trace as T
-        tp = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0, trace=True)
-        tp.set_tuning(**tuning)
-        for _ in range(2):
-            tp.build_tree(dpos, dq)
-            tp.upward()
-            tp.evaluate_into(phi=phi, field=field, energy=energy)
-        result["trace"] = T.summarize(tp.trace())
-        print("bench: task trace %s" % json.dumps(result["trace"]), file=sys.stderr, flush=True)
-        tp.close()
     if not a.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(w, min(a.cpu_n, n))
+        result["cpu_baseline"] = cpu_baseline(w, min(a.cpu_n, n) if a.cpu_n > 0 else n, a.cpu_n_1core)
     if not a.no_error:
         import oracle
         sample = W.error_sample(n, w["seed"])
@@ -318,7 +354,7 @@ def run_batch(a, torch, fmm, W):
         plan.evaluate_into(phi=phi, field=field, energy=energy)
 
     ms, stage_avg = timed(step, plan, a.steps, a.warmup, torch)
-    roof, work = queue_roofline(plan, stage_avg, p, n, a.precision, "batch256_p6")
+    roof, work = queue_roofline(plan, stage_avg, p, n, a.precision, "batch256_p6", tuning)
     # graph replay of upward + evaluate on the built forest
     plan.graph_capture(phi=phi, field=field, energy=energy)
     for _ in range(a.warmup):
@@ -380,9 +416,7 @@ def run_sweep(a, torch, fmm, W):
     cubes of N = 1e5, 1e6, 1e7 particles, p = 6 and 9 (ncrit 64, theta 1/2,
     mixed), M2L class entries per task in {16, 32, 64, 128} (the task size,
     the analogue of Q) with the default launch shape.  Per point: the mean of
-    3 timed steps (build + upward + evaluate, HIP events per stage) and the
-    balance of one traced evaluation."""
-    from paper_1203_0889_amd import trace as T
+    3 timed steps (build + upward + evaluate, HIP events per stage)."""
     dev = torch.device("cuda", 0)
     rows = []
     for n in (100000, 1000000, 10000000):
@@ -391,24 +425,16 @@ def run_sweep(a, torch, fmm, W):
         for p in (6, 9):
             for entries in (16, 32, 64, 128):
                 row = {"n": n, "p": p, "m2l_task_entries": entries}
-                for traced in (False, True):
-                    plan = fmm.Plan(p=p, ncrit=64, theta=(1, 2), precision="mixed", device=0, trace=traced)
-                    plan.set_tuning(m2l_task_entries=entries, grid_per_cu=1, p2p_per_cu=2)
+                plan = fmm.Plan(p=p, ncrit=64, theta=(1, 2), precision="mixed", device=0)
+                plan.set_tuning(m2l_task_entries=entries, grid_per_cu=1, p2p_per_cu=2)
 
-                    def step():
-                        plan.build_tree(dpos, dq)
-                        plan.upward()
-                        plan.evaluate(force=False, energy=False)
-                    if traced:
-                        step()
-                        s = T.summarize(plan.trace())
-                        row.update({"m2l_tasks": s["m2l"]["tasks"], "m2l_task_median_us": s["m2l"]["median_us"],
-                                    "cu_busy_imbalance": s["cu_busy_imbalance"],
-                                    "tail_us": s["cu_last_end_us"]["max"] - s["cu_last_end_us"]["min"]})
-                    else:
-                        ms, st = timed(step, plan, 3, 1, torch)
-                        row.update({"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3), "queue_ms": st["queue"]})
-                    plan.close()
+                def step():
+                    plan.build_tree(dpos, dq)
+                    plan.upward()
+                    plan.evaluate(force=False, energy=False)
+                ms, st = timed(step, plan, 3, 1, torch)
+                row.update({"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3), "queue_ms": st["queue"]})
+                plan.close()
                 print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
                 rows.append(row)
     return {"sweep": "M2L class entries per task x N x p, uniform, ncrit 64, theta 1/2, mixed", "rows": rows}
@@ -418,6 +444,9 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: runs on one GPU only (--gpus %d refused)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    if a.trace:
+        print("bench.py: --trace refused: the library does not record the device task trace", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1203_0889_amd import fmm, workloads as W

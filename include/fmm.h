@@ -65,9 +65,11 @@ enum {
                                         the stored sort permutation): a frozen
                                         topology, as finite-difference checks of
                                         the adjoint need */
-    FMM_FLAG_TRACE = 1u << 2          /* mixed precision: the work queue of
-                                        fmm_evaluate records one fmm_task_record
-                                        per task it runs (fmm_get_trace) */
+    FMM_FLAG_TRACE = 1u << 2          /* device task trace of the work queue:
+                                        not available; fmm_create returns
+                                        FMM_ERR_UNSUPPORTED for it with mixed
+                                        precision, and the FP64 path, which
+                                        has no queue, records nothing */
 };
 
 typedef struct {
@@ -92,8 +94,9 @@ typedef struct fmm_plan fmm_plan; /* opaque; owns all device workspaces */
  * (a hipStream_t; NULL = the null stream).  params is copied. */
 fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fmm_plan **out);
 
-/* Release every device allocation of the plan (synchronises its stream).
- * NULL is accepted. */
+/* Release every device allocation of the plan.  First waits for the plan's
+ * stream and for every internal stream of the plan, so no kernel of the
+ * plan still runs on its memory.  NULL is accepted. */
 fmm_status fmm_destroy(fmm_plan *plan);
 
 /*
@@ -233,14 +236,9 @@ fmm_status fmm_autotune(fmm_plan *plan, int32_t repeats, fmm_tuning *best, doubl
 fmm_status fmm_get_stage_times(const fmm_plan *plan, double *times, const char **names);
 
 /*
- * Device task trace (the per-task timeline the paper draws for its runtime,
- * Sec. 5): with FMM_FLAG_TRACE, every task the work queue of the last
- * fmm_evaluate ran, in completion order.  Times are ticks of the device's
- * constant 100 MHz real-time clock (s_memrealtime), from the claim of the
- * task to its completion (for an M2L task: all four waves of its workgroup
- * done).  hw_id is the raw HW_ID register of the recording wave: compute
- * unit bits 11:8, SIMD 5:4, shader array 12, shader engine 15:13; xcc is the
- * XCD.
+ * Device task trace record (the per-task timeline the paper draws for its
+ * runtime, Sec. 5).  The layout is kept for callers of fmm_get_trace, but no
+ * plan records a trace at present (see FMM_FLAG_TRACE).
  */
 typedef struct {
     uint64_t start, end;
@@ -252,10 +250,10 @@ typedef struct {
     uint32_t reserved;
 } fmm_task_record;
 
-/* Copy up to cap records of the last traced queue run to host memory
- * (synchronous); *count (host, may be NULL) receives the number recorded.
- * Without FMM_FLAG_TRACE, or before fmm_evaluate, *count = 0.  The FP64
- * path has no queue and records nothing. */
+/* Copy up to cap records of the last traced queue run to host memory;
+ * *count (host, may be NULL) receives the number recorded, which is 0 for
+ * every plan (see FMM_FLAG_TRACE).  cap < 0, or cap > 0 with records NULL,
+ * is FMM_ERR_INVALID_ARG. */
 fmm_status fmm_get_trace(const fmm_plan *plan, fmm_task_record *records, int64_t cap, int64_t *count);
 
 const char *fmm_status_string(fmm_status status);

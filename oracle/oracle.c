@@ -922,3 +922,14 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of later OpenMP regions (timing on a stated number of cores). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -61,6 +61,7 @@ def _load():
     lib.orc_l2p.argtypes = [I32, _d, _d, I64, _d, _d, _d]
     lib.orc_taylor.argtypes = [I32, _d, _d]
     lib.orc_num_threads.restype = I32
+    lib.orc_set_num_threads.argtypes = [I32]
     _lib = lib
     return lib
 
@@ -79,6 +80,11 @@ def _p(a, t):
 def num_threads() -> int:
     """OpenMP threads the oracle uses."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's later calls."""
+    _load().orc_set_num_threads(int(n))
 
 
 def direct(pos, q, targets=None):

@@ -24,10 +24,6 @@ struct NearFarArgs {
     // multipoles, qs the adjoint weights; operators are stored transposed.
     bool transposed = false;
     HostReader *reader = nullptr;  // fast device-to-host reads (optional)
-    // task trace of the queue (optional): records, counter, capacity
-    fmm_task_record *trace = nullptr;
-    int32_t *trace_count = nullptr;
-    int32_t trace_cap = 0;
     // set when build_p2p_leaves already ran on another stream: the build
     // waits for this event instead of building the P2P leaf order itself
     hipEvent_t p2p_ready = nullptr;

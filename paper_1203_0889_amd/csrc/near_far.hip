@@ -244,9 +244,6 @@ QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
     q.fld = a.fld;
     q.lists = st.lists.as<int4>();
     q.heads = st.cnt.as<int32_t>() + 40;
-    q.trace = a.trace && a.trace_count && a.trace_cap > 0 ? a.trace : nullptr;
-    q.trace_count = a.trace_count;
-    q.trace_cap = a.trace_cap;
     return q;
 }
 
@@ -258,7 +255,6 @@ bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool 
                     !st.lists.ptr))
         throw std::runtime_error("mixed near/far stage: queue inputs not prepared");
     QueueArgs q = queue_args(st, a);
-    if (q.trace) fill_zero(a.trace_count, sizeof(int32_t), s);
     const int ncu = compute_units();
     const int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
     const int side_per_cu = std::max(0, std::min(8, a.tuning.p2p_per_cu));

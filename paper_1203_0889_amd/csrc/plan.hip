@@ -113,9 +113,6 @@ struct fmm_plan {
     fmm::NearFarState nf_t;
     fmm::HostReader reader;
     DevBuf phi_near, fld_near, phi_far, fld_far, echunk, epart;
-    DevBuf trace, trace_count;   // task trace of the forward queue (FMM_FLAG_TRACE)
-    int32_t trace_cap = 0;
-    bool traced = false;
     int32_t nechunk = 0;
     fmm::NearFarState nf;
     fmm_tuning tuning;
@@ -562,6 +559,17 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     fmm::Geometry g = geom(p);
     const int32_t ncell = (int32_t)p->ncell;
     bool deferred = false;   // the queue's P2P tail still runs on the second stream
+    // if anything below throws while the tail runs, the plan's stream still
+    // waits for it: later work on this stream (the next evaluation's
+    // zeroing of the claim counters and rewrite of the FP32 particles, a
+    // release of the plan) must not overlap it
+    struct DeferredJoin {
+        fmm_plan *p;
+        bool pending = false;
+        ~DeferredJoin() {
+            if (pending && p->nf.join) (void)hipStreamWaitEvent(p->stream, p->nf.join, 0);
+        }
+    } join_guard{p};
     record(p, ST_M2L);
     if (p->prm.precision == FMM_PREC_FP64) {
         fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
@@ -574,23 +582,14 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         mark(p, ST_P2P);
     } else {
         fmm::NearFarArgs a = nf_args(p);
-        if (p->prm.flags & FMM_FLAG_TRACE) {
-            // one record per task: M2L tasks plus target leaves
-            const int64_t cap = (int64_t)p->nf.ntask + p->nleaf;
-            FMM_HIP_CHECK(p->trace.grow((size_t)std::max<int64_t>(cap, 1) * sizeof(fmm_task_record)));
-            FMM_HIP_CHECK(p->trace_count.grow(sizeof(int32_t)));
-            p->trace_cap = (int32_t)cap;
-            a.trace = p->trace.as<fmm_task_record>();
-            a.trace_count = p->trace_count.as<int32_t>();
-            a.trace_cap = p->trace_cap;
-            p->traced = true;
-        }
         fmm::near_far_prepare(p->nf, a, s);
         mark(p, ST_NF_PREP);
         // with a P2P side kernel the queue's P2P tail runs on beside the
         // FP64 M2L rest, L2L and L2P; the near field is joined before the
         // outputs
+        join_guard.pending = true;   // also if the launch itself throws half way
         deferred = fmm::near_far_queue(p->nf, a, s, /*defer_join=*/true);
+        join_guard.pending = deferred;
         if (!deferred) {
             mark(p, ST_QUEUE);
         } else if (p->ev_ok && !p->capturing && p->last_ev) {
@@ -628,6 +627,7 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     fmm::FinalOut out_e;   // outputs written by the energy pass (deferred queue with an energy)
     if (deferred) {
         fmm::near_far_join(p->nf, s);
+        join_guard.pending = false;
         if (energy && (phi || field || force)) {
             out_e.perm = p->idx.as<uint32_t>();
             out_e.qs = p->qs.as<double>();
@@ -785,6 +785,8 @@ fmm_status check_params(const fmm_params *q, std::string *why) {
         return *why = "unknown precision", FMM_ERR_INVALID_ARG;
     if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY | FMM_FLAG_TRACE))
         return *why = "unknown flag", FMM_ERR_INVALID_ARG;
+    if ((q->flags & FMM_FLAG_TRACE) && q->precision == FMM_PREC_MIXED)
+        return *why = "the device task trace of the work queue is not available", FMM_ERR_UNSUPPORTED;
     if ((q->flags & FMM_FLAG_USER_BOX) &&
         !(q->box_side > 0 && std::isfinite(q->box_side) && std::isfinite(q->box_min[0]) &&
           std::isfinite(q->box_min[1]) && std::isfinite(q->box_min[2])))
@@ -840,8 +842,14 @@ fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fm
 fmm_status fmm_destroy(fmm_plan *p) {
     if (!p) return FMM_OK;
     hipSetDevice(p->device);
+    // every stream that may still run kernels on plan memory drains before
+    // any buffer is released: the plan's stream, the build's second stream
+    // (an interrupted build) and the side streams of both work queues (a
+    // P2P tail whose join was never enqueued)
     hipStreamSynchronize(p->stream);
-    if (p->up_side) hipStreamSynchronize(p->up_side);   // an upward pass of an interrupted build
+    hipStream_t others[] = {p->up_side, p->nf.side, p->nf.side2, p->nf_t.side, p->nf_t.side2};
+    for (hipStream_t o : others)
+        if (o) hipStreamSynchronize(o);
     DevBuf *all[] = {&p->off, &p->ord, &p->flag, &p->box, &p->scale, &p->keys, &p->kalt, &p->idx, &p->valt,
                      &p->ikey, &p->ialt, &p->rank, &p->ralt, &p->tmp, &p->xs, &p->ys, &p->zs, &p->qs,
                      &p->leaf_of, &p->bounds, &p->nch, &p->counters, &p->front[0], &p->front[1], &p->m2l_pairs,
@@ -849,8 +857,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
                      &p->L, &p->ops_m2m, &p->ops_l2l, &p->m2m_part, &p->phi_near, &p->fld_near, &p->phi_far,
                      &p->fld_far, &p->echunk, &p->epart, &p->ops_m2m_t, &p->ops_l2l_t, &p->m2l_t_ptr,
                      &p->m2l_t_src, &p->p2p_t_ptr, &p->p2p_t_src, &p->tkeys, &p->tkeys_alt, &p->lam, &p->mu,
-                     &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far, &p->trace,
-                     &p->trace_count, &p->pair_alt2, &p->tmp2};
+                     &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far, &p->pair_alt2, &p->tmp2};
     drop_graph(p);
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
@@ -893,7 +900,6 @@ fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, c
         }
         p->state = kStateCreated;
         p->adj_ready = false;
-        p->traced = false;
         drop_graph(p);
         p->n = n;
         p->n_inst = n_inst;
@@ -1154,21 +1160,11 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
 }
 
 fmm_status fmm_get_trace(const fmm_plan *cp, fmm_task_record *records, int64_t cap, int64_t *count) {
-    fmm_plan *p = const_cast<fmm_plan *>(cp);
-    if (!p || cap < 0 || (cap > 0 && !records)) return FMM_ERR_INVALID_ARG;
-    return guarded(p, [&]() -> fmm_status {
-        int32_t n = 0;
-        if (p->traced && p->trace_count.ptr) {
-            FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
-            FMM_HIP_CHECK(hipMemcpy(&n, p->trace_count.ptr, sizeof(int32_t), hipMemcpyDeviceToHost));
-            n = std::min(n, p->trace_cap);
-        }
-        if (count) *count = n;
-        const int64_t m = std::min<int64_t>(n, cap);
-        if (m > 0)
-            FMM_HIP_CHECK(hipMemcpy(records, p->trace.ptr, (size_t)m * sizeof(fmm_task_record), hipMemcpyDeviceToHost));
-        return FMM_OK;
-    });
+    if (!cp || cap < 0 || (cap > 0 && !records)) return FMM_ERR_INVALID_ARG;
+    // no plan records a trace: fmm_create refuses FMM_FLAG_TRACE for the
+    // mixed path, and the FP64 path has no work queue
+    if (count) *count = 0;
+    return FMM_OK;
 }
 
 fmm_status fmm_get_stage_times(const fmm_plan *cp, double *times, const char **names) {

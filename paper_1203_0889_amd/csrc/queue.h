@@ -35,11 +35,6 @@ struct QueueArgs {
     int32_t *heads;            // 16 claim counters (zeroed before launch)
     int32_t role_split;        // set by queue_run
     int32_t m2l_only;          // set by queue_run: k_queue leaves the P2P tasks to k_p2p_side
-    // task trace (null: off): records, their counter (zeroed before the
-    // launch) and capacity; records past the capacity are dropped
-    fmm_task_record *trace;
-    int32_t *trace_count;
-    int32_t trace_cap;
 };
 
 bool queue_supported(int p);

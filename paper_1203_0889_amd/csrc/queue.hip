@@ -428,25 +428,8 @@ __device__ void m2l_group(const QueueArgs &a, int4 task, int w, int lane, v4f *r
 template <int RT>
 constexpr int queue_lds_f4() { return ring_f4<RT>() > 4 * kP2PTile ? ring_f4<RT>() : 4 * kP2PTile; }
 
-// One task record (task trace on): written by one lane.
-__device__ inline void trace_task(const QueueArgs &a, int kind, int32_t task, int kernel, uint64_t t0) {
-    const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
-    const int32_t i = atomicAdd(a.trace_count, 1);
-    if (i >= a.trace_cap) return;
-    fmm_task_record r;
-    r.start = t0;
-    r.end = t1;
-    r.kind = kind;
-    r.task = task;
-    r.kernel = kernel;
-    r.hw_id = (uint32_t)__builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (31 << 11));
-    r.xcc = (uint32_t)__builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (15 << 11));
-    r.reserved = 0;
-    a.trace[i] = r;
-}
-
 // All P2P tasks this wave can claim, own XCD's list first.
-__device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__restrict__ tile, int kernel) {
+__device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__restrict__ tile) {
     for (int k = 0; k < 8; k++) {
         const int L = (((x + k) & 7) << 1) | 1;
         const int4 li = a.lists[L];
@@ -455,10 +438,7 @@ __device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__
             if (lane == 0) t = atomicAdd(&a.heads[L], 1);
             t = __builtin_amdgcn_readfirstlane(t);      // lane 0's claim, wave-uniform
             if (t >= li.y) break;
-            const int32_t leaf = a.leaves[li.z + t];
-            const uint64_t t0 = a.trace ? __builtin_amdgcn_s_memrealtime() : 0;
-            p2p_leaf(a, leaf, tile, lane);
-            if (a.trace && lane == 0) trace_task(a, 1, leaf, kernel, t0);
+            p2p_leaf(a, a.leaves[li.z + t], tile, lane);
         }
     }
 }
@@ -476,30 +456,20 @@ __global__ void __launch_bounds__(256, (RT <= 3 ? 2 : 1)) k_queue(QueueArgs a) {
     const int role = a.role_split ? (__builtin_amdgcn_s_getreg((4 << 0) | (16 << 6) | (3 << 11)) & 1) : 0;
     for (int ph = 0; ph < 2; ph++) {
         if ((ph ^ role) == 0) {
-            // traced: the record of a task is written after the barrier
-            // that follows it, when all four waves are done
-            int32_t done = -1;
-            uint64_t t0 = 0;
             for (int k = 0; k < 8; k++) {
                 const int L = ((x + k) & 7) << 1;
                 const int4 li = a.lists[L];
                 for (;;) {
                     __syncthreads();
-                    if (a.trace && done >= 0 && threadIdx.x == 0) trace_task(a, 0, done, 0, t0);
-                    done = -1;
                     if (threadIdx.x == 0) claim = atomicAdd(&a.heads[L], 1);
                     __syncthreads();
                     const int32_t t = __builtin_amdgcn_readfirstlane(claim);
                     if (t >= li.y) break;
-                    if (a.trace) {
-                        t0 = __builtin_amdgcn_s_memrealtime();
-                        done = li.x + t;
-                    }
                     m2l_group<RT>(a, a.m2l_tasks[li.x + t], w, lane, lds);
                 }
             }
         } else if (!a.m2l_only) {
-            p2p_phase(a, x, lane, reinterpret_cast<float4 *>(lds) + w * kP2PTile, 0);
+            p2p_phase(a, x, lane, reinterpret_cast<float4 *>(lds) + w * kP2PTile);
         }
         __syncthreads();   // the LDS changes role
     }
@@ -512,7 +482,7 @@ __global__ void __launch_bounds__(256, (RT <= 3 ? 2 : 1)) k_queue(QueueArgs a) {
 __global__ void __launch_bounds__(256) k_p2p_side(QueueArgs a) {
     __shared__ float4 tiles[4 * kP2PTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    p2p_phase(a, blockIdx.x & 7, lane, tiles + w * kP2PTile, 1);
+    p2p_phase(a, blockIdx.x & 7, lane, tiles + w * kP2PTile);
 }
 
 // ------------------------------------------------------------------ prep

@@ -107,11 +107,18 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _check_dev(t, name, dtype=torch.float64, shape_tail=()):
+def _check_dev(t, name, dtype=torch.float64, shape_tail=(), shape=None, device=None):
+    """A device tensor the library reads or writes: the kernels index it as a
+    contiguous FP64 array of the given shape, so anything else is refused
+    here, before a pointer reaches the library."""
     if not isinstance(t, torch.Tensor):
         raise TypeError("%s must be a torch tensor" % name)
     if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
         raise ValueError("%s must be a contiguous %s tensor on the GPU" % (name, dtype))
+    if device is not None and t.device.index != device:
+        raise ValueError("%s must be on cuda:%d, the plan's device" % (name, device))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, not %s" % (name, tuple(shape), tuple(t.shape)))
     if shape_tail and tuple(t.shape[1:]) != shape_tail:
         raise ValueError("%s must have shape (N, %s)" % (name, ", ".join(map(str, shape_tail))))
 
@@ -173,8 +180,8 @@ class Plan:
     def build_tree(self, pos, q, offsets=None):
         """Keys, sort, octree and interaction lists.  offsets (host ints,
         n_inst + 1) batches independent instances."""
-        _check_dev(pos, "pos", shape_tail=(3,))
-        _check_dev(q, "q")
+        _check_dev(pos, "pos", shape_tail=(3,), device=self.device)
+        _check_dev(q, "q", device=self.device)
         n = pos.shape[0]
         if q.shape != (n,):
             raise ValueError("q must have shape (N,)")
@@ -201,14 +208,24 @@ class Plan:
                    _ptr(out["energy"]))
         return out
 
+    def _check_outputs(self, **named):
+        """Shapes the library writes: phi (N,), field and force (N, 3),
+        energy (n_inst,), grad_pos (N, 3), grad_q (N,), grad_energy (n_inst,)."""
+        shapes = {"phi": (self.n,), "field": (self.n, 3), "force": (self.n, 3), "energy": (self.n_inst,),
+                  "grad_energy": (self.n_inst,), "grad_pos": (self.n, 3), "grad_q": (self.n,)}
+        for name, t in named.items():
+            if t is not None:
+                _check_dev(t, name, shape=shapes[name], device=self.device)
+
     def evaluate_into(self, phi=None, field=None, force=None, energy=None):
+        self._check_outputs(phi=phi, field=field, force=force, energy=energy)
         self._call(self._lib.fmm_evaluate, _ptr(phi), _ptr(field), _ptr(force), _ptr(energy))
 
     def backward(self, grad_energy, want_pos=True, want_q=True):
         """Gradient of sum_k grad_energy[k] E_k (the FMM's energies) with
         respect to positions and charges: (grad_pos (N, 3), grad_q (N,))."""
         dev = torch.device("cuda", self.device)
-        _check_dev(grad_energy, "grad_energy")
+        self._check_outputs(grad_energy=grad_energy)
         gp = torch.empty((self.n, 3), dtype=torch.float64, device=dev) if want_pos else None
         gq = torch.empty(self.n, dtype=torch.float64, device=dev) if want_q else None
         self._call(self._lib.fmm_backward, _ptr(grad_energy), _ptr(gp), _ptr(gq))
@@ -219,6 +236,8 @@ class Plan:
                       grad_q=None):
         """Capture upward + evaluate (+ backward when grad_energy is given)
         into a HIP graph writing into the given tensors."""
+        self._check_outputs(phi=phi, field=field, force=force, energy=energy, grad_energy=grad_energy,
+                            grad_pos=grad_pos, grad_q=grad_q)
         self._graph_refs = (phi, field, force, energy, grad_energy, grad_pos, grad_q)
         self._call(self._lib.fmm_graph_capture, _ptr(phi), _ptr(field), _ptr(force), _ptr(energy), _ptr(grad_energy),
                    _ptr(grad_pos), _ptr(grad_q))

@@ -9,6 +9,7 @@ import torch
 
 import oracle
 from paper_1203_0889_amd import fmm, workloads as W
+from parity import MAX_FP64, MAX_MIXED, maxrel
 
 pytestmark = pytest.mark.gpu
 
@@ -94,8 +95,10 @@ def test_fp64_matches_oracle_fmm(case):
     phi_ref, fld_ref = T.fmm(case["q"], case["p"])
     out = case["out"]
     e_phi, e_fld = rel(out["phi"], phi_ref), rel(out["field"], fld_ref)
-    say(case["name"], "fp64 vs oracle fmm", e_phi, e_fld)
+    m_phi, m_fld = maxrel(out["phi"], phi_ref), maxrel(out["field"], fld_ref)
+    say(case["name"], "fp64 vs oracle fmm", e_phi, e_fld, "worst particle", m_phi, m_fld)
     assert e_phi < 1e-11 and e_fld < 1e-11
+    assert m_phi < MAX_FP64 and m_fld < MAX_FP64
     # force and energy follow from phi and field
     assert np.allclose(out["force"], case["q"][:, None] * out["field"], rtol=1e-15, atol=0)
     assert out["energy"][0] == pytest.approx(0.5 * np.dot(case["q"], out["phi"]), rel=1e-12)
@@ -176,6 +179,8 @@ def test_user_box_matches_oracle():
     assert np.array_equal(keys, T.keys) and np.array_equal(cells[:, :9], T.cells)
     phi_ref, fld_ref = T.fmm(q, 6)
     assert rel(out["phi"].cpu().numpy(), phi_ref) < 1e-11
+    assert maxrel(out["phi"].cpu().numpy(), phi_ref) < MAX_FP64
+    assert maxrel(out["field"].cpu().numpy(), fld_ref) < MAX_FP64
 
 
 def test_repeated_builds_reuse_plan():
@@ -189,6 +194,8 @@ def test_repeated_builds_reuse_plan():
         phi_ref, fld_ref, _ = oracle.fmm(pos, q, 6, 32, 1, 2)
         assert rel(out["phi"].cpu().numpy(), phi_ref) < 1e-11
         assert rel(out["field"].cpu().numpy(), fld_ref) < 1e-11
+        assert maxrel(out["phi"].cpu().numpy(), phi_ref) < MAX_FP64
+        assert maxrel(out["field"].cpu().numpy(), fld_ref) < MAX_FP64
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -198,9 +205,13 @@ def test_rebuilds_that_outgrow_the_last_tree(prec):
     last one (the octree's cell capacity and level batches are sized from
     the previous tree, so this takes the capacity retry and extra level
     batches), then a small one again.  Tree and lists stay bit-exact and the
-    potentials match the oracle."""
+    potentials match the oracle.  With 8 particles per leaf the far field
+    carries most of the potential, so the mixed path's error is set by the
+    split-bf16 M2L rounding (about 2^-17 per operand) rather than by the FP32
+    near field: 2e-5 relative L2 here instead of 1e-5."""
     plan = fmm.Plan(p=6, ncrit=8, theta=(1, 2), precision=prec, device=0)
     tol = 1e-11 if prec == "fp64" else 2e-5
+    mtol = MAX_FP64 if prec == "fp64" else MAX_MIXED
     for dist, n, seed in (("uniform", 3000, 31), ("plummer", 40000, 32), ("uniform", 2500, 33)):
         say("rebuild", prec, dist, n)
         pos, q = make(dist, n, seed)
@@ -216,7 +227,10 @@ def test_rebuilds_that_outgrow_the_last_tree(prec):
         for ptr, src, ref in ((mp, ms, T.m2l), (pp, ps, T.p2p)):
             assert np.array_equal(np.repeat(np.arange(T.ncell), np.diff(ptr)), ref[:, 0])
             assert np.array_equal(src, ref[:, 1])
-        phi_ref, _ = T.fmm(q, 6)
+        phi_ref, fld_ref = T.fmm(q, 6)
         e = rel(out["phi"].cpu().numpy(), phi_ref)
-        say("  depth", int(cells[:, 0].max()), "cells", T.ncell, "phi rel", e)
+        m_phi = maxrel(out["phi"].cpu().numpy(), phi_ref)
+        m_fld = maxrel(out["field"].cpu().numpy(), fld_ref)
+        say("  depth", int(cells[:, 0].max()), "cells", T.ncell, "phi rel", e, "worst particle", m_phi, m_fld)
         assert e < tol
+        assert m_phi < mtol and m_fld < mtol

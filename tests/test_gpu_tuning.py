@@ -6,7 +6,9 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_1203_0889_amd import fmm, workloads as W
+from parity import MAX_MIXED, maxrel
 
 pytestmark = pytest.mark.gpu
 
@@ -103,3 +105,23 @@ def test_launch_shapes_agree(dist):
         e = (rel(out["phi"], ref["phi"]), rel(out["field"], ref["field"]))
         print(dist, "shape", shape, e, flush=True)
         assert max(e) < 1e-12
+
+
+@pytest.mark.parametrize("entries", [1, 16, 96])
+def test_task_sizes_match_oracle(entries):
+    """The task-size knob (M2L class entries per task, the analogue of the
+    paper's granularity Q) away from its default: the results still match
+    the FP64 oracle FMM to the mixed path's bound, with a non-default launch
+    shape too."""
+    pos, q = W.plummer(25000, 64)
+    ref_phi, ref_fld, _ = oracle.fmm(pos, q, 6, 32, 1, 2)
+    plan = fmm.Plan(p=6, ncrit=32, theta=(1, 2), precision="mixed", device=0)
+    plan.set_tuning(m2l_task_entries=entries, grid_per_cu=2, p2p_per_cu=1)
+    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+    plan.upward()
+    out = {k: v.cpu().numpy() for k, v in plan.evaluate().items() if v is not None}
+    torch.cuda.synchronize()
+    e = (rel(out["phi"], ref_phi), rel(out["field"], ref_fld))
+    m = (maxrel(out["phi"], ref_phi), maxrel(out["field"], ref_fld))
+    print("entries", entries, "vs oracle", e, "worst particle", m, flush=True)
+    assert max(e) < 1e-5 and max(m) < MAX_MIXED
