@@ -103,7 +103,7 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="granularity sweep (the paper's Q experiment): M2L entries per task x N x p, one JSON line")
     ap.add_argument("--trace", action="store_true",
-                    help="refused: the library does not record the device task trace")
+                    help="after the timed steps, one evaluation with the device task trace: summary in the line")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -309,6 +309,21 @@ def run_single(a, torch, fmm, W):
     result["tuning"] = tuning
     result["work"] = work
     result["roofline"] = roof
+    if a.trace and a.precision == "mixed":
+        # outside the timed region: a second plan with the task trace on,
+        # writing into outputs of its own (the error check below reads the
+        # timed plan's outputs)
+        from paper_1203_0889_amd import trace as T
+        tp = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0, trace=True)
+        tp.set_tuning(**tuning)
+        t_phi, t_field = torch.empty_like(phi), torch.empty_like(field)
+        for _ in range(2):
+            tp.build_tree(dpos, dq)
+            tp.upward()
+            tp.evaluate_into(phi=t_phi, field=t_field)
+        result["trace"] = T.summarize(tp.trace())
+        print("bench: task trace %s" % json.dumps(result["trace"]), file=sys.stderr, flush=True)
+        tp.close()
     if not a.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w, min(a.cpu_n, n) if a.cpu_n > 0 else n, a.cpu_n_1core)
     if not a.no_error:
@@ -416,7 +431,9 @@ def run_sweep(a, torch, fmm, W):
     cubes of N = 1e5, 1e6, 1e7 particles, p = 6 and 9 (ncrit 64, theta 1/2,
     mixed), M2L class entries per task in {16, 32, 64, 128} (the task size,
     the analogue of Q) with the default launch shape.  Per point: the mean of
-    3 timed steps (build + upward + evaluate, HIP events per stage)."""
+    3 timed steps (build + upward + evaluate, HIP events per stage), the
+    number of M2L tasks, and the balance of one traced evaluation."""
+    from paper_1203_0889_amd import trace as T
     dev = torch.device("cuda", 0)
     rows = []
     for n in (100000, 1000000, 10000000):
@@ -425,16 +442,24 @@ def run_sweep(a, torch, fmm, W):
         for p in (6, 9):
             for entries in (16, 32, 64, 128):
                 row = {"n": n, "p": p, "m2l_task_entries": entries}
-                plan = fmm.Plan(p=p, ncrit=64, theta=(1, 2), precision="mixed", device=0)
-                plan.set_tuning(m2l_task_entries=entries, grid_per_cu=1, p2p_per_cu=2)
+                for traced in (False, True):
+                    plan = fmm.Plan(p=p, ncrit=64, theta=(1, 2), precision="mixed", device=0, trace=traced)
+                    plan.set_tuning(m2l_task_entries=entries, grid_per_cu=1, p2p_per_cu=2)
 
-                def step():
-                    plan.build_tree(dpos, dq)
-                    plan.upward()
-                    plan.evaluate(force=False, energy=False)
-                ms, st = timed(step, plan, 3, 1, torch)
-                row.update({"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3), "queue_ms": st["queue"]})
-                plan.close()
+                    def step():
+                        plan.build_tree(dpos, dq)
+                        plan.upward()
+                        plan.evaluate(force=False, energy=False)
+                    if traced:
+                        step()
+                        s = T.summarize(plan.trace())
+                        row.update({"m2l_tasks": plan.queue_info()["ntask"], "m2l_task_median_us": s["m2l"]["median_us"],
+                                    "cu_busy_imbalance": s["cu_busy_imbalance"],
+                                    "tail_us": s["cu_last_end_us"]["max"] - s["cu_last_end_us"]["min"]})
+                    else:
+                        ms, st = timed(step, plan, 3, 1, torch)
+                        row.update({"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3), "queue_ms": st["queue"]})
+                    plan.close()
                 print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
                 rows.append(row)
     return {"sweep": "M2L class entries per task x N x p, uniform, ncrit 64, theta 1/2, mixed", "rows": rows}
@@ -444,9 +469,6 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: runs on one GPU only (--gpus %d refused)" % a.gpus, file=sys.stderr)
-        sys.exit(2)
-    if a.trace:
-        print("bench.py: --trace refused: the library does not record the device task trace", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1203_0889_amd import fmm, workloads as W

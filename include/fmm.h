@@ -65,11 +65,16 @@ enum {
                                         the stored sort permutation): a frozen
                                         topology, as finite-difference checks of
                                         the adjoint need */
-    FMM_FLAG_TRACE = 1u << 2          /* device task trace of the work queue:
-                                        not available; fmm_create returns
-                                        FMM_ERR_UNSUPPORTED for it with mixed
-                                        precision, and the FP64 path, which
-                                        has no queue, records nothing */
+    FMM_FLAG_DETERMINISTIC = 1u << 3, /* bitwise reproducible results: every
+                                        floating-point sum is taken in a fixed
+                                        order (each target's sources sorted in
+                                        the lists, per-owner FP64 M2L of the
+                                        pairs outside the class table without
+                                        atomics); the work queue's M2L sums are
+                                        in a fixed order in every mode */
+    FMM_FLAG_TRACE = 1u << 2          /* mixed precision: the work queue of
+                                        fmm_evaluate records one fmm_task_record
+                                        per task it runs (fmm_get_trace) */
 };
 
 typedef struct {
@@ -176,6 +181,18 @@ fmm_status fmm_get_counts(const fmm_plan *plan, int64_t *ncell, int64_t *nleaf, 
                           int64_t *np2p);
 
 /*
+ * Sizes of the work-queue tables of the mixed path after fmm_build_tree
+ * (host outputs; any may be NULL): the target cells of the batched M2L
+ * (cells owning at least one pair of the class table, Sec. 4 lists regrouped
+ * by class), their groups of 256, the M2L tasks (the task size is the
+ * paper's granularity knob, Sec. 5), the operator classes in use, and the
+ * M2L pairs left to the per-pair FP64 kernel.  The FP64 path has no queue:
+ * every count is 0.  Before a build: FMM_ERR_STATE.
+ */
+fmm_status fmm_get_queue_info(const fmm_plan *plan, int64_t *ntarget, int64_t *ngroup, int64_t *ntask,
+                              int64_t *nclass, int64_t *nextra);
+
+/*
  * Copy the tree to host memory (synchronous).  Cells are in canonical order:
  * by level, then instance, then Morton prefix.
  *   keys   host uint64[N]: Morton key of every particle, input order
@@ -236,9 +253,14 @@ fmm_status fmm_autotune(fmm_plan *plan, int32_t repeats, fmm_tuning *best, doubl
 fmm_status fmm_get_stage_times(const fmm_plan *plan, double *times, const char **names);
 
 /*
- * Device task trace record (the per-task timeline the paper draws for its
- * runtime, Sec. 5).  The layout is kept for callers of fmm_get_trace, but no
- * plan records a trace at present (see FMM_FLAG_TRACE).
+ * Device task trace (the per-task timeline the paper draws for its runtime,
+ * Sec. 5): with FMM_FLAG_TRACE, every task the work queue of the last
+ * fmm_evaluate ran, in completion order.  Times are ticks of the device's
+ * constant 100 MHz real-time clock (s_memrealtime), from the claim of the
+ * task to its completion (for an M2L task: all four waves of its workgroup
+ * done).  hw_id is the raw HW_ID register of the recording wave: compute
+ * unit bits 11:8, SIMD 5:4, shader array 12, shader engine 15:13; xcc is the
+ * XCD.
  */
 typedef struct {
     uint64_t start, end;
@@ -250,10 +272,10 @@ typedef struct {
     uint32_t reserved;
 } fmm_task_record;
 
-/* Copy up to cap records of the last traced queue run to host memory;
- * *count (host, may be NULL) receives the number recorded, which is 0 for
- * every plan (see FMM_FLAG_TRACE).  cap < 0, or cap > 0 with records NULL,
- * is FMM_ERR_INVALID_ARG. */
+/* Copy up to cap records of the last traced queue run to host memory
+ * (synchronous); *count (host, may be NULL) receives the number recorded.
+ * Without FMM_FLAG_TRACE, or before fmm_evaluate, *count = 0.  The FP64
+ * path has no queue and records nothing. */
 fmm_status fmm_get_trace(const fmm_plan *plan, fmm_task_record *records, int64_t cap, int64_t *count);
 
 const char *fmm_status_string(fmm_status status);

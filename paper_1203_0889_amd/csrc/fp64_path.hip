@@ -87,7 +87,9 @@ __global__ void __launch_bounds__(kP2P64Threads)
 // by binary search, accumulates while the owner stays the same and adds each
 // owner's run into the output with FP64 atomics (so an owner with thousands
 // of pairs, like a large leaf facing a dense region, is spread over many
-// waves).  Per pair, with rho the class offset (c_A - c_B) / S_A and
+// waves).  In owner mode (deterministic results) a wave takes all pairs of
+// one owner instead, in list order, and adds them to the output with plain
+// stores: the order of every addition is then fixed.  Per pair, with rho the class offset (c_A - c_B) / S_A and
 // delta = l_A - l_B of the forward pair A <- B:
 //   forward:  L~_n^m += (-1)^n sum_(k <= p) 2^(delta k) sum_l M~_k^l I_(n+k)^(m+l)(rho)
 //   adjoint:  the transpose of that real map (see below), owner = B.
@@ -115,7 +117,7 @@ __device__ inline int tri(int n, int m) { return n * (n + 1) / 2 + m; }
 template <bool kAdjoint>
 __global__ void __launch_bounds__(kM2L64Threads)
     k_m2l_pairs(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
-                int64_t npair, const double *__restrict__ In, double *__restrict__ Out) {
+                int64_t npair, const double *__restrict__ In, double *__restrict__ Out, int owner_mode) {
     __shared__ double Ire[kMaxI], Iim[kMaxI];
     __shared__ double Xs[ncoef(kMaxP)];
     const int lane = threadIdx.x;
@@ -135,15 +137,26 @@ __global__ void __launch_bounds__(kM2L64Threads)
         }
     }
     const int64_t nchunk = (npair + kPairChunk - 1) / kPairChunk;
-    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        const int64_t e0 = ch * kPairChunk, e1 = e0 + kPairChunk < npair ? e0 + kPairChunk : npair;
-        // owner of e0: the last cell O with ptr[O] <= e0
-        int32_t lo = 0, hi = ncell;
-        while (lo < hi) {
-            int32_t mid = (lo + hi + 1) >> 1;
-            if (ptr[mid] <= e0) lo = mid; else hi = mid - 1;
+    const int64_t nunit = owner_mode ? (int64_t)ncell : nchunk;
+    for (int64_t ch = blockIdx.x; ch < nunit; ch += gridDim.x) {
+        int64_t e0, e1;
+        int32_t O;
+        if (owner_mode) {
+            O = (int32_t)ch;
+            e0 = ptr[O];
+            e1 = ptr[O + 1];
+            if (e0 == e1) continue;   // uniform over the wave
+        } else {
+            e0 = ch * kPairChunk;
+            e1 = e0 + kPairChunk < npair ? e0 + kPairChunk : npair;
+            // owner of e0: the last cell O with ptr[O] <= e0
+            int32_t lo = 0, hi = ncell;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (ptr[mid] <= e0) lo = mid; else hi = mid - 1;
+            }
+            O = lo;
         }
-        int32_t O = lo;
         double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
         auto flush = [&](int32_t owner) {
             double *out = Out + (int64_t)owner * P;
@@ -153,8 +166,13 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 const int m = om[s];
                 double vr = accr[s];
                 if (kAdjoint && m == 0) vr *= 0.5;
-                atomicAdd(&out[cidx_re(n, m)], vr);
-                if (m > 0) atomicAdd(&out[cidx_im(n, m)], acci[s]);
+                if (owner_mode) {   // the only wave writing this owner
+                    out[cidx_re(n, m)] += vr;
+                    if (m > 0) out[cidx_im(n, m)] += acci[s];
+                } else {
+                    atomicAdd(&out[cidx_re(n, m)], vr);
+                    if (m > 0) atomicAdd(&out[cidx_im(n, m)], acci[s]);
+                }
                 accr[s] = acci[s] = 0.0;
             }
         };
@@ -291,24 +309,25 @@ __global__ void __launch_bounds__(kM2L64Threads)
 
 namespace {
 void launch_pairs(bool adjoint, Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
-                  const double *In, double *Out, hipStream_t s) {
+                  const double *In, double *Out, bool owner_mode, hipStream_t s) {
     if (ncell == 0 || npair <= 0) return;
-    const int64_t nchunk = (npair + kPairChunk - 1) / kPairChunk;
-    const int grid = (int)(nchunk < 65536 ? nchunk : 65536);
+    const int64_t nunit = owner_mode ? (int64_t)ncell : (npair + kPairChunk - 1) / kPairChunk;
+    const int grid = (int)(nunit < 65536 ? nunit : 65536);
+    const int om = owner_mode ? 1 : 0;
     if (adjoint)
         hipLaunchKernelGGL(k_m2l_pairs<true>, dim3(grid), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, npair,
-                           In, Out);
+                           In, Out, om);
     else
         hipLaunchKernelGGL(k_m2l_pairs<false>, dim3(grid), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, npair,
-                           In, Out);
+                           In, Out, om);
     FMM_LAUNCH_CHECK();
 }
 }  // namespace
 
 void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *ptr_t, const int32_t *src_t,
-                             int64_t npair, const double *Lam, double *Mu, int add, hipStream_t s) {
+                             int64_t npair, const double *Lam, double *Mu, int add, bool owner_mode, hipStream_t s) {
     if (!add) fill_zero(Mu, (size_t)ncell * ncoef(p) * sizeof(double), s);
-    launch_pairs(true, g, ncell, p, ptr_t, src_t, npair, Lam, Mu, s);
+    launch_pairs(true, g, ncell, p, ptr_t, src_t, npair, Lam, Mu, owner_mode, s);
 }
 
 void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
@@ -320,14 +339,14 @@ void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_
 }
 
 void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
-                     const double *M, double *L, hipStream_t s) {
+                     const double *M, double *L, bool owner_mode, hipStream_t s) {
     fill_zero(L, (size_t)ncell * ncoef(p) * sizeof(double), s);
-    launch_pairs(false, g, ncell, p, ptr, src, npair, M, L, s);
+    launch_pairs(false, g, ncell, p, ptr, src, npair, M, L, owner_mode, s);
 }
 
 void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
-                         const double *M, double *L, hipStream_t s) {
-    launch_pairs(false, g, ncell, p, ptr, src, npair, M, L, s);
+                         const double *M, double *L, bool owner_mode, hipStream_t s) {
+    launch_pairs(false, g, ncell, p, ptr, src, npair, M, L, owner_mode, s);
 }
 
 }  // namespace fmm

@@ -17,6 +17,12 @@ void m2l_pair_codes(CellArrays c, int32_t ncell, const int32_t *ptr, const int32
 // Slots for the marked keys (nslots[0] = slots in use, new_keys[0 ..
 // nslots[1]) = the keys given one now); clears the marks.
 void m2l_alloc_slots(int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, hipStream_t s);
+// The same for an empty store (slot_of all -1, nslots zero), with the slots
+// given in ascending key order: slot = rank of the key among the marked
+// ones, independent of thread timing.  rank holds kDenseKeys + 1 ints, tmp
+// scan_tmp_elems(kDenseKeys).
+void m2l_alloc_slots_ordered(int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, int32_t *rank,
+                             int32_t *tmp, hipStream_t s);
 // Split-bf16 operator blocks of the new classes (op_elems bf16 per class,
 // RT row tiles, layout as the work queue reads it).  transposed: the keys
 // come from transposed pairs (owner = forward source) and each block holds

@@ -115,6 +115,20 @@ __global__ void k_alloc_slots(int32_t *__restrict__ used, int32_t nkeys, int32_t
     }
 }
 
+// Slots in key order: rank = exclusive scan of the marks, its total in
+// rank[nkeys].
+__global__ void k_alloc_slots_ordered(int32_t *__restrict__ used, int32_t nkeys, const int32_t *__restrict__ rank,
+                                      int32_t *__restrict__ slot_of, int32_t *__restrict__ nslots,
+                                      int32_t *__restrict__ new_keys) {
+    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nkeys; k += gridDim.x * blockDim.x) {
+        if (k == 0) nslots[0] = nslots[1] = rank[nkeys];
+        if (!used[k]) continue;
+        used[k] = 0;
+        slot_of[k] = rank[k];
+        new_keys[rank[k]] = k;
+    }
+}
+
 // operator slot of a pair code (-1: outside the table)
 __device__ inline int32_t code_slot(int32_t code, const int32_t *__restrict__ slot_of) {
     return code < -1 ? slot_of[-2 - code] : code;
@@ -305,6 +319,7 @@ __device__ inline void for_group_pairs(const uint64_t *__restrict__ tsorted, int
     const int nt = ntarget - t0 < kGroupM2L ? ntarget - t0 : kGroupM2L;
     for (int sl = split + kSplit * w; sl < nt; sl += kSplit * kGroupWaves) {   // uniform over the wave
         const int32_t A = (int32_t)(tsorted[t0 + sl] & 0xffffffffull);
+        if (A < 0) continue;   // a key without table pairs (never within ntarget)
         const int32_t end = ptr[A + 1];
         for (int32_t e0 = ptr[A] + lane; e0 < end; e0 += 64 * kPairUnroll) {
             int32_t code[kPairUnroll], sv[kPairUnroll];
@@ -378,27 +393,18 @@ __global__ void __launch_bounds__(256) k_group_prefix(int nwords, const uint32_t
 }
 
 // The number of targets: the sorted target keys end with the ~0 keys of
-// the cells without table pairs; one workgroup finds the first of them
-// (a coarse pass over 256 evenly spaced keys, then the interval it names).
-__global__ void __launch_bounds__(256) k_count_targets(const uint64_t *__restrict__ tsorted, int32_t ncell,
-                                                       int32_t *__restrict__ count) {
-    __shared__ int32_t first;
-    if (threadIdx.x == 0) first = 256;
-    __syncthreads();
-    const int32_t step = (ncell + 255) / 256;
-    const int32_t i = (int32_t)threadIdx.x * step;
-    if (i < ncell && tsorted[i] == ~0ull) atomicMin(&first, (int)threadIdx.x);
-    __syncthreads();
-    // the first ~0 key lies in ((first - 1) step, first step], or is ncell
-    const int32_t hi = first * step < ncell ? first * step : ncell;
-    const int32_t lo = first > 0 ? (first - 1) * step + 1 : 0;
-    __syncthreads();
-    if (threadIdx.x == 0) first = hi;
-    __syncthreads();
-    for (int32_t j = lo + (int32_t)threadIdx.x; j < hi; j += 256)
-        if (tsorted[j] == ~0ull) atomicMin(&first, (int)j);
-    __syncthreads();
-    if (threadIdx.x == 0) *count = first;
+// the cells without table pairs (their sorted bits hold 31 in the level
+// field, above every real level), so "key is ~0" is false then true along
+// the array; one thread finds the first ~0 key by binary search (ncell if
+// there is none).
+__global__ void k_count_targets(const uint64_t *__restrict__ tsorted, int32_t ncell, int32_t *__restrict__ count) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t lo = 0, hi = ncell;   // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (tsorted[mid] == ~0ull) hi = mid; else lo = mid + 1;
+    }
+    *count = lo;
 }
 
 // Exclusive scans of the per-group entry and task counts (goff, toff; the
@@ -521,6 +527,7 @@ __global__ void __launch_bounds__(64 * kGroupWaves) k_group_fill(
         __syncthreads();
         for (int sl = w; sl < kSlotsPerSplit && s0 + sl < nt; sl += kGroupWaves) {   // uniform over the wave
             const int32_t A = (int32_t)(tsorted[t0 + s0 + sl] & 0xffffffffull);
+            if (A < 0) continue;   // a key without table pairs (never within ntarget)
             const int32_t end = ptr[A + 1];
             for (int32_t e0 = ptr[A] + lane; e0 < end; e0 += 64 * kFillUnroll) {
                 int32_t code[kFillUnroll], sv[kFillUnroll];
@@ -563,7 +570,9 @@ __global__ void k_make_tasks(const int32_t *__restrict__ gcount, const int32_t *
         int32_t n = gcount[g], t = toff[g];
         int xcd = (int)((tsorted[(int64_t)g * kGroupM2L] >> 35) & 7ull);
         for (int32_t e = 0, j = 0; e < n; e += chunk, j++, t++) {
-            tasks[t] = make_int4(g, goff[g] + e, goff[g] + (e + chunk < n ? e + chunk : n), 0);
+            // .w: the task's slot in the partial-locals buffer, group-major
+            // (the group's tasks are toff[g] .. toff[g] + tcount[g] - 1)
+            tasks[t] = make_int4(g, goff[g] + e, goff[g] + (e + chunk < n ? e + chunk : n), t);
             // t is already in (group, chunk) order: a stable sort on the
             // (XCD, chunk index) bits above it yields (XCD, chunk, task)
             tkeys[t] = ((uint64_t)xcd << (32 + jbits)) | ((uint64_t)j << 32) | (uint32_t)t;
@@ -612,6 +621,14 @@ void m2l_alloc_slots(int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *
     FMM_LAUNCH_CHECK();
 }
 
+void m2l_alloc_slots_ordered(int32_t *used, int32_t *slot_of, int32_t *nslots, int32_t *new_keys, int32_t *rank,
+                             int32_t *tmp, hipStream_t s) {
+    exclusive_scan_oop(used, rank, kDenseKeys, rank + kDenseKeys, tmp, s);
+    hipLaunchKernelGGL(k_alloc_slots_ordered, dim3(grid_for(kDenseKeys, 256, 4096)), dim3(256), 0, s, used, kDenseKeys,
+                       rank, slot_of, nslots, new_keys);
+    FMM_LAUNCH_CHECK();
+}
+
 void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int64_t op_elems,
                    bool transposed, uint16_t *ops, hipStream_t s) {
     if (nnew <= 0) return;
@@ -632,7 +649,7 @@ void m2l_count_targets(const uint64_t *tsorted, int32_t ncell, int32_t *count, h
         fill_zero(count, sizeof(int32_t), s);
         return;
     }
-    hipLaunchKernelGGL(k_count_targets, dim3(1), dim3(256), 0, s, tsorted, ncell, count);
+    hipLaunchKernelGGL(k_count_targets, dim3(1), dim3(64), 0, s, tsorted, ncell, count);
     FMM_LAUNCH_CHECK();
 }
 

@@ -23,7 +23,12 @@ struct NearFarArgs {
     // source), M holds the duals of the locals, L receives the duals of the
     // multipoles, qs the adjoint weights; operators are stored transposed.
     bool transposed = false;
+    bool deterministic = false;    // fixed order of every floating-point addition
     HostReader *reader = nullptr;  // fast device-to-host reads (optional)
+    // task trace of the queue (optional): records, counter, capacity
+    fmm_task_record *trace = nullptr;
+    int32_t *trace_count = nullptr;
+    int32_t trace_cap = 0;
     // set when build_p2p_leaves already ran on another stream: the build
     // waits for this event instead of building the P2P leaf order itself
     hipEvent_t p2p_ready = nullptr;
@@ -36,6 +41,8 @@ struct NearFarState {
     DevBuf pcode, xcount, tkey, tkey_alt, has, gcount, goff, tcount, toff;
     DevBuf ecls, esrc, gtarget, tasks, xsrc, xptr, leafbuf, leaves, pf, M32, tmp, cnt, centre, gbits, gwpre;
     DevBuf tasks_alt, tkeys, tidx, lists, tmp2;
+    DevBuf part;   // per-task FP32 partial locals of the M2L tasks
+    DevBuf key_rank;   // deterministic mode: ranks of the marked class keys
     // stream and events of the P2P side kernel (created on first use)
     hipStream_t side = nullptr, side2 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, after_queue = nullptr, after_side = nullptr;
@@ -60,6 +67,8 @@ bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool 
 void near_far_join(NearFarState &st, hipStream_t s);
 // The stream on which a deferred queue's join is recorded.
 hipStream_t near_far_join_stream(const NearFarState &st);
+// After the queue (in stream order): the per-pair FP64 M2L of the pairs
+// outside the class table added to the locals.
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 void release_near_far(NearFarState &st);
 

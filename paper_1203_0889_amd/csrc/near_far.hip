@@ -62,8 +62,13 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     const int32_t ncell = a.ncell;
     const int64_t npair = a.nm2l;
     // ---- persistent class tables (slot_of, the operator store, and the
-    // key marks, which the slot allocation clears after each build)
-    if (st.p != p) {
+    // key marks, which the slot allocation clears after each build).  The
+    // order of a group's entries follows the operator slots, and the slots
+    // follow the order in which classes are first seen; in deterministic
+    // mode the store is therefore emptied at every build and refilled in
+    // key order, so the entries (and the FP32 sums of each task) come in
+    // the same order whatever the plan saw before.
+    if (st.p != p || a.deterministic) {
         FMM_HIP_CHECK(st.slot_of.grow(kDenseKeys * 4));
         FMM_HIP_CHECK(hipMemsetAsync(st.slot_of.ptr, 0xff, kDenseKeys * 4, s));
         FMM_HIP_CHECK(st.nslots.grow(2 * 4));
@@ -80,14 +85,21 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     FMM_HIP_CHECK(st.xptr.grow(((size_t)ncell + 1) * 4));
     FMM_HIP_CHECK(st.cnt.grow(64 * 4));  // [0..4] sizes, [16..32] per-XCD counts, [40..55] queue heads
     int64_t tmp_elems = std::max<int64_t>({(int64_t)scan_tmp_elems(np1), (int64_t)radix_tmp_elems(ncell + 1),
-                                           (int64_t)scan_tmp_elems(ncell + 1)});
+                                           (int64_t)scan_tmp_elems(ncell + 1), (int64_t)scan_tmp_elems(kDenseKeys)});
     FMM_HIP_CHECK(st.tmp.grow(tmp_elems * 4));
     int32_t *cnt = st.cnt.as<int32_t>();
 
     m2l_pair_codes(a.g.c, ncell, a.m2l_ptr, a.m2l_src, st.slot_of.as<int32_t>(), st.pcode.as<int32_t>(),
                    st.used.as<int32_t>(), st.xcount.as<int32_t>(), s);
     FMM_HIP_CHECK(hipMemsetAsync(st.nslots.as<int32_t>() + 1, 0, 4, s));
-    m2l_alloc_slots(st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.nslots.as<int32_t>(), st.new_keys.as<int32_t>(), s);
+    if (a.deterministic) {
+        FMM_HIP_CHECK(st.key_rank.grow(((size_t)kDenseKeys + 1) * 4));
+        m2l_alloc_slots_ordered(st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.nslots.as<int32_t>(),
+                                st.new_keys.as<int32_t>(), st.key_rank.as<int32_t>(), st.tmp.as<int32_t>(), s);
+    } else {
+        m2l_alloc_slots(st.used.as<int32_t>(), st.slot_of.as<int32_t>(), st.nslots.as<int32_t>(),
+                        st.new_keys.as<int32_t>(), s);
+    }
     // slot counts next to the sizes below: one read for all of them
     FMM_HIP_CHECK(hipMemcpyAsync(cnt + 5, st.nslots.ptr, 8, hipMemcpyDeviceToDevice, s));
     // CSR offsets of the pairs left to the per-pair kernel; xptr[ncell] (and
@@ -120,6 +132,8 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                       st.frags.as<uint16_t>(), s);
         st.nslot_total = h7[5];
     }
+    if (h7[2] < 0 || h7[2] > ncell || h7[1] < 0 || h7[1] > npair || h7[5] < 0)
+        throw std::runtime_error("M2L group build: device sizes out of range");
     st.nslot = h7[5];
     st.nextra = h7[1];
     st.ntarget = h7[2];
@@ -148,6 +162,8 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     m2l_extra(a.m2l_ptr, ncell, a.m2l_src, st.pcode.as<int32_t>(), st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), s);
     int32_t h2[2];
     rd.end(h2, s);
+    if (h2[0] < 0 || h2[1] < 0 || (st.ngroup > 0 && (h2[0] < st.ngroup || h2[1] < st.ngroup)))
+        throw std::runtime_error("M2L group build: entry or task count out of range");
     st.nentries = st.ngroup > 0 ? h2[0] : 0;
     st.ntask = st.ngroup > 0 ? h2[1] : 0;
     FMM_HIP_CHECK(st.ecls.grow((size_t)std::max(st.nentries, 1) * 4));
@@ -197,6 +213,7 @@ void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     FMM_HIP_CHECK(st.M32.grow((size_t)(ncell + 1) * queue_mrow_elems(a.p) * 2));
     FMM_HIP_CHECK(st.pf.grow((size_t)std::max<int64_t>(a.n, 1) * sizeof(float4)));
     FMM_HIP_CHECK(st.cnt.grow(64 * 4));
+    FMM_HIP_CHECK(st.part.grow((size_t)std::max(st.ntask, 1) * queue_part_elems(a.p) * sizeof(float)));
     queue_split_multipoles(a.M, ncell, a.p, st.M32.as<uint16_t>(), s);
     fill_zero(a.L, (size_t)ncell * P * 8, s);
     p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
@@ -234,8 +251,12 @@ QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
     q.ops = st.frags.as<uint16_t>();
     q.Mb = st.M32.as<uint16_t>();
     q.zero_row = ncell;
-    q.L = a.L;
+    q.part = st.part.as<float>();
     q.P = ncoef(a.p);
+    q.toff = st.toff.as<int32_t>();
+    q.tcount = st.tcount.as<int32_t>();
+    q.ngroup = st.ntask > 0 ? st.ngroup : 0;
+    q.L = a.L;
     q.leaves = st.leaves.as<int32_t>();
     q.p2p_ptr = a.p2p_ptr;
     q.p2p_src = a.p2p_src;
@@ -244,6 +265,9 @@ QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
     q.fld = a.fld;
     q.lists = st.lists.as<int4>();
     q.heads = st.cnt.as<int32_t>() + 40;
+    q.trace = a.trace && a.trace_count && a.trace_cap > 0 ? a.trace : nullptr;
+    q.trace_count = a.trace_count;
+    q.trace_cap = a.trace_cap;
     return q;
 }
 
@@ -252,9 +276,10 @@ QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
 bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join) {
     if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
     if (a.n > 0 && (!a.L || !a.phi || !a.fld || !st.M32.ptr || !st.pf.ptr || !st.centre.ptr || !st.leaves.ptr ||
-                    !st.lists.ptr))
+                    !st.lists.ptr || (st.ntask > 0 && st.part.bytes < (size_t)st.ntask * queue_part_elems(a.p) * 4)))
         throw std::runtime_error("mixed near/far stage: queue inputs not prepared");
     QueueArgs q = queue_args(st, a);
+    if (q.trace) fill_zero(a.trace_count, sizeof(int32_t), s);
     const int ncu = compute_units();
     const int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
     const int side_per_cu = std::max(0, std::min(8, a.tuning.p2p_per_cu));
@@ -277,15 +302,16 @@ void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (st.nextra <= 0) return;
     if (a.transposed)
         launch_m2l_fp64_adjoint(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), st.nextra, a.M, a.L,
-                                1, s);
+                                1, a.deterministic, s);
     else
-        launch_m2l_fp64_add(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), st.nextra, a.M, a.L, s);
+        launch_m2l_fp64_add(a.g, a.ncell, a.p, st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), st.nextra, a.M, a.L,
+                            a.deterministic, s);
 }
 
 void release_near_far(NearFarState &st) {
     DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.pcode, &st.xcount, &st.tkey,
                      &st.tkey_alt, &st.has, &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
-                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists, &st.tmp2};
+                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists, &st.tmp2, &st.part, &st.key_rank};
     if (st.side) {   // the side kernels may still read these buffers
         (void)hipStreamSynchronize(st.side);
         (void)hipStreamSynchronize(st.side2);

@@ -113,6 +113,9 @@ struct fmm_plan {
     fmm::NearFarState nf_t;
     fmm::HostReader reader;
     DevBuf phi_near, fld_near, phi_far, fld_far, echunk, epart;
+    DevBuf trace, trace_count;   // task trace of the forward queue (FMM_FLAG_TRACE)
+    int32_t trace_cap = 0;
+    bool traced = false;
     int32_t nechunk = 0;
     fmm::NearFarState nf;
     fmm_tuning tuning;
@@ -182,6 +185,8 @@ int bits_for(int64_t n) {
     while (((int64_t)1 << b) < n) b++;
     return b;
 }
+
+bool deterministic(const fmm_plan *p) { return (p->prm.flags & FMM_FLAG_DETERMINISTIC) != 0; }
 
 fmm::Geometry geom(fmm_plan *p) {
     fmm::Geometry g;
@@ -408,12 +413,16 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
     hipStream_t on[2] = {s, p->up_side};
     for (int t = 0; t < 2; t++) {   // the M2L sort (the longer chain) is enqueued first
         bool in_alt = false;   // an odd number of passes leaves the sorted pairs in the scratch buffer
+        // deterministic: the whole key (target, source), so that each
+        // target's sources come in ascending order whatever order the
+        // traversal appended them in; otherwise only the target bits
+        const int lo_bit = deterministic(p) ? 0 : bits;
         if (key32)
-            fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, (uint32_t *)alts[t], nullptr, cnts[t], bits, 2 * bits,
-                                tmps[t], on[t], &in_alt);
+            fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, (uint32_t *)alts[t], nullptr, cnts[t], lo_bit,
+                                2 * bits, tmps[t], on[t], &in_alt);
         else
-            fmm::radix_sort_u64((uint64_t *)lists[t], nullptr, (uint64_t *)alts[t], nullptr, cnts[t], bits, 2 * bits,
-                                tmps[t], on[t], &in_alt);
+            fmm::radix_sort_u64((uint64_t *)lists[t], nullptr, (uint64_t *)alts[t], nullptr, cnts[t], lo_bit,
+                                2 * bits, tmps[t], on[t], &in_alt);
         fmm::launch_csr(in_alt ? alts[t] : lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], on[t]);
         if (t == 1) {
             if (p->prm.precision == FMM_PREC_MIXED) fmm::build_p2p_leaves(p->nf, nf_args(p), p->up_side);
@@ -459,6 +468,7 @@ fmm::NearFarArgs nf_args(fmm_plan *p) {
     a.fld = p->fld_near.as<double>();
     a.tuning = p->tuning;
     a.reader = &p->reader;
+    a.deterministic = deterministic(p);
     return a;
 }
 
@@ -573,8 +583,7 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     record(p, ST_M2L);
     if (p->prm.precision == FMM_PREC_FP64) {
         fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
-                             p->M.as<double>(),
-                             p->L.as<double>(), s);
+                             p->M.as<double>(), p->L.as<double>(), deterministic(p), s);
         mark(p, ST_M2L);
         fmm::launch_p2p_fp64(g, ncell, p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(), p->xs.as<double>(),
                              p->ys.as<double>(), p->zs.as<double>(), p->qs.as<double>(), p->phi_near.as<double>(),
@@ -582,6 +591,17 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         mark(p, ST_P2P);
     } else {
         fmm::NearFarArgs a = nf_args(p);
+        if (p->prm.flags & FMM_FLAG_TRACE) {
+            // one record per task: M2L tasks plus target leaves
+            const int64_t cap = (int64_t)p->nf.ntask + p->nleaf;
+            FMM_HIP_CHECK(p->trace.grow((size_t)std::max<int64_t>(cap, 1) * sizeof(fmm_task_record)));
+            FMM_HIP_CHECK(p->trace_count.grow(sizeof(int32_t)));
+            p->trace_cap = (int32_t)cap;
+            a.trace = p->trace.as<fmm_task_record>();
+            a.trace_count = p->trace_count.as<int32_t>();
+            a.trace_cap = p->trace_cap;
+            p->traced = true;
+        }
         fmm::near_far_prepare(p->nf, a, s);
         mark(p, ST_NF_PREP);
         // with a P2P side kernel the queue's P2P tail runs on beside the
@@ -731,7 +751,7 @@ void do_backward(fmm_plan *p, const double *gE, double *grad_pos, double *grad_q
     // M2L^T and P2P^T
     if (p->prm.precision == FMM_PREC_FP64) {
         fmm::launch_m2l_fp64_adjoint(g, ncell, pp, p->m2l_t_ptr.as<int32_t>(), p->m2l_t_src.as<int32_t>(), p->nm2l,
-                                     p->lam.as<double>(), p->mu.as<double>(), 0, s);
+                                     p->lam.as<double>(), p->mu.as<double>(), 0, deterministic(p), s);
         fmm::launch_p2p_fp64(g, ncell, p->p2p_t_ptr.as<int32_t>(), p->p2p_t_src.as<int32_t>(), p->xs.as<double>(),
                              p->ys.as<double>(), p->zs.as<double>(), p->wts.as<double>(), p->psi_near.as<double>(),
                              p->epsi_near.as<double>(), s);
@@ -783,10 +803,8 @@ fmm_status check_params(const fmm_params *q, std::string *why) {
     if (q->max_level < 1 || q->max_level > fmm::kLevels) return *why = "max_level must be in [1, 21]", FMM_ERR_INVALID_ARG;
     if (q->precision != FMM_PREC_FP64 && q->precision != FMM_PREC_MIXED)
         return *why = "unknown precision", FMM_ERR_INVALID_ARG;
-    if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY | FMM_FLAG_TRACE))
+    if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY | FMM_FLAG_TRACE | FMM_FLAG_DETERMINISTIC))
         return *why = "unknown flag", FMM_ERR_INVALID_ARG;
-    if ((q->flags & FMM_FLAG_TRACE) && q->precision == FMM_PREC_MIXED)
-        return *why = "the device task trace of the work queue is not available", FMM_ERR_UNSUPPORTED;
     if ((q->flags & FMM_FLAG_USER_BOX) &&
         !(q->box_side > 0 && std::isfinite(q->box_side) && std::isfinite(q->box_min[0]) &&
           std::isfinite(q->box_min[1]) && std::isfinite(q->box_min[2])))
@@ -857,7 +875,8 @@ fmm_status fmm_destroy(fmm_plan *p) {
                      &p->L, &p->ops_m2m, &p->ops_l2l, &p->m2m_part, &p->phi_near, &p->fld_near, &p->phi_far,
                      &p->fld_far, &p->echunk, &p->epart, &p->ops_m2m_t, &p->ops_l2l_t, &p->m2l_t_ptr,
                      &p->m2l_t_src, &p->p2p_t_ptr, &p->p2p_t_src, &p->tkeys, &p->tkeys_alt, &p->lam, &p->mu,
-                     &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far, &p->pair_alt2, &p->tmp2};
+                     &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far, &p->trace,
+                     &p->trace_count, &p->pair_alt2, &p->tmp2};
     drop_graph(p);
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
@@ -900,6 +919,7 @@ fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, c
         }
         p->state = kStateCreated;
         p->adj_ready = false;
+        p->traced = false;
         drop_graph(p);
         p->n = n;
         p->n_inst = n_inst;
@@ -1020,6 +1040,19 @@ fmm_status fmm_get_counts(const fmm_plan *p, int64_t *ncell, int64_t *nleaf, int
     if (nleaf) *nleaf = p->nleaf;
     if (nm2l) *nm2l = p->nm2l;
     if (np2p) *np2p = p->np2p;
+    return FMM_OK;
+}
+
+fmm_status fmm_get_queue_info(const fmm_plan *p, int64_t *ntarget, int64_t *ngroup, int64_t *ntask, int64_t *nclass,
+                              int64_t *nextra) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateBuilt) return FMM_ERR_STATE;
+    const bool q = p->prm.precision == FMM_PREC_MIXED && p->nf.built;
+    if (ntarget) *ntarget = q ? p->nf.ntarget : 0;
+    if (ngroup) *ngroup = q ? p->nf.ngroup : 0;
+    if (ntask) *ntask = q ? p->nf.ntask : 0;
+    if (nclass) *nclass = q ? p->nf.nslot : 0;
+    if (nextra) *nextra = q ? p->nf.nextra : 0;
     return FMM_OK;
 }
 
@@ -1160,11 +1193,21 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
 }
 
 fmm_status fmm_get_trace(const fmm_plan *cp, fmm_task_record *records, int64_t cap, int64_t *count) {
-    if (!cp || cap < 0 || (cap > 0 && !records)) return FMM_ERR_INVALID_ARG;
-    // no plan records a trace: fmm_create refuses FMM_FLAG_TRACE for the
-    // mixed path, and the FP64 path has no work queue
-    if (count) *count = 0;
-    return FMM_OK;
+    fmm_plan *p = const_cast<fmm_plan *>(cp);
+    if (!p || cap < 0 || (cap > 0 && !records)) return FMM_ERR_INVALID_ARG;
+    return guarded(p, [&]() -> fmm_status {
+        int32_t n = 0;
+        if (p->traced && p->trace_count.ptr) {
+            FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+            FMM_HIP_CHECK(hipMemcpy(&n, p->trace_count.ptr, sizeof(int32_t), hipMemcpyDeviceToHost));
+            n = std::min(n, p->trace_cap);
+        }
+        if (count) *count = n;
+        const int64_t m = std::min<int64_t>(n, cap);
+        if (m > 0)
+            FMM_HIP_CHECK(hipMemcpy(records, p->trace.ptr, (size_t)m * sizeof(fmm_task_record), hipMemcpyDeviceToHost));
+        return FMM_OK;
+    });
 }
 
 fmm_status fmm_get_stage_times(const fmm_plan *cp, double *times, const char **names) {

@@ -13,7 +13,7 @@ struct QueueArgs {
     CellArrays c;
     const double *centre;      // per cell geometric centre (x, y, z), FP64
     // M2L
-    const int4 *m2l_tasks;     // (group, entry begin, entry end, 0)
+    const int4 *m2l_tasks;     // (group, entry begin, entry end, partial slot)
     const int32_t *gtarget;    // group x kGroupM2L target cells (-1 = empty slot)
     const int32_t *ecls;       // entry -> operator slot of its class
     const int32_t *esrc;       // entry x kGroupM2L source cells (-1 = absent)
@@ -21,8 +21,13 @@ struct QueueArgs {
     const uint16_t *Mb;        // multipoles, split bf16 rows (queue_mrow_elems per cell),
                                //   plus one all-zero row at index zero_row
     int32_t zero_row;
-    double *L;                 // FP64 local expansions (accumulated)
+    float *part;               // per-task FP32 partial locals: slot x P x kGroupM2L
     int P;
+    // the pass after k_queue that sums each group's partials into the
+    // locals: group task ranges (toff, tcount), group count, FP64 locals
+    const int32_t *toff, *tcount;
+    int32_t ngroup;
+    double *L;
     // P2P
     const int32_t *leaves;     // leaf cells, by XCD, costliest first
     const int32_t *p2p_ptr, *p2p_src;
@@ -35,9 +40,17 @@ struct QueueArgs {
     int32_t *heads;            // 16 claim counters (zeroed before launch)
     int32_t role_split;        // set by queue_run
     int32_t m2l_only;          // set by queue_run: k_queue leaves the P2P tasks to k_p2p_side
+    // task trace (null: off): records, their counter (zeroed before the
+    // launch) and capacity; records past the capacity are dropped
+    fmm_task_record *trace;
+    int32_t *trace_count;
+    int32_t trace_cap;
 };
 
 bool queue_supported(int p);
+// Floats of one task's partial locals (P coefficients x kGroupM2L targets).
+inline int64_t queue_part_elems(int p) { return (int64_t)ncoef(p) * kGroupM2L; }
+
 // Row tiles of 32 of the M2L operator; the contraction dimension is padded
 // to 32 RT as well (2 RT MFMA k-steps of 16).
 int queue_row_tiles(int p);
@@ -51,6 +64,10 @@ int64_t queue_mrow_elems(int p);
 // rows, row ncell is written as zero.
 void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb, hipStream_t s);
 // The work queue on stream s: nworkgroups persistent workgroups of k_queue
+// followed on s by the sum of the M2L partials into the locals:
+// L[gtarget[g][s]][k] = sum_j part[toff[g] + j][k][s], j < tcount[g], in
+// task order in FP64 (no atomics, so the locals do not depend on which task
+// ends first); cells outside every group keep their locals (zeroed before);
 // and, if nside > 0, nside P2P-only workgroups on the stream `side`, forked
 // from and joined back into s with the events fork and join.  Without side
 // workgroups the k_queue workgroups sharing a compute unit alternate which

@@ -14,8 +14,11 @@
 //     every product; the dropped lo.lo term is below 2^-16 of it.  The
 //     operator is staged through a three-deep LDS ring shared by the four
 //     waves (one barrier per two k-steps); multipoles stream from L2 two
-//     k-steps ahead.  The targets' local expansions accumulate in FP32 AGPRs
-//     and are added into the FP64 locals at the end of the task.
+//     k-steps ahead.  The targets' local expansions accumulate in FP32
+//     registers and are stored, at the end of the task, in the task's own
+//     slot of a partial-locals buffer (plain coalesced stores); one pass after
+//     the queue sums each group's task partials in task order into the FP64
+//     locals, so the result does not depend on which task ends first.
 //   * P2P task (one wave): one target leaf.  Sources are staged in the
 //     wave's LDS tile as float4 relative to the target centre; a leaf of nt
 //     targets is covered by at most two passes of 2^b targets x 64/2^b
@@ -409,27 +412,43 @@ __device__ void m2l_group(const QueueArgs &a, int4 task, int w, int lane, v4f *r
             }
         }
     }
+    // the task's partial locals: part[slot][row][target slot], the 32
+    // column lanes of a row write 128 contiguous bytes
+    float *out = a.part + (int64_t)task.w * a.P * kGroupM2L + w * 64 + col;
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-        const int32_t A = a.gtarget[(int64_t)task.x * kGroupM2L + w * 64 + b * 32 + col];
-        if (A < 0) continue;
-        double *Lc = a.L + (int64_t)A * a.P;
+    for (int b = 0; b < NB; b++)
 #pragma unroll
         for (int r = 0; r < RT; r++)
 #pragma unroll
             for (int i = 0; i < 16; i++) {
-                int row_i = r * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-                if (row_i < a.P) atomicAdd(&Lc[row_i], (double)acc[r][b][i]);
+                const int row_i = r * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+                if (row_i < a.P) out[(int64_t)row_i * kGroupM2L + b * 32] = acc[r][b][i];
             }
-    }
 }
 
 // ------------------------------------------------------------------ queue
 template <int RT>
 constexpr int queue_lds_f4() { return ring_f4<RT>() > 4 * kP2PTile ? ring_f4<RT>() : 4 * kP2PTile; }
 
+// One task record (task trace on): written by one lane.
+__device__ inline void trace_task(const QueueArgs &a, int kind, int32_t task, int kernel, uint64_t t0) {
+    const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+    const int32_t i = atomicAdd(a.trace_count, 1);
+    if (i >= a.trace_cap) return;
+    fmm_task_record r;
+    r.start = t0;
+    r.end = t1;
+    r.kind = kind;
+    r.task = task;
+    r.kernel = kernel;
+    r.hw_id = (uint32_t)__builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (31 << 11));
+    r.xcc = (uint32_t)__builtin_amdgcn_s_getreg((20 << 0) | (0 << 6) | (15 << 11));
+    r.reserved = 0;
+    a.trace[i] = r;
+}
+
 // All P2P tasks this wave can claim, own XCD's list first.
-__device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__restrict__ tile) {
+__device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__restrict__ tile, int kernel) {
     for (int k = 0; k < 8; k++) {
         const int L = (((x + k) & 7) << 1) | 1;
         const int4 li = a.lists[L];
@@ -438,7 +457,10 @@ __device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__
             if (lane == 0) t = atomicAdd(&a.heads[L], 1);
             t = __builtin_amdgcn_readfirstlane(t);      // lane 0's claim, wave-uniform
             if (t >= li.y) break;
-            p2p_leaf(a, a.leaves[li.z + t], tile, lane);
+            const int32_t leaf = a.leaves[li.z + t];
+            const uint64_t t0 = a.trace ? __builtin_amdgcn_s_memrealtime() : 0;
+            p2p_leaf(a, leaf, tile, lane);
+            if (a.trace && lane == 0) trace_task(a, 1, leaf, kernel, t0);
         }
     }
 }
@@ -456,20 +478,30 @@ __global__ void __launch_bounds__(256, (RT <= 3 ? 2 : 1)) k_queue(QueueArgs a) {
     const int role = a.role_split ? (__builtin_amdgcn_s_getreg((4 << 0) | (16 << 6) | (3 << 11)) & 1) : 0;
     for (int ph = 0; ph < 2; ph++) {
         if ((ph ^ role) == 0) {
+            // traced: the record of a task is written after the barrier
+            // that follows it, when all four waves are done
+            int32_t done = -1;
+            uint64_t t0 = 0;
             for (int k = 0; k < 8; k++) {
                 const int L = ((x + k) & 7) << 1;
                 const int4 li = a.lists[L];
                 for (;;) {
                     __syncthreads();
+                    if (a.trace && done >= 0 && threadIdx.x == 0) trace_task(a, 0, done, 0, t0);
+                    done = -1;
                     if (threadIdx.x == 0) claim = atomicAdd(&a.heads[L], 1);
                     __syncthreads();
                     const int32_t t = __builtin_amdgcn_readfirstlane(claim);
                     if (t >= li.y) break;
+                    if (a.trace) {
+                        t0 = __builtin_amdgcn_s_memrealtime();
+                        done = li.x + t;
+                    }
                     m2l_group<RT>(a, a.m2l_tasks[li.x + t], w, lane, lds);
                 }
             }
         } else if (!a.m2l_only) {
-            p2p_phase(a, x, lane, reinterpret_cast<float4 *>(lds) + w * kP2PTile);
+            p2p_phase(a, x, lane, reinterpret_cast<float4 *>(lds) + w * kP2PTile, 0);
         }
         __syncthreads();   // the LDS changes role
     }
@@ -482,7 +514,49 @@ __global__ void __launch_bounds__(256, (RT <= 3 ? 2 : 1)) k_queue(QueueArgs a) {
 __global__ void __launch_bounds__(256) k_p2p_side(QueueArgs a) {
     __shared__ float4 tiles[4 * kP2PTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    p2p_phase(a, blockIdx.x & 7, lane, tiles + w * kP2PTile);
+    p2p_phase(a, blockIdx.x & 7, lane, tiles + w * kP2PTile, 1);
+}
+
+// ------------------------------------------------------------------ reduce
+// One workgroup per (group, block of kRedRows coefficients): thread s sums
+// target slot s over the group's tasks in task order, the block goes
+// through LDS so that each target's run of coefficients is written as one
+// contiguous piece of its row of L.
+constexpr int kRedRows = 16;
+__global__ void __launch_bounds__(kGroupM2L) k_reduce_partials(const float *__restrict__ part,
+                                                               const int32_t *__restrict__ toff,
+                                                               const int32_t *__restrict__ tcount,
+                                                               const int32_t *__restrict__ gtarget, int P,
+                                                               int nrb, double *__restrict__ L) {
+    __shared__ double tile[kRedRows][kGroupM2L + 1];
+    __shared__ int32_t tgt[kGroupM2L];
+    const int g = blockIdx.x / nrb, k0 = (blockIdx.x % nrb) * kRedRows;
+    const int s = threadIdx.x;
+    const int nk = P - k0 < kRedRows ? P - k0 : kRedRows;
+    const int32_t t0 = toff[g], nt = tcount[g];
+    const int64_t ts = (int64_t)P * kGroupM2L;   // one task's partials
+    tgt[s] = gtarget[(int64_t)g * kGroupM2L + s];
+    const float *base = part + ((int64_t)t0 * P + k0) * kGroupM2L + s;
+    for (int k = 0; k < nk; k++) {
+        const float *src = base + (int64_t)k * kGroupM2L;
+        double acc = 0.0;
+        int32_t j = 0;
+        for (; j + 4 <= nt; j += 4) {   // four loads in flight, added in task order
+            const float v0 = src[j * ts], v1 = src[(j + 1) * ts], v2 = src[(j + 2) * ts], v3 = src[(j + 3) * ts];
+            acc += (double)v0;
+            acc += (double)v1;
+            acc += (double)v2;
+            acc += (double)v3;
+        }
+        for (; j < nt; j++) acc += (double)src[j * ts];
+        tile[k][s] = acc;
+    }
+    __syncthreads();
+    for (int i = s; i < nk * kGroupM2L; i += kGroupM2L) {
+        const int slot = i / nk, k = i - slot * nk;
+        const int32_t A = tgt[slot];
+        if (A >= 0) L[(int64_t)A * P + k0 + k] = tile[k][slot];
+    }
 }
 
 // ------------------------------------------------------------------ prep
@@ -570,10 +644,20 @@ bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, const Q
         hipLaunchKernelGGL(k_p2p_side, dim3(nside), dim3(256), 0, side, a);
         FMM_LAUNCH_CHECK();
     }
+    // the partials of each group summed into the locals, on the slots k_queue
+    // frees (before the deferred P2P workgroups below take them)
+    if (a.ngroup > 0) {
+        const int nrb = (a.P + kRedRows - 1) / kRedRows;
+        hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)(a.ngroup * nrb)), dim3(kGroupM2L), 0, s, a.part, a.toff,
+                           a.tcount, a.gtarget, a.P, nrb, a.L);
+        FMM_LAUNCH_CHECK();
+    }
     if (defer) {
-        // more P2P workgroups once k_queue is done (launching them with the
-        // side kernel could fill compute units before k_queue's workgroups
-        // are placed); join = the end of all three launches
+        // more P2P workgroups once k_queue and the sum of its partials are
+        // done (launching them with the side kernel could fill compute units
+        // before k_queue's workgroups are placed; launched right after
+        // k_queue they would leave the sum no room); join = the end of all
+        // three P2P launches
         FMM_HIP_CHECK(hipEventRecord(qs.after_queue, s));
         FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_queue, 0));
         hipLaunchKernelGGL(k_p2p_side, dim3(nworkgroups), dim3(256), 0, qs.side2, a);

@@ -130,18 +130,20 @@ std::vector<double> transpose_ops(const std::vector<double> &ops, int p);
 void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
                      const double *ys, const double *zs, const double *qs, double *phi, double *fld, hipStream_t s);
 // Per-pair FP64 M2L over the CSR list (ptr, src) of npair pairs (target-owned),
-// balanced over pairs; overwrites L (cells without pairs get zero).
+// balanced over pairs (FP64 atomics), or with owner_mode one wave per owner
+// in list order (no atomics: a fixed order of additions); overwrites L
+// (cells without pairs get zero).
 void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
-                     const double *M, double *L, hipStream_t s);
+                     const double *M, double *L, bool owner_mode, hipStream_t s);
 // Same, adding into L (used for the pairs the MFMA path leaves out).
 void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
-                         const double *M, double *L, hipStream_t s);
+                         const double *M, double *L, bool owner_mode, hipStream_t s);
 // Adjoint of the M2L stage over the transposed list (ptr_t, src_t): for every
 // pair (A <- B) of the forward list, Mu_B += T_(A<-B)^T Lam_A, with T the real
 // (p+1)^2 x (p+1)^2 matrix the forward kernel applies.  Owner = source cell B.
 // add = 0 overwrites Mu (cells without pairs get zero), add = 1 accumulates.
 void launch_m2l_fp64_adjoint(Geometry g, int32_t ncell, int p, const int32_t *ptr_t, const int32_t *src_t,
-                             int64_t npair, const double *Lam, double *Mu, int add, hipStream_t s);
+                             int64_t npair, const double *Lam, double *Mu, int add, bool owner_mode, hipStream_t s);
 
 // ---- output
 // The outputs (near + far field of every sorted particle) in input order.

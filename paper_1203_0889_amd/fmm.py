@@ -25,12 +25,13 @@ PREC = {"fp64": 0, "mixed": 1}
 FLAG_USER_BOX = 1
 FLAG_KEEP_TOPOLOGY = 2
 FLAG_TRACE = 4
+FLAG_DETERMINISTIC = 8
 
 # every symbol include/fmm.h declares
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
            "fmm_backward", "fmm_sync", "fmm_get_counts", "fmm_copy_tree", "fmm_copy_lists", "fmm_get_tuning",
            "fmm_set_tuning", "fmm_get_stage_times", "fmm_status_string", "fmm_last_error", "fmm_graph_capture",
-           "fmm_graph_launch", "fmm_autotune", "fmm_get_trace")
+           "fmm_graph_launch", "fmm_autotune", "fmm_get_trace", "fmm_get_queue_info")
 
 
 class fmm_params(ctypes.Structure):
@@ -86,6 +87,7 @@ def load_library():
     lib.fmm_graph_launch.argtypes = [vp]
     lib.fmm_autotune.argtypes = [vp, i32, P(fmm_tuning), P(ctypes.c_double)]
     lib.fmm_get_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64)]
+    lib.fmm_get_queue_info.argtypes = [vp, P(i64), P(i64), P(i64), P(i64), P(i64)]
     lib.fmm_copy_tree.argtypes = [vp, vp, vp, vp]
     lib.fmm_copy_lists.argtypes = [vp, vp, vp, vp, vp]
     lib.fmm_get_tuning.argtypes = [vp, P(fmm_tuning)]
@@ -127,7 +129,7 @@ class Plan:
     """One FMM plan: owns the tree, lists and expansions on one device/stream."""
 
     def __init__(self, p=8, ncrit=64, theta=(1, 2), max_level=21, precision="mixed", device=None, stream=None,
-                 box=None, keep_topology=False, trace=False):
+                 box=None, keep_topology=False, trace=False, deterministic=False):
         self._lib = load_library()
         prm = fmm_params()
         self._lib.fmm_default_params(ctypes.byref(prm))
@@ -143,6 +145,8 @@ class Plan:
             prm.flags |= FLAG_KEEP_TOPOLOGY
         if trace:
             prm.flags |= FLAG_TRACE
+        if deterministic:
+            prm.flags |= FLAG_DETERMINISTIC
         self.params = prm
         if device is None:
             device = torch.cuda.current_device()
@@ -253,6 +257,12 @@ class Plan:
         v = [ctypes.c_int64() for _ in range(4)]
         self._call(self._lib.fmm_get_counts, *[ctypes.byref(x) for x in v])
         return dict(zip(("ncell", "nleaf", "nm2l", "np2p"), (x.value for x in v)))
+
+    def queue_info(self):
+        """Work-queue table sizes of the last build (mixed path; zeros for FP64)."""
+        v = [ctypes.c_int64() for _ in range(5)]
+        self._call(self._lib.fmm_get_queue_info, *[ctypes.byref(x) for x in v])
+        return dict(zip(("ntarget", "ngroup", "ntask", "nclass", "nextra"), (x.value for x in v)))
 
     def copy_tree(self):
         import numpy as np

@@ -1,19 +1,45 @@
 """Error measures of the GPU parity tests (a helper module, not a test file).
 
-rel:    relative L2 over all particles, ||x - x_ref|| / ||x_ref|| (rows of a
-        field count as 3-vectors);
-maxrel: the worst single particle against the typical size of the
-        reference, max_i |x_i - x_ref,i| / rms_i |x_ref,i|.  A global L2 norm
-        can hide an error confined to a few leaves; this cannot.
+rel:     relative L2 over all particles, ||x - x_ref|| / ||x_ref|| (rows of a
+         field count as 3-vectors);
+maxrel:  the worst single particle against the typical size of the
+         reference, max_i |x_i - x_ref,i| / rms_i |x_ref,i|;
+leafrel: the worst leaf, max over leaves of the median over the leaf's
+         particles of |x_i - x_ref,i| / rms_i |x_ref,i|.
 
-Bounds of maxrel next to the relative-L2 bounds of the same comparisons:
-FP64 path vs the oracle FMM 1e-9 (next to 1e-11); mixed path vs the oracle
-FMM 2e-4 (next to 1e-5): an error of 3e-4 of the rms in a single leaf fails.
+A global L2 norm can hide an error confined to a few leaves.  maxrel cannot,
+but in the mixed path its value for the field is set by the FP32 rounding of
+the closest pairs: the field of a particle with a neighbour at distance r
+grows as 1/r^2 while the FP32 relative coordinates carry an absolute error
+of about 2^-24 of the leaf size, so a handful of particles sit far above the
+rest.  leafrel ignores such isolated particles (the median of a leaf) and
+catches anything that shifts a whole leaf.
+
+Bounds, next to the relative-L2 bounds of the same comparisons:
+  FP64 path vs the oracle FMM (1e-11): maxrel and leafrel 1e-9;
+  mixed path vs the oracle FMM (1e-5): maxrel 1e-4 for the potential and
+  5e-3 for the field (close pairs), leafrel 1e-4 for both, so an error of
+  3e-4 of the rms in a single leaf fails.  Measured on the MI355X: the
+  worst leaf sits at 2e-5 (potential) and 4e-5 (field, 8 particles per
+  leaf, where the far field dominates): the split-bf16 M2L rounds the
+  local expansion of a leaf as a whole, so its error is shared by the
+  leaf's particles.
 """
 import numpy as np
 
 MAX_FP64 = 1e-9
-MAX_MIXED = 2e-4
+LEAF_FP64 = 1e-9
+MAX_MIXED_PHI = 1e-4
+MAX_MIXED_FIELD = 5e-3
+LEAF_MIXED = 1e-4
+
+
+def _norms(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    d = a - b
+    if d.ndim == 2:
+        return np.linalg.norm(d, axis=1), np.linalg.norm(b, axis=1)
+    return np.abs(d), np.abs(b)
 
 
 def rel(a, b):
@@ -22,11 +48,52 @@ def rel(a, b):
 
 
 def maxrel(a, b):
-    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    d = a - b
-    if d.ndim == 2:
-        dn, bn = np.linalg.norm(d, axis=1), np.linalg.norm(b, axis=1)
-    else:
-        dn, bn = np.abs(d), np.abs(b)
-    rms = np.sqrt(np.mean(bn * bn))
-    return float(np.max(dn) / rms) if len(dn) else 0.0
+    dn, bn = _norms(a, b)
+    if len(dn) == 0:
+        return 0.0
+    return float(np.max(dn) / np.sqrt(np.mean(bn * bn)))
+
+
+def leaf_ids(perm, cells):
+    """Leaf index of every particle (input order) from a copied tree:
+    perm[r] = input index of sorted particle r; cells[:, 4:7] = first,
+    count, child_first."""
+    ids = np.full(len(perm), -1, dtype=np.int64)
+    leaves = np.nonzero(cells[:, 6] < 0)[0]
+    for k, c in enumerate(leaves):
+        f, n = cells[c, 4], cells[c, 5]
+        ids[perm[f:f + n]] = k
+    return ids
+
+
+def leafrel(a, b, ids):
+    dn, bn = _norms(a, b)
+    if len(dn) == 0:
+        return 0.0
+    e = dn / np.sqrt(np.mean(bn * bn))
+    order = np.argsort(ids, kind="stable")
+    ids_s, e_s = ids[order], e[order]
+    bounds = np.flatnonzero(np.diff(ids_s)) + 1
+    return float(max(np.median(g) for g in np.split(e_s, bounds)))
+
+
+def check_mixed(out, phi_ref, fld_ref, ids, say=print, label=""):
+    """Every per-particle and per-leaf bound of the mixed path; returns the
+    measured values."""
+    v = {"max_phi": maxrel(out["phi"], phi_ref), "max_field": maxrel(out["field"], fld_ref),
+         "leaf_phi": leafrel(out["phi"], phi_ref, ids), "leaf_field": leafrel(out["field"], fld_ref, ids)}
+    say(label, "worst particle / rms: phi %.3g field %.3g; worst leaf median: phi %.3g field %.3g"
+        % (v["max_phi"], v["max_field"], v["leaf_phi"], v["leaf_field"]))
+    assert v["max_phi"] < MAX_MIXED_PHI and v["max_field"] < MAX_MIXED_FIELD, v
+    assert v["leaf_phi"] < LEAF_MIXED and v["leaf_field"] < LEAF_MIXED, v
+    return v
+
+
+def check_fp64(out, phi_ref, fld_ref, ids, say=print, label=""):
+    v = {"max_phi": maxrel(out["phi"], phi_ref), "max_field": maxrel(out["field"], fld_ref),
+         "leaf_phi": leafrel(out["phi"], phi_ref, ids), "leaf_field": leafrel(out["field"], fld_ref, ids)}
+    say(label, "worst particle / rms: phi %.3g field %.3g; worst leaf median: phi %.3g field %.3g"
+        % (v["max_phi"], v["max_field"], v["leaf_phi"], v["leaf_field"]))
+    assert max(v["max_phi"], v["max_field"]) < MAX_FP64, v
+    assert max(v["leaf_phi"], v["leaf_field"]) < LEAF_FP64, v
+    return v

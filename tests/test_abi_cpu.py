@@ -125,14 +125,3 @@ def test_trace_summary_on_synthetic_records():
     assert abs(s["cu_busy_imbalance"] - 40.0 / 27.0) < 1e-12
     assert trace.summarize(rec[:0]) == {"tasks": 0}
 
-
-def test_traced_mixed_plan_is_refused_before_any_device_call():
-    # the parameter check comes first, so this holds without a GPU
-    lib = fmm.load_library()
-    prm = fmm.fmm_params()
-    assert lib.fmm_default_params(ctypes.byref(prm)) == 0
-    prm.precision = fmm.PREC["mixed"]
-    prm.flags = fmm.FLAG_TRACE
-    h = ctypes.c_void_p()
-    assert lib.fmm_create(ctypes.byref(prm), 0, None, ctypes.byref(h)) == -6
-    assert not h.value
