@@ -39,10 +39,10 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-def committed_traffic(workload, tuning):
-    """HBM bytes per queue launch from the committed PMC summary, if it was
+def committed_counters(workload, tuning):
+    """Fields of the committed PMC summary of the work queue, if it was
     taken on this workload, at this work-queue tuning and on the current
-    queue kernel source."""
+    queue kernel source (else None)."""
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if not os.path.exists(path):
         return None
@@ -56,10 +56,14 @@ def committed_traffic(workload, tuning):
         return None
     if fields.get("tuning") != tuning_text(tuning):
         return None
-    try:
-        return float(fields["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    out = {}
+    for k in ("hbm_bytes_per_launch", "mfma_flop_executed", "mfma_busy_simd_cycles", "p2p_valu_wave_insts",
+              "clock_ghz"):
+        try:
+            out[k] = float(fields[k])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def tuning_text(t):
@@ -181,8 +185,9 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload, tuning):
         tq = stage_avg.get("queue", 0.0) * 1e-3
         flops = p2p_flop + m2l_f
         t_min = p2p_flop / PEAK["fp32_valu"] + m2l_f / PEAK["bf16_mfma"]
+        ctr = committed_counters(workload, tuning) or {}
         roof = {"bound": "alu", "achieved": flops / tq / 1e12 if tq > 0 else None,
-                "peak": flops / t_min / 1e12, "unit": "TFLOP/s", "traffic": committed_traffic(workload, tuning),
+                "peak": flops / t_min / 1e12, "unit": "TFLOP/s", "traffic": ctr.get("hbm_bytes_per_launch"),
                 "kernel": "k_queue + k_p2p_side (P2P FP32 VALU + M2L split-bf16 MFMA)", "kernel_ms": tq * 1e3,
                 "peak_basis": "P2P flop / 157.3 TF fp32 vector + M2L flop (2 P^2 per pair) / 2.5 PF bf16 dense MFMA"}
         # the bound the implementation's own instruction mix allows: three
@@ -197,6 +202,16 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload, tuning):
         if tq > 0:
             for k in ("split_products", "split_products_nonpacked_fp32"):
                 roof[k]["frac"] = flops / tq / 1e12 / roof[k]["peak"]
+        # from the committed counters of this workload, tuning and queue
+        # source: what the matrix cores and vector units actually executed
+        if "mfma_flop_executed" in ctr:
+            roof["m2l_mfma"] = {"flop_executed": ctr["mfma_flop_executed"], "method_flop": m2l_f,
+                                "executed_per_method_flop": ctr["mfma_flop_executed"] / m2l_f}
+            if tq > 0 and "mfma_busy_simd_cycles" in ctr and "clock_ghz" in ctr:
+                simd_cycles = tq * ctr["clock_ghz"] * 1e9 * 1024
+                roof["m2l_mfma"]["busy_frac_of_queue"] = ctr["mfma_busy_simd_cycles"] / simd_cycles
+        if "p2p_valu_wave_insts" in ctr and inter > 0:
+            roof["p2p_valu_insts_per_interaction"] = ctr["p2p_valu_wave_insts"] * 64 / inter
     else:
         dom, t, f = ("p2p", t_p2p, p2p_flop) if t_p2p >= t_m2l else ("m2l", t_m2l, m2l_f)
         roof = {"bound": "alu", "achieved": f / t / 1e12 if t > 0 else None, "peak": PEAK["fp64"] / 1e12,

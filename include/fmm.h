@@ -235,13 +235,14 @@ fmm_status fmm_set_tuning(fmm_plan *plan, const fmm_tuning *tuning);
 /*
  * Autotuner of the work queue (the paper tunes its task granularity Q,
  * Sec. 5): on the plan's current tree and multipoles (after fmm_upward),
- * times the queue for m2l_task_entries in {32, 64, 96, 128} and
- * (grid_per_cu, p2p_per_cu) in {(1, 1), (1, 2), (1, 3), (2, 0), (3, 0)}
- * (the task tables are rebuilt per m2l_task_entries; each setting takes the
- * fastest of `repeats` >= 1 runs, HIP events on the plan's stream around the
- * queue's kernels), keeps the fastest setting and rebuilds the
- * tables with it.  Outputs (host, may be NULL): the chosen tuning and its
- * kernel time in ms.  Leaves the plan as after fmm_upward (call
+ * times one evaluation (fmm_evaluate without outputs: the queue, the far
+ * field that runs beside its P2P tail, the join) for m2l_task_entries in
+ * {32, 64, 96, 128} and (grid_per_cu, p2p_per_cu) in {(1, 1), (1, 2),
+ * (1, 3), (2, 0), (3, 0)} (the task tables are rebuilt per
+ * m2l_task_entries; each setting takes the fastest of `repeats` >= 1 runs,
+ * HIP events on the plan's stream), keeps the fastest setting and rebuilds
+ * the tables with it.  Outputs (host, may be NULL): the chosen tuning and
+ * its time in ms.  Leaves the plan as after fmm_upward (call
  * fmm_evaluate again); drops a captured graph.  The FP64 path has no queue:
  * the call then only reports the current tuning and time -1.
  */

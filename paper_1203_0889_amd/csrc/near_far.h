@@ -46,6 +46,7 @@ struct NearFarState {
     // stream and events of the P2P side kernel (created on first use)
     hipStream_t side = nullptr, side2 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, after_queue = nullptr, after_side = nullptr;
+    bool tail_pending = false;   // a deferred queue whose P2P tail is not launched yet
     int p = -1;
     int32_t nslot_total = 0, nslot = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0;
     bool built = false;
@@ -64,6 +65,9 @@ void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // defer_join: see queue_run; then near_far_join(st, s) before the near
 // field is read.  Returns whether the join was deferred.
 bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join = false);
+// The deferred P2P tail: more P2P workgroups once the work queued on s so
+// far (the far field) is done, then the join event.
+void near_far_tail(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 void near_far_join(NearFarState &st, hipStream_t s);
 // The stream on which a deferred queue's join is recorded.
 hipStream_t near_far_join_stream(const NearFarState &st);

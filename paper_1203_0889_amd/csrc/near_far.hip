@@ -291,10 +291,35 @@ bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool 
     qs.join = st.join;
     qs.after_queue = st.after_queue;
     qs.after_side = st.after_side;
-    return queue_run(q, a.p, ncu * per_cu, ncu * side_per_cu, qs, s, defer_join);
+    const bool deferred = queue_run(q, a.p, ncu * per_cu, ncu * side_per_cu, qs, s, defer_join);
+    st.tail_pending = deferred;
+    return deferred;
 }
 
-void near_far_join(NearFarState &st, hipStream_t s) { FMM_HIP_CHECK(hipStreamWaitEvent(s, st.join, 0)); }
+namespace {
+QueueStreams streams_of(const NearFarState &st) {
+    QueueStreams qs;
+    qs.side = st.side;
+    qs.side2 = st.side2;
+    qs.fork = st.fork;
+    qs.join = st.join;
+    qs.after_queue = st.after_queue;
+    qs.after_side = st.after_side;
+    return qs;
+}
+}  // namespace
+
+void near_far_tail(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    if (!st.tail_pending) return;
+    const int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
+    queue_tail(queue_args(st, a), compute_units() * per_cu, streams_of(st), s);
+    st.tail_pending = false;
+}
+
+void near_far_join(NearFarState &st, hipStream_t s) {
+    if (st.tail_pending) throw std::runtime_error("work queue joined before its P2P tail was launched");
+    FMM_HIP_CHECK(hipStreamWaitEvent(s, st.join, 0));
+}
 
 hipStream_t near_far_join_stream(const NearFarState &st) { return st.side2; }
 

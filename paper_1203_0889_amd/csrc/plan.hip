@@ -577,9 +577,19 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         fmm_plan *p;
         bool pending = false;
         ~DeferredJoin() {
-            if (pending && p->nf.join) (void)hipStreamWaitEvent(p->stream, p->nf.join, 0);
+            if (!pending) return;
+            fmm::NearFarState &nf = p->nf;
+            if (nf.tail_pending && nf.side && nf.after_side) {   // the tail was never launched
+                (void)hipEventRecord(nf.after_side, nf.side);
+                (void)hipStreamWaitEvent(p->stream, nf.after_side, 0);
+                nf.tail_pending = false;
+            } else if (nf.join) {
+                (void)hipStreamWaitEvent(p->stream, nf.join, 0);
+            }
         }
     } join_guard{p};
+    fmm::NearFarArgs a_nf;   // the mixed path's arguments (the P2P tail needs them again)
+    bool time_queue = false;  // the queue stage ends at the join (recorded after the tail)
     record(p, ST_M2L);
     if (p->prm.precision == FMM_PREC_FP64) {
         fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
@@ -590,7 +600,8 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
                              p->fld_near.as<double>(), s);
         mark(p, ST_P2P);
     } else {
-        fmm::NearFarArgs a = nf_args(p);
+        a_nf = nf_args(p);
+        fmm::NearFarArgs &a = a_nf;
         if (p->prm.flags & FMM_FLAG_TRACE) {
             // one record per task: M2L tasks plus target leaves
             const int64_t cap = (int64_t)p->nf.ntask + p->nleaf;
@@ -604,20 +615,20 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         }
         fmm::near_far_prepare(p->nf, a, s);
         mark(p, ST_NF_PREP);
-        // with a P2P side kernel the queue's P2P tail runs on beside the
-        // FP64 M2L rest, L2L and L2P; the near field is joined before the
-        // outputs
+        // with a P2P side kernel the P2P tasks run on beside the FP64 M2L
+        // rest, L2L and L2P, joined by more P2P workgroups once those are
+        // queued; the near field is joined before the outputs
         join_guard.pending = true;   // also if the launch itself throws half way
         deferred = fmm::near_far_queue(p->nf, a, s, /*defer_join=*/true);
         join_guard.pending = deferred;
         if (!deferred) {
             mark(p, ST_QUEUE);
         } else if (p->ev_ok && !p->capturing && p->last_ev) {
-            // the queue stage ends with both kernels (the join, on the side
-            // stream); the next stage begins after k_queue
-            FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_QUEUE], fmm::near_far_join_stream(p->nf)));
+            // the queue stage ends with all its kernels (the join, on the side
+            // stream, recorded after the tail); the next stage begins after
+            // k_queue and the sum of its partials
             p->beg_of[ST_QUEUE] = p->last_ev;
-            p->ev_used[ST_QUEUE] = true;
+            time_queue = true;
             record(p, ST_M2L_REST);
         }
         fmm::near_far_rest(p->nf, a, s);
@@ -646,6 +657,11 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     mark(p, ST_L2P);
     fmm::FinalOut out_e;   // outputs written by the energy pass (deferred queue with an energy)
     if (deferred) {
+        fmm::near_far_tail(p->nf, a_nf, s);
+        if (time_queue) {
+            FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_QUEUE], fmm::near_far_join_stream(p->nf)));
+            p->ev_used[ST_QUEUE] = true;
+        }
         fmm::near_far_join(p->nf, s);
         join_guard.pending = false;
         if (energy && (phi || field || force)) {
@@ -1156,13 +1172,12 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
                 for (const auto &sh : kShape) {
                     p->tuning.grid_per_cu = sh[0];
                     p->tuning.p2p_per_cu = sh[1];
-                    fmm::NearFarArgs a = nf_args(p);
                     float t_min = -1.0f;
                     for (int r = 0; r < repeats; r++) {
-                        fmm::near_far_prepare(p->nf, a, s);
+                        // the whole evaluation (queue, far field beside the
+                        // P2P tail, join), no outputs
                         FMM_HIP_CHECK(hipEventRecord(e0, s));
-                        // as the evaluation runs it (P2P tail deferred), joined for the timing
-                        if (fmm::near_far_queue(p->nf, a, s, /*defer_join=*/true)) fmm::near_far_join(p->nf, s);
+                        do_evaluate(p, nullptr, nullptr, nullptr, nullptr);
                         FMM_HIP_CHECK(hipEventRecord(e1, s));
                         FMM_HIP_CHECK(hipEventSynchronize(e1));
                         float ms = 0.0f;

@@ -79,12 +79,15 @@ struct QueueStreams {
     hipEvent_t fork = nullptr, join = nullptr, after_queue = nullptr, after_side = nullptr;
 };
 // defer_join (with side workgroups): k_queue runs the M2L tasks only and the
-// side kernel drains every P2P task, joined when k_queue ends by nworkgroups
-// more P2P workgroups on side2 (on the compute units k_queue leaves); s does
-// not wait for them: join (recorded on side2) marks the end of all three
-// launches and the caller waits for it before it reads the near field.
+// side kernel drains the P2P tasks; s does not wait for it: the caller
+// queues more work on s, then queue_tail, and waits for the join before it
+// reads the near field.
 // Returns whether the join was deferred.
 bool queue_run(const QueueArgs &a, int p, int nworkgroups, int nside, const QueueStreams &qs, hipStream_t s,
                bool defer_join = false);
+// The deferred P2P tail (after queue_run returned true): nworkgroups more
+// P2P-only workgroups on side2 once the work queued on s so far is done,
+// and the join event recorded after every P2P launch.
+void queue_tail(const QueueArgs &a, int nworkgroups, const QueueStreams &qs, hipStream_t s);
 
 }  // namespace fmm

@@ -653,24 +653,32 @@ bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, const Q
         FMM_LAUNCH_CHECK();
     }
     if (defer) {
-        // more P2P workgroups once k_queue and the sum of its partials are
-        // done (launching them with the side kernel could fill compute units
-        // before k_queue's workgroups are placed; launched right after
-        // k_queue they would leave the sum no room); join = the end of all
-        // three P2P launches
-        FMM_HIP_CHECK(hipEventRecord(qs.after_queue, s));
-        FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_queue, 0));
-        hipLaunchKernelGGL(k_p2p_side, dim3(nworkgroups), dim3(256), 0, qs.side2, a);
-        FMM_LAUNCH_CHECK();
-        FMM_HIP_CHECK(hipEventRecord(qs.after_side, side));
-        FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_side, 0));
-        FMM_HIP_CHECK(hipEventRecord(qs.join, qs.side2));
+        // the rest of the P2P tail: queue_tail, once the caller has queued
+        // what should run first on the compute units k_queue leaves
     } else if (nside > 0) {
         // join: work queued on s after this waits for the side kernel too
         FMM_HIP_CHECK(hipEventRecord(qs.join, side));
         FMM_HIP_CHECK(hipStreamWaitEvent(s, qs.join, 0));
     }
     return defer;
+}
+
+void queue_tail(const QueueArgs &a_in, int nworkgroups, const QueueStreams &qs, hipStream_t s) {
+    QueueArgs a = a_in;
+    a.role_split = 0;
+    a.m2l_only = 1;
+    // more P2P workgroups once everything queued on s so far is done
+    // (launched with the side kernel they could fill compute units before
+    // k_queue's workgroups are placed; launched as soon as k_queue ends they
+    // would take the slots it frees from the sum of its partials and the
+    // far field behind it); join = the end of all the P2P launches
+    FMM_HIP_CHECK(hipEventRecord(qs.after_queue, s));
+    FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_queue, 0));
+    hipLaunchKernelGGL(k_p2p_side, dim3(nworkgroups), dim3(256), 0, qs.side2, a);
+    FMM_LAUNCH_CHECK();
+    FMM_HIP_CHECK(hipEventRecord(qs.after_side, qs.side));
+    FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_side, 0));
+    FMM_HIP_CHECK(hipEventRecord(qs.join, qs.side2));
 }
 
 }  // namespace fmm
