@@ -135,6 +135,24 @@ fmm_status fmm_upward(fmm_plan *plan);
 fmm_status fmm_evaluate(fmm_plan *plan, double *phi, double *field, double *force, double *energy);
 
 /*
+ * fmm_evaluate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same outputs from the same kernels as fmm_evaluate, with no hipMalloc,
+ * hipFree or other allocation.  Every workspace of the plan must already be
+ * large enough for the current tree (an earlier fmm_evaluate on the plan
+ * sizes them, also for any later smaller tree); otherwise FMM_ERR_STATE,
+ * before or while work is enqueued (the outputs are then undefined).  The
+ * work queue's claim counters and the energy's chunk partials live in a
+ * fixed device array of 1 MiB per GPU (each GPU the library runs on holds it
+ * until the process ends): an energy needing more than 131,040 chunk
+ * partials (about 1,024 particles each, one chunk at least per instance) is
+ * FMM_ERR_CAPACITY.  Calls on one GPU share that array: calls that overlap
+ * on one GPU (plans on different streams without ordering between them)
+ * race, and must be ordered by the caller.
+ */
+fmm_status fmm_evaluate_noalloc(fmm_plan *plan, double *phi, double *field, double *force, double *energy);
+
+/*
  * Adjoint: gradient of the FMM total energy, sum_k g_k E_k with
  * E_k = 1/2 q_k^T A q_k, with respect to positions and charges, where A is
  * the matrix the FMM applies (P2M, M2M, M2L, L2L, L2P and P2P over the built

@@ -25,6 +25,7 @@ struct NearFarArgs {
     bool transposed = false;
     bool deterministic = false;    // fixed order of every floating-point addition
     HostReader *reader = nullptr;  // fast device-to-host reads (optional)
+    int32_t *heads = nullptr;      // 16 claim counters of the queue (null: the state's own)
     // task trace of the queue (optional): records, counter, capacity
     fmm_task_record *trace = nullptr;
     int32_t *trace_count = nullptr;

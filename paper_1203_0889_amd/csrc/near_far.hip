@@ -264,7 +264,7 @@ QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
     q.phi = a.phi;
     q.fld = a.fld;
     q.lists = st.lists.as<int4>();
-    q.heads = st.cnt.as<int32_t>() + 40;
+    q.heads = a.heads ? a.heads : st.cnt.as<int32_t>() + 40;
     q.trace = a.trace && a.trace_count && a.trace_cap > 0 ? a.trace : nullptr;
     q.trace_count = a.trace_count;
     q.trace_cap = a.trace_cap;

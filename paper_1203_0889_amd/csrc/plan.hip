@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <stdexcept>
 
 #include "../../include/fmm.h"
 #include "near_far.h"
@@ -14,8 +16,17 @@
 
 namespace fmm {
 
+// Set for the duration of a call that must not allocate device memory
+// (fmm_evaluate_noalloc): a workspace that would have to grow is an error.
+thread_local bool t_no_alloc = false;
+
+struct NoAllocError : std::logic_error {
+    using std::logic_error::logic_error;
+};
+
 hipError_t DevBuf::grow(size_t want) {
     if (want <= bytes) return hipSuccess;
+    if (t_no_alloc) throw NoAllocError("a workspace of the plan is smaller than this evaluation needs");
     size_t nb = want + want / 4 + 256;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, nb);
@@ -31,6 +42,7 @@ hipError_t DevBuf::grow(size_t want) {
 
 hipError_t DevBuf::grow_keep(size_t want, hipStream_t s) {
     if (want <= bytes) return hipSuccess;
+    if (t_no_alloc) throw NoAllocError("a workspace of the plan is smaller than this evaluation needs");
     size_t nb = want + want / 2 + 256;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, nb);
@@ -44,6 +56,32 @@ hipError_t DevBuf::grow_keep(size_t want, hipStream_t s) {
     ptr = p;
     bytes = nb;
     return hipSuccess;
+}
+
+// Scratch of fmm_evaluate_noalloc: a fixed device array (each GPU the
+// library runs on holds its own copy until the process ends).  In host code
+// `scratch` only names the symbol; its device address on a device comes from
+// hipGetSymbolAddress with that device current, resolved once per device
+// when a plan is created there and kept in g_scratch.
+constexpr size_t kScratchBytes = (size_t)1 << 20;
+constexpr size_t kScratchHeads = 256;   // bytes 0..255: the 16 claim counters of the work queue
+constexpr int kScratchMaxChunks = (int)((kScratchBytes - kScratchHeads) / sizeof(double));   // energy partials
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void *g_scratch[kMaxDevices] = {};
+static std::mutex g_scratch_mutex;
+
+// The device address of `scratch` on `device` (the current device); null
+// if it cannot be resolved.
+void *scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[device] = ptr;
+        else (void)hipGetLastError();
+    }
+    return g_scratch[device];
 }
 
 void DevBuf::release() {
@@ -117,6 +155,10 @@ struct fmm_plan {
     int32_t trace_cap = 0;
     bool traced = false;
     int32_t nechunk = 0;
+    // fmm_evaluate_noalloc: the claim counters and energy partials in the
+    // device's scratch array instead of the plan's buffers (null: the plan's)
+    int32_t *heads_override = nullptr;
+    double *epart_override = nullptr;
     fmm::NearFarState nf;
     fmm_tuning tuning;
     hipEvent_t ev_beg[ST_COUNT] = {}, ev_end[ST_COUNT] = {};
@@ -601,6 +643,7 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         mark(p, ST_P2P);
     } else {
         a_nf = nf_args(p);
+        a_nf.heads = p->heads_override;
         fmm::NearFarArgs &a = a_nf;
         if (p->prm.flags & FMM_FLAG_TRACE) {
             // one record per task: M2L tasks plus target leaves
@@ -680,7 +723,8 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     }
     if (energy)
         fmm::launch_energy(p->off.as<int64_t>(), p->n_inst, p->echunk.as<int32_t>(), p->nechunk, p->qs.as<double>(),
-                           p->phi_near.as<double>(), p->phi_far.as<double>(), p->epart.as<double>(), energy, s, out_e,
+                           p->phi_near.as<double>(), p->phi_far.as<double>(),
+                           p->epart_override ? p->epart_override : p->epart.as<double>(), energy, s, out_e,
                            p->fld_far.as<double>());
     mark(p, ST_OUT);
 }
@@ -803,6 +847,8 @@ fmm_status guarded(fmm_plan *p, F &&f) {
         return fail(p, FMM_ERR_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.err));
     } catch (const std::invalid_argument &e) {
         return fail(p, FMM_ERR_INVALID_ARG, e.what());
+    } catch (const fmm::NoAllocError &e) {
+        return fail(p, FMM_ERR_STATE, std::string(e.what()) + " (call fmm_evaluate once to size the workspaces)");
     } catch (const std::bad_alloc &) {
         return fail(p, FMM_ERR_OOM, "host allocation failed");
     } catch (const std::exception &e) {
@@ -865,6 +911,7 @@ fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fm
         return FMM_ERR_DEVICE;
     }
     p->reader.init();
+    (void)fmm::scratch_on(device);   // resolved once per device, before any no-allocation call
     p->ev_ok = true;
     for (int i = 0; i < ST_COUNT; i++)
         if (hipEventCreate(&p->ev_beg[i]) != hipSuccess || hipEventCreate(&p->ev_end[i]) != hipSuccess)
@@ -962,6 +1009,38 @@ fmm_status fmm_evaluate(fmm_plan *p, double *phi, double *field, double *force, 
     if (!p) return FMM_ERR_INVALID_ARG;
     if (p->state < kStateUp) return fail(p, FMM_ERR_STATE, "fmm_evaluate before fmm_upward");
     return guarded(p, [&]() -> fmm_status {
+        do_evaluate(p, phi, field, force, energy);
+        p->state = kStateEval;
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_evaluate_noalloc(fmm_plan *p, double *phi, double *field, double *force, double *energy) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateUp) return fail(p, FMM_ERR_STATE, "fmm_evaluate_noalloc before fmm_upward");
+    if (energy && p->nechunk > fmm::kScratchMaxChunks)
+        return fail(p, FMM_ERR_CAPACITY,
+                    "fmm_evaluate_noalloc: the energy needs " + std::to_string(p->nechunk) +
+                        " chunk partials, more than the scratch array holds (" +
+                        std::to_string(fmm::kScratchMaxChunks) + ")");
+    if (p->prm.precision == FMM_PREC_MIXED && p->tuning.p2p_per_cu > 0 && !p->nf.side)
+        return fail(p, FMM_ERR_STATE, "fmm_evaluate_noalloc: the work queue's side streams do not exist yet "
+                                      "(call fmm_evaluate once)");
+    return guarded(p, [&]() -> fmm_status {
+        unsigned char *base = static_cast<unsigned char *>(fmm::scratch_on(p->device));
+        if (!base) return fail(p, FMM_ERR_DEVICE, "fmm_evaluate_noalloc: the scratch array has no device address");
+        // every workspace the evaluation grows must be large enough already
+        struct Scope {
+            fmm_plan *p;
+            ~Scope() {
+                fmm::t_no_alloc = false;
+                p->heads_override = nullptr;
+                p->epart_override = nullptr;
+            }
+        } scope{p};
+        fmm::t_no_alloc = true;
+        p->heads_override = reinterpret_cast<int32_t *>(base);
+        p->epart_override = reinterpret_cast<double *>(base + fmm::kScratchHeads);
         do_evaluate(p, phi, field, force, energy);
         p->state = kStateEval;
         return FMM_OK;

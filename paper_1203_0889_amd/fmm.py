@@ -31,7 +31,7 @@ FLAG_DETERMINISTIC = 8
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
            "fmm_backward", "fmm_sync", "fmm_get_counts", "fmm_copy_tree", "fmm_copy_lists", "fmm_get_tuning",
            "fmm_set_tuning", "fmm_get_stage_times", "fmm_status_string", "fmm_last_error", "fmm_graph_capture",
-           "fmm_graph_launch", "fmm_autotune", "fmm_get_trace", "fmm_get_queue_info")
+           "fmm_graph_launch", "fmm_autotune", "fmm_get_trace", "fmm_get_queue_info", "fmm_evaluate_noalloc")
 
 
 class fmm_params(ctypes.Structure):
@@ -81,6 +81,7 @@ def load_library():
     lib.fmm_build_tree.argtypes = [vp, i32, P(i64), vp, vp]
     lib.fmm_upward.argtypes = [vp]
     lib.fmm_evaluate.argtypes = [vp, vp, vp, vp, vp]
+    lib.fmm_evaluate_noalloc.argtypes = [vp, vp, vp, vp, vp]
     lib.fmm_backward.argtypes = [vp, vp, vp, vp]
     lib.fmm_sync.argtypes = [vp]
     lib.fmm_graph_capture.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -224,6 +225,12 @@ class Plan:
     def evaluate_into(self, phi=None, field=None, force=None, energy=None):
         self._check_outputs(phi=phi, field=field, force=force, energy=energy)
         self._call(self._lib.fmm_evaluate, _ptr(phi), _ptr(field), _ptr(force), _ptr(energy))
+
+    def evaluate_noalloc_into(self, phi=None, field=None, force=None, energy=None):
+        """fmm_evaluate_noalloc: the evaluation into caller-owned outputs with
+        no device allocation (the plan's workspaces must already be sized)."""
+        self._check_outputs(phi=phi, field=field, force=force, energy=energy)
+        self._call(self._lib.fmm_evaluate_noalloc, _ptr(phi), _ptr(field), _ptr(force), _ptr(energy))
 
     def backward(self, grad_energy, want_pos=True, want_q=True):
         """Gradient of sum_k grad_energy[k] E_k (the FMM's energies) with
