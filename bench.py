@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--workload", default="uniform1m_p8",
                     help="uniform1m_p8 (default), plummer1m_p8, plummer4m_p10, uniform4k_p4 or batch256_p6")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--p", type=int, default=None,
+                    help="expansion order instead of the workload's (accuracy comparisons across orders)")
     ap.add_argument("--adjoint", action="store_true", help="time forward energy + fmm_backward per step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing leg")
     ap.add_argument("--no-error", action="store_true", help="skip the error check against the direct sum")
@@ -264,6 +266,8 @@ def base_result(a, value, ms, unit_metric):
 
 def run_single(a, torch, fmm, W):
     pos, q, w = W.make(a.workload)
+    if a.p is not None:
+        w = dict(w, p=a.p)
     n = len(q)
     print("bench: workload %s N=%d precision %s%s" % (a.workload, n, a.precision, " + adjoint" if a.adjoint else ""),
           file=sys.stderr, flush=True)
@@ -317,7 +321,7 @@ def run_single(a, torch, fmm, W):
         if a.workload != "uniform1m_p8":
             metric = "particles/s per FMM evaluation, %s" % a.workload
     result = base_result(a, n / (ms * 1e-3), ms, metric)
-    result["config"] = {"workload": a.workload, "n": n, "p": w["p"], "ncrit": w["ncrit"],
+    result["config"] = {"workload": a.workload if a.p is None else "%s_at_p%d" % (a.workload, a.p), "n": n, "p": w["p"], "ncrit": w["ncrit"],
                         "theta": "%d/%d" % tuple(w["theta"]), "precision": a.precision, "distribution": w["dist"],
                         "adjoint": bool(a.adjoint)}
     result["stages_ms"] = {k: round(v, 4) for k, v in stage_avg.items()}

@@ -14,7 +14,8 @@ OUT = os.path.join(HERE, "libfmm_mi355x.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sort.hip", "tree.hip", "lists.hip", "expansions.hip", "fp64_path.hip", "m2l_mfma.hip", "p2p_fp32.hip",
+SOURCES = ["sort.hip", "tree.hip", "lists.hip", "expansions.hip", "fp64_path.hip", "m2l_mfma.hip", "m2l_f64.hip",
+           "p2p_fp32.hip",
            "queue.hip", "near_far.hip", "plan.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

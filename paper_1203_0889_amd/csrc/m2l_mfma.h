@@ -29,6 +29,20 @@ void m2l_alloc_slots_ordered(int32_t *used, int32_t *slot_of, int32_t *nslots, i
 // the transpose of the forward pair's operator.
 void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int64_t op_elems,
                    bool transposed, uint16_t *ops, hipStream_t s);
+// The same operators in FP64 for the FP64 path's matrix cores
+// (v_mfma_f64_16x16x4f64 A fragments, m2l_f64_op_elems(p) doubles per class).
+void m2l_build_ops_f64(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int64_t op_elems,
+                       bool transposed, double *ops, hipStream_t s);
+// ---- m2l_f64.hip: the FP64 path's M2L on the FP64 matrix cores over the
+// class-batched tables; part receives FP64 partial locals per task (slot
+// task.w, P x kGroupM2L), summed by reduce_partials_f64.
+bool m2l_f64_supported(int p);
+void m2l_f64_tasks(const int4 *tasks, int32_t ntask, const int32_t *ecls, const int32_t *esrc, const double *ops,
+                   const double *M, int p, double *part, hipStream_t s);
+inline int64_t m2l_f64_op_elems(int p) {
+    const int P = ncoef(p);
+    return (int64_t)((P + 3) / 4) * ((P + 15) / 16) * 64;
+}
 // Sort keys (level, eighth, octant, cell) of the cells with table pairs;
 // xptr = exclusive scan of the per-owner counts of pairs outside the table.
 void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *xptr, uint64_t *tkey,

@@ -134,11 +134,14 @@ __device__ inline int32_t code_slot(int32_t code, const int32_t *__restrict__ sl
     return code < -1 ? slot_of[-2 - code] : code;
 }
 
-// Build the FP32 operator fragments of each new class: one workgroup per
-// class.  Lane m computes column m of I_n^m (n <= 2p) in FP64.
+// Build the operator fragments of each new class: one workgroup per class.
+// Lane m computes column m of I_n^m (n <= 2p) in FP64; the entries are
+// stored as split bf16 pieces for the mixed path's matrix cores, or (kF64)
+// as FP64 for the FP64 path's.
+template <bool kF64>
 __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ new_keys, int32_t nnew,
                                                    const int32_t *__restrict__ slot_of, int p, int RT,
-                                                   int64_t op_elems, int transposed, uint16_t *__restrict__ ops) {
+                                                   int64_t op_elems, int transposed, void *__restrict__ ops) {
     __shared__ double Ire[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2], Iim[(2 * kMaxP + 1) * (2 * kMaxP + 2) / 2];
     int32_t j = blockIdx.x;
     if (j >= nnew) return;
@@ -197,61 +200,76 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
     }
     __syncthreads();
     const int P = ncoef(p);
+    // entry (row, col) of the forward operator: output (n, m, part) and
+    // input (kk, l, part) of the real layouts
+    auto entry = [&](int row, int col) -> double {
+        if (row >= P || col >= P) return 0.0;
+        int n = 0;
+        while ((n + 1) * (n + 1) <= row) n++;
+        int ro = row - n * n, m = (ro + 1) / 2;
+        bool out_im = ro > 0 && !(ro & 1);
+        int kk = 0;
+        while ((kk + 1) * (kk + 1) <= col) kk++;
+        int co = col - kk * kk, l = (co + 1) / 2;
+        bool in_im = co > 0 && !(co & 1);
+        // I_(n+kk)^(mm) with conjugate symmetry for mm < 0
+        auto Ig = [&](int mm, double &re, double &im) {
+            int nn = n + kk, am = mm < 0 ? -mm : mm;
+            re = Ire[tri(nn, am)];
+            im = Iim[tri(nn, am)];
+            if (mm < 0) {
+                im = -im;
+                if (am & 1) {
+                    re = -re;
+                    im = -im;
+                }
+            }
+        };
+        double zr, zi;
+        if (l == 0) {
+            Ig(m, zr, zi);
+        } else {
+            double ar, ai, br, bi;
+            Ig(m + l, ar, ai);
+            Ig(m - l, br, bi);
+            double sg = (l & 1) ? -1.0 : 1.0;
+            if (!in_im) {
+                zr = ar + sg * br;
+                zi = ai + sg * bi;
+            } else {  // i * (a - sg b)
+                double dr = ar - sg * br, di = ai - sg * bi;
+                zr = -di;
+                zi = dr;
+            }
+        }
+        double v = out_im ? zi : zr;
+        v *= ldexp(1.0, delta * kk);
+        if (n & 1) v = -v;
+        return v;
+    };
+    if (kF64) {
+        // FP64 matrix-core fragments (v_mfma_f64_16x16x4f64, A operand):
+        // block (s RT + r) of 64 lanes holds T[16 r + lane % 16][4 s + lane / 16]
+        const int KS = (P + 3) / 4;
+        double *out = static_cast<double *>(ops) + (int64_t)slot_of[k] * op_elems;
+        const int total = KS * RT * 64;
+        for (int f = threadIdx.x; f < total; f += blockDim.x) {
+            const int lane = f & 63, r = (f >> 6) % RT, sk = (f >> 6) / RT;
+            const int orow = 16 * r + (lane & 15), ocol = 4 * sk + (lane >> 4);
+            out[f] = transposed ? entry(ocol, orow) : entry(orow, ocol);
+        }
+        return;
+    }
     // Block order: block ((s RT + r) 2 + piece) of 64 lanes x 8 bf16; lane
     // holds T[r 32 + lane % 32][16 s + 8 (lane / 32) + t], t < 8, piece 0 =
     // bf16 rounding of the value, piece 1 = bf16 rounding of the remainder.
     const int NK = 2 * RT;
-    uint16_t *out = ops + (int64_t)slot_of[k] * op_elems;
+    uint16_t *out = static_cast<uint16_t *>(ops) + (int64_t)slot_of[k] * op_elems;
     const int total = NK * RT * 64 * 8;  // values (each written as two pieces)
     for (int f = threadIdx.x; f < total; f += blockDim.x) {
         const int t = f & 7, lane = (f >> 3) & 63, r = (f >> 9) % RT, sk = (f >> 9) / RT;
         const int orow = r * 32 + (lane & 31), ocol = 16 * sk + 8 * (lane >> 5) + t;
-        const int row = transposed ? ocol : orow, col = transposed ? orow : ocol;  // entry of the forward T
-        double v = 0.0;
-        if (row < P && col < P) {
-            // output (n, m, part) and input (kk, l, part) of the real layouts
-            int n = 0;
-            while ((n + 1) * (n + 1) <= row) n++;
-            int ro = row - n * n, m = (ro + 1) / 2;
-            bool out_im = ro > 0 && !(ro & 1);
-            int kk = 0;
-            while ((kk + 1) * (kk + 1) <= col) kk++;
-            int co = col - kk * kk, l = (co + 1) / 2;
-            bool in_im = co > 0 && !(co & 1);
-            // I_(n+kk)^(mm) with conjugate symmetry for mm < 0
-            auto Ig = [&](int mm, double &re, double &im) {
-                int nn = n + kk, am = mm < 0 ? -mm : mm;
-                re = Ire[tri(nn, am)];
-                im = Iim[tri(nn, am)];
-                if (mm < 0) {
-                    im = -im;
-                    if (am & 1) {
-                        re = -re;
-                        im = -im;
-                    }
-                }
-            };
-            double zr, zi;
-            if (l == 0) {
-                Ig(m, zr, zi);
-            } else {
-                double ar, ai, br, bi;
-                Ig(m + l, ar, ai);
-                Ig(m - l, br, bi);
-                double sg = (l & 1) ? -1.0 : 1.0;
-                if (!in_im) {
-                    zr = ar + sg * br;
-                    zi = ai + sg * bi;
-                } else {  // i * (a - sg b)
-                    double dr = ar - sg * br, di = ai - sg * bi;
-                    zr = -di;
-                    zi = dr;
-                }
-            }
-            v = out_im ? zi : zr;
-            v *= ldexp(1.0, delta * kk);
-            if (n & 1) v = -v;
-        }
+        const double v = transposed ? entry(ocol, orow) : entry(orow, ocol);
         const uint32_t hi = bf16_bits((float)v);
         const uint32_t lo = bf16_bits((float)(v - (double)bf16_value(hi)));
         const int64_t blk = (int64_t)(sk * RT + r) * 2;
@@ -632,8 +650,16 @@ void m2l_alloc_slots_ordered(int32_t *used, int32_t *slot_of, int32_t *nslots, i
 void m2l_build_ops(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int RT, int64_t op_elems,
                    bool transposed, uint16_t *ops, hipStream_t s) {
     if (nnew <= 0) return;
-    hipLaunchKernelGGL(k_build_ops, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, op_elems,
-                       transposed ? 1 : 0, ops);
+    hipLaunchKernelGGL(k_build_ops<false>, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p, RT, op_elems,
+                       transposed ? 1 : 0, (void *)ops);
+    FMM_LAUNCH_CHECK();
+}
+
+void m2l_build_ops_f64(const int32_t *new_keys, int32_t nnew, const int32_t *slot_of, int p, int64_t op_elems,
+                       bool transposed, double *ops, hipStream_t s) {
+    if (nnew <= 0) return;
+    hipLaunchKernelGGL(k_build_ops<true>, dim3(nnew), dim3(256), 0, s, new_keys, nnew, slot_of, p,
+                       (ncoef(p) + 15) / 16, op_elems, transposed ? 1 : 0, (void *)ops);
     FMM_LAUNCH_CHECK();
 }
 

@@ -24,6 +24,9 @@ struct NearFarArgs {
     // multipoles, qs the adjoint weights; operators are stored transposed.
     bool transposed = false;
     bool deterministic = false;    // fixed order of every floating-point addition
+    // the FP64 path's tables: operators in FP64 for its matrix cores, no
+    // P2P task lists (its P2P is the FP64 kernel)
+    bool f64 = false;
     HostReader *reader = nullptr;  // fast device-to-host reads (optional)
     int32_t *heads = nullptr;      // 16 claim counters of the queue (null: the state's own)
     // task trace of the queue (optional): records, counter, capacity
@@ -44,10 +47,12 @@ struct NearFarState {
     DevBuf tasks_alt, tkeys, tidx, lists, tmp2;
     DevBuf part;   // per-task FP32 partial locals of the M2L tasks
     DevBuf key_rank;   // deterministic mode: ranks of the marked class keys
+    DevBuf frags64, part64;   // FP64 path: FP64 class operators, FP64 task partials
     // stream and events of the P2P side kernel (created on first use)
     hipStream_t side = nullptr, side2 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, after_queue = nullptr, after_side = nullptr;
     bool tail_pending = false;   // a deferred queue whose P2P tail is not launched yet
+    bool f64 = false;            // built for the FP64 path (FP64 operators, no task lists)
     int p = -1;
     int32_t nslot_total = 0, nslot = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0;
     bool built = false;
@@ -75,6 +80,10 @@ hipStream_t near_far_join_stream(const NearFarState &st);
 // After the queue (in stream order): the per-pair FP64 M2L of the pairs
 // outside the class table added to the locals.
 void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+// The FP64 path's M2L over the class tables (built with a.f64): zeroed
+// locals, the FP64 matrix-core tasks, their partials summed in task order,
+// then the per-pair FP64 M2L of the pairs outside the class table.
+void m2l_f64_run(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 void release_near_far(NearFarState &st);
 
 }  // namespace fmm

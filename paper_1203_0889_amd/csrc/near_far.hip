@@ -56,7 +56,8 @@ __global__ void k_make_lists(const int32_t *__restrict__ hc, int4 *__restrict__ 
 
 void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     const int p = a.p;
-    if (!queue_supported(p)) throw std::runtime_error("mixed precision supports p <= 12");
+    if (a.f64 ? !m2l_f64_supported(p) : !queue_supported(p))
+        throw std::runtime_error("the class-batched M2L supports p <= 12");
     const int RT = queue_row_tiles(p);
     const int64_t op_elems = queue_op_elems(p);
     const int32_t ncell = a.ncell;
@@ -123,13 +124,20 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     // while the host waits: the P2P leaves (by spatial eighth, costliest
     // first) and the cell centres, which need none of the sizes (unless
     // already built on another stream)
-    if (!a.p2p_ready) build_p2p_leaves(st, a, s);
+    if (!a.p2p_ready && !a.f64) build_p2p_leaves(st, a, s);
     int32_t h7[7];
     rd.end(h7, s);
     if (h7[5] > st.nslot_total) {
-        FMM_HIP_CHECK(st.frags.grow_keep((size_t)h7[5] * op_elems * 2, s));
-        m2l_build_ops(st.new_keys.as<int32_t>(), h7[6], st.slot_of.as<int32_t>(), p, RT, op_elems, a.transposed,
-                      st.frags.as<uint16_t>(), s);
+        if (a.f64) {
+            const int64_t e64 = m2l_f64_op_elems(p);
+            FMM_HIP_CHECK(st.frags64.grow_keep((size_t)h7[5] * e64 * 8, s));
+            m2l_build_ops_f64(st.new_keys.as<int32_t>(), h7[6], st.slot_of.as<int32_t>(), p, e64, a.transposed,
+                              st.frags64.as<double>(), s);
+        } else {
+            FMM_HIP_CHECK(st.frags.grow_keep((size_t)h7[5] * op_elems * 2, s));
+            m2l_build_ops(st.new_keys.as<int32_t>(), h7[6], st.slot_of.as<int32_t>(), p, RT, op_elems, a.transposed,
+                          st.frags.as<uint16_t>(), s);
+        }
         st.nslot_total = h7[5];
     }
     if (h7[2] < 0 || h7[2] > ncell || h7[1] < 0 || h7[1] > npair || h7[5] < 0)
@@ -183,6 +191,11 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                    st.tkey.as<uint64_t>(), st.ntask, st.tasks.as<int4>(), st.tasks_alt.as<int4>(),
                    st.tkeys.as<uint64_t>(), st.tkeys.as<uint64_t>() + nt1, st.tidx.as<uint32_t>(),
                    st.tidx.as<uint32_t>() + nt1, cnt + 16, st.tmp.as<int32_t>(), s);
+    st.f64 = a.f64;
+    if (a.f64) {   // no work queue: the tasks are launched as a grid
+        st.built = true;
+        return;
+    }
     // ---- the 16 task lists (M2L and P2P per XCD), built on the device
     if (a.p2p_ready) FMM_HIP_CHECK(hipStreamWaitEvent(s, a.p2p_ready, 0));
     FMM_HIP_CHECK(st.lists.grow(16 * sizeof(int4)));
@@ -333,10 +346,22 @@ void near_far_rest(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
                             a.deterministic, s);
 }
 
+void m2l_f64_run(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    if (!st.built || !st.f64) throw std::runtime_error("FP64 M2L tables not built");
+    const int P = ncoef(a.p);
+    FMM_HIP_CHECK(st.part64.grow((size_t)std::max(st.ntask, 1) * P * kGroupM2L * sizeof(double)));
+    fill_zero(a.L, (size_t)a.ncell * P * sizeof(double), s);
+    m2l_f64_tasks(st.tasks.as<int4>(), st.ntask, st.ecls.as<int32_t>(), st.esrc.as<int32_t>(), st.frags64.as<double>(),
+                  a.M, a.p, st.part64.as<double>(), s);
+    reduce_partials_f64(st.part64.as<double>(), st.toff.as<int32_t>(), st.tcount.as<int32_t>(),
+                        st.gtarget.as<int32_t>(), st.ntask > 0 ? st.ngroup : 0, a.p, a.L, s);
+    near_far_rest(st, a, s);
+}
+
 void release_near_far(NearFarState &st) {
     DevBuf *all[] = {&st.used, &st.slot_of, &st.nslots, &st.new_keys, &st.frags, &st.pcode, &st.xcount, &st.tkey,
                      &st.tkey_alt, &st.has, &st.gcount, &st.goff, &st.tcount, &st.toff, &st.ecls, &st.esrc, &st.gtarget, &st.tasks,
-                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists, &st.tmp2, &st.part, &st.key_rank};
+                     &st.xsrc, &st.xptr, &st.leafbuf, &st.leaves, &st.pf, &st.M32, &st.tmp, &st.cnt, &st.centre, &st.gbits, &st.gwpre, &st.tasks_alt, &st.tkeys, &st.tidx, &st.lists, &st.tmp2, &st.part, &st.key_rank, &st.frags64, &st.part64};
     if (st.side) {   // the side kernels may still read these buffers
         (void)hipStreamSynchronize(st.side);
         (void)hipStreamSynchronize(st.side2);

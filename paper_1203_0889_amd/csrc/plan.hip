@@ -11,6 +11,7 @@
 #include <stdexcept>
 
 #include "../../include/fmm.h"
+#include "m2l_mfma.h"
 #include "near_far.h"
 #include "tree.h"
 
@@ -484,6 +485,11 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         a.p2p_ready = p->p2p_done;   // the P2P leaf order, built on the second stream
         fmm::build_near_far_mixed(p->nf, a, s);
         mark(p, ST_NF_BUILD);
+    } else if (fmm::m2l_f64_supported(p->prm.p)) {
+        // the FP64 path's M2L runs over the same class tables, on the FP64
+        // matrix cores
+        fmm::build_near_far_mixed(p->nf, nf_args(p), s);
+        mark(p, ST_NF_BUILD);
     }
 }
 
@@ -511,6 +517,7 @@ fmm::NearFarArgs nf_args(fmm_plan *p) {
     a.tuning = p->tuning;
     a.reader = &p->reader;
     a.deterministic = deterministic(p);
+    a.f64 = p->prm.precision == FMM_PREC_FP64;
     return a;
 }
 
@@ -634,8 +641,11 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     bool time_queue = false;  // the queue stage ends at the join (recorded after the tail)
     record(p, ST_M2L);
     if (p->prm.precision == FMM_PREC_FP64) {
-        fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
-                             p->M.as<double>(), p->L.as<double>(), deterministic(p), s);
+        if (p->nf.built && p->nf.f64)
+            fmm::m2l_f64_run(p->nf, nf_args(p), s);
+        else
+            fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
+                                 p->M.as<double>(), p->L.as<double>(), deterministic(p), s);
         mark(p, ST_M2L);
         fmm::launch_p2p_fp64(g, ncell, p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(), p->xs.as<double>(),
                              p->ys.as<double>(), p->zs.as<double>(), p->qs.as<double>(), p->phi_near.as<double>(),
@@ -779,7 +789,8 @@ void build_adjoint(fmm_plan *p) {
     fmm::transpose_csr(p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(), ncell, p->np2p, bits, key32, p->tkeys.ptr,
                        p->tkeys_alt.ptr, p->tmp.as<int32_t>(), p->p2p_t_ptr.as<int32_t>(), p->p2p_t_src.as<int32_t>(),
                        s);
-    if (p->prm.precision == FMM_PREC_MIXED) fmm::build_near_far_mixed(p->nf_t, nf_args_adjoint(p), s);
+    if (p->prm.precision == FMM_PREC_MIXED || fmm::m2l_f64_supported(p->prm.p))
+        fmm::build_near_far_mixed(p->nf_t, nf_args_adjoint(p), s);
     p->adj_ready = true;
 }
 
@@ -810,8 +821,11 @@ void do_backward(fmm_plan *p, const double *gE, double *grad_pos, double *grad_q
                               p->lam.as<double>(), p->m2m_part.as<double>(), s);
     // M2L^T and P2P^T
     if (p->prm.precision == FMM_PREC_FP64) {
-        fmm::launch_m2l_fp64_adjoint(g, ncell, pp, p->m2l_t_ptr.as<int32_t>(), p->m2l_t_src.as<int32_t>(), p->nm2l,
-                                     p->lam.as<double>(), p->mu.as<double>(), 0, deterministic(p), s);
+        if (p->nf_t.built && p->nf_t.f64)
+            fmm::m2l_f64_run(p->nf_t, nf_args_adjoint(p), s);
+        else
+            fmm::launch_m2l_fp64_adjoint(g, ncell, pp, p->m2l_t_ptr.as<int32_t>(), p->m2l_t_src.as<int32_t>(),
+                                         p->nm2l, p->lam.as<double>(), p->mu.as<double>(), 0, deterministic(p), s);
         fmm::launch_p2p_fp64(g, ncell, p->p2p_t_ptr.as<int32_t>(), p->p2p_t_src.as<int32_t>(), p->xs.as<double>(),
                              p->ys.as<double>(), p->zs.as<double>(), p->wts.as<double>(), p->psi_near.as<double>(),
                              p->epsi_near.as<double>(), s);
@@ -1142,7 +1156,7 @@ fmm_status fmm_get_queue_info(const fmm_plan *p, int64_t *ntarget, int64_t *ngro
                               int64_t *nextra) {
     if (!p) return FMM_ERR_INVALID_ARG;
     if (p->state < kStateBuilt) return FMM_ERR_STATE;
-    const bool q = p->prm.precision == FMM_PREC_MIXED && p->nf.built;
+    const bool q = p->nf.built;
     if (ntarget) *ntarget = q ? p->nf.ntarget : 0;
     if (ngroup) *ngroup = q ? p->nf.ngroup : 0;
     if (ntask) *ntask = q ? p->nf.ntask : 0;

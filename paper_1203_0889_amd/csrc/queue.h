@@ -48,6 +48,10 @@ struct QueueArgs {
 };
 
 bool queue_supported(int p);
+// The sum of the FP64 path's per-task partial locals (the same layout in
+// FP64): L[gtarget[g][s]][k] = sum_j part[toff[g] + j][k][s] in task order.
+void reduce_partials_f64(const double *part, const int32_t *toff, const int32_t *tcount, const int32_t *gtarget,
+                         int32_t ngroup, int p, double *L, hipStream_t s);
 // Floats of one task's partial locals (P coefficients x kGroupM2L targets).
 inline int64_t queue_part_elems(int p) { return (int64_t)ncoef(p) * kGroupM2L; }
 

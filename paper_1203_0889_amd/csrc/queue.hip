@@ -523,7 +523,8 @@ __global__ void __launch_bounds__(256) k_p2p_side(QueueArgs a) {
 // through LDS so that each target's run of coefficients is written as one
 // contiguous piece of its row of L.
 constexpr int kRedRows = 16;
-__global__ void __launch_bounds__(kGroupM2L) k_reduce_partials(const float *__restrict__ part,
+template <class T>
+__global__ void __launch_bounds__(kGroupM2L) k_reduce_partials(const T *__restrict__ part,
                                                                const int32_t *__restrict__ toff,
                                                                const int32_t *__restrict__ tcount,
                                                                const int32_t *__restrict__ gtarget, int P,
@@ -536,13 +537,13 @@ __global__ void __launch_bounds__(kGroupM2L) k_reduce_partials(const float *__re
     const int32_t t0 = toff[g], nt = tcount[g];
     const int64_t ts = (int64_t)P * kGroupM2L;   // one task's partials
     tgt[s] = gtarget[(int64_t)g * kGroupM2L + s];
-    const float *base = part + ((int64_t)t0 * P + k0) * kGroupM2L + s;
+    const T *base = part + ((int64_t)t0 * P + k0) * kGroupM2L + s;
     for (int k = 0; k < nk; k++) {
-        const float *src = base + (int64_t)k * kGroupM2L;
+        const T *src = base + (int64_t)k * kGroupM2L;
         double acc = 0.0;
         int32_t j = 0;
         for (; j + 4 <= nt; j += 4) {   // four loads in flight, added in task order
-            const float v0 = src[j * ts], v1 = src[(j + 1) * ts], v2 = src[(j + 2) * ts], v3 = src[(j + 3) * ts];
+            const T v0 = src[j * ts], v1 = src[(j + 1) * ts], v2 = src[(j + 2) * ts], v3 = src[(j + 3) * ts];
             acc += (double)v0;
             acc += (double)v1;
             acc += (double)v2;
@@ -591,6 +592,15 @@ __global__ void k_split_multipoles(const double *__restrict__ M, int32_t ncell, 
 }  // namespace
 
 bool queue_supported(int p) { return p >= 0 && p <= 12; }
+
+void reduce_partials_f64(const double *part, const int32_t *toff, const int32_t *tcount, const int32_t *gtarget,
+                         int32_t ngroup, int p, double *L, hipStream_t s) {
+    if (ngroup <= 0) return;
+    const int P = ncoef(p), nrb = (P + kRedRows - 1) / kRedRows;
+    hipLaunchKernelGGL(k_reduce_partials<double>, dim3((unsigned)(ngroup * nrb)), dim3(kGroupM2L), 0, s, part, toff,
+                       tcount, gtarget, P, nrb, L);
+    FMM_LAUNCH_CHECK();
+}
 
 int queue_row_tiles(int p) { return (ncoef(p) + 31) / 32; }
 
@@ -648,8 +658,8 @@ bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, const Q
     // frees (before the deferred P2P workgroups below take them)
     if (a.ngroup > 0) {
         const int nrb = (a.P + kRedRows - 1) / kRedRows;
-        hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)(a.ngroup * nrb)), dim3(kGroupM2L), 0, s, a.part, a.toff,
-                           a.tcount, a.gtarget, a.P, nrb, a.L);
+        hipLaunchKernelGGL(k_reduce_partials<float>, dim3((unsigned)(a.ngroup * nrb)), dim3(kGroupM2L), 0, s, a.part,
+                           a.toff, a.tcount, a.gtarget, a.P, nrb, a.L);
         FMM_LAUNCH_CHECK();
     }
     if (defer) {
