@@ -110,6 +110,11 @@ def parse():
                     help="granularity sweep (the paper's Q experiment): M2L entries per task x N x p, one JSON line")
     ap.add_argument("--trace", action="store_true",
                     help="after the timed steps, one evaluation with the device task trace: summary in the line")
+    ap.add_argument("--timestep", type=int, default=0,
+                    help="time stepping: this many steps of straight-line motion per mode (full rebuild, "
+                         "incremental, incremental + step graph, incremental + cost reuse), one JSON line")
+    ap.add_argument("--drift", type=float, default=0.004,
+                    help="time stepping: largest move per step and axis, in units of the particle's leaf side")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -158,6 +163,38 @@ def cpu_baseline(w, n_cpu, n_1core):
             oracle.set_num_threads(cores)
         out["one_core"] = {"value": n_1core / (t1 - t0), "unit": "particles/s", "n": n_1core, "s": t1 - t0}
     return out
+
+
+def cpu_leg_error(pos, q, outs, w, n, grads=None):
+    """CPU leg, second part: the error of the GPU outputs against the
+    oracle's direct sum on a seeded sample of targets."""
+    import oracle
+    from paper_1203_0889_amd import workloads as W
+    sample = W.error_sample(n, w["seed"])
+    phi_d, fld_d = oracle.direct(pos, q, sample)
+    err = {"phi_rel_l2": rel_l2(outs["phi"].cpu().numpy()[sample], phi_d),
+           "field_rel_l2": rel_l2(outs["field"].cpu().numpy()[sample], fld_d), "sample": len(sample)}
+    if grads is not None:
+        # dE/dq = phi, dE/dx = -F of the exact (symmetric) direct sum
+        err["grad_q_rel_l2"] = rel_l2(grads[1].cpu().numpy()[sample], phi_d)
+        err["grad_pos_rel_l2"] = rel_l2(grads[0].cpu().numpy()[sample], -q[sample, None] * fld_d)
+    return err
+
+
+def cpu_leg_error_batch(pos, q, offs, phi, field):
+    """CPU leg for a batch: every 32nd instance against the oracle's direct
+    sum (all targets up to 8192 particles, else 1024 seeded targets)."""
+    import oracle
+    errs = []
+    ph, fl = phi.cpu().numpy(), field.cpu().numpy()
+    for k in range(0, len(offs) - 1, 32):
+        lo, hi = offs[k], offs[k + 1]
+        nk = hi - lo
+        tg = np.arange(nk) if nk <= 8192 else np.sort(np.random.default_rng(k).choice(nk, 1024, replace=False))
+        pd, fd = oracle.direct(pos[lo:hi], q[lo:hi], tg)
+        errs.append((rel_l2(ph[lo:hi][tg], pd), rel_l2(fl[lo:hi][tg], fd)))
+    return {"phi_rel_l2_max": max(e[0] for e in errs), "field_rel_l2_max": max(e[1] for e in errs),
+            "instances_checked": len(errs)}
 
 
 def rel_l2(a, b):
@@ -221,7 +258,8 @@ def queue_roofline(plan, stage_avg, p, n, precision, workload, tuning):
     if roof["achieved"] is not None:
         roof["frac"] = roof["achieved"] / roof["peak"]
     work = {"ncell": counts["ncell"], "nleaf": counts["nleaf"], "m2l_pairs": counts["nm2l"],
-            "p2p_pairs": counts["np2p"], "p2p_interactions": inter, "p2p_flop": p2p_flop, "m2l_flop": m2l_f}
+            "p2p_pairs": counts["np2p"], "p2p_interactions": inter, "p2p_flop": p2p_flop, "m2l_flop": m2l_f,
+            "m2l_tables": plan.queue_info()}
     return roof, work
 
 
@@ -346,16 +384,8 @@ def run_single(a, torch, fmm, W):
     if not a.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w, min(a.cpu_n, n) if a.cpu_n > 0 else n, a.cpu_n_1core)
     if not a.no_error:
-        import oracle
-        sample = W.error_sample(n, w["seed"])
-        phi_d, fld_d = oracle.direct(pos, q, sample)
-        err = {"phi_rel_l2": rel_l2(phi.cpu().numpy()[sample], phi_d),
-               "field_rel_l2": rel_l2(field.cpu().numpy()[sample], fld_d), "sample": len(sample)}
-        if a.adjoint:
-            # dE/dq = phi, dE/dx = -F of the exact (symmetric) direct sum
-            err["grad_q_rel_l2"] = rel_l2(grads[1].cpu().numpy()[sample], phi_d)
-            err["grad_pos_rel_l2"] = rel_l2(grads[0].cpu().numpy()[sample], -q[sample, None] * fld_d)
-        result["error"] = err
+        result["error"] = cpu_leg_error(pos, q, {"phi": phi, "field": field}, w, n,
+                                        grads if a.adjoint else None)
     return result
 
 
@@ -431,17 +461,7 @@ def run_batch(a, torch, fmm, W):
     result["sequential"] = {"ms": seq_ms, "particles_per_s": n / (seq_ms * 1e-3), "speedup_of_batch": seq_ms / ms}
     result["graph_replay_upward_evaluate"] = {"ms": graph_ms, "particles_per_s": n / (graph_ms * 1e-3)}
     if not a.no_error:
-        import oracle
-        errs = []
-        ph, fl = phi.cpu().numpy(), field.cpu().numpy()
-        for k in range(0, n_inst, 32):    # every 32nd instance: full direct sum if small, else 1024 targets
-            lo, hi = offs[k], offs[k + 1]
-            nk = hi - lo
-            tg = np.arange(nk) if nk <= 8192 else np.sort(np.random.default_rng(k).choice(nk, 1024, replace=False))
-            pd, fd = oracle.direct(pos[lo:hi], q[lo:hi], tg)
-            errs.append((rel_l2(ph[lo:hi][tg], pd), rel_l2(fl[lo:hi][tg], fd)))
-        result["error"] = {"phi_rel_l2_max": max(e[0] for e in errs), "field_rel_l2_max": max(e[1] for e in errs),
-                           "instances_checked": len(errs)}
+        result["error"] = cpu_leg_error_batch(pos, q, offs, phi, field)
     return result
 
 
@@ -484,6 +504,117 @@ def run_sweep(a, torch, fmm, W):
     return {"sweep": "M2L class entries per task x N x p, uniform, ncrit 64, theta 1/2, mixed", "rows": rows}
 
 
+def run_timestep(a, torch, fmm, W):
+    """Time stepping on one workload: every particle moves along a straight
+    line, at most `drift` of its leaf side per step and axis; each mode runs
+    `warmup` untimed then `timestep` timed steps of (tree, upward, evaluate)
+    from the step's positions, which sit in device memory beforehand.
+    Modes: full rebuild every step; FMM_FLAG_INCREMENTAL (the topology is
+    kept while every particle stays inside its leaf widened by 1/8 of a side);
+    the same with the whole step replayed from a captured graph (the step's
+    positions are copied into the graph's input first); both again with
+    FMM_FLAG_COST_REUSE (P2P tasks ordered by the durations measured in the
+    previous step).  `value` is the last mode's rate (mixed), else that of
+    the step graph."""
+    from paper_1203_0889_amd import trace as T
+    pos, q, w = W.make(a.workload)
+    n = len(q)
+    dev = torch.device("cuda", 0)
+    k_all = a.warmup + a.timestep
+    print("bench: time stepping %s N=%d, %d + %d steps, drift %.4g leaf sides per step"
+          % (a.workload, n, a.warmup, a.timestep, a.drift), file=sys.stderr, flush=True)
+    probe = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0)
+    dpos0, dq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
+    probe.build_tree(dpos0, dq)
+    _, perm, cells = probe.copy_tree()
+    tuning = probe.get_tuning()
+    if a.precision == "mixed" and not a.no_autotune:
+        probe.upward()
+        tuning, _ = probe.autotune(repeats=2)
+    probe.close()
+    # leaf side of every particle (input order): the tight cube's side over 2^level
+    side0 = float(np.max(pos.max(axis=0) - pos.min(axis=0)))
+    side = np.zeros(n)
+    for c in np.nonzero(cells[:, 6] < 0)[0]:
+        side[perm[cells[c, 4]:cells[c, 4] + cells[c, 5]]] = side0 / 2.0 ** cells[c, 0]
+    vel = torch.from_numpy(W.velocities(n, w["seed"] + 1000, a.drift * side)).to(dev)
+    steps_pos = [(dpos0 + k * vel).contiguous() for k in range(1, k_all + 1)]
+    outs = {"phi": torch.empty(n, dtype=torch.float64, device=dev),
+            "field": torch.empty((n, 3), dtype=torch.float64, device=dev),
+            "force": torch.empty((n, 3), dtype=torch.float64, device=dev),
+            "energy": torch.empty(1, dtype=torch.float64, device=dev)}
+    modes = {}
+    mode_names = ["rebuild", "incremental", "incremental_graph"]
+    if a.precision == "mixed":
+        mode_names += ["incremental_cost_reuse", "incremental_graph_cost_reuse"]
+    for mode in mode_names:
+        kw = dict(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0)
+        if mode != "rebuild":
+            kw["incremental"] = True
+        if mode.endswith("cost_reuse"):
+            kw["cost_reuse"] = True
+        plan = fmm.Plan(**kw)
+        plan.set_tuning(**tuning)
+        plan.build_tree(dpos0, dq)
+        gpos = None
+        if "graph" in mode:
+            gpos = steps_pos[0].clone()
+            plan.graph_capture_step(gpos, dq, **outs)
+
+        def step(k):
+            if gpos is not None:
+                gpos.copy_(steps_pos[k])
+                plan.graph_launch()
+            else:
+                plan.build_tree(steps_pos[k], dq)
+                plan.upward()
+                plan.evaluate_into(**outs)
+
+        for k in range(a.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(a.warmup, k_all):
+            step(k)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if gpos is not None:
+            plan.sync()          # the replays' leaf checks
+        ms = (t1 - t0) * 1e3 / a.timestep
+        modes[mode] = {"ms_per_step": ms, "particles_per_s": n / (ms * 1e-3), "builds": plan.build_info()}
+        print("bench: %s %s" % (mode, json.dumps(modes[mode])), file=sys.stderr, flush=True)
+        plan.close()
+    if a.precision == "mixed":
+        # the same steps with the task trace on, with and without cost
+        # reuse: the balance of the work queue in the last step
+        balance = {}
+        for reuse in (False, True):
+            tp = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0,
+                          incremental=True, trace=True, cost_reuse=reuse)
+            tp.set_tuning(**tuning)
+            tp.build_tree(dpos0, dq)
+            for k in range(k_all):
+                tp.build_tree(steps_pos[k], dq)
+                tp.upward()
+                tp.evaluate_into(**outs)
+            balance["cost_reuse" if reuse else "estimated_costs"] = T.summarize(tp.trace())
+            tp.close()
+        modes["queue_balance_last_step"] = balance
+        print("bench: balance %s" % json.dumps(balance), file=sys.stderr, flush=True)
+    best = "incremental_graph_cost_reuse" if a.precision == "mixed" else "incremental_graph"
+    result = base_result(a, modes[best]["particles_per_s"], modes[best]["ms_per_step"],
+                         "particles/s per time step (tree, upward, evaluate) on a kept topology, %s" % a.workload)
+    result["steps"] = a.timestep
+    result["config"] = {"workload": "%s_timestep" % a.workload, "n": n, "p": w["p"], "ncrit": w["ncrit"],
+                        "theta": "%d/%d" % tuple(w["theta"]), "precision": a.precision, "distribution": w["dist"],
+                        "drift_leaf_sides_per_step": a.drift}
+    result["tuning"] = tuning
+    result["modes"] = modes
+    if not a.no_error:
+        result["error"] = cpu_leg_error(steps_pos[-1].cpu().numpy(), q, outs, w, n)   # the last step's outputs
+    return result
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -493,6 +624,8 @@ def main():
     from paper_1203_0889_amd import fmm, workloads as W
     if a.sweep:
         result = run_sweep(a, torch, fmm, W)
+    elif a.timestep > 0:
+        result = run_timestep(a, torch, fmm, W)
     elif a.workload == "batch256_p6":
         result = run_batch(a, torch, fmm, W)
     else:

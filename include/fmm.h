@@ -72,9 +72,36 @@ enum {
                                         pairs outside the class table without
                                         atomics); the work queue's M2L sums are
                                         in a fixed order in every mode */
-    FMM_FLAG_TRACE = 1u << 2          /* mixed precision: the work queue of
+    FMM_FLAG_TRACE = 1u << 2,         /* mixed precision: the work queue of
                                         fmm_evaluate records one fmm_task_record
                                         per task it runs (fmm_get_trace) */
+    FMM_FLAG_INCREMENTAL = 1u << 4,   /* time stepping: a later fmm_build_tree with
+                                        the same n_inst and offsets keeps the
+                                        topology (as FMM_FLAG_KEEP_TOPOLOGY) while
+                                        every particle, in its stored sort order,
+                                        lies inside its old leaf cell widened by
+                                        1/8 of the cell's side on every face; it
+                                        rebuilds from scratch otherwise.  The
+                                        widening scales every cell's radius by
+                                        at most 5/4, so an accepted pair's
+                                        separation ratio (Sec. 2.1) stays below
+                                        5/4 theta: the expansions converge
+                                        (needs 5 num < 4 den, else
+                                        FMM_ERR_INVALID_ARG at fmm_create) and
+                                        the worst-case truncation bound is that
+                                        of theta' = 5/4 theta.
+                                        fmm_get_build_info counts both kinds of
+                                        build */
+    FMM_FLAG_COST_REUSE = 1u << 5     /* mixed precision: the work queue measures
+                                        the duration of every P2P task (device
+                                        clock, one store per task), and a kept-
+                                        topology rebuild (KEEP_TOPOLOGY /
+                                        INCREMENTAL, also inside a graph of
+                                        fmm_graph_capture_step) orders the next
+                                        evaluation's P2P tasks by those
+                                        durations instead of the estimated
+                                        costs (Sec. 2.2: the previous step's
+                                        work as the weights) */
 };
 
 typedef struct {
@@ -187,6 +214,22 @@ fmm_status fmm_backward(fmm_plan *plan, const double *grad_energy, double *grad_
 fmm_status fmm_graph_capture(fmm_plan *plan, double *phi, double *field, double *force, double *energy,
                              const double *grad_energy, double *grad_pos, double *grad_q);
 
+/*
+ * Record one whole time step into the plan's graph: the frozen-topology
+ * fmm_build_tree from pos / q (device, layouts as for fmm_build_tree; read
+ * at every replay, so the caller writes the next step's positions there),
+ * fmm_upward and fmm_evaluate into the given outputs.  Needs a built tree
+ * and FMM_FLAG_KEEP_TOPOLOGY or FMM_FLAG_INCREMENTAL; with INCREMENTAL a
+ * replay also checks that every particle stays inside its widened leaf cell
+ * and fmm_sync then returns FMM_ERR_STATE when one left it (the step's
+ * outputs are then not to be used: rebuild with fmm_build_tree and capture
+ * again).  A non-finite coordinate makes fmm_sync return
+ * FMM_ERR_INVALID_ARG.  Runs the step once eagerly, then captures it as
+ * fmm_graph_capture does.  N = 0: FMM_ERR_INVALID_ARG.
+ */
+fmm_status fmm_graph_capture_step(fmm_plan *plan, const double *pos, const double *q, double *phi, double *field,
+                                  double *force, double *energy);
+
 /* Replay the captured graph on the plan's stream (asynchronous). */
 fmm_status fmm_graph_launch(fmm_plan *plan);
 
@@ -198,14 +241,22 @@ fmm_status fmm_sync(fmm_plan *plan);
 fmm_status fmm_get_counts(const fmm_plan *plan, int64_t *ncell, int64_t *nleaf, int64_t *nm2l,
                           int64_t *np2p);
 
+/* Number of fmm_build_tree calls that built the tree from scratch and of
+ * those that kept the previous topology (host outputs; any may be NULL).
+ * The eager step of fmm_graph_capture_step counts as a kept build; graph
+ * replays are not counted. */
+fmm_status fmm_get_build_info(const fmm_plan *plan, int64_t *full_builds, int64_t *kept_builds);
+
 /*
  * Sizes of the work-queue tables of the mixed path after fmm_build_tree
  * (host outputs; any may be NULL): the target cells of the batched M2L
  * (cells owning at least one pair of the class table, Sec. 4 lists regrouped
  * by class), their groups of 256, the M2L tasks (the task size is the
  * paper's granularity knob, Sec. 5), the operator classes in use, and the
- * M2L pairs left to the per-pair FP64 kernel.  The FP64 path has no queue:
- * every count is 0.  Before a build: FMM_ERR_STATE.
+ * M2L pairs left to the per-pair FP64 kernel.  The FP64 path reports the
+ * same class tables, which its FP64 matrix-core M2L runs over for p <= 12
+ * (no P2P tasks; every count is 0 above p = 12).  Before a build:
+ * FMM_ERR_STATE.
  */
 fmm_status fmm_get_queue_info(const fmm_plan *plan, int64_t *ntarget, int64_t *ngroup, int64_t *ntask,
                               int64_t *nclass, int64_t *nextra);

@@ -1,6 +1,7 @@
 // Internal launchers of the class-batched MFMA M2L and the FP32 P2P.
 #pragma once
 
+#include "../../include/fmm.h"
 #include "tree.h"
 
 namespace fmm {
@@ -80,8 +81,11 @@ void m2l_extra(const int32_t *ptr, int32_t ncell, const int32_t *src, const int3
 // ---- p2p_fp32.hip (preparation of the P2P tasks)
 // Leaves ordered by (spatial eighth, cost descending); d_count[0] = number
 // of leaves, d_count[1 + x] = leaves in eighth x.
+// measured (nullable): per-cell durations of the previous evaluation's P2P
+// tasks, used as the cost where positive.
 void p2p_leaf_list(CellArrays c, int32_t ncell, int64_t n, const int32_t *p2p_ptr, const int32_t *p2p_src,
-                   int32_t *buf, int32_t *leaves, int32_t *tmp, int32_t *d_count, hipStream_t s);
+                   const float *measured, int32_t *buf, int32_t *leaves, int32_t *tmp, int32_t *d_count,
+                   hipStream_t s);
 void p2p_prepare(Geometry g, int64_t n, const int32_t *leaf_of, const double *xs, const double *ys,
                  const double *zs, const double *qs, float4 *pf, hipStream_t s);
 void cell_centres(Geometry g, int32_t ncell, double *centre, hipStream_t s);

@@ -29,6 +29,8 @@ struct NearFarArgs {
     bool f64 = false;
     HostReader *reader = nullptr;  // fast device-to-host reads (optional)
     int32_t *heads = nullptr;      // 16 claim counters of the queue (null: the state's own)
+    const float *leaf_cost = nullptr;   // measured P2P task durations by cell, read for the order (nullable)
+    float *cost_out = nullptr;          // the work queue writes its P2P task durations here (nullable)
     // task trace of the queue (optional): records, counter, capacity
     fmm_task_record *trace = nullptr;
     int32_t *trace_count = nullptr;
@@ -64,6 +66,9 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
 // The P2P leaf order and the cell centres (needs only the tree and the P2P
 // lists), for a second stream.
 void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+// The P2P leaf order again (a.leaf_cost: measured costs) and the 16 task
+// lists, on a kept topology.
+void reorder_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // Evaluate-time part, in stream order: inputs of the queue (bf16 multipoles,
 // FP32 particles, zeroed locals), the work-queue kernel (M2L and P2P tasks),
 // then the per-pair FP64 M2L of the pairs outside the class table.

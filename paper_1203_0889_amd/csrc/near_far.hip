@@ -210,11 +210,18 @@ void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     FMM_HIP_CHECK(st.leafbuf.grow((size_t)4 * (ncell + 1) * 4));
     FMM_HIP_CHECK(st.leaves.grow((size_t)std::max(ncell, 1) * 4));
     FMM_HIP_CHECK(st.tmp2.grow(radix_tmp_elems(ncell) * 4));
-    p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, st.leafbuf.as<int32_t>(), st.leaves.as<int32_t>(),
-                  st.tmp2.as<int32_t>(), st.cnt.as<int32_t>() + 24, s);
+    p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, a.leaf_cost, st.leafbuf.as<int32_t>(),
+                  st.leaves.as<int32_t>(), st.tmp2.as<int32_t>(), st.cnt.as<int32_t>() + 24, s);
     // the cell centres, which the P2P tasks read (target and source leaf offsets)
     FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
     cell_centres(a.g, ncell, st.centre.as<double>(), s);
+}
+
+void reorder_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
+    if (!st.built || st.f64) return;
+    build_p2p_leaves(st, a, s);
+    hipLaunchKernelGGL(k_make_lists, dim3(1), dim3(64), 0, s, st.cnt.as<int32_t>() + 16, st.lists.as<int4>());
+    FMM_LAUNCH_CHECK();
 }
 
 void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
@@ -281,6 +288,7 @@ QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
     q.trace = a.trace && a.trace_count && a.trace_cap > 0 ? a.trace : nullptr;
     q.trace_count = a.trace_count;
     q.trace_cap = a.trace_cap;
+    q.leaf_cost = a.cost_out;
     return q;
 }
 

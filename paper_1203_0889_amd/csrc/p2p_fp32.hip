@@ -32,8 +32,11 @@ __global__ void k_centres(Geometry g, int32_t ncell, double *__restrict__ centre
 // leaves by eighth (the XCD that runs them) and puts the costliest first
 // within each (to the resolution of q; equal keys keep cell order).
 // Non-leaves get 0xffff, after every leaf.
+// With measured (durations of the previous evaluation's P2P tasks, by
+// cell; 0 where none was measured) the measured cost replaces the estimate.
 __global__ void k_leaf_cost(CellArrays c, int32_t ncell, int64_t n, const int32_t *__restrict__ ptr,
-                            const int32_t *__restrict__ src, uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+                            const int32_t *__restrict__ src, const float *__restrict__ measured,
+                            uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
     const int lane = threadIdx.x & 63;
     const float inv_n8 = 8.0f / (float)n;
     for (int32_t i = blockIdx.x * blockDim.x / 64 + threadIdx.x / 64; i < ncell; i += gridDim.x * blockDim.x / 64) {
@@ -63,6 +66,7 @@ __global__ void k_leaf_cost(CellArrays c, int32_t ncell, int64_t n, const int32_
                 // eighth (a 64-bit integer division or an FP64 log2 costs
                 // a wave hundreds of instructions)
                 cost *= (uint64_t)c.count[i];
+                if (measured && measured[i] > 0.0f) cost = (uint64_t)measured[i];
                 int c8 = (int)((float)c.first[i] * inv_n8);
                 c8 = c8 > 7 ? 7 : c8;
                 const float lq = 200.0f * __log2f((float)cost + 1.0f);
@@ -108,7 +112,8 @@ __global__ void k_p2p_prepare(Geometry g, int64_t n, const int32_t *__restrict__
 
 // buf holds 4 * (ncell + 1) ints: keys, values, alternate keys/values.
 void p2p_leaf_list(CellArrays c, int32_t ncell, int64_t n, const int32_t *p2p_ptr, const int32_t *p2p_src,
-                   int32_t *buf, int32_t *leaves, int32_t *tmp, int32_t *d_count, hipStream_t s) {
+                   const float *measured, int32_t *buf, int32_t *leaves, int32_t *tmp, int32_t *d_count,
+                   hipStream_t s) {
     uint32_t *key = (uint32_t *)(buf + (ncell + 1));
     uint32_t *kalt = (uint32_t *)(buf + 2 * (ncell + 1));
     uint32_t *valt = (uint32_t *)(buf + 3 * (ncell + 1));
@@ -118,7 +123,7 @@ void p2p_leaf_list(CellArrays c, int32_t ncell, int64_t n, const int32_t *p2p_pt
         return;
     }
     hipLaunchKernelGGL(k_leaf_cost, dim3(grid_for((int64_t)ncell * 64, 256, 16384)), dim3(256), 0, s, c, ncell, n,
-                       p2p_ptr, p2p_src, key, val);
+                       p2p_ptr, p2p_src, measured, key, val);
     FMM_LAUNCH_CHECK();
     radix_sort_u32(key, val, kalt, valt, ncell, 0, 16, tmp, s);
     hipLaunchKernelGGL(k_leaf_counts, dim3(1), dim3(64), 0, s, key, ncell, d_count);

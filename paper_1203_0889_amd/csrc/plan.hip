@@ -68,6 +68,10 @@ constexpr size_t kScratchBytes = (size_t)1 << 20;
 constexpr size_t kScratchHeads = 256;   // bytes 0..255: the 16 claim counters of the work queue
 constexpr int kScratchMaxChunks = (int)((kScratchBytes - kScratchHeads) / sizeof(double));   // energy partials
 constexpr int kMaxDevices = 64;
+// flag[] (16 ints, device): [0] non-finite input of a build, [1] leaf
+// count, [kRefreshFlag, +1] non-finite coordinate / particle outside its
+// widened leaf in a frozen-topology rebuild
+constexpr int kRefreshFlag = 4;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 static void *g_scratch[kMaxDevices] = {};
 static std::mutex g_scratch_mutex;
@@ -153,6 +157,10 @@ struct fmm_plan {
     fmm::HostReader reader;
     DevBuf phi_near, fld_near, phi_far, fld_far, echunk, epart;
     DevBuf trace, trace_count;   // task trace of the forward queue (FMM_FLAG_TRACE)
+    DevBuf leaf_cost;            // P2P task durations by cell, measured by the last evaluation
+    bool leaf_cost_valid = false;
+    int64_t nbuild_full = 0, nbuild_kept = 0;   // builds from scratch / on a kept topology
+    bool graph_step = false;     // the captured graph starts with a frozen-topology rebuild
     int32_t trace_cap = 0;
     bool traced = false;
     int32_t nechunk = 0;
@@ -219,6 +227,7 @@ void drop_graph(fmm_plan *p) {
     if (p->graph) hipGraphDestroy(p->graph);
     p->graph_exec = nullptr;
     p->graph = nullptr;
+    p->graph_step = false;
 }
 
 void sync_read(fmm_plan *p, void *host, const void *dev, size_t bytes) { p->reader.read(host, dev, bytes, p->stream); }
@@ -230,6 +239,9 @@ int bits_for(int64_t n) {
 }
 
 bool deterministic(const fmm_plan *p) { return (p->prm.flags & FMM_FLAG_DETERMINISTIC) != 0; }
+bool cost_reuse(const fmm_plan *p) {
+    return (p->prm.flags & FMM_FLAG_COST_REUSE) && p->prm.precision == FMM_PREC_MIXED;
+}
 
 fmm::Geometry geom(fmm_plan *p) {
     fmm::Geometry g;
@@ -666,6 +678,12 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
             a.trace_cap = p->trace_cap;
             p->traced = true;
         }
+        // the queue measures every P2P task for the next kept-topology
+        // rebuild (leaf_cost is sized by the build)
+        if (cost_reuse(p)) {
+            a.cost_out = p->leaf_cost.as<float>();
+            p->leaf_cost_valid = true;
+        }
         fmm::near_far_prepare(p->nf, a, s);
         mark(p, ST_NF_PREP);
         // with a P2P side kernel the P2P tasks run on beside the FP64 M2L
@@ -740,17 +758,37 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
 }
 
 // Frozen-topology rebuild: new positions and charges through the stored
-// permutation; box, keys, tree, lists and task tables stay.
-void do_refresh(fmm_plan *p, const double *pos, const double *q) {
+// permutation; box, keys, tree, lists and task tables stay.  check_leaf
+// (incremental mode): also checks that every particle is still inside its
+// leaf cell widened by 1/8 of its side; returns false if one is not (the
+// caller then rebuilds).  Under graph capture nothing is read back: the
+// flags stay on the device for fmm_sync.  With the P2P task durations the
+// last evaluation on this topology measured (FMM_FLAG_COST_REUSE), the P2P
+// tasks are reordered by them.
+bool do_refresh(fmm_plan *p, const double *pos, const double *q, bool check_leaf) {
     hipStream_t s = p->stream;
     p->upward_fresh = false;   // new particles: fmm_upward recomputes
-    FMM_HIP_CHECK(hipMemsetAsync(p->flag.ptr, 0, 16 * sizeof(int), s));
-    fmm::launch_bbox(pos, p->n, p->off.as<int64_t>(), p->n_inst, p->ord.as<unsigned long long>(), p->flag.as<int>(), s);
+    int32_t *rflag = p->flag.as<int32_t>() + fmm::kRefreshFlag;   // the build's flags stay
+    fmm::fill_zero(rflag, 2 * sizeof(int32_t), s);
     fmm::launch_gather(pos, q, p->idx.as<uint32_t>(), p->n, p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
                        p->qs.as<double>(), s);
-    int bad = 0;
-    sync_read(p, &bad, p->flag.ptr, sizeof(int));
-    if (bad) throw std::invalid_argument("non-finite particle coordinate");
+    fmm::launch_refresh_check(cells_of(p), p->leaf_of.as<int32_t>(), p->xs.as<double>(), p->ys.as<double>(),
+                              p->zs.as<double>(), p->box.as<double>(), p->scale.as<double>(), p->n, check_leaf,
+                              rflag, s);
+    if (!p->capturing) {
+        int32_t f[2] = {0, 0};
+        sync_read(p, f, rflag, sizeof(f));
+        if (f[0]) throw std::invalid_argument("non-finite particle coordinate");
+        if (f[1]) return false;
+    }
+    if (cost_reuse(p) && p->leaf_cost_valid) {
+        // device work only, so a captured step reorders at every replay by
+        // the durations the previous replay measured
+        fmm::NearFarArgs a = nf_args(p);
+        a.leaf_cost = p->leaf_cost.as<float>();
+        fmm::reorder_p2p_leaves(p->nf, a, s);
+    }
+    return true;
 }
 
 fmm::NearFarArgs nf_args_adjoint(fmm_plan *p) {
@@ -876,10 +914,13 @@ fmm_status check_params(const fmm_params *q, std::string *why) {
     if (q->theta_num < 1 || q->theta_den < 1 || q->theta_num > 100 || q->theta_den > 100 ||
         q->theta_num >= q->theta_den)
         return *why = "theta must be num/den with 1 <= num < den <= 100", FMM_ERR_INVALID_ARG;
+    if ((q->flags & FMM_FLAG_INCREMENTAL) && 5 * q->theta_num >= 4 * q->theta_den)
+        return *why = "FMM_FLAG_INCREMENTAL needs theta < 4/5 (cells widened by 1/8 of a side)", FMM_ERR_INVALID_ARG;
     if (q->max_level < 1 || q->max_level > fmm::kLevels) return *why = "max_level must be in [1, 21]", FMM_ERR_INVALID_ARG;
     if (q->precision != FMM_PREC_FP64 && q->precision != FMM_PREC_MIXED)
         return *why = "unknown precision", FMM_ERR_INVALID_ARG;
-    if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY | FMM_FLAG_TRACE | FMM_FLAG_DETERMINISTIC))
+    if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY | FMM_FLAG_TRACE | FMM_FLAG_DETERMINISTIC |
+                               FMM_FLAG_INCREMENTAL | FMM_FLAG_COST_REUSE))
         return *why = "unknown flag", FMM_ERR_INVALID_ARG;
     if ((q->flags & FMM_FLAG_USER_BOX) &&
         !(q->box_side > 0 && std::isfinite(q->box_side) && std::isfinite(q->box_min[0]) &&
@@ -953,7 +994,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
                      &p->fld_far, &p->echunk, &p->epart, &p->ops_m2m_t, &p->ops_l2l_t, &p->m2l_t_ptr,
                      &p->m2l_t_src, &p->p2p_t_ptr, &p->p2p_t_src, &p->tkeys, &p->tkeys_alt, &p->lam, &p->mu,
                      &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far, &p->trace,
-                     &p->trace_count, &p->pair_alt2, &p->tmp2};
+                     &p->trace_count, &p->pair_alt2, &p->tmp2, &p->leaf_cost};
     drop_graph(p);
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();
@@ -986,17 +1027,25 @@ fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, c
     int64_t n = offsets[n_inst];
     if (n >= ((int64_t)1 << 31) - 1) return fail(p, FMM_ERR_INVALID_ARG, "too many particles (limit 2^31 - 2)");
     if (n > 0 && (!pos || !q)) return fail(p, FMM_ERR_INVALID_ARG, "pos and q required");
-    const bool keep = (p->prm.flags & FMM_FLAG_KEEP_TOPOLOGY) && p->state >= kStateBuilt && n_inst == p->n_inst &&
+    const bool same = p->state >= kStateBuilt && n_inst == p->n_inst &&
                       std::equal(offsets, offsets + n_inst + 1, p->h_off.begin());
+    const bool keep = same && (p->prm.flags & FMM_FLAG_KEEP_TOPOLOGY);
+    const bool incremental = same && !keep && (p->prm.flags & FMM_FLAG_INCREMENTAL);
     return guarded(p, [&]() -> fmm_status {
-        if (keep && n > 0) {
+        if ((keep || incremental) && n > 0) {
+            const int saved = p->state;
             p->state = kStateBuilt;
-            do_refresh(p, pos, q);
-            return FMM_OK;
+            if (do_refresh(p, pos, q, incremental)) {
+                p->nbuild_kept++;
+                return FMM_OK;
+            }
+            p->state = saved;   // a particle left its leaf: rebuild from these positions
         }
         p->state = kStateCreated;
         p->adj_ready = false;
         p->traced = false;
+        p->leaf_cost_valid = false;
+        p->nbuild_full++;
         drop_graph(p);
         p->n = n;
         p->n_inst = n_inst;
@@ -1004,6 +1053,7 @@ fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, c
         for (bool &u : p->ev_used) u = false;
         p->last_ev = nullptr;
         do_build(p, pos, q);
+        if (cost_reuse(p)) FMM_HIP_CHECK(p->leaf_cost.grow((size_t)std::max<int64_t>(p->ncell, 1) * sizeof(float)));
         p->state = kStateBuilt;
         return FMM_OK;
     });
@@ -1072,55 +1122,92 @@ fmm_status fmm_backward(fmm_plan *p, const double *grad_energy, double *grad_pos
     });
 }
 
+namespace {
+// Record a solve into the plan's graph: run it once eagerly (sizing every
+// workspace), synchronise, then capture the same calls on a private stream
+// (the plan's stream may be the legacy null stream, which cannot be
+// captured) and instantiate.  step_pos / step_q: the solve starts with a
+// frozen-topology rebuild from them.
+void capture_solve(fmm_plan *p, const double *step_pos, const double *step_q, double *phi, double *field, double *force,
+                   double *energy, const double *grad_energy, double *grad_pos, double *grad_q) {
+    drop_graph(p);
+    const bool check_leaf = (p->prm.flags & FMM_FLAG_INCREMENTAL) != 0;
+    auto solve = [&]() {
+        if (step_pos) {
+            if (!do_refresh(p, step_pos, step_q, check_leaf))
+                throw std::invalid_argument("a particle is outside its leaf cell: rebuild the tree before capturing");
+            if (!p->capturing) p->nbuild_kept++;
+        }
+        do_upward(p);
+        do_evaluate(p, phi, field, force, energy);
+        if (grad_energy) do_backward(p, grad_energy, grad_pos, grad_q);
+    };
+    solve();
+    p->state = kStateEval;
+    FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+    hipStream_t cs = nullptr;
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));   // default priority
+    hipStream_t saved = p->stream;
+    p->stream = cs;
+    p->capturing = true;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    hipGraph_t g = nullptr;
+    if (e == hipSuccess) {
+        try {
+            solve();
+        } catch (...) {
+            hipStreamEndCapture(cs, &g);
+            if (g) hipGraphDestroy(g);
+            p->capturing = false;
+            p->stream = saved;
+            hipStreamDestroy(cs);
+            throw;
+        }
+        e = hipStreamEndCapture(cs, &g);
+    }
+    p->capturing = false;
+    p->stream = saved;
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        throw fmm::HipError{e, "stream capture"};
+    }
+    p->graph = g;
+    FMM_HIP_CHECK(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+    p->graph_step = step_pos != nullptr;
+}
+}  // namespace
+
 fmm_status fmm_graph_capture(fmm_plan *p, double *phi, double *field, double *force, double *energy,
                              const double *grad_energy, double *grad_pos, double *grad_q) {
     if (!p) return FMM_ERR_INVALID_ARG;
     if (p->state < kStateBuilt) return fail(p, FMM_ERR_STATE, "fmm_graph_capture before fmm_build_tree");
     if (p->n == 0) return fail(p, FMM_ERR_INVALID_ARG, "nothing to capture (N = 0)");
     return guarded(p, [&]() -> fmm_status {
-        drop_graph(p);
-        // one eager pass sizes every workspace and builds the adjoint tables
-        do_upward(p);
-        do_evaluate(p, phi, field, force, energy);
-        p->state = kStateEval;
-        if (grad_energy) do_backward(p, grad_energy, grad_pos, grad_q);
-        FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
-        // The plan's stream may be the legacy null stream, which cannot be
-        // captured: record on a private stream (default priority), replay on
-        // the plan's stream.
-        hipStream_t cs = nullptr;
-        FMM_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipStream_t saved = p->stream;
-        p->stream = cs;
-        p->capturing = true;
-        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        hipGraph_t g = nullptr;
-        if (e == hipSuccess) {
-            try {
-                do_upward(p);
-                do_evaluate(p, phi, field, force, energy);
-                if (grad_energy) do_backward(p, grad_energy, grad_pos, grad_q);
-            } catch (...) {
-                hipStreamEndCapture(cs, &g);
-                if (g) hipGraphDestroy(g);
-                p->capturing = false;
-                p->stream = saved;
-                hipStreamDestroy(cs);
-                throw;
-            }
-            e = hipStreamEndCapture(cs, &g);
-        }
-        p->capturing = false;
-        p->stream = saved;
-        hipStreamDestroy(cs);
-        if (e != hipSuccess) {
-            if (g) hipGraphDestroy(g);
-            throw fmm::HipError{e, "stream capture"};
-        }
-        p->graph = g;
-        FMM_HIP_CHECK(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+        capture_solve(p, nullptr, nullptr, phi, field, force, energy, grad_energy, grad_pos, grad_q);
         return FMM_OK;
     });
+}
+
+fmm_status fmm_graph_capture_step(fmm_plan *p, const double *pos, const double *q, double *phi, double *field,
+                                  double *force, double *energy) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (p->state < kStateBuilt) return fail(p, FMM_ERR_STATE, "fmm_graph_capture_step before fmm_build_tree");
+    if (!(p->prm.flags & (FMM_FLAG_KEEP_TOPOLOGY | FMM_FLAG_INCREMENTAL)))
+        return fail(p, FMM_ERR_STATE, "fmm_graph_capture_step needs FMM_FLAG_KEEP_TOPOLOGY or FMM_FLAG_INCREMENTAL");
+    if (p->n == 0) return fail(p, FMM_ERR_INVALID_ARG, "nothing to capture (N = 0)");
+    if (!pos || !q) return fail(p, FMM_ERR_INVALID_ARG, "pos and q required");
+    return guarded(p, [&]() -> fmm_status {
+        capture_solve(p, pos, q, phi, field, force, energy, nullptr, nullptr, nullptr);
+        return FMM_OK;
+    });
+}
+
+fmm_status fmm_get_build_info(const fmm_plan *p, int64_t *full_builds, int64_t *kept_builds) {
+    if (!p) return FMM_ERR_INVALID_ARG;
+    if (full_builds) *full_builds = p->nbuild_full;
+    if (kept_builds) *kept_builds = p->nbuild_kept;
+    return FMM_OK;
 }
 
 fmm_status fmm_graph_launch(fmm_plan *p) {
@@ -1138,6 +1225,13 @@ fmm_status fmm_sync(fmm_plan *p) {
     if (!p) return FMM_ERR_INVALID_ARG;
     return guarded(p, [&]() -> fmm_status {
         FMM_HIP_CHECK(hipStreamSynchronize(p->stream));
+        if (p->graph_step && p->flag.ptr) {   // the checks of a replayed frozen-topology rebuild
+            int32_t f[2] = {0, 0};
+            FMM_HIP_CHECK(hipMemcpy(f, p->flag.as<int32_t>() + fmm::kRefreshFlag, sizeof(f), hipMemcpyDeviceToHost));
+            if (f[0]) return fail(p, FMM_ERR_INVALID_ARG, "non-finite particle coordinate in the replayed step");
+            if (f[1])
+                return fail(p, FMM_ERR_STATE, "a particle left its leaf cell in the replayed step: rebuild the tree");
+        }
         return FMM_OK;
     });
 }

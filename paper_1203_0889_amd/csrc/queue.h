@@ -45,6 +45,9 @@ struct QueueArgs {
     fmm_task_record *trace;
     int32_t *trace_count;
     int32_t trace_cap;
+    // measured P2P task durations (null: off): leaf_cost[leaf] = device
+    // clock ticks of the leaf's task, one plain store per task
+    float *leaf_cost;
 };
 
 bool queue_supported(int p);

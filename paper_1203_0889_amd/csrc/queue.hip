@@ -458,9 +458,11 @@ __device__ inline void p2p_phase(const QueueArgs &a, int x, int lane, float4 *__
             t = __builtin_amdgcn_readfirstlane(t);      // lane 0's claim, wave-uniform
             if (t >= li.y) break;
             const int32_t leaf = a.leaves[li.z + t];
-            const uint64_t t0 = a.trace ? __builtin_amdgcn_s_memrealtime() : 0;
+            const bool timed = a.trace || a.leaf_cost;
+            const uint64_t t0 = timed ? __builtin_amdgcn_s_memrealtime() : 0;
             p2p_leaf(a, leaf, tile, lane);
             if (a.trace && lane == 0) trace_task(a, 1, leaf, kernel, t0);
+            if (a.leaf_cost && lane == 0) a.leaf_cost[leaf] = (float)(__builtin_amdgcn_s_memrealtime() - t0);
         }
     }
 }

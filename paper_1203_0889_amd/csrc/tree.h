@@ -54,6 +54,12 @@ void launch_tree_level_dev(CellArrays c, int32_t *lev, int level, int nlev, int 
                            int32_t cap, hipStream_t s);
 // leaf_of[r] = leaf cell of sorted particle r; *nleaf = number of leaves.
 void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, int32_t *nleaf, hipStream_t s);
+// After a frozen-topology gather: flag[0] |= 1 if a coordinate is not
+// finite; with check_leaf, flag[1] |= 1 if a particle left its leaf cell
+// widened by 1/8 of the side on every face (the tree no longer fits it).
+void launch_refresh_check(CellArrays c, const int32_t *leaf_of, const double *xs, const double *ys, const double *zs,
+                          const double *box, const double *scale, int64_t n, bool check_leaf, int32_t *flag,
+                          hipStream_t s);
 
 // ---- lists.hip
 struct PairBuf {

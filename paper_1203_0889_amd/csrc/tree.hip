@@ -432,7 +432,46 @@ __global__ void k_leaf_of(CellArrays c, int32_t ncell, int32_t *__restrict__ lea
     }
 }
 
+// A frozen-topology rebuild: every sorted particle's new coordinates are
+// finite (flag[0]) and, with check_leaf, still inside its leaf cell widened
+// by 1/8 of its side on every face (flag[2] otherwise).  Coordinates in
+// grid units of the stored box, as the keys were computed.
+__global__ void k_refresh_check(CellArrays c, const int32_t *__restrict__ leaf_of, const double *__restrict__ xs,
+                                const double *__restrict__ ys, const double *__restrict__ zs,
+                                const double *__restrict__ box, const double *__restrict__ scale, int64_t n,
+                                int check_leaf, int32_t *__restrict__ flag) {
+    bool bad = false, out = false;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const double x[3] = {xs[r], ys[r], zs[r]};
+        if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+            bad = true;
+            continue;
+        }
+        if (!check_leaf) continue;
+        const int32_t A = leaf_of[r];
+        const int k = c.inst[A], L = c.level[A];
+        const double side = ldexp(1.0, kLevels - L), slack = side * 0.125;
+        const int32_t cc[3] = {c.ix[A], c.iy[A], c.iz[A]};
+        for (int d = 0; d < 3; d++) {
+            const double sg = __dmul_rn(__dsub_rn(x[d], box[4 * k + d]), scale[k]);
+            const double lo = cc[d] * side;
+            if (!(sg >= lo - slack && sg < lo + side + slack)) out = true;
+        }
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&flag[0], 1);
+    if (__ballot(out) && (threadIdx.x & 63) == 0) atomicOr(&flag[1], 1);
+}
+
 }  // namespace
+
+void launch_refresh_check(CellArrays c, const int32_t *leaf_of, const double *xs, const double *ys, const double *zs,
+                          const double *box, const double *scale, int64_t n, bool check_leaf, int32_t *flag,
+                          hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_refresh_check, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, c, leaf_of, xs, ys, zs, box,
+                       scale, n, check_leaf ? 1 : 0, flag);
+    FMM_LAUNCH_CHECK();
+}
 
 void launch_bbox(const double *pos, int64_t n, const int64_t *d_offsets, int n_inst, unsigned long long *d_ord,
                  int *d_bad, hipStream_t s) {

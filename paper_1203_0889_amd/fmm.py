@@ -26,12 +26,15 @@ FLAG_USER_BOX = 1
 FLAG_KEEP_TOPOLOGY = 2
 FLAG_TRACE = 4
 FLAG_DETERMINISTIC = 8
+FLAG_INCREMENTAL = 16
+FLAG_COST_REUSE = 32
 
 # every symbol include/fmm.h declares
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
            "fmm_backward", "fmm_sync", "fmm_get_counts", "fmm_copy_tree", "fmm_copy_lists", "fmm_get_tuning",
            "fmm_set_tuning", "fmm_get_stage_times", "fmm_status_string", "fmm_last_error", "fmm_graph_capture",
-           "fmm_graph_launch", "fmm_autotune", "fmm_get_trace", "fmm_get_queue_info", "fmm_evaluate_noalloc")
+           "fmm_graph_launch", "fmm_autotune", "fmm_get_trace", "fmm_get_queue_info", "fmm_evaluate_noalloc",
+           "fmm_graph_capture_step", "fmm_get_build_info")
 
 
 class fmm_params(ctypes.Structure):
@@ -85,7 +88,9 @@ def load_library():
     lib.fmm_backward.argtypes = [vp, vp, vp, vp]
     lib.fmm_sync.argtypes = [vp]
     lib.fmm_graph_capture.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.fmm_graph_capture_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.fmm_graph_launch.argtypes = [vp]
+    lib.fmm_get_build_info.argtypes = [vp, P(i64), P(i64)]
     lib.fmm_autotune.argtypes = [vp, i32, P(fmm_tuning), P(ctypes.c_double)]
     lib.fmm_get_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64)]
     lib.fmm_get_queue_info.argtypes = [vp, P(i64), P(i64), P(i64), P(i64), P(i64)]
@@ -130,7 +135,8 @@ class Plan:
     """One FMM plan: owns the tree, lists and expansions on one device/stream."""
 
     def __init__(self, p=8, ncrit=64, theta=(1, 2), max_level=21, precision="mixed", device=None, stream=None,
-                 box=None, keep_topology=False, trace=False, deterministic=False):
+                 box=None, keep_topology=False, trace=False, deterministic=False, incremental=False,
+                 cost_reuse=False):
         self._lib = load_library()
         prm = fmm_params()
         self._lib.fmm_default_params(ctypes.byref(prm))
@@ -148,6 +154,10 @@ class Plan:
             prm.flags |= FLAG_TRACE
         if deterministic:
             prm.flags |= FLAG_DETERMINISTIC
+        if incremental:
+            prm.flags |= FLAG_INCREMENTAL
+        if cost_reuse:
+            prm.flags |= FLAG_COST_REUSE
         self.params = prm
         if device is None:
             device = torch.cuda.current_device()
@@ -253,6 +263,17 @@ class Plan:
         self._call(self._lib.fmm_graph_capture, _ptr(phi), _ptr(field), _ptr(force), _ptr(energy), _ptr(grad_energy),
                    _ptr(grad_pos), _ptr(grad_q))
 
+    def graph_capture_step(self, pos, q, phi=None, field=None, force=None, energy=None):
+        """Capture a whole time step (frozen-topology rebuild from pos / q,
+        upward, evaluate) into a HIP graph; every replay reads pos and q
+        again, so write the next step's positions into the same tensors."""
+        _check_dev(pos, "pos", shape=(self.n, 3), device=self.device)
+        _check_dev(q, "q", shape=(self.n,), device=self.device)
+        self._check_outputs(phi=phi, field=field, force=force, energy=energy)
+        self._graph_refs = (pos, q, phi, field, force, energy)
+        self._call(self._lib.fmm_graph_capture_step, _ptr(pos), _ptr(q), _ptr(phi), _ptr(field), _ptr(force),
+                   _ptr(energy))
+
     def graph_launch(self):
         self._call(self._lib.fmm_graph_launch)
 
@@ -264,6 +285,12 @@ class Plan:
         v = [ctypes.c_int64() for _ in range(4)]
         self._call(self._lib.fmm_get_counts, *[ctypes.byref(x) for x in v])
         return dict(zip(("ncell", "nleaf", "nm2l", "np2p"), (x.value for x in v)))
+
+    def build_info(self):
+        """fmm_build_tree calls so far: built from scratch / on a kept topology."""
+        v = [ctypes.c_int64() for _ in range(2)]
+        self._call(self._lib.fmm_get_build_info, *[ctypes.byref(x) for x in v])
+        return {"full": v[0].value, "kept": v[1].value}
 
     def queue_info(self):
         """Work-queue table sizes of the last build (mixed path; zeros for FP64)."""

@@ -10,7 +10,9 @@ Distributions:
   * plummer  -- Plummer sphere with scale radius a = 1 truncated at r = 20
                 (inverse-CDF radius, isotropic direction, no recentring);
   * batch    -- instance sizes N_k = round(2^(10 + 6 u_k)), u_k ~ U[0, 1),
-                i.e. log-uniform in [1024, 65536].
+                i.e. log-uniform in [1024, 65536];
+  * velocities -- straight-line motion for time stepping: displacement
+                directions uniform in [-1, 1]^3, scaled per particle.
 Charges are uniform in [-1, 1] unless stated.
 """
 import numpy as np
@@ -41,6 +43,15 @@ def plummer(n, seed, a=1.0, rmax=20.0, equal_charges=False):
     else:
         q = rng.uniform(-1.0, 1.0, n)
     return pos, q
+
+
+def velocities(n, seed, amplitude=1.0):
+    """Per-particle displacement directions for synthetic time stepping:
+    amplitude (a scalar or one value per particle) times a vector uniform in
+    [-1, 1]^3.  Step k of a run moves particle i to pos_i + k dt v_i."""
+    a = np.asarray(amplitude, dtype=np.float64)
+    v = _rng(seed).uniform(-1.0, 1.0, (n, 3))
+    return v * (a[:, None] if a.ndim == 1 else a)
 
 
 def error_sample(n, seed, k=4096):

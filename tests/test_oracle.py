@@ -532,3 +532,35 @@ def test_workload_generators():
     assert sizes.min() >= 1024 and sizes.max() <= 65536 and len(sizes) == 256
     s = W.error_sample(1 << 20, 2)
     assert len(np.unique(s)) == 4096
+
+
+def leaf_sides(T):
+    """Side of the leaf cell holding every particle (input order)."""
+    lv, cf = T.cell("level"), T.cell("child_first")
+    first, cnt = T.cell("first"), T.cell("count")
+    side = np.zeros(T.n)
+    for c in np.nonzero(cf < 0)[0]:
+        side[T.perm[first[c]:first[c] + cnt[c]]] = T.box[3] / 2.0 ** lv[c]
+    return side
+
+
+def test_fmm_frozen_tree_moved_particles():
+    """Evaluation on a kept tree with moved particles (time stepping without
+    a rebuild): each particle moves by up to 1/10 of its leaf side per axis,
+    so it stays inside its leaf widened by 1/8; the result is still the
+    potential of the moved particles to the FMM's accuracy at p = 8, and far
+    from that of the old positions (the new ones are really read)."""
+    pos0, q = W.uniform_cube(3000, 51)
+    T = oracle.Tree(pos0, 32)
+    T.lists(1, 2)
+    side = leaf_sides(T)
+    assert np.all(side > 0)
+    phi0, E0 = T.fmm(q, 8)
+    phis, Es = T.fmm(q, 8, pos=pos0)
+    assert np.array_equal(phi0, phis) and np.array_equal(E0, Es)
+    pos1 = pos0 + W.velocities(3000, 52, 0.1 * side)
+    phi1, E1 = T.fmm(q, 8, pos=pos1)
+    pd, Ed = oracle.direct(pos1, q)
+    assert rel(phi1, pd) < 1e-6 and rel(E1, Ed) < 1e-6
+    pd0, Ed0 = oracle.direct(pos0, q)
+    assert rel(phi1, pd0) > 1e-2 and rel(E1, Ed0) > 1e-1
