@@ -67,8 +67,8 @@ def committed_counters(workload, tuning):
 
 
 def tuning_text(t):
-    return "m2l_task_entries=%d,grid_per_cu=%d,p2p_per_cu=%d" % (t["m2l_task_entries"], t["grid_per_cu"],
-                                                                  t["p2p_per_cu"])
+    return "m2l_task_entries=%d,grid_per_cu=%d,p2p_per_cu=%d,early_p2p_per_cu=%d" % (
+        t["m2l_task_entries"], t["grid_per_cu"], t["p2p_per_cu"], t.get("early_p2p_per_cu", 0))
 
 
 def fixed_tuning(text):
@@ -528,7 +528,9 @@ def run_timestep(a, torch, fmm, W):
     probe.build_tree(dpos0, dq)
     _, perm, cells = probe.copy_tree()
     tuning = probe.get_tuning()
-    if a.precision == "mixed" and not a.no_autotune:
+    if a.tuning:
+        tuning.update(fixed_tuning(a.tuning))
+    elif a.precision == "mixed" and not a.no_autotune:
         probe.upward()
         tuning, _ = probe.autotune(repeats=2)
     probe.close()

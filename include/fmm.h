@@ -295,6 +295,12 @@ typedef struct {
                                  the work-queue workgroups of a compute unit alternate
                                  between starting with M2L and with P2P tasks, otherwise
                                  all of them start with M2L */
+    int32_t early_p2p_per_cu; /* of those, workgroups per compute unit started by
+                                 fmm_build_tree as soon as the near field's inputs exist
+                                 (the P2P lists; Sec. 3: a task runs once its inputs are
+                                 ready), beside the upward pass and the far-field build
+                                 (0..p2p_per_cu; 0: the near field starts with the work
+                                 queue; not with FMM_FLAG_TRACE) */
 } fmm_tuning;
 
 fmm_status fmm_get_tuning(const fmm_plan *plan, fmm_tuning *tuning);
@@ -307,7 +313,9 @@ fmm_status fmm_set_tuning(fmm_plan *plan, const fmm_tuning *tuning);
  * times one evaluation (fmm_evaluate without outputs: the queue, the far
  * field that runs beside its P2P tail, the join) for m2l_task_entries in
  * {32, 64, 96, 128} and (grid_per_cu, p2p_per_cu) in {(1, 1), (1, 2),
- * (1, 3), (2, 0), (3, 0)} (the task tables are rebuilt per
+ * (1, 3), (2, 0), (3, 0), (2, 1), (2, 2)}; early_p2p_per_cu is kept as set
+ * (at most p2p_per_cu), since its gain depends on the build it overlaps
+ * (the task tables are rebuilt per
  * m2l_task_entries; each setting takes the fastest of `repeats` >= 1 runs,
  * HIP events on the plan's stream), keeps the fastest setting and rebuilds
  * the tables with it.  Outputs (host, may be NULL): the chosen tuning and

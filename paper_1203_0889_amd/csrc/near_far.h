@@ -50,10 +50,20 @@ struct NearFarState {
     DevBuf part;   // per-task FP32 partial locals of the M2L tasks
     DevBuf key_rank;   // deterministic mode: ranks of the marked class keys
     DevBuf frags64, part64;   // FP64 path: FP64 class operators, FP64 task partials
-    // stream and events of the P2P side kernel (created on first use)
-    hipStream_t side = nullptr, side2 = nullptr;
+    // streams and events of the P2P side kernels (created on first use):
+    // side (launched with the queue), side2 (the deferred tail), side3 (the
+    // early near field)
+    hipStream_t side = nullptr, side2 = nullptr, side3 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, after_queue = nullptr, after_side = nullptr;
     bool tail_pending = false;   // a deferred queue whose P2P tail is not launched yet
+    bool tail_side = false, tail_early = false;   // what the pending tail joins
+    // a P2P side kernel of the current particles was started early
+    // (near_far_start_p2p, early_wg workgroups) with these claim counters
+    // and not yet joined by a queue
+    bool early = false;
+    int early_wg = 0;
+    const int32_t *early_heads = nullptr;
+    hipEvent_t early_fork = nullptr, early_done = nullptr;
     bool f64 = false;            // built for the FP64 path (FP64 operators, no task lists)
     int p = -1;
     int32_t nslot_total = 0, nslot = 0, ngroup = 0, ntarget = 0, nentries = 0, ntask = 0, nextra = 0;
@@ -69,13 +79,26 @@ void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // The P2P leaf order again (a.leaf_cost: measured costs) and the 16 task
 // lists, on a kept topology.
 void reorder_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s);
+// Start the near field as soon as its inputs exist (the paper's data-driven
+// order: P2P needs neither the upward pass nor the far-field tables): zero
+// the claim counters on `from`, then on the side stream the FP32 particles
+// and the P2P side kernel.  Needs the P2P leaf order and task lists
+// (build_p2p_leaves) and the near-field outputs sized.  The next
+// near_far_queue joins the running kernel instead of launching one.
+// Returns false (nothing started) without side workgroups or with a trace.
+bool near_far_start_p2p(NearFarState &st, const NearFarArgs &a, hipStream_t from);
+// Make s wait for an early P2P kernel that no queue joined (before its
+// inputs or outputs change); no-op otherwise.
+void near_far_drop_early(NearFarState &st, hipStream_t s);
 // Evaluate-time part, in stream order: inputs of the queue (bf16 multipoles,
 // FP32 particles, zeroed locals), the work-queue kernel (M2L and P2P tasks),
 // then the per-pair FP64 M2L of the pairs outside the class table.
 void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // defer_join: see queue_run; then near_far_join(st, s) before the near
 // field is read.  Returns whether the join was deferred.
-bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join = false);
+// *joined_early: the queue joined an early P2P kernel.
+bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join = false,
+                    bool *joined_early = nullptr);
 // The deferred P2P tail: more P2P workgroups once the work queued on s so
 // far (the far field) is done, then the join event.
 void near_far_tail(NearFarState &st, const NearFarArgs &a, hipStream_t s);

@@ -13,6 +13,7 @@ fmm_tuning default_tuning() {
     t.m2l_task_entries = 128;
     t.grid_per_cu = 1;
     t.p2p_per_cu = 2;
+    t.early_p2p_per_cu = 0;
     return t;
 }
 
@@ -38,18 +39,16 @@ struct Reader {
     }
 };
 
-// The 16 task lists from the per-XCD counts (cnt[16..23] M2L tasks,
-// cnt[25..32] leaves): list 2x = (first task, count, 0, 0), list 2x + 1 =
-// (0, leaves, first leaf, 0).
-__global__ void k_make_lists(const int32_t *__restrict__ hc, int4 *__restrict__ lists) {
+// The 16 task lists from the per-XCD counts: list 2x = (first task,
+// count, 0, 0) from the M2L task counts hc[0..7] (kind 0); list 2x + 1 =
+// (0, leaves, first leaf, 0) from the leaf counts hc[0..7] (kind 1).  The
+// two halves are written by different streams and never overlap.
+__global__ void k_make_lists(const int32_t *__restrict__ hc, int kind, int4 *__restrict__ lists) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int32_t mt = 0, lf = 0;
+    int32_t first = 0;
     for (int x = 0; x < 8; x++) {
-        lists[2 * x] = make_int4(mt, hc[x], 0, 0);
-        mt += hc[x];
-        const int32_t nl = hc[9 + x];
-        lists[2 * x + 1] = make_int4(0, nl, lf, 0);
-        lf += nl;
+        lists[2 * x + kind] = kind == 0 ? make_int4(first, hc[x], 0, 0) : make_int4(0, hc[x], first, 0);
+        first += hc[x];
     }
 }
 }  // namespace
@@ -199,7 +198,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     // ---- the 16 task lists (M2L and P2P per XCD), built on the device
     if (a.p2p_ready) FMM_HIP_CHECK(hipStreamWaitEvent(s, a.p2p_ready, 0));
     FMM_HIP_CHECK(st.lists.grow(16 * sizeof(int4)));
-    hipLaunchKernelGGL(k_make_lists, dim3(1), dim3(64), 0, s, cnt + 16, st.lists.as<int4>());
+    hipLaunchKernelGGL(k_make_lists, dim3(1), dim3(64), 0, s, cnt + 16, 0, st.lists.as<int4>());
     FMM_LAUNCH_CHECK();
     st.built = true;
 }
@@ -212,6 +211,10 @@ void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     FMM_HIP_CHECK(st.tmp2.grow(radix_tmp_elems(ncell) * 4));
     p2p_leaf_list(a.g.c, ncell, a.n, a.p2p_ptr, a.p2p_src, a.leaf_cost, st.leafbuf.as<int32_t>(),
                   st.leaves.as<int32_t>(), st.tmp2.as<int32_t>(), st.cnt.as<int32_t>() + 24, s);
+    // the P2P task lists (the M2L ones follow from the far-field build)
+    FMM_HIP_CHECK(st.lists.grow(16 * sizeof(int4)));
+    hipLaunchKernelGGL(k_make_lists, dim3(1), dim3(64), 0, s, st.cnt.as<int32_t>() + 25, 1, st.lists.as<int4>());
+    FMM_LAUNCH_CHECK();
     // the cell centres, which the P2P tasks read (target and source leaf offsets)
     FMM_HIP_CHECK(st.centre.grow((size_t)std::max(ncell, 1) * 3 * 8));
     cell_centres(a.g, ncell, st.centre.as<double>(), s);
@@ -220,8 +223,6 @@ void build_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
 void reorder_p2p_leaves(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (!st.built || st.f64) return;
     build_p2p_leaves(st, a, s);
-    hipLaunchKernelGGL(k_make_lists, dim3(1), dim3(64), 0, s, st.cnt.as<int32_t>() + 16, st.lists.as<int4>());
-    FMM_LAUNCH_CHECK();
 }
 
 void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
@@ -236,7 +237,7 @@ void near_far_prepare(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     FMM_HIP_CHECK(st.part.grow((size_t)std::max(st.ntask, 1) * queue_part_elems(a.p) * sizeof(float)));
     queue_split_multipoles(a.M, ncell, a.p, st.M32.as<uint16_t>(), s);
     fill_zero(a.L, (size_t)ncell * P * 8, s);
-    p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
+    if (!st.early) p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), s);
 }
 
 namespace {
@@ -250,6 +251,9 @@ void ensure_streams(NearFarState &st) {
     FMM_HIP_CHECK(hipEventCreateWithFlags(&st.join, hipEventDisableTiming));
     FMM_HIP_CHECK(hipEventCreateWithFlags(&st.after_queue, hipEventDisableTiming));
     FMM_HIP_CHECK(hipEventCreateWithFlags(&st.after_side, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&st.side3, hipStreamNonBlocking));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&st.early_fork, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&st.early_done, hipEventDisableTiming));
 }
 
 int compute_units() {
@@ -257,6 +261,20 @@ int compute_units() {
     FMM_HIP_CHECK(hipGetDevice(&dev));
     FMM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     return ncu;
+}
+
+// with_side / with_early: this queue's side kernel, an early P2P kernel
+QueueStreams streams_of(const NearFarState &st, bool with_side, bool with_early) {
+    QueueStreams qs;
+    qs.side = with_side ? st.side : nullptr;
+    qs.side2 = st.side2;
+    qs.fork = st.fork;
+    qs.join = st.join;
+    qs.after_queue = st.after_queue;
+    qs.after_side = st.after_side;
+    qs.early = with_early ? st.side3 : nullptr;
+    qs.early_done = st.early_done;
+    return qs;
 }
 
 QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
@@ -294,46 +312,70 @@ QueueArgs queue_args(NearFarState &st, const NearFarArgs &a) {
 
 }  // namespace
 
-bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join) {
+bool near_far_start_p2p(NearFarState &st, const NearFarArgs &a, hipStream_t from) {
+    near_far_drop_early(st, from);
+    const int side_per_cu = std::max(0, std::min(8, a.tuning.p2p_per_cu));
+    const int early_per_cu = std::max(0, std::min(side_per_cu, a.tuning.early_p2p_per_cu));
+    if (early_per_cu == 0 || a.trace || a.n <= 0 || st.f64) return false;
+    if (!a.phi || !a.fld || !a.qs || !st.leaves.ptr || !st.lists.ptr || !st.centre.ptr || !st.cnt.ptr)
+        throw std::runtime_error("early near field: inputs or outputs not prepared");
+    ensure_streams(st);
+    FMM_HIP_CHECK(st.pf.grow((size_t)a.n * sizeof(float4)));
+    QueueArgs q = queue_args(st, a);
+    // on `from`, so that whatever follows it (the k_queue that later claims
+    // the M2L tasks) sees the counters zeroed
+    fill_zero(q.heads, 16 * sizeof(int32_t), from);
+    FMM_HIP_CHECK(hipEventRecord(st.early_fork, from));
+    FMM_HIP_CHECK(hipStreamWaitEvent(st.side3, st.early_fork, 0));
+    p2p_prepare(a.g, a.n, a.leaf_of, a.xs, a.ys, a.zs, a.qs, st.pf.as<float4>(), st.side3);
+    st.early_wg = compute_units() * early_per_cu;
+    queue_p2p_start(q, st.early_wg, st.side3);
+    st.early = true;
+    st.early_heads = q.heads;
+    return true;
+}
+
+void near_far_drop_early(NearFarState &st, hipStream_t s) {
+    if (!st.early) return;
+    FMM_HIP_CHECK(hipEventRecord(st.early_done, st.side3));
+    FMM_HIP_CHECK(hipStreamWaitEvent(s, st.early_done, 0));
+    st.early = false;
+    st.early_heads = nullptr;
+}
+
+bool near_far_queue(NearFarState &st, const NearFarArgs &a, hipStream_t s, bool defer_join, bool *joined_early) {
+    if (joined_early) *joined_early = false;
     if (!st.built) throw std::runtime_error("mixed near/far stage used before its build");
     if (a.n > 0 && (!a.L || !a.phi || !a.fld || !st.M32.ptr || !st.pf.ptr || !st.centre.ptr || !st.leaves.ptr ||
                     !st.lists.ptr || (st.ntask > 0 && st.part.bytes < (size_t)st.ntask * queue_part_elems(a.p) * 4)))
         throw std::runtime_error("mixed near/far stage: queue inputs not prepared");
     QueueArgs q = queue_args(st, a);
+    // an early P2P kernel with other claim counters (or without room for
+    // it in this launch shape) is waited for and the near field recomputed
+    if (st.early && (st.early_heads != q.heads || q.trace)) near_far_drop_early(st, s);
+    const bool side_running = st.early;
     if (q.trace) fill_zero(a.trace_count, sizeof(int32_t), s);
     const int ncu = compute_units();
     const int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
     const int side_per_cu = std::max(0, std::min(8, a.tuning.p2p_per_cu));
-    if (side_per_cu > 0) ensure_streams(st);
-    QueueStreams qs;
-    qs.side = st.side;
-    qs.side2 = st.side2;
-    qs.fork = st.fork;
-    qs.join = st.join;
-    qs.after_queue = st.after_queue;
-    qs.after_side = st.after_side;
-    const bool deferred = queue_run(q, a.p, ncu * per_cu, ncu * side_per_cu, qs, s, defer_join);
+    // the side workgroups not started early
+    const int nside = std::max(0, ncu * side_per_cu - (side_running ? st.early_wg : 0));
+    if (nside > 0 || side_running) ensure_streams(st);
+    QueueStreams qs = streams_of(st, nside > 0, side_running);
+    const bool deferred = queue_run(q, a.p, ncu * per_cu, nside, qs, s, defer_join);
     st.tail_pending = deferred;
+    st.tail_side = nside > 0;
+    st.tail_early = side_running;
+    st.early = false;   // joined by this queue from now on
+    st.early_heads = nullptr;
+    if (joined_early) *joined_early = side_running;
     return deferred;
 }
-
-namespace {
-QueueStreams streams_of(const NearFarState &st) {
-    QueueStreams qs;
-    qs.side = st.side;
-    qs.side2 = st.side2;
-    qs.fork = st.fork;
-    qs.join = st.join;
-    qs.after_queue = st.after_queue;
-    qs.after_side = st.after_side;
-    return qs;
-}
-}  // namespace
 
 void near_far_tail(NearFarState &st, const NearFarArgs &a, hipStream_t s) {
     if (!st.tail_pending) return;
     const int per_cu = std::max(1, std::min(8, a.tuning.grid_per_cu));
-    queue_tail(queue_args(st, a), compute_units() * per_cu, streams_of(st), s);
+    queue_tail(queue_args(st, a), compute_units() * per_cu, streams_of(st, st.tail_side, st.tail_early), s);
     st.tail_pending = false;
 }
 
@@ -373,6 +415,7 @@ void release_near_far(NearFarState &st) {
     if (st.side) {   // the side kernels may still read these buffers
         (void)hipStreamSynchronize(st.side);
         (void)hipStreamSynchronize(st.side2);
+        (void)hipStreamSynchronize(st.side3);
     }
     for (DevBuf *b : all) b->release();
     if (st.side) {
@@ -382,9 +425,14 @@ void release_near_far(NearFarState &st) {
         (void)hipEventDestroy(st.join);
         (void)hipEventDestroy(st.after_queue);
         (void)hipEventDestroy(st.after_side);
+        (void)hipStreamDestroy(st.side3);
+        (void)hipEventDestroy(st.early_fork);
+        (void)hipEventDestroy(st.early_done);
     }
-    st.side = st.side2 = nullptr;
-    st.fork = st.join = st.after_queue = st.after_side = nullptr;
+    st.early = false;
+    st.early_heads = nullptr;
+    st.side = st.side2 = st.side3 = nullptr;
+    st.fork = st.join = st.after_queue = st.after_side = st.early_fork = st.early_done = nullptr;
     st.p = -1;
     st.built = false;
 }

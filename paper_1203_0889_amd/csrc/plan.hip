@@ -174,6 +174,8 @@ struct fmm_plan {
     hipEvent_t beg_of[ST_COUNT] = {};
     hipEvent_t last_ev = nullptr;
     bool ev_ok = false;
+    hipEvent_t ev_early = nullptr;   // start of an early near field (queue stage begins there)
+    bool early_timed = false;
     bool ev_used[ST_COUNT] = {};
     // HIP graph of the numeric part of a solve (fmm_graph_capture)
     hipGraph_t graph = nullptr;
@@ -253,6 +255,7 @@ fmm::Geometry geom(fmm_plan *p) {
 fmm::NearFarArgs nf_args(fmm_plan *p);
 void start_upward(fmm_plan *p);
 void ensure_side(fmm_plan *p);
+void start_near_early(fmm_plan *p, hipStream_t from);
 
 void do_build(fmm_plan *p, const double *pos, const double *q) {
     hipStream_t s = p->stream;
@@ -480,7 +483,12 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
                                 2 * bits, tmps[t], on[t], &in_alt);
         fmm::launch_csr(in_alt ? alts[t] : lists[t], key32, cnts[t], bits, (int32_t)ncell, ptrs[t], srcs[t], on[t]);
         if (t == 1) {
-            if (p->prm.precision == FMM_PREC_MIXED) fmm::build_p2p_leaves(p->nf, nf_args(p), p->up_side);
+            if (p->prm.precision == FMM_PREC_MIXED) {
+                fmm::build_p2p_leaves(p->nf, nf_args(p), p->up_side);
+                // the near field needs nothing more: it runs beside the
+                // upward pass and the far-field build
+                start_near_early(p, p->up_side);
+            }
             FMM_HIP_CHECK(hipEventRecord(p->p2p_done, p->up_side));
             FMM_HIP_CHECK(hipEventRecord(p->up_join, p->up_side));
         }
@@ -613,6 +621,29 @@ void start_upward(fmm_plan *p) {
     p->upward_fresh = true;
 }
 
+// The mixed path's near field (P2P tasks of the work queue) depends only on
+// the particles, the tree and the P2P lists (Sec. 3: a task runs once its
+// inputs exist): started here, on `from`, it runs beside the upward pass
+// and the far-field build, and the next evaluation's queue joins it.  Not
+// with a task trace (its buffers are sized by the evaluation).
+void ensure_eval_buffers(fmm_plan *p);
+void start_near_early(fmm_plan *p, hipStream_t from) {
+    if (p->prm.precision != FMM_PREC_MIXED || (p->prm.flags & FMM_FLAG_TRACE) || p->n == 0 ||
+        p->tuning.early_p2p_per_cu <= 0 || p->tuning.p2p_per_cu <= 0)
+        return;
+    ensure_eval_buffers(p);
+    fmm::NearFarArgs a = nf_args(p);
+    if (cost_reuse(p)) {
+        FMM_HIP_CHECK(p->leaf_cost.grow((size_t)std::max<int64_t>(p->ncell, 1) * sizeof(float)));
+        a.cost_out = p->leaf_cost.as<float>();
+    }
+    const bool timed = p->ev_ok && !p->capturing;
+    if (timed) FMM_HIP_CHECK(hipEventRecord(p->ev_early, from));
+    const bool started = fmm::near_far_start_p2p(p->nf, a, from);
+    p->early_timed = started && timed;
+    if (started && cost_reuse(p)) p->leaf_cost_valid = true;
+}
+
 // Workspaces of the evaluate stage (locals, near and far fields).
 void ensure_eval_buffers(fmm_plan *p) {
     const int P = fmm::ncoef(p->prm.p);
@@ -643,6 +674,10 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
             if (nf.tail_pending && nf.side && nf.after_side) {   // the tail was never launched
                 (void)hipEventRecord(nf.after_side, nf.side);
                 (void)hipStreamWaitEvent(p->stream, nf.after_side, 0);
+                if (nf.tail_early && nf.side3 && nf.early_done) {
+                    (void)hipEventRecord(nf.early_done, nf.side3);
+                    (void)hipStreamWaitEvent(p->stream, nf.early_done, 0);
+                }
                 nf.tail_pending = false;
             } else if (nf.join) {
                 (void)hipStreamWaitEvent(p->stream, nf.join, 0);
@@ -690,15 +725,24 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
         // rest, L2L and L2P, joined by more P2P workgroups once those are
         // queued; the near field is joined before the outputs
         join_guard.pending = true;   // also if the launch itself throws half way
-        deferred = fmm::near_far_queue(p->nf, a, s, /*defer_join=*/true);
+        bool joined_early = false;
+        deferred = fmm::near_far_queue(p->nf, a, s, /*defer_join=*/true, &joined_early);
         join_guard.pending = deferred;
+        // with an early near field the queue stage begins where it started
+        hipEvent_t q_beg = joined_early ? (p->early_timed ? p->ev_early : nullptr) : p->last_ev;
+        p->early_timed = false;
         if (!deferred) {
-            mark(p, ST_QUEUE);
-        } else if (p->ev_ok && !p->capturing && p->last_ev) {
+            if (q_beg && p->ev_ok && !p->capturing) {
+                hipEventRecord(p->ev_end[ST_QUEUE], s);
+                p->beg_of[ST_QUEUE] = q_beg;
+                p->ev_used[ST_QUEUE] = true;
+                p->last_ev = p->ev_end[ST_QUEUE];
+            }
+        } else if (p->ev_ok && !p->capturing && q_beg) {
             // the queue stage ends with all its kernels (the join, on the side
             // stream, recorded after the tail); the next stage begins after
             // k_queue and the sum of its partials
-            p->beg_of[ST_QUEUE] = p->last_ev;
+            p->beg_of[ST_QUEUE] = q_beg;
             time_queue = true;
             record(p, ST_M2L_REST);
         }
@@ -788,6 +832,7 @@ bool do_refresh(fmm_plan *p, const double *pos, const double *q, bool check_leaf
         a.leaf_cost = p->leaf_cost.as<float>();
         fmm::reorder_p2p_leaves(p->nf, a, s);
     }
+    if (p->nf.built) start_near_early(p, s);
     return true;
 }
 
@@ -971,6 +1016,7 @@ fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fm
     for (int i = 0; i < ST_COUNT; i++)
         if (hipEventCreate(&p->ev_beg[i]) != hipSuccess || hipEventCreate(&p->ev_end[i]) != hipSuccess)
             p->ev_ok = false;
+    if (hipEventCreate(&p->ev_early) != hipSuccess) p->ev_ok = false;
     *out = p;
     return FMM_OK;
 }
@@ -1014,6 +1060,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
         if (p->ev_beg[i]) hipEventDestroy(p->ev_beg[i]);
         if (p->ev_end[i]) hipEventDestroy(p->ev_end[i]);
     }
+    if (p->ev_early) hipEventDestroy(p->ev_early);
     delete p;
     return FMM_OK;
 }
@@ -1032,6 +1079,9 @@ fmm_status fmm_build_tree(fmm_plan *p, int32_t n_inst, const int64_t *offsets, c
     const bool keep = same && (p->prm.flags & FMM_FLAG_KEEP_TOPOLOGY);
     const bool incremental = same && !keep && (p->prm.flags & FMM_FLAG_INCREMENTAL);
     return guarded(p, [&]() -> fmm_status {
+        // a near field started for the previous particles and never joined
+        // must end before its inputs change
+        fmm::near_far_drop_early(p->nf, p->stream);
         if ((keep || incremental) && n > 0) {
             const int saved = p->state;
             p->state = kStateBuilt;
@@ -1324,7 +1374,7 @@ fmm_status fmm_get_tuning(const fmm_plan *p, fmm_tuning *t) {
 fmm_status fmm_set_tuning(fmm_plan *p, const fmm_tuning *t) {
     if (!p || !t) return FMM_ERR_INVALID_ARG;
     if (t->m2l_task_entries < 1 || t->m2l_task_entries > 128 || t->grid_per_cu < 1 || t->grid_per_cu > 8 ||
-        t->p2p_per_cu < 0 || t->p2p_per_cu > 8)
+        t->p2p_per_cu < 0 || t->p2p_per_cu > 8 || t->early_p2p_per_cu < 0 || t->early_p2p_per_cu > t->p2p_per_cu)
         return fail(p, FMM_ERR_INVALID_ARG, "tuning out of range");
     p->tuning = *t;
     return FMM_OK;
@@ -1343,10 +1393,13 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
         hipStream_t s = p->stream;
         drop_graph(p);
         p->adj_ready = false;
+        fmm::near_far_drop_early(p->nf, s);   // every trial launches its own near field
         ensure_eval_buffers(p);   // the queue writes the locals and the near field
         static const int kEntries[] = {32, 64, 96, 128};
-        // (work-queue, P2P side) workgroups per compute unit
-        static const int kShape[][2] = {{1, 1}, {1, 2}, {1, 3}, {2, 0}, {3, 0}};
+        // (work-queue, P2P side) workgroups per compute unit; the early near
+        // field stays as set (its gain depends on what the build lets it
+        // overlap, which one evaluation does not show)
+        static const int kShape[][3] = {{1, 1, 0}, {1, 2, 0}, {1, 3, 0}, {2, 0, 0}, {3, 0, 0}, {2, 1, 0}, {2, 2, 0}};
         hipEvent_t e0, e1;
         FMM_HIP_CHECK(hipEventCreate(&e0));
         FMM_HIP_CHECK(hipEventCreate(&e1));
@@ -1359,6 +1412,7 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
                 for (const auto &sh : kShape) {
                     p->tuning.grid_per_cu = sh[0];
                     p->tuning.p2p_per_cu = sh[1];
+                    p->tuning.early_p2p_per_cu = std::min(keep.early_p2p_per_cu, sh[1]);
                     float t_min = -1.0f;
                     for (int r = 0; r < repeats; r++) {
                         // the whole evaluation (queue, far field beside the

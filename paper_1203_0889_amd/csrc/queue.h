@@ -84,14 +84,25 @@ void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb,
 struct QueueStreams {
     hipStream_t side = nullptr, side2 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr, after_queue = nullptr, after_side = nullptr;
+    // an early P2P kernel (queue_p2p_start) on its own stream, joined with
+    // the side kernels (null: none)
+    hipStream_t early = nullptr;
+    hipEvent_t early_done = nullptr;
 };
 // defer_join (with side workgroups): k_queue runs the M2L tasks only and the
 // side kernel drains the P2P tasks; s does not wait for it: the caller
 // queues more work on s, then queue_tail, and waits for the join before it
 // reads the near field.
+// With qs.early: a P2P kernel already runs there (queue_p2p_start, the
+// claim counters zeroed before it); nside more side workgroups join it and
+// the join covers both.
 // Returns whether the join was deferred.
 bool queue_run(const QueueArgs &a, int p, int nworkgroups, int nside, const QueueStreams &qs, hipStream_t s,
                bool defer_join = false);
+// The P2P side kernel alone, nside workgroups on stream side: the near
+// field started as soon as its inputs exist (the claim counters must be
+// zeroed before, in stream order).
+void queue_p2p_start(const QueueArgs &a, int nside, hipStream_t side);
 // The deferred P2P tail (after queue_run returned true): nworkgroups more
 // P2P-only workgroups on side2 once the work queued on s so far is done,
 // and the join event recorded after every P2P launch.

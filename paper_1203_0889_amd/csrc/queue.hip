@@ -623,14 +623,17 @@ void queue_split_multipoles(const double *M, int32_t ncell, int p, uint16_t *Mb,
 
 bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, const QueueStreams &qs, hipStream_t s,
                bool defer_join) {
-    if (nworkgroups < 1 || nside < 0 || (nside > 0 && (!qs.side || !qs.fork || !qs.join)))
+    const bool early = qs.early != nullptr;
+    const bool any_side = nside > 0 || early;
+    if (nworkgroups < 1 || nside < 0 || (nside > 0 && (!qs.side || !qs.fork || !qs.join)) ||
+        (early && (!qs.early_done || !qs.join)))
         throw HipError{hipErrorInvalidValue, "queue: bad launch configuration"};
-    const bool defer = defer_join && nside > 0 && qs.side2 && qs.after_queue && qs.after_side;
+    const bool defer = defer_join && any_side && qs.side2 && qs.after_queue && qs.after_side;
     hipStream_t side = qs.side;
     QueueArgs a = a_in;
-    a.role_split = nside == 0;
+    a.role_split = !any_side;
     a.m2l_only = defer ? 1 : 0;
-    fill_zero(a.heads, 16 * sizeof(int32_t), s);
+    if (!early) fill_zero(a.heads, 16 * sizeof(int32_t), s);
     if (nside > 0) {
         // fork: the side stream starts after everything queued on s so far
         FMM_HIP_CHECK(hipEventRecord(qs.fork, s));
@@ -667,12 +670,27 @@ bool queue_run(const QueueArgs &a_in, int p, int nworkgroups, int nside, const Q
     if (defer) {
         // the rest of the P2P tail: queue_tail, once the caller has queued
         // what should run first on the compute units k_queue leaves
-    } else if (nside > 0) {
-        // join: work queued on s after this waits for the side kernel too
-        FMM_HIP_CHECK(hipEventRecord(qs.join, side));
-        FMM_HIP_CHECK(hipStreamWaitEvent(s, qs.join, 0));
+    } else {
+        // join: work queued on s after this waits for the side kernels too
+        if (nside > 0) {
+            FMM_HIP_CHECK(hipEventRecord(qs.join, side));
+            FMM_HIP_CHECK(hipStreamWaitEvent(s, qs.join, 0));
+        }
+        if (early) {
+            FMM_HIP_CHECK(hipEventRecord(qs.early_done, qs.early));
+            FMM_HIP_CHECK(hipStreamWaitEvent(s, qs.early_done, 0));
+        }
     }
     return defer;
+}
+
+void queue_p2p_start(const QueueArgs &a_in, int nside, hipStream_t side) {
+    if (nside < 1) throw HipError{hipErrorInvalidValue, "queue: bad launch configuration"};
+    QueueArgs a = a_in;
+    a.role_split = 0;
+    a.m2l_only = 1;
+    hipLaunchKernelGGL(k_p2p_side, dim3(nside), dim3(256), 0, side, a);
+    FMM_LAUNCH_CHECK();
 }
 
 void queue_tail(const QueueArgs &a_in, int nworkgroups, const QueueStreams &qs, hipStream_t s) {
@@ -688,8 +706,14 @@ void queue_tail(const QueueArgs &a_in, int nworkgroups, const QueueStreams &qs, 
     FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_queue, 0));
     hipLaunchKernelGGL(k_p2p_side, dim3(nworkgroups), dim3(256), 0, qs.side2, a);
     FMM_LAUNCH_CHECK();
-    FMM_HIP_CHECK(hipEventRecord(qs.after_side, qs.side));
-    FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_side, 0));
+    if (qs.side) {   // the side kernel of this queue, if it launched one
+        FMM_HIP_CHECK(hipEventRecord(qs.after_side, qs.side));
+        FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.after_side, 0));
+    }
+    if (qs.early) {
+        FMM_HIP_CHECK(hipEventRecord(qs.early_done, qs.early));
+        FMM_HIP_CHECK(hipStreamWaitEvent(qs.side2, qs.early_done, 0));
+    }
     FMM_HIP_CHECK(hipEventRecord(qs.join, qs.side2));
 }
 

@@ -44,7 +44,8 @@ class fmm_params(ctypes.Structure):
 
 
 class fmm_tuning(ctypes.Structure):
-    _fields_ = [("m2l_task_entries", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("p2p_per_cu", ctypes.c_int32)]
+    _fields_ = [("m2l_task_entries", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("p2p_per_cu", ctypes.c_int32),
+                ("early_p2p_per_cu", ctypes.c_int32)]
 
 
 class fmm_task_record(ctypes.Structure):

@@ -26,7 +26,8 @@ def test_autotune_mixed():
     tuning, ms = plan.autotune(repeats=2)
     print("autotune:", tuning, ms, flush=True)
     assert tuning["m2l_task_entries"] in (32, 64, 96, 128)
-    assert (tuning["grid_per_cu"], tuning["p2p_per_cu"]) in ((1, 1), (1, 2), (1, 3), (2, 0), (3, 0))
+    assert (tuning["grid_per_cu"], tuning["p2p_per_cu"]) in ((1, 1), (1, 2), (1, 3), (2, 0), (3, 0), (2, 1), (2, 2))
+    assert tuning["early_p2p_per_cu"] == 0
     assert ms > 0
     assert plan.get_tuning() == tuning
     out = {k: v.cpu().numpy() for k, v in plan.evaluate().items() if v is not None}
@@ -59,6 +60,10 @@ def test_tuning_validation():
         plan.set_tuning(p2p_per_cu=9)
     with pytest.raises(fmm.FMMError):
         plan.set_tuning(p2p_per_cu=-1)
+    with pytest.raises(fmm.FMMError):
+        plan.set_tuning(p2p_per_cu=1, early_p2p_per_cu=2)   # more early workgroups than side ones
+    with pytest.raises(fmm.FMMError):
+        plan.set_tuning(early_p2p_per_cu=-1)
     with pytest.raises(fmm.FMMError) as ei:
         plan.autotune()
     assert ei.value.status == -2
@@ -126,3 +131,50 @@ def test_task_sizes_match_oracle(entries):
     assert max(e) < 1e-5
     _, perm, cells = plan.copy_tree()
     check_mixed(out, ref_phi, ref_fld, leaf_ids(perm, cells), label="entries %d" % entries)
+
+
+def test_early_near_field_changes_no_result():
+    """The near field started by the build (early_p2p_per_cu > 0, beside the
+    upward pass and the far-field build) gives bitwise the results of the
+    near field started with the queue, in deterministic mode: after a full
+    build, after a kept-topology rebuild, from a step graph, through the
+    evaluation that cannot allocate (other claim counters: the early kernel
+    is waited for and the near field recomputed), and for a second
+    evaluation of the same build (the queue's own near field)."""
+    pos, q = W.uniform_cube(100000, 54)
+    v = W.velocities(100000, 55, 1e-4)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    res = {}
+    for early in (0, 1):
+        plan = fmm.Plan(p=8, ncrit=64, theta=(1, 2), precision="mixed", device=0, incremental=True,
+                        deterministic=True)
+        plan.set_tuning(grid_per_cu=1, p2p_per_cu=2, early_p2p_per_cu=early)
+        got = []
+        plan.build_tree(dev(pos), dev(q))
+        plan.upward()
+        got.append(plan.evaluate())
+        got.append(plan.evaluate())                      # no new particles: the queue's near field
+        plan.build_tree(dev(pos + v), dev(q))            # kept topology
+        assert plan.build_info()["kept"] == 1
+        plan.upward()
+        got.append(plan.evaluate())
+        plan.build_tree(dev(pos + 2 * v), dev(q))
+        plan.upward()
+        outs = {"phi": torch.empty(100000, dtype=torch.float64, device="cuda"),
+                "field": torch.empty((100000, 3), dtype=torch.float64, device="cuda")}
+        plan.evaluate_noalloc_into(**outs)
+        got.append(dict(outs))
+        gpos = dev(pos + 3 * v)
+        g = {"phi": torch.empty(100000, dtype=torch.float64, device="cuda"),
+             "field": torch.empty((100000, 3), dtype=torch.float64, device="cuda")}
+        plan.graph_capture_step(gpos, dev(q), **g)
+        gpos.copy_(dev(pos + 4 * v))
+        plan.graph_launch()
+        plan.sync()
+        got.append(dict(g))
+        res[early] = [{k: t.cpu().numpy() for k, t in o.items() if t is not None and k in ("phi", "field")}
+                      for o in got]
+        plan.close()
+    for i, (a, b) in enumerate(zip(res[0], res[1])):
+        for k in ("phi", "field"):
+            assert np.array_equal(a[k], b[k]), (i, k)
