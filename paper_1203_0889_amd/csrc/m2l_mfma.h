@@ -8,7 +8,8 @@ namespace fmm {
 
 constexpr int kRhoMax = 24;                                  // |rho_i| covered by the dense class table
 constexpr int kRhoSpan = 2 * kRhoMax + 1;
-constexpr int kDenseKeys = 3 * kRhoSpan * kRhoSpan * kRhoSpan;  // delta in {-1, 0, 1}
+constexpr int kDeltaMax = 2;                                 // |delta| covered by the dense class table
+constexpr int kDenseKeys = (2 * kDeltaMax + 1) * kRhoSpan * kRhoSpan * kRhoSpan;
 
 // Class code of every pair: its operator slot (>= 0), -1 outside the dense
 // table, -2 - key for a class that has no slot yet (its key is marked in

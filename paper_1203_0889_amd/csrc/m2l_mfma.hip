@@ -9,10 +9,10 @@
 // irregular solid harmonics I_n^m(rho / (2 S_A / S_min)) and stored as two
 // bf16 pieces (the rounding of each entry and of its remainder):
 //   L~_n^m += (-1)^n sum_k 2^(delta k) sum_l M~_k^l I_(n+k)^(m+l)
-// Classes with |delta| <= 1 (all pairs of a uniform tree, >95% of an
-// adaptive one) index a dense table; their operators are cached in the plan
-// across builds.  Pairs with |delta| >= 2 are nearly one class each and go
-// to the per-pair FP64 kernel instead.
+// Classes with |delta| <= 2 and |rho_i| <= 24 (all pairs of a uniform tree,
+// 99.8% of the 1M-particle Plummer tree at theta = 1/2) index a dense table;
+// their operators are cached in the plan across builds.  The rest (deeper
+// level differences: a few pairs per class) go to the per-pair FP64 kernel.
 //
 // Batching: targets are grouped 256 at a time (same level and octant,
 // Morton order, so neighbouring targets share their class sets).  A group's
@@ -37,9 +37,10 @@ __device__ inline uint32_t bf16_bits(float x) {
 __device__ inline float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
 
 __device__ inline int dense_key(int delta, int rx, int ry, int rz) {
-    if (delta < -1 || delta > 1) return -1;
+    if (delta < -kDeltaMax || delta > kDeltaMax) return -1;
     if (rx < -kRhoMax || rx > kRhoMax || ry < -kRhoMax || ry > kRhoMax || rz < -kRhoMax || rz > kRhoMax) return -1;
-    return (((delta + 1) * kRhoSpan + (rx + kRhoMax)) * kRhoSpan + (ry + kRhoMax)) * kRhoSpan + (rz + kRhoMax);
+    return (((delta + kDeltaMax) * kRhoSpan + (rx + kRhoMax)) * kRhoSpan + (ry + kRhoMax)) * kRhoSpan +
+           (rz + kRhoMax);
 }
 
 // Class code of every M2L pair in CSR order (one wave per owner cell): the
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(256) k_build_ops(const int32_t *__restrict__ n
     int ry = t % kRhoSpan - kRhoMax;
     t /= kRhoSpan;
     int rx = t % kRhoSpan - kRhoMax;
-    int delta = t / kRhoSpan - 1;
+    int delta = t / kRhoSpan - kDeltaMax;
     if (transposed) {
         // key of a transposed pair (owner B, partner A): the forward pair
         // A <- B has the opposite level difference and displacement, and the

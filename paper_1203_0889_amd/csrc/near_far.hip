@@ -164,7 +164,7 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
                     st.toff.as<int32_t>(), cnt + 3, cnt + 16, st.tmp.as<int32_t>(), s);
     rd.begin(cnt + 3, 8, s);
     // while the host waits: the pairs left to the per-pair kernel
-    // (|delta| >= 2 or far displacement), whose number is known
+    // (|delta| > kDeltaMax or far displacement), whose number is known
     FMM_HIP_CHECK(st.xsrc.grow((size_t)std::max(st.nextra, 1) * 4));
     m2l_extra(a.m2l_ptr, ncell, a.m2l_src, st.pcode.as<int32_t>(), st.xptr.as<int32_t>(), st.xsrc.as<int32_t>(), s);
     int32_t h2[2];

@@ -194,21 +194,21 @@ def test_output_subsets_agree(shape):
 
 def table_targets(T):
     """Cells owning at least one M2L pair of the class table (level
-    difference at most 1, integer centre offset in units of the smaller cell
+    difference at most 2, integer centre offset in units of the smaller cell
     at most 24 per axis), from the oracle's lists: the targets of the
-    batched M2L."""
+    batched M2L; and the number of pairs outside the table."""
     c, m = T.cells, T.m2l
     A, B = m[:, 0], m[:, 1]
     la, lb = c[A, 0], c[B, 0]
     SA, SB = np.left_shift(1, 21 - la), np.left_shift(1, 21 - lb)
     sh = 21 - np.maximum(la, lb)
-    ok = np.abs(la - lb) <= 1
+    ok = np.abs(la - lb) <= 2
     for d in range(3):
         rho = np.right_shift((2 * c[A, 1 + d] + 1) * SA - (2 * c[B, 1 + d] + 1) * SB, sh)
         ok &= np.abs(rho) <= 24
     has = np.zeros(T.ncell, dtype=bool)
     has[A[ok]] = True
-    return int(has.sum())
+    return int(has.sum()), int((~ok).sum())
 
 
 # Regression: the count of batched M2L targets came from a sampled search
@@ -231,5 +231,6 @@ def test_m2l_target_count(case):
     plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
     info = plan.queue_info()
     say(name, "ncell", T.ncell, info)
-    assert info["ntarget"] == table_targets(T)
+    ntarget, nextra = table_targets(T)
+    assert info["ntarget"] == ntarget and info["nextra"] == nextra
     assert info["ngroup"] == (info["ntarget"] + 255) // 256
