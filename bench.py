@@ -41,20 +41,25 @@ def source_hash(paths):
 
 def committed_counters(workload, tuning):
     """Fields of the committed PMC summary of the work queue, if it was
-    taken on this workload, at this work-queue tuning and on the current
-    queue kernel source (else None)."""
+    taken on this workload, on the current queue kernel source and at this
+    work-queue tuning (the file holds one block per profiled tuning; else
+    None)."""
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if not os.path.exists(path):
         return None
-    fields = {}
+    head, blocks = {}, []
     with open(path) as f:
         for line in f:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                fields[k.strip()] = v.strip()
-    if fields.get("workload") != workload or fields.get("source_sha256_16") != source_hash(QUEUE_SOURCES):
+            if ":" not in line or line.startswith("#"):
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            if k == "tuning":
+                blocks.append({})
+            (blocks[-1] if blocks else head)[k] = v
+    if head.get("workload") != workload or head.get("source_sha256_16") != source_hash(QUEUE_SOURCES):
         return None
-    if fields.get("tuning") != tuning_text(tuning):
+    fields = next((b for b in blocks if b.get("tuning") == tuning_text(tuning)), None)
+    if fields is None:
         return None
     out = {}
     for k in ("hbm_bytes_per_launch", "mfma_flop_executed", "mfma_busy_simd_cycles", "p2p_valu_wave_insts",
