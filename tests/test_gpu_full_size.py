@@ -1,0 +1,113 @@
+"""Parity at the benchmark configurations' full sizes, in the launch
+configuration the benchmark times (the autotuned work queue): outputs at a
+seeded sample of targets against the oracle's direct sum, which computes
+them one by one.
+
+  uniform 2^20, p = 8, ncrit 64, theta 1/2: mixed and plain FP64 paths
+  Plummer 2^22 (equal charges 1/N), p = 10, ncrit 32, theta 2/5: mixed
+  Plummer 2^20, p = 8: forward energy and its gradient (fmm_backward)
+  256 instances (N_k log-uniform in [2^10, 2^16]), p = 6: every 16th instance
+
+Bounds: the relative L2 error of the sample under the benchmark metric's
+1e-4 (the p = 6 batch: 1e-4 as well; measured 5e-6), and no sampled
+particle off by more than 1e-3 (potential) or 5e-3 (field) of the sample's
+rms: the field of a particle with a very close neighbour carries the FP32
+rounding of their relative coordinates (see the parity helper), on top of
+the truncation error.  The rel. L2 bound of the uniform 2^20 FP64 path is
+1e-5 (measured 1.5e-7 for the potential).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1203_0889_amd import fmm, workloads as W
+from parity import maxrel, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def solve(name, precision="mixed", autotune=True):
+    pos, q, w = W.make(name)
+    say("case", name, precision, "N", len(q))
+    plan = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=precision, device=0)
+    dp, dq = dev(pos), dev(q)
+    if autotune and precision == "mixed":
+        plan.build_tree(dp, dq)
+        plan.upward()
+        say("tuning", plan.autotune(repeats=1)[0])
+    plan.build_tree(dp, dq)
+    plan.upward()
+    out = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    torch.cuda.synchronize()
+    return pos, q, w, plan, out
+
+
+def check_sample(label, got_phi, got_fld, ref_phi, ref_fld, tol):
+    e = (rel(got_phi, ref_phi), rel(got_fld, ref_fld))
+    m = (maxrel(got_phi, ref_phi), maxrel(got_fld, ref_fld))
+    say(label, "rel L2 vs direct", e, "worst particle / rms", m)
+    assert max(e) < tol
+    assert m[0] < 1e-3 and m[1] < 5e-3
+
+
+@pytest.mark.parametrize("precision,tol", [("mixed", 1e-4), ("fp64", 1e-5)])
+def test_uniform1m_p8(precision, tol):
+    pos, q, w, plan, out = solve("uniform1m_p8", precision)
+    tg = W.error_sample(len(q), 21, 2048)
+    pd, fd = oracle.direct(pos, q, tg)
+    check_sample("uniform1m_p8 " + precision, out["phi"][tg], out["field"][tg], pd, fd, tol)
+    assert out["energy"][0] == pytest.approx(0.5 * np.dot(q, out["phi"]), rel=1e-12)
+    assert np.allclose(out["force"], q[:, None] * out["field"], rtol=1e-15, atol=0)
+
+
+def test_plummer4m_p10_equal_charges():
+    pos, q, w, plan, out = solve("plummer4m_p10")
+    assert np.all(q == q[0])
+    tg = W.error_sample(len(q), 22, 1024)
+    pd, fd = oracle.direct(pos, q, tg)
+    check_sample("plummer4m_p10", out["phi"][tg], out["field"][tg], pd, fd, 1e-4)
+
+
+def test_plummer1m_p8_energy_gradient():
+    pos, q, w, plan, out = solve("plummer1m_p8")
+    gp, gq = plan.backward(dev(np.ones(1)))
+    gp, gq = gp.cpu().numpy(), gq.cpu().numpy()
+    tg = W.error_sample(len(q), 23, 2048)
+    pd, fd = oracle.direct(pos, q, tg)
+    check_sample("plummer1m_p8 forward", out["phi"][tg], out["field"][tg], pd, fd, 1e-4)
+    # dE/dq_i = phi_i and dE/dx_i = -q_i E_i of the exact (symmetric) sum
+    e = (rel(gq[tg], pd), rel(gp[tg], -q[tg, None] * fd))
+    say("plummer1m_p8 gradient rel L2 vs direct", e)
+    assert max(e) < 1e-4
+    assert maxrel(gq[tg], pd) < 1e-3 and maxrel(gp[tg], -q[tg, None] * fd) < 5e-3
+
+
+def test_batch256_p6():
+    pos, q, offsets = W.batch(256, 5)
+    offs = [int(o) for o in offsets]
+    plan = fmm.Plan(p=6, ncrit=64, theta=(1, 2), precision="mixed", device=0)
+    dp, dq = dev(pos), dev(q)
+    plan.build_tree(dp, dq, offs)
+    plan.upward()
+    say("tuning", plan.autotune(repeats=1)[0])
+    plan.build_tree(dp, dq, offs)
+    plan.upward()
+    out = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    torch.cuda.synchronize()
+    for k in range(0, 256, 16):
+        lo, hi = offs[k], offs[k + 1]
+        nk = hi - lo
+        tg = np.arange(nk) if nk <= 4096 else W.error_sample(nk, 24 + k, 1024)
+        pd, fd = oracle.direct(pos[lo:hi], q[lo:hi], tg)
+        check_sample("batch instance %d (N %d)" % (k, nk), out["phi"][lo:hi][tg], out["field"][lo:hi][tg], pd, fd,
+                     1e-4)
+        assert out["energy"][k] == pytest.approx(0.5 * np.dot(q[lo:hi], out["phi"][lo:hi]), rel=1e-12)
