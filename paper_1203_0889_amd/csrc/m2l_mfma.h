@@ -45,7 +45,7 @@ inline int64_t m2l_f64_op_elems(int p) {
     const int P = ncoef(p);
     return (int64_t)((P + 3) / 4) * ((P + 15) / 16) * 64;
 }
-// Sort keys (level, eighth, octant, cell) of the cells with table pairs;
+// Sort keys (level, octant, eighth, cell) of the cells with table pairs;
 // xptr = exclusive scan of the per-owner counts of pairs outside the table.
 void m2l_target_keys(CellArrays c, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *xptr, uint64_t *tkey,
                      int32_t *has, hipStream_t s);

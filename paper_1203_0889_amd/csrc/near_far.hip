@@ -114,8 +114,9 @@ void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s)
     m2l_target_keys(a.g.c, ncell, a.n, a.m2l_ptr, st.xptr.as<int32_t>(), st.tkey.as<uint64_t>(), st.has.as<int32_t>(),
                     s);
     // the keys are written in cell order: a stable sort on the (level,
-    // eighth, octant) bits 32..42 keeps cells in order within each class
-    radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 32, 43,
+    // octant) bits 35..42 keeps cells in order within each class (one pass;
+    // the eighth below them never decreases in cell order within a level)
+    radix_sort_u64(st.tkey.as<uint64_t>(), nullptr, st.tkey_alt.as<uint64_t>(), nullptr, ncell, 35, 43,
                    st.tmp.as<int32_t>(), s);
     m2l_count_targets(st.tkey.as<uint64_t>(), ncell, cnt + 2, s);
     Reader rd{a};
