@@ -110,16 +110,23 @@ __global__ void __launch_bounds__(kP2P64Threads)
 // terms coincide for l = 0, where M~_k^0 is real).
 constexpr int kM2L64Threads = 64;
 constexpr int kPairChunk = 16;
-constexpr int kMaxI = (2 * kMaxP + 1) * (2 * kMaxP + 2) / 2;
 
-__device__ inline int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+// LDS of one wave (sized by p at launch): the irregular harmonics of the
+// current pair for every order m, negative m included (J_n^m at
+// n^2 + n + m, n <= 2p), and the source multipole as complex coefficients
+// of every order (M_k^l at k^2 + k + l, k <= p).  With the signs of the
+// negative orders stored, the inner sums are plain complex products.
+__host__ __device__ constexpr int m2l_pairs_lds_doubles(int p) {
+    return 2 * (2 * p + 1) * (2 * p + 1) + 2 * (p + 1) * (p + 1);
+}
 
 template <bool kAdjoint>
 __global__ void __launch_bounds__(kM2L64Threads)
     k_m2l_pairs(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
                 int64_t npair, const double *__restrict__ In, double *__restrict__ Out, int owner_mode) {
-    __shared__ double Ire[kMaxI], Iim[kMaxI];
-    __shared__ double Xs[ncoef(kMaxP)];
+    extern __shared__ double lds[];
+    const int NJ = (2 * p + 1) * (2 * p + 1), NM = (p + 1) * (p + 1);
+    double *Jre = lds, *Jim = lds + NJ, *Mre = lds + 2 * NJ, *Mim = lds + 2 * NJ + NM;
     const int lane = threadIdx.x;
     const int P = ncoef(p);
     const int NC = (p + 1) * (p + 2) / 2;
@@ -193,10 +200,30 @@ __global__ void __launch_bounds__(kM2L64Threads)
             const double rz = ldexp((double)((2 * (int64_t)c.iz[A] + 1) * SA - (2 * (int64_t)c.iz[B] + 1) * SB),
                                     -(kLevels - la + 1));
             const int delta = la - lb;
-            __syncthreads();
-            for (int i = lane; i < P; i += 64) Xs[i] = In[(int64_t)other * P + i];
+            __syncthreads();   // the previous pair's readers are done
+            // the input coefficients as complex M_k^l, l in [-k, k], with
+            // M_k^(-l) = (-1)^l conj(M_k^l)
+            for (int i = lane; i < NM; i += 64) {
+                int k = 0;
+                while ((k + 1) * (k + 1) <= i) k++;
+                const int l = i - k * k - k, al = l < 0 ? -l : l;
+                const double *x = In + (int64_t)other * P;
+                double re = x[cidx_re(k, al)], im = al > 0 ? x[cidx_im(k, al)] : 0.0;
+                if (l < 0) {
+                    im = -im;
+                    if (al & 1) {
+                        re = -re;
+                        im = -im;
+                    }
+                }
+                Mre[i] = re;
+                Mim[i] = im;
+            }
             if (lane <= 2 * p) {
+                // column m of the harmonics, and its mirror J_n^(-m) =
+                // (-1)^m conj(J_n^m)
                 int m = lane, nmax = 2 * p;
+                const double sg = (m & 1) ? -1.0 : 1.0;
                 double r2 = rx * rx + ry * ry + rz * rz;
                 double ir2 = 1.0 / r2;
                 double mr = 1.0 / sqrt(r2), mi = 0.0;  // I_m^m
@@ -206,8 +233,15 @@ __global__ void __launch_bounds__(kM2L64Threads)
                     mr = nr;
                     mi = ni;
                 }
-                Ire[tri(m, m)] = mr;
-                Iim[tri(m, m)] = mi;
+                auto put = [&](int n, double re, double im) {
+                    Jre[n * n + n + m] = re;
+                    Jim[n * n + n + m] = im;
+                    if (m > 0) {
+                        Jre[n * n + n - m] = sg * re;
+                        Jim[n * n + n - m] = -sg * im;
+                    }
+                };
+                put(m, mr, mi);
                 double pr = 0, pi = 0, cr = mr, ci = mi;
                 for (int n = m + 1; n <= nmax; n++) {
                     double nr, ni;
@@ -220,8 +254,7 @@ __global__ void __launch_bounds__(kM2L64Threads)
                         nr = (aa * cr - bb * pr) * ir2;
                         ni = (aa * ci - bb * pi) * ir2;
                     }
-                    Ire[tri(n, m)] = nr;
-                    Iim[tri(n, m)] = ni;
+                    put(n, nr, ni);
                     pr = cr;
                     pi = ci;
                     cr = nr;
@@ -235,31 +268,16 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 const int m = om[s];
                 double sr = 0, si = 0;
                 if (!kAdjoint) {
+                    // S_n^m = sum_k 2^(delta k) sum_l M_k^l J_(n+k)^(m+l)
                     for (int k = 0; k <= p; k++) {
                         const double fk = ldexp(1.0, delta * k);
+                        const int nn = n + k, mb = k * k + k, jb = nn * nn + nn + m;
                         double tr = 0, ti = 0;
                         for (int l = -k; l <= k; l++) {
-                            const int al = l < 0 ? -l : l;
-                            double mre = Xs[cidx_re(k, al)], mim = al > 0 ? Xs[cidx_im(k, al)] : 0.0;
-                            if (l < 0) {
-                                mim = -mim;
-                                if (al & 1) {
-                                    mre = -mre;
-                                    mim = -mim;
-                                }
-                            }
-                            const int nn = n + k, mm = m + l;
-                            const int amm = mm < 0 ? -mm : mm;
-                            double ire = Ire[tri(nn, amm)], iim = Iim[tri(nn, amm)];
-                            if (mm < 0) {
-                                iim = -iim;
-                                if (amm & 1) {
-                                    ire = -ire;
-                                    iim = -iim;
-                                }
-                            }
-                            tr += mre * ire - mim * iim;
-                            ti += mre * iim + mim * ire;
+                            const double mre = Mre[mb + l], mim = Mim[mb + l];
+                            const double jre = Jre[jb + l], jim = Jim[jb + l];
+                            tr += mre * jre - mim * jim;
+                            ti += mre * jim + mim * jre;
                         }
                         sr += fk * tr;
                         si += fk * ti;
@@ -275,20 +293,12 @@ __global__ void __launch_bounds__(kM2L64Threads)
                     const double sl = (l & 1) ? -1.0 : 1.0;
                     for (int nu = 0; nu <= p; nu++) {
                         const double cn = (nu & 1) ? -fk : fk;
+                        const int nn = nu + k, ub = nu * nu + nu, jb = nn * nn + nn;
                         double tr = 0, ti = 0;
                         for (int mu = 0; mu <= nu; mu++) {
-                            const double ur = Xs[cidx_re(nu, mu)], ui = mu > 0 ? Xs[cidx_im(nu, mu)] : 0.0;
-                            const int nn = nu + k;
-                            const double i1r = Ire[tri(nn, mu + l)], i1i = Iim[tri(nn, mu + l)];
-                            const int d = mu - l, ad = d < 0 ? -d : d;
-                            double i2r = Ire[tri(nn, ad)], i2i = Iim[tri(nn, ad)];
-                            if (d < 0) {
-                                i2i = -i2i;
-                                if (ad & 1) {
-                                    i2r = -i2r;
-                                    i2i = -i2i;
-                                }
-                            }
+                            const double ur = Mre[ub + mu], ui = Mim[ub + mu];
+                            const double i1r = Jre[jb + mu + l], i1i = Jim[jb + mu + l];
+                            const double i2r = Jre[jb + mu - l], i2i = Jim[jb + mu - l];
                             // U conj(I1) + sl conj(U) I2
                             tr += (ur * i1r + ui * i1i) + sl * (ur * i2r + ui * i2i);
                             ti += (ui * i1r - ur * i1i) + sl * (ur * i2i - ui * i2r);
@@ -314,11 +324,12 @@ void launch_pairs(bool adjoint, Geometry g, int32_t ncell, int p, const int32_t 
     const int64_t nunit = owner_mode ? (int64_t)ncell : (npair + kPairChunk - 1) / kPairChunk;
     const int grid = (int)(nunit < 65536 ? nunit : 65536);
     const int om = owner_mode ? 1 : 0;
+    const size_t lds = (size_t)m2l_pairs_lds_doubles(p) * sizeof(double);
     if (adjoint)
-        hipLaunchKernelGGL(k_m2l_pairs<true>, dim3(grid), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, npair,
+        hipLaunchKernelGGL(k_m2l_pairs<true>, dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr, src, npair,
                            In, Out, om);
     else
-        hipLaunchKernelGGL(k_m2l_pairs<false>, dim3(grid), dim3(kM2L64Threads), 0, s, g.c, ncell, p, ptr, src, npair,
+        hipLaunchKernelGGL(k_m2l_pairs<false>, dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr, src, npair,
                            In, Out, om);
     FMM_LAUNCH_CHECK();
 }

@@ -49,6 +49,9 @@ CASES = [
     ("plummer20k_p6", "plummer", 20000, 3, 6, 16, (1, 2)),
     ("plummer9k_p10_theta04", "plummer", 9001, 5, 10, 32, (2, 5)),
     ("uniform70k_p8", "uniform", 70000, 2, 8, 64, (1, 2)),
+    # above p = 12 every M2L pair goes through the per-pair FP64 kernel
+    ("uniform3k_p16", "uniform", 3000, 9, 16, 64, (1, 2)),
+    ("plummer2k_p13", "plummer", 2000, 11, 13, 16, (1, 2)),
 ]
 
 
@@ -110,7 +113,8 @@ def test_fp64_vs_direct_sum(case):
     out = case["out"]
     e_phi, e_fld = rel(out["phi"][tg], pd), rel(out["field"][tg], fd)
     say(case["name"], "fp64 vs direct", e_phi, e_fld)
-    tol = {4: (1e-3, 1e-2), 6: (1e-4, 1e-3), 8: (1e-5, 1e-4), 10: (1e-6, 1e-5)}[case["p"]]
+    tol = {4: (1e-3, 1e-2), 6: (1e-4, 1e-3), 8: (1e-5, 1e-4), 10: (1e-6, 1e-5), 13: (1e-7, 1e-6),
+           16: (1e-8, 1e-7)}[case["p"]]
     assert e_phi < tol[0] and e_fld < tol[1]
 
 
