@@ -119,6 +119,10 @@ constexpr int kPairChunk = 16;
 __host__ __device__ constexpr int m2l_pairs_lds_doubles(int p) {
     return 2 * (2 * p + 1) * (2 * p + 1) + 2 * (p + 1) * (p + 1);
 }
+// pair streams per wave (one per half wave when a half holds every output)
+__host__ __device__ constexpr int m2l_pairs_streams(int p, bool owner_mode) {
+    return (!owner_mode && (p + 1) * (p + 2) / 2 <= 32) ? 2 : 1;
+}
 
 template <bool kAdjoint>
 __global__ void __launch_bounds__(kM2L64Threads)
@@ -126,14 +130,19 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 int64_t npair, const double *__restrict__ In, double *__restrict__ Out, int owner_mode) {
     extern __shared__ double lds[];
     const int NJ = (2 * p + 1) * (2 * p + 1), NM = (p + 1) * (p + 1);
-    double *Jre = lds, *Jim = lds + NJ, *Mre = lds + 2 * NJ, *Mim = lds + 2 * NJ + NM;
-    const int lane = threadIdx.x;
     const int P = ncoef(p);
     const int NC = (p + 1) * (p + 2) / 2;
-    // this lane's outputs: complex index j = lane, lane + 64, lane + 128
+    // H pair streams per wave: with at most 32 outputs (p <= 6) each half
+    // of the wave takes every other pair of the chunk, with LDS of its own
+    // (owner mode keeps one stream: one owner's pairs in list order)
+    const int H = m2l_pairs_streams(p, owner_mode != 0), W = 64 / H;
+    const int h = threadIdx.x / W, lane = threadIdx.x - h * W;
+    double *base = lds + h * m2l_pairs_lds_doubles(p);
+    double *Jre = base, *Jim = base + NJ, *Mre = base + 2 * NJ, *Mim = base + 2 * NJ + NM;
+    // this lane's outputs: complex index j = lane, lane + W, lane + 2 W
     int on[3], om[3];
     for (int s = 0; s < 3; s++) {
-        int j = lane + 64 * s;
+        int j = lane + W * s;
         on[s] = -1;
         om[s] = 0;
         if (j < NC) {
@@ -156,14 +165,17 @@ __global__ void __launch_bounds__(kM2L64Threads)
         } else {
             e0 = ch * kPairChunk;
             e1 = e0 + kPairChunk < npair ? e0 + kPairChunk : npair;
-            // owner of e0: the last cell O with ptr[O] <= e0
+            // owner of this stream's first pair e0 + h (if it has one): the
+            // last cell O with ptr[O] <= e0 + h
+            const int64_t ef = e0 + h < e1 ? e0 + h : e0;
             int32_t lo = 0, hi = ncell;
             while (lo < hi) {
                 int32_t mid = (lo + hi + 1) >> 1;
-                if (ptr[mid] <= e0) lo = mid; else hi = mid - 1;
+                if (ptr[mid] <= ef) lo = mid; else hi = mid - 1;
             }
             O = lo;
         }
+        const bool any = e0 + h < e1;   // this stream has a pair in the chunk
         double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
         auto flush = [&](int32_t owner) {
             double *out = Out + (int64_t)owner * P;
@@ -183,12 +195,16 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 accr[s] = acci[s] = 0.0;
             }
         };
-        for (int64_t e = e0; e < e1; e++) {
-            if (e >= ptr[O + 1]) {
+        // the same number of rounds in every stream (the barriers below)
+        const int64_t rounds = (e1 - e0 + H - 1) / H;
+        for (int64_t t = 0; t < rounds; t++) {
+            const int64_t e = e0 + h + H * t;
+            const bool act = e < e1;
+            if (act && e >= ptr[O + 1]) {
                 flush(O);
                 while (e >= ptr[O + 1]) O++;
             }
-            const int32_t other = src[e];
+            const int32_t other = act ? src[e] : src[e0];
             const int32_t A = kAdjoint ? other : O, B = kAdjoint ? O : other;
             const int la = c.level[A], lb = c.level[B];
             const int64_t SA = (int64_t)1 << (kLevels - la), SB = (int64_t)1 << (kLevels - lb);
@@ -203,7 +219,7 @@ __global__ void __launch_bounds__(kM2L64Threads)
             __syncthreads();   // the previous pair's readers are done
             // the input coefficients as complex M_k^l, l in [-k, k], with
             // M_k^(-l) = (-1)^l conj(M_k^l)
-            for (int i = lane; i < NM; i += 64) {
+            for (int i = lane; act && i < NM; i += W) {
                 int k = 0;
                 while ((k + 1) * (k + 1) <= i) k++;
                 const int l = i - k * k - k, al = l < 0 ? -l : l;
@@ -219,7 +235,7 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 Mre[i] = re;
                 Mim[i] = im;
             }
-            if (lane <= 2 * p) {
+            if (act && lane <= 2 * p) {
                 // column m of the harmonics, and its mirror J_n^(-m) =
                 // (-1)^m conj(J_n^m)
                 int m = lane, nmax = 2 * p;
@@ -262,7 +278,7 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 }
             }
             __syncthreads();
-            for (int s = 0; s < 3; s++) {
+            for (int s = 0; act && s < 3; s++) {
                 const int n = on[s];
                 if (n < 0) continue;
                 const int m = om[s];
@@ -311,7 +327,7 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 acci[s] += si;
             }
         }
-        flush(O);
+        if (any) flush(O);
     }
 }
 
@@ -324,7 +340,7 @@ void launch_pairs(bool adjoint, Geometry g, int32_t ncell, int p, const int32_t 
     const int64_t nunit = owner_mode ? (int64_t)ncell : (npair + kPairChunk - 1) / kPairChunk;
     const int grid = (int)(nunit < 65536 ? nunit : 65536);
     const int om = owner_mode ? 1 : 0;
-    const size_t lds = (size_t)m2l_pairs_lds_doubles(p) * sizeof(double);
+    const size_t lds = (size_t)m2l_pairs_streams(p, owner_mode) * m2l_pairs_lds_doubles(p) * sizeof(double);
     if (adjoint)
         hipLaunchKernelGGL(k_m2l_pairs<true>, dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr, src, npair,
                            In, Out, om);
