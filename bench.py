@@ -26,7 +26,9 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32_valu": 157.3e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "fp64": 78.6e12, "hbm": 8.0e12}
 P2P_FLOP = 20          # per particle pair: potential + field, one reciprocal square root counted once
 M2L_SPLIT_PRODUCTS = 3  # bf16 products per FP32-accurate product in the mixed M2L (hi.hi, hi.lo, lo.hi)
-QUEUE_SOURCES = ("paper_1203_0889_amd/csrc/queue.hip", "paper_1203_0889_amd/csrc/queue.h")
+# the work queue's kernels and the build of the task tables they run
+QUEUE_SOURCES = ("paper_1203_0889_amd/csrc/queue.hip", "paper_1203_0889_amd/csrc/queue.h",
+                 "paper_1203_0889_amd/csrc/m2l_mfma.hip", "paper_1203_0889_amd/csrc/near_far.hip")
 TRAFFIC_PROFILE = "profiles/k_queue_uniform1m_p8_traffic.txt"
 
 
