@@ -103,6 +103,8 @@ def parse():
     ap.add_argument("--p", type=int, default=None,
                     help="expansion order instead of the workload's (accuracy comparisons across orders)")
     ap.add_argument("--adjoint", action="store_true", help="time forward energy + fmm_backward per step")
+    ap.add_argument("--mutual", action="store_true",
+                    help="FP64 path: the mutual interaction (FMM_FLAG_MUTUAL), each pair listed both ways once")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing leg")
     ap.add_argument("--no-error", action="store_true", help="skip the error check against the direct sum")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default work-queue tuning")
@@ -319,7 +321,7 @@ def run_single(a, torch, fmm, W):
     dev = torch.device("cuda", 0)
     dpos = torch.from_numpy(pos).to(dev)
     dq = torch.from_numpy(q).to(dev)
-    plan = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0)
+    plan = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0, mutual=a.mutual)
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     field = torch.empty((n, 3), dtype=torch.float64, device=dev)
     force = torch.empty((n, 3), dtype=torch.float64, device=dev)
@@ -369,6 +371,8 @@ def run_single(a, torch, fmm, W):
     result["config"] = {"workload": a.workload if a.p is None else "%s_at_p%d" % (a.workload, a.p), "n": n, "p": w["p"], "ncrit": w["ncrit"],
                         "theta": "%d/%d" % tuple(w["theta"]), "precision": a.precision, "distribution": w["dist"],
                         "adjoint": bool(a.adjoint)}
+    if a.mutual:
+        result["config"]["mutual"] = True
     result["stages_ms"] = {k: round(v, 4) for k, v in stage_avg.items()}
     result["tuning"] = tuning
     result["work"] = work
@@ -628,6 +632,9 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: runs on one GPU only (--gpus %d refused)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    if a.mutual and (a.precision != "fp64" or a.sweep or a.timestep > 0 or a.workload == "batch256_p6"):
+        print("bench.py: --mutual is an FP64-path option of a single workload", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1203_0889_amd import fmm, workloads as W

@@ -92,7 +92,7 @@ enum {
                                         of theta' = 5/4 theta.
                                         fmm_get_build_info counts both kinds of
                                         build */
-    FMM_FLAG_COST_REUSE = 1u << 5     /* mixed precision: the work queue measures
+    FMM_FLAG_COST_REUSE = 1u << 5,    /* mixed precision: the work queue measures
                                         the duration of every P2P task (device
                                         clock, one store per task), and a kept-
                                         topology rebuild (KEEP_TOPOLOGY /
@@ -102,6 +102,20 @@ enum {
                                         durations instead of the estimated
                                         costs (Sec. 2.2: the previous step's
                                         work as the weights) */
+    FMM_FLAG_MUTUAL = 1u << 6         /* FP64 precision: the mutual interaction
+                                        (Sec. 4): each M2L or P2P pair listed
+                                        in both directions is evaluated once
+                                        for both cells (P2P: one distance and
+                                        inverse square root per particle pair;
+                                        M2L: one set of irregular harmonics,
+                                        the reverse direction taking the sign
+                                        flip of the odd terms), both cells'
+                                        sums added with FP64 atomics; M2L runs
+                                        per pair rather than over the class
+                                        tables.  Not with FMM_PREC_MIXED or
+                                        FMM_FLAG_DETERMINISTIC
+                                        (FMM_ERR_INVALID_ARG at fmm_create);
+                                        fmm_backward is unchanged */
 };
 
 typedef struct {
@@ -183,7 +197,8 @@ fmm_status fmm_evaluate_noalloc(fmm_plan *plan, double *phi, double *field, doub
  * Adjoint: gradient of the FMM total energy, sum_k g_k E_k with
  * E_k = 1/2 q_k^T A q_k, with respect to positions and charges, where A is
  * the matrix the FMM applies (P2M, M2M, M2L, L2L, L2P and P2P over the built
- * lists; not symmetric, since M2L is non-mutual, Sec. 4).  Computed exactly
+ * lists; not symmetric, since the M2L lists are not, Sec. 4: FMM_FLAG_MUTUAL
+ * evaluates the same pairs).  Computed exactly
  * for that A, in the plan's precision: with w = g q and psi = A^T w (a
  * transposed evaluation: L2P^T, L2L^T, M2L^T, P2P^T, M2M^T, P2M^T),
  *   grad_q_i   = (g_i phi_i + psi_i) / 2

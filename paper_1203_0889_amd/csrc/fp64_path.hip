@@ -81,6 +81,126 @@ __global__ void __launch_bounds__(kP2P64Threads)
     }
 }
 
+// Is A among the sources of target B?  Each target's sources are sorted
+// ascending (the lists are sorted by the whole (target, source) key).
+__device__ __forceinline__ bool listed(const int32_t *__restrict__ ptr, const int32_t *__restrict__ src, int32_t B,
+                                       int32_t A) {
+    int32_t lo = ptr[B], hi = ptr[B + 1];
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        const int32_t v = src[mid];
+        if (v == A) return true;
+        if (v < A) lo = mid + 1; else hi = mid;
+    }
+    return false;
+}
+
+// The mutual P2P (Sec. 4, the mutual interaction): a leaf pair listed in
+// both directions is evaluated once, by the workgroup of the smaller cell
+// index, and each particle pair's distance and inverse square root serve
+// both leaves.  Pairs listed in one direction only, and a leaf with itself,
+// are evaluated forward as in k_p2p_fp64.  The source leaf's sums are
+// gathered in LDS with FP64 LDS atomics: in round i lane (t, s) takes source
+// s + S ((t + i) mod K), so lanes of one stream mostly hit different
+// sources, then added to the source particles with FP64 atomics; the target
+// sums are added with atomics as well (other workgroups add to the same
+// particles), so phi and fld start at zero and the order of the additions
+// is not fixed.
+__global__ void __launch_bounds__(kP2P64Threads)
+    k_p2p_fp64_mutual(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                      const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
+                      const double *__restrict__ qs, double *__restrict__ phi, double *__restrict__ fld) {
+    __shared__ double sx[kP2P64Threads], sy[kP2P64Threads], sz[kP2P64Threads], sq[kP2P64Threads];
+    __shared__ double rp[kP2P64Threads], rx[kP2P64Threads], ry[kP2P64Threads], rz[kP2P64Threads];
+    int32_t A = blockIdx.x;
+    if (A >= ncell || c.child[A] >= 0) return;
+    const int lane = threadIdx.x;
+    int32_t tf = c.first[A], tc = c.count[A];
+    int32_t e0 = ptr[A], e1 = ptr[A + 1];
+    for (int32_t t0 = 0; t0 < tc; t0 += kP2P64Threads) {
+        const int nt = tc - t0 < kP2P64Threads ? tc - t0 : kP2P64Threads;
+        int T = kP2P64Threads;
+        while (T / 2 >= nt) T /= 2;
+        const int S = kP2P64Threads / T;
+        const int t = lane & (T - 1), sidx = lane / T;
+        int32_t r = tf + t0 + t;
+        bool active = t < nt;
+        double xt = active ? xs[r] : 0.0, yt = active ? ys[r] : 0.0, zt = active ? zs[r] : 0.0;
+        double qt = active ? qs[r] : 0.0;
+        double p = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int32_t e = e0; e < e1; e++) {
+            const int32_t B = src[e];
+            // the same B on every lane: the branches below are uniform
+            if (B < A && listed(ptr, src, B, A)) continue;   // taken by B's workgroup
+            const bool mutual = B > A && listed(ptr, src, B, A);
+            int32_t sf = c.first[B], sc = c.count[B];
+            for (int32_t s0 = 0; s0 < sc; s0 += kP2P64Threads) {
+                int ns = sc - s0 < kP2P64Threads ? sc - s0 : kP2P64Threads;
+                __syncthreads();
+                if (lane < ns) {
+                    sx[lane] = xs[sf + s0 + lane];
+                    sy[lane] = ys[sf + s0 + lane];
+                    sz[lane] = zs[sf + s0 + lane];
+                    sq[lane] = qs[sf + s0 + lane];
+                }
+                rp[lane] = rx[lane] = ry[lane] = rz[lane] = 0.0;
+                __syncthreads();
+                const int K = (ns + S - 1) / S;   // rounds: sources per stream, the last may be past ns
+                int u = t % K;
+                for (int i = 0; i < K; i++) {
+                    const int j = sidx + S * u;
+                    u = u + 1 == K ? 0 : u + 1;
+                    if (j >= ns) continue;
+                    double dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
+                    double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 > 0.0) {
+                        double inv = rsqrt(r2);
+                        double inv2 = inv * inv;
+                        double qi = sq[j] * inv;
+                        double qi3 = qi * inv2;
+                        p += qi;
+                        ex += dx * qi3;
+                        ey += dy * qi3;
+                        ez += dz * qi3;
+                        if (mutual && active) {
+                            // the target's charge at the source: the field
+                            // there points along -d
+                            double qj = qt * inv;
+                            double qj3 = qj * inv2;
+                            atomicAdd(&rp[j], qj);
+                            atomicAdd(&rx[j], -dx * qj3);
+                            atomicAdd(&ry[j], -dy * qj3);
+                            atomicAdd(&rz[j], -dz * qj3);
+                        }
+                    }
+                }
+                if (mutual) {
+                    __syncthreads();
+                    if (lane < ns) {
+                        const int64_t k = sf + s0 + lane;
+                        atomicAdd(&phi[k], rp[lane]);
+                        atomicAdd(&fld[3 * k], rx[lane]);
+                        atomicAdd(&fld[3 * k + 1], ry[lane]);
+                        atomicAdd(&fld[3 * k + 2], rz[lane]);
+                    }
+                }
+            }
+        }
+        for (int o = kP2P64Threads / 2; o >= T; o >>= 1) {
+            p += __shfl_xor(p, o, kP2P64Threads);
+            ex += __shfl_xor(ex, o, kP2P64Threads);
+            ey += __shfl_xor(ey, o, kP2P64Threads);
+            ez += __shfl_xor(ez, o, kP2P64Threads);
+        }
+        if (active && sidx == 0) {
+            atomicAdd(&phi[r], p);
+            atomicAdd(&fld[3 * (int64_t)r], ex);
+            atomicAdd(&fld[3 * (int64_t)r + 1], ey);
+            atomicAdd(&fld[3 * (int64_t)r + 2], ez);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- M2L
 // Per-pair M2L in FP64, balanced over pairs: a wave takes kPairChunk
 // consecutive entries of a CSR pair list, finds the owner of its first entry
@@ -124,10 +244,25 @@ __host__ __device__ constexpr int m2l_pairs_streams(int p, bool owner_mode) {
     return (!owner_mode && (p + 1) * (p + 2) / 2 <= 32) ? 2 : 1;
 }
 
-template <bool kAdjoint>
+// Mutual M2L (Sec. 4, the mutual interaction; forward only, balanced
+// mode): a pair listed in both directions is evaluated once, at the entry
+// whose owner A has the smaller index, and the reverse pair B <- A reuses the
+// harmonics of A <- B.  With rho' = -2^(-delta) rho the reverse offset in
+// units of B's side, homogeneity (I_N(lambda x) = lambda^(-N-1) I_N(x)) and
+// parity (I_N(-x) = (-1)^N I_N(x)) of the irregular harmonics give
+//   reverse:  L~_n^m(B) += 2^(delta (n+1)) sum_k (-1)^k sum_l M~_k^l(A) I_(n+k)^(m+l)(rho),
+// the forward sum with the sign flip of the odd terms moved from the output
+// degree n to the input degree k.  The reverse sums go to B with FP64
+// atomics after every pair.
+__host__ __device__ constexpr int m2l_pairs_lds_mutual_doubles(int p, bool mutual) {
+    return m2l_pairs_lds_doubles(p) + (mutual ? 2 * (p + 1) * (p + 1) : 0);
+}
+
+template <bool kAdjoint, bool kMutual>
 __global__ void __launch_bounds__(kM2L64Threads)
     k_m2l_pairs(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
                 int64_t npair, const double *__restrict__ In, double *__restrict__ Out, int owner_mode) {
+    static_assert(!(kAdjoint && kMutual), "the mutual variant is forward only");
     extern __shared__ double lds[];
     const int NJ = (2 * p + 1) * (2 * p + 1), NM = (p + 1) * (p + 1);
     const int P = ncoef(p);
@@ -137,8 +272,10 @@ __global__ void __launch_bounds__(kM2L64Threads)
     // (owner mode keeps one stream: one owner's pairs in list order)
     const int H = m2l_pairs_streams(p, owner_mode != 0), W = 64 / H;
     const int h = threadIdx.x / W, lane = threadIdx.x - h * W;
-    double *base = lds + h * m2l_pairs_lds_doubles(p);
+    double *base = lds + h * m2l_pairs_lds_mutual_doubles(p, kMutual);
     double *Jre = base, *Jim = base + NJ, *Mre = base + 2 * NJ, *Mim = base + 2 * NJ + NM;
+    // mutual: the owner's multipole (the reverse pair's source)
+    double *Are = base + 2 * NJ + 2 * NM, *Aim = base + 2 * NJ + 3 * NM;
     // this lane's outputs: complex index j = lane, lane + W, lane + 2 W
     int on[3], om[3];
     for (int s = 0; s < 3; s++) {
@@ -177,6 +314,7 @@ __global__ void __launch_bounds__(kM2L64Threads)
         }
         const bool any = e0 + h < e1;   // this stream has a pair in the chunk
         double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
+        double revr[3] = {0, 0, 0}, revi[3] = {0, 0, 0};   // mutual: the reverse pair's sums
         auto flush = [&](int32_t owner) {
             double *out = Out + (int64_t)owner * P;
             for (int s = 0; s < 3; s++) {
@@ -199,13 +337,20 @@ __global__ void __launch_bounds__(kM2L64Threads)
         const int64_t rounds = (e1 - e0 + H - 1) / H;
         for (int64_t t = 0; t < rounds; t++) {
             const int64_t e = e0 + h + H * t;
-            const bool act = e < e1;
+            bool act = e < e1;
             if (act && e >= ptr[O + 1]) {
                 flush(O);
                 while (e >= ptr[O + 1]) O++;
             }
             const int32_t other = act ? src[e] : src[e0];
             const int32_t A = kAdjoint ? other : O, B = kAdjoint ? O : other;
+            bool mutual = false;
+            if (kMutual && act) {
+                // the same (O, other) on every lane of the stream
+                const bool both = listed(ptr, src, other, O);
+                if (both && other < O) act = false;   // evaluated at the entry owned by other
+                mutual = both && other > O;
+            }
             const int la = c.level[A], lb = c.level[B];
             const int64_t SA = (int64_t)1 << (kLevels - la), SB = (int64_t)1 << (kLevels - lb);
             // rho in units of the target side: (C_A - C_B) / (2 S_A), exact
@@ -234,6 +379,19 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 }
                 Mre[i] = re;
                 Mim[i] = im;
+                if (kMutual && mutual) {
+                    const double *y = In + (int64_t)O * P;
+                    double are = y[cidx_re(k, al)], aim = al > 0 ? y[cidx_im(k, al)] : 0.0;
+                    if (l < 0) {
+                        aim = -aim;
+                        if (al & 1) {
+                            are = -are;
+                            aim = -aim;
+                        }
+                    }
+                    Are[i] = are;
+                    Aim[i] = aim;
+                }
             }
             if (act && lane <= 2 * p) {
                 // column m of the harmonics, and its mirror J_n^(-m) =
@@ -283,7 +441,40 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 if (n < 0) continue;
                 const int m = om[s];
                 double sr = 0, si = 0;
-                if (!kAdjoint) {
+                if (kMutual && mutual) {
+                    // forward and reverse over the same harmonics
+                    double qr = 0, qi = 0;
+                    for (int k = 0; k <= p; k++) {
+                        const double fk = ldexp(1.0, delta * k);
+                        const int nn = n + k, mb = k * k + k, jb = nn * nn + nn + m;
+                        double tr = 0, ti = 0, ur = 0, ui = 0;
+                        for (int l = -k; l <= k; l++) {
+                            const double jre = Jre[jb + l], jim = Jim[jb + l];
+                            const double mre = Mre[mb + l], mim = Mim[mb + l];
+                            const double are = Are[mb + l], aim = Aim[mb + l];
+                            tr += mre * jre - mim * jim;
+                            ti += mre * jim + mim * jre;
+                            ur += are * jre - aim * jim;
+                            ui += are * jim + aim * jre;
+                        }
+                        sr += fk * tr;
+                        si += fk * ti;
+                        if (k & 1) {
+                            qr -= ur;
+                            qi -= ui;
+                        } else {
+                            qr += ur;
+                            qi += ui;
+                        }
+                    }
+                    if (n & 1) {
+                        sr = -sr;
+                        si = -si;
+                    }
+                    const double fo = ldexp(1.0, delta * (n + 1));
+                    revr[s] = fo * qr;
+                    revi[s] = fo * qi;
+                } else if (!kAdjoint) {
                     // S_n^m = sum_k 2^(delta k) sum_l M_k^l J_(n+k)^(m+l)
                     for (int k = 0; k <= p; k++) {
                         const double fk = ldexp(1.0, delta * k);
@@ -326,6 +517,16 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 accr[s] += sr;
                 acci[s] += si;
             }
+            if (kMutual && mutual) {
+                double *out = Out + (int64_t)other * P;
+                for (int s = 0; s < 3; s++) {
+                    const int n = on[s];
+                    if (n < 0) continue;
+                    const int m = om[s];
+                    atomicAdd(&out[cidx_re(n, m)], revr[s]);
+                    if (m > 0) atomicAdd(&out[cidx_im(n, m)], revi[s]);
+                }
+            }
         }
         if (any) flush(O);
     }
@@ -335,18 +536,24 @@ __global__ void __launch_bounds__(kM2L64Threads)
 
 namespace {
 void launch_pairs(bool adjoint, Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
-                  const double *In, double *Out, bool owner_mode, hipStream_t s) {
+                  const double *In, double *Out, bool owner_mode, hipStream_t s, bool mutual = false) {
     if (ncell == 0 || npair <= 0) return;
+    if (mutual && (adjoint || owner_mode))
+        throw HipError{hipErrorInvalidValue, "mutual M2L: forward, balanced mode only"};
     const int64_t nunit = owner_mode ? (int64_t)ncell : (npair + kPairChunk - 1) / kPairChunk;
     const int grid = (int)(nunit < 65536 ? nunit : 65536);
     const int om = owner_mode ? 1 : 0;
-    const size_t lds = (size_t)m2l_pairs_streams(p, owner_mode) * m2l_pairs_lds_doubles(p) * sizeof(double);
+    const size_t lds =
+        (size_t)m2l_pairs_streams(p, owner_mode) * m2l_pairs_lds_mutual_doubles(p, mutual) * sizeof(double);
     if (adjoint)
-        hipLaunchKernelGGL(k_m2l_pairs<true>, dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr, src, npair,
-                           In, Out, om);
+        hipLaunchKernelGGL((k_m2l_pairs<true, false>), dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr,
+                           src, npair, In, Out, om);
+    else if (mutual)
+        hipLaunchKernelGGL((k_m2l_pairs<false, true>), dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr,
+                           src, npair, In, Out, om);
     else
-        hipLaunchKernelGGL(k_m2l_pairs<false>, dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr, src, npair,
-                           In, Out, om);
+        hipLaunchKernelGGL((k_m2l_pairs<false, false>), dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr,
+                           src, npair, In, Out, om);
     FMM_LAUNCH_CHECK();
 }
 }  // namespace
@@ -374,6 +581,23 @@ void launch_m2l_fp64(Geometry g, int32_t ncell, int p, const int32_t *ptr, const
 void launch_m2l_fp64_add(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
                          const double *M, double *L, bool owner_mode, hipStream_t s) {
     launch_pairs(false, g, ncell, p, ptr, src, npair, M, L, owner_mode, s);
+}
+
+void launch_p2p_fp64_mutual(Geometry g, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *src,
+                            const double *xs, const double *ys, const double *zs, const double *qs, double *phi,
+                            double *fld, hipStream_t s) {
+    if (ncell == 0) return;
+    fill_zero(phi, (size_t)n * sizeof(double), s);
+    fill_zero(fld, (size_t)n * 3 * sizeof(double), s);
+    hipLaunchKernelGGL(k_p2p_fp64_mutual, dim3(ncell), dim3(kP2P64Threads), 0, s, g.c, ncell, ptr, src, xs, ys, zs,
+                       qs, phi, fld);
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_m2l_fp64_mutual(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
+                            const double *M, double *L, hipStream_t s) {
+    fill_zero(L, (size_t)ncell * ncoef(p) * sizeof(double), s);
+    launch_pairs(false, g, ncell, p, ptr, src, npair, M, L, false, s, true);
 }
 
 }  // namespace fmm

@@ -135,6 +135,16 @@ std::vector<double> transpose_ops(const std::vector<double> &ops, int p);
 // ---- near / far field, FP64 plain path
 void launch_p2p_fp64(Geometry g, int32_t ncell, const int32_t *ptr, const int32_t *src, const double *xs,
                      const double *ys, const double *zs, const double *qs, double *phi, double *fld, hipStream_t s);
+// The mutual variants (forward only; each target's sources sorted
+// ascending): a pair listed in both directions is evaluated once for both
+// cells, with FP64 atomics into outputs zeroed first (phi, fld of n sorted
+// particles; L of every cell); pairs listed one way only are evaluated
+// forward.  The order of the additions is not fixed.
+void launch_p2p_fp64_mutual(Geometry g, int32_t ncell, int64_t n, const int32_t *ptr, const int32_t *src,
+                            const double *xs, const double *ys, const double *zs, const double *qs, double *phi,
+                            double *fld, hipStream_t s);
+void launch_m2l_fp64_mutual(Geometry g, int32_t ncell, int p, const int32_t *ptr, const int32_t *src, int64_t npair,
+                            const double *M, double *L, hipStream_t s);
 // Per-pair FP64 M2L over the CSR list (ptr, src) of npair pairs (target-owned),
 // balanced over pairs (FP64 atomics), or with owner_mode one wave per owner
 // in list order (no atomics: a fixed order of additions); overwrites L

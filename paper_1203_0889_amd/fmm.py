@@ -28,6 +28,7 @@ FLAG_TRACE = 4
 FLAG_DETERMINISTIC = 8
 FLAG_INCREMENTAL = 16
 FLAG_COST_REUSE = 32
+FLAG_MUTUAL = 64
 
 # every symbol include/fmm.h declares
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
@@ -137,7 +138,7 @@ class Plan:
 
     def __init__(self, p=8, ncrit=64, theta=(1, 2), max_level=21, precision="mixed", device=None, stream=None,
                  box=None, keep_topology=False, trace=False, deterministic=False, incremental=False,
-                 cost_reuse=False):
+                 cost_reuse=False, mutual=False):
         self._lib = load_library()
         prm = fmm_params()
         self._lib.fmm_default_params(ctypes.byref(prm))
@@ -159,6 +160,8 @@ class Plan:
             prm.flags |= FLAG_INCREMENTAL
         if cost_reuse:
             prm.flags |= FLAG_COST_REUSE
+        if mutual:
+            prm.flags |= FLAG_MUTUAL
         self.params = prm
         if device is None:
             device = torch.cuda.current_device()

@@ -1,0 +1,142 @@
+"""The mutual interaction (FMM_FLAG_MUTUAL, FP64 path): every M2L and P2P
+pair listed in both directions is evaluated once for both cells; the
+reverse M2L reuses the forward pair's harmonics with the sign flip of the
+odd terms and a power-of-two level scaling.  In exact arithmetic it computes
+the same function as the non-mutual FMM (same tree, lists, centres and
+degrees), so the bound against the oracle FMM is the FP64 path's: 1e-11
+relative L2 plus the per-particle checks; against the non-mutual GPU path
+(same kernels' rounding, other summation order) 1e-12 of the rms per
+particle.  The cases cover both M2L lane layouts (two pair streams per wave
+at p <= 6), leaves of more than 64 particles (several target and source
+chunks), adaptive trees with cross-level pairs listed one way only, and a
+batch of instances."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1203_0889_amd import fmm, workloads as W
+from parity import check_fp64, leaf_ids, maxrel, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run(pos, q, p, ncrit, theta, mutual, offsets=None, backward=False):
+    plan = fmm.Plan(p=p, ncrit=ncrit, theta=theta, precision="fp64", device=0, mutual=mutual)
+    plan.build_tree(dev(pos), dev(q), offsets)
+    plan.upward()
+    out = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    if backward:
+        gp, gq = plan.backward(dev(np.ones(1 if offsets is None else len(offsets) - 1)))
+        out["grad_pos"], out["grad_q"] = gp.cpu().numpy(), gq.cpu().numpy()
+    torch.cuda.synchronize()
+    return plan, out
+
+
+# (name, dist, n, seed, p, ncrit, theta)
+CASES = [
+    ("uniform5k_p8_ragged", "uniform", 5003, 7, 8, 40, (1, 2)),
+    ("plummer20k_p6", "plummer", 20000, 3, 6, 16, (1, 2)),
+    ("plummer9k_p10_theta04", "plummer", 9001, 5, 10, 32, (2, 5)),
+    ("uniform20k_p4_ncrit150", "uniform", 20000, 13, 4, 150, (1, 2)),
+    ("plummer2k_p13", "plummer", 2000, 11, 13, 16, (1, 2)),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    name, dist, n, seed, p, ncrit, theta = request.param
+    say("case", name)
+    pos, q = W.uniform_cube(n, seed) if dist == "uniform" else W.plummer(n, seed)
+    T = oracle.Tree(pos, ncrit)
+    T.lists(*theta)
+    plan, out = run(pos, q, p, ncrit, theta, True)
+    return dict(name=name, pos=pos, q=q, p=p, ncrit=ncrit, theta=theta, T=T, plan=plan, out=out)
+
+
+def test_mutual_matches_oracle_fmm(case):
+    T = case["T"]
+    phi_ref, fld_ref = T.fmm(case["q"], case["p"])
+    out = case["out"]
+    e = (rel(out["phi"], phi_ref), rel(out["field"], fld_ref))
+    say(case["name"], "mutual fp64 vs oracle fmm", e)
+    assert max(e) < 1e-11
+    check_fp64(out, phi_ref, fld_ref, leaf_ids(T.perm, T.cells), say, case["name"])
+    assert np.allclose(out["force"], case["q"][:, None] * out["field"], rtol=1e-15, atol=0)
+    assert out["energy"][0] == pytest.approx(0.5 * np.dot(case["q"], out["phi"]), rel=1e-12)
+
+
+def test_mutual_matches_non_mutual(case):
+    _, ref = run(case["pos"], case["q"], case["p"], case["ncrit"], case["theta"], False)
+    m = (maxrel(case["out"]["phi"], ref["phi"]), maxrel(case["out"]["field"], ref["field"]))
+    say(case["name"], "mutual vs non-mutual worst particle / rms", m)
+    assert max(m) < 1e-12
+
+
+def test_mutual_lists_are_the_canonical_lists(case):
+    # the mutual plan evaluates the oracle's pair sets (each target's sources
+    # sorted on the device, which the reverse-pair lookup needs)
+    mp, ms, pp, ps = case["plan"].copy_lists()
+    T = case["T"]
+    for ptr, src, ref in ((mp, ms, T.m2l), (pp, ps, T.p2p)):
+        assert np.array_equal(np.repeat(np.arange(T.ncell), np.diff(ptr)), ref[:, 0])
+        assert np.array_equal(src, ref[:, 1])
+
+
+def test_mutual_batch_and_backward():
+    pos, q, offsets = W.batch(6, 17)
+    offs = [int(o) for o in offsets]
+    _, a = run(pos, q, 6, 32, (1, 2), True, offs, backward=True)
+    _, b = run(pos, q, 6, 32, (1, 2), False, offs, backward=True)
+    for k in ("phi", "field", "grad_pos", "grad_q"):
+        say("batch", k, maxrel(a[k], b[k]))
+        assert maxrel(a[k], b[k]) < 1e-12
+    assert np.allclose(a["energy"], b["energy"], rtol=1e-12, atol=0)
+
+
+def test_mutual_repeat_and_rebuild():
+    # atomics reorder the sums: repeated evaluations agree to rounding; a
+    # kept-topology rebuild with new charges uses the same sorted lists
+    pos, q = W.uniform_cube(30000, 21)
+    plan = fmm.Plan(p=8, ncrit=64, theta=(1, 2), precision="fp64", device=0, mutual=True, keep_topology=True)
+    plan.build_tree(dev(pos), dev(q))
+    plan.upward()
+    o1 = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    o2 = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    assert maxrel(o1["phi"], o2["phi"]) < 1e-13 and maxrel(o1["field"], o2["field"]) < 1e-13
+    q2 = -0.5 * q + 0.25
+    plan.build_tree(dev(pos), dev(q2))
+    plan.upward()
+    o3 = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    _, ref = run(pos, q2, 8, 64, (1, 2), False)
+    assert maxrel(o3["phi"], ref["phi"]) < 1e-12 and maxrel(o3["field"], ref["field"]) < 1e-12
+
+
+def test_mutual_flag_validation():
+    with pytest.raises(fmm.FMMError):
+        fmm.Plan(p=4, precision="mixed", device=0, mutual=True)
+    with pytest.raises(fmm.FMMError):
+        fmm.Plan(p=4, precision="fp64", device=0, mutual=True, deterministic=True)
+
+
+def test_mutual_small_edge_cases():
+    # one leaf (only the self pair), one particle, coincident particles
+    for pos, q, ncrit in ((W.uniform_cube(60, 4)[0], W.uniform_cube(60, 4)[1], 64),
+                          (np.array([[0.3, 0.2, 0.1]]), np.array([2.0]), 8),
+                          (np.array([[0.1, 0.1, 0.1], [0.1, 0.1, 0.1], [0.9, 0.2, 0.4]]),
+                           np.array([1.0, -2.0, 0.5]), 1)):
+        _, out = run(pos, q, 4, ncrit, (1, 2), True)
+        pd, fd = oracle.direct(pos, q)
+        assert np.all(np.isfinite(out["phi"])) and np.all(np.isfinite(out["field"]))
+        if len(q) == 1:
+            assert out["phi"][0] == 0.0 and np.all(out["field"][0] == 0.0)
+        else:
+            assert rel(out["phi"], pd) < 1e-13 and rel(out["field"], fd) < 1e-12

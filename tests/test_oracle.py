@@ -237,6 +237,26 @@ def test_lists_cover_every_pair_once(dist, n, ncrit, theta):
         assert np.all(np.diff(key) > 0)
 
 
+@pytest.mark.parametrize("dist,n,ncrit,theta", [("uniform", 3000, 16, (1, 2)), ("plummer", 4000, 8, (2, 5)),
+                                                ("plummer", 2500, 4, (99, 100))])
+def test_p2p_lists_are_symmetric(dist, n, ncrit, theta):
+    # For theta < 1 a failed MAC stays failed when a cell is replaced by its
+    # parent (the radius doubles while the centre moves by at most the old
+    # radius), so every ancestor pair of a P2P leaf pair is split and the
+    # traversal reaches the pair in both orders: the P2P list equals its
+    # transpose (the mutual P2P evaluates each such pair once).  An M2L
+    # pair need not come in both orders: (A_i <- B_j) may be reached through
+    # (A_i <- B) while the reverse stops one level up at (B_j <- A), so the
+    # M2L list is only partly symmetric.
+    pos, q = W.uniform_cube(n, 8) if dist == "uniform" else W.plummer(n, 8)
+    T = oracle.Tree(pos, ncrit)
+    m2l, p2p = T.lists(*theta)
+    key = lambda a, b: a.astype(np.int64) * (1 << 32) + b
+    assert np.array_equal(np.sort(key(p2p[:, 0], p2p[:, 1])), np.sort(key(p2p[:, 1], p2p[:, 0])))
+    both = np.isin(key(m2l[:, 1], m2l[:, 0]), key(m2l[:, 0], m2l[:, 1]))
+    assert 0.5 < both.mean() < 1.0
+
+
 def _grid_particles(level):
     k = 2 ** level
     g = np.array([[i, j, l] for l in range(k) for j in range(k) for i in range(k)], float)
