@@ -11,18 +11,117 @@ namespace {
 
 // ---------------------------------------------------------------- P2P
 // One wave per target leaf; source particles of every listed source leaf
-// staged through LDS 64 at a time.  A chunk of nt <= 64 / S targets puts S
-// lanes on each target (S a power of two, as large as fits), each taking
-// every S-th staged source; the S partial sums are added with a fixed
-// butterfly at the end, so leaves of 32 or fewer particles keep every lane
-// busy.
+// staged through LDS 64 at a time as (x, y, z, q), the slots past the leaf's
+// end zero.  A chunk of nt <= 64 targets is covered by two passes: pass 0
+// takes the first T0 = 2^floor(log2 nt) targets with 64 / T0 source streams
+// (every lane busy), pass 1 the remaining r = nt - T0 with
+// T1 = 2^ceil(log2 r) lanes per stream (lane = stream * T + target).  In a
+// pass every lane runs the same number of rounds, four sources loaded before
+// their arithmetic; a pair at zero distance (coincident particles, or an
+// underflowing r^2) is skipped by a select, and the last round (slots past
+// the end) is masked.  A pass's streams are added with a fixed butterfly at
+// the end.
 constexpr int kP2P64Threads = 64;
+
+// 1/sqrt(r2) for r2 > 0: the hardware estimate y refined by one second-order
+// step of the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., with
+// e = 1 - r2 y^2, which squares and cubes the estimate's relative error.
+__device__ __forceinline__ double rsqrt_fp64(double r2) {
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-r2, y * y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+struct Pass64 {
+    int lg;           // log2 of targets per stream (T = 1 << lg); -1 = unused
+    int n;            // targets in the pass
+    int base;         // first target of the pass within the chunk
+    double x, y, z;   // this lane's target
+    double p, ex, ey, ez;
+};
+
+template <bool kMask>
+__device__ __forceinline__ void p2p64_one(const double4 &v, Pass64 &a, bool valid) {
+    const double dx = a.x - v.x, dy = a.y - v.y, dz = a.z - v.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double inv = ((!kMask || valid) && r2 > 0.0) ? rsqrt_fp64(r2) : 0.0;
+    const double qi = v.w * inv;
+    const double qi3 = qi * inv * inv;
+    a.p += qi;
+    a.ex += dx * qi3;
+    a.ey += dy * qi3;
+    a.ez += dz * qi3;
+}
+
+__device__ __forceinline__ void pass64_init(Pass64 &ps, int n, int base, const double *__restrict__ xs,
+                                            const double *__restrict__ ys, const double *__restrict__ zs,
+                                            int64_t first, int lane) {
+    ps.n = n;
+    ps.base = base;
+    ps.x = ps.y = ps.z = 0.0;
+    ps.p = ps.ex = ps.ey = ps.ez = 0.0;
+    if (n <= 0) {
+        ps.lg = -1;
+        return;
+    }
+    int lg = 0;
+    while ((1 << lg) < n) lg++;
+    ps.lg = lg;
+    const int t = lane & ((1 << lg) - 1);
+    if (t < n) {
+        ps.x = xs[first + base + t];
+        ps.y = ys[first + base + t];
+        ps.z = zs[first + base + t];
+    }
+}
+
+// The staged chunk of ns <= 64 sources against this lane's target of the
+// pass: stream s takes sources s, s + S, ...; with K = ceil(ns / S) rounds,
+// S K <= 64 (S a power of two), so every slot read is < 64, and the rounds
+// before the last read slots < ns only.
+__device__ __forceinline__ void pass64_run(const double4 *__restrict__ st, int ns, Pass64 &ps, int lane) {
+    if (ps.lg < 0) return;
+    const int S = kP2P64Threads >> ps.lg;
+    const int s = lane >> ps.lg;
+    const int K = (ns + S - 1) / S;
+    int i = 0;
+    for (; i + 4 <= K - 1; i += 4) {
+        const double4 a0 = st[s + S * i], a1 = st[s + S * (i + 1)];
+        const double4 a2 = st[s + S * (i + 2)], a3 = st[s + S * (i + 3)];
+        p2p64_one<false>(a0, ps, true);
+        p2p64_one<false>(a1, ps, true);
+        p2p64_one<false>(a2, ps, true);
+        p2p64_one<false>(a3, ps, true);
+    }
+    for (; i < K - 1; i++) p2p64_one<false>(st[s + S * i], ps, true);
+    const int j = s + S * (K - 1);   // the last round
+    p2p64_one<true>(st[j], ps, j < ns);
+}
+
+__device__ __forceinline__ void pass64_write(Pass64 &ps, double *__restrict__ phi, double *__restrict__ fld,
+                                             int64_t first, int lane) {
+    if (ps.lg < 0) return;
+    double p = ps.p, ex = ps.ex, ey = ps.ey, ez = ps.ez;
+    for (int o = kP2P64Threads / 2; o >= (1 << ps.lg); o >>= 1) {   // the streams of a target
+        p += __shfl_xor(p, o, kP2P64Threads);
+        ex += __shfl_xor(ex, o, kP2P64Threads);
+        ey += __shfl_xor(ey, o, kP2P64Threads);
+        ez += __shfl_xor(ez, o, kP2P64Threads);
+    }
+    if (lane < ps.n) {   // stream 0, target `lane`
+        const int64_t r = first + ps.base + lane;
+        phi[r] = p;
+        fld[3 * r] = ex;
+        fld[3 * r + 1] = ey;
+        fld[3 * r + 2] = ez;
+    }
+}
 
 __global__ void __launch_bounds__(kP2P64Threads)
     k_p2p_fp64(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
                const double *__restrict__ xs, const double *__restrict__ ys, const double *__restrict__ zs,
                const double *__restrict__ qs, double *__restrict__ phi, double *__restrict__ fld) {
-    __shared__ double sx[kP2P64Threads], sy[kP2P64Threads], sz[kP2P64Threads], sq[kP2P64Threads];
+    __shared__ double4 st[kP2P64Threads];
     int32_t A = blockIdx.x;
     if (A >= ncell || c.child[A] >= 0) return;
     const int lane = threadIdx.x;
@@ -30,54 +129,30 @@ __global__ void __launch_bounds__(kP2P64Threads)
     int32_t e0 = ptr[A], e1 = ptr[A + 1];
     for (int32_t t0 = 0; t0 < tc; t0 += kP2P64Threads) {
         const int nt = tc - t0 < kP2P64Threads ? tc - t0 : kP2P64Threads;
-        int T = kP2P64Threads;   // targets per pass: the smallest power of two >= nt
-        while (T / 2 >= nt) T /= 2;
-        const int S = kP2P64Threads / T;
-        const int t = lane & (T - 1), sidx = lane / T;
-        int32_t r = tf + t0 + t;
-        bool active = t < nt;
-        double xt = active ? xs[r] : 0.0, yt = active ? ys[r] : 0.0, zt = active ? zs[r] : 0.0;
-        double p = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        int hb = 0;
+        while ((2 << hb) <= nt) hb++;
+        Pass64 p0, p1;
+        pass64_init(p0, 1 << hb, 0, xs, ys, zs, tf + t0, lane);
+        pass64_init(p1, nt - (1 << hb), 1 << hb, xs, ys, zs, tf + t0, lane);
         for (int32_t e = e0; e < e1; e++) {
-            int32_t B = src[e];
+            const int32_t B = src[e];
             int32_t sf = c.first[B], sc = c.count[B];
             for (int32_t s0 = 0; s0 < sc; s0 += kP2P64Threads) {
-                int ns = sc - s0 < kP2P64Threads ? sc - s0 : kP2P64Threads;
+                const int ns = sc - s0 < kP2P64Threads ? sc - s0 : kP2P64Threads;
                 __syncthreads();
+                double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
                 if (lane < ns) {
-                    sx[lane] = xs[sf + s0 + lane];
-                    sy[lane] = ys[sf + s0 + lane];
-                    sz[lane] = zs[sf + s0 + lane];
-                    sq[lane] = qs[sf + s0 + lane];
+                    const int64_t k = sf + s0 + lane;
+                    v = make_double4(xs[k], ys[k], zs[k], qs[k]);
                 }
+                st[lane] = v;
                 __syncthreads();
-                for (int j = sidx; j < ns; j += S) {
-                    double dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
-                    double r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 > 0.0) {
-                        double inv = rsqrt(r2);
-                        double qi = sq[j] * inv;
-                        double qi3 = qi * inv * inv;
-                        p += qi;
-                        ex += dx * qi3;
-                        ey += dy * qi3;
-                        ez += dz * qi3;
-                    }
-                }
+                pass64_run(st, ns, p0, lane);
+                pass64_run(st, ns, p1, lane);
             }
         }
-        for (int o = kP2P64Threads / 2; o >= T; o >>= 1) {   // the S streams of a target
-            p += __shfl_xor(p, o, kP2P64Threads);
-            ex += __shfl_xor(ex, o, kP2P64Threads);
-            ey += __shfl_xor(ey, o, kP2P64Threads);
-            ez += __shfl_xor(ez, o, kP2P64Threads);
-        }
-        if (active && sidx == 0) {
-            phi[r] = p;
-            fld[3 * (int64_t)r] = ex;
-            fld[3 * (int64_t)r + 1] = ey;
-            fld[3 * (int64_t)r + 2] = ez;
-        }
+        pass64_write(p0, phi, fld, tf + t0, lane);
+        pass64_write(p1, phi, fld, tf + t0, lane);
     }
 }
 
