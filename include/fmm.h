@@ -270,8 +270,8 @@ fmm_status fmm_get_build_info(const fmm_plan *plan, int64_t *full_builds, int64_
  * paper's granularity knob, Sec. 5), the operator classes in use, and the
  * M2L pairs left to the per-pair FP64 kernel.  The FP64 path reports the
  * same class tables, which its FP64 matrix-core M2L runs over for p <= 12
- * (no P2P tasks; every count is 0 above p = 12).  Before a build:
- * FMM_ERR_STATE.
+ * (no P2P tasks; every count is 0 above p = 12 and with FMM_FLAG_MUTUAL,
+ * whose M2L runs per pair).  Before a build: FMM_ERR_STATE.
  */
 fmm_status fmm_get_queue_info(const fmm_plan *plan, int64_t *ntarget, int64_t *ngroup, int64_t *ntask,
                               int64_t *nclass, int64_t *nextra);

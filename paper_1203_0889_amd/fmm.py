@@ -297,7 +297,9 @@ class Plan:
         return {"full": v[0].value, "kept": v[1].value}
 
     def queue_info(self):
-        """Work-queue table sizes of the last build (mixed path; zeros for FP64)."""
+        """Class-table and work-queue sizes of the last build (the FP64 path
+        reports its class tables; zeros where M2L runs per pair: p > 12 or
+        mutual)."""
         v = [ctypes.c_int64() for _ in range(5)]
         self._call(self._lib.fmm_get_queue_info, *[ctypes.byref(x) for x in v])
         return dict(zip(("ntarget", "ngroup", "ntask", "nclass", "nextra"), (x.value for x in v)))
