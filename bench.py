@@ -103,8 +103,8 @@ def parse():
     ap.add_argument("--p", type=int, default=None,
                     help="expansion order instead of the workload's (accuracy comparisons across orders)")
     ap.add_argument("--adjoint", action="store_true", help="time forward energy + fmm_backward per step")
-    ap.add_argument("--mutual", action="store_true",
-                    help="FP64 path: the mutual interaction (FMM_FLAG_MUTUAL), each pair listed both ways once")
+    ap.add_argument("--mutual", nargs="?", const="both", default=None, choices=["both", "m2l", "p2p"],
+                    help="FP64 path: the mutual interaction for M2L, P2P or both (each pair listed both ways once)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing leg")
     ap.add_argument("--no-error", action="store_true", help="skip the error check against the direct sum")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default work-queue tuning")
@@ -321,7 +321,8 @@ def run_single(a, torch, fmm, W):
     dev = torch.device("cuda", 0)
     dpos = torch.from_numpy(pos).to(dev)
     dq = torch.from_numpy(q).to(dev)
-    plan = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0, mutual=a.mutual)
+    plan = fmm.Plan(p=w["p"], ncrit=w["ncrit"], theta=w["theta"], precision=a.precision, device=0,
+                    mutual=a.mutual or False)
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     field = torch.empty((n, 3), dtype=torch.float64, device=dev)
     force = torch.empty((n, 3), dtype=torch.float64, device=dev)
@@ -372,7 +373,7 @@ def run_single(a, torch, fmm, W):
                         "theta": "%d/%d" % tuple(w["theta"]), "precision": a.precision, "distribution": w["dist"],
                         "adjoint": bool(a.adjoint)}
     if a.mutual:
-        result["config"]["mutual"] = True
+        result["config"]["mutual"] = a.mutual
     result["stages_ms"] = {k: round(v, 4) for k, v in stage_avg.items()}
     result["tuning"] = tuning
     result["work"] = work

@@ -102,18 +102,23 @@ enum {
                                         durations instead of the estimated
                                         costs (Sec. 2.2: the previous step's
                                         work as the weights) */
-    FMM_FLAG_MUTUAL = 1u << 6         /* FP64 precision: the mutual interaction
-                                        (Sec. 4): each M2L or P2P pair listed
-                                        in both directions is evaluated once
-                                        for both cells (P2P: one distance and
-                                        inverse square root per particle pair;
-                                        M2L: one set of irregular harmonics,
-                                        the reverse direction taking the sign
-                                        flip of the odd terms), both cells'
-                                        sums added with FP64 atomics; M2L runs
-                                        per pair rather than over the class
-                                        tables.  Not with FMM_PREC_MIXED or
-                                        FMM_FLAG_DETERMINISTIC
+    FMM_FLAG_MUTUAL_M2L = 1u << 6,    /* FP64 precision: the mutual interaction
+                                        (Sec. 4) for M2L: each pair listed in
+                                        both directions is evaluated once for
+                                        both cells, with one set of irregular
+                                        harmonics (the reverse direction takes
+                                        the sign flip of the odd terms), both
+                                        cells' locals added with FP64 atomics;
+                                        M2L then runs per pair rather than
+                                        over the class tables */
+    FMM_FLAG_MUTUAL_P2P = 1u << 7,    /* FP64 precision: the mutual interaction
+                                        for P2P: each leaf pair listed in both
+                                        directions is evaluated once for both
+                                        leaves (one distance and inverse square
+                                        root per particle pair), both leaves'
+                                        sums added with FP64 atomics */
+    FMM_FLAG_MUTUAL = (1u << 6) | (1u << 7) /* both.  Neither is allowed with
+                                        FMM_PREC_MIXED or FMM_FLAG_DETERMINISTIC
                                         (FMM_ERR_INVALID_ARG at fmm_create);
                                         fmm_backward is unchanged */
 };
@@ -197,8 +202,8 @@ fmm_status fmm_evaluate_noalloc(fmm_plan *plan, double *phi, double *field, doub
  * Adjoint: gradient of the FMM total energy, sum_k g_k E_k with
  * E_k = 1/2 q_k^T A q_k, with respect to positions and charges, where A is
  * the matrix the FMM applies (P2M, M2M, M2L, L2L, L2P and P2P over the built
- * lists; not symmetric, since the M2L lists are not, Sec. 4: FMM_FLAG_MUTUAL
- * evaluates the same pairs).  Computed exactly
+ * lists; not symmetric, since the M2L lists are not, Sec. 4: the mutual
+ * flags evaluate the same pairs).  Computed exactly
  * for that A, in the plan's precision: with w = g q and psi = A^T w (a
  * transposed evaluation: L2P^T, L2L^T, M2L^T, P2P^T, M2M^T, P2M^T),
  *   grad_q_i   = (g_i phi_i + psi_i) / 2
@@ -270,8 +275,9 @@ fmm_status fmm_get_build_info(const fmm_plan *plan, int64_t *full_builds, int64_
  * paper's granularity knob, Sec. 5), the operator classes in use, and the
  * M2L pairs left to the per-pair FP64 kernel.  The FP64 path reports the
  * same class tables, which its FP64 matrix-core M2L runs over for p <= 12
- * (no P2P tasks; every count is 0 above p = 12 and with FMM_FLAG_MUTUAL,
- * whose M2L runs per pair).  Before a build: FMM_ERR_STATE.
+ * (no P2P tasks; every count is 0 above p = 12 and with
+ * FMM_FLAG_MUTUAL_M2L, whose M2L runs per pair).  Before a build:
+ * FMM_ERR_STATE.
  */
 fmm_status fmm_get_queue_info(const fmm_plan *plan, int64_t *ntarget, int64_t *ngroup, int64_t *ntask,
                               int64_t *nclass, int64_t *nextra);

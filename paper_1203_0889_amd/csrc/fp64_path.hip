@@ -333,11 +333,12 @@ __host__ __device__ constexpr int m2l_pairs_lds_mutual_doubles(int p, bool mutua
     return m2l_pairs_lds_doubles(p) + (mutual ? 2 * (p + 1) * (p + 1) : 0);
 }
 
-template <bool kAdjoint, bool kMutual>
+// The adjoint per pair (the order a launch argument): owner = the forward
+// pair's source B, Out its dual multipole.
 __global__ void __launch_bounds__(kM2L64Threads)
-    k_m2l_pairs(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
-                int64_t npair, const double *__restrict__ In, double *__restrict__ Out, int owner_mode) {
-    static_assert(!(kAdjoint && kMutual), "the mutual variant is forward only");
+    k_m2l_pairs_adj(CellArrays c, int32_t ncell, int p, const int32_t *__restrict__ ptr,
+                    const int32_t *__restrict__ src, int64_t npair, const double *__restrict__ In,
+                    double *__restrict__ Out, int owner_mode) {
     extern __shared__ double lds[];
     const int NJ = (2 * p + 1) * (2 * p + 1), NM = (p + 1) * (p + 1);
     const int P = ncoef(p);
@@ -347,10 +348,8 @@ __global__ void __launch_bounds__(kM2L64Threads)
     // (owner mode keeps one stream: one owner's pairs in list order)
     const int H = m2l_pairs_streams(p, owner_mode != 0), W = 64 / H;
     const int h = threadIdx.x / W, lane = threadIdx.x - h * W;
-    double *base = lds + h * m2l_pairs_lds_mutual_doubles(p, kMutual);
+    double *base = lds + h * m2l_pairs_lds_doubles(p);
     double *Jre = base, *Jim = base + NJ, *Mre = base + 2 * NJ, *Mim = base + 2 * NJ + NM;
-    // mutual: the owner's multipole (the reverse pair's source)
-    double *Are = base + 2 * NJ + 2 * NM, *Aim = base + 2 * NJ + 3 * NM;
     // this lane's outputs: complex index j = lane, lane + W, lane + 2 W
     int on[3], om[3];
     for (int s = 0; s < 3; s++) {
@@ -389,7 +388,6 @@ __global__ void __launch_bounds__(kM2L64Threads)
         }
         const bool any = e0 + h < e1;   // this stream has a pair in the chunk
         double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
-        double revr[3] = {0, 0, 0}, revi[3] = {0, 0, 0};   // mutual: the reverse pair's sums
         auto flush = [&](int32_t owner) {
             double *out = Out + (int64_t)owner * P;
             for (int s = 0; s < 3; s++) {
@@ -397,7 +395,7 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 if (n < 0) continue;
                 const int m = om[s];
                 double vr = accr[s];
-                if (kAdjoint && m == 0) vr *= 0.5;
+                if (m == 0) vr *= 0.5;
                 if (owner_mode) {   // the only wave writing this owner
                     out[cidx_re(n, m)] += vr;
                     if (m > 0) out[cidx_im(n, m)] += acci[s];
@@ -412,20 +410,13 @@ __global__ void __launch_bounds__(kM2L64Threads)
         const int64_t rounds = (e1 - e0 + H - 1) / H;
         for (int64_t t = 0; t < rounds; t++) {
             const int64_t e = e0 + h + H * t;
-            bool act = e < e1;
+            const bool act = e < e1;
             if (act && e >= ptr[O + 1]) {
                 flush(O);
                 while (e >= ptr[O + 1]) O++;
             }
             const int32_t other = act ? src[e] : src[e0];
-            const int32_t A = kAdjoint ? other : O, B = kAdjoint ? O : other;
-            bool mutual = false;
-            if (kMutual && act) {
-                // the same (O, other) on every lane of the stream
-                const bool both = listed(ptr, src, other, O);
-                if (both && other < O) act = false;   // evaluated at the entry owned by other
-                mutual = both && other > O;
-            }
+            const int32_t A = other, B = O;   // the forward pair A <- B
             const int la = c.level[A], lb = c.level[B];
             const int64_t SA = (int64_t)1 << (kLevels - la), SB = (int64_t)1 << (kLevels - lb);
             // rho in units of the target side: (C_A - C_B) / (2 S_A), exact
@@ -454,19 +445,6 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 }
                 Mre[i] = re;
                 Mim[i] = im;
-                if (kMutual && mutual) {
-                    const double *y = In + (int64_t)O * P;
-                    double are = y[cidx_re(k, al)], aim = al > 0 ? y[cidx_im(k, al)] : 0.0;
-                    if (l < 0) {
-                        aim = -aim;
-                        if (al & 1) {
-                            are = -are;
-                            aim = -aim;
-                        }
-                    }
-                    Are[i] = are;
-                    Aim[i] = aim;
-                }
             }
             if (act && lane <= 2 * p) {
                 // column m of the harmonics, and its mirror J_n^(-m) =
@@ -516,59 +494,7 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 if (n < 0) continue;
                 const int m = om[s];
                 double sr = 0, si = 0;
-                if (kMutual && mutual) {
-                    // forward and reverse over the same harmonics
-                    double qr = 0, qi = 0;
-                    for (int k = 0; k <= p; k++) {
-                        const double fk = ldexp(1.0, delta * k);
-                        const int nn = n + k, mb = k * k + k, jb = nn * nn + nn + m;
-                        double tr = 0, ti = 0, ur = 0, ui = 0;
-                        for (int l = -k; l <= k; l++) {
-                            const double jre = Jre[jb + l], jim = Jim[jb + l];
-                            const double mre = Mre[mb + l], mim = Mim[mb + l];
-                            const double are = Are[mb + l], aim = Aim[mb + l];
-                            tr += mre * jre - mim * jim;
-                            ti += mre * jim + mim * jre;
-                            ur += are * jre - aim * jim;
-                            ui += are * jim + aim * jre;
-                        }
-                        sr += fk * tr;
-                        si += fk * ti;
-                        if (k & 1) {
-                            qr -= ur;
-                            qi -= ui;
-                        } else {
-                            qr += ur;
-                            qi += ui;
-                        }
-                    }
-                    if (n & 1) {
-                        sr = -sr;
-                        si = -si;
-                    }
-                    const double fo = ldexp(1.0, delta * (n + 1));
-                    revr[s] = fo * qr;
-                    revi[s] = fo * qi;
-                } else if (!kAdjoint) {
-                    // S_n^m = sum_k 2^(delta k) sum_l M_k^l J_(n+k)^(m+l)
-                    for (int k = 0; k <= p; k++) {
-                        const double fk = ldexp(1.0, delta * k);
-                        const int nn = n + k, mb = k * k + k, jb = nn * nn + nn + m;
-                        double tr = 0, ti = 0;
-                        for (int l = -k; l <= k; l++) {
-                            const double mre = Mre[mb + l], mim = Mim[mb + l];
-                            const double jre = Jre[jb + l], jim = Jim[jb + l];
-                            tr += mre * jre - mim * jim;
-                            ti += mre * jim + mim * jre;
-                        }
-                        sr += fk * tr;
-                        si += fk * ti;
-                    }
-                    if (n & 1) {
-                        sr = -sr;
-                        si = -si;
-                    }
-                } else {
+                {
                     // output (k, l) = (n, m) of this lane; inputs (nu, mu) of the dual
                     const int k = n, l = m;
                     const double fk = ldexp(1.0, delta * k);
@@ -592,8 +518,247 @@ __global__ void __launch_bounds__(kM2L64Threads)
                 accr[s] += sr;
                 acci[s] += si;
             }
+        }
+        if (any) flush(O);
+    }
+}
+
+// The forward per-pair M2L with the order a compile-time constant, harmonics
+// and multipoles stored as complex pairs (one 16-byte LDS read per
+// coefficient) and the sums over the input coefficients unrolled: for an
+// output (n, m) and input degree k both operands of the inner sum are
+// contiguous, J_(n+k)^(m+l) and M_k^l for l = -k..k.  With kMutual (balanced
+// mode only) a pair listed in both directions is evaluated once, at the
+// entry whose owner A has the smaller index, the reverse pair B <- A reusing
+// the harmonics of A <- B as described above; its sums go to B with FP64
+// atomics after every pair.
+template <int PP, bool kMutual>
+__global__ void __launch_bounds__(kM2L64Threads)
+    k_m2l_pairs_fwd(CellArrays c, int32_t ncell, const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                    int64_t npair, const double *__restrict__ In, double *__restrict__ Out, int owner_mode) {
+    extern __shared__ double2 lds2[];
+    constexpr int p = PP;
+    constexpr int NJ = (2 * p + 1) * (2 * p + 1), NM = (p + 1) * (p + 1);
+    constexpr int P = ncoef(p);
+    constexpr int NC = (p + 1) * (p + 2) / 2;
+    constexpr int NS = NJ + (kMutual ? 2 : 1) * NM;   // complex entries per stream
+    static_assert(m2l_pairs_lds_mutual_doubles(p, kMutual) == 2 * NS, "LDS layout");
+    const int H = m2l_pairs_streams(p, owner_mode != 0), W = 64 / H;
+    const int h = threadIdx.x / W, lane = threadIdx.x - h * W;
+    double2 *J = lds2 + h * NS;   // J_n^m at n^2 + n + m, |m| <= n <= 2p
+    double2 *Mc = J + NJ;         // M_k^l of the source at k^2 + k + l, |l| <= k <= p
+    double2 *Ac = Mc + NM;        // mutual: the owner's multipole, same layout
+    int on[3], om[3];
+    for (int s = 0; s < 3; s++) {
+        int j = lane + W * s;
+        on[s] = -1;
+        om[s] = 0;
+        if (j < NC) {
+            int n = 0;
+            while ((n + 1) * (n + 2) / 2 <= j) n++;
+            on[s] = n;
+            om[s] = j - n * (n + 1) / 2;
+        }
+    }
+    const int64_t nchunk = (npair + kPairChunk - 1) / kPairChunk;
+    const int64_t nunit = owner_mode ? (int64_t)ncell : nchunk;
+    for (int64_t ch = blockIdx.x; ch < nunit; ch += gridDim.x) {
+        int64_t e0, e1;
+        int32_t O;
+        if (owner_mode) {
+            O = (int32_t)ch;
+            e0 = ptr[O];
+            e1 = ptr[O + 1];
+            if (e0 == e1) continue;   // uniform over the wave
+        } else {
+            e0 = ch * kPairChunk;
+            e1 = e0 + kPairChunk < npair ? e0 + kPairChunk : npair;
+            const int64_t ef = e0 + h < e1 ? e0 + h : e0;
+            int32_t lo = 0, hi = ncell;
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (ptr[mid] <= ef) lo = mid; else hi = mid - 1;
+            }
+            O = lo;
+        }
+        const bool any = e0 + h < e1;
+        double accr[3] = {0, 0, 0}, acci[3] = {0, 0, 0};
+        double revr[3] = {0, 0, 0}, revi[3] = {0, 0, 0};   // mutual: the reverse pair's sums
+        auto flush = [&](int32_t owner) {
+            double *out = Out + (int64_t)owner * P;
+            for (int s = 0; s < 3; s++) {
+                const int n = on[s];
+                if (n < 0) continue;
+                const int m = om[s];
+                if (owner_mode) {
+                    out[cidx_re(n, m)] += accr[s];
+                    if (m > 0) out[cidx_im(n, m)] += acci[s];
+                } else {
+                    atomicAdd(&out[cidx_re(n, m)], accr[s]);
+                    if (m > 0) atomicAdd(&out[cidx_im(n, m)], acci[s]);
+                }
+                accr[s] = acci[s] = 0.0;
+            }
+        };
+        const int64_t rounds = (e1 - e0 + H - 1) / H;
+        for (int64_t t = 0; t < rounds; t++) {
+            const int64_t e = e0 + h + H * t;
+            bool act = e < e1;
+            if (act && e >= ptr[O + 1]) {
+                flush(O);
+                while (e >= ptr[O + 1]) O++;
+            }
+            const int32_t B = act ? src[e] : src[e0];
+            const int32_t A = O;
+            bool mutual = false;
+            if (kMutual && act) {
+                // the same (A, B) on every lane of the stream
+                const bool both = listed(ptr, src, B, A);
+                if (both && B < A) act = false;   // evaluated at the entry owned by B
+                mutual = both && B > A;
+            }
+            const int la = c.level[A], lb = c.level[B];
+            const int64_t SA = (int64_t)1 << (kLevels - la), SB = (int64_t)1 << (kLevels - lb);
+            const double rx = ldexp((double)((2 * (int64_t)c.ix[A] + 1) * SA - (2 * (int64_t)c.ix[B] + 1) * SB),
+                                    -(kLevels - la + 1));
+            const double ry = ldexp((double)((2 * (int64_t)c.iy[A] + 1) * SA - (2 * (int64_t)c.iy[B] + 1) * SB),
+                                    -(kLevels - la + 1));
+            const double rz = ldexp((double)((2 * (int64_t)c.iz[A] + 1) * SA - (2 * (int64_t)c.iz[B] + 1) * SB),
+                                    -(kLevels - la + 1));
+            const int delta = la - lb;
+            __syncthreads();   // the previous pair's readers are done
+            for (int i = lane; act && i < NM; i += W) {
+                int k = 0;
+                while ((k + 1) * (k + 1) <= i) k++;
+                const int l = i - k * k - k, al = l < 0 ? -l : l;
+                const double *x = In + (int64_t)B * P;
+                double re = x[cidx_re(k, al)], im = al > 0 ? x[cidx_im(k, al)] : 0.0;
+                if (l < 0) {
+                    im = -im;
+                    if (al & 1) {
+                        re = -re;
+                        im = -im;
+                    }
+                }
+                Mc[i] = make_double2(re, im);
+                if (kMutual && mutual) {
+                    const double *y = In + (int64_t)A * P;
+                    double are = y[cidx_re(k, al)], aim = al > 0 ? y[cidx_im(k, al)] : 0.0;
+                    if (l < 0) {
+                        aim = -aim;
+                        if (al & 1) {
+                            are = -are;
+                            aim = -aim;
+                        }
+                    }
+                    Ac[i] = make_double2(are, aim);
+                }
+            }
+            if (act && lane <= 2 * p) {
+                const int m = lane;
+                const double sg = (m & 1) ? -1.0 : 1.0;
+                const double r2 = rx * rx + ry * ry + rz * rz;
+                const double ir2 = 1.0 / r2;
+                double mr = 1.0 / sqrt(r2), mi = 0.0;   // I_m^m
+                for (int j = 1; j <= m; j++) {
+                    const double f = (2 * j - 1) * ir2;
+                    const double nr = (mr * rx - mi * ry) * f, ni = (mr * ry + mi * rx) * f;
+                    mr = nr;
+                    mi = ni;
+                }
+                auto put = [&](int n, double re, double im) {
+                    J[n * n + n + m] = make_double2(re, im);
+                    if (m > 0) J[n * n + n - m] = make_double2(sg * re, -sg * im);
+                };
+                put(m, mr, mi);
+                double pr = 0, pi = 0, cr = mr, ci = mi;
+                for (int n = m + 1; n <= 2 * p; n++) {
+                    double nr, ni;
+                    if (n == m + 1) {
+                        const double f = (2 * m + 1) * rz * ir2;
+                        nr = f * cr;
+                        ni = f * ci;
+                    } else {
+                        const double aa = (2 * n - 1) * rz, bb = (double)((n - 1) * (n - 1) - m * m);
+                        nr = (aa * cr - bb * pr) * ir2;
+                        ni = (aa * ci - bb * pi) * ir2;
+                    }
+                    put(n, nr, ni);
+                    pr = cr;
+                    pi = ci;
+                    cr = nr;
+                    ci = ni;
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int s = 0; s < 3; s++) {
+                const int n = on[s];
+                if (!act || n < 0) continue;
+                const int m = om[s];
+                // S_n^m = sum_k 2^(delta k) sum_l M_k^l J_(n+k)^(m+l); with
+                // |m| <= n and |l| <= k every J index lies in row n + k <= 2p
+                double sr = 0, si = 0;
+                if (kMutual && mutual) {
+                    // and the reverse R_n^m = sum_k (-1)^k sum_l A_k^l J_(n+k)^(m+l)
+                    double qr = 0, qi = 0;
+#pragma unroll
+                    for (int k = 0; k <= p; k++) {
+                        const int nn = n + k;
+                        const double2 *jr = J + (nn * nn + nn + m);
+                        const double2 *mk = Mc + (k * k + k);
+                        const double2 *ak = Ac + (k * k + k);
+                        double tr = 0, ti = 0, ur = 0, ui = 0;
+#pragma unroll
+                        for (int l = -k; l <= k; l++) {
+                            const double2 jv = jr[l], mv = mk[l], av = ak[l];
+                            tr = fma(mv.x, jv.x, tr);
+                            tr = fma(-mv.y, jv.y, tr);
+                            ti = fma(mv.x, jv.y, ti);
+                            ti = fma(mv.y, jv.x, ti);
+                            ur = fma(av.x, jv.x, ur);
+                            ur = fma(-av.y, jv.y, ur);
+                            ui = fma(av.x, jv.y, ui);
+                            ui = fma(av.y, jv.x, ui);
+                        }
+                        const double fk = ldexp(1.0, delta * k);
+                        sr = fma(fk, tr, sr);
+                        si = fma(fk, ti, si);
+                        qr += (k & 1) ? -ur : ur;
+                        qi += (k & 1) ? -ui : ui;
+                    }
+                    const double fo = ldexp(1.0, delta * (n + 1));
+                    revr[s] = fo * qr;
+                    revi[s] = fo * qi;
+                } else {
+#pragma unroll
+                    for (int k = 0; k <= p; k++) {
+                        const int nn = n + k;
+                        const double2 *jr = J + (nn * nn + nn + m);
+                        const double2 *mk = Mc + (k * k + k);
+                        double tr = 0, ti = 0;
+#pragma unroll
+                        for (int l = -k; l <= k; l++) {
+                            const double2 mv = mk[l], jv = jr[l];
+                            tr = fma(mv.x, jv.x, tr);
+                            tr = fma(-mv.y, jv.y, tr);
+                            ti = fma(mv.x, jv.y, ti);
+                            ti = fma(mv.y, jv.x, ti);
+                        }
+                        const double fk = ldexp(1.0, delta * k);
+                        sr = fma(fk, tr, sr);
+                        si = fma(fk, ti, si);
+                    }
+                }
+                if (n & 1) {
+                    sr = -sr;
+                    si = -si;
+                }
+                accr[s] += sr;
+                acci[s] += si;
+            }
             if (kMutual && mutual) {
-                double *out = Out + (int64_t)other * P;
+                double *out = Out + (int64_t)B * P;
                 for (int s = 0; s < 3; s++) {
                     const int n = on[s];
                     if (n < 0) continue;
@@ -620,15 +785,27 @@ void launch_pairs(bool adjoint, Geometry g, int32_t ncell, int p, const int32_t 
     const int om = owner_mode ? 1 : 0;
     const size_t lds =
         (size_t)m2l_pairs_streams(p, owner_mode) * m2l_pairs_lds_mutual_doubles(p, mutual) * sizeof(double);
-    if (adjoint)
-        hipLaunchKernelGGL((k_m2l_pairs<true, false>), dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr,
-                           src, npair, In, Out, om);
-    else if (mutual)
-        hipLaunchKernelGGL((k_m2l_pairs<false, true>), dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr,
-                           src, npair, In, Out, om);
-    else
-        hipLaunchKernelGGL((k_m2l_pairs<false, false>), dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr,
-                           src, npair, In, Out, om);
+    if (adjoint) {
+        hipLaunchKernelGGL(k_m2l_pairs_adj, dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, p, ptr, src, npair,
+                           In, Out, om);
+    } else {
+        switch (p) {
+#define FMM_PAIRS(PP)                                                                                             \
+    case PP:                                                                                                      \
+        if (mutual)                                                                                               \
+            hipLaunchKernelGGL((k_m2l_pairs_fwd<PP, true>), dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell, ptr, \
+                               src, npair, In, Out, om);                                                          \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_m2l_pairs_fwd<PP, false>), dim3(grid), dim3(kM2L64Threads), lds, s, g.c, ncell,     \
+                               ptr, src, npair, In, Out, om);                                                     \
+        break;
+            FMM_PAIRS(0) FMM_PAIRS(1) FMM_PAIRS(2) FMM_PAIRS(3) FMM_PAIRS(4) FMM_PAIRS(5) FMM_PAIRS(6)
+            FMM_PAIRS(7) FMM_PAIRS(8) FMM_PAIRS(9) FMM_PAIRS(10) FMM_PAIRS(11) FMM_PAIRS(12) FMM_PAIRS(13)
+            FMM_PAIRS(14) FMM_PAIRS(15) FMM_PAIRS(16)
+#undef FMM_PAIRS
+            default: throw HipError{hipErrorInvalidValue, "per-pair M2L: unsupported order"};
+        }
+    }
     FMM_LAUNCH_CHECK();
 }
 }  // namespace

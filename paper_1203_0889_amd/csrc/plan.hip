@@ -241,7 +241,8 @@ int bits_for(int64_t n) {
 }
 
 bool deterministic(const fmm_plan *p) { return (p->prm.flags & FMM_FLAG_DETERMINISTIC) != 0; }
-bool mutual(const fmm_plan *p) { return (p->prm.flags & FMM_FLAG_MUTUAL) != 0; }
+bool mutual_m2l(const fmm_plan *p) { return (p->prm.flags & FMM_FLAG_MUTUAL_M2L) != 0; }
+bool mutual_p2p(const fmm_plan *p) { return (p->prm.flags & FMM_FLAG_MUTUAL_P2P) != 0; }
 bool cost_reuse(const fmm_plan *p) {
     return (p->prm.flags & FMM_FLAG_COST_REUSE) && p->prm.precision == FMM_PREC_MIXED;
 }
@@ -475,7 +476,7 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         // deterministic or mutual: the whole key (target, source), so that
         // each target's sources come in ascending order whatever order the
         // traversal appended them in; otherwise only the target bits
-        const int lo_bit = deterministic(p) || mutual(p) ? 0 : bits;
+        const int lo_bit = deterministic(p) || mutual_m2l(p) || mutual_p2p(p) ? 0 : bits;
         if (key32)
             fmm::radix_sort_u32((uint32_t *)lists[t], nullptr, (uint32_t *)alts[t], nullptr, cnts[t], lo_bit,
                                 2 * bits, tmps[t], on[t], &in_alt);
@@ -506,7 +507,7 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
         a.p2p_ready = p->p2p_done;   // the P2P leaf order, built on the second stream
         fmm::build_near_far_mixed(p->nf, a, s);
         mark(p, ST_NF_BUILD);
-    } else if (fmm::m2l_f64_supported(p->prm.p) && !mutual(p)) {
+    } else if (fmm::m2l_f64_supported(p->prm.p) && !mutual_m2l(p)) {
         // the FP64 path's M2L runs over the same class tables, on the FP64
         // matrix cores (the mutual M2L runs per pair)
         fmm::build_near_far_mixed(p->nf, nf_args(p), s);
@@ -688,24 +689,24 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     fmm::NearFarArgs a_nf;   // the mixed path's arguments (the P2P tail needs them again)
     bool time_queue = false;  // the queue stage ends at the join (recorded after the tail)
     record(p, ST_M2L);
-    if (p->prm.precision == FMM_PREC_FP64 && mutual(p)) {
-        fmm::launch_m2l_fp64_mutual(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
-                                    p->M.as<double>(), p->L.as<double>(), s);
-        mark(p, ST_M2L);
-        fmm::launch_p2p_fp64_mutual(g, ncell, p->n, p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(),
-                                    p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(), p->qs.as<double>(),
-                                    p->phi_near.as<double>(), p->fld_near.as<double>(), s);
-        mark(p, ST_P2P);
-    } else if (p->prm.precision == FMM_PREC_FP64) {
-        if (p->nf.built && p->nf.f64)
+    if (p->prm.precision == FMM_PREC_FP64) {
+        if (mutual_m2l(p))
+            fmm::launch_m2l_fp64_mutual(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(),
+                                        p->nm2l, p->M.as<double>(), p->L.as<double>(), s);
+        else if (p->nf.built && p->nf.f64)
             fmm::m2l_f64_run(p->nf, nf_args(p), s);
         else
             fmm::launch_m2l_fp64(g, ncell, p->prm.p, p->m2l_ptr.as<int32_t>(), p->m2l_src.as<int32_t>(), p->nm2l,
                                  p->M.as<double>(), p->L.as<double>(), deterministic(p), s);
         mark(p, ST_M2L);
-        fmm::launch_p2p_fp64(g, ncell, p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(), p->xs.as<double>(),
-                             p->ys.as<double>(), p->zs.as<double>(), p->qs.as<double>(), p->phi_near.as<double>(),
-                             p->fld_near.as<double>(), s);
+        if (mutual_p2p(p))
+            fmm::launch_p2p_fp64_mutual(g, ncell, p->n, p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(),
+                                        p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
+                                        p->qs.as<double>(), p->phi_near.as<double>(), p->fld_near.as<double>(), s);
+        else
+            fmm::launch_p2p_fp64(g, ncell, p->p2p_ptr.as<int32_t>(), p->p2p_src.as<int32_t>(), p->xs.as<double>(),
+                                 p->ys.as<double>(), p->zs.as<double>(), p->qs.as<double>(), p->phi_near.as<double>(),
+                                 p->fld_near.as<double>(), s);
         mark(p, ST_P2P);
     } else {
         a_nf = nf_args(p);
@@ -974,12 +975,13 @@ fmm_status check_params(const fmm_params *q, std::string *why) {
     if (q->precision != FMM_PREC_FP64 && q->precision != FMM_PREC_MIXED)
         return *why = "unknown precision", FMM_ERR_INVALID_ARG;
     if (q->flags & ~(uint32_t)(FMM_FLAG_USER_BOX | FMM_FLAG_KEEP_TOPOLOGY | FMM_FLAG_TRACE | FMM_FLAG_DETERMINISTIC |
-                               FMM_FLAG_INCREMENTAL | FMM_FLAG_COST_REUSE | FMM_FLAG_MUTUAL))
+                               FMM_FLAG_INCREMENTAL | FMM_FLAG_COST_REUSE | FMM_FLAG_MUTUAL_M2L |
+                               FMM_FLAG_MUTUAL_P2P))
         return *why = "unknown flag", FMM_ERR_INVALID_ARG;
     if ((q->flags & FMM_FLAG_MUTUAL) && q->precision != FMM_PREC_FP64)
-        return *why = "FMM_FLAG_MUTUAL needs FMM_PREC_FP64", FMM_ERR_INVALID_ARG;
+        return *why = "the mutual flags need FMM_PREC_FP64", FMM_ERR_INVALID_ARG;
     if ((q->flags & FMM_FLAG_MUTUAL) && (q->flags & FMM_FLAG_DETERMINISTIC))
-        return *why = "FMM_FLAG_MUTUAL adds with atomics: not with FMM_FLAG_DETERMINISTIC", FMM_ERR_INVALID_ARG;
+        return *why = "the mutual flags add with atomics: not with FMM_FLAG_DETERMINISTIC", FMM_ERR_INVALID_ARG;
     if ((q->flags & FMM_FLAG_USER_BOX) &&
         !(q->box_side > 0 && std::isfinite(q->box_side) && std::isfinite(q->box_min[0]) &&
           std::isfinite(q->box_min[1]) && std::isfinite(q->box_min[2])))

@@ -28,7 +28,10 @@ FLAG_TRACE = 4
 FLAG_DETERMINISTIC = 8
 FLAG_INCREMENTAL = 16
 FLAG_COST_REUSE = 32
-FLAG_MUTUAL = 64
+FLAG_MUTUAL_M2L = 64
+FLAG_MUTUAL_P2P = 128
+FLAG_MUTUAL = FLAG_MUTUAL_M2L | FLAG_MUTUAL_P2P
+MUTUAL = {False: 0, None: 0, True: FLAG_MUTUAL, "both": FLAG_MUTUAL, "m2l": FLAG_MUTUAL_M2L, "p2p": FLAG_MUTUAL_P2P}
 
 # every symbol include/fmm.h declares
 EXPORTS = ("fmm_default_params", "fmm_create", "fmm_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate",
@@ -160,8 +163,9 @@ class Plan:
             prm.flags |= FLAG_INCREMENTAL
         if cost_reuse:
             prm.flags |= FLAG_COST_REUSE
-        if mutual:
-            prm.flags |= FLAG_MUTUAL
+        if mutual not in MUTUAL:
+            raise ValueError("mutual must be False, True, 'both', 'm2l' or 'p2p'")
+        prm.flags |= MUTUAL[mutual]   # FP64: the mutual interaction for M2L, P2P or both
         self.params = prm
         if device is None:
             device = torch.cuda.current_device()

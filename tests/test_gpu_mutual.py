@@ -1,7 +1,9 @@
-"""The mutual interaction (FMM_FLAG_MUTUAL, FP64 path): every M2L and P2P
-pair listed in both directions is evaluated once for both cells; the
-reverse M2L reuses the forward pair's harmonics with the sign flip of the
-odd terms and a power-of-two level scaling.  In exact arithmetic it computes
+"""The mutual interaction (FP64 path; FMM_FLAG_MUTUAL = FMM_FLAG_MUTUAL_M2L |
+FMM_FLAG_MUTUAL_P2P): every M2L and P2P pair listed in both directions is
+evaluated once for both cells (the pairs of one stage only with one of the
+two flags); the reverse M2L reuses the forward pair's harmonics with the
+sign flip of the odd terms and a power-of-two level scaling.  In exact
+arithmetic it computes
 the same function as the non-mutual FMM (same tree, lists, centres and
 degrees), so the bound against the oracle FMM is the FP64 path's: 1e-11
 relative L2 plus the per-particle checks; against the non-mutual GPU path
@@ -120,11 +122,35 @@ def test_mutual_repeat_and_rebuild():
     assert maxrel(o3["phi"], ref["phi"]) < 1e-12 and maxrel(o3["field"], ref["field"]) < 1e-12
 
 
+@pytest.mark.parametrize("part", ["m2l", "p2p"])
+@pytest.mark.parametrize("dist,n,seed,p,ncrit,theta", [("plummer", 9001, 5, 10, 32, (2, 5)),
+                                                       ("uniform", 3000, 9, 16, 64, (1, 2))])
+def test_mutual_one_stage(part, dist, n, seed, p, ncrit, theta):
+    # FMM_FLAG_MUTUAL_M2L or FMM_FLAG_MUTUAL_P2P alone (the other stage as
+    # without the flags): the oracle FMM and the non-mutual path
+    pos, q = W.uniform_cube(n, seed) if dist == "uniform" else W.plummer(n, seed)
+    plan, out = run(pos, q, p, ncrit, theta, part)
+    if part == "m2l":
+        assert plan.queue_info()["ntask"] == 0   # M2L per pair: no class tables
+    T = oracle.Tree(pos, ncrit)
+    T.lists(*theta)
+    phi_ref, fld_ref = T.fmm(q, p)
+    e = (rel(out["phi"], phi_ref), rel(out["field"], fld_ref))
+    say(dist, p, "mutual", part, "vs oracle fmm", e)
+    assert max(e) < 1e-11
+    check_fp64(out, phi_ref, fld_ref, leaf_ids(T.perm, T.cells), say, "%s mutual %s" % (dist, part))
+    _, ref = run(pos, q, p, ncrit, theta, False)
+    assert maxrel(out["phi"], ref["phi"]) < 1e-12 and maxrel(out["field"], ref["field"]) < 1e-12
+
+
 def test_mutual_flag_validation():
-    with pytest.raises(fmm.FMMError):
-        fmm.Plan(p=4, precision="mixed", device=0, mutual=True)
-    with pytest.raises(fmm.FMMError):
-        fmm.Plan(p=4, precision="fp64", device=0, mutual=True, deterministic=True)
+    for m in (True, "m2l", "p2p"):
+        with pytest.raises(fmm.FMMError):
+            fmm.Plan(p=4, precision="mixed", device=0, mutual=m)
+        with pytest.raises(fmm.FMMError):
+            fmm.Plan(p=4, precision="fp64", device=0, mutual=m, deterministic=True)
+    with pytest.raises(ValueError):
+        fmm.Plan(p=4, precision="fp64", device=0, mutual="l2l")
 
 
 def test_mutual_small_edge_cases():
