@@ -6,7 +6,8 @@ them one by one.
   uniform 2^20, p = 8, ncrit 64, theta 1/2: mixed and plain FP64 paths
   Plummer 2^22 (equal charges 1/N), p = 10, ncrit 32, theta 2/5: mixed
   Plummer 2^20, p = 8: forward energy and its gradient (fmm_backward)
-  256 instances (N_k log-uniform in [2^10, 2^16]), p = 6: every 16th instance
+  256 instances (N_k log-uniform in [2^10, 2^16]), p = 6: every instance,
+  in full when N_k <= 8192, else on a 1024-particle sample
 
 Bounds: the relative L2 error of the sample under the benchmark metric's
 1e-4 (the p = 6 batch: 1e-4 as well; measured 5e-6), and no sampled
@@ -103,10 +104,10 @@ def test_batch256_p6():
     plan.upward()
     out = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
     torch.cuda.synchronize()
-    for k in range(0, 256, 16):
+    for k in range(256):
         lo, hi = offs[k], offs[k + 1]
         nk = hi - lo
-        tg = np.arange(nk) if nk <= 4096 else W.error_sample(nk, 24 + k, 1024)
+        tg = np.arange(nk) if nk <= 8192 else W.error_sample(nk, 24 + k, 1024)
         pd, fd = oracle.direct(pos[lo:hi], q[lo:hi], tg)
         check_sample("batch instance %d (N %d)" % (k, nk), out["phi"][lo:hi][tg], out["field"][lo:hi][tg], pd, fd,
                      1e-4)
