@@ -63,7 +63,7 @@ def check_sample(label, got_phi, got_fld, ref_phi, ref_fld, tol):
 @pytest.mark.parametrize("precision,tol", [("mixed", 1e-4), ("fp64", 1e-5)])
 def test_uniform1m_p8(precision, tol):
     pos, q, w, plan, out = solve("uniform1m_p8", precision)
-    tg = W.error_sample(len(q), 21, 2048)
+    tg = W.error_sample(len(q), 21, 4096)
     pd, fd = oracle.direct(pos, q, tg)
     check_sample("uniform1m_p8 " + precision, out["phi"][tg], out["field"][tg], pd, fd, tol)
     assert out["energy"][0] == pytest.approx(0.5 * np.dot(q, out["phi"]), rel=1e-12)
@@ -73,7 +73,7 @@ def test_uniform1m_p8(precision, tol):
 def test_plummer4m_p10_equal_charges():
     pos, q, w, plan, out = solve("plummer4m_p10")
     assert np.all(q == q[0])
-    tg = W.error_sample(len(q), 22, 1024)
+    tg = W.error_sample(len(q), 22, 4096)
     pd, fd = oracle.direct(pos, q, tg)
     check_sample("plummer4m_p10", out["phi"][tg], out["field"][tg], pd, fd, 1e-4)
 
@@ -82,7 +82,7 @@ def test_plummer1m_p8_energy_gradient():
     pos, q, w, plan, out = solve("plummer1m_p8")
     gp, gq = plan.backward(dev(np.ones(1)))
     gp, gq = gp.cpu().numpy(), gq.cpu().numpy()
-    tg = W.error_sample(len(q), 23, 2048)
+    tg = W.error_sample(len(q), 23, 4096)
     pd, fd = oracle.direct(pos, q, tg)
     check_sample("plummer1m_p8 forward", out["phi"][tg], out["field"][tg], pd, fd, 1e-4)
     # dE/dq_i = phi_i and dE/dx_i = -q_i E_i of the exact (symmetric) sum
