@@ -1,7 +1,8 @@
 // The plain FP64 GPU path of the two dominant stages (Sec. 2.1: M2L and P2P
-// take most of the time).  Target-owned: each workgroup owns one target cell
-// and walks its CSR list, so no two workgroups write the same data (the
-// non-mutual interaction of Sec. 4).  This path is the accuracy anchor and
+// take most of the time).  By default target-owned: each workgroup owns one
+// target cell and walks its CSR list, so no two workgroups write the same
+// data (the non-mutual interaction of Sec. 4); the mutual variants write
+// both cells of a pair, with atomics.  This path is the accuracy anchor and
 // the baseline the mixed-precision work queue is measured against.
 #include "tree.h"
 
@@ -229,7 +230,7 @@ __global__ void __launch_bounds__(kP2P64Threads)
                     double dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
                     double r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 > 0.0) {
-                        double inv = rsqrt(r2);
+                        double inv = rsqrt_fp64(r2);
                         double inv2 = inv * inv;
                         double qi = sq[j] * inv;
                         double qi3 = qi * inv2;
