@@ -306,10 +306,13 @@ fmm_status fmm_copy_lists(const fmm_plan *plan, int64_t *m2l_ptr, int32_t *m2l_s
 
 /*
  * Tuning knobs of the work queue and kernels (an autotuner fills them).
- * Results do not depend on them, only speed.
+ * Results change only within rounding (the M2L sums of a task follow the
+ * task size) or not at all (the launch shape).
  */
 typedef struct {
-    int32_t m2l_task_entries; /* M2L class entries per work-queue task (1..128) */
+    int32_t m2l_task_entries; /* M2L class entries per work-queue task (1..128; default
+                                 128 with FMM_PREC_MIXED, 32 with FMM_PREC_FP64, whose
+                                 matrix-core M2L runs its tasks as one plain launch) */
     int32_t grid_per_cu;      /* persistent work-queue workgroups per compute unit (1..8) */
     int32_t p2p_per_cu;       /* P2P-only workgroups per compute unit launched beside the
                                  work queue on a second stream of the plan (0..8); with 0

@@ -71,6 +71,9 @@ struct NearFarState {
 };
 
 fmm_tuning default_tuning();
+// M2L class entries per task of the FP64 path's matrix-core M2L by default
+// (one plain launch over its tasks, so smaller tasks than the work queue's)
+constexpr int kFp64TaskEntries = 32;
 // Build-time part (after the lists): classes, operators, groups, tasks.
 void build_near_far_mixed(NearFarState &st, const NearFarArgs &a, hipStream_t s);
 // The P2P leaf order and the cell centres (needs only the tree and the P2P

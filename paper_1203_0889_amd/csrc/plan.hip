@@ -1021,6 +1021,9 @@ fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fm
     p->device = device;
     p->stream = (hipStream_t)hip_stream;
     p->tuning = fmm::default_tuning();
+    // the FP64 matrix-core M2L runs its tasks as one plain launch (no queue
+    // to balance them): smaller tasks fill the chip more evenly
+    if (params->precision == FMM_PREC_FP64) p->tuning.m2l_task_entries = fmm::kFp64TaskEntries;
     if (hipSetDevice(device) != hipSuccess) {
         delete p;
         return FMM_ERR_DEVICE;

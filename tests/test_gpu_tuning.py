@@ -50,6 +50,13 @@ def test_autotune_fp64_reports_no_queue():
     assert ms == -1.0
 
 
+def test_default_task_size_by_precision():
+    # the FP64 path's matrix-core M2L runs its tasks as one plain launch and
+    # takes smaller tasks by default than the mixed path's work queue
+    assert fmm.Plan(p=4, precision="fp64", device=0).get_tuning()["m2l_task_entries"] == 32
+    assert fmm.Plan(p=4, precision="mixed", device=0).get_tuning()["m2l_task_entries"] == 128
+
+
 def test_tuning_validation():
     plan = fmm.Plan(p=4, precision="mixed", device=0)
     with pytest.raises(fmm.FMMError):
