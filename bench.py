@@ -441,6 +441,25 @@ def run_batch(a, torch, fmm, W):
         plan.graph_launch()
     torch.cuda.synchronize()
     graph_ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    # a whole step in one graph on a kept topology (rebuild from the
+    # positions and charges through the stored permutation, upward,
+    # evaluate): a second plan with FMM_FLAG_KEEP_TOPOLOGY
+    kplan = fmm.Plan(p=p, ncrit=ncrit, theta=theta, precision=a.precision, device=0, keep_topology=True)
+    kplan.set_tuning(**tuning)
+    kplan.build_tree(dpos, dq, offs)
+    kphi, kfield = torch.empty_like(phi), torch.empty_like(field)
+    kenergy = torch.empty_like(energy)
+    kplan.graph_capture_step(dpos, dq, phi=kphi, field=kfield, energy=kenergy)
+    for _ in range(a.warmup):
+        kplan.graph_launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        kplan.graph_launch()
+    torch.cuda.synchronize()
+    step_graph_ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    kplan.sync()
+    del kplan
     # 256 sequential single-instance solves (same tuning), one warm pass first
     singles = [fmm.Plan(p=p, ncrit=ncrit, theta=theta, precision=a.precision, device=0) for _ in range(n_inst)]
     for s_ in singles:
@@ -461,8 +480,8 @@ def run_batch(a, torch, fmm, W):
     sequential()
     torch.cuda.synchronize()
     seq_ms = (time.perf_counter() - t0) * 1e3
-    print("bench: batched %.3f ms, graph replay %.3f ms, sequential %.3f ms" % (ms, graph_ms, seq_ms),
-          file=sys.stderr, flush=True)
+    print("bench: batched %.3f ms, graph replay %.3f ms, step graph (kept topology) %.3f ms, sequential %.3f ms"
+          % (ms, graph_ms, step_graph_ms, seq_ms), file=sys.stderr, flush=True)
     result = base_result(a, n / (ms * 1e-3), ms, "particles/s, 256 instances solved as one batch (sum N_k / time)")
     result["config"] = {"workload": "batch256_p6", "n": n, "instances": n_inst, "p": p, "ncrit": ncrit,
                         "theta": "1/2", "precision": a.precision, "distribution": "even k uniform, odd k Plummer"}
@@ -472,6 +491,8 @@ def run_batch(a, torch, fmm, W):
     result["roofline"] = roof
     result["sequential"] = {"ms": seq_ms, "particles_per_s": n / (seq_ms * 1e-3), "speedup_of_batch": seq_ms / ms}
     result["graph_replay_upward_evaluate"] = {"ms": graph_ms, "particles_per_s": n / (graph_ms * 1e-3)}
+    result["graph_replay_kept_topology_step"] = {"ms": step_graph_ms,
+                                                 "particles_per_s": n / (step_graph_ms * 1e-3)}
     if not a.no_error:
         result["error"] = cpu_leg_error_batch(pos, q, offs, phi, field)
     return result

@@ -182,6 +182,44 @@ def test_step_graph_replays(prec):
         plan.graph_launch()
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_step_graph_batch(prec):
+    """A batch of instances in one step graph (kept topology): every replay
+    with new positions and charges equals, bit for bit, an eager step of a
+    second plan (deterministic mode), per-instance energies included."""
+    pos0, q0, offsets = W.batch(6, 17)
+    offs = [int(o) for o in offsets]
+    n = len(q0)
+    say("step graph batch", prec, "N", n)
+    kw = dict(p=6, ncrit=64, theta=(1, 2), precision=prec, device=0, keep_topology=True, deterministic=True)
+    plan, ref_plan = fmm.Plan(**kw), fmm.Plan(**kw)
+    plan.build_tree(dev(pos0), dev(q0), offs)
+    ref_plan.build_tree(dev(pos0), dev(q0), offs)
+    pos_t, q_t = dev(pos0), dev(q0)
+    out = {"phi": torch.empty(n, dtype=torch.float64, device="cuda"),
+           "field": torch.empty((n, 3), dtype=torch.float64, device="cuda"),
+           "energy": torch.empty(6, dtype=torch.float64, device="cuda")}
+    plan.graph_capture_step(pos_t, q_t, **out)
+    rng = np.random.default_rng(3)
+    for k in range(3):
+        pos = pos0 + 1e-4 * rng.standard_normal(pos0.shape)
+        q = q0 * (1.0 + 0.1 * k)
+        pos_t.copy_(dev(pos))
+        q_t.copy_(dev(q))
+        for t in out.values():
+            t.zero_()
+        torch.cuda.synchronize()
+        plan.graph_launch()
+        plan.sync()
+        got = host(out)
+        ref_plan.build_tree(dev(pos), dev(q), offs)
+        ref_plan.upward()
+        ref = host(ref_plan.evaluate())
+        for name in ("phi", "field", "energy"):
+            assert np.array_equal(got[name], ref[name]), (k, name)
+        other_work()
+
+
 def test_step_graph_needs_a_kept_topology():
     pos, q = W.uniform_cube(2000, 86)
     plan = fmm.Plan(p=4, ncrit=32, theta=(1, 2), precision="mixed", device=0)
