@@ -336,12 +336,13 @@ def run_single(a, torch, fmm, W):
     if a.tuning:
         plan.set_tuning(**fixed_tuning(a.tuning))
         tuning = plan.get_tuning()
-    elif not a.no_autotune and a.precision == "mixed":
-        # set-up, not timed: pick the work-queue setting on this workload
+    elif not a.no_autotune:
+        # set-up, not timed: pick the work-queue setting (FP64: the task
+        # size of its matrix-core M2L) on this workload
         plan.build_tree(dpos, dq)
         plan.upward()
         tuning, tq_ms = plan.autotune(repeats=2)
-        print("bench: autotuned %s (queue %.3f ms)" % (tuning, tq_ms), file=sys.stderr, flush=True)
+        print("bench: autotuned %s (evaluation %.3f ms)" % (tuning, tq_ms), file=sys.stderr, flush=True)
 
     ev = [torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
 

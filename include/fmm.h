@@ -345,7 +345,10 @@ fmm_status fmm_set_tuning(fmm_plan *plan, const fmm_tuning *tuning);
  * the tables with it.  Outputs (host, may be NULL): the chosen tuning and
  * its time in ms.  Leaves the plan as after fmm_upward (call
  * fmm_evaluate again); drops a captured graph.  The FP64 path has no queue:
- * the call then only reports the current tuning and time -1.
+ * it times m2l_task_entries in {16, 32, 64, 128} for its matrix-core M2L
+ * over the class tables (the other fields kept); where its M2L runs per
+ * pair (p > 12, FMM_FLAG_MUTUAL_M2L) the call only reports the current
+ * tuning and time -1.
  */
 fmm_status fmm_autotune(fmm_plan *plan, int32_t repeats, fmm_tuning *best, double *best_ms);
 

@@ -1402,7 +1402,10 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
     if (!p) return FMM_ERR_INVALID_ARG;
     if (repeats < 1) return fail(p, FMM_ERR_INVALID_ARG, "repeats must be >= 1");
     if (p->state < kStateUp) return fail(p, FMM_ERR_STATE, "fmm_autotune before fmm_upward");
-    if (p->prm.precision != FMM_PREC_MIXED || p->n == 0) {
+    // the FP64 path tunes the task size of its matrix-core M2L (over the
+    // class tables; nothing to tune where M2L runs per pair)
+    const bool fp64 = p->prm.precision == FMM_PREC_FP64;
+    if (p->n == 0 || (fp64 && !(p->nf.built && p->nf.f64))) {
         if (best) *best = p->tuning;
         if (best_ms) *best_ms = -1.0;
         return FMM_OK;
@@ -1414,23 +1417,28 @@ fmm_status fmm_autotune(fmm_plan *p, int32_t repeats, fmm_tuning *best, double *
         fmm::near_far_drop_early(p->nf, s);   // every trial launches its own near field
         ensure_eval_buffers(p);   // the queue writes the locals and the near field
         static const int kEntries[] = {32, 64, 96, 128};
+        static const int kEntries64[] = {16, 32, 64, 128};
         // (work-queue, P2P side) workgroups per compute unit; the early near
         // field stays as set (its gain depends on what the build lets it
         // overlap, which one evaluation does not show)
         static const int kShape[][3] = {{1, 1, 0}, {1, 2, 0}, {1, 3, 0}, {2, 0, 0}, {3, 0, 0}, {2, 1, 0}, {2, 2, 0}};
+        const int nshape = fp64 ? 1 : (int)(sizeof(kShape) / sizeof(kShape[0]));   // FP64: no queue to shape
         hipEvent_t e0, e1;
         FMM_HIP_CHECK(hipEventCreate(&e0));
         FMM_HIP_CHECK(hipEventCreate(&e1));
         fmm_tuning keep = p->tuning, top = keep;
         float top_ms = -1.0f;
         try {
-            for (int ce : kEntries) {
-                p->tuning.m2l_task_entries = ce;
+            for (int ei = 0; ei < 4; ei++) {
+                p->tuning.m2l_task_entries = fp64 ? kEntries64[ei] : kEntries[ei];
                 fmm::build_near_far_mixed(p->nf, nf_args(p), s);
-                for (const auto &sh : kShape) {
-                    p->tuning.grid_per_cu = sh[0];
-                    p->tuning.p2p_per_cu = sh[1];
-                    p->tuning.early_p2p_per_cu = std::min(keep.early_p2p_per_cu, sh[1]);
+                for (int si = 0; si < nshape; si++) {
+                    if (!fp64) {
+                        const int *sh = kShape[si];
+                        p->tuning.grid_per_cu = sh[0];
+                        p->tuning.p2p_per_cu = sh[1];
+                        p->tuning.early_p2p_per_cu = std::min(keep.early_p2p_per_cu, sh[1]);
+                    }
                     float t_min = -1.0f;
                     for (int r = 0; r < repeats; r++) {
                         // the whole evaluation (queue, far field beside the

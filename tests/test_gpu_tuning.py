@@ -41,13 +41,28 @@ def test_autotune_mixed():
     assert rel(out2["phi"], ref["phi"]) < 1e-6
 
 
-def test_autotune_fp64_reports_no_queue():
-    pos, q = W.uniform_cube(5000, 52)
-    plan = fmm.Plan(p=4, ncrit=64, theta=(1, 2), precision="fp64", device=0)
-    plan.build_tree(torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda())
+def test_autotune_fp64_task_size():
+    # the FP64 path tunes the task size of its matrix-core M2L (the launch
+    # shape untouched); results stay the FP64 path's to rounding
+    pos, q = W.uniform_cube(20000, 52)
+    dpos, dq = torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda()
+    plan = fmm.Plan(p=6, ncrit=32, theta=(1, 2), precision="fp64", device=0)
+    plan.build_tree(dpos, dq)
     plan.upward()
-    tuning, ms = plan.autotune()
-    assert ms == -1.0
+    ref = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    shape = {k: v for k, v in plan.get_tuning().items() if k != "m2l_task_entries"}
+    tuning, ms = plan.autotune(repeats=1)
+    assert ms > 0 and tuning["m2l_task_entries"] in (16, 32, 64, 128)
+    assert {k: v for k, v in tuning.items() if k != "m2l_task_entries"} == shape
+    assert plan.get_tuning() == tuning
+    out = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    assert rel(out["phi"], ref["phi"]) < 1e-13 and rel(out["field"], ref["field"]) < 1e-13
+    # nothing to tune where M2L runs per pair
+    for kw in (dict(p=13), dict(p=6, mutual="m2l")):
+        plan = fmm.Plan(ncrit=32, theta=(1, 2), precision="fp64", device=0, **kw)
+        plan.build_tree(dpos, dq)
+        plan.upward()
+        assert plan.autotune()[1] == -1.0
 
 
 def test_default_task_size_by_precision():
