@@ -166,3 +166,34 @@ def test_mutual_small_edge_cases():
             assert out["phi"][0] == 0.0 and np.all(out["field"][0] == 0.0)
         else:
             assert rel(out["phi"], pd) < 1e-13 and rel(out["field"], fd) < 1e-12
+
+
+def test_mutual_step_graph_and_noalloc():
+    # the mutual kernels inside a captured step graph (kept topology) and
+    # behind fmm_evaluate_noalloc: the same results as fmm_evaluate, to the
+    # order of the atomic additions
+    pos, q = W.plummer(8000, 31)
+    n = len(q)
+    plan = fmm.Plan(p=8, ncrit=32, theta=(1, 2), precision="fp64", device=0, mutual=True, keep_topology=True)
+    dpos, dq = dev(pos), dev(q)
+    plan.build_tree(dpos, dq)
+    plan.upward()
+    ref = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
+    out = {"phi": torch.empty(n, dtype=torch.float64, device="cuda"),
+           "field": torch.empty((n, 3), dtype=torch.float64, device="cuda"),
+           "energy": torch.empty(1, dtype=torch.float64, device="cuda")}
+    plan.evaluate_noalloc_into(**out)
+    torch.cuda.synchronize()
+    for k in ("phi", "field"):
+        assert maxrel(out[k].cpu().numpy(), ref[k]) < 1e-13
+    plan.graph_capture_step(dpos, dq, **out)
+    for _ in range(3):
+        for t in out.values():
+            t.zero_()
+        torch.cuda.synchronize()
+        plan.graph_launch()
+        plan.sync()
+        for k in ("phi", "field"):
+            assert maxrel(out[k].cpu().numpy(), ref[k]) < 1e-13
+        assert out["energy"].item() == pytest.approx(ref["energy"][0], rel=1e-12)
+

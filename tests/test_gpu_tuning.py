@@ -57,6 +57,16 @@ def test_autotune_fp64_task_size():
     assert plan.get_tuning() == tuning
     out = {k: v.cpu().numpy() for k, v in plan.evaluate().items()}
     assert rel(out["phi"], ref["phi"]) < 1e-13 and rel(out["field"], ref["field"]) < 1e-13
+    # deterministic mode: another plan with the chosen task size gives the
+    # same bits
+    plans = []
+    for _ in range(2):
+        pl = fmm.Plan(p=6, ncrit=32, theta=(1, 2), precision="fp64", device=0, deterministic=True)
+        pl.set_tuning(**tuning)
+        pl.build_tree(dpos, dq)
+        pl.upward()
+        plans.append({k: v.cpu().numpy() for k, v in pl.evaluate().items()})
+    assert all(np.array_equal(plans[0][k], plans[1][k]) for k in ("phi", "field", "energy"))
     # nothing to tune where M2L runs per pair
     for kw in (dict(p=13), dict(p=6, mutual="m2l")):
         plan = fmm.Plan(ncrit=32, theta=(1, 2), precision="fp64", device=0, **kw)
