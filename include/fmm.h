@@ -142,7 +142,10 @@ fmm_status fmm_default_params(fmm_params *params);
 typedef struct fmm_plan fmm_plan; /* opaque; owns all device workspaces */
 
 /* Create a plan on HIP device `device` that enqueues on `hip_stream`
- * (a hipStream_t; NULL = the null stream).  params is copied. */
+ * (a hipStream_t; NULL = the null stream).  params is copied.  Parameters
+ * are checked first (FMM_ERR_INVALID_ARG, before any device call); a
+ * device index with no device behind it, or one that cannot be selected,
+ * is FMM_ERR_DEVICE. */
 fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fmm_plan **out);
 
 /* Release every device allocation of the plan.  First waits for the plan's

@@ -1013,8 +1013,9 @@ fmm_status fmm_create(const fmm_params *params, int device, void *hip_stream, fm
     std::string why;
     fmm_status st = check_params(params, &why);
     if (st != FMM_OK) return st;
+    if (device < 0) return FMM_ERR_INVALID_ARG;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FMM_ERR_INVALID_ARG;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return FMM_ERR_DEVICE;
     fmm_plan *p = new (std::nothrow) fmm_plan();
     if (!p) return FMM_ERR_OOM;
     p->prm = *params;

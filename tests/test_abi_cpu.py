@@ -37,19 +37,41 @@ def test_default_params_and_status_strings():
     assert lib.fmm_status_string(0).decode() == "ok"
 
 
-@pytest.mark.parametrize("field,value", [("p", -1), ("p", 17), ("ncrit", 0), ("theta_num", 0), ("theta_den", 0),
-                                         ("theta_num", 3), ("max_level", 0), ("max_level", 22), ("precision", 7),
-                                         ("flags", 8)])
-def test_create_rejects_bad_params_before_touching_a_device(field, value):
+def _create_status(**fields):
     lib = fmm.load_library()
     prm = fmm.fmm_params()
     lib.fmm_default_params(ctypes.byref(prm))
-    if field == "theta_num" and value == 3:
-        prm.theta_den = 2   # theta >= 1
-    setattr(prm, field, value)
+    for k, v in fields.items():
+        setattr(prm, k, v)
     h = ctypes.c_void_p()
-    assert lib.fmm_create(ctypes.byref(prm), 0, None, ctypes.byref(h)) == -1
-    assert not h.value
+    st = lib.fmm_create(ctypes.byref(prm), 0, None, ctypes.byref(h))
+    if st == 0:
+        lib.fmm_destroy(h)
+    else:
+        assert not h.value
+    return st
+
+
+@pytest.mark.parametrize("fields", [dict(p=-1), dict(p=17), dict(ncrit=0), dict(theta_num=0), dict(theta_den=0),
+                                    dict(theta_num=3, theta_den=2), dict(theta_num=1, theta_den=1),
+                                    dict(max_level=0), dict(max_level=22), dict(precision=7),
+                                    dict(flags=1 << 8),
+                                    dict(flags=fmm.FLAG_INCREMENTAL, theta_num=4, theta_den=5),
+                                    dict(flags=fmm.FLAG_MUTUAL),   # mixed precision
+                                    dict(flags=fmm.FLAG_MUTUAL_M2L), dict(flags=fmm.FLAG_MUTUAL_P2P),
+                                    dict(precision=0, flags=fmm.FLAG_MUTUAL_P2P | fmm.FLAG_DETERMINISTIC)])
+def test_create_rejects_bad_params_before_touching_a_device(fields):
+    assert _create_status(**fields) == -1
+
+
+@pytest.mark.parametrize("fields", [dict(), dict(flags=fmm.FLAG_DETERMINISTIC), dict(precision=0),
+                                    dict(precision=0, flags=fmm.FLAG_MUTUAL),
+                                    dict(precision=0, flags=fmm.FLAG_MUTUAL_M2L),
+                                    dict(flags=fmm.FLAG_INCREMENTAL | fmm.FLAG_COST_REUSE, theta_num=2, theta_den=5)])
+def test_create_accepts_good_params(fields):
+    # past the parameter checks: a plan where a GPU is present, otherwise
+    # the device error, never FMM_ERR_INVALID_ARG
+    assert _create_status(**fields) in (0, -4)
 
 
 def test_create_rejects_bad_user_box():
@@ -60,6 +82,11 @@ def test_create_rejects_bad_user_box():
     prm.box_side = 0.0
     h = ctypes.c_void_p()
     assert lib.fmm_create(ctypes.byref(prm), 0, None, ctypes.byref(h)) == -1
+
+
+def test_python_binding_rejects_unknown_mutual_value():
+    with pytest.raises(ValueError):
+        fmm.Plan(p=4, precision="fp64", device=0, mutual="l2l")
 
 
 def test_null_plan_is_rejected_everywhere():
