@@ -237,3 +237,40 @@ def test_rebuilds_that_outgrow_the_last_tree(prec):
         o = {k: v.cpu().numpy() for k, v in out.items()}
         (check_fp64 if prec == "fp64" else check_mixed)(o, phi_ref, fld_ref, leaf_ids(T.perm, T.cells), say,
                                                         "rebuild %s %d" % (dist, n))
+
+
+def test_binding_refuses_bad_tensors():
+    # the binding checks every tensor it hands to the library (dtype, device,
+    # contiguity, exact shape) before any pointer reaches a kernel; the plan
+    # still works afterwards
+    pos, q = W.uniform_cube(3000, 41)
+    n = len(q)
+    plan = fmm.Plan(p=4, ncrit=64, theta=(1, 2), precision="fp64", device=0)
+    dpos = torch.from_numpy(pos).cuda()
+    dq = torch.from_numpy(q).cuda()
+    f64 = dict(dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        plan.build_tree(dpos.float(), dq)
+    with pytest.raises(ValueError):
+        plan.build_tree(dpos.t(), dq)   # not contiguous
+    plan.build_tree(dpos, dq)
+    plan.upward()
+    bad = [dict(phi=torch.empty(n, dtype=torch.float32, device="cuda")),
+           dict(phi=torch.empty(n + 1, **f64)),
+           dict(field=torch.empty(n, **f64)),
+           dict(force=torch.empty((3, n), **f64).t()),
+           dict(energy=torch.empty(2, **f64)),
+           dict(phi=torch.empty(n, dtype=torch.float64))]   # host memory
+    for kw in bad:
+        with pytest.raises(ValueError):
+            plan.evaluate_into(**kw)
+        with pytest.raises(ValueError):
+            plan.graph_capture(**kw)
+    out = plan.evaluate()
+    with pytest.raises(ValueError):
+        plan.backward(torch.ones(2, **f64))   # one instance: grad_energy has length 1
+    gp, gq = plan.backward(torch.ones(1, **f64))
+    torch.cuda.synchronize()
+    pd, fd = oracle.direct(pos, q)
+    assert rel(out["phi"].cpu().numpy(), pd) < 1e-3 and np.all(np.isfinite(gp.cpu().numpy()))
+
