@@ -152,3 +152,36 @@ def test_trace_summary_on_synthetic_records():
     assert abs(s["cu_busy_imbalance"] - 40.0 / 27.0) < 1e-12
     assert trace.summarize(rec[:0]) == {"tasks": 0}
 
+
+C_CONSUMER = r"""
+#include <stdio.h>
+#include "fmm.h"
+int main(void) {
+    fmm_params prm;
+    fmm_plan *plan = NULL;
+    if (fmm_default_params(&prm) != FMM_OK) return 1;
+    prm.flags = FMM_FLAG_MUTUAL;   /* needs FP64: refused before any device call */
+    if (fmm_create(&prm, 0, NULL, &plan) != FMM_ERR_INVALID_ARG || plan) return 2;
+    printf("%d %d %s\n", prm.p, prm.ncrit, fmm_status_string(FMM_ERR_CAPACITY));
+    return 0;
+}
+"""
+
+
+def test_c_consumer_compiles_links_and_runs(tmp_path):
+    # the header is plain C99 and the library links into a C program
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_1203_0889_amd")
+    src, exe = tmp_path / "consumer.c", tmp_path / "consumer"
+    src.write_text(C_CONSUMER)
+    cmd = ["gcc", "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(root, "include"),
+           str(src), "-o", str(exe), "-L", pkg, "-lfmm_mi355x", "-Wl,-rpath," + pkg]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    p, ncrit, msg = r.stdout.split(" ", 2)
+    assert (int(p), int(ncrit)) == (8, 64) and msg.strip()
+
