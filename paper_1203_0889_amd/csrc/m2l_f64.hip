@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256, 1) k_m2l_f64(const int4 *__restrict__ tas
         const double *mrow[4];
 #pragma unroll
         for (int c = 0; c < 4; c++) mrow[c] = M + (int64_t)(src[c] >= 0 ? src[c] : 0) * P;
-#pragma unroll 3
+#pragma unroll 6
         for (int s = 0; s < KS; s++) {
             const int k = 4 * s + q;
             double a[RB], b[4];
