@@ -52,6 +52,8 @@ CASES = [
     # above p = 12 every M2L pair goes through the per-pair FP64 kernel
     ("uniform3k_p16", "uniform", 3000, 9, 16, 64, (1, 2)),
     ("plummer2k_p13", "plummer", 2000, 11, 13, 16, (1, 2)),
+    ("plummer1500_p14", "plummer", 1500, 61, 14, 16, (1, 2)),
+    ("plummer1500_p15", "plummer", 1500, 61, 15, 16, (1, 2)),
 ]
 
 
@@ -114,7 +116,7 @@ def test_fp64_vs_direct_sum(case):
     e_phi, e_fld = rel(out["phi"][tg], pd), rel(out["field"][tg], fd)
     say(case["name"], "fp64 vs direct", e_phi, e_fld)
     tol = {4: (1e-3, 1e-2), 6: (1e-4, 1e-3), 8: (1e-5, 1e-4), 10: (1e-6, 1e-5), 13: (1e-7, 1e-6),
-           16: (1e-8, 1e-7)}[case["p"]]
+           14: (1e-7, 1e-6), 15: (1e-8, 1e-7), 16: (1e-8, 1e-7)}[case["p"]]
     assert e_phi < tol[0] and e_fld < tol[1]
 
 
