@@ -101,6 +101,26 @@ def test_mixed_orders_at_the_ends(p):
     check_mixed(out, phi_ref, fld_ref, leaf_ids(perm, cells), say, "p=%d" % p)
 
 
+# The odd orders the other cases skip, on an adaptive tree (pairs outside
+# the class table go through the per-pair FP64 kernel): every order-templated
+# kernel of both paths (the work queue, the FP64 class-table M2L, the
+# per-pair M2L) at p = 3, 5, 7, 9 against the oracle FMM.
+@pytest.mark.parametrize("p", [3, 5, 7, 9])
+def test_odd_orders_both_paths(p):
+    say("odd order", p)
+    pos, q = W.plummer(4000, 71)
+    phi_ref, fld_ref, _ = oracle.fmm(pos, q, p, 16, 1, 2)
+    for precision, tol in (("fp64", 1e-11), ("mixed", 1e-5)):
+        plan, out = gpu_run(pos, q, p, 16, (1, 2), precision)
+        e = (rel(out["phi"], phi_ref), rel(out["field"], fld_ref))
+        say("p", p, precision, "vs oracle FMM", e, "pairs outside the class table", plan.queue_info()["nextra"])
+        assert max(e) < tol
+        _, perm, cells = plan.copy_tree()
+        check = check_fp64 if precision == "fp64" else check_mixed
+        check(out, phi_ref, fld_ref, leaf_ids(perm, cells), say, "p=%d %s" % (p, precision))
+    assert plan.queue_info()["nextra"] > 0
+
+
 def test_mixed_coincident_cluster_reaches_max_level():
     # 24 coincident particles (no leaf can split them below ncrit = 8, so the
     # tree goes down to level 21) inside a uniform background: the coincident
