@@ -99,6 +99,12 @@ def test_mixed_orders_at_the_ends(p):
     assert e_phi < 1e-5 and e_fld < 1e-5
     _, perm, cells = plan.copy_tree()
     check_mixed(out, phi_ref, fld_ref, leaf_ids(perm, cells), say, "p=%d" % p)
+    # the FP64 path's class-table M2L at the same orders
+    _, out = gpu_run(pos, q, p, 48, (1, 2), "fp64")
+    e = (rel(out["phi"], phi_ref), rel(out["field"], fld_ref))
+    say("p", p, "fp64 vs oracle FMM", e)
+    assert max(e) < 1e-11
+    check_fp64(out, phi_ref, fld_ref, leaf_ids(perm, cells), say, "p=%d fp64" % p)
 
 
 # The odd orders the other cases skip, on an adaptive tree (pairs outside
