@@ -420,7 +420,10 @@ def run_batch(a, torch, fmm, W):
     field = torch.empty((n, 3), dtype=torch.float64, device=dev)
     energy = torch.empty(n_inst, dtype=torch.float64, device=dev)
     tuning = plan.get_tuning()
-    if not a.no_autotune and a.precision == "mixed":
+    if a.tuning:
+        plan.set_tuning(**fixed_tuning(a.tuning))
+        tuning = plan.get_tuning()
+    elif not a.no_autotune and a.precision == "mixed":
         plan.build_tree(dpos, dq, offs)
         plan.upward()
         tuning, _ = plan.autotune(repeats=2)

@@ -122,9 +122,11 @@ __device__ inline int octant_of(const CellArrays &c, int32_t cell) {
 }
 
 // M2M and L2L, octant-major: for each octant o a dense (p+1)^2 x (p+1)^2
-// operator (column-major) applied to the vectors of a level; wide levels in
-// a register-tiled kernel, levels of at most kSmallLevel parents one block
-// per (parent, octant).
+// operator (column-major) applied to the vectors of a level's parents; wide
+// levels in a register-tiled kernel, levels of at most kSmallLevel parents
+// one block per (parent, octant).  A level's parents are listed (cells with
+// children, in cell order), so its leaves take no blocks: on an adaptive
+// tree most cells of the deep levels are leaves.
 
 __device__ inline int32_t child_in_octant(const CellArrays &c, int32_t parent, int o) {
     int32_t ch = c.child[parent];
@@ -137,20 +139,27 @@ __device__ inline int32_t child_in_octant(const CellArrays &c, int32_t parent, i
 
 constexpr int kTransMaxThreads = 320;  // rows_block(p) for p <= 16
 
-__global__ void k_m2m_sum(Geometry g, int32_t lb, int32_t le, int p, const double *__restrict__ part,
+// Number of parents of the level with cells [lb, le): at most the host's
+// bound, which sizes the grids and the partial sums.
+__device__ inline int32_t level_parents(const LevelParents &lp, int32_t lb, int32_t le) {
+    const int32_t n = lp.ppos[le] - lp.ppos[lb];
+    return n < 0 ? 0 : (n < lp.npar_max ? n : lp.npar_max);
+}
+
+__global__ void k_m2m_sum(int32_t lb, int32_t le, int p, LevelParents lp, const double *__restrict__ part,
                           double *__restrict__ M) {
     const int P = ncoef(p);
-    const int64_t n = (int64_t)(le - lb) * P;
+    const int64_t n = (int64_t)level_parents(lp, lb, le) * P, stride = (int64_t)lp.npar_max * P;
+    const int32_t *__restrict__ pl = lp.plist + lp.ppos[lb];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int32_t par = lb + (int32_t)(i / P);
-        if (g.c.child[par] < 0) continue;
+        const int32_t par = pl[i / P];
         double s = 0.0;
-        for (int o = 0; o < 8; o++) s += part[(int64_t)o * n + i];
+        for (int o = 0; o < 8; o++) s += part[(int64_t)o * stride + i];
         M[(int64_t)par * P + (i % P)] = s;
     }
 }
 
-// Wide levels, register-tiled: block (npb parents, octant o), 256 threads;
+// Wide levels, register-tiled: block (npb listed parents, octant o), 256 threads;
 // a thread owns a tile of kTR rows x kTP parents.  Per chunk of cw columns
 // the block stages the operator columns (rows padded to Pp = kTR
 // ceil(P / kTR), zeros below P) and the matching rows of the npb input
@@ -158,7 +167,7 @@ __global__ void k_m2m_sum(Geometry g, int32_t lb, int32_t le, int p, const doubl
 // kTR kTP FMAs.  Sums run over the columns in order with one accumulator
 // per output, like the small-level kernels, so both give the same values.
 //   M2M (kL2L = false): input = the octant-o children's M, output
-//       part[o][parent][row] (zero without such a child);
+//       part[o][parent's rank in the level][row] (zero without such a child);
 //   L2L (kL2L = true): input = the parents' L, output added into the
 //       octant-o children's L.
 // Measured at p = 8 on the 4,096-parent level (L2L / M2M): 4 x 8 tiles,
@@ -175,22 +184,26 @@ struct TileShape {
 
 template <bool kL2L>
 __global__ void __launch_bounds__(kTileThreads) k_trans_tiled(Geometry g, int32_t lb, int32_t le, int p, TileShape ts,
-                                                              const double *__restrict__ ops,
+                                                              LevelParents lp, const double *__restrict__ ops,
                                                               const double *__restrict__ in, double *__restrict__ out) {
     extern __shared__ double dyn[];
-    __shared__ int32_t kid[kTileThreads];
+    __shared__ int32_t kid[kTileMaxParents], pid[kTileMaxParents];
     const int P = ncoef(p);
     const int Pp = ts.Pp, npb = ts.npb, XS = ts.xs, cw = ts.cw;
     double *opS = dyn;              // cw x Pp, column-major
     double *xS = dyn + cw * Pp;     // cw x XS, k-major
     const int o = blockIdx.y;
-    const int32_t p0 = lb + blockIdx.x * npb;
+    const int32_t npar = level_parents(lp, lb, le);
+    const int32_t r0 = blockIdx.x * npb;   // rank of the block's first parent in the level
+    if (r0 >= npar) return;                // the grid covers the host's bound on the parents
     const int PG = npb / kTP, RG = Pp / kTR;
     const int rg = threadIdx.x / PG, pg = threadIdx.x - rg * PG;
     const bool active = rg < RG;
     if (threadIdx.x < npb) {
-        const int32_t par = p0 + threadIdx.x;
-        kid[threadIdx.x] = par < le ? child_in_octant(g.c, par, o) : -1;
+        const int32_t r = r0 + threadIdx.x;
+        const int32_t par = r < npar ? lp.plist[lp.ppos[lb] + r] : -1;
+        pid[threadIdx.x] = par;
+        kid[threadIdx.x] = par >= 0 ? child_in_octant(g.c, par, o) : -1;
     }
     double acc[kTR][kTP];
 #pragma unroll
@@ -222,7 +235,7 @@ __global__ void __launch_bounds__(kTileThreads) k_trans_tiled(Geometry g, int32_
             for (int b = 0; b < kStageBatch; b++) {
                 const int i = i0 + b * kTileThreads;
                 const int j = i / w, k = i - j * w;   // consecutive threads read consecutive coefficients
-                const int32_t src = i >= nx ? -1 : (kL2L ? (p0 + j < le ? p0 + j : -1) : kid[j]);
+                const int32_t src = i >= nx || kid[j] < 0 ? -1 : (kL2L ? pid[j] : kid[j]);
                 v[b] = src >= 0 ? in[(int64_t)src * P + c0 + k] : 0.0;
             }
 #pragma unroll
@@ -254,8 +267,7 @@ __global__ void __launch_bounds__(kTileThreads) k_trans_tiled(Geometry g, int32_
         double old[kTR][kTP];
 #pragma unroll
         for (int j = 0; j < kTP; j++) {
-            const int jj = kTP * pg + j;
-            ch[j] = p0 + jj < le ? kid[jj] : -1;
+            ch[j] = kid[kTP * pg + j];
 #pragma unroll
             for (int i = 0; i < kTR; i++) {
                 const int r = kTR * rg + i;
@@ -273,15 +285,12 @@ __global__ void __launch_bounds__(kTileThreads) k_trans_tiled(Geometry g, int32_
     }
 #pragma unroll
     for (int j = 0; j < kTP; j++) {
-        const int jj = kTP * pg + j;
-        const int32_t par = p0 + jj;
-        if (par >= le) continue;
-        {
+        const int32_t rank = r0 + kTP * pg + j;
+        if (rank >= npar) continue;
 #pragma unroll
-            for (int i = 0; i < kTR; i++) {
-                const int r = kTR * rg + i;
-                if (r < P) out[((int64_t)o * (le - lb) + (par - lb)) * P + r] = acc[i][j];
-            }
+        for (int i = 0; i < kTR; i++) {
+            const int r = kTR * rg + i;
+            if (r < P) out[((int64_t)o * lp.npar_max + rank) * P + r] = acc[i][j];
         }
     }
 }
@@ -297,15 +306,17 @@ constexpr int32_t kSmallLevel = 256;   // parents per level up to which these ar
 constexpr int kMaxCoef = 17 * 17;      // (p + 1)^2 for p <= 16
 
 __global__ void __launch_bounds__(kTransMaxThreads) k_m2m_small(Geometry g, int32_t lb, int32_t le, int p,
-                                                                const double *__restrict__ ops,
+                                                                LevelParents lp, const double *__restrict__ ops,
                                                                 const double *__restrict__ M, double *__restrict__ part) {
     __shared__ double x[kMaxCoef];
     const int P = ncoef(p);
     const int o = blockIdx.y;
-    const int32_t par = lb + blockIdx.x;
+    const int32_t rank = blockIdx.x;
+    if (rank >= level_parents(lp, lb, le)) return;
+    const int32_t par = lp.plist[lp.ppos[lb] + rank];
     const int row = threadIdx.x;
     const int32_t ch = child_in_octant(g.c, par, o);   // the same in every thread
-    double *out = part + ((int64_t)o * (le - lb) + (par - lb)) * P;
+    double *out = part + ((int64_t)o * lp.npar_max + rank) * P;
     if (ch < 0) {
         if (row < P) out[row] = 0.0;
         return;
@@ -320,11 +331,14 @@ __global__ void __launch_bounds__(kTransMaxThreads) k_m2m_small(Geometry g, int3
 }
 
 __global__ void __launch_bounds__(kTransMaxThreads) k_l2l_small(Geometry g, int32_t lb, int32_t le, int p,
-                                                                const double *__restrict__ ops, double *__restrict__ L) {
+                                                                LevelParents lp, const double *__restrict__ ops,
+                                                                double *__restrict__ L) {
     __shared__ double x[kMaxCoef];
     const int P = ncoef(p);
     const int o = blockIdx.y;
-    const int32_t par = lb + blockIdx.x;
+    const int32_t rank = blockIdx.x;
+    if (rank >= level_parents(lp, lb, le)) return;
+    const int32_t par = lp.plist[lp.ppos[lb] + rank];
     const int row = threadIdx.x;
     const int32_t ch = child_in_octant(g.c, par, o);
     if (ch < 0) return;
@@ -724,34 +738,39 @@ static void allow_lds(const void *fn, size_t bytes) {
         FMM_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, double *part,
-                      hipStream_t s) {
-    if (le <= lb) return;
-    if (le - lb <= kSmallLevel) {
-        hipLaunchKernelGGL(k_m2m_small, dim3(le - lb, 8), dim3(rows_block(p)), 0, s, g, lb, le, p, ops, M, part);
+// The grids cover lp.npar_max parents; blocks beyond the level's parent
+// count return at once.
+void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, LevelParents lp, const double *ops, double *M,
+                      double *part, hipStream_t s) {
+    if (le <= lb || lp.npar_max <= 0) return;
+    if (lp.npar_max <= kSmallLevel) {
+        hipLaunchKernelGGL(k_m2m_small, dim3(lp.npar_max, 8), dim3(rows_block(p)), 0, s, g, lb, le, p, lp, ops, M,
+                           part);
     } else {
         const TileShape t = tile_shape(p);
         const size_t lds = tile_lds(t);
         allow_lds(reinterpret_cast<const void *>(&k_trans_tiled<false>), lds);
-        dim3 grid((le - lb + t.npb - 1) / t.npb, 8);
-        hipLaunchKernelGGL(k_trans_tiled<false>, grid, dim3(kTileThreads), lds, s, g, lb, le, p, t, ops, M, part);
+        dim3 grid((lp.npar_max + t.npb - 1) / t.npb, 8);
+        hipLaunchKernelGGL(k_trans_tiled<false>, grid, dim3(kTileThreads), lds, s, g, lb, le, p, t, lp, ops, M,
+                           part);
     }
     FMM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_m2m_sum, dim3(grid_for((int64_t)(le - lb) * ncoef(p), 256, 4096)), dim3(256), 0, s, g, lb, le, p,
-                       part, M);
+    hipLaunchKernelGGL(k_m2m_sum, dim3(grid_for((int64_t)lp.npar_max * ncoef(p), 256, 4096)), dim3(256), 0, s, lb, le,
+                       p, lp, part, M);
     FMM_LAUNCH_CHECK();
 }
 
-void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *L, hipStream_t s) {
-    if (le <= lb) return;
-    if (le - lb <= kSmallLevel) {
-        hipLaunchKernelGGL(k_l2l_small, dim3(le - lb, 8), dim3(rows_block(p)), 0, s, g, lb, le, p, ops, L);
+void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, LevelParents lp, const double *ops, double *L,
+                      hipStream_t s) {
+    if (le <= lb || lp.npar_max <= 0) return;
+    if (lp.npar_max <= kSmallLevel) {
+        hipLaunchKernelGGL(k_l2l_small, dim3(lp.npar_max, 8), dim3(rows_block(p)), 0, s, g, lb, le, p, lp, ops, L);
     } else {
         const TileShape t = tile_shape(p);
         const size_t lds = tile_lds(t);
         allow_lds(reinterpret_cast<const void *>(&k_trans_tiled<true>), lds);
-        dim3 grid((le - lb + t.npb - 1) / t.npb, 8);
-        hipLaunchKernelGGL(k_trans_tiled<true>, grid, dim3(kTileThreads), lds, s, g, lb, le, p, t, ops, L, L);
+        dim3 grid((lp.npar_max + t.npb - 1) / t.npb, 8);
+        hipLaunchKernelGGL(k_trans_tiled<true>, grid, dim3(kTileThreads), lds, s, g, lb, le, p, t, lp, ops, L, L);
     }
     FMM_LAUNCH_CHECK();
 }

@@ -132,6 +132,7 @@ struct fmm_plan {
     DevBuf bounds, nch, counters;
     int64_t ncell = 0, nleaf = 0, nm2l = 0, np2p = 0;
     std::vector<int32_t> level_begin;  // level l cells: [level_begin[l], level_begin[l+1])
+    DevBuf ppos, plist, ptmp;          // the cells with children (fmm::launch_parent_list) and its scan scratch
     // lists
     DevBuf front[2], m2l_pairs, p2p_pairs, pair_alt, m2l_ptr, m2l_src, p2p_ptr, p2p_src;
     DevBuf pair_alt2, tmp2;     // scratch of the P2P pair sort (second stream)
@@ -252,6 +253,13 @@ fmm::Geometry geom(fmm_plan *p) {
     g.box = p->box.as<double>();
     g.c = cells_of(p);
     return g;
+}
+
+// The parents of level l (which has a level below it) for the M2M and L2L
+// launches.
+fmm::LevelParents level_parents(const fmm_plan *p, int l) {
+    const std::vector<int32_t> &lb = p->level_begin;
+    return {p->plist.as<int32_t>(), p->ppos.as<int32_t>(), std::min(lb[l + 1] - lb[l], lb[l + 2] - lb[l + 1])};
 }
 
 fmm::NearFarArgs nf_args(fmm_plan *p);
@@ -386,6 +394,20 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
             p->side_pending = false;
         }
     } join_side{p};
+
+    // the parents of every level for the level-by-level M2M and L2L, on the
+    // second stream beside the traversal (its later work, the upward pass
+    // included, follows on that stream; this stream joins it at the end)
+    FMM_HIP_CHECK(p->ppos.grow(((size_t)p->ncell + 1) * sizeof(int32_t)));
+    FMM_HIP_CHECK(p->plist.grow((size_t)std::max<int64_t>(p->ncell, 1) * sizeof(int32_t)));
+    FMM_HIP_CHECK(p->ptmp.grow(fmm::scan_tmp_elems(p->ncell) * sizeof(int32_t)));
+    ensure_side(p);
+    FMM_HIP_CHECK(hipEventRecord(p->p2p_fork, s));
+    FMM_HIP_CHECK(hipStreamWaitEvent(p->up_side, p->p2p_fork, 0));
+    p->side_pending = true;
+    fmm::launch_parent_list(cells_of(p), (int32_t)p->ncell, p->ppos.as<int32_t>(), p->plist.as<int32_t>(),
+                            p->ptmp.as<int32_t>(), p->up_side);
+    FMM_HIP_CHECK(hipEventRecord(p->up_join, p->up_side));
 
     // the non-finite flag and the leaf count are read back with the
     // traversal's sizes (the traversal runs on any tree, even one built from
@@ -569,7 +591,7 @@ void upward_kernels(fmm_plan *p, hipStream_t s, bool side) {
     FMM_HIP_CHECK(p->M.grow((size_t)std::max<int64_t>(p->ncell, 1) * P * 8));
     int depth = (int)p->level_begin.size() - 1;  // number of levels present
     int32_t widest = 1;
-    for (int l = 0; l + 1 < depth; l++) widest = std::max(widest, p->level_begin[l + 1] - p->level_begin[l]);
+    for (int l = 0; l + 1 < depth; l++) widest = std::max(widest, level_parents(p, l).npar_max);
     FMM_HIP_CHECK(p->m2m_part.grow((size_t)8 * widest * P * 8));
     fmm::Geometry g = geom(p);
     const bool timed = side && p->ev_ok && !p->capturing;
@@ -580,8 +602,8 @@ void upward_kernels(fmm_plan *p, hipStream_t s, bool side) {
     if (timed) FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_P2M], s));
     else mark(p, ST_P2M);
     for (int l = depth - 2; l >= 0; l--)
-        fmm::launch_m2m_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_m2m.as<double>(),
-                              p->M.as<double>(), p->m2m_part.as<double>(), s);
+        fmm::launch_m2m_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, level_parents(p, l),
+                              p->ops_m2m.as<double>(), p->M.as<double>(), p->m2m_part.as<double>(), s);
     if (timed) {
         FMM_HIP_CHECK(hipEventRecord(p->ev_end[ST_M2M], s));
         p->beg_of[ST_P2M] = p->ev_beg[ST_P2M];
@@ -761,8 +783,8 @@ void do_evaluate(fmm_plan *p, double *phi, double *field, double *force, double 
     }
     int depth = (int)p->level_begin.size() - 1;
     for (int l = 0; l + 1 < depth; l++)  // parents of level l push to level l + 1
-        fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, p->ops_l2l.as<double>(),
-                              p->L.as<double>(), s);
+        fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], p->prm.p, level_parents(p, l),
+                              p->ops_l2l.as<double>(), p->L.as<double>(), s);
     mark(p, ST_L2L);
     // L2P also writes the outputs (near + far, input order) when the near
     // field is complete; the far field stays for the energy and a later
@@ -910,8 +932,8 @@ void do_backward(fmm_plan *p, const double *gE, double *grad_pos, double *grad_q
     fmm::launch_dual_scale(g, ncell, pp, p->lam.as<double>(), 0, s);
     const int depth = (int)p->level_begin.size() - 1;
     for (int l = depth - 2; l >= 0; l--)
-        fmm::launch_m2m_level(g, p->level_begin[l], p->level_begin[l + 1], pp, p->ops_l2l_t.as<double>(),
-                              p->lam.as<double>(), p->m2m_part.as<double>(), s);
+        fmm::launch_m2m_level(g, p->level_begin[l], p->level_begin[l + 1], pp, level_parents(p, l),
+                              p->ops_l2l_t.as<double>(), p->lam.as<double>(), p->m2m_part.as<double>(), s);
     // M2L^T and P2P^T
     if (p->prm.precision == FMM_PREC_FP64) {
         if (p->nf_t.built && p->nf_t.f64)
@@ -930,8 +952,8 @@ void do_backward(fmm_plan *p, const double *gE, double *grad_pos, double *grad_q
     }
     // M2M^T down the tree, then P2M^T at the particles
     for (int l = 0; l + 1 < depth; l++)
-        fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], pp, p->ops_m2m_t.as<double>(),
-                              p->mu.as<double>(), s);
+        fmm::launch_l2l_level(g, p->level_begin[l], p->level_begin[l + 1], pp, level_parents(p, l),
+                              p->ops_m2m_t.as<double>(), p->mu.as<double>(), s);
     fmm::launch_dual_scale(g, ncell, pp, p->mu.as<double>(), 1, s);
     fmm::launch_l2p(g, p->n, pp, p->leaf_of.as<int32_t>(), p->xs.as<double>(), p->ys.as<double>(), p->zs.as<double>(),
                     p->mu.as<double>(), p->psi_far.as<double>(), p->epsi_far.as<double>(), s);
@@ -1059,7 +1081,7 @@ fmm_status fmm_destroy(fmm_plan *p) {
                      &p->fld_far, &p->echunk, &p->epart, &p->ops_m2m_t, &p->ops_l2l_t, &p->m2l_t_ptr,
                      &p->m2l_t_src, &p->p2p_t_ptr, &p->p2p_t_src, &p->tkeys, &p->tkeys_alt, &p->lam, &p->mu,
                      &p->wts, &p->psi_near, &p->epsi_near, &p->psi_far, &p->epsi_far, &p->trace,
-                     &p->trace_count, &p->pair_alt2, &p->tmp2, &p->leaf_cost};
+                     &p->trace_count, &p->pair_alt2, &p->tmp2, &p->leaf_cost, &p->ppos, &p->plist, &p->ptmp};
     drop_graph(p);
     for (DevBuf *b : all) b->release();
     for (auto &b : p->cb) b.release();

@@ -54,6 +54,11 @@ void launch_tree_level_dev(CellArrays c, int32_t *lev, int level, int nlev, int 
                            int32_t cap, hipStream_t s);
 // leaf_of[r] = leaf cell of sorted particle r; *nleaf = number of leaves.
 void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, int32_t *nleaf, hipStream_t s);
+// The cells with children, in cell order: ppos[c] = number of such cells
+// before c (ppos[ncell] = all of them; ncell + 1 entries) and
+// plist[ppos[c]] = c for each (ncell entries).  The parents of the level
+// with cells [lb, le) are plist[ppos[lb] .. ppos[le]).  tmp: scan_tmp_elems(ncell).
+void launch_parent_list(CellArrays c, int32_t ncell, int32_t *ppos, int32_t *plist, int32_t *tmp, hipStream_t s);
 // After a frozen-topology gather: flag[0] |= 1 if a coordinate is not
 // finite; with check_leaf, flag[1] |= 1 if a particle left its leaf cell
 // widened by 1/8 of the side on every face (the tree no longer fits it).
@@ -93,10 +98,20 @@ struct Geometry {
 };
 void launch_p2m(Geometry g, int32_t ncell, int p, const double *xs, const double *ys, const double *zs,
                 const double *qs, double *M, hipStream_t s);
-// part: scratch of 8 * (le - lb) * (p+1)^2 doubles.
-void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *M, double *part,
+// The parents of one level (cells [lb, le)), as launch_parent_list lists
+// them, and a bound on their number that the host knows: the smaller of the
+// level's and the next level's cell counts (a parent has at least one child
+// there).  The translation kernels take only the parents, so a level's
+// leaves cost nothing.
+struct LevelParents {
+    const int32_t *plist, *ppos;
+    int32_t npar_max;
+};
+// part: scratch of 8 * npar_max * (p+1)^2 doubles.
+void launch_m2m_level(Geometry g, int32_t lb, int32_t le, int p, LevelParents lp, const double *ops, double *M,
+                      double *part, hipStream_t s);
+void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, LevelParents lp, const double *ops, double *L,
                       hipStream_t s);
-void launch_l2l_level(Geometry g, int32_t lb, int32_t le, int p, const double *ops, double *L, hipStream_t s);
 // The outputs of an evaluation, written by the L2P kernel once a particle's
 // far field is known: near + far field in input order (perm[r] = input index
 // of sorted particle r); force = q E.  Null members are not written; a null

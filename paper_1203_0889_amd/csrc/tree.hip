@@ -432,6 +432,19 @@ __global__ void k_leaf_of(CellArrays c, int32_t ncell, int32_t *__restrict__ lea
     }
 }
 
+// The cells with children: a flag per cell, scanned in place into each
+// parent's rank, then every parent stores its index at its rank.
+__global__ void k_parent_flags(const int32_t *__restrict__ child, int32_t ncell, int32_t *__restrict__ flag) {
+    for (int32_t cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x)
+        flag[cell] = child[cell] >= 0 ? 1 : 0;
+}
+
+__global__ void k_parent_scatter(const int32_t *__restrict__ child, int32_t ncell, const int32_t *__restrict__ ppos,
+                                 int32_t *__restrict__ plist) {
+    for (int32_t cell = blockIdx.x * blockDim.x + threadIdx.x; cell < ncell; cell += gridDim.x * blockDim.x)
+        if (child[cell] >= 0) plist[ppos[cell]] = cell;
+}
+
 // A frozen-topology rebuild: every sorted particle's new coordinates are
 // finite (flag[0]) and, with check_leaf, still inside its leaf cell widened
 // by 1/8 of its side on every face (flag[2] otherwise).  Coordinates in
@@ -560,6 +573,17 @@ void launch_tree_level_dev(CellArrays c, int32_t *lev, int level, int nlev, int 
 void launch_leaf_of(CellArrays c, int32_t ncell, int32_t *leaf_of, int32_t *nleaf, hipStream_t s) {
     FMM_HIP_CHECK(hipMemsetAsync(nleaf, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(k_leaf_of, dim3(grid_for(ncell, 256, 8192)), dim3(256), 0, s, c, ncell, leaf_of, nleaf);
+    FMM_LAUNCH_CHECK();
+}
+
+void launch_parent_list(CellArrays c, int32_t ncell, int32_t *ppos, int32_t *plist, int32_t *tmp, hipStream_t s) {
+    if (ncell <= 0) return;
+    const dim3 grid(grid_for(ncell, 256, 8192)), block(256);
+    hipLaunchKernelGGL(k_parent_flags, grid, block, 0, s, (const int32_t *)c.child, ncell, ppos);
+    FMM_LAUNCH_CHECK();
+    exclusive_scan_i32(ppos, ncell, ppos + ncell, tmp, s);
+    hipLaunchKernelGGL(k_parent_scatter, grid, block, 0, s, (const int32_t *)c.child, ncell, (const int32_t *)ppos,
+                       plist);
     FMM_LAUNCH_CHECK();
 }
 
