@@ -397,17 +397,16 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
 
     // the parents of every level for the level-by-level M2M and L2L, on the
     // second stream beside the traversal (its later work, the upward pass
-    // included, follows on that stream; this stream joins it at the end)
+    // included, follows on that stream; this stream joins it at the end).
+    // The fork is marked here; its launches are enqueued once the
+    // traversal's are, so that the host enqueues them while the GPU
+    // traverses instead of the GPU waiting for the host.
     FMM_HIP_CHECK(p->ppos.grow(((size_t)p->ncell + 1) * sizeof(int32_t)));
     FMM_HIP_CHECK(p->plist.grow((size_t)std::max<int64_t>(p->ncell, 1) * sizeof(int32_t)));
     FMM_HIP_CHECK(p->ptmp.grow(fmm::scan_tmp_elems(p->ncell) * sizeof(int32_t)));
     ensure_side(p);
     FMM_HIP_CHECK(hipEventRecord(p->p2p_fork, s));
-    FMM_HIP_CHECK(hipStreamWaitEvent(p->up_side, p->p2p_fork, 0));
-    p->side_pending = true;
-    fmm::launch_parent_list(cells_of(p), (int32_t)p->ncell, p->ppos.as<int32_t>(), p->plist.as<int32_t>(),
-                            p->ptmp.as<int32_t>(), p->up_side);
-    FMM_HIP_CHECK(hipEventRecord(p->up_join, p->up_side));
+    bool parents_listed = false;
 
     // the non-finite flag and the leaf count are read back with the
     // traversal's sizes (the traversal runs on any tree, even one built from
@@ -441,6 +440,14 @@ void do_build(fmm_plan *p, const double *pos, const double *q) {
             fmm::launch_traverse(cells_of(p), p->front[k & 1].as<int2>(), ctr + 2 + k, p->front[(k + 1) & 1].as<int2>(),
                                  ctr + 3 + k, (int32_t)p->cap_front, pb, ctr, bits, ta, tb, s);
         FMM_HIP_CHECK(hipMemcpyAsync(ctr + nsteps + 3, p->flag.ptr, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        if (!parents_listed) {
+            FMM_HIP_CHECK(hipStreamWaitEvent(p->up_side, p->p2p_fork, 0));
+            p->side_pending = true;
+            fmm::launch_parent_list(cells_of(p), (int32_t)p->ncell, p->ppos.as<int32_t>(), p->plist.as<int32_t>(),
+                                    p->ptmp.as<int32_t>(), p->up_side);
+            FMM_HIP_CHECK(hipEventRecord(p->up_join, p->up_side));
+            parents_listed = true;
+        }
         sync_read(p, hc.data(), ctr, (size_t)(nsteps + 5) * sizeof(int32_t));
         if (hc[nsteps + 3]) throw std::invalid_argument("non-finite particle coordinate");
         p->nleaf = hc[nsteps + 4];
